@@ -1,0 +1,357 @@
+/*
+ * Plain FP64 CPU oracle of the kinematical powder-XRD pipeline.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the checker for the GPU library:
+ * only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark load it.  It shares no code, header or table with the library.
+ *
+ * Every function is the textbook definition written out in double precision,
+ * in the order the method states it (paper, Section 2: reciprocal-lattice
+ * points inside the limiting sphere, structure factors as a sum over atoms for
+ * each reflection, Lorentz-polarisation and Debye-Waller corrections, merging
+ * of reflections within an angular tolerance).  The paper names these steps
+ * but prints no formula; the formulas below are the standard kinematical ones:
+ *
+ *   G       metric tensor of (a, b, c, alpha, beta, gamma); G* = G^-1
+ *   q       = h^T G* h = 1/d^2
+ *   s^2     = q / 4           (s = sin(theta)/lambda)
+ *   2theta  = 2 asin(lambda sqrt(q) / 2), degrees
+ *   f_t(s)  = sum_{i=1..4} a_i exp(-b_i s^2) + c      (Cromer-Mann form)
+ *   F(hkl)  = sum_j occ_j f_{t_j}(s) exp(-B_j s^2) exp(2 pi i (h x_j + k y_j + l z_j))
+ *   LP      = (1 + cos^2 2theta) / (sin^2 theta cos theta)
+ *   I       = |F|^2 LP
+ *
+ * Peaks: reflections sorted by (2theta, h, k, l); walking that order, a
+ * reflection joins the open peak when its 2theta minus the 2theta of the
+ * peak's first member is below the tolerance, otherwise it opens a new peak.
+ * The peak sits at its first member's 2theta and carries the sum of member
+ * intensities and the member count.
+ *
+ * Build: gcc -O2 -ffp-contract=off -fopenmp -fPIC -shared xrd_oracle.c -lm
+ * (no contraction, so every product and sum is rounded as written).
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_AMBIG 1e-9 /* degrees: a comparison this close to its threshold is ambiguous */
+
+/* ---- cell ------------------------------------------------------------- */
+
+/* Metric tensor G and its inverse G* of a cell, both stored as
+ * [11, 22, 33, 12, 13, 23].  Returns 0, or 1 when the cell is invalid:
+ * non-positive lengths, angles outside (0, 180), or det(G)/(abc)^2 < 1e-3. */
+int orc_cell(const double lat[6], double g[6], double gs[6], double *volume)
+{
+    double a = lat[0], b = lat[1], c = lat[2];
+    if (!(a > 0.0) || !(b > 0.0) || !(c > 0.0)) return 1;
+    for (int i = 3; i < 6; ++i)
+        if (!(lat[i] > 0.0) || !(lat[i] < 180.0)) return 1;
+    double ca = cos(lat[3] * ORC_PI / 180.0);
+    double cb = cos(lat[4] * ORC_PI / 180.0);
+    double cg = cos(lat[5] * ORC_PI / 180.0);
+    double g11 = a * a, g22 = b * b, g33 = c * c;
+    double g12 = a * b * cg, g13 = a * c * cb, g23 = b * c * ca;
+    double c11 = g22 * g33 - g23 * g23;
+    double c22 = g11 * g33 - g13 * g13;
+    double c33 = g11 * g22 - g12 * g12;
+    double c12 = g13 * g23 - g12 * g33;
+    double c13 = g12 * g23 - g13 * g22;
+    double c23 = g12 * g13 - g11 * g23;
+    double det = g11 * c11 + g12 * c12 + g13 * c13;
+    if (!(det / (g11 * g22 * g33) >= 1e-3)) return 1;
+    if (g) { g[0] = g11; g[1] = g22; g[2] = g33; g[3] = g12; g[4] = g13; g[5] = g23; }
+    if (gs) {
+        gs[0] = c11 / det; gs[1] = c22 / det; gs[2] = c33 / det;
+        gs[3] = c12 / det; gs[4] = c13 / det; gs[5] = c23 / det;
+    }
+    if (volume) *volume = sqrt(det);
+    return 0;
+}
+
+/* q = h^T G* h, summed in this fixed order. */
+double orc_q(const double gs[6], int h, int k, int l)
+{
+    double hh = (double)h * h, kk = (double)k * k, ll = (double)l * l;
+    double hk = (double)h * k, hl = (double)h * l, kl = (double)k * l;
+    return gs[0] * hh + gs[1] * kk + gs[2] * ll + 2.0 * (gs[3] * hk + gs[4] * hl + gs[5] * kl);
+}
+
+/* 2theta in degrees for q = 1/d^2; returns -1 when sin(theta) > 1. */
+double orc_two_theta(double q, double lambda)
+{
+    double s = 0.5 * lambda * sqrt(q);
+    if (s > 1.0) return -1.0;
+    return 2.0 * asin(s) * (180.0 / ORC_PI);
+}
+
+/* Lorentz-polarisation factor at 2theta (degrees), unpolarised beam. */
+double orc_lp(double two_theta)
+{
+    double th = 0.5 * two_theta * ORC_PI / 180.0;
+    double c2 = cos(2.0 * th);
+    double st = sin(th), ct = cos(th);
+    return (1.0 + c2 * c2) / (st * st * ct);
+}
+
+/* Cromer-Mann scattering factor at s^2 = (sin(theta)/lambda)^2. */
+double orc_fsc(const double coeff[9], double s2)
+{
+    double f = coeff[8];
+    for (int i = 0; i < 4; ++i) f += coeff[i] * exp(-coeff[4 + i] * s2);
+    return f;
+}
+
+/* ---- enumeration -------------------------------------------------------- */
+
+/* All integer (h, k, l) != 0 with tmin <= 2theta <= tmax, in lexicographic
+ * order (h outermost).  The search box is generous on purpose:
+ * |h| <= ceil(gmax |a|) + 1 and likewise for k, l, where gmax = 2 sin(theta_max)
+ * / lambda, since h = g . a for a reciprocal vector g.  Writes at most
+ * ``cap`` reflections and returns the total count (so cap = 0 only counts),
+ * or -1 for an invalid cell or range.  ``amb`` (may be NULL) receives the
+ * number of reflections whose 2theta lies within 1e-9 deg of a range bound. */
+long orc_enumerate(const double lat[6], double lambda, double tmin, double tmax,
+                   long cap, int *hkl, double *q, double *tt, long *amb)
+{
+    double gs[6];
+    if (orc_cell(lat, NULL, gs, NULL)) return -1;
+    if (!(lambda > 0.0) || !(tmin >= 0.0) || !(tmax > tmin) || !(tmax < 180.0)) return -1;
+    double gmax = 2.0 * sin(0.5 * tmax * ORC_PI / 180.0) / lambda;
+    int bh = (int)ceil(gmax * lat[0]) + 1;
+    int bk = (int)ceil(gmax * lat[1]) + 1;
+    int bl = (int)ceil(gmax * lat[2]) + 1;
+    long n = 0, namb = 0;
+    for (int h = -bh; h <= bh; ++h)
+        for (int k = -bk; k <= bk; ++k)
+            for (int l = -bl; l <= bl; ++l) {
+                if (h == 0 && k == 0 && l == 0) continue;
+                double qq = orc_q(gs, h, k, l);
+                double t = orc_two_theta(qq, lambda);
+                if (t < 0.0) continue;
+                if (fabs(t - tmin) < ORC_AMBIG || fabs(t - tmax) < ORC_AMBIG) ++namb;
+                if (t < tmin || t > tmax) continue;
+                if (n < cap) {
+                    hkl[3 * n] = h; hkl[3 * n + 1] = k; hkl[3 * n + 2] = l;
+                    q[n] = qq; tt[n] = t;
+                }
+                ++n;
+            }
+    if (amb) *amb = namb;
+    return n;
+}
+
+/* ---- structure factors -------------------------------------------------- */
+
+/* F for each listed reflection: a direct sum over the crystal's atoms in
+ * double precision with libm cos/sin/exp, no reduction of the phase.
+ * ``absw`` (may be NULL) receives sum_j |w_j|, the size of the largest
+ * possible |F|, which bounds the rounding error of the sum. */
+void orc_structure_factors(long nr, const int *hkl, const double *q,
+                           long na, const double *frac, const int *species,
+                           const double *occ, const double *bfac, const double *coeff,
+                           double *fr, double *fi, double *absw)
+{
+    for (long r = 0; r < nr; ++r) {
+        double h = hkl[3 * r], k = hkl[3 * r + 1], l = hkl[3 * r + 2];
+        double s2 = q[r] / 4.0;
+        double re = 0.0, im = 0.0, aw = 0.0;
+        for (long j = 0; j < na; ++j) {
+            double f = orc_fsc(coeff + 9 * species[j], s2);
+            double w = occ[j] * f * exp(-bfac[j] * s2);
+            double t = h * frac[3 * j] + k * frac[3 * j + 1] + l * frac[3 * j + 2];
+            double phi = 2.0 * ORC_PI * t;
+            re += w * cos(phi);
+            im += w * sin(phi);
+            aw += fabs(w);
+        }
+        fr[r] = re; fi[r] = im;
+        if (absw) absw[r] = aw;
+    }
+}
+
+/* ---- sort and merge ----------------------------------------------------- */
+
+typedef struct { double tt; int h, k, l; long idx; } orc_key;
+
+static int orc_cmp(const void *pa, const void *pb)
+{
+    const orc_key *a = (const orc_key *)pa, *b = (const orc_key *)pb;
+    if (a->tt < b->tt) return -1;
+    if (a->tt > b->tt) return 1;
+    if (a->h != b->h) return a->h < b->h ? -1 : 1;
+    if (a->k != b->k) return a->k < b->k ? -1 : 1;
+    if (a->l != b->l) return a->l < b->l ? -1 : 1;
+    return 0;
+}
+
+/* perm[i] = index of the i-th reflection in (2theta, h, k, l) order. */
+void orc_sort(long nr, const double *tt, const int *hkl, long *perm)
+{
+    orc_key *keys = (orc_key *)malloc(sizeof(orc_key) * (size_t)(nr > 0 ? nr : 1));
+    for (long r = 0; r < nr; ++r) {
+        keys[r].tt = tt[r];
+        keys[r].h = hkl[3 * r]; keys[r].k = hkl[3 * r + 1]; keys[r].l = hkl[3 * r + 2];
+        keys[r].idx = r;
+    }
+    qsort(keys, (size_t)nr, sizeof(orc_key), orc_cmp);
+    for (long r = 0; r < nr; ++r) perm[r] = keys[r].idx;
+    free(keys);
+}
+
+/* Anchor-rule merge of an ascending 2theta list.  Writes at most nr peaks
+ * (position = anchor 2theta, summed intensity in list order, member count,
+ * index of the first member) and returns their number.  ``amb`` receives the
+ * number of anchor comparisons within 1e-9 deg of the tolerance. */
+long orc_merge(long nr, const double *tt_sorted, const double *i_sorted, double tol,
+               double *pk_tt, double *pk_i, int *pk_mult, long *pk_first, long *amb)
+{
+    long np = -1, namb = 0;
+    double anchor = 0.0;
+    for (long r = 0; r < nr; ++r) {
+        int join = 0;
+        if (np >= 0) {
+            double d = tt_sorted[r] - anchor;
+            if (fabs(d - tol) < ORC_AMBIG) ++namb;
+            join = d < tol;
+        }
+        if (!join) {
+            ++np;
+            anchor = tt_sorted[r];
+            pk_tt[np] = anchor; pk_i[np] = 0.0; pk_mult[np] = 0; pk_first[np] = r;
+        }
+        pk_i[np] += i_sorted[r];
+        pk_mult[np] += 1;
+    }
+    if (amb) *amb = namb;
+    return np + 1;
+}
+
+/* ---- broadening --------------------------------------------------------- */
+
+/* y_g = sum_r I_r exp(-(x_g - t_r)^2 / (2 sigma^2)) / (sigma sqrt(2 pi)) over
+ * the reflections with |x_g - t_r| <= window * sigma, x_g = t0 + g dt.
+ * The loop visits, for each reflection, the grid points one step beyond its
+ * window on each side and applies the window test to every one of them. */
+void orc_broaden(long nr, const double *tt, const double *inten,
+                 double t0, double dt, long npts, double sigma, double window, double *y)
+{
+    double half = window * sigma;
+    double norm = 1.0 / (sigma * sqrt(2.0 * ORC_PI));
+    for (long g = 0; g < npts; ++g) y[g] = 0.0;
+    for (long r = 0; r < nr; ++r) {
+        long glo = (long)floor((tt[r] - half - t0) / dt) - 1;
+        long ghi = (long)ceil((tt[r] + half - t0) / dt) + 1;
+        if (glo < 0) glo = 0;
+        if (ghi > npts - 1) ghi = npts - 1;
+        for (long g = glo; g <= ghi; ++g) {
+            double x = t0 + (double)g * dt;
+            double d = x - tt[r];
+            if (fabs(d) > half) continue;
+            y[g] += inten[r] * norm * exp(-(d * d) / (2.0 * sigma * sigma));
+        }
+    }
+}
+
+/* ---- whole pattern of one crystal, and a batch driver ------------------- */
+
+typedef struct {
+    long n_refl, n_peaks, amb_bound, amb_gap;
+    int *hkl;                   /* [3 n_refl], enumeration (lexicographic) order */
+    double *q, *tt, *lp, *fr, *fi, *absw, *inten; /* [n_refl] */
+    long *perm;                 /* [n_refl], (2theta, h, k, l) order */
+    double *pk_tt, *pk_i, *pk_y; /* [n_peaks] */
+    int *pk_mult;
+    long *pk_first;             /* position in perm of the peak's first member */
+    int status;                 /* 0 ok, 1 invalid input, 2 out of memory */
+} orc_crystal;
+
+void orc_free_crystal(orc_crystal *c)
+{
+    free(c->hkl); free(c->q); free(c->tt); free(c->lp); free(c->fr); free(c->fi);
+    free(c->absw); free(c->inten); free(c->perm);
+    free(c->pk_tt); free(c->pk_i); free(c->pk_y); free(c->pk_mult); free(c->pk_first);
+    memset(c, 0, sizeof(*c));
+}
+
+/* Full pattern of one crystal: enumerate, structure factors, LP, intensity,
+ * sort, merge, scale to 0-100 (y = 100 I / max I, 0 when max I = 0), then
+ * drop peaks with I < threshold * max I when threshold > 0. */
+void orc_pattern(const double lat[6], double lambda, double tmin, double tmax, double tol,
+                 double threshold, long na, const double *frac, const int *species,
+                 const double *occ, const double *bfac, const double *coeff,
+                 orc_crystal *out)
+{
+    memset(out, 0, sizeof(*out));
+    long amb = 0;
+    long n = orc_enumerate(lat, lambda, tmin, tmax, 0, NULL, NULL, NULL, NULL);
+    if (n < 0 || !(tol > 0.0)) { out->status = 1; return; }
+    size_t m = (size_t)(n > 0 ? n : 1);
+    out->hkl = (int *)malloc(3 * m * sizeof(int));
+    out->q = (double *)malloc(m * sizeof(double));
+    out->tt = (double *)malloc(m * sizeof(double));
+    out->lp = (double *)malloc(m * sizeof(double));
+    out->fr = (double *)malloc(m * sizeof(double));
+    out->fi = (double *)malloc(m * sizeof(double));
+    out->absw = (double *)malloc(m * sizeof(double));
+    out->inten = (double *)malloc(m * sizeof(double));
+    out->perm = (long *)malloc(m * sizeof(long));
+    out->pk_tt = (double *)malloc(m * sizeof(double));
+    out->pk_i = (double *)malloc(m * sizeof(double));
+    out->pk_y = (double *)malloc(m * sizeof(double));
+    out->pk_mult = (int *)malloc(m * sizeof(int));
+    out->pk_first = (long *)malloc(m * sizeof(long));
+    double *ts = (double *)malloc(m * sizeof(double));
+    double *is = (double *)malloc(m * sizeof(double));
+    if (!out->hkl || !out->q || !out->tt || !out->lp || !out->fr || !out->fi || !out->absw ||
+        !out->inten || !out->perm || !out->pk_tt || !out->pk_i || !out->pk_y ||
+        !out->pk_mult || !out->pk_first || !ts || !is) {
+        free(ts); free(is); orc_free_crystal(out); out->status = 2; return;
+    }
+    out->n_refl = orc_enumerate(lat, lambda, tmin, tmax, n, out->hkl, out->q, out->tt, &amb);
+    out->amb_bound = amb;
+    orc_structure_factors(n, out->hkl, out->q, na, frac, species, occ, bfac, coeff,
+                          out->fr, out->fi, out->absw);
+    for (long r = 0; r < n; ++r) {
+        out->lp[r] = orc_lp(out->tt[r]);
+        out->inten[r] = (out->fr[r] * out->fr[r] + out->fi[r] * out->fi[r]) * out->lp[r];
+    }
+    orc_sort(n, out->tt, out->hkl, out->perm);
+    for (long r = 0; r < n; ++r) { ts[r] = out->tt[out->perm[r]]; is[r] = out->inten[out->perm[r]]; }
+    long np = orc_merge(n, ts, is, tol, out->pk_tt, out->pk_i, out->pk_mult, out->pk_first, &amb);
+    out->amb_gap = amb;
+    free(ts); free(is);
+    double mx = 0.0;
+    for (long p = 0; p < np; ++p) if (out->pk_i[p] > mx) mx = out->pk_i[p];
+    long kept = 0;
+    for (long p = 0; p < np; ++p) {
+        if (threshold > 0.0 && out->pk_i[p] < threshold * mx) continue;
+        out->pk_tt[kept] = out->pk_tt[p];
+        out->pk_i[kept] = out->pk_i[p];
+        out->pk_mult[kept] = out->pk_mult[p];
+        out->pk_first[kept] = out->pk_first[p];
+        out->pk_y[kept] = mx > 0.0 ? 100.0 * out->pk_i[p] / mx : 0.0;
+        ++kept;
+    }
+    out->n_peaks = kept;
+}
+
+/* Patterns of a CSR batch, crystals spread over ``nthreads`` OpenMP threads
+ * (values below 1 mean one thread).  ``out`` has one entry per crystal; free each with
+ * orc_free_crystal. */
+void orc_pattern_batch(long nc, const double *lattice, const long *atom_offset,
+                       const double *frac, const int *species, const double *occ,
+                       const double *bfac, const double *coeff, double lambda,
+                       const double *tmin, const double *tmax, double tol, double threshold,
+                       int nthreads, orc_crystal *out)
+{
+    int nt = nthreads > 0 ? nthreads : 1;
+    (void)nt;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nt)
+    for (long c = 0; c < nc; ++c) {
+        long a0 = atom_offset[c], a1 = atom_offset[c + 1];
+        orc_pattern(lattice + 6 * c, lambda, tmin[c], tmax[c], tol, threshold, a1 - a0,
+                    frac + 3 * a0, species + a0, occ + a0, bfac + a0, coeff, out + c);
+    }
+}
