@@ -1,0 +1,199 @@
+/*
+ * xrd.h -- C ABI of the gfx950 kinematical powder-XRD library (libxrd.so).
+ *
+ * The library computes powder X-ray diffraction patterns of batches of
+ * crystals on one MI355X GPU.  The method is the one the paper
+ * (Rust-accelerated powder XRD, Section 2) accelerates on CPUs: generate the
+ * reciprocal-lattice points inside the limiting sphere, evaluate each
+ * reflection's structure factor as a sum over the atoms, apply the
+ * Lorentz-polarisation and Debye-Waller corrections, and merge reflections
+ * whose 2-theta agree within a tolerance into peaks.  The paper states the
+ * problem as: lattice, atoms with species, occupancies and thermal factors,
+ * wavelength, 2-theta range, and a scaled flag (Section 2, Fig. 1); the
+ * output is a list of peaks with 2-theta, intensity, hkl list and
+ * multiplicity, unfiltered (Section 2).
+ *
+ * Formulas (standard kinematical theory; the paper names the terms only):
+ *   G* = inverse metric tensor, q = h^T G* h = 1/d^2, s^2 = q/4,
+ *   2theta = 2 asin(lambda sqrt(q) / 2),
+ *   f_t(s) = sum_{i=1..4} a_i exp(-b_i s^2) + c            (Cromer-Mann)
+ *   F(hkl) = sum_j occ_j f_{t_j}(s) exp(-B_j s^2) exp(2 pi i (h x_j + k y_j + l z_j))
+ *   LP = (1 + cos^2 2theta) / (sin^2 theta cos theta),  I = |F|^2 LP.
+ *
+ * Conventions
+ *  - Every call returns XRD_OK (0) or a negative XRD_ERR_* code and leaves a
+ *    message for xrd_last_error() (thread-local).  No C++ exception crosses
+ *    the ABI.
+ *  - The caller owns every device buffer and the workspace; the batch
+ *    handle owns only host memory.  The library never frees caller memory.
+ *  - Device work is enqueued on the batch's stream in call order; no call
+ *    synchronises the host except xrd_read_counts.  Buffers must stay valid
+ *    until that stream work completes.
+ *  - Outputs are CSR over crystals.  A crystal with no atoms or no reflection
+ *    in its range is legal and yields an empty or all-zero segment.
+ *  - Angles are in degrees, lengths in Angstrom, B in Angstrom^2.
+ *  - Calls on one batch handle must not overlap from several host threads.
+ */
+#ifndef XRD_H
+#define XRD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes --------------------------------------------------------- */
+#define XRD_OK 0
+#define XRD_ERR_INVALID_ARG (-1)  /* null pointer, bad size, tolerance, range or wavelength */
+#define XRD_ERR_INVALID_CELL (-2) /* lengths <= 0, angles outside (0,180), det(G)/(abc)^2 < 1e-3 */
+#define XRD_ERR_CAPACITY (-3)     /* a size exceeds what the library's index types can hold */
+#define XRD_ERR_HIP (-4)          /* a HIP runtime call failed (message names it) */
+#define XRD_ERR_UNSUPPORTED (-5)  /* option combination not provided */
+
+/* Arithmetic of the structure-factor, broadening and adjoint kernels. */
+#define XRD_FP64 0  /* plain path: every step in double precision */
+#define XRD_MIXED 1 /* phase h.x reduced mod 1 in double precision; sin/cos, scattering
+                       factors and weights in single precision with compensated
+                       accumulation; q, 2theta, LP, merge keys and intensities in double */
+
+typedef struct xrd_batch xrd_batch; /* opaque */
+
+/* A batch of crystals.  Host arrays are read during xrd_batch_create only;
+ * device arrays are read by the device calls and must stay valid until the
+ * batch's work on the stream has completed. */
+typedef struct {
+    int64_t n_crystals;           /* >= 0 */
+    int32_t n_species;            /* rows of sf_coeff, >= 1 */
+    int32_t precision;            /* XRD_FP64 or XRD_MIXED */
+    const double *lattice;        /* HOST [n_crystals*6]: a, b, c, alpha, beta, gamma */
+    const int64_t *atom_offset;   /* HOST [n_crystals+1]: CSR offsets, atom_offset[0] == 0 */
+    const double *two_theta_min;  /* HOST [n_crystals]: inclusive lower bound, >= 0 */
+    const double *two_theta_max;  /* HOST [n_crystals]: inclusive upper bound, < 180 */
+    double wavelength;            /* > 0 */
+    double merge_tol;             /* > 0: anchor-rule merge tolerance in 2theta */
+    double rel_threshold;         /* >= 0: drop merged peaks with I < rel_threshold * max I
+                                     of their crystal (0 keeps every peak) */
+    int32_t friedel;              /* 1: evaluate one reflection of each (h, -h) pair and copy
+                                     the conjugate to its mate; 0: evaluate every reflection */
+    int32_t reserved;
+    const double *frac;           /* DEVICE [N*3]: fractional x, y, z per atom */
+    const int32_t *species;       /* DEVICE [N]: row of sf_coeff, 0 <= species < n_species */
+    const double *occ;            /* DEVICE [N]: occupancy, >= 0 */
+    const double *bfac;           /* DEVICE [N]: isotropic B */
+    const double *sf_coeff;       /* DEVICE [n_species*9]: a1..a4, b1..b4, c */
+    void *stream;                 /* hipStream_t; NULL = the null stream */
+} xrd_batch_desc;
+
+typedef struct {
+    int64_t n_crystals;
+    int64_t n_atoms;
+    int64_t refl_capacity;   /* upper bound on the batch's reflections (sum of search boxes) */
+    int64_t peak_capacity;   /* == refl_capacity */
+    int64_t workspace_bytes; /* device workspace the batch needs, 256-byte aligned base */
+    int64_t half_capacity;   /* upper bound on one-per-Friedel-pair reflections */
+} xrd_sizes;
+
+/* Reflection arrays (caller-owned device memory, capacity refl_capacity).
+ * Crystal c owns [refl_offset[c], refl_offset[c+1]), listed in ascending
+ * lexicographic (h, k, l) order; reflections i and (start + end - 1 - i) of a
+ * crystal are Friedel mates. */
+typedef struct {
+    int16_t *h, *k, *l;
+    double *q;           /* 1/d^2 */
+    double *two_theta;   /* degrees */
+    double *lp;          /* Lorentz-polarisation factor */
+    int64_t *refl_offset;/* [n_crystals+1] */
+} xrd_refl;
+
+/* Merged peaks (caller-owned device memory, capacity peak_capacity).
+ * Crystal c owns peaks [peak_offset[c], peak_offset[c+1]) in ascending 2theta.
+ * perm lists every reflection in (2theta, h, k, l) order (global reflection
+ * indices); a peak's members are perm[first .. first + mult). */
+typedef struct {
+    double *two_theta;   /* 2theta of the peak's first (smallest-angle) member */
+    double *intensity;   /* sum of member intensities */
+    double *scaled;      /* 100 * intensity / max intensity of the crystal (0 if that max is 0) */
+    int32_t *mult;       /* number of member reflections */
+    int64_t *first;      /* position in perm of the first member */
+    int64_t *perm;       /* [refl_capacity] */
+    int64_t *peak_offset;/* [n_crystals+1] */
+} xrd_peaks;
+
+/* Grid of a Gaussian-broadened pattern: x_g = t0 + g * dt, g in [0, n_points);
+ * each reflection adds I exp(-(x - 2theta)^2 / (2 sigma^2)) / (sigma sqrt(2 pi))
+ * at every grid point with |x - 2theta| <= window_sigmas * sigma. */
+typedef struct {
+    double t0, dt;
+    int64_t n_points;
+    double sigma, window_sigmas;
+} xrd_grid;
+
+/* Validate the batch and plan it on the host: metric inverses, search boxes,
+ * capacities and launch tables.  Allocates host memory only and makes no HIP
+ * call, so it also runs without a GPU.  On failure *out is NULL. */
+int xrd_batch_create(const xrd_batch_desc *desc, xrd_batch **out);
+
+/* Capacities and workspace size of a created batch (host only). */
+int xrd_batch_sizes(const xrd_batch *b, xrd_sizes *out);
+
+/* Copy the batch's launch tables into the workspace ``ws`` (device memory of
+ * at least workspace_bytes, 256-byte aligned), enqueued on the batch's
+ * stream.  Required once per workspace before the device calls below; kept
+ * out of those calls so that they can be captured into a HIP graph. */
+int xrd_batch_upload(xrd_batch *b, void *ws);
+
+/* Reciprocal-lattice enumeration (paper, Section 2: lattice points inside
+ * the physically accessible sphere): every integer (h, k, l) != 0 with
+ * two_theta_min <= 2theta <= two_theta_max, with q, 2theta and LP, written
+ * into ``r`` together with refl_offset. */
+int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r);
+
+/* Structure factors (paper, Section 2: sum of atomic contributions for each
+ * reflection, with Debye-Waller and Lorentz-polarisation factors) of every
+ * reflection in ``r``.  A and B receive Re F and Im F (float under
+ * XRD_MIXED, double under XRD_FP64; [refl_capacity]); I receives
+ * |F|^2 LP in double ([refl_capacity]). */
+int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, void *B, double *I);
+
+/* Merge (paper, Section 2: merging of reflections within the angular
+ * tolerance): sort each crystal's reflections by (2theta, h, k, l), then walk
+ * them keeping a peak open while 2theta - 2theta(first member) < merge_tol;
+ * scale to 0-100 and apply rel_threshold. */
+int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, xrd_peaks *p);
+
+/* Gaussian-broadened pattern y [n_crystals * n_points] (row per crystal) of
+ * the reflections in ``r`` with intensities I; every reflection contributes
+ * on its own (no merge).  Enumerate over the grid range widened by the
+ * window on both sides so that no reflection reaching the grid is missed. */
+int xrd_pattern_forward(xrd_batch *b, void *ws, const xrd_refl *r, const double *I,
+                        const xrd_grid *g, double *y);
+
+/* Adjoint of y(frac, lattice, bfac) = xrd_pattern_forward(enumerate, structure
+ * factors): given dL/dy [n_crystals * n_points], writes dL/dfrac [N*3],
+ * dL/dbfac [N] and dL/dlattice [n_crystals*6] (per degree for the angles).
+ * The reflection set is held fixed (it is piecewise constant in the
+ * lattice).  Device buffers, all double. */
+int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_grid *g,
+                         const double *dL_dy, double *dL_dfrac, double *dL_dbfac,
+                         double *dL_dlattice);
+
+/* Wait for the batch's stream and copy refl_offset and peak_offset
+ * ([n_crystals+1] each; either may be NULL) to host memory. */
+int xrd_read_counts(xrd_batch *b, const xrd_refl *r, const xrd_peaks *p,
+                    int64_t *host_refl_offset, int64_t *host_peak_offset);
+
+/* Free the handle (host memory only). NULL is ignored. */
+void xrd_batch_destroy(xrd_batch *b);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *xrd_last_error(void);
+
+/* Library version string. */
+const char *xrd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* XRD_H */

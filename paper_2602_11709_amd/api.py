@@ -1,0 +1,296 @@
+"""PyTorch front end: device buffers and streams around the C ABI.
+
+PyTorch supplies device memory and the stream; every computation runs in the
+library's kernels.  ``XrdBatch`` owns one batch handle, its workspace and the
+device copies of the atom arrays; its methods mirror the C calls.
+``simulate`` runs the whole forward pipeline and returns host arrays, and
+``XrdPattern`` is the differentiable broadened pattern (``torch.autograd``)
+whose backward is the library's hand-written adjoint.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import capi
+from .synth import CrystalBatch
+
+PRECISIONS = {"fp64": capi.XRD_FP64, "mixed": capi.XRD_MIXED}
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else t.data_ptr()
+
+
+@dataclasses.dataclass
+class Grid:
+    t0: float
+    dt: float
+    n_points: int
+    sigma: float
+    window_sigmas: float = 8.0
+
+    def c(self) -> capi.xrd_grid:
+        return capi.xrd_grid(self.t0, self.dt, int(self.n_points), self.sigma, self.window_sigmas)
+
+
+@dataclasses.dataclass
+class Reflections:
+    h: torch.Tensor
+    k: torch.Tensor
+    l: torch.Tensor
+    q: torch.Tensor
+    two_theta: torch.Tensor
+    lp: torch.Tensor
+    refl_offset: torch.Tensor
+
+    def c(self) -> capi.xrd_refl:
+        return capi.xrd_refl(*(t.data_ptr() for t in (self.h, self.k, self.l, self.q, self.two_theta, self.lp,
+                                                      self.refl_offset)))
+
+
+@dataclasses.dataclass
+class Peaks:
+    two_theta: torch.Tensor
+    intensity: torch.Tensor
+    scaled: torch.Tensor
+    mult: torch.Tensor
+    first: torch.Tensor
+    perm: torch.Tensor
+    peak_offset: torch.Tensor
+
+    def c(self) -> capi.xrd_peaks:
+        return capi.xrd_peaks(*(t.data_ptr() for t in (self.two_theta, self.intensity, self.scaled, self.mult,
+                                                       self.first, self.perm, self.peak_offset)))
+
+
+class XrdBatch:
+    """One planned batch on one GPU.
+
+    Host inputs (lattice, atom offsets, 2theta ranges) are read at
+    construction; atom arrays are copied to the device once and kept alive
+    here.  All work goes to the stream that is current at construction.
+    ``frac``/``bfac`` may be given as device tensors (float64) to override
+    the batch's arrays (the differentiable path does this)."""
+
+    def __init__(self, batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
+                 rel_threshold: float = 0.0, device="cuda", frac: Optional[torch.Tensor] = None,
+                 bfac: Optional[torch.Tensor] = None, lattice: Optional[np.ndarray] = None,
+                 two_theta_range: Optional[tuple] = None):
+        if precision not in PRECISIONS:
+            raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+        self.device = torch.device(device)
+        if self.device.type != "cuda":
+            raise RuntimeError("XrdBatch needs a GPU device; there is no CPU path")
+        self.precision = precision
+        self.friedel = (precision == "mixed") if friedel is None else bool(friedel)
+        self.batch = batch
+        dev = self.device
+        self.stream = torch.cuda.current_stream(dev)
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.frac = (frac if frac is not None else torch.as_tensor(batch.frac, **f64)).contiguous()
+        self.bfac = (bfac if bfac is not None else torch.as_tensor(batch.bfac, **f64)).contiguous()
+        self.species = torch.as_tensor(batch.species, dtype=torch.int32, device=dev).contiguous()
+        self.occ = torch.as_tensor(batch.occ, **f64).contiguous()
+        self.coeff = torch.as_tensor(batch.sf_coeff, **f64).contiguous()
+        self.lattice = np.ascontiguousarray(batch.lattice if lattice is None else lattice, dtype=np.float64)
+        self.atom_offset = np.ascontiguousarray(batch.atom_offset, dtype=np.int64)
+        if two_theta_range is None:
+            self.tmin = np.ascontiguousarray(batch.two_theta_min, dtype=np.float64)
+            self.tmax = np.ascontiguousarray(batch.two_theta_max, dtype=np.float64)
+        else:
+            self.tmin = np.full(batch.n_crystals, float(two_theta_range[0]))
+            self.tmax = np.full(batch.n_crystals, float(two_theta_range[1]))
+        d = capi.xrd_batch_desc()
+        d.n_crystals = batch.n_crystals
+        d.n_species = batch.n_species
+        d.precision = PRECISIONS[precision]
+        d.lattice = self.lattice.ctypes.data
+        d.atom_offset = self.atom_offset.ctypes.data
+        d.two_theta_min = self.tmin.ctypes.data
+        d.two_theta_max = self.tmax.ctypes.data
+        d.wavelength = batch.wavelength
+        d.merge_tol = batch.merge_tol
+        d.rel_threshold = rel_threshold
+        d.friedel = 1 if self.friedel else 0
+        d.frac = _p(self.frac) if batch.n_atoms else None
+        d.species = _p(self.species) if batch.n_atoms else None
+        d.occ = _p(self.occ) if batch.n_atoms else None
+        d.bfac = _p(self.bfac) if batch.n_atoms else None
+        d.sf_coeff = _p(self.coeff)
+        d.stream = self.stream.cuda_stream
+        self.desc = d
+        self.handle = None
+        self.handle = capi.xrd_batch_create(d)
+        self.sizes = capi.xrd_batch_sizes(self.handle)
+        nb = int(self.sizes.workspace_bytes)
+        self._ws_raw = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        self.ws = self._ws_raw.data_ptr() + (-self._ws_raw.data_ptr()) % 256
+        capi.xrd_batch_upload(self.handle, self.ws)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            capi.xrd_batch_destroy(h)
+            self.handle = None
+
+    @property
+    def n_crystals(self):
+        return self.batch.n_crystals
+
+    @property
+    def refl_capacity(self):
+        return int(self.sizes.refl_capacity)
+
+    # ---- allocation --------------------------------------------------------
+
+    def new_reflections(self) -> Reflections:
+        n = max(self.refl_capacity, 1)
+        dev = self.device
+        return Reflections(
+            h=torch.empty(n, dtype=torch.int16, device=dev), k=torch.empty(n, dtype=torch.int16, device=dev),
+            l=torch.empty(n, dtype=torch.int16, device=dev), q=torch.empty(n, dtype=torch.float64, device=dev),
+            two_theta=torch.empty(n, dtype=torch.float64, device=dev),
+            lp=torch.empty(n, dtype=torch.float64, device=dev),
+            refl_offset=torch.empty(self.n_crystals + 1, dtype=torch.int64, device=dev))
+
+    def new_peaks(self) -> Peaks:
+        n = max(self.refl_capacity, 1)
+        dev = self.device
+        return Peaks(
+            two_theta=torch.empty(n, dtype=torch.float64, device=dev),
+            intensity=torch.empty(n, dtype=torch.float64, device=dev),
+            scaled=torch.empty(n, dtype=torch.float64, device=dev),
+            mult=torch.empty(n, dtype=torch.int32, device=dev), first=torch.empty(n, dtype=torch.int64, device=dev),
+            perm=torch.empty(n, dtype=torch.int64, device=dev),
+            peak_offset=torch.empty(self.n_crystals + 1, dtype=torch.int64, device=dev))
+
+    def new_sf(self):
+        n = max(self.refl_capacity, 1)
+        dt = torch.float32 if self.precision == "mixed" else torch.float64
+        return (torch.empty(n, dtype=dt, device=self.device), torch.empty(n, dtype=dt, device=self.device),
+                torch.empty(n, dtype=torch.float64, device=self.device))
+
+    # ---- the C calls --------------------------------------------------------
+
+    def enumerate(self, refl: Optional[Reflections] = None) -> Reflections:
+        refl = refl or self.new_reflections()
+        capi.xrd_enumerate_hkl(self.handle, self.ws, refl.c())
+        return refl
+
+    def structure_factors(self, refl: Reflections, out=None):
+        A, B, I = out or self.new_sf()
+        capi.xrd_structure_factors(self.handle, self.ws, refl.c(), A.data_ptr(), B.data_ptr(), I.data_ptr())
+        return A, B, I
+
+    def merge(self, refl: Reflections, I: torch.Tensor, peaks: Optional[Peaks] = None) -> Peaks:
+        peaks = peaks or self.new_peaks()
+        capi.xrd_merge_peaks(self.handle, self.ws, refl.c(), I.data_ptr(), peaks.c())
+        return peaks
+
+    def pattern_forward(self, refl: Reflections, I: torch.Tensor, grid: Grid, y=None) -> torch.Tensor:
+        if y is None:
+            y = torch.empty(self.n_crystals, grid.n_points, dtype=torch.float64, device=self.device)
+        capi.xrd_pattern_forward(self.handle, self.ws, refl.c(), I.data_ptr(), grid.c(), y.data_ptr())
+        return y
+
+    def pattern_backward(self, refl: Reflections, grid: Grid, dy: torch.Tensor):
+        dy = dy.to(torch.float64).contiguous()
+        n = max(self.batch.n_atoms, 1)
+        dfrac = torch.empty(n, 3, dtype=torch.float64, device=self.device)
+        dbfac = torch.empty(n, dtype=torch.float64, device=self.device)
+        dlat = torch.empty(max(self.n_crystals, 1), 6, dtype=torch.float64, device=self.device)
+        capi.xrd_pattern_backward(self.handle, self.ws, refl.c(), grid.c(), dy.data_ptr(), dfrac.data_ptr(),
+                                  dbfac.data_ptr(), dlat.data_ptr())
+        return dfrac[: self.batch.n_atoms], dbfac[: self.batch.n_atoms], dlat[: self.n_crystals]
+
+    def read_counts(self, refl: Optional[Reflections] = None, peaks: Optional[Peaks] = None):
+        ro = np.zeros(self.n_crystals + 1, np.int64) if refl is not None else None
+        po = np.zeros(self.n_crystals + 1, np.int64) if peaks is not None else None
+        capi.xrd_read_counts(self.handle, refl.c() if refl is not None else None,
+                             peaks.c() if peaks is not None else None,
+                             ro.ctypes.data if ro is not None else None, po.ctypes.data if po is not None else None)
+        return ro, po
+
+
+@dataclasses.dataclass
+class PatternResult:
+    """Host copy of a batch's forward pipeline (CSR over crystals)."""
+
+    refl_offset: np.ndarray
+    hkl: np.ndarray
+    q: np.ndarray
+    two_theta: np.ndarray
+    lp: np.ndarray
+    A: np.ndarray
+    B: np.ndarray
+    I: np.ndarray
+    peak_offset: np.ndarray
+    pk_two_theta: np.ndarray
+    pk_intensity: np.ndarray
+    pk_scaled: np.ndarray
+    pk_mult: np.ndarray
+    pk_first: np.ndarray
+    perm: np.ndarray
+
+    def crystal(self, c):
+        r0, r1 = int(self.refl_offset[c]), int(self.refl_offset[c + 1])
+        p0, p1 = int(self.peak_offset[c]), int(self.peak_offset[c + 1])
+        return slice(r0, r1), slice(p0, p1)
+
+
+def simulate(batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
+             rel_threshold: float = 0.0, device="cuda") -> PatternResult:
+    """Enumerate, structure factors, merge for every crystal; host arrays back."""
+    xb = XrdBatch(batch, precision=precision, friedel=friedel, rel_threshold=rel_threshold, device=device)
+    refl = xb.enumerate()
+    A, B, I = xb.structure_factors(refl)
+    pk = xb.merge(refl, I)
+    ro, po = xb.read_counts(refl, pk)
+    n, m = int(ro[-1]), int(po[-1])
+    cpu = lambda t, k: t[:k].cpu().numpy()
+    hkl = np.stack([cpu(refl.h, n), cpu(refl.k, n), cpu(refl.l, n)], axis=1).astype(np.int32)
+    return PatternResult(refl_offset=ro, hkl=hkl, q=cpu(refl.q, n), two_theta=cpu(refl.two_theta, n),
+                         lp=cpu(refl.lp, n), A=cpu(A, n).astype(np.float64), B=cpu(B, n).astype(np.float64),
+                         I=cpu(I, n), peak_offset=po, pk_two_theta=cpu(pk.two_theta, m),
+                         pk_intensity=cpu(pk.intensity, m), pk_scaled=cpu(pk.scaled, m), pk_mult=cpu(pk.mult, m),
+                         pk_first=cpu(pk.first, m), perm=cpu(pk.perm, n))
+
+
+class _PatternFn(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, frac, lattice, bfac, spec):
+        lat = lattice.detach().to("cpu", torch.float64).numpy()
+        xb = XrdBatch(spec["batch"], precision=spec["precision"], friedel=spec["friedel"], device=frac.device,
+                      frac=frac.detach().to(torch.float64).contiguous(),
+                      bfac=bfac.detach().to(torch.float64).contiguous(), lattice=lat)
+        refl = xb.enumerate()
+        _, _, I = xb.structure_factors(refl)
+        y = xb.pattern_forward(refl, I, spec["grid"])
+        ctx.xb, ctx.refl, ctx.grid = xb, refl, spec["grid"]
+        ctx.lat_device, ctx.lat_dtype = lattice.device, lattice.dtype
+        return y
+
+    @staticmethod
+    def backward(ctx, dy):
+        dfrac, dbfac, dlat = ctx.xb.pattern_backward(ctx.refl, ctx.grid, dy)
+        return dfrac, dlat.to(ctx.lat_device, ctx.lat_dtype), dbfac, None
+
+
+def xrd_pattern(frac: torch.Tensor, lattice: torch.Tensor, bfac: torch.Tensor, batch: CrystalBatch, grid: Grid,
+                precision: str = "mixed", friedel: Optional[bool] = None) -> torch.Tensor:
+    """Differentiable Gaussian-broadened pattern [n_crystals, n_points].
+
+    ``frac`` [N, 3] and ``bfac`` [N] are device tensors, ``lattice``
+    [n_crystals, 6] any tensor (read on the host to plan the batch); species,
+    occupancies, scattering factors, wavelength and the enumeration range come
+    from ``batch`` (whose 2theta range should cover the grid widened by the
+    window).  Gradients flow to frac, lattice (per degree for angles) and bfac
+    through the library's adjoint; the reflection set is held fixed."""
+    spec = {"batch": batch, "grid": grid, "precision": precision,
+            "friedel": (precision == "mixed") if friedel is None else friedel}
+    return _PatternFn.apply(frac, lattice, bfac, spec)

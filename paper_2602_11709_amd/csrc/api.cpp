@@ -1,0 +1,543 @@
+// C ABI of libxrd: validation, host planning, workspace layout and launches.
+//
+// Planning (the cell-preparation step) runs on the host once per batch: the
+// inverse metric from the reciprocal-cell formulas, the search box of each
+// crystal (|h| <= gmax a since h = g . a for a reciprocal vector g of length
+// at most gmax = 2 sin(theta_max) / lambda), capacities, and the launch tables
+// of every kernel.  The tables are sized at capacity so that every launch
+// has a host-known grid; blocks whose work lies beyond a crystal's actual
+// reflection count exit at once.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/xrd.h"
+#include "xrd_internal.h"
+
+using namespace xrd;
+
+struct xrd_batch {
+  xrd_batch_desc desc;
+  std::vector<double> lattice, tmin, tmax;
+  std::vector<int64_t> atom_offset;
+  std::vector<CrystalPlan> plan;
+  std::vector<int32_t> enum_chunk_crystal, sort_chunk_crystal, hchunk_crystal;
+  std::vector<SfItem> sf_items;
+  std::vector<BwItem> bw_items;
+  std::vector<AbItem> ab_items;
+  int64_t n_atoms = 0, refl_cap = 0, half_cap = 0, n_bins = 0, run_cap = 0, part_rows = 0;
+  int runs_cap_max = 1, bw_tile = 64;
+  WsLayout ws{};
+  void *last_ws = nullptr;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_check(const char *what) {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string(what) + ": " + hipGetErrorString(e));
+  return XRD_OK;
+}
+
+constexpr double kPi = 3.14159265358979323846;
+
+int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+
+// Inverse metric of a cell from the reciprocal-cell formulas; false if the
+// cell is invalid (lengths <= 0, angles outside (0, 180), or flatness
+// 1 - sum cos^2 + 2 prod cos below 1e-3).
+bool reciprocal_metric(const double *lat, double gs[6]) {
+  const double a = lat[0], b = lat[1], c = lat[2];
+  if (!(a > 0) || !(b > 0) || !(c > 0) || !std::isfinite(a) || !std::isfinite(b) || !std::isfinite(c)) return false;
+  for (int i = 3; i < 6; ++i)
+    if (!(lat[i] > 0.0 && lat[i] < 180.0)) return false;
+  const double al = lat[3] * kPi / 180.0, be = lat[4] * kPi / 180.0, ga = lat[5] * kPi / 180.0;
+  const double ca = std::cos(al), cb = std::cos(be), cg = std::cos(ga);
+  const double sa = std::sin(al), sb = std::sin(be), sg = std::sin(ga);
+  const double flat = 1.0 - ca * ca - cb * cb - cg * cg + 2.0 * ca * cb * cg;
+  if (!(flat >= 1e-3)) return false;
+  const double V = a * b * c * std::sqrt(flat);
+  const double as = b * c * sa / V, bs = a * c * sb / V, cs = a * b * sg / V;
+  const double cas = (cb * cg - ca) / (sb * sg);
+  const double cbs = (ca * cg - cb) / (sa * sg);
+  const double cgs = (ca * cb - cg) / (sa * sb);
+  gs[0] = as * as;
+  gs[1] = bs * bs;
+  gs[2] = cs * cs;
+  gs[3] = as * bs * cgs;
+  gs[4] = as * cs * cbs;
+  gs[5] = bs * cs * cas;
+  return true;
+}
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+template <class T>
+T *at(void *ws, int64_t off) {
+  return reinterpret_cast<T *>(static_cast<char *>(ws) + off);
+}
+
+hipStream_t stream_of(const xrd_batch *b) { return static_cast<hipStream_t>(b->desc.stream); }
+
+int check_ws(const xrd_batch *b, const void *ws) {
+  if (!ws) return fail(XRD_ERR_INVALID_ARG, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(XRD_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+  return XRD_OK;
+}
+
+int check_refl(const xrd_refl *r) {
+  if (!r || !r->h || !r->k || !r->l || !r->q || !r->two_theta || !r->lp || !r->refl_offset)
+    return fail(XRD_ERR_INVALID_ARG, "reflection arrays must be non-NULL");
+  return XRD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *xrd_last_error(void) { return g_err.c_str(); }
+
+const char *xrd_version(void) { return "xrd-gfx950 1.0"; }
+
+int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
+  if (!out) return fail(XRD_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!d) return fail(XRD_ERR_INVALID_ARG, "desc is NULL");
+  const int64_t nc = d->n_crystals;
+  if (nc < 0) return fail(XRD_ERR_INVALID_ARG, "n_crystals < 0");
+  if (nc > (int64_t)1 << 30) return fail(XRD_ERR_CAPACITY, "n_crystals too large");
+  if (d->n_species < 1) return fail(XRD_ERR_INVALID_ARG, "n_species < 1");
+  if (d->n_species > 8192) return fail(XRD_ERR_CAPACITY, "n_species > 8192");
+  if (d->precision != XRD_FP64 && d->precision != XRD_MIXED) return fail(XRD_ERR_INVALID_ARG, "unknown precision");
+  if (d->friedel != 0 && d->friedel != 1) return fail(XRD_ERR_INVALID_ARG, "friedel must be 0 or 1");
+  if (!(d->wavelength > 0.0) || !std::isfinite(d->wavelength)) return fail(XRD_ERR_INVALID_ARG, "wavelength must be > 0");
+  if (!(d->merge_tol > 0.0) || !std::isfinite(d->merge_tol)) return fail(XRD_ERR_INVALID_ARG, "merge_tol must be > 0");
+  if (!(d->rel_threshold >= 0.0) || !std::isfinite(d->rel_threshold))
+    return fail(XRD_ERR_INVALID_ARG, "rel_threshold must be >= 0");
+  if (nc > 0 && (!d->lattice || !d->atom_offset || !d->two_theta_min || !d->two_theta_max))
+    return fail(XRD_ERR_INVALID_ARG, "host arrays must be non-NULL");
+  if (!d->sf_coeff) return fail(XRD_ERR_INVALID_ARG, "sf_coeff is NULL");
+  if (nc > 0 && d->atom_offset[0] != 0) return fail(XRD_ERR_INVALID_ARG, "atom_offset[0] must be 0");
+  for (int64_t c = 0; c < nc; ++c)
+    if (d->atom_offset[c + 1] < d->atom_offset[c]) return fail(XRD_ERR_INVALID_ARG, "atom_offset must be non-decreasing");
+  const int64_t n_atoms = nc > 0 ? d->atom_offset[nc] : 0;
+  if (n_atoms >= ((int64_t)1 << 31)) return fail(XRD_ERR_CAPACITY, "more than 2^31 atoms");
+  if (n_atoms > 0 && (!d->frac || !d->species || !d->occ || !d->bfac))
+    return fail(XRD_ERR_INVALID_ARG, "atom arrays must be non-NULL");
+  for (int64_t c = 0; c < nc; ++c) {
+    const double lo = d->two_theta_min[c], hi = d->two_theta_max[c];
+    if (!(lo >= 0.0) || !(hi > lo) || !(hi < 180.0))
+      return fail(XRD_ERR_INVALID_ARG, "crystal " + std::to_string(c) + ": need 0 <= two_theta_min < two_theta_max < 180");
+  }
+
+  xrd_batch *b = new (std::nothrow) xrd_batch();
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "out of host memory");
+  b->desc = *d;
+  b->lattice.assign(d->lattice, d->lattice + 6 * nc);
+  b->atom_offset.assign(d->atom_offset, d->atom_offset + nc + 1);
+  b->tmin.assign(d->two_theta_min, d->two_theta_min + nc);
+  b->tmax.assign(d->two_theta_max, d->two_theta_max + nc);
+  b->desc.lattice = b->lattice.data();
+  b->desc.atom_offset = b->atom_offset.data();
+  b->desc.two_theta_min = b->tmin.data();
+  b->desc.two_theta_max = b->tmax.data();
+  b->n_atoms = n_atoms;
+  b->plan.resize(nc);
+
+  const bool friedel = d->friedel != 0;
+  const double lam = d->wavelength;
+  int64_t ec = 0, sc = 0, hc = 0, bins = 0, runs = 0, parts = 0, refl = 0;
+  int runs_cap_max = 1;
+  for (int64_t c = 0; c < nc; ++c) {
+    CrystalPlan &P = b->plan[c];
+    std::memset(&P, 0, sizeof(P));
+    const double *lat = b->lattice.data() + 6 * c;
+    if (!reciprocal_metric(lat, P.gs)) {
+      delete b;
+      return fail(XRD_ERR_INVALID_CELL, "crystal " + std::to_string(c) + ": invalid cell");
+    }
+    for (int i = 0; i < 6; ++i) P.lat[i] = lat[i];
+    P.tmin = b->tmin[c];
+    P.tmax = b->tmax[c];
+    const double gmax = 2.0 * std::sin(0.5 * P.tmax * kPi / 180.0) / lam;
+    const double gmin = 2.0 * std::sin(0.5 * P.tmin * kPi / 180.0) / lam;
+    P.qhi = gmax * gmax * (1.0 + 1e-9);
+    P.qlo = gmin * gmin * (1.0 - 1e-9);
+    const double bh = std::floor(gmax * lat[0] * (1.0 + 1e-9));
+    const double bk = std::floor(gmax * lat[1] * (1.0 + 1e-9));
+    const double bl = std::floor(gmax * lat[2] * (1.0 + 1e-9));
+    if (bh > 16000 || bk > 16000 || bl > 16000) {
+      delete b;
+      return fail(XRD_ERR_CAPACITY, "crystal " + std::to_string(c) + ": search box exceeds 16000 in an index");
+    }
+    P.H = (int32_t)bh;
+    P.K = (int32_t)bk;
+    P.L = (int32_t)bl;
+    const int64_t box = (2 * (int64_t)P.H + 1) * (2 * (int64_t)P.K + 1) * (2 * (int64_t)P.L + 1);
+    P.half_box = (box - 1) / 2;
+    refl += 2 * P.half_box;
+    if (refl >= ((int64_t)1 << 31) - 1) {
+      delete b;
+      return fail(XRD_ERR_CAPACITY, "reflection capacity exceeds 2^31; split the batch");
+    }
+    P.enum_chunk_begin = ec;
+    P.enum_chunks = (int32_t)ceil_div(P.half_box, kEnumChunk);
+    ec += P.enum_chunks;
+    P.sort_chunk_begin = sc;
+    P.sort_chunks = (int32_t)ceil_div(2 * P.half_box, kSortChunk);
+    sc += P.sort_chunks;
+    P.n_bins = (int32_t)std::max<int64_t>(1, 2 * P.half_box / kBinDiv);
+    P.bin_begin = bins;
+    P.bin_scale = (double)P.n_bins / (P.tmax - P.tmin);
+    bins += P.n_bins;
+    P.atom_begin = b->atom_offset[c];
+    P.atom_end = b->atom_offset[c + 1];
+    const int64_t na = P.atom_end - P.atom_begin;
+    const int64_t rc = std::min<int64_t>(d->n_species, na);
+    P.run_begin = runs;
+    runs += rc;
+    runs_cap_max = (int)std::max<int64_t>(runs_cap_max, rc);
+    const int64_t evalcap = friedel ? P.half_box : 2 * P.half_box;
+    P.n_hchunks = (int32_t)ceil_div(evalcap, kHalfChunk);
+    P.hchunk_begin = hc;
+    hc += P.n_hchunks;
+    P.part_begin = parts;
+    parts += (int64_t)P.n_hchunks * na;
+  }
+  b->refl_cap = refl;
+  b->half_cap = refl / 2;
+  b->n_bins = bins;
+  b->run_cap = runs;
+  b->part_rows = parts;
+  b->runs_cap_max = runs_cap_max;
+  const bool mixed = d->precision == XRD_MIXED;
+  int tile = 64;
+  while (tile > 8 && atom_bw_lds_bytes(mixed, tile, runs_cap_max) > 48 * 1024) tile -= 8;
+  b->bw_tile = tile;
+  if (atom_bw_lds_bytes(mixed, tile, runs_cap_max) > 48 * 1024) {
+    delete b;
+    return fail(XRD_ERR_CAPACITY, "too many species per crystal for the adjoint's LDS tile");
+  }
+
+  // launch tables
+  b->enum_chunk_crystal.resize(ec);
+  b->sort_chunk_crystal.resize(sc);
+  b->hchunk_crystal.resize(hc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const CrystalPlan &P = b->plan[c];
+    for (int32_t i = 0; i < P.enum_chunks; ++i) b->enum_chunk_crystal[P.enum_chunk_begin + i] = (int32_t)c;
+    for (int32_t i = 0; i < P.sort_chunks; ++i) b->sort_chunk_crystal[P.sort_chunk_begin + i] = (int32_t)c;
+    for (int32_t i = 0; i < P.n_hchunks; ++i) b->hchunk_crystal[P.hchunk_begin + i] = (int32_t)c;
+  }
+  // structure-factor items: crystals in descending atom count (the cost of
+  // one item), so the heaviest work is dispatched first
+  std::vector<int64_t> order(nc);
+  for (int64_t c = 0; c < nc; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    return (b->atom_offset[x + 1] - b->atom_offset[x]) > (b->atom_offset[y + 1] - b->atom_offset[y]);
+  });
+  for (int64_t c : order) {
+    const CrystalPlan &P = b->plan[c];
+    const int64_t evalcap = friedel ? P.half_box : 2 * P.half_box;
+    const int64_t tiles = ceil_div(evalcap, kSfTile);
+    for (int64_t t = 0; t < tiles; ++t) b->sf_items.push_back(SfItem{(int32_t)c, (int32_t)t});
+    const int64_t na = P.atom_end - P.atom_begin;
+    const int64_t ab = ceil_div(na, kAtomBlock);
+    for (int64_t a = 0; a < ab; ++a) {
+      b->ab_items.push_back(AbItem{(int32_t)c, (int32_t)a});
+      for (int32_t k = 0; k < P.n_hchunks; ++k) b->bw_items.push_back(BwItem{(int32_t)c, (int32_t)a, k, 0});
+    }
+  }
+  if ((int64_t)b->sf_items.size() >= ((int64_t)1 << 31) || (int64_t)b->bw_items.size() >= ((int64_t)1 << 31)) {
+    delete b;
+    return fail(XRD_ERR_CAPACITY, "launch tables exceed 2^31 entries");
+  }
+
+  // workspace layout
+  WsLayout &L = b->ws;
+  int64_t o = 0;
+  auto take = [&](int64_t bytes) {
+    const int64_t r = o;
+    o = align256(o + std::max<int64_t>(bytes, 8));
+    return r;
+  };
+  const int64_t rc = b->refl_cap, pc = b->refl_cap;
+  L.plan = take((int64_t)sizeof(CrystalPlan) * nc);
+  L.enum_chunk_crystal = take(4 * ec);
+  L.sf_items = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items.size());
+  L.sort_chunk_crystal = take(4 * sc);
+  L.hchunk_crystal = take(4 * hc);
+  L.bw_items = take((int64_t)sizeof(BwItem) * (int64_t)b->bw_items.size());
+  L.ab_items = take((int64_t)sizeof(AbItem) * (int64_t)b->ab_items.size());
+  L.enum_count = take(4 * ec);
+  L.enum_prefix = take(8 * (ec + 1));
+  L.atoms = take((int64_t)sizeof(AtomRec) * n_atoms);
+  L.atom_orig = take(4 * n_atoms);
+  L.runs = take((int64_t)sizeof(SpeciesRun) * runs);
+  L.run_count = take(4 * nc);
+  L.err_flag = take(4);
+  L.bin_count = take(4 * bins);
+  L.bin_start = take(8 * (bins + 1));
+  L.skey = take(8 * rc);
+  L.sidx = take(4 * rc);
+  L.flags = take(4 * rc);
+  L.pscan = take(8 * (rc + 1));
+  L.cmax = take(8 * nc);
+  L.n_peaks = take(8);
+  const bool thr = d->rel_threshold > 0.0;
+  L.tmp_tt = thr ? take(8 * pc) : 0;
+  L.tmp_i = thr ? take(8 * pc) : 0;
+  L.tmp_y = thr ? take(8 * pc) : 0;
+  L.tmp_mult = thr ? take(4 * pc) : 0;
+  L.tmp_first = thr ? take(8 * pc) : 0;
+  L.keep = thr ? take(4 * pc) : 0;
+  L.kscan = thr ? take(8 * (pc + 1)) : 0;
+  L.raw_peak_offset = thr ? take(8 * (nc + 1)) : 0;
+  int64_t scan_n = std::max<int64_t>(std::max<int64_t>(ec, bins), rc);
+  L.scan_part = take(8 * scan_part_elems(scan_n));
+  L.bw_w1 = take(8 * rc);
+  L.bw_w2 = take(8 * rc);
+  L.bw_ga = take(8 * rc);
+  L.bw_gb = take(8 * rc);
+  L.bw_dq = take(8 * rc);
+  L.bw_part = take(32 * parts);
+  L.bw_part6 = take(48 * hc);
+  L.total = o;
+  *out = b;
+  g_err.clear();
+  return XRD_OK;
+}
+
+int xrd_batch_sizes(const xrd_batch *b, xrd_sizes *out) {
+  if (!b || !out) return fail(XRD_ERR_INVALID_ARG, "NULL argument");
+  out->n_crystals = b->desc.n_crystals;
+  out->n_atoms = b->n_atoms;
+  out->refl_capacity = b->refl_cap;
+  out->peak_capacity = b->refl_cap;
+  out->workspace_bytes = b->ws.total;
+  out->half_capacity = b->half_cap;
+  return XRD_OK;
+}
+
+int xrd_batch_upload(xrd_batch *b, void *ws) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  hipStream_t s = stream_of(b);
+  const WsLayout &L = b->ws;
+  auto up = [&](int64_t off, const void *src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(at<char>(ws, off), src, bytes, hipMemcpyHostToDevice, s);
+  };
+  hipError_t e = hipSuccess;
+  if (e == hipSuccess) e = up(L.plan, b->plan.data(), sizeof(CrystalPlan) * b->plan.size());
+  if (e == hipSuccess) e = up(L.enum_chunk_crystal, b->enum_chunk_crystal.data(), 4 * b->enum_chunk_crystal.size());
+  if (e == hipSuccess) e = up(L.sf_items, b->sf_items.data(), sizeof(SfItem) * b->sf_items.size());
+  if (e == hipSuccess) e = up(L.sort_chunk_crystal, b->sort_chunk_crystal.data(), 4 * b->sort_chunk_crystal.size());
+  if (e == hipSuccess) e = up(L.hchunk_crystal, b->hchunk_crystal.data(), 4 * b->hchunk_crystal.size());
+  if (e == hipSuccess) e = up(L.bw_items, b->bw_items.data(), sizeof(BwItem) * b->bw_items.size());
+  if (e == hipSuccess) e = up(L.ab_items, b->ab_items.data(), sizeof(AbItem) * b->ab_items.size());
+  if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("upload: ") + hipGetErrorString(e));
+  launch_fill_i32(at<int32_t>(ws, L.err_flag), 1, 0, s);
+  // pageable copies complete before return, but the tables stay owned by the
+  // handle anyway; wait so that the handle may be destroyed right after
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("upload sync: ") + hipGetErrorString(e));
+  b->last_ws = ws;
+  return hip_check("upload");
+}
+
+int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  if (int e = check_refl(r)) return e;
+  const WsLayout &L = b->ws;
+  launch_enumerate(at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, at<int32_t>(ws, L.enum_chunk_crystal),
+                   (int64_t)b->enum_chunk_crystal.size(), b->desc.wavelength, at<int32_t>(ws, L.enum_count),
+                   at<int64_t>(ws, L.enum_prefix), at<int64_t>(ws, L.scan_part), r->h, r->k, r->l, r->q,
+                   r->two_theta, r->lp, r->refl_offset, stream_of(b));
+  b->last_ws = ws;
+  return hip_check("enumerate");
+}
+
+static void pack_atoms(xrd_batch *b, void *ws) {
+  const WsLayout &L = b->ws;
+  launch_atom_prep(at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, b->desc.n_species, b->desc.frac,
+                   b->desc.species, b->desc.occ, b->desc.bfac, at<AtomRec>(ws, L.atoms), at<int32_t>(ws, L.atom_orig),
+                   at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), at<int32_t>(ws, L.err_flag),
+                   stream_of(b));
+}
+
+int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, void *B, double *I) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  if (int e = check_refl(r)) return e;
+  if (!A || !B || !I) return fail(XRD_ERR_INVALID_ARG, "A, B and I must be non-NULL");
+  const WsLayout &L = b->ws;
+  pack_atoms(b, ws);
+  launch_sf(b->desc.precision == XRD_MIXED, b->desc.friedel != 0, at<SfItem>(ws, L.sf_items),
+            (int64_t)b->sf_items.size(), at<CrystalPlan>(ws, L.plan), r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
+            at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), b->desc.sf_coeff, A, B,
+            I, stream_of(b));
+  b->last_ws = ws;
+  return hip_check("structure_factors");
+}
+
+static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r) {
+  const WsLayout &L = b->ws;
+  SortArgs a;
+  a.plan = at<CrystalPlan>(ws, L.plan);
+  a.chunk_crystal = at<int32_t>(ws, L.sort_chunk_crystal);
+  a.n_chunks = (int64_t)b->sort_chunk_crystal.size();
+  a.refl_offset = r->refl_offset;
+  a.tt = r->two_theta;
+  a.h = r->h;
+  a.k = r->k;
+  a.l = r->l;
+  a.bin_count = at<int32_t>(ws, L.bin_count);
+  a.bin_start = at<int64_t>(ws, L.bin_start);
+  a.n_bins = b->n_bins;
+  a.skey = at<double>(ws, L.skey);
+  a.sidx = at<int32_t>(ws, L.sidx);
+  a.scan_part = at<int64_t>(ws, L.scan_part);
+  return a;
+}
+
+int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, xrd_peaks *p) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  if (int e = check_refl(r)) return e;
+  if (!I || !p || !p->two_theta || !p->intensity || !p->scaled || !p->mult || !p->first || !p->perm ||
+      !p->peak_offset)
+    return fail(XRD_ERR_INVALID_ARG, "peak arrays and I must be non-NULL");
+  const WsLayout &L = b->ws;
+  MergeArgs a;
+  a.sort = sort_args(b, ws, r);
+  a.n_c = b->desc.n_crystals;
+  a.refl_cap = b->refl_cap;
+  a.tol = b->desc.merge_tol;
+  a.thr = b->desc.rel_threshold;
+  a.inten = I;
+  a.flags = at<int32_t>(ws, L.flags);
+  a.pscan = at<int64_t>(ws, L.pscan);
+  a.cmax = at<uint64_t>(ws, L.cmax);
+  a.n_peaks = at<int64_t>(ws, L.n_peaks);
+  const bool thr = a.thr > 0.0;
+  a.tmp_tt = thr ? at<double>(ws, L.tmp_tt) : nullptr;
+  a.tmp_i = thr ? at<double>(ws, L.tmp_i) : nullptr;
+  a.tmp_y = thr ? at<double>(ws, L.tmp_y) : nullptr;
+  a.tmp_mult = thr ? at<int32_t>(ws, L.tmp_mult) : nullptr;
+  a.tmp_first = thr ? at<int64_t>(ws, L.tmp_first) : nullptr;
+  a.keep = thr ? at<int32_t>(ws, L.keep) : nullptr;
+  a.kscan = thr ? at<int64_t>(ws, L.kscan) : nullptr;
+  a.raw_peak_offset = thr ? at<int64_t>(ws, L.raw_peak_offset) : nullptr;
+  a.pk_tt = p->two_theta;
+  a.pk_i = p->intensity;
+  a.pk_y = p->scaled;
+  a.pk_mult = p->mult;
+  a.pk_first = p->first;
+  a.perm = p->perm;
+  a.peak_offset = p->peak_offset;
+  launch_merge(a, stream_of(b));
+  b->last_ws = ws;
+  return hip_check("merge_peaks");
+}
+
+static int check_grid(const xrd_grid *g) {
+  if (!g) return fail(XRD_ERR_INVALID_ARG, "grid is NULL");
+  if (!(g->n_points >= 1) || !(g->dt > 0.0) || !(g->sigma > 0.0) || !(g->window_sigmas > 0.0) ||
+      !std::isfinite(g->t0) || !std::isfinite(g->dt) || !std::isfinite(g->sigma) || !std::isfinite(g->window_sigmas))
+    return fail(XRD_ERR_INVALID_ARG, "grid needs n_points >= 1, dt > 0, sigma > 0, window_sigmas > 0");
+  return XRD_OK;
+}
+
+int xrd_pattern_forward(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, const xrd_grid *g, double *y) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  if (int e = check_refl(r)) return e;
+  if (int e = check_grid(g)) return e;
+  if (!I || !y) return fail(XRD_ERR_INVALID_ARG, "I and y must be non-NULL");
+  const SortArgs sa = sort_args(b, ws, r);
+  launch_sort(sa, stream_of(b));
+  launch_broaden_fwd(b->desc.n_crystals, r->refl_offset, sa.skey, sa.sidx, I, g->t0, g->dt, g->n_points, g->sigma,
+                     g->window_sigmas, y, stream_of(b));
+  b->last_ws = ws;
+  return hip_check("pattern_forward");
+}
+
+int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_grid *g, const double *dL_dy,
+                         double *dL_dfrac, double *dL_dbfac, double *dL_dlattice) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  if (int e = check_refl(r)) return e;
+  if (int e = check_grid(g)) return e;
+  if (!dL_dy || !dL_dlattice || (b->n_atoms > 0 && (!dL_dfrac || !dL_dbfac)))
+    return fail(XRD_ERR_INVALID_ARG, "gradient buffers must be non-NULL");
+  const WsLayout &L = b->ws;
+  hipStream_t s = stream_of(b);
+  const bool mixed = b->desc.precision == XRD_MIXED, friedel = b->desc.friedel != 0;
+  const CrystalPlan *plan = at<CrystalPlan>(ws, L.plan);
+  const SfItem *items = at<SfItem>(ws, L.sf_items);
+  const int64_t n_items = (int64_t)b->sf_items.size();
+  double *w1 = at<double>(ws, L.bw_w1), *w2 = at<double>(ws, L.bw_w2);
+  double *ga = at<double>(ws, L.bw_ga), *gb = at<double>(ws, L.bw_gb), *dq = at<double>(ws, L.bw_dq);
+  pack_atoms(b, ws);
+  launch_broaden_adj(items, n_items, friedel, r->refl_offset, r->two_theta, dL_dy, g->t0, g->dt, g->n_points,
+                     g->sigma, g->window_sigmas, w1, w2, s);
+  launch_sf_bw(mixed, friedel, items, n_items, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
+               b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
+               b->desc.sf_coeff, w1, w2, ga, gb, dq, s);
+  launch_atom_bw(mixed, friedel, at<BwItem>(ws, L.bw_items), (int64_t)b->bw_items.size(), plan, r->refl_offset,
+                 r->h, r->k, r->l, r->q, ga, gb, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
+                 at<int32_t>(ws, L.run_count), b->desc.sf_coeff, b->bw_tile, b->runs_cap_max,
+                 at<double>(ws, L.bw_part), s);
+  launch_atom_bw_reduce(at<AbItem>(ws, L.ab_items), (int64_t)b->ab_items.size(), plan, at<double>(ws, L.bw_part),
+                        at<int32_t>(ws, L.atom_orig), dL_dfrac, dL_dbfac, s);
+  launch_gstar_part(at<int32_t>(ws, L.hchunk_crystal), (int64_t)b->hchunk_crystal.size(), friedel, plan,
+                    r->refl_offset, r->h, r->k, r->l, dq, at<double>(ws, L.bw_part6), s);
+  launch_lattice_chain(plan, b->desc.n_crystals, at<double>(ws, L.bw_part6), dL_dlattice, s);
+  b->last_ws = ws;
+  return hip_check("pattern_backward");
+}
+
+int xrd_read_counts(xrd_batch *b, const xrd_refl *r, const xrd_peaks *p, int64_t *host_refl_offset,
+                    int64_t *host_peak_offset) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  hipStream_t s = stream_of(b);
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("sync: ") + hipGetErrorString(e));
+  const size_t n = (size_t)(b->desc.n_crystals + 1) * sizeof(int64_t);
+  if (host_refl_offset) {
+    if (!r || !r->refl_offset) return fail(XRD_ERR_INVALID_ARG, "refl_offset is NULL");
+    e = hipMemcpy(host_refl_offset, r->refl_offset, n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("copy refl_offset: ") + hipGetErrorString(e));
+  }
+  if (host_peak_offset) {
+    if (!p || !p->peak_offset) return fail(XRD_ERR_INVALID_ARG, "peak_offset is NULL");
+    e = hipMemcpy(host_peak_offset, p->peak_offset, n, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("copy peak_offset: ") + hipGetErrorString(e));
+  }
+  if (b->last_ws) {
+    int32_t flag = 0;
+    e = hipMemcpy(&flag, at<int32_t>(b->last_ws, b->ws.err_flag), 4, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("copy error flag: ") + hipGetErrorString(e));
+    if (flag) return fail(XRD_ERR_INVALID_ARG, "a species index was outside [0, n_species)");
+  }
+  return XRD_OK;
+}
+
+void xrd_batch_destroy(xrd_batch *b) { delete b; }
+
+}  // extern "C"

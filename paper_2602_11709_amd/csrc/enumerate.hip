@@ -1,0 +1,188 @@
+// Reciprocal-lattice enumeration inside the limiting sphere (paper, Section
+// 2: generation of the reciprocal lattice points within the physically
+// accessible sphere), with the per-reflection geometry q, 2theta and the
+// Lorentz-polarisation factor.
+//
+// Each crystal's search box [-H,H]x[-K,K]x[-L,L] is split at the origin; only
+// the points above it in lexicographic order are visited, since (h,k,l) and
+// (-h,-k,-l) share q, 2theta and LP bit for bit.  Two passes over fixed-size
+// chunks of that half box: count survivors per chunk, scan the counts, then
+// recompute the test and write each survivor and its Friedel mate.  The
+// output of a crystal is its full sphere shell in ascending (h, k, l) order:
+// the positive half occupies the upper half of the segment and mate i sits at
+// the mirror position, so no sort is needed for the hkl listing.
+//
+// q and 2theta are evaluated in double precision in a fixed order with FMA
+// contraction off, as the definition writes them.
+#include <math.h>
+
+#include "xrd_internal.h"
+
+namespace xrd {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kPer = kEnumChunk / kThreads;  // 8
+constexpr double kPi = 3.14159265358979323846;
+
+struct Hkl {
+  int h, k, l;
+};
+
+__device__ __forceinline__ Hkl decode(const CrystalPlan &P, int64_t p) {
+  // linear index of the full box (h outermost); the origin is the centre
+  const int64_t nl = 2 * P.L + 1, nk = 2 * P.K + 1;
+  const int64_t i = P.half_box + 1 + p;
+  Hkl r;
+  r.l = (int)(i % nl) - P.L;
+  const int64_t t = i / nl;
+  r.k = (int)(t % nk) - P.K;
+  r.h = (int)(t / nk) - P.H;
+  return r;
+}
+
+__device__ __forceinline__ double q_of(const CrystalPlan &P, const Hkl &m) {
+#pragma clang fp contract(off)
+  const double h = m.h, k = m.k, l = m.l;
+  const double hh = h * h, kk = k * k, ll = l * l, hk = h * k, hl = h * l, kl = k * l;
+  return P.gs[0] * hh + P.gs[1] * kk + P.gs[2] * ll + 2.0 * (P.gs[3] * hk + P.gs[4] * hl + P.gs[5] * kl);
+}
+
+// 2theta (deg) of q; negative when sin(theta) would exceed 1.
+__device__ __forceinline__ double two_theta_of(double q, double lambda) {
+#pragma clang fp contract(off)
+  const double s = 0.5 * lambda * sqrt(q);
+  if (s > 1.0) return -1.0;
+  return 2.0 * asin(s) * (180.0 / kPi);
+}
+
+__device__ __forceinline__ bool keep(const CrystalPlan &P, int64_t p, double lambda, Hkl *m, double *q,
+                                     double *tt) {
+  if (p >= P.half_box) return false;
+  *m = decode(P, p);
+  *q = q_of(P, *m);
+  if (*q < P.qlo || *q > P.qhi) return false;
+  *tt = two_theta_of(*q, lambda);
+  return *tt >= P.tmin && *tt <= P.tmax;
+}
+
+__device__ __forceinline__ double lp_of(double tt) {
+#pragma clang fp contract(off)
+  const double th = 0.5 * tt * (kPi / 180.0);
+  double st, ct;
+  sincos(th, &st, &ct);
+  const double c2 = cos(2.0 * th);
+  return (1.0 + c2 * c2) / (st * st * ct);
+}
+
+__global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__restrict__ plan,
+                                                         const int32_t *__restrict__ chunk_crystal,
+                                                         double lambda, int32_t *__restrict__ counts) {
+  const int chunk = blockIdx.x;
+  const CrystalPlan &P = plan[chunk_crystal[chunk]];
+  const int64_t p0 = (int64_t)(chunk - P.enum_chunk_begin) * kEnumChunk;
+  int n = 0;
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    Hkl m;
+    double q, tt;
+    n += keep(P, p0 + u * kThreads + threadIdx.x, lambda, &m, &q, &tt) ? 1 : 0;
+  }
+  // block sum
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) n += __shfl_xor(n, d, 64);
+  __shared__ int ws[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = n;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < kThreads / 64; ++w) s += ws[w];
+    counts[chunk] = s;
+  }
+}
+
+__global__ void k_enum_offsets(const CrystalPlan *__restrict__ plan, int64_t n_c, int64_t n_chunks,
+                               const int64_t *__restrict__ prefix, int64_t *__restrict__ refl_offset) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < n_c) refl_offset[c] = 2 * prefix[plan[c].enum_chunk_begin];
+  if (c == n_c) refl_offset[n_c] = 2 * prefix[n_chunks];
+}
+
+__global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__restrict__ plan,
+                                                        const int32_t *__restrict__ chunk_crystal,
+                                                        const int64_t *__restrict__ prefix, double lambda,
+                                                        int16_t *__restrict__ oh, int16_t *__restrict__ ok,
+                                                        int16_t *__restrict__ ol, double *__restrict__ oq,
+                                                        double *__restrict__ ott, double *__restrict__ olp) {
+  const int chunk = blockIdx.x;
+  const CrystalPlan &P = plan[chunk_crystal[chunk]];
+  const int64_t first_chunk = P.enum_chunk_begin;
+  const int64_t c_begin = prefix[first_chunk];
+  const int64_t rh = prefix[first_chunk + P.enum_chunks] - c_begin;  // positive-half count
+  const int64_t seg = 2 * c_begin;                                     // crystal's first reflection
+  int64_t rank = prefix[chunk] - c_begin;
+  const int64_t p0 = (int64_t)(chunk - first_chunk) * kEnumChunk;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __shared__ int wcount[kPer][kThreads / 64];
+  Hkl m[kPer];
+  double q[kPer], tt[kPer];
+  bool kp[kPer];
+  int wrank[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    kp[u] = keep(P, p0 + u * kThreads + threadIdx.x, lambda, &m[u], &q[u], &tt[u]);
+    const uint64_t b = __ballot(kp[u]);
+    wrank[u] = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+    if (lane == 0) wcount[u][wid] = __popcll(b);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    int before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) {
+      const int cnt = wcount[u][w];
+      before += w < wid ? cnt : 0;
+      total += cnt;
+    }
+    if (kp[u]) {
+      const int64_t r = rank + before + wrank[u];
+      const int64_t pos = seg + rh + r;
+      const int64_t mate = seg + rh - 1 - r;
+      const double lp = lp_of(tt[u]);
+      oh[pos] = (int16_t)m[u].h;
+      ok[pos] = (int16_t)m[u].k;
+      ol[pos] = (int16_t)m[u].l;
+      oh[mate] = (int16_t)(-m[u].h);
+      ok[mate] = (int16_t)(-m[u].k);
+      ol[mate] = (int16_t)(-m[u].l);
+      oq[pos] = q[u];
+      oq[mate] = q[u];
+      ott[pos] = tt[u];
+      ott[mate] = tt[u];
+      olp[pos] = lp;
+      olp[mate] = lp;
+    }
+    rank += total;
+  }
+}
+
+}  // namespace
+
+void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk_crystal, int64_t n_chunks,
+                      double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h,
+                      int16_t *k, int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset,
+                      hipStream_t s) {
+  if (n_chunks > 0)
+    hipLaunchKernelGGL(k_enum_count, dim3((unsigned)n_chunks), dim3(kThreads), 0, s, plan, chunk_crystal, lambda,
+                       counts);
+  launch_scan_i32(counts, n_chunks, nullptr, prefix, scan_part, s);
+  hipLaunchKernelGGL(k_enum_offsets, dim3((unsigned)((n_c + 1 + 255) / 256)), dim3(256), 0, s, plan, n_c, n_chunks,
+                     prefix, refl_offset);
+  if (n_chunks > 0)
+    hipLaunchKernelGGL(k_enum_fill, dim3((unsigned)n_chunks), dim3(kThreads), 0, s, plan, chunk_crystal, prefix,
+                       lambda, h, k, l, q, tt, lp);
+}
+
+}  // namespace xrd

@@ -1,0 +1,777 @@
+// Structure factors (paper, Section 2: the nested loops summing atomic
+// contributions for each reflection, with the Debye-Waller and
+// Lorentz-polarisation corrections; Section 4.2: this is where the time goes
+// for large cells).
+//
+//   F(hkl) = sum_t f_t(s) sum_{j in t} occ_j exp(-B_j s^2) exp(2 pi i (h x_j + k y_j + l z_j))
+//
+// Atoms are first packed per crystal and sorted by species (a stable
+// partition), so the Cromer-Mann factor f_t(s) is evaluated once per
+// (reflection, species) and multiplies a partial sum over that species'
+// atoms instead of every term.
+//
+// One wavefront owns one work item: 64 x kSfRpt reflections of one crystal.
+// It walks the crystal's atoms in order; the atom index is uniform across the
+// wavefront, so the atom records stream through the scalar cache into SGPRs
+// and are broadcast to every lane with no LDS traffic and no barrier.  Each
+// lane keeps kSfRpt reflections in registers.
+//
+// Mixed precision (XRD_MIXED): t = h x + k y + l z in double, reduced mod 1
+// in double (v_fract_f64), then sin/cos of the revolution in single precision
+// by v_sin_f32 / v_cos_f32 (which take revolutions); weights
+// occ exp(-B s^2) = exp2(log2(occ) - B log2(e) s^2) in single precision;
+// single-precision sums over runs of at most kAtomTile atoms, folded into a
+// compensated (two-sum) float accumulator.  Plain path (XRD_FP64): the same
+// loop in double with sincospi.
+//
+// Friedel: F(-h) = conj F(h) for real scattering factors, so with the option
+// on only the positive half of each crystal's shell is evaluated and the
+// conjugate is written to the mirror position.
+#include <math.h>
+
+#include <type_traits>
+
+#include "xrd_internal.h"
+
+namespace xrd {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kAtomTile = 64;  // atoms per single-precision partial sum
+constexpr float kLog2e = 1.4426950408889634f;
+
+// ---- atom packing ----------------------------------------------------------
+
+// One wavefront per crystal: species histogram in LDS, ascending-species
+// runs, then a stable scatter (peeling one species per step with a ballot).
+__global__ __launch_bounds__(64) void k_atom_prep(const CrystalPlan *__restrict__ plan, int32_t n_species,
+                                                  const double *__restrict__ frac, const int32_t *__restrict__ species,
+                                                  const double *__restrict__ occ, const double *__restrict__ bfac,
+                                                  AtomRec *__restrict__ atoms, int32_t *__restrict__ orig,
+                                                  SpeciesRun *__restrict__ runs, int32_t *__restrict__ run_count,
+                                                  int32_t *__restrict__ err) {
+  extern __shared__ int32_t cursor[];  // n_species
+  const int c = blockIdx.x;
+  const CrystalPlan &P = plan[c];
+  const int64_t a0 = P.atom_begin, a1 = P.atom_end;
+  const int lane = threadIdx.x;
+  for (int t = lane; t < n_species; t += 64) cursor[t] = 0;
+  __syncthreads();
+  for (int64_t j = a0 + lane; j < a1; j += 64) {
+    int sp = species[j];
+    if (sp < 0 || sp >= n_species) {
+      atomicOr(err, 1);
+      sp = 0;
+    }
+    atomicAdd(&cursor[sp], 1);
+  }
+  __syncthreads();
+  // ascending-species runs and cursors (exclusive scan of the histogram)
+  int64_t running = a0;
+  int nruns = 0;
+  for (int t0 = 0; t0 < n_species; t0 += 64) {
+    const int t = t0 + lane;
+    const int v = t < n_species ? cursor[t] : 0;
+    int inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      int o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    const int tot = __shfl(inc, 63, 64);
+    const uint64_t nz = __ballot(v > 0);
+    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(nz >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nz, 0u));
+    const int64_t start = running + inc - v;
+    if (v > 0) {
+      SpeciesRun r;
+      r.begin = (int32_t)start;
+      r.end = (int32_t)(start + v);
+      r.species = t;
+      r.local = nruns + rank;
+      runs[P.run_begin + nruns + rank] = r;
+    }
+    if (t < n_species) cursor[t] = (int32_t)start;
+    __syncthreads();
+    running += tot;
+    nruns += __popcll(nz);
+  }
+  if (lane == 0) run_count[c] = nruns;
+  __syncthreads();
+  for (int64_t base = a0; base < a1; base += 64) {
+    const int64_t j = base + lane;
+    bool active = j < a1;
+    int sp = -1;
+    if (active) {
+      sp = species[j];
+      if (sp < 0 || sp >= n_species) sp = 0;
+    }
+    while (true) {
+      const uint64_t act = __ballot(active);
+      if (act == 0) break;
+      const int leader = __builtin_ctzll(act);
+      const int t = __shfl(sp, leader, 64);
+      const uint64_t m = __ballot(active && sp == t);
+      const int base_pos = cursor[t];
+      __syncthreads();
+      if (active && sp == t) {
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const int pos = base_pos + rank;
+        AtomRec a;
+        a.x = frac[3 * j];
+        a.y = frac[3 * j + 1];
+        a.z = frac[3 * j + 2];
+        a.occ = occ[j];
+        a.bfac = bfac[j];
+        a.log2occ = __log2f((float)a.occ);
+        a.bl2e = (float)a.bfac * kLog2e;
+        atoms[pos] = a;
+        orig[pos] = (int32_t)j;
+        active = false;
+      }
+      if (lane == leader) cursor[t] = base_pos + __popcll(m);
+      __syncthreads();
+    }
+  }
+}
+
+// ---- structure factors -----------------------------------------------------
+
+// (s, e) += x with the rounding error of the addition carried in e (two-sum).
+__device__ __forceinline__ void two_sum_acc(float &s, float &e, float x) {
+#pragma clang fp contract(off)
+  const float t = s + x;
+  const float bp = t - s;
+  e += (s - (t - bp)) + (x - bp);
+  s = t;
+}
+
+// Cromer-Mann factor at s^2 in single precision via exp2.
+__device__ __forceinline__ float fsc_f32(const double *__restrict__ c9, float s2) {
+  float f = (float)c9[8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f = fmaf((float)c9[i], __builtin_amdgcn_exp2f(-(float)c9[4 + i] * kLog2e * s2), f);
+  return f;
+}
+
+__device__ __forceinline__ double fsc_f64(const double *__restrict__ c9, double s2) {
+  double f = c9[8];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) f = fma(c9[i], exp(-c9[4 + i] * s2), f);
+  return f;
+}
+
+template <bool MIXED, bool FRIEDEL>
+__global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ items, int64_t n_items,
+                                                 const CrystalPlan *__restrict__ plan,
+                                                 const int64_t *__restrict__ refl_offset,
+                                                 const int16_t *__restrict__ hh, const int16_t *__restrict__ kk,
+                                                 const int16_t *__restrict__ ll, const double *__restrict__ qq,
+                                                 const double *__restrict__ lpp, const AtomRec *__restrict__ atoms,
+                                                 const SpeciesRun *__restrict__ runs,
+                                                 const int32_t *__restrict__ run_count,
+                                                 const double *__restrict__ coeff, void *__restrict__ Aout,
+                                                 void *__restrict__ Bout, double *__restrict__ Iout) {
+  constexpr int R = kSfRpt;
+  // the wavefront index is uniform; say so, so that everything derived from
+  // the item (crystal, runs, atom records) is loaded once per wave into SGPRs
+  const int64_t item =
+      (int64_t)blockIdx.x * (kThreads / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (item >= n_items) return;
+  const SfItem it = items[item];
+  const int64_t r0 = refl_offset[it.crystal], r1 = refl_offset[it.crystal + 1];
+  const int64_t nref = r1 - r0;
+  const int64_t first = FRIEDEL ? r0 + nref / 2 : r0;
+  const int64_t count = FRIEDEL ? nref / 2 : nref;
+  const int64_t tbase = (int64_t)it.tile * kSfTile;
+  if (tbase >= count) return;
+  const int lane = threadIdx.x & 63;
+
+  int64_t idx[R];
+  bool valid[R];
+  double h[R], k[R], l[R], s2d[R];
+  float s2[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int64_t t = tbase + u * 64 + lane;
+    valid[u] = t < count;
+    idx[u] = first + (valid[u] ? t : 0);
+    h[u] = hh[idx[u]];
+    k[u] = kk[idx[u]];
+    l[u] = ll[idx[u]];
+    s2d[u] = 0.25 * qq[idx[u]];
+    s2[u] = (float)s2d[u];
+  }
+
+  const CrystalPlan &P = plan[it.crystal];
+  const SpeciesRun *cr = runs + P.run_begin;
+  const int nr = run_count[it.crystal];
+
+  if constexpr (MIXED) {
+    float Sa[R], Ea[R], Sb[R], Eb[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) Sa[u] = Ea[u] = Sb[u] = Eb[u] = 0.f;
+    for (int ir = 0; ir < nr; ++ir) {
+      const SpeciesRun run = cr[ir];
+      const double *c9 = coeff + 9 * run.species;
+      float f[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) f[u] = fsc_f32(c9, s2[u]);
+      for (int j0 = run.begin; j0 < run.end; j0 += kAtomTile) {
+        const int j1 = min(j0 + kAtomTile, run.end);
+        float pa[R], pb[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) pa[u] = pb[u] = 0.f;
+        for (int j = j0; j < j1; ++j) {
+          const AtomRec a = atoms[j];
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+            const float rho = (float)__builtin_amdgcn_fract(t);
+            const float sn = __builtin_amdgcn_sinf(rho);
+            const float cs = __builtin_amdgcn_cosf(rho);
+            const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
+            pa[u] = fmaf(w, cs, pa[u]);
+            pb[u] = fmaf(w, sn, pb[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          two_sum_acc(Sa[u], Ea[u], f[u] * pa[u]);
+          two_sum_acc(Sb[u], Eb[u], f[u] * pb[u]);
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      if (!valid[u]) continue;
+      const double A = (double)Sa[u] + (double)Ea[u];
+      const double B = (double)Sb[u] + (double)Eb[u];
+      const double I = (A * A + B * B) * lpp[idx[u]];
+      float *Af = (float *)Aout;
+      float *Bf = (float *)Bout;
+      Af[idx[u]] = (float)A;
+      Bf[idx[u]] = (float)B;
+      Iout[idx[u]] = I;
+      if (FRIEDEL) {
+        const int64_t m = r0 + r1 - 1 - idx[u];
+        Af[m] = (float)A;
+        Bf[m] = -(float)B;
+        Iout[m] = I;
+      }
+    }
+  } else {
+    double Sa[R], Sb[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) Sa[u] = Sb[u] = 0.0;
+    for (int ir = 0; ir < nr; ++ir) {
+      const SpeciesRun run = cr[ir];
+      const double *c9 = coeff + 9 * run.species;
+      double f[R], pa[R], pb[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        f[u] = fsc_f64(c9, s2d[u]);
+        pa[u] = pb[u] = 0.0;
+      }
+      for (int j = run.begin; j < run.end; ++j) {
+        const AtomRec a = atoms[j];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+          const double rho = t - rint(t);
+          double sn, cs;
+          sincospi(2.0 * rho, &sn, &cs);
+          const double w = a.occ * exp(-a.bfac * s2d[u]);
+          pa[u] = fma(w, cs, pa[u]);
+          pb[u] = fma(w, sn, pb[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        Sa[u] = fma(f[u], pa[u], Sa[u]);
+        Sb[u] = fma(f[u], pb[u], Sb[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      if (!valid[u]) continue;
+      const double A = Sa[u], B = Sb[u];
+      const double I = (A * A + B * B) * lpp[idx[u]];
+      double *Ad = (double *)Aout;
+      double *Bd = (double *)Bout;
+      Ad[idx[u]] = A;
+      Bd[idx[u]] = B;
+      Iout[idx[u]] = I;
+      if (FRIEDEL) {
+        const int64_t m = r0 + r1 - 1 - idx[u];
+        Ad[m] = A;
+        Bd[m] = -B;
+        Iout[m] = I;
+      }
+    }
+  }
+}
+
+
+// ---- adjoint ---------------------------------------------------------------
+//
+// Reflection-major pass: for each evaluated reflection recompute
+//   A + iB = sum_t f_t S_t,                 S_t  = sum_{j in t} occ_j e^{-B_j s^2} e^{i phi_j}
+//   d(A + iB)/ds^2 = sum_t (f'_t S_t + f_t S'_t),  S'_t = sum_{j in t} (-B_j) occ_j e^{-B_j s^2} e^{i phi_j}
+// with f'_t = -sum_i a_i b_i e^{-b_i s^2}; then, with gI = dL/dI summed over
+// the reflection and (when Friedel pairing is on) its mate,
+//   gA = 2 LP A gI,  gB = 2 LP B gI,
+//   dL/dq = gI |F|^2 dLP/dq + (gA dA/ds^2 + gB dB/ds^2) / 4 + m w2 I d(2theta)/dq,
+// where w1, w2 come from the grid adjoint and m = 2 with pairing, else 1.
+
+__device__ __forceinline__ void fsc_df_f32(const double *__restrict__ c9, float s2, float *f, float *df) {
+  float a = (float)c9[8], d = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float ai = (float)c9[i], bi = (float)c9[4 + i];
+    const float e = __builtin_amdgcn_exp2f(-bi * kLog2e * s2);
+    a = fmaf(ai, e, a);
+    d = fmaf(-ai * bi, e, d);
+  }
+  *f = a;
+  *df = d;
+}
+
+__device__ __forceinline__ void fsc_df_f64(const double *__restrict__ c9, double s2, double *f, double *df) {
+  double a = c9[8], d = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double e = exp(-c9[4 + i] * s2);
+    a = fma(c9[i], e, a);
+    d = fma(-c9[i] * c9[4 + i], e, d);
+  }
+  *f = a;
+  *df = d;
+}
+
+template <bool MIXED>
+__global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ items, int64_t n_items, bool friedel,
+                                                    const CrystalPlan *__restrict__ plan,
+                                                    const int64_t *__restrict__ refl_offset,
+                                                    const int16_t *__restrict__ hh, const int16_t *__restrict__ kk,
+                                                    const int16_t *__restrict__ ll, const double *__restrict__ qq,
+                                                    const double *__restrict__ lpp, double lambda,
+                                                    const AtomRec *__restrict__ atoms,
+                                                    const SpeciesRun *__restrict__ runs,
+                                                    const int32_t *__restrict__ run_count,
+                                                    const double *__restrict__ coeff, const double *__restrict__ w1,
+                                                    const double *__restrict__ w2, double *__restrict__ ga,
+                                                    double *__restrict__ gb, double *__restrict__ dq) {
+  constexpr int R = kSfRpt;
+  // the wavefront index is uniform; say so, so that everything derived from
+  // the item (crystal, runs, atom records) is loaded once per wave into SGPRs
+  const int64_t item =
+      (int64_t)blockIdx.x * (kThreads / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  if (item >= n_items) return;
+  const SfItem it = items[item];
+  const int64_t r0 = refl_offset[it.crystal], r1 = refl_offset[it.crystal + 1];
+  const int64_t nref = r1 - r0;
+  const int64_t first = friedel ? r0 + nref / 2 : r0;
+  const int64_t count = friedel ? nref / 2 : nref;
+  const int64_t tbase = (int64_t)it.tile * kSfTile;
+  if (tbase >= count) return;
+  const int lane = threadIdx.x & 63;
+  int64_t idx[R];
+  bool valid[R];
+  double h[R], k[R], l[R], s2d[R];
+  float s2[R];
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    const int64_t t = tbase + u * 64 + lane;
+    valid[u] = t < count;
+    idx[u] = first + (valid[u] ? t : 0);
+    h[u] = hh[idx[u]];
+    k[u] = kk[idx[u]];
+    l[u] = ll[idx[u]];
+    s2d[u] = 0.25 * qq[idx[u]];
+    s2[u] = (float)s2d[u];
+  }
+  const CrystalPlan &P = plan[it.crystal];
+  const SpeciesRun *cr = runs + P.run_begin;
+  const int nr = run_count[it.crystal];
+  double A[R], B[R], dA[R], dB[R];
+  if constexpr (MIXED) {
+    float Sa[R], Ea[R], Sb[R], Eb[R], Sda[R], Eda[R], Sdb[R], Edb[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) Sa[u] = Ea[u] = Sb[u] = Eb[u] = Sda[u] = Eda[u] = Sdb[u] = Edb[u] = 0.f;
+    for (int ir = 0; ir < nr; ++ir) {
+      const SpeciesRun run = cr[ir];
+      const double *c9 = coeff + 9 * run.species;
+      float f[R], df[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) fsc_df_f32(c9, s2[u], &f[u], &df[u]);
+      for (int j0 = run.begin; j0 < run.end; j0 += kAtomTile) {
+        const int j1 = min(j0 + kAtomTile, run.end);
+        float pa[R], pb[R], qa[R], qb[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) pa[u] = pb[u] = qa[u] = qb[u] = 0.f;
+        for (int j = j0; j < j1; ++j) {
+          const AtomRec a = atoms[j];
+          const float nb = -(float)a.bfac;
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+            const float rho = (float)__builtin_amdgcn_fract(t);
+            const float sn = __builtin_amdgcn_sinf(rho);
+            const float cs = __builtin_amdgcn_cosf(rho);
+            const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
+            const float wc = w * cs, ws = w * sn;
+            pa[u] += wc;
+            pb[u] += ws;
+            qa[u] = fmaf(nb, wc, qa[u]);
+            qb[u] = fmaf(nb, ws, qb[u]);
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          two_sum_acc(Sa[u], Ea[u], f[u] * pa[u]);
+          two_sum_acc(Sb[u], Eb[u], f[u] * pb[u]);
+          two_sum_acc(Sda[u], Eda[u], fmaf(df[u], pa[u], f[u] * qa[u]));
+          two_sum_acc(Sdb[u], Edb[u], fmaf(df[u], pb[u], f[u] * qb[u]));
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      A[u] = (double)Sa[u] + (double)Ea[u];
+      B[u] = (double)Sb[u] + (double)Eb[u];
+      dA[u] = (double)Sda[u] + (double)Eda[u];
+      dB[u] = (double)Sdb[u] + (double)Edb[u];
+    }
+  } else {
+#pragma unroll
+    for (int u = 0; u < R; ++u) A[u] = B[u] = dA[u] = dB[u] = 0.0;
+    for (int ir = 0; ir < nr; ++ir) {
+      const SpeciesRun run = cr[ir];
+      const double *c9 = coeff + 9 * run.species;
+      double f[R], df[R], pa[R], pb[R], qa[R], qb[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        fsc_df_f64(c9, s2d[u], &f[u], &df[u]);
+        pa[u] = pb[u] = qa[u] = qb[u] = 0.0;
+      }
+      for (int j = run.begin; j < run.end; ++j) {
+        const AtomRec a = atoms[j];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+          const double rho = t - rint(t);
+          double sn, cs;
+          sincospi(2.0 * rho, &sn, &cs);
+          const double w = a.occ * exp(-a.bfac * s2d[u]);
+          const double wc = w * cs, ws = w * sn;
+          pa[u] += wc;
+          pb[u] += ws;
+          qa[u] = fma(-a.bfac, wc, qa[u]);
+          qb[u] = fma(-a.bfac, ws, qb[u]);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        A[u] = fma(f[u], pa[u], A[u]);
+        B[u] = fma(f[u], pb[u], B[u]);
+        dA[u] += df[u] * pa[u] + f[u] * qa[u];
+        dB[u] += df[u] * pb[u] + f[u] * qb[u];
+      }
+    }
+  }
+  const double m = friedel ? 2.0 : 1.0;
+  const double l2 = lambda * lambda;
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    if (!valid[u]) continue;
+    const int64_t i = idx[u];
+    const double q = qq[i], lp = lpp[i];
+    const double us = 0.25 * l2 * q;  // sin^2(theta)
+    const double sq = sqrt(1.0 - us);
+    const double num = 1.0 + (1.0 - 2.0 * us) * (1.0 - 2.0 * us);
+    const double den = us * sq;
+    const double dnum = -4.0 * (1.0 - 2.0 * us);
+    const double dden = (2.0 - 3.0 * us) / (2.0 * sq);
+    const double dlp_dq = (dnum * den - num * dden) / (den * den) * (0.25 * l2);
+    const double dtt_dq = (360.0 / 3.14159265358979323846) * lambda / (4.0 * sqrt(q) * sq);
+    const double f2 = A[u] * A[u] + B[u] * B[u];
+    const double gI = m * w1[i];
+    const double gA = 2.0 * lp * A[u] * gI, gB = 2.0 * lp * B[u] * gI;
+    ga[i] = gA;
+    gb[i] = gB;
+    dq[i] = gI * f2 * dlp_dq + 0.25 * (gA * dA[u] + gB * dB[u]) + m * w2[i] * f2 * lp * dtt_dq;
+  }
+}
+
+// Atom-major pass: block = (crystal, 256 atoms, chunk of kHalfChunk evaluated
+// reflections).  Reflection tiles are staged in LDS with the scattering
+// factor of every species of the crystal; each thread accumulates for its atom
+//   dx += h P, dy += k P, dz += l P with P = w (gB cos phi - gA sin phi),
+//   dB += s^2 Q with Q = w (gA cos phi + gB sin phi),   w = occ f e^{-B s^2},
+// and writes the chunk's partial sums (the reduction applies 2 pi and -1).
+template <bool MIXED>
+__global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__ items, bool friedel,
+                                                      const CrystalPlan *__restrict__ plan,
+                                                      const int64_t *__restrict__ refl_offset,
+                                                      const int16_t *__restrict__ hh, const int16_t *__restrict__ kk,
+                                                      const int16_t *__restrict__ ll, const double *__restrict__ qq,
+                                                      const double *__restrict__ ga, const double *__restrict__ gb,
+                                                      const AtomRec *__restrict__ atoms,
+                                                      const SpeciesRun *__restrict__ runs,
+                                                      const int32_t *__restrict__ run_count,
+                                                      const double *__restrict__ coeff, int tile, int runs_cap,
+                                                      double4 *__restrict__ part) {
+  using real = typename std::conditional<MIXED, float, double>::type;
+  extern __shared__ __align__(16) unsigned char smem[];
+  double *th = (double *)smem;
+  double *tk = th + tile;
+  double *tl = tk + tile;
+  real *ts2 = (real *)(tl + tile);
+  real *tga = ts2 + tile;
+  real *tgb = tga + tile;
+  real *tf = tgb + tile;  // [tile][runs_cap]
+
+  const BwItem it = items[blockIdx.x];
+  const CrystalPlan &P = plan[it.crystal];
+  const int64_t r0 = refl_offset[it.crystal], r1 = refl_offset[it.crystal + 1];
+  const int64_t nref = r1 - r0;
+  const int64_t first = friedel ? r0 + nref / 2 : r0;
+  const int64_t count = friedel ? nref / 2 : nref;
+  const int64_t na = P.atom_end - P.atom_begin;
+  const int64_t ja = (int64_t)it.ablock * kAtomBlock + threadIdx.x;  // atom within crystal
+  const bool valid = ja < na;
+  const int64_t j = P.atom_begin + (valid ? ja : 0);
+  double4 *out = part + P.part_begin + (int64_t)it.chunk * na;
+  const int64_t e0 = (int64_t)it.chunk * kHalfChunk;
+  const int64_t e1 = min(e0 + (int64_t)kHalfChunk, count);
+  if (e0 >= e1) {  // chunk beyond this crystal's reflections: zero partials
+    if (valid) out[ja] = make_double4(0.0, 0.0, 0.0, 0.0);
+    return;
+  }
+  const SpeciesRun *cr = runs + P.run_begin;
+  const int nr = run_count[it.crystal];
+  int myrun = 0;
+  for (int ir = 0; ir < nr; ++ir)
+    if (j >= cr[ir].begin && j < cr[ir].end) myrun = ir;
+  const AtomRec a = atoms[j];
+  double sx = 0.0, sy = 0.0, sz = 0.0, sB = 0.0;
+  for (int64_t t0 = e0; t0 < e1; t0 += tile) {
+    __syncthreads();
+    for (int r = threadIdx.x; r < tile; r += kThreads) {
+      const int64_t e = t0 + r;
+      if (e < e1) {
+        const int64_t i = first + e;
+        th[r] = hh[i];
+        tk[r] = kk[i];
+        tl[r] = ll[i];
+        ts2[r] = (real)(0.25 * qq[i]);
+        tga[r] = (real)ga[i];
+        tgb[r] = (real)gb[i];
+      } else {
+        th[r] = tk[r] = tl[r] = 0.0;
+        ts2[r] = tga[r] = tgb[r] = (real)0;
+      }
+    }
+    __syncthreads();
+    for (int x = threadIdx.x; x < tile * nr; x += kThreads) {
+      const int r = x / nr, ir = x - r * nr;
+      const double *c9 = coeff + 9 * cr[ir].species;
+      if constexpr (MIXED) tf[r * runs_cap + ir] = fsc_f32(c9, ts2[r]);
+      else tf[r * runs_cap + ir] = fsc_f64(c9, ts2[r]);
+    }
+    __syncthreads();
+    if (valid) {
+      const int nt = (int)min((int64_t)tile, e1 - t0);
+      real px = 0, py = 0, pz = 0, pB = 0;
+      for (int r = 0; r < nt; ++r) {
+        const double t = fma(th[r], a.x, fma(tk[r], a.y, tl[r] * a.z));
+        real sn, cs, w;
+        if constexpr (MIXED) {
+          const float rho = (float)__builtin_amdgcn_fract(t);
+          sn = __builtin_amdgcn_sinf(rho);
+          cs = __builtin_amdgcn_cosf(rho);
+          w = tf[r * runs_cap + myrun] * __builtin_amdgcn_exp2f(fmaf(-a.bl2e, ts2[r], a.log2occ));
+        } else {
+          const double rho = t - rint(t);
+          sincospi(2.0 * rho, &sn, &cs);
+          w = tf[r * runs_cap + myrun] * a.occ * exp(-a.bfac * ts2[r]);
+        }
+        const real pP = w * (tgb[r] * cs - tga[r] * sn);
+        const real pQ = w * (tga[r] * cs + tgb[r] * sn);
+        px += (real)th[r] * pP;
+        py += (real)tk[r] * pP;
+        pz += (real)tl[r] * pP;
+        pB += ts2[r] * pQ;
+      }
+      sx += (double)px;
+      sy += (double)py;
+      sz += (double)pz;
+      sB += (double)pB;
+    }
+  }
+  if (valid) out[ja] = make_double4(sx, sy, sz, sB);
+}
+
+// Sum of the chunk partials in chunk order; scatter to the caller's atom order.
+
+__global__ __launch_bounds__(kThreads) void k_atom_bw_reduce(const AbItem *__restrict__ items,
+                                                             const CrystalPlan *__restrict__ plan,
+                                                             const double4 *__restrict__ part,
+                                                             const int32_t *__restrict__ orig,
+                                                             double *__restrict__ dfrac, double *__restrict__ dbfac) {
+  const AbItem it = items[blockIdx.x];
+  const CrystalPlan &P = plan[it.crystal];
+  const int64_t na = P.atom_end - P.atom_begin;
+  const int64_t ja = (int64_t)it.ablock * kAtomBlock + threadIdx.x;
+  if (ja >= na) return;
+  const double4 *p = part + P.part_begin + ja;
+  double sx = 0.0, sy = 0.0, sz = 0.0, sB = 0.0;
+  for (int k = 0; k < P.n_hchunks; ++k) {
+    const double4 v = p[(int64_t)k * na];
+    sx += v.x;
+    sy += v.y;
+    sz += v.z;
+    sB += v.w;
+  }
+  const double tp = 2.0 * 3.14159265358979323846;
+  const int64_t o = orig[P.atom_begin + ja];
+  dfrac[3 * o] = tp * sx;
+  dfrac[3 * o + 1] = tp * sy;
+  dfrac[3 * o + 2] = tp * sz;
+  dbfac[o] = -sB;
+}
+
+// Per adjoint chunk: sum of dL/dq (h^2, k^2, l^2, 2hk, 2hl, 2kl), fixed-order block reduction.
+__global__ __launch_bounds__(kThreads) void k_gstar_part(const int32_t *__restrict__ hchunk_crystal, bool friedel,
+                                                         const CrystalPlan *__restrict__ plan,
+                                                         const int64_t *__restrict__ refl_offset,
+                                                         const int16_t *__restrict__ hh,
+                                                         const int16_t *__restrict__ kk,
+                                                         const int16_t *__restrict__ ll,
+                                                         const double *__restrict__ dq, double *__restrict__ part6) {
+  const int32_t c = hchunk_crystal[blockIdx.x];
+  const CrystalPlan &P = plan[c];
+  const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
+  const int64_t first = friedel ? r0 + (r1 - r0) / 2 : r0;
+  const int64_t count = friedel ? (r1 - r0) / 2 : r1 - r0;
+  const int64_t e0 = (int64_t)(blockIdx.x - P.hchunk_begin) * kHalfChunk;
+  double acc[6] = {0, 0, 0, 0, 0, 0};
+  for (int u = 0; u < kHalfChunk / kThreads; ++u) {
+    const int64_t e = e0 + u * kThreads + threadIdx.x;
+    if (e >= count) break;
+    const int64_t i = first + e;
+    const double g = dq[i], h = hh[i], k = kk[i], l = ll[i];
+    acc[0] += g * h * h;
+    acc[1] += g * k * k;
+    acc[2] += g * l * l;
+    acc[3] += 2.0 * g * h * k;
+    acc[4] += 2.0 * g * h * l;
+    acc[5] += 2.0 * g * k * l;
+  }
+  __shared__ double red[6][kThreads / 64];
+  for (int e = 0; e < 6; ++e) {
+    double v = acc[e];
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    if ((threadIdx.x & 63) == 0) red[e][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    double v = 0.0;
+    for (int w = 0; w < kThreads / 64; ++w) v += red[threadIdx.x][w];
+    part6[(int64_t)blockIdx.x * 6 + threadIdx.x] = v;
+  }
+}
+
+}  // namespace
+
+void launch_atom_prep(const CrystalPlan *plan, int64_t n_c, int32_t n_species, const double *frac,
+                      const int32_t *species, const double *occ, const double *bfac, AtomRec *atoms, int32_t *orig,
+                      SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s) {
+  if (n_c <= 0) return;
+  hipLaunchKernelGGL(k_atom_prep, dim3((unsigned)n_c), dim3(64), (size_t)n_species * sizeof(int32_t), s, plan,
+                     n_species, frac, species, occ, bfac, atoms, orig, runs, run_count, err);
+}
+
+void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
+               const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
+               const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
+               const double *coeff, void *A, void *B, double *I, hipStream_t s) {
+  if (n_items <= 0) return;
+  const dim3 grid((unsigned)((n_items + 3) / 4)), block(kThreads);
+  if (mixed) {
+    if (friedel)
+      hipLaunchKernelGGL((k_sf<true, true>), grid, block, 0, s, items, n_items, plan, refl_offset, h, k, l, q, lp,
+                         atoms, runs, run_count, coeff, A, B, I);
+    else
+      hipLaunchKernelGGL((k_sf<true, false>), grid, block, 0, s, items, n_items, plan, refl_offset, h, k, l, q, lp,
+                         atoms, runs, run_count, coeff, A, B, I);
+  } else {
+    if (friedel)
+      hipLaunchKernelGGL((k_sf<false, true>), grid, block, 0, s, items, n_items, plan, refl_offset, h, k, l, q, lp,
+                         atoms, runs, run_count, coeff, A, B, I);
+    else
+      hipLaunchKernelGGL((k_sf<false, false>), grid, block, 0, s, items, n_items, plan, refl_offset, h, k, l, q, lp,
+                         atoms, runs, run_count, coeff, A, B, I);
+  }
+}
+
+}  // namespace xrd
+
+namespace xrd {
+
+void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
+                  const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
+                  const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
+                  const int32_t *run_count, const double *coeff, const double *w1, const double *w2, double *ga,
+                  double *gb, double *dq, hipStream_t s) {
+  if (n_items <= 0) return;
+  const dim3 grid((unsigned)((n_items + 3) / 4)), block(kThreads);
+  if (mixed)
+    hipLaunchKernelGGL(k_sf_bw<true>, grid, block, 0, s, items, n_items, friedel, plan, refl_offset, h, k, l, q, lp,
+                       lambda, atoms, runs, run_count, coeff, w1, w2, ga, gb, dq);
+  else
+    hipLaunchKernelGGL(k_sf_bw<false>, grid, block, 0, s, items, n_items, friedel, plan, refl_offset, h, k, l, q, lp,
+                       lambda, atoms, runs, run_count, coeff, w1, w2, ga, gb, dq);
+}
+
+size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap) {
+  const size_t rs = mixed ? sizeof(float) : sizeof(double);
+  return (size_t)tile * 3 * sizeof(double) + (size_t)tile * 3 * rs + (size_t)tile * runs_cap * rs;
+}
+
+void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,
+                    const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
+                    const double *q, const double *ga, const double *gb, const AtomRec *atoms,
+                    const SpeciesRun *runs, const int32_t *run_count, const double *coeff, int tile, int runs_cap,
+                    double *part, hipStream_t s) {
+  if (n_items <= 0) return;
+  const size_t lds = atom_bw_lds_bytes(mixed, tile, runs_cap);
+  const BwItem *it = items;
+  if (mixed)
+    hipLaunchKernelGGL(k_atom_bw<true>, dim3((unsigned)n_items), dim3(kThreads), lds, s, it, friedel, plan,
+                       refl_offset, h, k, l, q, ga, gb, atoms, runs, run_count, coeff, tile, runs_cap,
+                       (double4 *)part);
+  else
+    hipLaunchKernelGGL(k_atom_bw<false>, dim3((unsigned)n_items), dim3(kThreads), lds, s, it, friedel, plan,
+                       refl_offset, h, k, l, q, ga, gb, atoms, runs, run_count, coeff, tile, runs_cap,
+                       (double4 *)part);
+}
+
+void launch_atom_bw_reduce(const AbItem *items, int64_t n_items, const CrystalPlan *plan, const double *part,
+                           const int32_t *orig, double *dfrac, double *dbfac, hipStream_t s) {
+  if (n_items <= 0) return;
+  hipLaunchKernelGGL(k_atom_bw_reduce, dim3((unsigned)n_items), dim3(kThreads), 0, s, items, plan,
+                     (const double4 *)part, orig, dfrac, dbfac);
+}
+
+void launch_gstar_part(const int32_t *hchunk_crystal, int64_t n_hchunks, bool friedel, const CrystalPlan *plan,
+                       const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
+                       const double *dq, double *part6, hipStream_t s) {
+  if (n_hchunks <= 0) return;
+  hipLaunchKernelGGL(k_gstar_part, dim3((unsigned)n_hchunks), dim3(kThreads), 0, s, hchunk_crystal, friedel, plan,
+                     refl_offset, h, k, l, dq, part6);
+}
+
+}  // namespace xrd

@@ -1,0 +1,179 @@
+// Internal layout shared by the host planner and the gfx950 kernels of libxrd.
+//
+// The host plans a batch once (metric inverses, search boxes, capacities and
+// launch tables); the plan is copied into the caller's workspace and every
+// kernel reads it from there.  All device scratch lives in that workspace at
+// offsets fixed by the plan, so no call allocates device memory and every
+// launch has a grid size known on the host (HIP-graph friendly).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace xrd {
+
+// Work granularity.
+constexpr int kEnumChunk = 2048;  // search-box points per enumeration block (256 threads x 8)
+constexpr int kSortChunk = 1024;  // reflections per sort/merge block (256 threads x 4)
+constexpr int kBinDiv = 4;        // merge-sort bins per crystal = capacity / kBinDiv
+constexpr int kHalfChunk = 2048;  // reflections per adjoint chunk
+constexpr int kScanBlock = 2048;  // elements per scan block (256 threads x 8)
+constexpr int kAtomBlock = 256;   // atoms per adjoint block
+constexpr int kSfRpt = 2;         // reflections per lane in the structure-factor kernel
+constexpr int kSfTile = 64 * kSfRpt;
+
+// Per-crystal plan (device copy in the workspace), 256 bytes.
+struct alignas(16) CrystalPlan {
+  double gs[6];       // G* as [11, 22, 33, 12, 13, 23]
+  double lat[6];      // a, b, c (A), alpha, beta, gamma (deg)
+  double tmin, tmax;  // inclusive 2theta range (deg)
+  double qlo, qhi;    // conservative q prefilter: points outside never pass the 2theta test
+  double bin_scale;   // merge-sort bins per degree
+  int32_t H, K, L;    // search box half extents
+  int32_t n_bins;
+  int64_t half_box;   // points of the search box above the origin: ((2H+1)(2K+1)(2L+1)-1)/2
+  int64_t enum_chunk_begin;
+  int32_t enum_chunks;
+  int32_t n_hchunks;  // adjoint chunks at capacity
+  int64_t atom_begin, atom_end;
+  int64_t run_begin;  // first slot of this crystal's species-run table (capacity min(S, N))
+  int64_t bin_begin;
+  int64_t sort_chunk_begin;
+  int64_t hchunk_begin;  // first adjoint chunk (global id)
+  int64_t part_begin;    // first adjoint partial row: rows = n_hchunks * N
+  int32_t sort_chunks;
+  int32_t pad0;
+  double pad1[2];
+};
+static_assert(sizeof(CrystalPlan) == 256, "CrystalPlan layout");
+
+// Packed atom, species-sorted within each crystal (48 bytes).
+struct alignas(16) AtomRec {
+  double x, y, z;
+  double occ, bfac;
+  float log2occ;   // log2(occ) (mixed path weight exponent)
+  float bl2e;      // B * log2(e)
+};
+static_assert(sizeof(AtomRec) == 48, "AtomRec layout");
+
+// A run of same-species atoms: [begin, end) in the packed array.
+struct alignas(16) SpeciesRun {
+  int32_t begin, end, species, local;  // local = run index within the crystal
+};
+
+// Structure-factor work item: a tile of reflections of one crystal.
+struct SfItem {
+  int32_t crystal;
+  int32_t tile;
+};
+
+// Workspace byte offsets (all 256-aligned).
+struct WsLayout {
+  int64_t plan, enum_chunk_crystal, sf_items, sort_chunk_crystal, hchunk_crystal, bw_items, ab_items;
+  int64_t enum_count, enum_prefix;
+  int64_t atoms, atom_orig, runs, run_count, err_flag;
+  int64_t bin_count, bin_start;
+  int64_t skey, sidx;
+  int64_t flags, pscan;
+  int64_t cmax, n_peaks, tmp_tt, tmp_i, tmp_y, tmp_mult, tmp_first, keep, kscan, raw_peak_offset;
+  int64_t scan_part;
+  int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6;
+  int64_t total;
+};
+
+void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
+
+// Exclusive scan of int32 in[0, n) into int64 out[0, n] (out[n] = total).
+// If n_dev is non-null, elements at index >= *n_dev count as zero and
+// out[*n_dev .. n] all hold the total.  ``part`` needs scan_part_elems(n) int64.
+int64_t scan_part_elems(int64_t n);
+void launch_scan_i32(const int32_t *in, int64_t n, const int64_t *n_dev, int64_t *out, int64_t *part,
+                     hipStream_t s);
+
+
+// ---- launch wrappers (defined in the .hip files) ---------------------------
+
+struct BwItem {
+  int32_t crystal, ablock, chunk, pad;
+};
+struct AbItem {
+  int32_t crystal, ablock;
+};
+
+void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk_crystal, int64_t n_chunks,
+                      double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h, int16_t *k,
+                      int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset, hipStream_t s);
+void launch_atom_prep(const CrystalPlan *plan, int64_t n_c, int32_t n_species, const double *frac,
+                      const int32_t *species, const double *occ, const double *bfac, AtomRec *atoms, int32_t *orig,
+                      SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s);
+void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
+               const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
+               const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
+               const double *coeff, void *A, void *B, double *I, hipStream_t s);
+
+struct SortArgs {
+  const CrystalPlan *plan;
+  const int32_t *chunk_crystal;
+  int64_t n_chunks;
+  const int64_t *refl_offset;
+  const double *tt;
+  const int16_t *h, *k, *l;
+  int32_t *bin_count;
+  int64_t *bin_start;
+  int64_t n_bins;
+  double *skey;
+  int32_t *sidx;
+  int64_t *scan_part;
+};
+void launch_sort(const SortArgs &a, hipStream_t s);
+
+struct MergeArgs {
+  SortArgs sort;
+  int64_t n_c;
+  int64_t refl_cap;
+  double tol, thr;
+  const double *inten;
+  int32_t *flags;
+  int64_t *pscan;
+  uint64_t *cmax;
+  int64_t *n_peaks;
+  // staging of the threshold path (NULL when thr == 0)
+  double *tmp_tt, *tmp_i, *tmp_y;
+  int32_t *tmp_mult;
+  int64_t *tmp_first;
+  int32_t *keep;
+  int64_t *kscan;
+  int64_t *raw_peak_offset;
+  // outputs
+  double *pk_tt, *pk_i, *pk_y;
+  int32_t *pk_mult;
+  int64_t *pk_first, *perm, *peak_offset;
+};
+void launch_merge(const MergeArgs &a, hipStream_t s);
+
+void launch_broaden_fwd(int64_t n_c, const int64_t *refl_offset, const double *skey, const int32_t *sidx,
+                        const double *inten, double t0, double dt, int64_t n, double sigma, double window, double *y,
+                        hipStream_t s);
+void launch_broaden_adj(const SfItem *items, int64_t n_items, bool friedel, const int64_t *refl_offset,
+                        const double *tt, const double *dy, double t0, double dt, int64_t n, double sigma,
+                        double window, double *w1, double *w2, hipStream_t s);
+void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s);
+void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
+                  const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
+                  const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
+                  const int32_t *run_count, const double *coeff, const double *w1, const double *w2, double *ga,
+                  double *gb, double *dq, hipStream_t s);
+size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap);
+void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,
+                    const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
+                    const double *q, const double *ga, const double *gb, const AtomRec *atoms,
+                    const SpeciesRun *runs, const int32_t *run_count, const double *coeff, int tile, int runs_cap,
+                    double *part, hipStream_t s);
+void launch_atom_bw_reduce(const AbItem *items, int64_t n_items, const CrystalPlan *plan, const double *part,
+                           const int32_t *orig, double *dfrac, double *dbfac, hipStream_t s);
+void launch_gstar_part(const int32_t *hchunk_crystal, int64_t n_hchunks, bool friedel, const CrystalPlan *plan,
+                       const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
+                       const double *dq, double *part6, hipStream_t s);
+
+}  // namespace xrd

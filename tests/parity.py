@@ -1,0 +1,104 @@
+"""Element-by-element comparison of the GPU pipeline with the FP64 oracle.
+
+Tolerances follow from the arithmetic of each path:
+
+* reflections (h, k, l), their order, peak partition (first member, member
+  count, member set) are integers: exact;
+* q: both sides evaluate the same double expression from G*, which they
+  obtain by different formulas (reciprocal cell vs. cofactor inverse), so
+  they differ by a few ulp: relative 1e-13;
+* 2theta: the merge keys; 1e-9 deg (the bar for "exact positions"), and a
+  peak's position is the 2theta of its first member;
+* structure factors: the error of a sum is bounded by the sum of the
+  magnitudes of its terms, sum_j |w_j| (the oracle reports it as ``absw``).
+  Double path: each term carries a few ulp (sincos, exp, the phase), so
+  |dF| <= 1e-12 sum|w|.  Mixed path: each term carries the float error of
+  v_sin/v_cos (measured 1.2e-7 absolute on gfx950), of exp2 and of the
+  weight (~2e-7 relative), and float sums of at most 64 atoms add up to
+  63 * 2^-24 of sum|w|; the compensated outer sum adds nothing at this
+  level, so |dF| <= 4.5e-6 sum|w|;
+* intensities I = |F|^2 LP: |dI| <= LP (2 |F| dF + dF^2) + 1e-12 I, and for
+  merged peaks the sum of the member bounds.  On top, the headline bar:
+  peaks with I >= 1e-3 of the crystal's strongest peak agree within 1e-4
+  relative.
+"""
+
+from __future__ import annotations
+
+import numpy as np
+
+F_REL = {"fp64": 1e-12, "mixed": 4.5e-6}
+
+
+def compare_crystal(res, c, orc, precision, label=""):
+    """Assert parity of crystal ``c`` of a PatternResult with an OracleCrystal.
+    Returns a dict of error statistics."""
+    rs, ps = res.crystal(c)
+    tag = f"{label} crystal {c}"
+    n = rs.stop - rs.start
+    assert n == orc.n_refl, f"{tag}: {n} reflections vs oracle {orc.n_refl}"
+    stats = {"n_refl": n, "n_peaks": ps.stop - ps.start}
+    if n == 0:
+        assert ps.stop == ps.start
+        return stats
+    np.testing.assert_array_equal(res.hkl[rs], orc.hkl, err_msg=f"{tag}: hkl list")
+    np.testing.assert_allclose(res.q[rs], orc.q, rtol=1e-13, atol=0, err_msg=f"{tag}: q")
+    assert np.max(np.abs(res.two_theta[rs] - orc.tt)) <= 1e-9, f"{tag}: 2theta"
+    np.testing.assert_allclose(res.lp[rs], orc.lp, rtol=1e-12, err_msg=f"{tag}: LP")
+
+    dF = F_REL[precision] * orc.absw
+    eA = np.abs(res.A[rs] - orc.fr)
+    eB = np.abs(res.B[rs] - orc.fi)
+    assert np.all(eA <= dF + 1e-300), f"{tag}: Re F max err/bound {np.max(eA / np.maximum(dF, 1e-300)):.3g}"
+    assert np.all(eB <= dF + 1e-300), f"{tag}: Im F max err/bound {np.max(eB / np.maximum(dF, 1e-300)):.3g}"
+    fabs = np.sqrt(orc.fr ** 2 + orc.fi ** 2)
+    dI = orc.lp * (2 * fabs * dF + dF * dF) + 1e-12 * orc.inten
+    eI = np.abs(res.I[rs] - orc.inten)
+    assert np.all(eI <= dI + 1e-300), f"{tag}: I max err/bound {np.max(eI / np.maximum(dI, 1e-300)):.3g}"
+    stats["F_err_over_absw"] = float(np.max(np.maximum(eA, eB) / np.maximum(orc.absw, 1e-300)))
+
+    # peaks: partition, positions, multiplicities, members, intensities
+    m = ps.stop - ps.start
+    assert m == len(orc.pk_tt), f"{tag}: {m} peaks vs oracle {len(orc.pk_tt)}"
+    first = res.pk_first[ps] - rs.start
+    np.testing.assert_array_equal(first, orc.pk_first, err_msg=f"{tag}: peak first member")
+    np.testing.assert_array_equal(res.pk_mult[ps], orc.pk_mult, err_msg=f"{tag}: multiplicity")
+    assert np.max(np.abs(res.pk_two_theta[ps] - orc.pk_tt)) <= 1e-9, f"{tag}: peak 2theta"
+    perm = res.perm[rs] - rs.start
+    assert sorted(perm.tolist()) == list(range(n)), f"{tag}: perm is not a permutation"
+    # members of each peak: equal as sets (the order of equal keys may differ by an ulp of 2theta)
+    bounds = np.append(orc.pk_first, n)
+    for p in range(m):
+        a, b = bounds[p], bounds[p + 1]
+        if not np.array_equal(np.sort(perm[a:b]), np.sort(orc.perm[a:b])):
+            raise AssertionError(f"{tag}: members of peak {p} differ")
+    # sorted order is ascending 2theta
+    assert np.all(np.diff(res.two_theta[rs][perm]) >= 0), f"{tag}: perm not ascending"
+    pk_bound = np.add.reduceat(dI[orc.perm], orc.pk_first) if m else np.zeros(0)
+    ePk = np.abs(res.pk_intensity[ps] - orc.pk_i)
+    assert np.all(ePk <= pk_bound + 1e-300), f"{tag}: peak I max err/bound {np.max(ePk / np.maximum(pk_bound, 1e-300)):.3g}"
+    imax = orc.pk_i.max() if m else 0.0
+    if imax > 0:
+        strong = orc.pk_i >= 1e-3 * imax
+        rel = ePk[strong] / orc.pk_i[strong]
+        assert np.all(rel <= 1e-4), f"{tag}: strong-peak relative error {rel.max():.3g}"
+        stats["peak_rel_err"] = float(rel.max())
+        stats["weak_abs_err_over_max"] = float(np.max(ePk[~strong]) / imax) if np.any(~strong) else 0.0
+        # y = 100 I / I_max: error from I and from I_max
+        jmax = int(np.argmax(orc.pk_i))
+        y_bound = 100.0 * (pk_bound + orc.pk_i * pk_bound[jmax] / imax) / imax + 1e-12 * orc.pk_y
+        eY = np.abs(res.pk_scaled[ps] - orc.pk_y)
+        assert np.all(eY <= y_bound), f"{tag}: scaled max err/bound {np.max(eY / np.maximum(y_bound, 1e-300)):.3g}"
+    else:
+        assert np.all(res.pk_scaled[ps] == 0)
+    return stats
+
+
+def compare_batch(res, batch, orcs, precision, label=""):
+    worst = {}
+    for c in range(batch.n_crystals):
+        st = compare_crystal(res, c, orcs[c], precision, label)
+        for k, v in st.items():
+            if isinstance(v, float):
+                worst[k] = max(worst.get(k, 0.0), v)
+    return worst

@@ -1,0 +1,171 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every
+function include/xrd.h declares, and validates and plans batches on the host
+(xrd_batch_create makes no HIP call)."""
+
+import ctypes as C
+import math
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_11709_amd import capi, synth
+
+
+def declared_functions():
+    text = open(capi.HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(xrd_\w+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_function():
+    names = declared_functions()
+    assert len(names) >= 12
+    lib = C.CDLL(capi.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(capi.SIGNATURES)
+    assert capi.xrd_version().startswith("xrd-gfx950")
+
+
+def make_desc(b: synth.CrystalBatch, keep, **over):
+    """Descriptor with fake (never dereferenced) device pointers."""
+    lat = np.ascontiguousarray(b.lattice)
+    off = np.ascontiguousarray(b.atom_offset, np.int64)
+    tmin = np.ascontiguousarray(b.two_theta_min)
+    tmax = np.ascontiguousarray(b.two_theta_max)
+    keep.extend([lat, off, tmin, tmax])
+    d = capi.xrd_batch_desc()
+    d.n_crystals = b.n_crystals
+    d.n_species = b.n_species
+    d.precision = capi.XRD_MIXED
+    d.lattice, d.atom_offset = lat.ctypes.data, off.ctypes.data
+    d.two_theta_min, d.two_theta_max = tmin.ctypes.data, tmax.ctypes.data
+    d.wavelength, d.merge_tol, d.rel_threshold = b.wavelength, b.merge_tol, 0.0
+    d.friedel = 1
+    fake = 0x10000
+    d.frac = d.species = d.occ = d.bfac = d.sf_coeff = fake
+    d.stream = None
+    for k, v in over.items():
+        setattr(d, k, v)
+    return d
+
+
+def test_plan_capacity_bounds_oracle_counts():
+    b = synth.random_triclinic(21, 40, atoms_hi=30)
+    keep = []
+    h = capi.xrd_batch_create(make_desc(b, keep))
+    try:
+        s = capi.xrd_batch_sizes(h)
+        counts = [len(oracle.enumerate_hkl(b.lattice[c], b.wavelength, b.two_theta_min[c],
+                                           b.two_theta_max[c])[2]) for c in range(b.n_crystals)]
+        assert s.refl_capacity >= sum(counts)
+        assert s.refl_capacity <= 6 * sum(counts)  # box / sphere volume ratio is modest
+        assert s.n_atoms == b.n_atoms and s.n_crystals == 40
+        assert s.workspace_bytes % 256 == 0 and s.workspace_bytes > 0
+        assert s.half_capacity * 2 == s.refl_capacity
+    finally:
+        capi.xrd_batch_destroy(h)
+
+
+def test_plan_capacity_per_crystal_tight_box():
+    # one crystal at a time: capacity = (2H+1)(2K+1)(2L+1) - 1 with H = floor(gmax a)
+    for lat in ([5.64, 5.64, 5.64, 90, 90, 90], [7.1, 3.3, 12.0, 64.0, 101.0, 117.0]):
+        b = synth.rocksalt()
+        b.lattice = np.array([lat], float)
+        keep = []
+        h = capi.xrd_batch_create(make_desc(b, keep))
+        s = capi.xrd_batch_sizes(h)
+        capi.xrd_batch_destroy(h)
+        gmax = 2 * math.sin(math.radians(45.0)) / b.wavelength
+        H, K, L = (math.floor(gmax * x) for x in lat[:3])
+        assert s.refl_capacity == (2 * H + 1) * (2 * K + 1) * (2 * L + 1) - 1
+        n = len(oracle.enumerate_hkl(lat, b.wavelength, 0.0, 90.0)[2])
+        assert s.refl_capacity >= n
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("wavelength", 0.0, capi.XRD_ERR_INVALID_ARG),
+    ("wavelength", -1.0, capi.XRD_ERR_INVALID_ARG),
+    ("merge_tol", 0.0, capi.XRD_ERR_INVALID_ARG),
+    ("rel_threshold", -0.1, capi.XRD_ERR_INVALID_ARG),
+    ("precision", 7, capi.XRD_ERR_INVALID_ARG),
+    ("friedel", 2, capi.XRD_ERR_INVALID_ARG),
+    ("n_species", 0, capi.XRD_ERR_INVALID_ARG),
+    ("n_crystals", -1, capi.XRD_ERR_INVALID_ARG),
+    ("sf_coeff", None, capi.XRD_ERR_INVALID_ARG),
+    ("frac", None, capi.XRD_ERR_INVALID_ARG),
+    ("lattice", None, capi.XRD_ERR_INVALID_ARG),
+])
+def test_create_rejects_bad_arguments(field, value, code):
+    b = synth.random_triclinic(3, 4, atoms_hi=10)
+    keep = []
+    d = make_desc(b, keep, **{field: value})
+    h = C.c_void_p()
+    rc = capi.lib().xrd_batch_create(C.byref(d), C.byref(h))
+    assert rc == code
+    assert not h.value
+    assert capi.xrd_last_error()
+
+
+def test_create_rejects_bad_cells_and_ranges():
+    b = synth.random_triclinic(3, 3, atoms_hi=10)
+    for lat, code in (([5, 5, 5, 120, 120, 120], capi.XRD_ERR_INVALID_CELL),
+                      ([0, 5, 5, 90, 90, 90], capi.XRD_ERR_INVALID_CELL),
+                      ([5, 5, 5, 90, 180, 90], capi.XRD_ERR_INVALID_CELL),
+                      ([5e4, 5e4, 5e4, 90, 90, 90], capi.XRD_ERR_CAPACITY)):
+        b2 = b.subset([0, 1, 2])
+        b2.lattice[1] = lat
+        keep = []
+        with pytest.raises(capi.XrdError) as e:
+            capi.xrd_batch_create(make_desc(b2, keep))
+        assert e.value.code == code
+    for lo, hi in ((-1.0, 90.0), (50.0, 40.0), (10.0, 180.0), (10.0, 10.0)):
+        b2 = b.subset([0, 1, 2])
+        b2.two_theta_min[2], b2.two_theta_max[2] = lo, hi
+        keep = []
+        with pytest.raises(capi.XrdError) as e:
+            capi.xrd_batch_create(make_desc(b2, keep))
+        assert e.value.code == capi.XRD_ERR_INVALID_ARG
+        assert "crystal 2" in str(e.value)
+
+
+def test_create_rejects_bad_offsets():
+    b = synth.random_triclinic(3, 3, atoms_hi=10)
+    b2 = b.subset([0, 1, 2])
+    b2.atom_offset = b2.atom_offset.copy()
+    b2.atom_offset[1] = b2.atom_offset[2] + 1
+    keep = []
+    with pytest.raises(capi.XrdError):
+        capi.xrd_batch_create(make_desc(b2, keep))
+    b3 = b.subset([0, 1, 2])
+    b3.atom_offset = b3.atom_offset + 1
+    with pytest.raises(capi.XrdError):
+        capi.xrd_batch_create(make_desc(b3, keep))
+
+
+def test_empty_batch_and_atomless_crystals_plan():
+    b = synth.random_triclinic(3, 0)
+    keep = []
+    h = capi.xrd_batch_create(make_desc(b, keep, frac=None, species=None, occ=None, bfac=None))
+    s = capi.xrd_batch_sizes(h)
+    assert s.refl_capacity == 0 and s.n_crystals == 0
+    capi.xrd_batch_destroy(h)
+    capi.xrd_batch_destroy(None)
+
+
+def test_device_calls_reject_null_workspace():
+    b = synth.rocksalt()
+    keep = []
+    h = capi.xrd_batch_create(make_desc(b, keep))
+    try:
+        r = capi.xrd_refl()
+        assert capi.lib().xrd_enumerate_hkl(h, None, C.byref(r)) == capi.XRD_ERR_INVALID_ARG
+        assert capi.lib().xrd_enumerate_hkl(h, 0x1001, C.byref(r)) == capi.XRD_ERR_INVALID_ARG  # misaligned
+        assert capi.lib().xrd_enumerate_hkl(h, 0x1000, C.byref(r)) == capi.XRD_ERR_INVALID_ARG  # null arrays
+        g = capi.xrd_grid(10.0, 0.0, 100, 0.1, 8.0)
+        assert capi.lib().xrd_pattern_forward(h, 0x1000, C.byref(r), None, C.byref(g), None) == \
+            capi.XRD_ERR_INVALID_ARG
+    finally:
+        capi.xrd_batch_destroy(h)
