@@ -138,15 +138,19 @@ int xrd_batch_create(const xrd_batch_desc *desc, xrd_batch **out);
 int xrd_batch_sizes(const xrd_batch *b, xrd_sizes *out);
 
 /* Copy the batch's launch tables into the workspace ``ws`` (device memory of
- * at least workspace_bytes, 256-byte aligned), enqueued on the batch's
- * stream.  Required once per workspace before the device calls below; kept
- * out of those calls so that they can be captured into a HIP graph. */
+ * at least workspace_bytes, 256-byte aligned) on the batch's stream, and
+ * wait for the copy.  Required once per workspace before the device calls
+ * below, which then only launch kernels (so a caller may capture them into a
+ * HIP graph and replay it). */
 int xrd_batch_upload(xrd_batch *b, void *ws);
 
 /* Reciprocal-lattice enumeration (paper, Section 2: lattice points inside
  * the physically accessible sphere): every integer (h, k, l) != 0 with
  * two_theta_min <= 2theta <= two_theta_max, with q, 2theta and LP, written
- * into ``r`` together with refl_offset. */
+ * into ``r`` together with refl_offset.  Also packs the batch's atoms
+ * (species-sorted copy) into the workspace: xrd_structure_factors and
+ * xrd_pattern_backward read that copy, so the device atom arrays are read
+ * here and changes made to them later take effect at the next call. */
 int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r);
 
 /* Structure factors (paper, Section 2: sum of atomic contributions for each
@@ -173,7 +177,8 @@ int xrd_pattern_forward(xrd_batch *b, void *ws, const xrd_refl *r, const double 
  * factors): given dL/dy [n_crystals * n_points], writes dL/dfrac [N*3],
  * dL/dbfac [N] and dL/dlattice [n_crystals*6] (per degree for the angles).
  * The reflection set is held fixed (it is piecewise constant in the
- * lattice).  Device buffers, all double. */
+ * lattice).  Uses the atoms packed by the last xrd_enumerate_hkl on ``ws``.
+ * Device buffers, all double. */
 int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_grid *g,
                          const double *dL_dy, double *dL_dfrac, double *dL_dbfac,
                          double *dL_dlattice);

@@ -198,12 +198,16 @@ class XrdBatch:
         capi.xrd_pattern_forward(self.handle, self.ws, refl.c(), I.data_ptr(), grid.c(), y.data_ptr())
         return y
 
-    def pattern_backward(self, refl: Reflections, grid: Grid, dy: torch.Tensor):
-        dy = dy.to(torch.float64).contiguous()
+    def new_grads(self):
         n = max(self.batch.n_atoms, 1)
-        dfrac = torch.empty(n, 3, dtype=torch.float64, device=self.device)
-        dbfac = torch.empty(n, dtype=torch.float64, device=self.device)
-        dlat = torch.empty(max(self.n_crystals, 1), 6, dtype=torch.float64, device=self.device)
+        return (torch.empty(n, 3, dtype=torch.float64, device=self.device),
+                torch.empty(n, dtype=torch.float64, device=self.device),
+                torch.empty(max(self.n_crystals, 1), 6, dtype=torch.float64, device=self.device))
+
+    def pattern_backward(self, refl: Reflections, grid: Grid, dy: torch.Tensor, out=None):
+        if dy.dtype != torch.float64 or not dy.is_contiguous():
+            dy = dy.to(torch.float64).contiguous()
+        dfrac, dbfac, dlat = out or self.new_grads()
         capi.xrd_pattern_backward(self.handle, self.ws, refl.c(), grid.c(), dy.data_ptr(), dfrac.data_ptr(),
                                   dbfac.data_ptr(), dlat.data_ptr())
         return dfrac[: self.batch.n_atoms], dbfac[: self.batch.n_atoms], dlat[: self.n_crystals]

@@ -31,10 +31,15 @@ struct xrd_batch {
   std::vector<SfItem> sf_items;
   std::vector<BwItem> bw_items;
   std::vector<AbItem> ab_items;
-  int64_t n_atoms = 0, refl_cap = 0, half_cap = 0, n_bins = 0, run_cap = 0, part_rows = 0;
+  int64_t n_atoms = 0, refl_cap = 0, half_cap = 0, n_bins = 0, run_cap = 0, part_rows = 0, partf_rows = 0;
   int runs_cap_max = 1, bw_tile = 64;
   WsLayout ws{};
   void *last_ws = nullptr;
+  // the (2theta, hkl) order in a workspace is computed once per enumeration:
+  // merge and broadening share it (host-side record of the call sequence, so
+  // a captured graph replays the same decision)
+  const void *sorted_ws = nullptr;
+  const double *sorted_tt = nullptr;
 };
 
 namespace {
@@ -159,7 +164,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
 
   const bool friedel = d->friedel != 0;
   const double lam = d->wavelength;
-  int64_t ec = 0, sc = 0, hc = 0, bins = 0, runs = 0, parts = 0, refl = 0;
+  int64_t ec = 0, sc = 0, hc = 0, bins = 0, runs = 0, parts = 0, pfused = 0, refl = 0;
   int runs_cap_max = 1;
   for (int64_t c = 0; c < nc; ++c) {
     CrystalPlan &P = b->plan[c];
@@ -214,18 +219,26 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     P.n_hchunks = (int32_t)ceil_div(evalcap, kHalfChunk);
     P.hchunk_begin = hc;
     hc += P.n_hchunks;
-    P.part_begin = parts;
-    parts += (int64_t)P.n_hchunks * na;
+    P.n_tiles = (int32_t)ceil_div(evalcap, kSfTile);
+    P.fused = na <= kFusedMaxAtoms ? 1 : 0;
+    if (P.fused) {
+      P.pf_begin = pfused;
+      pfused += (int64_t)P.n_tiles * na;
+    } else {
+      P.part_begin = parts;
+      parts += (int64_t)P.n_hchunks * na;
+    }
   }
   b->refl_cap = refl;
   b->half_cap = refl / 2;
   b->n_bins = bins;
   b->run_cap = runs;
   b->part_rows = parts;
+  b->partf_rows = pfused;
   b->runs_cap_max = runs_cap_max;
   const bool mixed = d->precision == XRD_MIXED;
-  int tile = 64;
-  while (tile > 8 && atom_bw_lds_bytes(mixed, tile, runs_cap_max) > 48 * 1024) tile -= 8;
+  int tile = 256;
+  while (tile > 8 && atom_bw_lds_bytes(mixed, tile, runs_cap_max) > 48 * 1024) tile /= 2;
   b->bw_tile = tile;
   if (atom_bw_lds_bytes(mixed, tile, runs_cap_max) > 48 * 1024) {
     delete b;
@@ -258,7 +271,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     const int64_t ab = ceil_div(na, kAtomBlock);
     for (int64_t a = 0; a < ab; ++a) {
       b->ab_items.push_back(AbItem{(int32_t)c, (int32_t)a});
-      for (int32_t k = 0; k < P.n_hchunks; ++k) b->bw_items.push_back(BwItem{(int32_t)c, (int32_t)a, k, 0});
+      if (!P.fused)
+        for (int32_t k = 0; k < P.n_hchunks; ++k) b->bw_items.push_back(BwItem{(int32_t)c, (int32_t)a, k, 0});
     }
   }
   if ((int64_t)b->sf_items.size() >= ((int64_t)1 << 31) || (int64_t)b->bw_items.size() >= ((int64_t)1 << 31)) {
@@ -314,6 +328,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.bw_gb = take(8 * rc);
   L.bw_dq = take(8 * rc);
   L.bw_part = take(32 * parts);
+  L.bw_partf = take(32 * pfused);
   L.bw_part6 = take(48 * hc);
   L.total = o;
   *out = b;
@@ -359,11 +374,16 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   return hip_check("upload");
 }
 
+static void pack_atoms(xrd_batch *b, void *ws);
+
 int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r) {
   if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
   if (int e = check_ws(b, ws)) return e;
   if (int e = check_refl(r)) return e;
   const WsLayout &L = b->ws;
+  pack_atoms(b, ws);
+  b->sorted_ws = nullptr;
+  b->sorted_tt = nullptr;
   launch_enumerate(at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, at<int32_t>(ws, L.enum_chunk_crystal),
                    (int64_t)b->enum_chunk_crystal.size(), b->desc.wavelength, at<int32_t>(ws, L.enum_count),
                    at<int64_t>(ws, L.enum_prefix), at<int64_t>(ws, L.scan_part), r->h, r->k, r->l, r->q,
@@ -386,7 +406,6 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
   if (int e = check_refl(r)) return e;
   if (!A || !B || !I) return fail(XRD_ERR_INVALID_ARG, "A, B and I must be non-NULL");
   const WsLayout &L = b->ws;
-  pack_atoms(b, ws);
   launch_sf(b->desc.precision == XRD_MIXED, b->desc.friedel != 0, at<SfItem>(ws, L.sf_items),
             (int64_t)b->sf_items.size(), at<CrystalPlan>(ws, L.plan), r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
             at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), b->desc.sf_coeff, A, B,
@@ -395,9 +414,21 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
   return hip_check("structure_factors");
 }
 
+static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r);
+
+// Sort the reflections of ``r`` into the workspace unless this enumeration
+// has been sorted there already.
+static void ensure_sorted(xrd_batch *b, void *ws, const xrd_refl *r) {
+  if (b->sorted_ws == ws && b->sorted_tt == r->two_theta) return;
+  launch_sort(sort_args(b, ws, r), stream_of(b));
+  b->sorted_ws = ws;
+  b->sorted_tt = r->two_theta;
+}
+
 static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r) {
   const WsLayout &L = b->ws;
   SortArgs a;
+  a.n_c = b->desc.n_crystals;
   a.plan = at<CrystalPlan>(ws, L.plan);
   a.chunk_crystal = at<int32_t>(ws, L.sort_chunk_crystal);
   a.n_chunks = (int64_t)b->sort_chunk_crystal.size();
@@ -450,6 +481,7 @@ int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, 
   a.pk_first = p->first;
   a.perm = p->perm;
   a.peak_offset = p->peak_offset;
+  ensure_sorted(b, ws, r);
   launch_merge(a, stream_of(b));
   b->last_ws = ws;
   return hip_check("merge_peaks");
@@ -460,6 +492,10 @@ static int check_grid(const xrd_grid *g) {
   if (!(g->n_points >= 1) || !(g->dt > 0.0) || !(g->sigma > 0.0) || !(g->window_sigmas > 0.0) ||
       !std::isfinite(g->t0) || !std::isfinite(g->dt) || !std::isfinite(g->sigma) || !std::isfinite(g->window_sigmas))
     return fail(XRD_ERR_INVALID_ARG, "grid needs n_points >= 1, dt > 0, sigma > 0, window_sigmas > 0");
+  if (g->n_points > ((int64_t)1 << 31) || g->dt < 1e-9 || std::fabs(g->t0) > 1e6 || g->window_sigmas > 30.0 ||
+      g->window_sigmas * g->sigma > 1e3)
+    return fail(XRD_ERR_INVALID_ARG, "grid out of range: n_points <= 2^31, dt >= 1e-9, |t0| <= 1e6, "
+                                     "window_sigmas <= 30, window <= 1000 deg");
   return XRD_OK;
 }
 
@@ -470,9 +506,9 @@ int xrd_pattern_forward(xrd_batch *b, void *ws, const xrd_refl *r, const double 
   if (int e = check_grid(g)) return e;
   if (!I || !y) return fail(XRD_ERR_INVALID_ARG, "I and y must be non-NULL");
   const SortArgs sa = sort_args(b, ws, r);
-  launch_sort(sa, stream_of(b));
-  launch_broaden_fwd(b->desc.n_crystals, r->refl_offset, sa.skey, sa.sidx, I, g->t0, g->dt, g->n_points, g->sigma,
-                     g->window_sigmas, y, stream_of(b));
+  ensure_sorted(b, ws, r);
+  launch_broaden_fwd(b->desc.precision == XRD_MIXED, b->desc.n_crystals, r->refl_offset, sa.skey, sa.sidx, I,
+                     b->desc.friedel != 0, g->t0, g->dt, g->n_points, g->sigma, g->window_sigmas, y, stream_of(b));
   b->last_ws = ws;
   return hip_check("pattern_forward");
 }
@@ -493,18 +529,19 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   const int64_t n_items = (int64_t)b->sf_items.size();
   double *w1 = at<double>(ws, L.bw_w1), *w2 = at<double>(ws, L.bw_w2);
   double *ga = at<double>(ws, L.bw_ga), *gb = at<double>(ws, L.bw_gb), *dq = at<double>(ws, L.bw_dq);
-  pack_atoms(b, ws);
-  launch_broaden_adj(items, n_items, friedel, r->refl_offset, r->two_theta, dL_dy, g->t0, g->dt, g->n_points,
-                     g->sigma, g->window_sigmas, w1, w2, s);
+  launch_broaden_adj(at<int32_t>(ws, L.hchunk_crystal), (int64_t)b->hchunk_crystal.size(), plan, friedel,
+                     r->refl_offset, r->two_theta, dL_dy, g->t0, g->dt, g->n_points, g->sigma, g->window_sigmas, w1,
+                     w2, s);
   launch_sf_bw(mixed, friedel, items, n_items, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
                b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
-               b->desc.sf_coeff, w1, w2, ga, gb, dq, s);
+               b->desc.sf_coeff, w1, w2, ga, gb, dq, at<double>(ws, L.bw_partf), s);
   launch_atom_bw(mixed, friedel, at<BwItem>(ws, L.bw_items), (int64_t)b->bw_items.size(), plan, r->refl_offset,
                  r->h, r->k, r->l, r->q, ga, gb, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
                  at<int32_t>(ws, L.run_count), b->desc.sf_coeff, b->bw_tile, b->runs_cap_max,
                  at<double>(ws, L.bw_part), s);
-  launch_atom_bw_reduce(at<AbItem>(ws, L.ab_items), (int64_t)b->ab_items.size(), plan, at<double>(ws, L.bw_part),
-                        at<int32_t>(ws, L.atom_orig), dL_dfrac, dL_dbfac, s);
+  launch_atom_bw_reduce(at<AbItem>(ws, L.ab_items), (int64_t)b->ab_items.size(), friedel, plan, r->refl_offset,
+                        at<double>(ws, L.bw_part), at<double>(ws, L.bw_partf), at<int32_t>(ws, L.atom_orig),
+                        dL_dfrac, dL_dbfac, s);
   launch_gstar_part(at<int32_t>(ws, L.hchunk_crystal), (int64_t)b->hchunk_crystal.size(), friedel, plan,
                     r->refl_offset, r->h, r->k, r->l, dq, at<double>(ws, L.bw_part6), s);
   launch_lattice_chain(plan, b->desc.n_crystals, at<double>(ws, L.bw_part6), dL_dlattice, s);

@@ -6,11 +6,14 @@
 //   y_g = sum_r I_r K(x_g - 2theta_r),  K(d) = exp(-d^2 / (2 sigma^2)) / (sigma sqrt(2 pi)),
 //   restricted to |x_g - 2theta_r| <= window * sigma, x_g = t0 + g dt.
 //
-// Forward: a gather per grid point over the crystal's 2theta-sorted
-// reflections (binary search for the window), summed in sorted order, so the
-// result is deterministic without atomics.  Adjoint: per evaluated reflection,
-// w1 = sum_g dL/dy_g K and w2 = sum_g dL/dy_g K (x_g - 2theta)/sigma^2 over the
-// same window test.  Then the lattice chain rule of the per-crystal dL/dG*.
+// Forward: a gather in which each thread owns one grid point and sums, in
+// 2theta order, the reflections staged in LDS whose window holds it, so the
+// result is deterministic without atomics.  Adjoint: per evaluated
+// reflection, w1 = sum_g dL/dy_g K and w2 = sum_g dL/dy_g K (x_g - 2theta) /
+// sigma^2 over the same window; on the uniform grid the Gaussian follows a
+// two-term multiplicative recurrence, so a whole window costs two exp and a
+// few products per point.  Then the lattice chain rule of the per-crystal
+// dL/dG*.
 #include <math.h>
 
 #include "xrd_internal.h"
@@ -26,72 +29,189 @@ struct GridArgs {
   int64_t n;
 };
 
+// Grid points covered by a reflection at 2theta t: the interval of g in
+// [0, n) with |x_g - t| <= half, x_g = t0 + g dt (an interval because x_g - t
+// is monotone in g).  Empty when lo > hi.
+__device__ __forceinline__ void window_of(const GridArgs &g, double t, int64_t *lo, int64_t *hi) {
+#pragma clang fp contract(off)
+  int64_t a = (int64_t)ceil((t - g.half - g.t0) / g.dt);
+  int64_t b = (int64_t)floor((t + g.half - g.t0) / g.dt);
+  // the estimates are off by at most one step either way; settle them with the exact test
+  while (a > 0 && fabs(g.t0 + (double)(a - 1) * g.dt - t) <= g.half) --a;
+  while (a <= b && fabs(g.t0 + (double)a * g.dt - t) > g.half) ++a;
+  while (b + 1 < g.n && fabs(g.t0 + (double)(b + 1) * g.dt - t) <= g.half) ++b;
+  while (b >= a && fabs(g.t0 + (double)b * g.dt - t) > g.half) --b;
+  if (a < 0) a = 0;
+  if (b > g.n - 1) b = g.n - 1;
+  *lo = a;
+  *hi = b;
+}
+
+// Gaussian values along the grid by recurrence: with d = x_g - t,
+// K(d + dt) = K(d) r(d), r(d) = exp(-(2 d dt + dt^2) / (2 sigma^2)) and
+// r(d + dt) = r(d) rho, rho = exp(-dt^2 / sigma^2); two exp per window.
+struct GaussWalk {
+  double K, r;
+  __device__ __forceinline__ void start(const GridArgs &g, double d, double scale) {
+    K = scale * g.norm * exp(-(d * d) * g.inv2s2);
+    r = exp(-(2.0 * d * g.dt + g.dt * g.dt) * g.inv2s2);
+  }
+  __device__ __forceinline__ void step(double rho) {
+    K *= r;
+    r *= rho;
+  }
+};
+
+constexpr int kSegPts = 256;     // grid points per block of the forward gather (one per thread)
+constexpr int kTileR = 1024;     // reflections per LDS tile of the gather
+constexpr int kAdjDyLds = 8192;  // grid rows up to this length are staged in LDS by the adjoint
+
+__device__ __forceinline__ int64_t lower_bound(const double *__restrict__ a, int64_t lo, int64_t hi, double v) {
+  while (lo < hi) {
+    const int64_t m = (lo + hi) >> 1;
+    if (a[m] < v) lo = m + 1;
+    else hi = m;
+  }
+  return lo;
+}
+
+// Forward gather.  A block owns 256 consecutive grid points of one crystal,
+// a thread one point.  The crystal's 2theta-sorted reflections that reach the
+// block's points are staged through LDS in tiles (with Friedel pairing, whose
+// mates have bit-identical 2theta and I, one reflection per pair with twice
+// the intensity).  Each thread sums, in sorted order, the reflections whose
+// window holds its point: deterministic, no atomics.  The kernel value is
+// exp(-d^2 / 2 sigma^2) with d = x - 2theta in double; under MIXED the
+// exponential is taken in single precision (v_exp_f32 on -d^2 log2(e) / 2 sigma^2).
+template <bool MIXED>
 __global__ __launch_bounds__(256) void k_broaden_fwd(const int64_t *__restrict__ refl_offset,
                                                      const double *__restrict__ skey,
                                                      const int32_t *__restrict__ sidx,
-                                                     const double *__restrict__ inten, GridArgs g,
+                                                     const double *__restrict__ inten, GridArgs g, bool friedel,
                                                      double *__restrict__ y) {
 #pragma clang fp contract(off)
-  const int64_t per = (g.n + 255) / 256;  // blocks per crystal
-  const int64_t c = blockIdx.x / per;
-  const int64_t gi = (int64_t)(blockIdx.x % per) * blockDim.x + threadIdx.x;
-  if (gi >= g.n) return;
-  const double x = g.t0 + (double)gi * g.dt;
+  __shared__ double s_tt[kTileR], s_i[kTileR];
+  __shared__ int64_t s_range[2];
+  __shared__ int32_t s_wcnt[256 / 64];
+  const int64_t segs = (g.n + kSegPts - 1) / kSegPts;
+  const int64_t c = blockIdx.x / segs;
+  const int64_t G0 = (int64_t)(blockIdx.x % segs) * kSegPts;
+  const int64_t G1 = min(G0 + kSegPts, g.n) - 1;
+  const int64_t gi = G0 + threadIdx.x;
   const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
-  // first sorted position with 2theta >= x - half - guard; the exact window
-  // test below decides, the guard only keeps rounding of the bound from
-  // skipping a reflection the test would accept
+  const int64_t mid = r0 + (r1 - r0) / 2;  // first reflection of the positive half
+  if (threadIdx.x == 0) {
+    const double xa = g.t0 + (double)G0 * g.dt, xb = g.t0 + (double)G1 * g.dt;
+    const double guard = 1e-9 * (fabs(xa) + fabs(xb) + 1.0);
+    s_range[0] = lower_bound(skey, r0, r1, xa - g.half - guard);
+    s_range[1] = lower_bound(skey, r0, r1, xb + g.half + guard);
+  }
+  __syncthreads();
+  const int64_t ja = s_range[0], jb = s_range[1];
+  const double x = g.t0 + (double)gi * g.dt;
   const double guard = 1e-9 * (fabs(x) + 1.0);
-  const double lo = x - g.half - guard;
-  int64_t a = r0, b = r1;
-  while (a < b) {
-    const int64_t m = (a + b) >> 1;
-    if (skey[m] < lo) a = m + 1;
-    else b = m;
-  }
+  const float c2 = (float)(g.inv2s2 * 1.4426950408889634);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   double acc = 0.0;
-  for (int64_t j = a; j < r1; ++j) {
-    const double t = skey[j];
-    const double d = x - t;
-    if (t > x + g.half + guard) break;
-    if (fabs(d) > g.half) continue;
-    acc += inten[sidx[j]] * g.norm * exp(-(d * d) * g.inv2s2);
+  for (int64_t jt = ja; jt < jb; jt += kTileR) {
+    // stage in sorted order, compacted with a ballot per wave
+    int base = 0;
+    for (int u = 0; u < kTileR / 256; ++u) {
+      const int64_t j = jt + u * 256 + threadIdx.x;
+      bool keep = j < jb;
+      int32_t id = 0;
+      if (keep) {
+        id = sidx[j];
+        keep = !friedel || id >= mid;
+      }
+      const uint64_t bal = __ballot(keep);
+      if (lane == 0) s_wcnt[wid] = __popcll(bal);
+      __syncthreads();
+      int before = 0, total = 0;
+      for (int w = 0; w < 256 / 64; ++w) {
+        before += w < wid ? s_wcnt[w] : 0;
+        total += s_wcnt[w];
+      }
+      if (keep) {
+        const int e = base + before +
+                      __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+        s_tt[e] = skey[j];
+        s_i[e] = (friedel ? 2.0 : 1.0) * inten[id] * g.norm;
+      }
+      base += total;
+      __syncthreads();
+    }
+    const int nt = base;
+    if (gi <= G1) {
+      // first staged reflection with 2theta >= x - half - guard
+      int e = 0, hi = nt;
+      const double lo = x - g.half - guard;
+      while (e < hi) {
+        const int m = (e + hi) >> 1;
+        if (s_tt[m] < lo) e = m + 1;
+        else hi = m;
+      }
+      for (; e < nt; ++e) {
+        const double t = s_tt[e];
+        const double d = x - t;
+        if (t > x + g.half + guard) break;
+        if (fabs(d) > g.half) continue;
+        if constexpr (MIXED) {
+          const float df = (float)d;
+          acc += s_i[e] * (double)__builtin_amdgcn_exp2f(-(df * df) * c2);
+        } else {
+          acc += s_i[e] * exp(-(d * d) * g.inv2s2);
+        }
+      }
+    }
+    __syncthreads();
   }
-  y[c * g.n + gi] = acc;
+  if (gi <= G1) y[c * g.n + gi] = acc;
 }
 
-// Per evaluated reflection: w1 = sum dy K, w2 = sum dy K d / sigma^2 (d = x - 2theta).
-__global__ __launch_bounds__(256) void k_broaden_adj(const SfItem *__restrict__ items, int64_t n_items,
-                                                     bool friedel, const int64_t *__restrict__ refl_offset,
+// Adjoint on the grid side: a block per chunk of a crystal's evaluated
+// reflections, the crystal's dL/dy row staged in LDS; per reflection
+//   w1 = sum_g dy_g K,  w2 = sum_g dy_g K d / sigma^2  (d = x_g - 2theta)
+// over the same window, K by the same recurrence.
+template <bool LDS_ROW>
+__global__ __launch_bounds__(256) void k_broaden_adj(const int32_t *__restrict__ hchunk_crystal,
+                                                     const CrystalPlan *__restrict__ plan, bool friedel,
+                                                     const int64_t *__restrict__ refl_offset,
                                                      const double *__restrict__ tt, const double *__restrict__ dy,
                                                      GridArgs g, double *__restrict__ w1, double *__restrict__ w2) {
 #pragma clang fp contract(off)
-  const int64_t item = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  if (item >= n_items) return;
-  const SfItem it = items[item];
-  const int64_t r0 = refl_offset[it.crystal], r1 = refl_offset[it.crystal + 1];
+  extern __shared__ double s_dy[];  // the crystal's dL/dy row when LDS_ROW
+  const int32_t c = hchunk_crystal[blockIdx.x];
+  const CrystalPlan &P = plan[c];
+  const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
   const int64_t first = friedel ? r0 + (r1 - r0) / 2 : r0;
   const int64_t count = friedel ? (r1 - r0) / 2 : r1 - r0;
-  const int lane = threadIdx.x & 63;
-  const double *dyc = dy + (int64_t)it.crystal * g.n;
+  const int64_t e0 = (int64_t)(blockIdx.x - P.hchunk_begin) * kHalfChunk;
+  if (e0 >= count) return;
+  const int64_t e1 = min(e0 + (int64_t)kHalfChunk, count);
+  const double *dyc = dy + (int64_t)c * g.n;
+  if (LDS_ROW) {
+    for (int64_t i = threadIdx.x; i < g.n; i += 256) s_dy[i] = dyc[i];
+    __syncthreads();
+  }
   const double inv_s2 = 1.0 / (g.sigma * g.sigma);
-  for (int u = 0; u < kSfRpt; ++u) {
-    const int64_t e = (int64_t)it.tile * kSfTile + u * 64 + lane;
-    if (e >= count) break;
+  const double rho = exp(-(g.dt * g.dt) * inv_s2);
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
     const int64_t i = first + e;
     const double t = tt[i];
-    int64_t glo = (int64_t)floor((t - g.half - g.t0) / g.dt) - 1;
-    int64_t ghi = (int64_t)ceil((t + g.half - g.t0) / g.dt) + 1;
-    if (glo < 0) glo = 0;
-    if (ghi > g.n - 1) ghi = g.n - 1;
+    int64_t wl, wh;
+    window_of(g, t, &wl, &wh);
     double a1 = 0.0, a2 = 0.0;
-    for (int64_t gi = glo; gi <= ghi; ++gi) {
-      const double x = g.t0 + (double)gi * g.dt;
-      const double d = x - t;
-      if (fabs(d) > g.half) continue;
-      const double kv = dyc[gi] * g.norm * exp(-(d * d) * g.inv2s2);
-      a1 += kv;
-      a2 += kv * d * inv_s2;
+    if (wl <= wh) {
+      GaussWalk w;
+      w.start(g, g.t0 + (double)wl * g.dt - t, 1.0);
+      for (int64_t gi = wl; gi <= wh; ++gi) {
+        const double d = g.t0 + (double)gi * g.dt - t;
+        const double kv = (LDS_ROW ? s_dy[gi] : dyc[gi]) * w.K;
+        a1 += kv;
+        a2 += kv * d * inv_s2;
+        w.step(rho);
+      }
     }
     w1[i] = a1;
     w2[i] = a2;
@@ -156,22 +276,31 @@ GridArgs make_grid(double t0, double dt, int64_t n, double sigma, double window)
 
 }  // namespace
 
-void launch_broaden_fwd(int64_t n_c, const int64_t *refl_offset, const double *skey, const int32_t *sidx,
-                        const double *inten, double t0, double dt, int64_t n, double sigma, double window,
-                        double *y, hipStream_t s) {
+void launch_broaden_fwd(bool mixed, int64_t n_c, const int64_t *refl_offset, const double *skey,
+                        const int32_t *sidx, const double *inten, bool friedel, double t0, double dt, int64_t n,
+                        double sigma, double window, double *y, hipStream_t s) {
   if (n_c <= 0 || n <= 0) return;
   const GridArgs g = make_grid(t0, dt, n, sigma, window);
-  hipLaunchKernelGGL(k_broaden_fwd, dim3((unsigned)(((n + 255) / 256) * n_c)), dim3(256), 0, s, refl_offset,
-                     skey, sidx, inten, g, y);
+  const int64_t segs = (n + kSegPts - 1) / kSegPts;
+  if (mixed)
+    hipLaunchKernelGGL(k_broaden_fwd<true>, dim3((unsigned)(segs * n_c)), dim3(256), 0, s, refl_offset, skey, sidx,
+                       inten, g, friedel, y);
+  else
+    hipLaunchKernelGGL(k_broaden_fwd<false>, dim3((unsigned)(segs * n_c)), dim3(256), 0, s, refl_offset, skey, sidx,
+                       inten, g, friedel, y);
 }
 
-void launch_broaden_adj(const SfItem *items, int64_t n_items, bool friedel, const int64_t *refl_offset,
-                        const double *tt, const double *dy, double t0, double dt, int64_t n, double sigma,
-                        double window, double *w1, double *w2, hipStream_t s) {
-  if (n_items <= 0) return;
+void launch_broaden_adj(const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan, bool friedel,
+                        const int64_t *refl_offset, const double *tt, const double *dy, double t0, double dt,
+                        int64_t n, double sigma, double window, double *w1, double *w2, hipStream_t s) {
+  if (n_hchunks <= 0) return;
   const GridArgs g = make_grid(t0, dt, n, sigma, window);
-  hipLaunchKernelGGL(k_broaden_adj, dim3((unsigned)((n_items + 3) / 4)), dim3(256), 0, s, items, n_items, friedel,
-                     refl_offset, tt, dy, g, w1, w2);
+  if (n <= kAdjDyLds)
+    hipLaunchKernelGGL(k_broaden_adj<true>, dim3((unsigned)n_hchunks), dim3(256), (size_t)n * sizeof(double), s,
+                       hchunk_crystal, plan, friedel, refl_offset, tt, dy, g, w1, w2);
+  else
+    hipLaunchKernelGGL(k_broaden_adj<false>, dim3((unsigned)n_hchunks), dim3(256), 0, s, hchunk_crystal, plan,
+                       friedel, refl_offset, tt, dy, g, w1, w2);
 }
 
 void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s) {

@@ -222,8 +222,7 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
         float pa[R], pb[R];
 #pragma unroll
         for (int u = 0; u < R; ++u) pa[u] = pb[u] = 0.f;
-        for (int j = j0; j < j1; ++j) {
-          const AtomRec a = atoms[j];
+        auto term = [&](const AtomRec &a) {
 #pragma unroll
           for (int u = 0; u < R; ++u) {
             const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
@@ -234,7 +233,17 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
             pa[u] = fmaf(w, cs, pa[u]);
             pb[u] = fmaf(w, sn, pb[u]);
           }
+        };
+        // four records per round: their scalar loads are issued together
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+          const AtomRec a0 = atoms[j], a1 = atoms[j + 1], a2 = atoms[j + 2], a3 = atoms[j + 3];
+          term(a0);
+          term(a1);
+          term(a2);
+          term(a3);
         }
+        for (; j < j1; ++j) term(atoms[j]);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
           two_sum_acc(Sa[u], Ea[u], f[u] * pa[u]);
@@ -361,7 +370,8 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
                                                     const int32_t *__restrict__ run_count,
                                                     const double *__restrict__ coeff, const double *__restrict__ w1,
                                                     const double *__restrict__ w2, double *__restrict__ ga,
-                                                    double *__restrict__ gb, double *__restrict__ dq) {
+                                                    double *__restrict__ gb, double *__restrict__ dq,
+                                                    double4 *__restrict__ part_fused) {
   constexpr int R = kSfRpt;
   // the wavefront index is uniform; say so, so that everything derived from
   // the item (crystal, runs, atom records) is loaded once per wave into SGPRs
@@ -482,8 +492,10 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
   }
   const double m = friedel ? 2.0 : 1.0;
   const double l2 = lambda * lambda;
+  double gA[R], gB[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
+    gA[u] = gB[u] = 0.0;
     if (!valid[u]) continue;
     const int64_t i = idx[u];
     const double q = qq[i], lp = lpp[i];
@@ -497,19 +509,109 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
     const double dtt_dq = (360.0 / 3.14159265358979323846) * lambda / (4.0 * sqrt(q) * sq);
     const double f2 = A[u] * A[u] + B[u] * B[u];
     const double gI = m * w1[i];
-    const double gA = 2.0 * lp * A[u] * gI, gB = 2.0 * lp * B[u] * gI;
-    ga[i] = gA;
-    gb[i] = gB;
-    dq[i] = gI * f2 * dlp_dq + 0.25 * (gA * dA[u] + gB * dB[u]) + m * w2[i] * f2 * lp * dtt_dq;
+    gA[u] = 2.0 * lp * A[u] * gI;
+    gB[u] = 2.0 * lp * B[u] * gI;
+    if (!P.fused) {
+      ga[i] = gA[u];
+      gb[i] = gB[u];
+    }
+    dq[i] = gI * f2 * dlp_dq + 0.25 * (gA[u] * dA[u] + gB[u] * dB[u]) + m * w2[i] * f2 * lp * dtt_dq;
+  }
+  if (!P.fused) return;
+  // Fused atom gradients (small crystals): walk the atoms again; for each atom
+  // the lanes' contributions from this tile's reflections are summed across
+  // the wavefront and written as one partial row (tile, atom):
+  //   (sum h P, sum k P, sum l P, sum s^2 Q),  P = w (gB cos - gA sin),
+  //   Q = w (gA cos + gB sin),  w = occ f e^{-B s^2}.
+  double4 *out = part_fused + P.pf_begin + (int64_t)it.tile * (P.atom_end - P.atom_begin);
+  for (int ir = 0; ir < nr; ++ir) {
+    const SpeciesRun run = cr[ir];
+    const double *c9 = coeff + 9 * run.species;
+    if constexpr (MIXED) {
+      float f[R], fA[R], fB[R], hf[R], kf[R], lf[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        f[u] = fsc_f32(c9, s2[u]);
+        fA[u] = (float)gA[u] * f[u];
+        fB[u] = (float)gB[u] * f[u];
+        hf[u] = (float)h[u];
+        kf[u] = (float)k[u];
+        lf[u] = (float)l[u];
+      }
+      for (int j = run.begin; j < run.end; ++j) {
+        const AtomRec a = atoms[j];
+        float sx = 0.f, sy = 0.f, sz = 0.f, sb = 0.f;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+          const float rho = (float)__builtin_amdgcn_fract(t);
+          const float sn = __builtin_amdgcn_sinf(rho);
+          const float cs = __builtin_amdgcn_cosf(rho);
+          const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
+          const float pP = w * (fB[u] * cs - fA[u] * sn);
+          const float pQ = w * (fA[u] * cs + fB[u] * sn);
+          sx = fmaf(hf[u], pP, sx);
+          sy = fmaf(kf[u], pP, sy);
+          sz = fmaf(lf[u], pP, sz);
+          sb = fmaf(s2[u], pQ, sb);
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+          sx += __shfl_xor(sx, d, 64);
+          sy += __shfl_xor(sy, d, 64);
+          sz += __shfl_xor(sz, d, 64);
+          sb += __shfl_xor(sb, d, 64);
+        }
+        if (lane == 0) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
+      }
+    } else {
+      double f[R], fA[R], fB[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        f[u] = fsc_f64(c9, s2d[u]);
+        fA[u] = gA[u] * f[u];
+        fB[u] = gB[u] * f[u];
+      }
+      for (int j = run.begin; j < run.end; ++j) {
+        const AtomRec a = atoms[j];
+        double sx = 0.0, sy = 0.0, sz = 0.0, sb = 0.0;
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+          const double rho = t - rint(t);
+          double sn, cs;
+          sincospi(2.0 * rho, &sn, &cs);
+          const double w = a.occ * exp(-a.bfac * s2d[u]);
+          const double pP = w * (fB[u] * cs - fA[u] * sn);
+          const double pQ = w * (fA[u] * cs + fB[u] * sn);
+          sx = fma(h[u], pP, sx);
+          sy = fma(k[u], pP, sy);
+          sz = fma(l[u], pP, sz);
+          sb = fma(s2d[u], pQ, sb);
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) {
+          sx += __shfl_xor(sx, d, 64);
+          sy += __shfl_xor(sy, d, 64);
+          sz += __shfl_xor(sz, d, 64);
+          sb += __shfl_xor(sb, d, 64);
+        }
+        if (lane == 0) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
+      }
+    }
   }
 }
 
-// Atom-major pass: block = (crystal, 256 atoms, chunk of kHalfChunk evaluated
-// reflections).  Reflection tiles are staged in LDS with the scattering
-// factor of every species of the crystal; each thread accumulates for its atom
+// Atom-major pass: block = (crystal, up to 256 atoms, chunk of kHalfChunk
+// evaluated reflections).  Reflection tiles are staged in LDS with the
+// scattering factor of every species of the crystal; each thread accumulates
+// for its atom
 //   dx += h P, dy += k P, dz += l P with P = w (gB cos phi - gA sin phi),
-//   dB += s^2 Q with Q = w (gA cos phi + gB sin phi),   w = occ f e^{-B s^2},
-// and writes the chunk's partial sums (the reduction applies 2 pi and -1).
+//   dB += s^2 Q with Q = w (gA cos phi + gB sin phi),   w = occ f e^{-B s^2}.
+// A block whose crystal has A < 256 atoms splits into S = 256 / A slices that
+// take every S-th reflection of a tile; the slices' sums are added in slice
+// order through LDS, so the result does not depend on scheduling.  Writes the
+// chunk's partial sums (the reduction applies 2 pi and the sign of dB).
 template <bool MIXED>
 __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__ items, bool friedel,
                                                       const CrystalPlan *__restrict__ plan,
@@ -530,7 +632,8 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
   real *ts2 = (real *)(tl + tile);
   real *tga = ts2 + tile;
   real *tgb = tga + tile;
-  real *tf = tgb + tile;  // [tile][runs_cap]
+  real *tf = tgb + tile;           // [tile][runs_cap]
+  real *tcoef = tf + tile * runs_cap;  // [runs_cap][9]: the crystal's species coefficients
 
   const BwItem it = items[blockIdx.x];
   const CrystalPlan &P = plan[it.crystal];
@@ -539,14 +642,18 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
   const int64_t first = friedel ? r0 + nref / 2 : r0;
   const int64_t count = friedel ? nref / 2 : nref;
   const int64_t na = P.atom_end - P.atom_begin;
-  const int64_t ja = (int64_t)it.ablock * kAtomBlock + threadIdx.x;  // atom within crystal
-  const bool valid = ja < na;
-  const int64_t j = P.atom_begin + (valid ? ja : 0);
+  const int64_t a_base = (int64_t)it.ablock * kAtomBlock;
+  const int A = (int)min((int64_t)kAtomBlock, na - a_base);  // atoms of this block (>= 1)
+  const int S = kThreads / A;                                // slices
+  const int slice = threadIdx.x / A, al = threadIdx.x - slice * A;
+  const bool valid = slice < S;
+  const int64_t ja = a_base + (valid ? al : 0);  // atom within the crystal
+  const int64_t j = P.atom_begin + ja;
   double4 *out = part + P.part_begin + (int64_t)it.chunk * na;
   const int64_t e0 = (int64_t)it.chunk * kHalfChunk;
   const int64_t e1 = min(e0 + (int64_t)kHalfChunk, count);
   if (e0 >= e1) {  // chunk beyond this crystal's reflections: zero partials
-    if (valid) out[ja] = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (valid && slice == 0) out[ja] = make_double4(0.0, 0.0, 0.0, 0.0);
     return;
   }
   const SpeciesRun *cr = runs + P.run_begin;
@@ -554,6 +661,10 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
   int myrun = 0;
   for (int ir = 0; ir < nr; ++ir)
     if (j >= cr[ir].begin && j < cr[ir].end) myrun = ir;
+  for (int x = threadIdx.x; x < nr * 9; x += kThreads) {
+    const int ir = x / 9, q9 = x - ir * 9;
+    tcoef[ir * 9 + q9] = (real)coeff[9 * cr[ir].species + q9];
+  }
   const AtomRec a = atoms[j];
   double sx = 0.0, sy = 0.0, sz = 0.0, sB = 0.0;
   for (int64_t t0 = e0; t0 < e1; t0 += tile) {
@@ -576,15 +687,20 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
     __syncthreads();
     for (int x = threadIdx.x; x < tile * nr; x += kThreads) {
       const int r = x / nr, ir = x - r * nr;
-      const double *c9 = coeff + 9 * cr[ir].species;
-      if constexpr (MIXED) tf[r * runs_cap + ir] = fsc_f32(c9, ts2[r]);
-      else tf[r * runs_cap + ir] = fsc_f64(c9, ts2[r]);
+      const real *c9 = tcoef + 9 * ir;
+      real f = c9[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if constexpr (MIXED) f = fmaf(c9[i], __builtin_amdgcn_exp2f(-c9[4 + i] * kLog2e * ts2[r]), f);
+        else f = fma(c9[i], exp(-c9[4 + i] * ts2[r]), f);
+      }
+      tf[r * runs_cap + ir] = f;
     }
     __syncthreads();
     if (valid) {
       const int nt = (int)min((int64_t)tile, e1 - t0);
       real px = 0, py = 0, pz = 0, pB = 0;
-      for (int r = 0; r < nt; ++r) {
+      for (int r = slice; r < nt; r += S) {
         const double t = fma(th[r], a.x, fma(tk[r], a.y, tl[r] * a.z));
         real sn, cs, w;
         if constexpr (MIXED) {
@@ -610,14 +726,31 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
       sB += (double)pB;
     }
   }
-  if (valid) out[ja] = make_double4(sx, sy, sz, sB);
+  // slice sums in slice order
+  __syncthreads();
+  double4 *red = (double4 *)smem;  // kThreads entries; the tile arrays are no longer needed
+  red[threadIdx.x] = make_double4(sx, sy, sz, sB);
+  __syncthreads();
+  if (valid && slice == 0) {
+    double4 v = red[al];
+    for (int s2 = 1; s2 < S; ++s2) {
+      const double4 o = red[s2 * A + al];
+      v.x += o.x;
+      v.y += o.y;
+      v.z += o.z;
+      v.w += o.w;
+    }
+    out[ja] = v;
+  }
 }
 
-// Sum of the chunk partials in chunk order; scatter to the caller's atom order.
-
-__global__ __launch_bounds__(kThreads) void k_atom_bw_reduce(const AbItem *__restrict__ items,
+// Sum of the partials of each atom in a fixed order (tile order for fused
+// crystals, chunk order otherwise); scatter to the caller's atom order.
+__global__ __launch_bounds__(kThreads) void k_atom_bw_reduce(const AbItem *__restrict__ items, bool friedel,
                                                              const CrystalPlan *__restrict__ plan,
+                                                             const int64_t *__restrict__ refl_offset,
                                                              const double4 *__restrict__ part,
+                                                             const double4 *__restrict__ part_fused,
                                                              const int32_t *__restrict__ orig,
                                                              double *__restrict__ dfrac, double *__restrict__ dbfac) {
   const AbItem it = items[blockIdx.x];
@@ -625,14 +758,28 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw_reduce(const AbItem *__res
   const int64_t na = P.atom_end - P.atom_begin;
   const int64_t ja = (int64_t)it.ablock * kAtomBlock + threadIdx.x;
   if (ja >= na) return;
-  const double4 *p = part + P.part_begin + ja;
   double sx = 0.0, sy = 0.0, sz = 0.0, sB = 0.0;
-  for (int k = 0; k < P.n_hchunks; ++k) {
-    const double4 v = p[(int64_t)k * na];
-    sx += v.x;
-    sy += v.y;
-    sz += v.z;
-    sB += v.w;
+  if (P.fused) {
+    const int64_t nref = refl_offset[it.crystal + 1] - refl_offset[it.crystal];
+    const int64_t count = friedel ? nref / 2 : nref;
+    const int64_t tiles = (count + kSfTile - 1) / kSfTile;  // tiles that ran
+    const double4 *p = part_fused + P.pf_begin + ja;
+    for (int64_t t = 0; t < tiles; ++t) {
+      const double4 v = p[t * na];
+      sx += v.x;
+      sy += v.y;
+      sz += v.z;
+      sB += v.w;
+    }
+  } else {
+    const double4 *p = part + P.part_begin + ja;
+    for (int k = 0; k < P.n_hchunks; ++k) {
+      const double4 v = p[(int64_t)k * na];
+      sx += v.x;
+      sy += v.y;
+      sz += v.z;
+      sB += v.w;
+    }
   }
   const double tp = 2.0 * 3.14159265358979323846;
   const int64_t o = orig[P.atom_begin + ja];
@@ -725,20 +872,24 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
                   const int32_t *run_count, const double *coeff, const double *w1, const double *w2, double *ga,
-                  double *gb, double *dq, hipStream_t s) {
+                  double *gb, double *dq, double *part_fused, hipStream_t s) {
   if (n_items <= 0) return;
   const dim3 grid((unsigned)((n_items + 3) / 4)), block(kThreads);
+  double4 *pf = (double4 *)part_fused;
   if (mixed)
     hipLaunchKernelGGL(k_sf_bw<true>, grid, block, 0, s, items, n_items, friedel, plan, refl_offset, h, k, l, q, lp,
-                       lambda, atoms, runs, run_count, coeff, w1, w2, ga, gb, dq);
+                       lambda, atoms, runs, run_count, coeff, w1, w2, ga, gb, dq, pf);
   else
     hipLaunchKernelGGL(k_sf_bw<false>, grid, block, 0, s, items, n_items, friedel, plan, refl_offset, h, k, l, q, lp,
-                       lambda, atoms, runs, run_count, coeff, w1, w2, ga, gb, dq);
+                       lambda, atoms, runs, run_count, coeff, w1, w2, ga, gb, dq, pf);
 }
 
 size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap) {
   const size_t rs = mixed ? sizeof(float) : sizeof(double);
-  return (size_t)tile * 3 * sizeof(double) + (size_t)tile * 3 * rs + (size_t)tile * runs_cap * rs;
+  const size_t tiles = (size_t)tile * 3 * sizeof(double) + (size_t)tile * 3 * rs + (size_t)tile * runs_cap * rs +
+                       (size_t)runs_cap * 9 * rs;
+  const size_t red = (size_t)kThreads * sizeof(double4);  // slice reduction reuses the space
+  return tiles > red ? tiles : red;
 }
 
 void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,
@@ -759,11 +910,12 @@ void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_ite
                        (double4 *)part);
 }
 
-void launch_atom_bw_reduce(const AbItem *items, int64_t n_items, const CrystalPlan *plan, const double *part,
+void launch_atom_bw_reduce(const AbItem *items, int64_t n_items, bool friedel, const CrystalPlan *plan,
+                           const int64_t *refl_offset, const double *part, const double *part_fused,
                            const int32_t *orig, double *dfrac, double *dbfac, hipStream_t s) {
   if (n_items <= 0) return;
-  hipLaunchKernelGGL(k_atom_bw_reduce, dim3((unsigned)n_items), dim3(kThreads), 0, s, items, plan,
-                     (const double4 *)part, orig, dfrac, dbfac);
+  hipLaunchKernelGGL(k_atom_bw_reduce, dim3((unsigned)n_items), dim3(kThreads), 0, s, items, friedel, plan,
+                     refl_offset, (const double4 *)part, (const double4 *)part_fused, orig, dfrac, dbfac);
 }
 
 void launch_gstar_part(const int32_t *hchunk_crystal, int64_t n_hchunks, bool friedel, const CrystalPlan *plan,

@@ -2,7 +2,9 @@
 // peaks (paper, Section 2: merging of reflections within specified angular
 // tolerances; grouping of reflections into peaks).
 //
-// Sort: a bucket sort with exactly monotone buckets.  The bucket of a
+// Sort: crystals of up to 4096 reflections are sorted by one block each in
+// LDS; larger crystals use the same bucket sort through global memory.  The
+// buckets are exactly monotone.  The bucket of a
 // reflection is floor((2theta - tmin) * bins_per_degree), clamped; a
 // subtraction, a product with a positive constant and floor are each monotone
 // in IEEE arithmetic, so bucket order never contradicts key order and equal
@@ -27,6 +29,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kPer = kSortChunk / kThreads;  // 4
+constexpr int kSmallSort = 4096;              // reflections sorted by one block in LDS
+static_assert(kSortChunk / kBinDiv == kThreads, "one bucket per thread of a sort chunk");
 
 __device__ __forceinline__ int bin_of(const CrystalPlan &P, double tt) {
 #pragma clang fp contract(off)
@@ -57,11 +61,102 @@ __device__ __forceinline__ ChunkRange chunk_range(const CrystalPlan *__restrict_
   return c;
 }
 
+// Crystals with at most kSmallSort reflections: one block sorts the whole
+// crystal in LDS with the same monotone buckets as the large-crystal path
+// (R/2 of them): count with LDS atomics, scan, scatter with LDS atomics, then
+// an insertion sort of each bucket on (2theta bits, position).  The input is
+// in lexicographic (h, k, l) order, so ordering ties by position orders them
+// by (h, k, l); positive doubles order like their bit patterns.
+__global__ __launch_bounds__(kThreads) void k_sort_small(const CrystalPlan *__restrict__ plan,
+                                                         const int64_t *__restrict__ refl_offset,
+                                                         const double *__restrict__ tt, double *__restrict__ skey,
+                                                         int32_t *__restrict__ sidx) {
+  __shared__ uint64_t key[kSmallSort];
+  __shared__ uint32_t pos[kSmallSort];
+  __shared__ int32_t cnt[kSmallSort / 2];
+  __shared__ int32_t wsum[kThreads / 64];
+  const CrystalPlan &P = plan[blockIdx.x];
+  const int64_t r0 = refl_offset[blockIdx.x], r1 = refl_offset[blockIdx.x + 1];
+  if (r1 - r0 > kSmallSort || r1 <= r0) return;
+  const int R = (int)(r1 - r0);
+  const int B = R / 2 > 1 ? R / 2 : 1;
+  const double scale = (double)B / (P.tmax - P.tmin);
+  for (int b = threadIdx.x; b < B; b += kThreads) cnt[b] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < R; i += kThreads) {
+#pragma clang fp contract(off)
+    const double x = floor((tt[r0 + i] - P.tmin) * scale);
+    const int b = x < 0.0 ? 0 : (x >= (double)(B - 1) ? B - 1 : (int)x);
+    atomicAdd(&cnt[b], 1);
+  }
+  __syncthreads();
+  // exclusive scan of the bucket counts: each thread owns a contiguous run
+  {
+    constexpr int per = (kSmallSort / 2 + kThreads - 1) / kThreads;
+    const int b0 = threadIdx.x * per;
+    int v[per], sum = 0;
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+      v[u] = b0 + u < B ? cnt[b0 + u] : 0;
+      sum += v[u];
+    }
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int inc = sum;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int ex = inc - sum;
+    for (int w = 0; w < wid; ++w) ex += wsum[w];
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+      if (b0 + u < B) cnt[b0 + u] = ex;
+      ex += v[u];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < R; i += kThreads) {
+#pragma clang fp contract(off)
+    const double t = tt[r0 + i];
+    const double x = floor((t - P.tmin) * scale);
+    const int b = x < 0.0 ? 0 : (x >= (double)(B - 1) ? B - 1 : (int)x);
+    const int slot = atomicAdd(&cnt[b], 1);
+    key[slot] = (uint64_t)__double_as_longlong(t);
+    pos[slot] = (uint32_t)i;
+  }
+  __syncthreads();
+  // cnt[b] is now the end of bucket b, and its start is the end of bucket b - 1
+  for (int b = threadIdx.x; b < B; b += kThreads) {
+    const int s = b ? cnt[b - 1] : 0, e = cnt[b];
+    for (int i = s + 1; i < e; ++i) {
+      const uint64_t k = key[i];
+      const uint32_t p = pos[i];
+      int j = i - 1;
+      while (j >= s && (key[j] > k || (key[j] == k && pos[j] > p))) {
+        key[j + 1] = key[j];
+        pos[j + 1] = pos[j];
+        --j;
+      }
+      key[j + 1] = k;
+      pos[j + 1] = p;
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < R; i += kThreads) {
+    skey[r0 + i] = __longlong_as_double((long long)key[i]);
+    sidx[r0 + i] = (int32_t)(r0 + pos[i]);
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_bin_count(const CrystalPlan *__restrict__ plan,
                                                         const int32_t *__restrict__ chunk_crystal,
                                                         const int64_t *__restrict__ refl_offset,
                                                         const double *__restrict__ tt, int32_t *__restrict__ count) {
   const ChunkRange cr = chunk_range(plan, chunk_crystal, refl_offset);
+  if (cr.r1 - cr.r0 <= kSmallSort) return;  // sorted in LDS by k_sort_small
   const CrystalPlan &P = plan[cr.cry];
   for (int u = 0; u < kPer; ++u) {
     const int64_t i = cr.base + u * kThreads + threadIdx.x;
@@ -78,26 +173,41 @@ __global__ __launch_bounds__(kThreads) void k_bin_scatter(const CrystalPlan *__r
                                                           int32_t *__restrict__ count, double *__restrict__ skey,
                                                           int32_t *__restrict__ sidx) {
   const ChunkRange cr = chunk_range(plan, chunk_crystal, refl_offset);
+  if (cr.r1 - cr.r0 <= kSmallSort) return;
   const CrystalPlan &P = plan[cr.cry];
   for (int u = 0; u < kPer; ++u) {
     const int64_t i = cr.base + u * kThreads + threadIdx.x;
     if (i >= cr.r1) break;
     const double t = tt[i];
     const int64_t gb = P.bin_begin + bin_of(P, t);
-    const int64_t slot = start[gb] + atomicSub(&count[gb], 1) - 1;
+    // bucket ranges are relative to the crystal's first bucket: crystals
+    // sorted in LDS leave their buckets empty, so the global prefix is not
+    // the crystal's reflection offset
+    const int64_t slot = cr.r0 + (start[gb] - start[P.bin_begin]) + atomicSub(&count[gb], 1) - 1;
     skey[slot] = t;
     sidx[slot] = (int32_t)i;
   }
 }
 
-// One thread per bin: insertion sort on (2theta, h, k, l).  Bins hold a few
-// reflections on average (at most a few tens for high-symmetry cells).
-__global__ void k_bin_sort(const int64_t *__restrict__ start, int64_t n_bins, double *__restrict__ skey,
-                           int32_t *__restrict__ sidx, const int16_t *__restrict__ h, const int16_t *__restrict__ k,
-                           const int16_t *__restrict__ l) {
-  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= n_bins) return;
-  const int64_t s = start[b], e = start[b + 1];
+// One thread per bucket of a large crystal (blocks follow the sort chunks:
+// 256 buckets per chunk, and a crystal has at most 256 buckets per chunk):
+// insertion sort on (2theta, h, k, l).  Buckets hold a few reflections on
+// average (at most a few tens for high-symmetry cells).
+__global__ __launch_bounds__(kThreads) void k_bin_sort(const CrystalPlan *__restrict__ plan,
+                                                       const int32_t *__restrict__ chunk_crystal,
+                                                       const int64_t *__restrict__ refl_offset,
+                                                       const int64_t *__restrict__ start, double *__restrict__ skey,
+                                                       int32_t *__restrict__ sidx, const int16_t *__restrict__ h,
+                                                       const int16_t *__restrict__ k,
+                                                       const int16_t *__restrict__ l) {
+  const int32_t cry = chunk_crystal[blockIdx.x];
+  const CrystalPlan &P = plan[cry];
+  const int64_t r0 = refl_offset[cry], r1 = refl_offset[cry + 1];
+  if (r1 - r0 <= kSmallSort) return;
+  const int64_t bl = (int64_t)(blockIdx.x - P.sort_chunk_begin) * kThreads + threadIdx.x;
+  if (bl >= P.n_bins) return;
+  const int64_t b = P.bin_begin + bl;
+  const int64_t s = r0 + (start[b] - start[P.bin_begin]), e = r0 + (start[b + 1] - start[P.bin_begin]);
   for (int64_t i = s + 1; i < e; ++i) {
     const double key = skey[i];
     const int32_t id = sidx[i];
@@ -241,6 +351,9 @@ __global__ void k_peak_offsets_compact(int64_t n_c, const int64_t *__restrict__ 
 }  // namespace
 
 void launch_sort(const SortArgs &a, hipStream_t s) {
+  if (a.n_c > 0)
+    hipLaunchKernelGGL(k_sort_small, dim3((unsigned)a.n_c), dim3(kThreads), 0, s, a.plan, a.refl_offset, a.tt,
+                       a.skey, a.sidx);
   launch_fill_i32(a.bin_count, a.n_bins, 0, s);
   if (a.n_chunks > 0)
     hipLaunchKernelGGL(k_bin_count, dim3((unsigned)a.n_chunks), dim3(kThreads), 0, s, a.plan, a.chunk_crystal,
@@ -249,14 +362,13 @@ void launch_sort(const SortArgs &a, hipStream_t s) {
   if (a.n_chunks > 0)
     hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)a.n_chunks), dim3(kThreads), 0, s, a.plan, a.chunk_crystal,
                        a.refl_offset, a.tt, a.bin_start, a.bin_count, a.skey, a.sidx);
-  if (a.n_bins > 0)
-    hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)((a.n_bins + 255) / 256)), dim3(256), 0, s, a.bin_start, a.n_bins,
-                       a.skey, a.sidx, a.h, a.k, a.l);
+  if (a.n_chunks > 0)
+    hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)a.n_chunks), dim3(kThreads), 0, s, a.plan, a.chunk_crystal,
+                       a.refl_offset, a.bin_start, a.skey, a.sidx, a.h, a.k, a.l);
 }
 
 void launch_merge(const MergeArgs &a, hipStream_t s) {
-  const SortArgs &o = a.sort;
-  launch_sort(o, s);
+  const SortArgs &o = a.sort;  // sorted by the caller
   launch_fill_u64(a.cmax, a.n_c, 0, s);
   const dim3 cg((unsigned)(o.n_chunks > 0 ? o.n_chunks : 1)), cb(kThreads);
   if (o.n_chunks > 0)

@@ -21,6 +21,7 @@ constexpr int kScanBlock = 2048;  // elements per scan block (256 threads x 8)
 constexpr int kAtomBlock = 256;   // atoms per adjoint block
 constexpr int kSfRpt = 2;         // reflections per lane in the structure-factor kernel
 constexpr int kSfTile = 64 * kSfRpt;
+constexpr int kFusedMaxAtoms = 512;  // crystals up to this size take the fused atom-gradient path
 
 // Per-crystal plan (device copy in the workspace), 256 bytes.
 struct alignas(16) CrystalPlan {
@@ -42,8 +43,10 @@ struct alignas(16) CrystalPlan {
   int64_t hchunk_begin;  // first adjoint chunk (global id)
   int64_t part_begin;    // first adjoint partial row: rows = n_hchunks * N
   int32_t sort_chunks;
+  int32_t fused;       // 1: atom gradients reduced inside the reflection-major adjoint
+  int64_t pf_begin;    // first row of the fused adjoint partials: rows = n_tiles * N
+  int32_t n_tiles;     // structure-factor tiles at capacity
   int32_t pad0;
-  double pad1[2];
 };
 static_assert(sizeof(CrystalPlan) == 256, "CrystalPlan layout");
 
@@ -77,7 +80,7 @@ struct WsLayout {
   int64_t flags, pscan;
   int64_t cmax, n_peaks, tmp_tt, tmp_i, tmp_y, tmp_mult, tmp_first, keep, kscan, raw_peak_offset;
   int64_t scan_part;
-  int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6;
+  int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6, bw_partf;
   int64_t total;
 };
 
@@ -113,6 +116,7 @@ void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, c
                const double *coeff, void *A, void *B, double *I, hipStream_t s);
 
 struct SortArgs {
+  int64_t n_c;
   const CrystalPlan *plan;
   const int32_t *chunk_crystal;
   int64_t n_chunks;
@@ -152,25 +156,26 @@ struct MergeArgs {
 };
 void launch_merge(const MergeArgs &a, hipStream_t s);
 
-void launch_broaden_fwd(int64_t n_c, const int64_t *refl_offset, const double *skey, const int32_t *sidx,
-                        const double *inten, double t0, double dt, int64_t n, double sigma, double window, double *y,
-                        hipStream_t s);
-void launch_broaden_adj(const SfItem *items, int64_t n_items, bool friedel, const int64_t *refl_offset,
-                        const double *tt, const double *dy, double t0, double dt, int64_t n, double sigma,
-                        double window, double *w1, double *w2, hipStream_t s);
+void launch_broaden_fwd(bool mixed, int64_t n_c, const int64_t *refl_offset, const double *skey,
+                        const int32_t *sidx, const double *inten, bool friedel, double t0, double dt, int64_t n,
+                        double sigma, double window, double *y, hipStream_t s);
+void launch_broaden_adj(const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan, bool friedel,
+                        const int64_t *refl_offset, const double *tt, const double *dy, double t0, double dt,
+                        int64_t n, double sigma, double window, double *w1, double *w2, hipStream_t s);
 void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s);
 void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
                   const int32_t *run_count, const double *coeff, const double *w1, const double *w2, double *ga,
-                  double *gb, double *dq, hipStream_t s);
+                  double *gb, double *dq, double *part_fused, hipStream_t s);
 size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap);
 void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,
                     const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
                     const double *q, const double *ga, const double *gb, const AtomRec *atoms,
                     const SpeciesRun *runs, const int32_t *run_count, const double *coeff, int tile, int runs_cap,
                     double *part, hipStream_t s);
-void launch_atom_bw_reduce(const AbItem *items, int64_t n_items, const CrystalPlan *plan, const double *part,
+void launch_atom_bw_reduce(const AbItem *items, int64_t n_items, bool friedel, const CrystalPlan *plan,
+                           const int64_t *refl_offset, const double *part, const double *part_fused,
                            const int32_t *orig, double *dfrac, double *dbfac, hipStream_t s);
 void launch_gstar_part(const int32_t *hchunk_crystal, int64_t n_hchunks, bool friedel, const CrystalPlan *plan,
                        const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,

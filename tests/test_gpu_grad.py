@@ -1,0 +1,163 @@
+"""Adjoint of the broadened pattern against central finite differences of the
+FP64 oracle's loss (h = 1e-6 in each parameter's own unit: fractional
+coordinate, Angstrom, degree, Angstrom^2).
+
+The target pattern is the oracle's broadened pattern of the perturbed
+structure; the loss is the mean over crystals and grid points of
+(y - target)^2.  Bars: ||g - g_FD|| / ||g_FD|| <= 1e-7 for the double adjoint
+and <= 1e-4 for the mixed one (float sin/cos and weights carry ~1e-7
+relative error per term, and per-atom sums over ~1e4 reflections cancel
+strongly, which costs up to three more digits)."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_11709_amd import synth
+
+pytestmark = pytest.mark.gpu
+H = 1e-6
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2602_11709_amd import capi
+    capi.lib()
+
+
+def problem(n_crystals, atoms_lo, atoms_hi, grid_n=4001, seed=4):
+    return synth.gradient_problem(seed=seed, n_crystals=n_crystals, atoms_lo=atoms_lo, atoms_hi=atoms_hi,
+                                  grid_n=grid_n)
+
+
+def grid_args(p):
+    return (p.grid_t0, p.grid_dt, p.grid_n, p.sigma, p.window_sigmas)
+
+
+def targets_of(p):
+    return [oracle.broadened(p.target, c, *grid_args(p)) for c in range(p.target.n_crystals)]
+
+
+def gpu_grads(p, targets, precision):
+    from paper_2602_11709_amd.api import Grid, xrd_pattern
+    b = p.batch
+    frac = torch.tensor(b.frac, device="cuda", requires_grad=True)
+    lat = torch.tensor(b.lattice, requires_grad=True)
+    bf = torch.tensor(b.bfac, device="cuda", requires_grad=True)
+    grid = Grid(p.grid_t0, p.grid_dt, p.grid_n, p.sigma, p.window_sigmas)
+    y = xrd_pattern(frac, lat, bf, b, grid, precision=precision)
+    T = torch.tensor(np.stack(targets), device="cuda")
+    loss = ((y - T) ** 2).mean()
+    loss.backward()
+    return (float(loss), y.detach().cpu().numpy(), frac.grad.cpu().numpy(), lat.grad.numpy(),
+            bf.grad.cpu().numpy())
+
+
+def sse(b, c, target, p):
+    y = oracle.broadened(b, c, *grid_args(p))
+    d = y - target
+    return float(d @ d)
+
+
+def fd(p, targets, c, kind, idx, direction=None):
+    """Central difference of the loss in one parameter (or a direction)."""
+    scale = 1.0 / (p.batch.n_crystals * p.grid_n)
+    vals = []
+    for sgn in (+1, -1):
+        b = p.batch.subset(range(p.batch.n_crystals))
+        if kind == "frac":
+            b.frac[idx] += sgn * H
+        elif kind == "lattice":
+            b.lattice[c, idx] += sgn * H
+        elif kind == "bfac":
+            b.bfac[idx] += sgn * H
+        else:  # direction over all of crystal c's parameters
+            sl = b.atoms_of(c)
+            dfr, dla, dbf = direction
+            b.frac[sl] += sgn * H * dfr
+            b.lattice[c] += sgn * H * dla
+            b.bfac[sl] += sgn * H * dbf
+        vals.append(sse(b, c, targets[c], p))
+    return (vals[0] - vals[1]) / (2 * H) * scale
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-7), ("mixed", 1e-4)])
+def test_gradients_match_finite_differences(precision, bar):
+    p = problem(3, 12, 30)
+    targets = targets_of(p)
+    loss, y, gf, gl, gb = gpu_grads(p, targets, precision)
+    # forward parity of the broadened pattern itself
+    for c in range(p.batch.n_crystals):
+        yo = oracle.broadened(p.batch, c, *grid_args(p))
+        tol = 1e-10 if precision == "fp64" else 2e-5
+        assert np.max(np.abs(y[c] - yo)) <= tol * np.max(np.abs(yo)), f"crystal {c} pattern"
+    got, want, kind = [], [], []
+    rng = np.random.default_rng(0)
+    for c in range(p.batch.n_crystals):
+        sl = p.batch.atoms_of(c)
+        atoms = rng.choice(np.arange(sl.start, sl.stop), size=min(4, sl.stop - sl.start), replace=False)
+        for j in atoms:
+            for d in range(3):
+                got.append(gf[j, d])
+                want.append(fd(p, targets, c, "frac", (j, d)))
+                kind.append("frac")
+            got.append(gb[j])
+            want.append(fd(p, targets, c, "bfac", j))
+            kind.append("bfac")
+        for k in range(6):
+            got.append(gl[c, k])
+            want.append(fd(p, targets, c, "lattice", k))
+            kind.append("lattice")
+    got, want, kind = np.array(got), np.array(want), np.array(kind)
+    err = np.linalg.norm(got - want) / np.linalg.norm(want)
+    print(precision, "grad rel err", err, "components", len(got), flush=True)
+    assert err <= bar
+    # each block on its own too, so that an error in a small block cannot hide
+    for k in ("frac", "bfac", "lattice"):
+        m = kind == k
+        e = np.linalg.norm(got[m] - want[m]) / np.linalg.norm(want[m])
+        print(precision, k, "rel err", e, flush=True)
+        assert e <= bar
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-7), ("mixed", 1e-4)])
+def test_directional_derivative_full_size_crystals(precision, bar):
+    """Crystals of the full differentiation workload (50-500 atoms): the
+    gradient along a random direction of every parameter of a crystal."""
+    p = problem(2, 150, 300, seed=14)
+    targets = targets_of(p)
+    loss, y, gf, gl, gb = gpu_grads(p, targets, precision)
+    rng = np.random.default_rng(1)
+    for c in range(p.batch.n_crystals):
+        sl = p.batch.atoms_of(c)
+        n = sl.stop - sl.start
+        dfr = rng.normal(size=(n, 3))
+        dla = rng.normal(size=6)
+        dbf = rng.normal(size=n)
+        g_dir = float((gf[sl] * dfr).sum() + (gl[c] * dla).sum() + (gb[sl] * dbf).sum())
+        want = fd(p, targets, c, "direction", None, (dfr, dla, dbf))
+        rel = abs(g_dir - want) / abs(want)
+        print(precision, "crystal", c, "atoms", n, "directional rel err", rel, flush=True)
+        assert rel <= bar
+
+
+def test_gradient_of_full_differentiation_batch_runs_and_is_deterministic():
+    """256 crystals of 50-500 atoms: the backward runs at full size, twice
+    with identical bits (no float atomics anywhere in the reductions)."""
+    p = synth.gradient_problem()
+    from paper_2602_11709_amd.api import Grid, xrd_pattern
+    b = p.batch
+    grid = Grid(p.grid_t0, p.grid_dt, p.grid_n, p.sigma, p.window_sigmas)
+    outs = []
+    for _ in range(2):
+        frac = torch.tensor(b.frac, device="cuda", requires_grad=True)
+        lat = torch.tensor(b.lattice, requires_grad=True)
+        bf = torch.tensor(b.bfac, device="cuda", requires_grad=True)
+        y = xrd_pattern(frac, lat, bf, b, grid, precision="mixed")
+        (y * y).mean().backward()
+        outs.append((frac.grad.cpu().numpy(), lat.grad.numpy(), bf.grad.cpu().numpy()))
+    for a, bb in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, bb)
+        assert np.all(np.isfinite(a))
