@@ -192,6 +192,10 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     P.K = (int32_t)bk;
     P.L = (int32_t)bl;
     const int64_t box = (2 * (int64_t)P.H + 1) * (2 * (int64_t)P.K + 1) * (2 * (int64_t)P.L + 1);
+    if (box >= ((int64_t)1 << 31)) {
+      delete b;
+      return fail(XRD_ERR_CAPACITY, "crystal " + std::to_string(c) + ": search box exceeds 2^31 points");
+    }
     P.half_box = (box - 1) / 2;
     refl += 2 * P.half_box;
     if (refl >= ((int64_t)1 << 31) - 1) {
@@ -305,6 +309,9 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.err_flag = take(4);
   L.bin_count = take(4 * bins);
   L.bin_start = take(8 * (bins + 1));
+  L.big_list = take(4 * nc);
+  L.big_chunks = take(8 * sc);
+  L.sort_counters = take(8);
   L.skey = take(8 * rc);
   L.sidx = take(4 * rc);
   L.flags = take(4 * rc);
@@ -443,6 +450,9 @@ static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r) {
   a.skey = at<double>(ws, L.skey);
   a.sidx = at<int32_t>(ws, L.sidx);
   a.scan_part = at<int64_t>(ws, L.scan_part);
+  a.big_list = at<int32_t>(ws, L.big_list);
+  a.big_chunks = at<int2>(ws, L.big_chunks);
+  a.counters = at<int32_t>(ws, L.sort_counters);
   return a;
 }
 
@@ -492,7 +502,7 @@ static int check_grid(const xrd_grid *g) {
   if (!(g->n_points >= 1) || !(g->dt > 0.0) || !(g->sigma > 0.0) || !(g->window_sigmas > 0.0) ||
       !std::isfinite(g->t0) || !std::isfinite(g->dt) || !std::isfinite(g->sigma) || !std::isfinite(g->window_sigmas))
     return fail(XRD_ERR_INVALID_ARG, "grid needs n_points >= 1, dt > 0, sigma > 0, window_sigmas > 0");
-  if (g->n_points > ((int64_t)1 << 31) || g->dt < 1e-9 || std::fabs(g->t0) > 1e6 || g->window_sigmas > 30.0 ||
+  if (g->n_points >= ((int64_t)1 << 31) || g->dt < 1e-9 || std::fabs(g->t0) > 1e6 || g->window_sigmas > 30.0 ||
       g->window_sigmas * g->sigma > 1e3)
     return fail(XRD_ERR_INVALID_ARG, "grid out of range: n_points <= 2^31, dt >= 1e-9, |t0| <= 1e6, "
                                      "window_sigmas <= 30, window <= 1000 deg");
@@ -529,7 +539,7 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   const int64_t n_items = (int64_t)b->sf_items.size();
   double *w1 = at<double>(ws, L.bw_w1), *w2 = at<double>(ws, L.bw_w2);
   double *ga = at<double>(ws, L.bw_ga), *gb = at<double>(ws, L.bw_gb), *dq = at<double>(ws, L.bw_dq);
-  launch_broaden_adj(at<int32_t>(ws, L.hchunk_crystal), (int64_t)b->hchunk_crystal.size(), plan, friedel,
+  launch_broaden_adj(mixed, at<int32_t>(ws, L.hchunk_crystal), (int64_t)b->hchunk_crystal.size(), plan, friedel,
                      r->refl_offset, r->two_theta, dL_dy, g->t0, g->dt, g->n_points, g->sigma, g->window_sigmas, w1,
                      w2, s);
   launch_sf_bw(mixed, friedel, items, n_items, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,

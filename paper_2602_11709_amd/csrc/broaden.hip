@@ -16,6 +16,8 @@
 // dL/dG*.
 #include <math.h>
 
+#include <type_traits>
+
 #include "xrd_internal.h"
 
 namespace xrd {
@@ -62,27 +64,45 @@ struct GaussWalk {
   }
 };
 
-constexpr int kSegPts = 256;     // grid points per block of the forward gather (one per thread)
-constexpr int kTileR = 1024;     // reflections per LDS tile of the gather
-constexpr int kAdjDyLds = 8192;  // grid rows up to this length are staged in LDS by the adjoint
+constexpr int kPtsPerThread = 4;
+constexpr int kSegPts = 256 * kPtsPerThread;  // grid points per block of the forward gather
+constexpr int kTileR = 1024;                  // reflections per LDS tile of the gather
+constexpr int kAdjDyLds = 8192;               // grid rows up to this length are staged in LDS by the adjoint
+constexpr int kAdjSplit = 4;                  // adjoint blocks per chunk of evaluated reflections
 
-__device__ __forceinline__ int64_t lower_bound(const double *__restrict__ a, int64_t lo, int64_t hi, double v) {
-  while (lo < hi) {
-    const int64_t m = (lo + hi) >> 1;
-    if (a[m] < v) lo = m + 1;
-    else hi = m;
+// First position in [lo, hi) of a sorted array with a[i] >= v, searched by the
+// whole block: each level probes 256 evenly spaced positions with one load
+// per thread and counts the probes below v, so a level shrinks the range
+// 256-fold (two levels for a crystal of up to 65536 reflections).  Every
+// thread of the block must call it.
+__device__ __forceinline__ int64_t block_lower_bound(const double *__restrict__ a, int64_t lo, int64_t hi, double v) {
+  int64_t base = lo, len = hi - lo;
+  while (len > 0) {
+    const int64_t stride = (len + 255) / 256;
+    const int64_t p = base + (int64_t)threadIdx.x * stride;
+    const bool below = p < base + len && a[p] < v;
+    const int cnt = __syncthreads_count(below);
+    if (cnt == 0) return base;
+    const int64_t nb = base + (int64_t)(cnt - 1) * stride + 1;
+    const int64_t ne = min(base + (int64_t)cnt * stride, base + len);
+    base = nb;
+    len = ne - nb;
   }
-  return lo;
+  return base;
 }
 
-// Forward gather.  A block owns 256 consecutive grid points of one crystal,
-// a thread one point.  The crystal's 2theta-sorted reflections that reach the
-// block's points are staged through LDS in tiles (with Friedel pairing, whose
-// mates have bit-identical 2theta and I, one reflection per pair with twice
-// the intensity).  Each thread sums, in sorted order, the reflections whose
-// window holds its point: deterministic, no atomics.  The kernel value is
-// exp(-d^2 / 2 sigma^2) with d = x - 2theta in double; under MIXED the
-// exponential is taken in single precision (v_exp_f32 on -d^2 log2(e) / 2 sigma^2).
+// Forward gather.  A block owns kSegPts consecutive grid points of one
+// crystal; each thread kPtsPerThread of them, 256 apart.  The crystal's
+// 2theta-sorted reflections that reach the block's points are staged through
+// LDS in tiles (with Friedel pairing, whose mates have bit-identical 2theta
+// and I, one reflection per pair with twice the intensity), each with its
+// exact grid window [gl, gh] (the points with |x - 2theta| <= half).  Windows
+// are ordered like 2theta, so the reflections reaching point p form a range
+// [first e with gh_e >= p, last e with gl_e <= p]; both ends are scattered
+// into per-point LDS arrays, and every point then sums its range in sorted
+// order with no data-dependent exit: deterministic, no atomics.  The kernel
+// value is exp(-d^2 / 2 sigma^2) with d = x - 2theta in double; under MIXED
+// the exponential is taken in single precision (v_exp_f32).
 template <bool MIXED>
 __global__ __launch_bounds__(256) void k_broaden_fwd(const int64_t *__restrict__ refl_offset,
                                                      const double *__restrict__ skey,
@@ -91,32 +111,33 @@ __global__ __launch_bounds__(256) void k_broaden_fwd(const int64_t *__restrict__
                                                      double *__restrict__ y) {
 #pragma clang fp contract(off)
   __shared__ double s_tt[kTileR], s_i[kTileR];
-  __shared__ int64_t s_range[2];
+  __shared__ int32_t s_gl[kTileR], s_gh[kTileR];
+  __shared__ int16_t s_first[kSegPts], s_last[kSegPts];
   __shared__ int32_t s_wcnt[256 / 64];
   const int64_t segs = (g.n + kSegPts - 1) / kSegPts;
   const int64_t c = blockIdx.x / segs;
   const int64_t G0 = (int64_t)(blockIdx.x % segs) * kSegPts;
   const int64_t G1 = min(G0 + kSegPts, g.n) - 1;
-  const int64_t gi = G0 + threadIdx.x;
+  const int npts = (int)(G1 - G0 + 1);
   const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
   const int64_t mid = r0 + (r1 - r0) / 2;  // first reflection of the positive half
-  if (threadIdx.x == 0) {
-    const double xa = g.t0 + (double)G0 * g.dt, xb = g.t0 + (double)G1 * g.dt;
-    const double guard = 1e-9 * (fabs(xa) + fabs(xb) + 1.0);
-    s_range[0] = lower_bound(skey, r0, r1, xa - g.half - guard);
-    s_range[1] = lower_bound(skey, r0, r1, xb + g.half + guard);
-  }
-  __syncthreads();
-  const int64_t ja = s_range[0], jb = s_range[1];
-  const double x = g.t0 + (double)gi * g.dt;
-  const double guard = 1e-9 * (fabs(x) + 1.0);
+  const double xa = g.t0 + (double)G0 * g.dt, xb = g.t0 + (double)G1 * g.dt;
+  const double bguard = 1e-9 * (fabs(xa) + fabs(xb) + 1.0);
+  const int64_t ja = block_lower_bound(skey, r0, r1, xa - g.half - bguard);
+  const int64_t jb = block_lower_bound(skey, ja, r1, xb + g.half + bguard);
   const float c2 = (float)(g.inv2s2 * 1.4426950408889634);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double acc = 0.0;
+  double acc[kPtsPerThread], x[kPtsPerThread];
+#pragma unroll
+  for (int q = 0; q < kPtsPerThread; ++q) {
+    acc[q] = 0.0;
+    x[q] = g.t0 + (double)(G0 + q * 256 + threadIdx.x) * g.dt;
+  }
   for (int64_t jt = ja; jt < jb; jt += kTileR) {
     // stage in sorted order, compacted with a ballot per wave
     int base = 0;
-    for (int u = 0; u < kTileR / 256; ++u) {
+    const int rounds = (int)min((int64_t)(kTileR / 256), (jb - jt + 255) / 256);
+    for (int u = 0; u < rounds; ++u) {
       const int64_t j = jt + u * 256 + threadIdx.x;
       bool keep = j < jb;
       int32_t id = 0;
@@ -135,86 +156,113 @@ __global__ __launch_bounds__(256) void k_broaden_fwd(const int64_t *__restrict__
       if (keep) {
         const int e = base + before +
                       __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        s_tt[e] = skey[j];
+        const double t = skey[j];
+        int64_t wl, wh;
+        window_of(g, t, &wl, &wh);
+        s_tt[e] = t;
         s_i[e] = (friedel ? 2.0 : 1.0) * inten[id] * g.norm;
+        // window relative to the segment, clamped to [-1, npts]
+        s_gl[e] = (int32_t)max((int64_t)-1, min((int64_t)npts, wl - G0));
+        s_gh[e] = (int32_t)max((int64_t)-1, min((int64_t)npts, wh - G0));
       }
       base += total;
       __syncthreads();
     }
     const int nt = base;
-    if (gi <= G1) {
-      // first staged reflection with 2theta >= x - half - guard
-      int e = 0, hi = nt;
-      const double lo = x - g.half - guard;
-      while (e < hi) {
-        const int m = (e + hi) >> 1;
-        if (s_tt[m] < lo) e = m + 1;
-        else hi = m;
-      }
-      for (; e < nt; ++e) {
-        const double t = s_tt[e];
-        const double d = x - t;
-        if (t > x + g.half + guard) break;
-        if (fabs(d) > g.half) continue;
+    // per point: first entry with gh >= p and last entry with gl <= p (empty: last < first)
+    for (int p = threadIdx.x; p < npts; p += 256) {
+      s_first[p] = (int16_t)nt;
+      s_last[p] = (int16_t)-1;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nt; e += 256) {
+      // points p in (gh_{e-1}, gh_e] have first = e; points in [gl_e, gl_{e+1}) have last = e
+      const int ghp = e ? s_gh[e - 1] : -1, gh = s_gh[e];
+      for (int p = max(ghp + 1, 0); p <= min(gh, npts - 1); ++p) s_first[p] = (int16_t)e;
+      const int gl = s_gl[e], gln = e + 1 < nt ? s_gl[e + 1] : npts;
+      for (int p = max(gl, 0); p < min(gln, npts); ++p) s_last[p] = (int16_t)e;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPtsPerThread; ++q) {
+      const int p = q * 256 + threadIdx.x;
+      if (p >= npts) continue;
+      const int e0 = s_first[p], e1 = s_last[p];
+      double a = 0.0;
+      for (int e = e0; e <= e1; ++e) {
+        const double d = x[q] - s_tt[e];
         if constexpr (MIXED) {
           const float df = (float)d;
-          acc += s_i[e] * (double)__builtin_amdgcn_exp2f(-(df * df) * c2);
+          a += s_i[e] * (double)__builtin_amdgcn_exp2f(-(df * df) * c2);
         } else {
-          acc += s_i[e] * exp(-(d * d) * g.inv2s2);
+          a += s_i[e] * exp(-(d * d) * g.inv2s2);
         }
       }
+      acc[q] += a;
     }
     __syncthreads();
   }
-  if (gi <= G1) y[c * g.n + gi] = acc;
+#pragma unroll
+  for (int q = 0; q < kPtsPerThread; ++q) {
+    const int64_t gi = G0 + q * 256 + threadIdx.x;
+    if (gi <= G1) y[c * g.n + gi] = acc[q];
+  }
 }
 
-// Adjoint on the grid side: a block per chunk of a crystal's evaluated
-// reflections, the crystal's dL/dy row staged in LDS; per reflection
+// Adjoint on the grid side: kAdjSplit blocks per chunk of a crystal's
+// evaluated reflections, the crystal's dL/dy row staged in LDS; per reflection
 //   w1 = sum_g dy_g K,  w2 = sum_g dy_g K d / sigma^2  (d = x_g - 2theta)
-// over the same window, K by the same recurrence.
-template <bool LDS_ROW>
+// over the same window as the forward, K by the Gaussian recurrence (in
+// single precision under MIXED, where 81-step products stay within ~1e-6).
+template <bool LDS_ROW, bool MIXED>
 __global__ __launch_bounds__(256) void k_broaden_adj(const int32_t *__restrict__ hchunk_crystal,
                                                      const CrystalPlan *__restrict__ plan, bool friedel,
                                                      const int64_t *__restrict__ refl_offset,
                                                      const double *__restrict__ tt, const double *__restrict__ dy,
                                                      GridArgs g, double *__restrict__ w1, double *__restrict__ w2) {
 #pragma clang fp contract(off)
+  using real = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ double s_dy[];  // the crystal's dL/dy row when LDS_ROW
-  const int32_t c = hchunk_crystal[blockIdx.x];
+  const int hc = blockIdx.x / kAdjSplit, sub = blockIdx.x % kAdjSplit;
+  const int32_t c = hchunk_crystal[hc];
   const CrystalPlan &P = plan[c];
   const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
   const int64_t first = friedel ? r0 + (r1 - r0) / 2 : r0;
   const int64_t count = friedel ? (r1 - r0) / 2 : r1 - r0;
-  const int64_t e0 = (int64_t)(blockIdx.x - P.hchunk_begin) * kHalfChunk;
+  const int64_t e0 = (int64_t)(hc - P.hchunk_begin) * kHalfChunk + sub * (kHalfChunk / kAdjSplit);
   if (e0 >= count) return;
-  const int64_t e1 = min(e0 + (int64_t)kHalfChunk, count);
+  const int64_t e1 = min(e0 + (int64_t)(kHalfChunk / kAdjSplit), count);
   const double *dyc = dy + (int64_t)c * g.n;
   if (LDS_ROW) {
-    for (int64_t i = threadIdx.x; i < g.n; i += 256) s_dy[i] = dyc[i];
+    for (int i = threadIdx.x; i < (int)g.n; i += 256) s_dy[i] = dyc[i];
     __syncthreads();
   }
   const double inv_s2 = 1.0 / (g.sigma * g.sigma);
-  const double rho = exp(-(g.dt * g.dt) * inv_s2);
+  const real rho = (real)exp(-(g.dt * g.dt) * inv_s2);
+  const real dtr = (real)g.dt;
   for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
     const int64_t i = first + e;
     const double t = tt[i];
-    int64_t wl, wh;
-    window_of(g, t, &wl, &wh);
-    double a1 = 0.0, a2 = 0.0;
+    int64_t wl64, wh64;
+    window_of(g, t, &wl64, &wh64);
+    const int wl = (int)wl64, wh = (int)wh64;
+    real a1 = 0, a2 = 0;
     if (wl <= wh) {
-      GaussWalk w;
-      w.start(g, g.t0 + (double)wl * g.dt - t, 1.0);
-      for (int64_t gi = wl; gi <= wh; ++gi) {
-        const double d = g.t0 + (double)gi * g.dt - t;
-        const double kv = (LDS_ROW ? s_dy[gi] : dyc[gi]) * w.K;
+      const double d0 = g.t0 + (double)wl * g.dt - t;
+      real K = (real)(g.norm * exp(-(d0 * d0) * g.inv2s2));
+      real r = (real)exp(-(2.0 * d0 * g.dt + g.dt * g.dt) * g.inv2s2);
+      real d = (real)d0;
+      for (int gi = wl; gi <= wh; ++gi) {
+        const real kv = (real)(LDS_ROW ? s_dy[gi] : dyc[gi]) * K;
         a1 += kv;
-        a2 += kv * d * inv_s2;
-        w.step(rho);
+        a2 += kv * d;
+        K *= r;
+        r *= rho;
+        d += dtr;
       }
     }
-    w1[i] = a1;
-    w2[i] = a2;
+    w1[i] = (double)a1;
+    w2[i] = (double)a2 * inv_s2;
   }
 }
 
@@ -290,17 +338,28 @@ void launch_broaden_fwd(bool mixed, int64_t n_c, const int64_t *refl_offset, con
                        inten, g, friedel, y);
 }
 
-void launch_broaden_adj(const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan, bool friedel,
-                        const int64_t *refl_offset, const double *tt, const double *dy, double t0, double dt,
-                        int64_t n, double sigma, double window, double *w1, double *w2, hipStream_t s) {
+void launch_broaden_adj(bool mixed, const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan,
+                        bool friedel, const int64_t *refl_offset, const double *tt, const double *dy, double t0,
+                        double dt, int64_t n, double sigma, double window, double *w1, double *w2, hipStream_t s) {
   if (n_hchunks <= 0) return;
   const GridArgs g = make_grid(t0, dt, n, sigma, window);
-  if (n <= kAdjDyLds)
-    hipLaunchKernelGGL(k_broaden_adj<true>, dim3((unsigned)n_hchunks), dim3(256), (size_t)n * sizeof(double), s,
-                       hchunk_crystal, plan, friedel, refl_offset, tt, dy, g, w1, w2);
-  else
-    hipLaunchKernelGGL(k_broaden_adj<false>, dim3((unsigned)n_hchunks), dim3(256), 0, s, hchunk_crystal, plan,
-                       friedel, refl_offset, tt, dy, g, w1, w2);
+  const dim3 grid((unsigned)(n_hchunks * kAdjSplit)), block(256);
+  const size_t lds = (size_t)n * sizeof(double);
+  if (n <= kAdjDyLds) {
+    if (mixed)
+      hipLaunchKernelGGL((k_broaden_adj<true, true>), grid, block, lds, s, hchunk_crystal, plan, friedel, refl_offset,
+                         tt, dy, g, w1, w2);
+    else
+      hipLaunchKernelGGL((k_broaden_adj<true, false>), grid, block, lds, s, hchunk_crystal, plan, friedel,
+                         refl_offset, tt, dy, g, w1, w2);
+  } else {
+    if (mixed)
+      hipLaunchKernelGGL((k_broaden_adj<false, true>), grid, block, 0, s, hchunk_crystal, plan, friedel, refl_offset,
+                         tt, dy, g, w1, w2);
+    else
+      hipLaunchKernelGGL((k_broaden_adj<false, false>), grid, block, 0, s, hchunk_crystal, plan, friedel,
+                         refl_offset, tt, dy, g, w1, w2);
+  }
 }
 
 void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s) {

@@ -31,14 +31,16 @@ struct Hkl {
 };
 
 __device__ __forceinline__ Hkl decode(const CrystalPlan &P, int64_t p) {
-  // linear index of the full box (h outermost); the origin is the centre
-  const int64_t nl = 2 * P.L + 1, nk = 2 * P.K + 1;
-  const int64_t i = P.half_box + 1 + p;
+  // linear index of the full box (h outermost); the origin is the centre.
+  // The plan keeps boxes below 2^31 points, so 32-bit division suffices.
+  const uint32_t nl = 2 * P.L + 1, nk = 2 * P.K + 1;
+  const uint32_t i = (uint32_t)(P.half_box + 1 + p);
   Hkl r;
-  r.l = (int)(i % nl) - P.L;
-  const int64_t t = i / nl;
-  r.k = (int)(t % nk) - P.K;
-  r.h = (int)(t / nk) - P.H;
+  const uint32_t t = i / nl;
+  r.l = (int)(i - t * nl) - P.L;
+  const uint32_t u = t / nk;
+  r.k = (int)(t - u * nk) - P.K;
+  r.h = (int)u - P.H;
   return r;
 }
 

@@ -94,7 +94,7 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(const int32_t *__restri
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     int64_t i = t0 + u;
-    if (i < n) out[i] = ex;
+    if (i <= lim && i < n) out[i] = ex;
     ex += v[u];
   }
   if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = part[nb];

@@ -137,6 +137,48 @@ __global__ __launch_bounds__(64) void k_atom_prep(const CrystalPlan *__restrict_
 
 // ---- structure factors -----------------------------------------------------
 
+// Sum over the 64 lanes of a wavefront with DPP row shifts and row
+// broadcasts (VALU only); the total lands in lane 63.  Lanes a shift reads
+// from outside their row contribute 0 (bound_ctrl); rows a broadcast does not
+// write keep their value (old = 0 is added).
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ int dpp_i32(int x) {
+  return __builtin_amdgcn_update_dpp(0, x, CTRL, ROW_MASK, 0xf, BOUND);
+}
+
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ float dpp_f32(float x) {
+  return __int_as_float(dpp_i32<CTRL, ROW_MASK, BOUND>(__float_as_int(x)));
+}
+
+template <int CTRL, int ROW_MASK, bool BOUND>
+__device__ __forceinline__ double dpp_f64(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = dpp_i32<CTRL, ROW_MASK, BOUND>((int)(b & 0xffffffffll));
+  const int hi = dpp_i32<CTRL, ROW_MASK, BOUND>((int)(b >> 32));
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+__device__ __forceinline__ float wave_sum_to_63(float v) {
+  v += dpp_f32<0x111, 0xf, true>(v);   // row_shr:1
+  v += dpp_f32<0x112, 0xf, true>(v);   // row_shr:2
+  v += dpp_f32<0x114, 0xf, true>(v);   // row_shr:4
+  v += dpp_f32<0x118, 0xf, true>(v);   // row_shr:8: lane 15 of each row holds the row sum
+  v += dpp_f32<0x142, 0xa, false>(v);  // row_bcast:15 into rows 1 and 3
+  v += dpp_f32<0x143, 0xc, false>(v);  // row_bcast:31 into rows 2 and 3
+  return v;
+}
+
+__device__ __forceinline__ double wave_sum_to_63(double v) {
+  v += dpp_f64<0x111, 0xf, true>(v);
+  v += dpp_f64<0x112, 0xf, true>(v);
+  v += dpp_f64<0x114, 0xf, true>(v);
+  v += dpp_f64<0x118, 0xf, true>(v);
+  v += dpp_f64<0x142, 0xa, false>(v);
+  v += dpp_f64<0x143, 0xc, false>(v);
+  return v;
+}
+
 // (s, e) += x with the rounding error of the addition carried in e (two-sum).
 __device__ __forceinline__ void two_sum_acc(float &s, float &e, float x) {
 #pragma clang fp contract(off)
@@ -555,14 +597,11 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
           sz = fmaf(lf[u], pP, sz);
           sb = fmaf(s2[u], pQ, sb);
         }
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-          sx += __shfl_xor(sx, d, 64);
-          sy += __shfl_xor(sy, d, 64);
-          sz += __shfl_xor(sz, d, 64);
-          sb += __shfl_xor(sb, d, 64);
-        }
-        if (lane == 0) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
+        sx = wave_sum_to_63(sx);
+        sy = wave_sum_to_63(sy);
+        sz = wave_sum_to_63(sz);
+        sb = wave_sum_to_63(sb);
+        if (lane == 63) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
       }
     } else {
       double f[R], fA[R], fB[R];
@@ -589,14 +628,11 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
           sz = fma(l[u], pP, sz);
           sb = fma(s2d[u], pQ, sb);
         }
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) {
-          sx += __shfl_xor(sx, d, 64);
-          sy += __shfl_xor(sy, d, 64);
-          sz += __shfl_xor(sz, d, 64);
-          sb += __shfl_xor(sb, d, 64);
-        }
-        if (lane == 0) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
+        sx = wave_sum_to_63(sx);
+        sy = wave_sum_to_63(sy);
+        sz = wave_sum_to_63(sz);
+        sb = wave_sum_to_63(sb);
+        if (lane == 63) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
       }
     }
   }

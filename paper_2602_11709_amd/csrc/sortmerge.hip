@@ -3,8 +3,9 @@
 // tolerances; grouping of reflections into peaks).
 //
 // Sort: crystals of up to 4096 reflections are sorted by one block each in
-// LDS; larger crystals use the same bucket sort through global memory.  The
-// buckets are exactly monotone.  The bucket of a
+// LDS; larger crystals use the same bucket sort through global memory, by
+// kernels that walk a device-built list of those crystals.  The buckets are
+// exactly monotone.  The bucket of a
 // reflection is floor((2theta - tmin) * bins_per_degree), clamped; a
 // subtraction, a product with a positive constant and floor are each monotone
 // in IEEE arithmetic, so bucket order never contradicts key order and equal
@@ -29,7 +30,8 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kPer = kSortChunk / kThreads;  // 4
-constexpr int kSmallSort = 4096;              // reflections sorted by one block in LDS
+constexpr int kSmallSort = 4096;              // reflections sorted by one 256-thread block in LDS
+constexpr int kMidSort = 12288;               // reflections sorted by one 1024-thread block in LDS
 static_assert(kSortChunk / kBinDiv == kThreads, "one bucket per thread of a sort chunk");
 
 __device__ __forceinline__ int bin_of(const CrystalPlan &P, double tt) {
@@ -61,29 +63,51 @@ __device__ __forceinline__ ChunkRange chunk_range(const CrystalPlan *__restrict_
   return c;
 }
 
-// Crystals with at most kSmallSort reflections: one block sorts the whole
-// crystal in LDS with the same monotone buckets as the large-crystal path
-// (R/2 of them): count with LDS atomics, scan, scatter with LDS atomics, then
-// an insertion sort of each bucket on (2theta bits, position).  The input is
-// in lexicographic (h, k, l) order, so ordering ties by position orders them
-// by (h, k, l); positive doubles order like their bit patterns.
-__global__ __launch_bounds__(kThreads) void k_sort_small(const CrystalPlan *__restrict__ plan,
-                                                         const int64_t *__restrict__ refl_offset,
-                                                         const double *__restrict__ tt, double *__restrict__ skey,
-                                                         int32_t *__restrict__ sidx) {
-  __shared__ uint64_t key[kSmallSort];
-  __shared__ uint32_t pos[kSmallSort];
-  __shared__ int32_t cnt[kSmallSort / 2];
-  __shared__ int32_t wsum[kThreads / 64];
+// Crystals of at most CAP reflections: one block of T threads sorts the
+// whole crystal in LDS with the same kind of monotone buckets as the global
+// path (R/2 of them): count with LDS atomics, scan, scatter with LDS atomics,
+// then an insertion sort of each bucket on (2theta bits, position).  The input
+// is in lexicographic (h, k, l) order, so ordering ties by position orders them
+// by (h, k, l); positive doubles order like their bit patterns.  Two sizes
+// are launched: CAP 4096 (256 threads, ~48 KB of LDS) takes the crystals up to
+// 4096 reflections, CAP 12288 (1024 threads, 144 KB of LDS, which gfx950
+// provides per workgroup) the ones up to 12288.  The larger one zeroes the
+// buckets of still larger crystals and registers their chunks for the
+// bucket kernels.
+template <int CAP, int T, bool LARGE>
+__global__ __launch_bounds__(T) void k_sort_lds(const CrystalPlan *__restrict__ plan,
+                                                const int64_t *__restrict__ refl_offset,
+                                                const double *__restrict__ tt, double *__restrict__ skey,
+                                                int32_t *__restrict__ sidx, int32_t *__restrict__ bin_count,
+                                                int32_t *__restrict__ big_list, int2 *__restrict__ big_chunks,
+                                                int32_t *__restrict__ counters) {
+  __shared__ uint64_t key[CAP];
+  __shared__ uint16_t pos[CAP];
+  __shared__ int32_t cnt[CAP / 2];
+  __shared__ int32_t wsum[T / 64];
   const CrystalPlan &P = plan[blockIdx.x];
   const int64_t r0 = refl_offset[blockIdx.x], r1 = refl_offset[blockIdx.x + 1];
-  if (r1 - r0 > kSmallSort || r1 <= r0) return;
+  if (LARGE && r1 - r0 > CAP) {
+    // too large for LDS: zero the crystal's buckets and register its chunks
+    // for the bucket kernels (their order in the list does not matter)
+    for (int64_t b = threadIdx.x; b < P.n_bins; b += T) bin_count[P.bin_begin + b] = 0;
+    const int nch = (int)((r1 - r0 + kSortChunk - 1) / kSortChunk);
+    if (threadIdx.x == 0) {
+      big_list[atomicAdd(&counters[0], 1)] = blockIdx.x;
+      wsum[0] = atomicAdd(&counters[1], nch);
+    }
+    __syncthreads();
+    const int base = wsum[0];
+    for (int k = threadIdx.x; k < nch; k += T) big_chunks[base + k] = make_int2((int)blockIdx.x, k);
+    return;
+  }
+  if (r1 - r0 > CAP || r1 - r0 <= (LARGE ? kSmallSort : 0)) return;
   const int R = (int)(r1 - r0);
   const int B = R / 2 > 1 ? R / 2 : 1;
   const double scale = (double)B / (P.tmax - P.tmin);
-  for (int b = threadIdx.x; b < B; b += kThreads) cnt[b] = 0;
+  for (int b = threadIdx.x; b < B; b += T) cnt[b] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < R; i += kThreads) {
+  for (int i = threadIdx.x; i < R; i += T) {
 #pragma clang fp contract(off)
     const double x = floor((tt[r0 + i] - P.tmin) * scale);
     const int b = x < 0.0 ? 0 : (x >= (double)(B - 1) ? B - 1 : (int)x);
@@ -92,7 +116,7 @@ __global__ __launch_bounds__(kThreads) void k_sort_small(const CrystalPlan *__re
   __syncthreads();
   // exclusive scan of the bucket counts: each thread owns a contiguous run
   {
-    constexpr int per = (kSmallSort / 2 + kThreads - 1) / kThreads;
+    constexpr int per = (CAP / 2 + T - 1) / T;
     const int b0 = threadIdx.x * per;
     int v[per], sum = 0;
 #pragma unroll
@@ -118,22 +142,22 @@ __global__ __launch_bounds__(kThreads) void k_sort_small(const CrystalPlan *__re
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < R; i += kThreads) {
+  for (int i = threadIdx.x; i < R; i += T) {
 #pragma clang fp contract(off)
     const double t = tt[r0 + i];
     const double x = floor((t - P.tmin) * scale);
     const int b = x < 0.0 ? 0 : (x >= (double)(B - 1) ? B - 1 : (int)x);
     const int slot = atomicAdd(&cnt[b], 1);
     key[slot] = (uint64_t)__double_as_longlong(t);
-    pos[slot] = (uint32_t)i;
+    pos[slot] = (uint16_t)i;
   }
   __syncthreads();
   // cnt[b] is now the end of bucket b, and its start is the end of bucket b - 1
-  for (int b = threadIdx.x; b < B; b += kThreads) {
+  for (int b = threadIdx.x; b < B; b += T) {
     const int s = b ? cnt[b - 1] : 0, e = cnt[b];
     for (int i = s + 1; i < e; ++i) {
       const uint64_t k = key[i];
-      const uint32_t p = pos[i];
+      const uint16_t p = pos[i];
       int j = i - 1;
       while (j >= s && (key[j] > k || (key[j] == k && pos[j] > p))) {
         key[j + 1] = key[j];
@@ -145,85 +169,135 @@ __global__ __launch_bounds__(kThreads) void k_sort_small(const CrystalPlan *__re
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < R; i += kThreads) {
+  for (int i = threadIdx.x; i < R; i += T) {
     skey[r0 + i] = __longlong_as_double((long long)key[i]);
     sidx[r0 + i] = (int32_t)(r0 + pos[i]);
   }
 }
 
+// Bucket path for the crystals registered by k_sort_lds: each kernel walks
+// the device-built list of their sort chunks with a grid-stride loop, so the
+// launch size does not depend on how many crystals are small.
 __global__ __launch_bounds__(kThreads) void k_bin_count(const CrystalPlan *__restrict__ plan,
-                                                        const int32_t *__restrict__ chunk_crystal,
+                                                        const int2 *__restrict__ big_chunks,
+                                                        const int32_t *__restrict__ counters,
                                                         const int64_t *__restrict__ refl_offset,
                                                         const double *__restrict__ tt, int32_t *__restrict__ count) {
-  const ChunkRange cr = chunk_range(plan, chunk_crystal, refl_offset);
-  if (cr.r1 - cr.r0 <= kSmallSort) return;  // sorted in LDS by k_sort_small
-  const CrystalPlan &P = plan[cr.cry];
-  for (int u = 0; u < kPer; ++u) {
-    const int64_t i = cr.base + u * kThreads + threadIdx.x;
-    if (i >= cr.r1) break;
-    atomicAdd(&count[P.bin_begin + bin_of(P, tt[i])], 1);
+  const int n = counters[1];
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int2 ck = big_chunks[i];
+    const CrystalPlan &P = plan[ck.x];
+    const int64_t r1 = refl_offset[ck.x + 1];
+    const int64_t base = refl_offset[ck.x] + (int64_t)ck.y * kSortChunk;
+    for (int u = 0; u < kPer; ++u) {
+      const int64_t j = base + u * kThreads + threadIdx.x;
+      if (j >= r1) break;
+      atomicAdd(&count[P.bin_begin + bin_of(P, tt[j])], 1);
+    }
+  }
+}
+
+// Exclusive scan of one registered crystal's bucket counts per block
+// (crystal-relative starts).
+__global__ __launch_bounds__(kThreads) void k_bin_scan(const CrystalPlan *__restrict__ plan,
+                                                       const int32_t *__restrict__ big_list,
+                                                       const int32_t *__restrict__ counters,
+                                                       const int32_t *__restrict__ count,
+                                                       int64_t *__restrict__ start) {
+  __shared__ int64_t wsum[kThreads / 64];
+  const int n = counters[0];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const CrystalPlan &P = plan[big_list[i]];
+    int64_t carry = 0;
+    for (int64_t b0 = 0; b0 < P.n_bins; b0 += kThreads) {
+      const int64_t b = b0 + threadIdx.x;
+      const int64_t v = b < P.n_bins ? count[P.bin_begin + b] : 0;
+      int64_t inc = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int64_t o = __shfl_up(inc, d, 64);
+        if (lane >= d) inc += o;
+      }
+      if (lane == 63) wsum[wid] = inc;
+      __syncthreads();
+      int64_t before = 0, total = 0;
+      for (int w = 0; w < kThreads / 64; ++w) {
+        before += w < wid ? wsum[w] : 0;
+        total += wsum[w];
+      }
+      if (b < P.n_bins) start[P.bin_begin + b] = carry + before + inc - v;
+      carry += total;
+      __syncthreads();
+    }
   }
 }
 
 __global__ __launch_bounds__(kThreads) void k_bin_scatter(const CrystalPlan *__restrict__ plan,
-                                                          const int32_t *__restrict__ chunk_crystal,
+                                                          const int2 *__restrict__ big_chunks,
+                                                          const int32_t *__restrict__ counters,
                                                           const int64_t *__restrict__ refl_offset,
                                                           const double *__restrict__ tt,
                                                           const int64_t *__restrict__ start,
                                                           int32_t *__restrict__ count, double *__restrict__ skey,
                                                           int32_t *__restrict__ sidx) {
-  const ChunkRange cr = chunk_range(plan, chunk_crystal, refl_offset);
-  if (cr.r1 - cr.r0 <= kSmallSort) return;
-  const CrystalPlan &P = plan[cr.cry];
-  for (int u = 0; u < kPer; ++u) {
-    const int64_t i = cr.base + u * kThreads + threadIdx.x;
-    if (i >= cr.r1) break;
-    const double t = tt[i];
-    const int64_t gb = P.bin_begin + bin_of(P, t);
-    // bucket ranges are relative to the crystal's first bucket: crystals
-    // sorted in LDS leave their buckets empty, so the global prefix is not
-    // the crystal's reflection offset
-    const int64_t slot = cr.r0 + (start[gb] - start[P.bin_begin]) + atomicSub(&count[gb], 1) - 1;
-    skey[slot] = t;
-    sidx[slot] = (int32_t)i;
+  const int n = counters[1];
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int2 ck = big_chunks[i];
+    const CrystalPlan &P = plan[ck.x];
+    const int64_t r0 = refl_offset[ck.x], r1 = refl_offset[ck.x + 1];
+    const int64_t base = r0 + (int64_t)ck.y * kSortChunk;
+    for (int u = 0; u < kPer; ++u) {
+      const int64_t j = base + u * kThreads + threadIdx.x;
+      if (j >= r1) break;
+      const double t = tt[j];
+      const int64_t gb = P.bin_begin + bin_of(P, t);
+      const int64_t slot = r0 + start[gb] + atomicSub(&count[gb], 1) - 1;
+      skey[slot] = t;
+      sidx[slot] = (int32_t)j;
+    }
   }
 }
 
-// One thread per bucket of a large crystal (blocks follow the sort chunks:
-// 256 buckets per chunk, and a crystal has at most 256 buckets per chunk):
-// insertion sort on (2theta, h, k, l).  Buckets hold a few reflections on
-// average (at most a few tens for high-symmetry cells).
+// One thread per bucket: insertion sort on (2theta, h, k, l).  Buckets hold a
+// few reflections on average (a few tens at most for high-symmetry cells).
 __global__ __launch_bounds__(kThreads) void k_bin_sort(const CrystalPlan *__restrict__ plan,
-                                                       const int32_t *__restrict__ chunk_crystal,
+                                                       const int2 *__restrict__ big_chunks,
+                                                       const int32_t *__restrict__ counters,
                                                        const int64_t *__restrict__ refl_offset,
                                                        const int64_t *__restrict__ start, double *__restrict__ skey,
                                                        int32_t *__restrict__ sidx, const int16_t *__restrict__ h,
                                                        const int16_t *__restrict__ k,
                                                        const int16_t *__restrict__ l) {
-  const int32_t cry = chunk_crystal[blockIdx.x];
-  const CrystalPlan &P = plan[cry];
-  const int64_t r0 = refl_offset[cry], r1 = refl_offset[cry + 1];
-  if (r1 - r0 <= kSmallSort) return;
-  const int64_t bl = (int64_t)(blockIdx.x - P.sort_chunk_begin) * kThreads + threadIdx.x;
-  if (bl >= P.n_bins) return;
-  const int64_t b = P.bin_begin + bl;
-  const int64_t s = r0 + (start[b] - start[P.bin_begin]), e = r0 + (start[b + 1] - start[P.bin_begin]);
-  for (int64_t i = s + 1; i < e; ++i) {
-    const double key = skey[i];
-    const int32_t id = sidx[i];
-    const int64_t hk = hkl_key(h, k, l, id);
-    int64_t j = i - 1;
-    while (j >= s) {
-      const double kj = skey[j];
-      const int32_t ij = sidx[j];
-      const bool gt = kj > key || (kj == key && hkl_key(h, k, l, ij) > hk);
-      if (!gt) break;
-      skey[j + 1] = kj;
-      sidx[j + 1] = ij;
-      --j;
+  const int n = counters[1];
+  for (int i = blockIdx.x; i < n; i += gridDim.x) {
+    const int2 ck = big_chunks[i];
+    const CrystalPlan &P = plan[ck.x];
+    const int64_t r0 = refl_offset[ck.x], r1 = refl_offset[ck.x + 1];
+    // the crystal's chunks follow its reflection count and its buckets its
+    // capacity (more of them): chunk ck.y takes every nch-th group of 256
+    const int64_t nch = (r1 - r0 + kSortChunk - 1) / kSortChunk;
+    for (int64_t bl = (int64_t)ck.y * kThreads + threadIdx.x; bl < P.n_bins; bl += nch * kThreads) {
+      const int64_t b = P.bin_begin + bl;
+      const int64_t s = r0 + start[b], e = bl + 1 < P.n_bins ? r0 + start[b + 1] : r1;
+      for (int64_t x = s + 1; x < e; ++x) {
+        const double key = skey[x];
+        const int32_t id = sidx[x];
+        const int64_t hk = hkl_key(h, k, l, id);
+        int64_t j = x - 1;
+        while (j >= s) {
+          const double kj = skey[j];
+          const int32_t ij = sidx[j];
+          const bool gt = kj > key || (kj == key && hkl_key(h, k, l, ij) > hk);
+          if (!gt) break;
+          skey[j + 1] = kj;
+          sidx[j + 1] = ij;
+          --j;
+        }
+        skey[j + 1] = key;
+        sidx[j + 1] = id;
+      }
     }
-    skey[j + 1] = key;
-    sidx[j + 1] = id;
   }
 }
 
@@ -351,20 +425,23 @@ __global__ void k_peak_offsets_compact(int64_t n_c, const int64_t *__restrict__ 
 }  // namespace
 
 void launch_sort(const SortArgs &a, hipStream_t s) {
-  if (a.n_c > 0)
-    hipLaunchKernelGGL(k_sort_small, dim3((unsigned)a.n_c), dim3(kThreads), 0, s, a.plan, a.refl_offset, a.tt,
-                       a.skey, a.sidx);
-  launch_fill_i32(a.bin_count, a.n_bins, 0, s);
-  if (a.n_chunks > 0)
-    hipLaunchKernelGGL(k_bin_count, dim3((unsigned)a.n_chunks), dim3(kThreads), 0, s, a.plan, a.chunk_crystal,
-                       a.refl_offset, a.tt, a.bin_count);
-  launch_scan_i32(a.bin_count, a.n_bins, nullptr, a.bin_start, a.scan_part, s);
-  if (a.n_chunks > 0)
-    hipLaunchKernelGGL(k_bin_scatter, dim3((unsigned)a.n_chunks), dim3(kThreads), 0, s, a.plan, a.chunk_crystal,
-                       a.refl_offset, a.tt, a.bin_start, a.bin_count, a.skey, a.sidx);
-  if (a.n_chunks > 0)
-    hipLaunchKernelGGL(k_bin_sort, dim3((unsigned)a.n_chunks), dim3(kThreads), 0, s, a.plan, a.chunk_crystal,
-                       a.refl_offset, a.bin_start, a.skey, a.sidx, a.h, a.k, a.l);
+  if (a.n_c <= 0) return;
+  launch_fill_i32(a.counters, 2, 0, s);
+  hipLaunchKernelGGL((k_sort_lds<kSmallSort, 256, false>), dim3((unsigned)a.n_c), dim3(256), 0, s, a.plan,
+                     a.refl_offset, a.tt, a.skey, a.sidx, a.bin_count, a.big_list, a.big_chunks, a.counters);
+  hipLaunchKernelGGL((k_sort_lds<kMidSort, 1024, true>), dim3((unsigned)a.n_c), dim3(1024), 0, s, a.plan,
+                     a.refl_offset, a.tt, a.skey, a.sidx, a.bin_count, a.big_list, a.big_chunks, a.counters);
+  if (a.n_chunks <= 0) return;
+  const unsigned g = (unsigned)(a.n_chunks < 2048 ? a.n_chunks : 2048);
+  const unsigned gc = (unsigned)(a.n_c < 1024 ? a.n_c : 1024);
+  hipLaunchKernelGGL(k_bin_count, dim3(g), dim3(kThreads), 0, s, a.plan, a.big_chunks, a.counters, a.refl_offset, a.tt,
+                     a.bin_count);
+  hipLaunchKernelGGL(k_bin_scan, dim3(gc), dim3(kThreads), 0, s, a.plan, a.big_list, a.counters, a.bin_count,
+                     a.bin_start);
+  hipLaunchKernelGGL(k_bin_scatter, dim3(g), dim3(kThreads), 0, s, a.plan, a.big_chunks, a.counters, a.refl_offset,
+                     a.tt, a.bin_start, a.bin_count, a.skey, a.sidx);
+  hipLaunchKernelGGL(k_bin_sort, dim3(g), dim3(kThreads), 0, s, a.plan, a.big_chunks, a.counters, a.refl_offset,
+                     a.bin_start, a.skey, a.sidx, a.h, a.k, a.l);
 }
 
 void launch_merge(const MergeArgs &a, hipStream_t s) {

@@ -19,7 +19,7 @@ constexpr int kBinDiv = 4;        // merge-sort bins per crystal = capacity / kB
 constexpr int kHalfChunk = 2048;  // reflections per adjoint chunk
 constexpr int kScanBlock = 2048;  // elements per scan block (256 threads x 8)
 constexpr int kAtomBlock = 256;   // atoms per adjoint block
-constexpr int kSfRpt = 2;         // reflections per lane in the structure-factor kernel
+constexpr int kSfRpt = 2;         // reflections per lane in the structure-factor kernels
 constexpr int kSfTile = 64 * kSfRpt;
 constexpr int kFusedMaxAtoms = 512;  // crystals up to this size take the fused atom-gradient path
 
@@ -75,7 +75,7 @@ struct WsLayout {
   int64_t plan, enum_chunk_crystal, sf_items, sort_chunk_crystal, hchunk_crystal, bw_items, ab_items;
   int64_t enum_count, enum_prefix;
   int64_t atoms, atom_orig, runs, run_count, err_flag;
-  int64_t bin_count, bin_start;
+  int64_t bin_count, bin_start, big_list, big_chunks, sort_counters;
   int64_t skey, sidx;
   int64_t flags, pscan;
   int64_t cmax, n_peaks, tmp_tt, tmp_i, tmp_y, tmp_mult, tmp_first, keep, kscan, raw_peak_offset;
@@ -88,8 +88,9 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 
 // Exclusive scan of int32 in[0, n) into int64 out[0, n] (out[n] = total).
-// If n_dev is non-null, elements at index >= *n_dev count as zero and
-// out[*n_dev .. n] all hold the total.  ``part`` needs scan_part_elems(n) int64.
+// If n_dev is non-null, only the first m = min(n, *n_dev) elements are
+// scanned: out[0..m] is written (out[m] = total) and out[n] = total; the
+// entries between are left as they were.  ``part`` needs scan_part_elems(n).
 int64_t scan_part_elems(int64_t n);
 void launch_scan_i32(const int32_t *in, int64_t n, const int64_t *n_dev, int64_t *out, int64_t *part,
                      hipStream_t s);
@@ -129,6 +130,9 @@ struct SortArgs {
   double *skey;
   int32_t *sidx;
   int64_t *scan_part;
+  int32_t *big_list;   // [n_c] crystals sorted by the bucket path
+  int2 *big_chunks;    // [n_chunks] their sort chunks
+  int32_t *counters;   // [2] list lengths
 };
 void launch_sort(const SortArgs &a, hipStream_t s);
 
@@ -159,9 +163,9 @@ void launch_merge(const MergeArgs &a, hipStream_t s);
 void launch_broaden_fwd(bool mixed, int64_t n_c, const int64_t *refl_offset, const double *skey,
                         const int32_t *sidx, const double *inten, bool friedel, double t0, double dt, int64_t n,
                         double sigma, double window, double *y, hipStream_t s);
-void launch_broaden_adj(const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan, bool friedel,
-                        const int64_t *refl_offset, const double *tt, const double *dy, double t0, double dt,
-                        int64_t n, double sigma, double window, double *w1, double *w2, hipStream_t s);
+void launch_broaden_adj(bool mixed, const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan,
+                        bool friedel, const int64_t *refl_offset, const double *tt, const double *dy, double t0,
+                        double dt, int64_t n, double sigma, double window, double *w1, double *w2, hipStream_t s);
 void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s);
 void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
