@@ -76,7 +76,8 @@ typedef struct {
                                      of their crystal (0 keeps every peak) */
     int32_t friedel;              /* 1: evaluate one reflection of each (h, -h) pair and copy
                                      the conjugate to its mate; 0: evaluate every reflection */
-    int32_t reserved;
+    int32_t grid_capacity;        /* largest n_points a broadened-pattern call on this batch
+                                     will use; 0 selects 16384.  Sizes the workspace. */
     const double *frac;           /* DEVICE [N*3]: fractional x, y, z per atom */
     const int32_t *species;       /* DEVICE [N]: row of sf_coeff, 0 <= species < n_species */
     const double *occ;            /* DEVICE [N]: occupancy, >= 0 */
@@ -169,7 +170,8 @@ int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, 
 /* Gaussian-broadened pattern y [n_crystals * n_points] (row per crystal) of
  * the reflections in ``r`` with intensities I; every reflection contributes
  * on its own (no merge).  Enumerate over the grid range widened by the
- * window on both sides so that no reflection reaching the grid is missed. */
+ * window on both sides so that no reflection reaching the grid is missed.
+ * n_points must not exceed the batch's grid_capacity. */
 int xrd_pattern_forward(xrd_batch *b, void *ws, const xrd_refl *r, const double *I,
                         const xrd_grid *g, double *y);
 

@@ -75,12 +75,14 @@ class XrdBatch:
     construction; atom arrays are copied to the device once and kept alive
     here.  All work goes to the stream that is current at construction.
     ``frac``/``bfac`` may be given as device tensors (float64) to override
-    the batch's arrays (the differentiable path does this)."""
+    the batch's arrays (the differentiable path does this).
+    ``grid_capacity`` bounds the grid of broadened-pattern calls (0: 16384
+    points)."""
 
     def __init__(self, batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
                  rel_threshold: float = 0.0, device="cuda", frac: Optional[torch.Tensor] = None,
                  bfac: Optional[torch.Tensor] = None, lattice: Optional[np.ndarray] = None,
-                 two_theta_range: Optional[tuple] = None):
+                 two_theta_range: Optional[tuple] = None, grid_capacity: int = 0):
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         self.device = torch.device(device)
@@ -117,6 +119,7 @@ class XrdBatch:
         d.merge_tol = batch.merge_tol
         d.rel_threshold = rel_threshold
         d.friedel = 1 if self.friedel else 0
+        d.grid_capacity = int(grid_capacity)
         d.frac = _p(self.frac) if batch.n_atoms else None
         d.species = _p(self.species) if batch.n_atoms else None
         d.occ = _p(self.occ) if batch.n_atoms else None
@@ -134,8 +137,12 @@ class XrdBatch:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h:
-            capi.xrd_batch_destroy(h)
+        destroy = getattr(capi, "xrd_batch_destroy", None)
+        if h and callable(destroy):  # the module may already be torn down at interpreter exit
+            try:
+                destroy(h)
+            except Exception:
+                pass
             self.handle = None
 
     @property
@@ -271,7 +278,8 @@ class _PatternFn(torch.autograd.Function):
         lat = lattice.detach().to("cpu", torch.float64).numpy()
         xb = XrdBatch(spec["batch"], precision=spec["precision"], friedel=spec["friedel"], device=frac.device,
                       frac=frac.detach().to(torch.float64).contiguous(),
-                      bfac=bfac.detach().to(torch.float64).contiguous(), lattice=lat)
+                      bfac=bfac.detach().to(torch.float64).contiguous(), lattice=lat,
+                      grid_capacity=spec["grid"].n_points)
         refl = xb.enumerate()
         _, _, I = xb.structure_factors(refl)
         y = xb.pattern_forward(refl, I, spec["grid"])

@@ -28,10 +28,14 @@ struct xrd_batch {
   std::vector<int64_t> atom_offset;
   std::vector<CrystalPlan> plan;
   std::vector<int32_t> enum_chunk_crystal, sort_chunk_crystal, hchunk_crystal;
+  std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
   std::vector<SfItem> sf_items;
   std::vector<BwItem> bw_items;
   std::vector<AbItem> ab_items;
   int64_t n_atoms = 0, refl_cap = 0, half_cap = 0, n_bins = 0, run_cap = 0, part_rows = 0, partf_rows = 0;
+  int64_t n_mid = 0;      // crystals whose reflection capacity exceeds kSmallSort
+  int64_t grid_cap = 0;   // largest grid of a broadened-pattern call
+  int64_t span_cap = 0;   // span-table entries per crystal: ceil(grid_cap / kSpanPts)
   int runs_cap_max = 1, bw_tile = 64;
   WsLayout ws{};
   void *last_ws = nullptr;
@@ -132,6 +136,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   if (!(d->merge_tol > 0.0) || !std::isfinite(d->merge_tol)) return fail(XRD_ERR_INVALID_ARG, "merge_tol must be > 0");
   if (!(d->rel_threshold >= 0.0) || !std::isfinite(d->rel_threshold))
     return fail(XRD_ERR_INVALID_ARG, "rel_threshold must be >= 0");
+  if (d->grid_capacity < 0) return fail(XRD_ERR_INVALID_ARG, "grid_capacity < 0");
   if (nc > 0 && (!d->lattice || !d->atom_offset || !d->two_theta_min || !d->two_theta_max))
     return fail(XRD_ERR_INVALID_ARG, "host arrays must be non-NULL");
   if (!d->sf_coeff) return fail(XRD_ERR_INVALID_ARG, "sf_coeff is NULL");
@@ -198,6 +203,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     }
     P.half_box = (box - 1) / 2;
     refl += 2 * P.half_box;
+    if (2 * P.half_box > kSmallSort) ++b->n_mid;
     if (refl >= ((int64_t)1 << 31) - 1) {
       delete b;
       return fail(XRD_ERR_CAPACITY, "reflection capacity exceeds 2^31; split the batch");
@@ -235,6 +241,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   }
   b->refl_cap = refl;
   b->half_cap = refl / 2;
+  b->grid_cap = d->grid_capacity > 0 ? d->grid_capacity : 16384;
+  b->span_cap = ceil_div(b->grid_cap, kSpanPts);
   b->n_bins = bins;
   b->run_cap = runs;
   b->part_rows = parts;
@@ -259,6 +267,11 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     for (int32_t i = 0; i < P.sort_chunks; ++i) b->sort_chunk_crystal[P.sort_chunk_begin + i] = (int32_t)c;
     for (int32_t i = 0; i < P.n_hchunks; ++i) b->hchunk_crystal[P.hchunk_begin + i] = (int32_t)c;
   }
+  // gather order: crystals by descending capacity (their broadening cost)
+  b->crystal_order.resize(nc);
+  for (int64_t c = 0; c < nc; ++c) b->crystal_order[c] = (int32_t)c;
+  std::stable_sort(b->crystal_order.begin(), b->crystal_order.end(),
+                   [&](int32_t x, int32_t y) { return b->plan[x].half_box > b->plan[y].half_box; });
   // structure-factor items: crystals in descending atom count (the cost of
   // one item), so the heaviest work is dispatched first
   std::vector<int64_t> order(nc);
@@ -292,12 +305,13 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     o = align256(o + std::max<int64_t>(bytes, 8));
     return r;
   };
-  const int64_t rc = b->refl_cap, pc = b->refl_cap;
+  const int64_t rc = b->refl_cap;
   L.plan = take((int64_t)sizeof(CrystalPlan) * nc);
   L.enum_chunk_crystal = take(4 * ec);
   L.sf_items = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items.size());
   L.sort_chunk_crystal = take(4 * sc);
   L.hchunk_crystal = take(4 * hc);
+  L.crystal_order = take(4 * nc);
   L.bw_items = take((int64_t)sizeof(BwItem) * (int64_t)b->bw_items.size());
   L.ab_items = take((int64_t)sizeof(AbItem) * (int64_t)b->ab_items.size());
   L.enum_count = take(4 * ec);
@@ -309,24 +323,22 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.err_flag = take(4);
   L.bin_count = take(4 * bins);
   L.bin_start = take(8 * (bins + 1));
-  L.big_list = take(4 * nc);
-  L.big_chunks = take(8 * sc);
-  L.sort_counters = take(8);
   L.skey = take(8 * rc);
   L.sidx = take(4 * rc);
+  // entries (evaluated reflections in 2theta order): their own arrays under
+  // Friedel pairing, the full sorted list otherwise
+  L.ent_key = friedel ? take(8 * b->half_cap) : L.skey;
+  L.ent_idx = friedel ? take(4 * b->half_cap) : L.sidx;
+  L.ent_w = take(8 * (friedel ? b->half_cap : rc));
+  L.span_first = take(4 * nc * b->span_cap);
+  L.span_last = take(4 * nc * b->span_cap);
   L.flags = take(4 * rc);
-  L.pscan = take(8 * (rc + 1));
   L.cmax = take(8 * nc);
-  L.n_peaks = take(8);
-  const bool thr = d->rel_threshold > 0.0;
-  L.tmp_tt = thr ? take(8 * pc) : 0;
-  L.tmp_i = thr ? take(8 * pc) : 0;
-  L.tmp_y = thr ? take(8 * pc) : 0;
-  L.tmp_mult = thr ? take(4 * pc) : 0;
-  L.tmp_first = thr ? take(8 * pc) : 0;
-  L.keep = thr ? take(4 * pc) : 0;
-  L.kscan = thr ? take(8 * (pc + 1)) : 0;
-  L.raw_peak_offset = thr ? take(8 * (nc + 1)) : 0;
+  L.pk_count = take(4 * nc);
+  L.tmp_tt = take(8 * rc);
+  L.tmp_i = take(8 * rc);
+  L.tmp_mult = take(4 * rc);
+  L.tmp_first = take(8 * rc);
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(ec, bins), rc);
   L.scan_part = take(8 * scan_part_elems(scan_n));
   L.bw_w1 = take(8 * rc);
@@ -369,6 +381,7 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   if (e == hipSuccess) e = up(L.sf_items, b->sf_items.data(), sizeof(SfItem) * b->sf_items.size());
   if (e == hipSuccess) e = up(L.sort_chunk_crystal, b->sort_chunk_crystal.data(), 4 * b->sort_chunk_crystal.size());
   if (e == hipSuccess) e = up(L.hchunk_crystal, b->hchunk_crystal.data(), 4 * b->hchunk_crystal.size());
+  if (e == hipSuccess) e = up(L.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
   if (e == hipSuccess) e = up(L.bw_items, b->bw_items.data(), sizeof(BwItem) * b->bw_items.size());
   if (e == hipSuccess) e = up(L.ab_items, b->ab_items.data(), sizeof(AbItem) * b->ab_items.size());
   if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("upload: ") + hipGetErrorString(e));
@@ -450,9 +463,11 @@ static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r) {
   a.skey = at<double>(ws, L.skey);
   a.sidx = at<int32_t>(ws, L.sidx);
   a.scan_part = at<int64_t>(ws, L.scan_part);
-  a.big_list = at<int32_t>(ws, L.big_list);
-  a.big_chunks = at<int2>(ws, L.big_chunks);
-  a.counters = at<int32_t>(ws, L.sort_counters);
+  a.order = at<int32_t>(ws, L.crystal_order);
+  a.n_mid = b->n_mid;
+  a.friedel = b->desc.friedel != 0 ? 1 : 0;
+  a.ent_key = at<double>(ws, L.ent_key);
+  a.ent_idx = at<int32_t>(ws, L.ent_idx);
   return a;
 }
 
@@ -467,23 +482,16 @@ int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, 
   MergeArgs a;
   a.sort = sort_args(b, ws, r);
   a.n_c = b->desc.n_crystals;
-  a.refl_cap = b->refl_cap;
   a.tol = b->desc.merge_tol;
   a.thr = b->desc.rel_threshold;
   a.inten = I;
   a.flags = at<int32_t>(ws, L.flags);
-  a.pscan = at<int64_t>(ws, L.pscan);
+  a.tmp_tt = at<double>(ws, L.tmp_tt);
+  a.tmp_i = at<double>(ws, L.tmp_i);
+  a.tmp_mult = at<int32_t>(ws, L.tmp_mult);
+  a.tmp_first = at<int64_t>(ws, L.tmp_first);
+  a.pk_count = at<int32_t>(ws, L.pk_count);
   a.cmax = at<uint64_t>(ws, L.cmax);
-  a.n_peaks = at<int64_t>(ws, L.n_peaks);
-  const bool thr = a.thr > 0.0;
-  a.tmp_tt = thr ? at<double>(ws, L.tmp_tt) : nullptr;
-  a.tmp_i = thr ? at<double>(ws, L.tmp_i) : nullptr;
-  a.tmp_y = thr ? at<double>(ws, L.tmp_y) : nullptr;
-  a.tmp_mult = thr ? at<int32_t>(ws, L.tmp_mult) : nullptr;
-  a.tmp_first = thr ? at<int64_t>(ws, L.tmp_first) : nullptr;
-  a.keep = thr ? at<int32_t>(ws, L.keep) : nullptr;
-  a.kscan = thr ? at<int64_t>(ws, L.kscan) : nullptr;
-  a.raw_peak_offset = thr ? at<int64_t>(ws, L.raw_peak_offset) : nullptr;
   a.pk_tt = p->two_theta;
   a.pk_i = p->intensity;
   a.pk_y = p->scaled;
@@ -491,8 +499,10 @@ int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, 
   a.pk_first = p->first;
   a.perm = p->perm;
   a.peak_offset = p->peak_offset;
-  ensure_sorted(b, ws, r);
+  // the merge sorts as it goes, and leaves the sorted order behind
   launch_merge(a, stream_of(b));
+  b->sorted_ws = ws;
+  b->sorted_tt = r->two_theta;
   b->last_ws = ws;
   return hip_check("merge_peaks");
 }
@@ -515,10 +525,16 @@ int xrd_pattern_forward(xrd_batch *b, void *ws, const xrd_refl *r, const double 
   if (int e = check_refl(r)) return e;
   if (int e = check_grid(g)) return e;
   if (!I || !y) return fail(XRD_ERR_INVALID_ARG, "I and y must be non-NULL");
-  const SortArgs sa = sort_args(b, ws, r);
+  if (g->n_points > b->grid_cap)
+    return fail(XRD_ERR_INVALID_ARG, "n_points exceeds the batch's grid_capacity (" + std::to_string(b->grid_cap) + ")");
   ensure_sorted(b, ws, r);
-  launch_broaden_fwd(b->desc.precision == XRD_MIXED, b->desc.n_crystals, r->refl_offset, sa.skey, sa.sidx, I,
-                     b->desc.friedel != 0, g->t0, g->dt, g->n_points, g->sigma, g->window_sigmas, y, stream_of(b));
+  const WsLayout &L = b->ws;
+  launch_broaden_fwd(b->desc.precision == XRD_MIXED, at<int32_t>(ws, L.hchunk_crystal),
+                     (int64_t)b->hchunk_crystal.size(), at<CrystalPlan>(ws, L.plan),
+                     at<int32_t>(ws, L.crystal_order), b->desc.n_crystals,
+                     b->desc.friedel != 0, r->refl_offset, at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), I,
+                     g->t0, g->dt, g->n_points, g->sigma, g->window_sigmas, b->span_cap, at<double>(ws, L.ent_w),
+                     at<int32_t>(ws, L.span_first), at<int32_t>(ws, L.span_last), y, stream_of(b));
   b->last_ws = ws;
   return hip_check("pattern_forward");
 }
@@ -539,9 +555,10 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   const int64_t n_items = (int64_t)b->sf_items.size();
   double *w1 = at<double>(ws, L.bw_w1), *w2 = at<double>(ws, L.bw_w2);
   double *ga = at<double>(ws, L.bw_ga), *gb = at<double>(ws, L.bw_gb), *dq = at<double>(ws, L.bw_dq);
+  ensure_sorted(b, ws, r);
   launch_broaden_adj(mixed, at<int32_t>(ws, L.hchunk_crystal), (int64_t)b->hchunk_crystal.size(), plan, friedel,
-                     r->refl_offset, r->two_theta, dL_dy, g->t0, g->dt, g->n_points, g->sigma, g->window_sigmas, w1,
-                     w2, s);
+                     r->refl_offset, at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), dL_dy, g->t0, g->dt,
+                     g->n_points, g->sigma, g->window_sigmas, w1, w2, s);
   launch_sf_bw(mixed, friedel, items, n_items, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
                b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
                b->desc.sf_coeff, w1, w2, ga, gb, dq, at<double>(ws, L.bw_partf), s);

@@ -6,14 +6,18 @@
 //   y_g = sum_r I_r K(x_g - 2theta_r),  K(d) = exp(-d^2 / (2 sigma^2)) / (sigma sqrt(2 pi)),
 //   restricted to |x_g - 2theta_r| <= window * sigma, x_g = t0 + g dt.
 //
-// Forward: a gather in which each thread owns one grid point and sums, in
-// 2theta order, the reflections staged in LDS whose window holds it, so the
-// result is deterministic without atomics.  Adjoint: per evaluated
-// reflection, w1 = sum_g dL/dy_g K and w2 = sum_g dL/dy_g K (x_g - 2theta) /
-// sigma^2 over the same window; on the uniform grid the Gaussian follows a
-// two-term multiplicative recurrence, so a whole window costs two exp and a
-// few products per point.  Then the lattice chain rule of the per-crystal
-// dL/dG*.
+// Both directions work on the entries that the sort leaves behind: each
+// crystal's evaluated reflections in ascending 2theta.  Forward: a gather in
+// which each lane owns one grid point and sums, in 2theta order, the entries
+// whose window holds it, so the result is deterministic without atomics; a
+// preparation pass gives every wave the entry range of its 64 points.
+// Adjoint: per entry, w1 = sum_g dL/dy_g K and w2 = sum_g dL/dy_g K
+// (x_g - 2theta) / sigma^2 over the same window; on the uniform grid the
+// Gaussian follows a two-term multiplicative recurrence
+//   K(d + dt) = K(d) r(d),  r(d) = exp(-(2 d dt + dt^2) / (2 sigma^2)),
+//   r(d + dt) = r(d) rho,   rho = exp(-dt^2 / sigma^2),
+// so a whole window costs two exp and a few products per point.  Then the
+// lattice chain rule of the per-crystal dL/dG*.
 #include <math.h>
 
 #include <type_traits>
@@ -49,220 +53,313 @@ __device__ __forceinline__ void window_of(const GridArgs &g, double t, int64_t *
   *hi = b;
 }
 
-// Gaussian values along the grid by recurrence: with d = x_g - t,
-// K(d + dt) = K(d) r(d), r(d) = exp(-(2 d dt + dt^2) / (2 sigma^2)) and
-// r(d + dt) = r(d) rho, rho = exp(-dt^2 / sigma^2); two exp per window.
-struct GaussWalk {
-  double K, r;
-  __device__ __forceinline__ void start(const GridArgs &g, double d, double scale) {
-    K = scale * g.norm * exp(-(d * d) * g.inv2s2);
-    r = exp(-(2.0 * d * g.dt + g.dt * g.dt) * g.inv2s2);
-  }
-  __device__ __forceinline__ void step(double rho) {
-    K *= r;
-    r *= rho;
-  }
+constexpr int kEntBlock = 1024;                // entries per block of the preparation and the adjoint
+constexpr int kEntSplit = kHalfChunk / kEntBlock;  // such blocks per chunk of kHalfChunk entries
+constexpr int kSegPts = 1024;                  // grid points per gather block (4 per thread)
+constexpr int kGTile = 1024;                   // entries per LDS tile of the gather
+constexpr int kAdjSpan = 4096;                 // grid points of dL/dy an adjoint block stages in LDS
+static_assert(kSegPts == 16 * kSpanPts, "a gather block covers 16 spans, four per wave");
+
+// Entries: the evaluated reflections of a crystal in ascending 2theta (both
+// mates of a Friedel pair share 2theta and I exactly, so with pairing one
+// entry of weight 2 I stands for both).  Entry e of crystal c sits at
+// base(c) + e, base = r0/2 with pairing and r0 without.
+struct EntryRange {
+  int64_t base, count;
 };
-
-constexpr int kPtsPerThread = 4;
-constexpr int kSegPts = 256 * kPtsPerThread;  // grid points per block of the forward gather
-constexpr int kTileR = 1024;                  // reflections per LDS tile of the gather
-constexpr int kAdjDyLds = 8192;               // grid rows up to this length are staged in LDS by the adjoint
-constexpr int kAdjSplit = 4;                  // adjoint blocks per chunk of evaluated reflections
-
-// First position in [lo, hi) of a sorted array with a[i] >= v, searched by the
-// whole block: each level probes 256 evenly spaced positions with one load
-// per thread and counts the probes below v, so a level shrinks the range
-// 256-fold (two levels for a crystal of up to 65536 reflections).  Every
-// thread of the block must call it.
-__device__ __forceinline__ int64_t block_lower_bound(const double *__restrict__ a, int64_t lo, int64_t hi, double v) {
-  int64_t base = lo, len = hi - lo;
-  while (len > 0) {
-    const int64_t stride = (len + 255) / 256;
-    const int64_t p = base + (int64_t)threadIdx.x * stride;
-    const bool below = p < base + len && a[p] < v;
-    const int cnt = __syncthreads_count(below);
-    if (cnt == 0) return base;
-    const int64_t nb = base + (int64_t)(cnt - 1) * stride + 1;
-    const int64_t ne = min(base + (int64_t)cnt * stride, base + len);
-    base = nb;
-    len = ne - nb;
-  }
-  return base;
+__device__ __forceinline__ EntryRange entry_range(const int64_t *__restrict__ refl_offset, int64_t c, bool friedel) {
+  const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
+  EntryRange e;
+  e.base = friedel ? r0 / 2 : r0;
+  e.count = friedel ? (r1 - r0) / 2 : r1 - r0;
+  return e;
 }
 
-// Forward gather.  A block owns kSegPts consecutive grid points of one
-// crystal; each thread kPtsPerThread of them, 256 apart.  The crystal's
-// 2theta-sorted reflections that reach the block's points are staged through
-// LDS in tiles (with Friedel pairing, whose mates have bit-identical 2theta
-// and I, one reflection per pair with twice the intensity), each with its
-// exact grid window [gl, gh] (the points with |x - 2theta| <= half).  Windows
-// are ordered like 2theta, so the reflections reaching point p form a range
-// [first e with gh_e >= p, last e with gl_e <= p]; both ends are scattered
-// into per-point LDS arrays, and every point then sums its range in sorted
-// order with no data-dependent exit: deterministic, no atomics.  The kernel
-// value is exp(-d^2 / 2 sigma^2) with d = x - 2theta in double; under MIXED
-// the exponential is taken in single precision (v_exp_f32).
+// Window of an entry as int32, clamped to [0, n] x [-1, n-1] (empty: lo > hi).
+__device__ __forceinline__ int2 window32(const GridArgs &g, double t) {
+  int64_t lo, hi;
+  window_of(g, t, &lo, &hi);
+  return make_int2((int)min(lo, g.n), (int)max(hi, (int64_t)-1));
+}
+
+// Entry preparation, one block per kEntBlock entries of a crystal: the
+// weight w_e = m I norm of every entry, and the entry ranges of the
+// crystal's spans of kSpanPts grid points:
+//   first[s] = min{e : gh_e >= 64 s},  last[s] = max{e : gl_e <= 64 s + 63},
+// with [gl_e, gh_e] the (clamped) window of entry e.  Both ends are
+// nondecreasing in e, so entry e owns first[s] for s in
+// (gh_{e-1} / 64, gh_e / 64] and last[s] for s in [gl_e / 64, gl_{e+1} / 64)
+// (integer floors), the first and last entries also own the spans beyond;
+// every span of a crystal with entries is written exactly once.
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_broaden_fwd(const int64_t *__restrict__ refl_offset,
-                                                     const double *__restrict__ skey,
-                                                     const int32_t *__restrict__ sidx,
-                                                     const double *__restrict__ inten, GridArgs g, bool friedel,
-                                                     double *__restrict__ y) {
+__global__ __launch_bounds__(256) void k_entry_prep(const int32_t *__restrict__ hchunk_crystal,
+                                                    const CrystalPlan *__restrict__ plan, bool friedel,
+                                                    const int64_t *__restrict__ refl_offset,
+                                                    const double *__restrict__ ent_key,
+                                                    const int32_t *__restrict__ ent_idx,
+                                                    const double *__restrict__ inten, GridArgs g, int64_t span_cap,
+                                                    double *__restrict__ ent_w, int32_t *__restrict__ span_first,
+                                                    int32_t *__restrict__ span_last) {
 #pragma clang fp contract(off)
-  __shared__ double s_tt[kTileR], s_i[kTileR];
-  __shared__ int32_t s_gl[kTileR], s_gh[kTileR];
-  __shared__ int16_t s_first[kSegPts], s_last[kSegPts];
-  __shared__ int32_t s_wcnt[256 / 64];
-  const int64_t segs = (g.n + kSegPts - 1) / kSegPts;
-  const int64_t c = blockIdx.x / segs;
-  const int64_t G0 = (int64_t)(blockIdx.x % segs) * kSegPts;
-  const int64_t G1 = min(G0 + kSegPts, g.n) - 1;
-  const int npts = (int)(G1 - G0 + 1);
-  const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
-  const int64_t mid = r0 + (r1 - r0) / 2;  // first reflection of the positive half
-  const double xa = g.t0 + (double)G0 * g.dt, xb = g.t0 + (double)G1 * g.dt;
-  const double bguard = 1e-9 * (fabs(xa) + fabs(xb) + 1.0);
-  const int64_t ja = block_lower_bound(skey, r0, r1, xa - g.half - bguard);
-  const int64_t jb = block_lower_bound(skey, ja, r1, xb + g.half + bguard);
-  const float c2 = (float)(g.inv2s2 * 1.4426950408889634);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  double acc[kPtsPerThread], x[kPtsPerThread];
+  __shared__ int32_t s_gl[kEntBlock + 2], s_gh[kEntBlock + 2];
+  const int hc = blockIdx.x / kEntSplit, sub = blockIdx.x % kEntSplit;
+  const int32_t c = hchunk_crystal[hc];
+  const CrystalPlan &P = plan[c];
+  const EntryRange er = entry_range(refl_offset, c, friedel);
+  const int64_t e0 = (int64_t)(hc - P.hchunk_begin) * kHalfChunk + (int64_t)sub * kEntBlock;
+  if (e0 >= er.count) return;
+  const int64_t e1 = min(e0 + (int64_t)kEntBlock, er.count);
+  const int S = (int)((g.n + kSpanPts - 1) / kSpanPts);
+  constexpr int U = kEntBlock / 256;
+  // loads first, all at once: keys (and the two neighbours at the block's
+  // ends), reflection indices, then intensities
+  double key[U];
+  int32_t idx[U];
 #pragma unroll
-  for (int q = 0; q < kPtsPerThread; ++q) {
-    acc[q] = 0.0;
-    x[q] = g.t0 + (double)(G0 + q * 256 + threadIdx.x) * g.dt;
+  for (int u = 0; u < U; ++u) {
+    const int64_t e = e0 + u * 256 + threadIdx.x;
+    key[u] = e < e1 ? ent_key[er.base + e] : 0.0;
+    idx[u] = e < e1 ? ent_idx[er.base + e] : 0;
   }
-  for (int64_t jt = ja; jt < jb; jt += kTileR) {
-    // stage in sorted order, compacted with a ballot per wave
-    int base = 0;
-    const int rounds = (int)min((int64_t)(kTileR / 256), (jb - jt + 255) / 256);
-    for (int u = 0; u < rounds; ++u) {
-      const int64_t j = jt + u * 256 + threadIdx.x;
-      bool keep = j < jb;
-      int32_t id = 0;
-      if (keep) {
-        id = sidx[j];
-        keep = !friedel || id >= mid;
-      }
-      const uint64_t bal = __ballot(keep);
-      if (lane == 0) s_wcnt[wid] = __popcll(bal);
-      __syncthreads();
-      int before = 0, total = 0;
-      for (int w = 0; w < 256 / 64; ++w) {
-        before += w < wid ? s_wcnt[w] : 0;
-        total += s_wcnt[w];
-      }
-      if (keep) {
-        const int e = base + before +
-                      __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-        const double t = skey[j];
-        int64_t wl, wh;
-        window_of(g, t, &wl, &wh);
-        s_tt[e] = t;
-        s_i[e] = (friedel ? 2.0 : 1.0) * inten[id] * g.norm;
-        // window relative to the segment, clamped to [-1, npts]
-        s_gl[e] = (int32_t)max((int64_t)-1, min((int64_t)npts, wl - G0));
-        s_gh[e] = (int32_t)max((int64_t)-1, min((int64_t)npts, wh - G0));
-      }
-      base += total;
-      __syncthreads();
+  double halo = 0.0;
+  const int64_t eh = threadIdx.x == 0 ? e0 - 1 : e1;  // thread 0: left neighbour, thread 1: right
+  const bool has_halo = threadIdx.x < 2 && eh >= 0 && eh < er.count;
+  if (has_halo) halo = ent_key[er.base + eh];
+  double iv[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) iv[u] = e0 + u * 256 + threadIdx.x < e1 ? inten[idx[u]] : 0.0;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t e = e0 + u * 256 + threadIdx.x;
+    if (e < e1) {
+      const int2 w = window32(g, key[u]);
+      s_gl[e - e0 + 1] = w.x;
+      s_gh[e - e0 + 1] = w.y;
     }
-    const int nt = base;
-    // per point: first entry with gh >= p and last entry with gl <= p (empty: last < first)
-    for (int p = threadIdx.x; p < npts; p += 256) {
-      s_first[p] = (int16_t)nt;
-      s_last[p] = (int16_t)-1;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nt; e += 256) {
-      // points p in (gh_{e-1}, gh_e] have first = e; points in [gl_e, gl_{e+1}) have last = e
-      const int ghp = e ? s_gh[e - 1] : -1, gh = s_gh[e];
-      for (int p = max(ghp + 1, 0); p <= min(gh, npts - 1); ++p) s_first[p] = (int16_t)e;
-      const int gl = s_gl[e], gln = e + 1 < nt ? s_gl[e + 1] : npts;
-      for (int p = max(gl, 0); p < min(gln, npts); ++p) s_last[p] = (int16_t)e;
+  }
+  if (has_halo) {
+    const int2 w = window32(g, halo);
+    s_gl[eh - e0 + 1] = w.x;
+    s_gh[eh - e0 + 1] = w.y;
+  }
+  __syncthreads();
+  const double m = friedel ? 2.0 : 1.0;
+  int32_t *__restrict__ first = span_first + (int64_t)c * span_cap;
+  int32_t *__restrict__ last = span_last + (int64_t)c * span_cap;
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int64_t e = e0 + u * 256 + threadIdx.x;
+    if (e >= e1) continue;
+    if constexpr (MIXED)
+      reinterpret_cast<float *>(ent_w)[er.base + e] = (float)(m * iv[u] * g.norm);
+    else
+      ent_w[er.base + e] = m * iv[u] * g.norm;
+    const int i = (int)(e - e0) + 1;
+    const int gh = s_gh[i], gl = s_gl[i];
+    const int fb = gh >= 0 ? gh / kSpanPts : -1;
+    const int fa = e == 0 ? 0 : (s_gh[i - 1] >= 0 ? s_gh[i - 1] / kSpanPts : -1) + 1;
+    for (int s = max(fa, 0); s <= min(fb, S - 1); ++s) first[s] = (int32_t)e;
+    if (e == er.count - 1)
+      for (int s = max(fb + 1, 0); s < S; ++s) first[s] = (int32_t)er.count;
+    const int la = gl / kSpanPts;
+    const int lb = e == er.count - 1 ? S - 1 : s_gl[i + 1] / kSpanPts - 1;
+    for (int s = la; s <= min(lb, S - 1); ++s) last[s] = (int32_t)e;
+    if (e == 0)
+      for (int s = 0; s < min(la, S); ++s) last[s] = -1;
+  }
+}
+
+// Forward gather: a block owns kSegPts consecutive grid points of one
+// crystal, each lane four of them, 256 apart, so that wave w of the block
+// covers spans 4j + w (j = 0..3) of the segment.  The entries reaching the
+// segment (first of its first span .. last of its last span) are staged in
+// LDS in tiles; each wave walks, for each of its spans, that span's entry
+// range in 2theta order with wave-uniform LDS reads, and each lane adds
+// w K(x - 2theta) when its point lies in the entry's window (the same
+// |x - 2theta| <= half test that defines the window), so every point sums
+// exactly its reflections, in sorted order, deterministically.  The offset
+// x - 2theta and the window test are double precision in both paths; under
+// MIXED the weight, the exponential (v_exp_f32) and the sums are single
+// precision, otherwise double.  Blocks take the crystals heaviest first and
+// each crystal's segments from the high-angle end, where reflections are
+// densest, so the longest blocks start first.
+template <bool MIXED>
+__global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restrict__ crystal_order,
+                                                        const int64_t *__restrict__ refl_offset, bool friedel,
+                                                        const double *__restrict__ ent_key,
+                                                        const double *__restrict__ ent_w,
+                                                        const int32_t *__restrict__ span_first,
+                                                        const int32_t *__restrict__ span_last, int64_t span_cap,
+                                                        GridArgs g, double *__restrict__ y) {
+#pragma clang fp contract(off)
+  using real = typename std::conditional<MIXED, float, double>::type;
+  struct Ent {
+    double t;
+    real w;
+  };
+  __shared__ Ent s_ent[kGTile];
+  const int S = (int)((g.n + kSpanPts - 1) / kSpanPts);
+  const int segs = (int)((g.n + kSegPts - 1) / kSegPts);
+  const int64_t c = crystal_order[blockIdx.x / segs];
+  const int sb = (segs - 1 - (int)(blockIdx.x % segs)) * (kSegPts / kSpanPts);
+  const int se = min(sb + kSegPts / kSpanPts, S) - 1;  // last span of the block
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const EntryRange er = entry_range(refl_offset, c, friedel);
+  const int32_t *__restrict__ fs = span_first + c * span_cap;
+  const int32_t *__restrict__ ls = span_last + c * span_cap;
+  // entry ranges of the wave's spans (empty for spans past the grid's end)
+  int f[4], l[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int s = sb + 4 * j + wid;
+    f[j] = s <= se ? max(fs[s], 0) : 0;
+    l[j] = s <= se ? (int)min((int64_t)ls[s], er.count - 1) : -1;
+  }
+  const int E0 = max(fs[sb], 0);
+  const int E1 = (int)min((int64_t)ls[se], er.count - 1);
+  double x[4];
+  real acc[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    x[j] = g.t0 + (double)((int64_t)sb * kSpanPts + j * 256 + threadIdx.x) * g.dt;
+    acc[j] = 0;
+  }
+  const real *__restrict__ wts = reinterpret_cast<const real *>(ent_w);
+  const float c2 = (float)(g.inv2s2 * 1.4426950408889634);
+  for (int T0 = E0; T0 <= E1; T0 += kGTile) {
+    const int T1 = min(T0 + kGTile - 1, E1);
+#pragma unroll
+    for (int k = 0; k < kGTile / 256; ++k) {
+      const int e = T0 + k * 256 + (int)threadIdx.x;
+      if (e <= T1) s_ent[e - T0] = Ent{ent_key[er.base + e], wts[er.base + e]};
     }
     __syncthreads();
 #pragma unroll
-    for (int q = 0; q < kPtsPerThread; ++q) {
-      const int p = q * 256 + threadIdx.x;
-      if (p >= npts) continue;
-      const int e0 = s_first[p], e1 = s_last[p];
-      double a = 0.0;
-      for (int e = e0; e <= e1; ++e) {
-        const double d = x[q] - s_tt[e];
-        if constexpr (MIXED) {
-          const float df = (float)d;
-          a += s_i[e] * (double)__builtin_amdgcn_exp2f(-(df * df) * c2);
-        } else {
-          a += s_i[e] * exp(-(d * d) * g.inv2s2);
+    for (int j = 0; j < 4; ++j) {
+      const int a = max(f[j], T0) - T0, b = min(l[j], T1) - T0;
+      real sacc = acc[j];
+#pragma unroll 8
+      for (int e = a; e <= b; ++e) {
+        const Ent ent = s_ent[e];
+        const double d = x[j] - ent.t;
+        if (fabs(d) <= g.half) {
+          if constexpr (MIXED) {
+            const float df = (float)d;
+            sacc = __builtin_fmaf(ent.w, __builtin_amdgcn_exp2f(-(df * df) * c2), sacc);
+          } else {
+            sacc += ent.w * exp(-(d * d) * g.inv2s2);
+          }
         }
       }
-      acc[q] += a;
+      acc[j] = sacc;
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int q = 0; q < kPtsPerThread; ++q) {
-    const int64_t gi = G0 + q * 256 + threadIdx.x;
-    if (gi <= G1) y[c * g.n + gi] = acc[q];
+  for (int j = 0; j < 4; ++j) {
+    const int64_t p = (int64_t)sb * kSpanPts + j * 256 + threadIdx.x;
+    if (p < g.n) y[c * g.n + p] = (double)acc[j];
   }
 }
 
-// Adjoint on the grid side: kAdjSplit blocks per chunk of a crystal's
-// evaluated reflections, the crystal's dL/dy row staged in LDS; per reflection
+// Adjoint on the grid side, one block per kEntBlock consecutive entries of a
+// crystal, four per thread (256 apart):
 //   w1 = sum_g dy_g K,  w2 = sum_g dy_g K d / sigma^2  (d = x_g - 2theta)
 // over the same window as the forward, K by the Gaussian recurrence (in
 // single precision under MIXED, where 81-step products stay within ~1e-6).
-template <bool LDS_ROW, bool MIXED>
+// The block's entries are consecutive in 2theta, so their windows cover one
+// interval of the grid; the block stages that stretch of the crystal's
+// dL/dy row in LDS (converted to the working precision) when it has at most
+// kAdjSpan points and reads the row from global memory otherwise.  Results
+// go to w1/w2 at the entries' reflection indices.
+template <typename real, typename src_t>
+__device__ __forceinline__ void adj_walk(const src_t *__restrict__ src, int off, int wl, int wh, const GridArgs &g,
+                                         double t, real rho, real dtr, real *a1o, real *a2o) {
+#pragma clang fp contract(off)
+  real a1 = 0, a2 = 0;
+  if (wl <= wh) {
+    const double d0 = g.t0 + (double)wl * g.dt - t;
+    real K = (real)(g.norm * exp(-(d0 * d0) * g.inv2s2));
+    real r = (real)exp(-(2.0 * d0 * g.dt + g.dt * g.dt) * g.inv2s2);
+    real d = (real)d0;
+#pragma unroll 4
+    for (int gi = wl; gi <= wh; ++gi) {
+      const real kv = (real)src[gi - off] * K;
+      a1 += kv;
+      a2 += kv * d;
+      K *= r;
+      r *= rho;
+      d += dtr;
+    }
+  }
+  *a1o = a1;
+  *a2o = a2;
+}
+
+template <bool MIXED>
 __global__ __launch_bounds__(256) void k_broaden_adj(const int32_t *__restrict__ hchunk_crystal,
                                                      const CrystalPlan *__restrict__ plan, bool friedel,
                                                      const int64_t *__restrict__ refl_offset,
-                                                     const double *__restrict__ tt, const double *__restrict__ dy,
-                                                     GridArgs g, double *__restrict__ w1, double *__restrict__ w2) {
+                                                     const double *__restrict__ ent_key,
+                                                     const int32_t *__restrict__ ent_idx,
+                                                     const double *__restrict__ dy, GridArgs g,
+                                                     double *__restrict__ w1, double *__restrict__ w2) {
 #pragma clang fp contract(off)
   using real = typename std::conditional<MIXED, float, double>::type;
-  extern __shared__ double s_dy[];  // the crystal's dL/dy row when LDS_ROW
-  const int hc = blockIdx.x / kAdjSplit, sub = blockIdx.x % kAdjSplit;
+  __shared__ real s_dy[kAdjSpan];
+  __shared__ int32_t s_span[2];
+  constexpr int U = kEntBlock / 256;
+  const int hc = blockIdx.x / kEntSplit, sub = blockIdx.x % kEntSplit;
   const int32_t c = hchunk_crystal[hc];
   const CrystalPlan &P = plan[c];
-  const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
-  const int64_t first = friedel ? r0 + (r1 - r0) / 2 : r0;
-  const int64_t count = friedel ? (r1 - r0) / 2 : r1 - r0;
-  const int64_t e0 = (int64_t)(hc - P.hchunk_begin) * kHalfChunk + sub * (kHalfChunk / kAdjSplit);
-  if (e0 >= count) return;
-  const int64_t e1 = min(e0 + (int64_t)(kHalfChunk / kAdjSplit), count);
-  const double *dyc = dy + (int64_t)c * g.n;
-  if (LDS_ROW) {
-    for (int i = threadIdx.x; i < (int)g.n; i += 256) s_dy[i] = dyc[i];
-    __syncthreads();
+  const EntryRange er = entry_range(refl_offset, c, friedel);
+  const int64_t e0 = (int64_t)(hc - P.hchunk_begin) * kHalfChunk + (int64_t)sub * kEntBlock;
+  if (e0 >= er.count) return;
+  const int ne = (int)min((int64_t)kEntBlock, er.count - e0);
+  double t[U];
+  int32_t idx[U];
+  int2 w[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = u * 256 + (int)threadIdx.x;
+    t[u] = ent_key[er.base + e0 + min(i, ne - 1)];
+    idx[u] = i < ne ? ent_idx[er.base + e0 + i] : 0;
   }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = u * 256 + (int)threadIdx.x;
+    w[u] = window32(g, t[u]);
+    // windows are nondecreasing in e: the block's stretch is [gl(first), gh(last)]
+    if (i == 0) s_span[0] = w[u].x;
+    if (i == ne - 1) s_span[1] = w[u].y;
+  }
+  __syncthreads();
+  const int lo = s_span[0], hi = s_span[1];
+  const double *__restrict__ dyc = dy + (int64_t)c * g.n;
   const double inv_s2 = 1.0 / (g.sigma * g.sigma);
   const real rho = (real)exp(-(g.dt * g.dt) * inv_s2);
   const real dtr = (real)g.dt;
-  for (int64_t e = e0 + threadIdx.x; e < e1; e += 256) {
-    const int64_t i = first + e;
-    const double t = tt[i];
-    int64_t wl64, wh64;
-    window_of(g, t, &wl64, &wh64);
-    const int wl = (int)wl64, wh = (int)wh64;
-    real a1 = 0, a2 = 0;
-    if (wl <= wh) {
-      const double d0 = g.t0 + (double)wl * g.dt - t;
-      real K = (real)(g.norm * exp(-(d0 * d0) * g.inv2s2));
-      real r = (real)exp(-(2.0 * d0 * g.dt + g.dt * g.dt) * g.inv2s2);
-      real d = (real)d0;
-      for (int gi = wl; gi <= wh; ++gi) {
-        const real kv = (real)(LDS_ROW ? s_dy[gi] : dyc[gi]) * K;
-        a1 += kv;
-        a2 += kv * d;
-        K *= r;
-        r *= rho;
-        d += dtr;
-      }
+  const bool staged = hi - lo + 1 <= kAdjSpan;
+  if (staged) {
+    const int len = hi - lo + 1;
+#pragma unroll
+    for (int k = 0; k < kAdjSpan / 256; ++k) {
+      const int i = k * 256 + (int)threadIdx.x;
+      if (i < len) s_dy[i] = (real)dyc[lo + i];
     }
-    w1[i] = (double)a1;
-    w2[i] = (double)a2 * inv_s2;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int i = u * 256 + (int)threadIdx.x;
+    if (i >= ne) continue;
+    real a1, a2;
+    if (staged)
+      adj_walk<real, real>(s_dy, lo, w[u].x, w[u].y, g, t[u], rho, dtr, &a1, &a2);
+    else
+      adj_walk<real, double>(dyc, 0, w[u].x, w[u].y, g, t[u], rho, dtr, &a1, &a2);
+    w1[idx[u]] = (double)a1;
+    w2[idx[u]] = (double)a2 * inv_s2;
   }
 }
 
@@ -324,42 +421,45 @@ GridArgs make_grid(double t0, double dt, int64_t n, double sigma, double window)
 
 }  // namespace
 
-void launch_broaden_fwd(bool mixed, int64_t n_c, const int64_t *refl_offset, const double *skey,
-                        const int32_t *sidx, const double *inten, bool friedel, double t0, double dt, int64_t n,
-                        double sigma, double window, double *y, hipStream_t s) {
+void launch_broaden_fwd(bool mixed, const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan,
+                        const int32_t *crystal_order, int64_t n_c, bool friedel, const int64_t *refl_offset, const double *ent_key,
+                        const int32_t *ent_idx, const double *inten, double t0, double dt, int64_t n, double sigma,
+                        double window, int64_t span_cap, double *ent_w, int32_t *span_first, int32_t *span_last,
+                        double *y, hipStream_t s) {
   if (n_c <= 0 || n <= 0) return;
   const GridArgs g = make_grid(t0, dt, n, sigma, window);
-  const int64_t segs = (n + kSegPts - 1) / kSegPts;
+  if (n_hchunks > 0) {
+    if (mixed)
+      hipLaunchKernelGGL(k_entry_prep<true>, dim3((unsigned)(n_hchunks * kEntSplit)), dim3(256), 0, s, hchunk_crystal,
+                         plan, friedel, refl_offset, ent_key, ent_idx, inten, g, span_cap, ent_w, span_first,
+                         span_last);
+    else
+      hipLaunchKernelGGL(k_entry_prep<false>, dim3((unsigned)(n_hchunks * kEntSplit)), dim3(256), 0, s,
+                         hchunk_crystal, plan, friedel, refl_offset, ent_key, ent_idx, inten, g, span_cap, ent_w,
+                         span_first, span_last);
+  }
+  const dim3 grid((unsigned)(n_c * ((n + kSegPts - 1) / kSegPts))), block(256);
   if (mixed)
-    hipLaunchKernelGGL(k_broaden_fwd<true>, dim3((unsigned)(segs * n_c)), dim3(256), 0, s, refl_offset, skey, sidx,
-                       inten, g, friedel, y);
+    hipLaunchKernelGGL(k_broaden_gather<true>, grid, block, 0, s, crystal_order, refl_offset, friedel, ent_key, ent_w,
+                       span_first, span_last, span_cap, g, y);
   else
-    hipLaunchKernelGGL(k_broaden_fwd<false>, dim3((unsigned)(segs * n_c)), dim3(256), 0, s, refl_offset, skey, sidx,
-                       inten, g, friedel, y);
+    hipLaunchKernelGGL(k_broaden_gather<false>, grid, block, 0, s, crystal_order, refl_offset, friedel, ent_key,
+                       ent_w, span_first, span_last, span_cap, g, y);
 }
 
 void launch_broaden_adj(bool mixed, const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan,
-                        bool friedel, const int64_t *refl_offset, const double *tt, const double *dy, double t0,
-                        double dt, int64_t n, double sigma, double window, double *w1, double *w2, hipStream_t s) {
-  if (n_hchunks <= 0) return;
+                        bool friedel, const int64_t *refl_offset, const double *ent_key, const int32_t *ent_idx,
+                        const double *dy, double t0, double dt, int64_t n, double sigma, double window, double *w1,
+                        double *w2, hipStream_t s) {
+  if (n_hchunks <= 0 || n <= 0) return;
   const GridArgs g = make_grid(t0, dt, n, sigma, window);
-  const dim3 grid((unsigned)(n_hchunks * kAdjSplit)), block(256);
-  const size_t lds = (size_t)n * sizeof(double);
-  if (n <= kAdjDyLds) {
-    if (mixed)
-      hipLaunchKernelGGL((k_broaden_adj<true, true>), grid, block, lds, s, hchunk_crystal, plan, friedel, refl_offset,
-                         tt, dy, g, w1, w2);
-    else
-      hipLaunchKernelGGL((k_broaden_adj<true, false>), grid, block, lds, s, hchunk_crystal, plan, friedel,
-                         refl_offset, tt, dy, g, w1, w2);
-  } else {
-    if (mixed)
-      hipLaunchKernelGGL((k_broaden_adj<false, true>), grid, block, 0, s, hchunk_crystal, plan, friedel, refl_offset,
-                         tt, dy, g, w1, w2);
-    else
-      hipLaunchKernelGGL((k_broaden_adj<false, false>), grid, block, 0, s, hchunk_crystal, plan, friedel,
-                         refl_offset, tt, dy, g, w1, w2);
-  }
+  const dim3 grid((unsigned)(n_hchunks * kEntSplit)), block(256);
+  if (mixed)
+    hipLaunchKernelGGL(k_broaden_adj<true>, grid, block, 0, s, hchunk_crystal, plan, friedel, refl_offset, ent_key,
+                       ent_idx, dy, g, w1, w2);
+  else
+    hipLaunchKernelGGL(k_broaden_adj<false>, grid, block, 0, s, hchunk_crystal, plan, friedel, refl_offset, ent_key,
+                       ent_idx, dy, g, w1, w2);
 }
 
 void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s) {

@@ -22,6 +22,9 @@ constexpr int kAtomBlock = 256;   // atoms per adjoint block
 constexpr int kSfRpt = 2;         // reflections per lane in the structure-factor kernels
 constexpr int kSfTile = 64 * kSfRpt;
 constexpr int kFusedMaxAtoms = 512;  // crystals up to this size take the fused atom-gradient path
+constexpr int kSmallSort = 4096;     // reflections sorted in LDS by one 256-thread block
+constexpr int kMidSort = 12288;      // reflections sorted in LDS by one 1024-thread block
+constexpr int kSpanPts = 64;         // grid points per wave of the broadening gather
 
 // Per-crystal plan (device copy in the workspace), 256 bytes.
 struct alignas(16) CrystalPlan {
@@ -72,13 +75,13 @@ struct SfItem {
 
 // Workspace byte offsets (all 256-aligned).
 struct WsLayout {
-  int64_t plan, enum_chunk_crystal, sf_items, sort_chunk_crystal, hchunk_crystal, bw_items, ab_items;
+  int64_t plan, enum_chunk_crystal, sf_items, sort_chunk_crystal, hchunk_crystal, crystal_order, bw_items, ab_items;
   int64_t enum_count, enum_prefix;
   int64_t atoms, atom_orig, runs, run_count, err_flag;
-  int64_t bin_count, bin_start, big_list, big_chunks, sort_counters;
-  int64_t skey, sidx;
-  int64_t flags, pscan;
-  int64_t cmax, n_peaks, tmp_tt, tmp_i, tmp_y, tmp_mult, tmp_first, keep, kscan, raw_peak_offset;
+  int64_t bin_count, bin_start;
+  int64_t skey, sidx, ent_key, ent_idx, ent_w, span_first, span_last;
+  int64_t flags;
+  int64_t cmax, pk_count, tmp_tt, tmp_i, tmp_mult, tmp_first;
   int64_t scan_part;
   int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6, bw_partf;
   int64_t total;
@@ -130,29 +133,26 @@ struct SortArgs {
   double *skey;
   int32_t *sidx;
   int64_t *scan_part;
-  int32_t *big_list;   // [n_c] crystals sorted by the bucket path
-  int2 *big_chunks;    // [n_chunks] their sort chunks
-  int32_t *counters;   // [2] list lengths
+  const int32_t *order;  // [n_c] crystals by descending capacity
+  int64_t n_mid;         // leading entries of ``order`` with capacity above kSmallSort
+  int32_t friedel;       // write the evaluated-half entries below
+  double *ent_key;       // [half capacity] 2theta of the evaluated half, sorted per crystal
+  int32_t *ent_idx;      // its global reflection indices
 };
 void launch_sort(const SortArgs &a, hipStream_t s);
 
 struct MergeArgs {
   SortArgs sort;
   int64_t n_c;
-  int64_t refl_cap;
   double tol, thr;
   const double *inten;
-  int32_t *flags;
-  int64_t *pscan;
-  uint64_t *cmax;
-  int64_t *n_peaks;
-  // staging of the threshold path (NULL when thr == 0)
-  double *tmp_tt, *tmp_i, *tmp_y;
+  int32_t *flags;      // [refl_cap] peak starts of crystals sorted in global memory
+  // each crystal's peaks staged at its reflection offset, with counts and maxima
+  double *tmp_tt, *tmp_i;
   int32_t *tmp_mult;
   int64_t *tmp_first;
-  int32_t *keep;
-  int64_t *kscan;
-  int64_t *raw_peak_offset;
+  int32_t *pk_count;   // [n_c]
+  uint64_t *cmax;      // [n_c]
   // outputs
   double *pk_tt, *pk_i, *pk_y;
   int32_t *pk_mult;
@@ -160,12 +160,19 @@ struct MergeArgs {
 };
 void launch_merge(const MergeArgs &a, hipStream_t s);
 
-void launch_broaden_fwd(bool mixed, int64_t n_c, const int64_t *refl_offset, const double *skey,
-                        const int32_t *sidx, const double *inten, bool friedel, double t0, double dt, int64_t n,
-                        double sigma, double window, double *y, hipStream_t s);
+// Gaussian broadening over the sorted entries (evaluated reflections in
+// 2theta order).  The forward also fills ent_w (double weights, or float
+// weights in its first half under mixed precision) and the span tables;
+// crystal_order lists the crystals heaviest first.
+void launch_broaden_fwd(bool mixed, const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan,
+                        const int32_t *crystal_order, int64_t n_c, bool friedel, const int64_t *refl_offset, const double *ent_key,
+                        const int32_t *ent_idx, const double *inten, double t0, double dt, int64_t n, double sigma,
+                        double window, int64_t span_cap, double *ent_w, int32_t *span_first, int32_t *span_last,
+                        double *y, hipStream_t s);
 void launch_broaden_adj(bool mixed, const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan,
-                        bool friedel, const int64_t *refl_offset, const double *tt, const double *dy, double t0,
-                        double dt, int64_t n, double sigma, double window, double *w1, double *w2, hipStream_t s);
+                        bool friedel, const int64_t *refl_offset, const double *ent_key, const int32_t *ent_idx,
+                        const double *dy, double t0, double dt, int64_t n, double sigma, double window, double *w1,
+                        double *w2, hipStream_t s);
 void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s);
 void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,

@@ -161,3 +161,37 @@ def test_gradient_of_full_differentiation_batch_runs_and_is_deterministic():
     for a, bb in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a, bb)
         assert np.all(np.isfinite(a))
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-7), ("mixed", 1e-4)])
+def test_adjoint_dot_product_consistency(precision, bar):
+    """<J v, w> = <v, J^T w> for the GPU path itself: J^T w from the adjoint
+    with dL/dy = w, J v from central differences (h = 1e-6 along v) of the
+    GPU's own double-precision forward.  Independent of the oracle, so a
+    mistake shared by the forward and the adjoint of the broadening would
+    still be caught by the finite-difference tests above, and a mistake in
+    the adjoint alone by this one."""
+    from paper_2602_11709_amd.api import Grid, xrd_pattern
+    p = problem(3, 20, 80, seed=24)
+    b = p.batch
+    grid = Grid(p.grid_t0, p.grid_dt, p.grid_n, p.sigma, p.window_sigmas)
+    rng = np.random.default_rng(5)
+    vf, vl, vb = rng.normal(size=b.frac.shape), rng.normal(size=b.lattice.shape), rng.normal(size=b.n_atoms)
+    w = rng.normal(size=(b.n_crystals, p.grid_n))
+    frac = torch.tensor(b.frac, device="cuda", requires_grad=True)
+    lat = torch.tensor(b.lattice, requires_grad=True)
+    bf = torch.tensor(b.bfac, device="cuda", requires_grad=True)
+    y = xrd_pattern(frac, lat, bf, b, grid, precision=precision)
+    (y * torch.tensor(w, device="cuda")).sum().backward()
+    lhs = float((frac.grad.cpu().numpy() * vf).sum() + (lat.grad.numpy() * vl).sum()
+                + (bf.grad.cpu().numpy() * vb).sum())
+    ys = []
+    for s in (1, -1):
+        with torch.no_grad():
+            yy = xrd_pattern(torch.tensor(b.frac + s * H * vf, device="cuda"), torch.tensor(b.lattice + s * H * vl),
+                             torch.tensor(b.bfac + s * H * vb, device="cuda"), b, grid, precision="fp64")
+        ys.append(yy.cpu().numpy())
+    rhs = float((((ys[0] - ys[1]) / (2 * H)) * w).sum())
+    rel = abs(lhs - rhs) / abs(rhs)
+    print(precision, "<v, J^T w>", lhs, "<J v, w>", rhs, "rel", rel, flush=True)
+    assert rel <= bar
