@@ -34,6 +34,7 @@ struct xrd_batch {
   std::vector<AbItem> ab_items;
   int64_t n_atoms = 0, refl_cap = 0, half_cap = 0, n_bins = 0, run_cap = 0, part_rows = 0, partf_rows = 0;
   int64_t n_mid = 0;      // crystals whose reflection capacity exceeds kSmallSort
+  int64_t sf_heavy = 0;   // leading structure-factor items that take a block each
   int64_t grid_cap = 0;   // largest grid of a broadened-pattern call
   int64_t span_cap = 0;   // span-table entries per crystal: ceil(grid_cap / kSpanPts)
   int runs_cap_max = 1, bw_tile = 64;
@@ -226,7 +227,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     runs += rc;
     runs_cap_max = (int)std::max<int64_t>(runs_cap_max, rc);
     const int64_t evalcap = friedel ? P.half_box : 2 * P.half_box;
-    P.n_hchunks = (int32_t)ceil_div(evalcap, kHalfChunk);
+    // at least one chunk, so that every crystal gets its lattice gradient
+    P.n_hchunks = (int32_t)std::max<int64_t>(1, ceil_div(evalcap, kHalfChunk));
     P.hchunk_begin = hc;
     hc += P.n_hchunks;
     P.n_tiles = (int32_t)ceil_div(evalcap, kSfTile);
@@ -285,6 +287,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     const int64_t tiles = ceil_div(evalcap, kSfTile);
     for (int64_t t = 0; t < tiles; ++t) b->sf_items.push_back(SfItem{(int32_t)c, (int32_t)t});
     const int64_t na = P.atom_end - P.atom_begin;
+    // crystals in descending atom count: the heavy ones form the table's head
+    if (na >= kSplitAtoms) b->sf_heavy += tiles;
     const int64_t ab = ceil_div(na, kAtomBlock);
     for (int64_t a = 0; a < ab; ++a) {
       b->ab_items.push_back(AbItem{(int32_t)c, (int32_t)a});
@@ -427,7 +431,7 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
   if (!A || !B || !I) return fail(XRD_ERR_INVALID_ARG, "A, B and I must be non-NULL");
   const WsLayout &L = b->ws;
   launch_sf(b->desc.precision == XRD_MIXED, b->desc.friedel != 0, at<SfItem>(ws, L.sf_items),
-            (int64_t)b->sf_items.size(), at<CrystalPlan>(ws, L.plan), r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
+            (int64_t)b->sf_items.size(), b->sf_heavy, at<CrystalPlan>(ws, L.plan), r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
             at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), b->desc.sf_coeff, A, B,
             I, stream_of(b));
   b->last_ws = ws;
@@ -559,7 +563,7 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   launch_broaden_adj(mixed, at<int32_t>(ws, L.hchunk_crystal), (int64_t)b->hchunk_crystal.size(), plan, friedel,
                      r->refl_offset, at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), dL_dy, g->t0, g->dt,
                      g->n_points, g->sigma, g->window_sigmas, w1, w2, s);
-  launch_sf_bw(mixed, friedel, items, n_items, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
+  launch_sf_bw(mixed, friedel, items, n_items, b->sf_heavy, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
                b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
                b->desc.sf_coeff, w1, w2, ga, gb, dq, at<double>(ws, L.bw_partf), s);
   launch_atom_bw(mixed, friedel, at<BwItem>(ws, L.bw_items), (int64_t)b->bw_items.size(), plan, r->refl_offset,

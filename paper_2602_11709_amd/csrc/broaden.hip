@@ -16,8 +16,7 @@
 // Gaussian follows a two-term multiplicative recurrence
 //   K(d + dt) = K(d) r(d),  r(d) = exp(-(2 d dt + dt^2) / (2 sigma^2)),
 //   r(d + dt) = r(d) rho,   rho = exp(-dt^2 / sigma^2),
-// so a whole window costs two exp and a few products per point.  Then the
-// lattice chain rule of the per-crystal dL/dG*.
+// so a whole window costs two exp and a few products per point.
 #include <math.h>
 
 #include <type_traits>
@@ -363,50 +362,6 @@ __global__ __launch_bounds__(256) void k_broaden_adj(const int32_t *__restrict__
   }
 }
 
-// dL/dG* (6 unique entries) -> dL/d(a, b, c, alpha, beta, gamma), angles in degrees.
-// q = sum_ij M_ij h_i h_j with M = G*, so dL/dM_ij = U_ij for i == j and
-// U_ij / 2 for i != j (the unique entry appears twice); dL/dG = -M (dL/dM) M.
-__global__ void k_lattice_chain(const CrystalPlan *__restrict__ plan, int64_t n_c, const double *__restrict__ part6,
-                                double *__restrict__ dlat) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_c) return;
-  const CrystalPlan &P = plan[c];
-  double U[6] = {0, 0, 0, 0, 0, 0};
-  for (int k = 0; k < P.n_hchunks; ++k)
-    for (int e = 0; e < 6; ++e) U[e] += part6[(P.hchunk_begin + k) * 6 + e];
-  const double M[3][3] = {{P.gs[0], P.gs[3], P.gs[4]}, {P.gs[3], P.gs[1], P.gs[5]}, {P.gs[4], P.gs[5], P.gs[2]}};
-  const double D[3][3] = {{U[0], 0.5 * U[3], 0.5 * U[4]}, {0.5 * U[3], U[1], 0.5 * U[5]}, {0.5 * U[4], 0.5 * U[5], U[2]}};
-  double T[3][3], Gb[3][3];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      double s = 0.0;
-      for (int m = 0; m < 3; ++m) s += D[i][m] * M[m][j];
-      T[i][j] = s;
-    }
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) {
-      double s = 0.0;
-      for (int m = 0; m < 3; ++m) s += M[i][m] * T[m][j];
-      Gb[i][j] = -s;
-    }
-  const double a = P.lat[0], b = P.lat[1], cc = P.lat[2];
-  const double rad = kPi / 180.0;
-  double sa, ca, sb, cb, sg, cg;
-  sincos(P.lat[3] * rad, &sa, &ca);
-  sincos(P.lat[4] * rad, &sb, &cb);
-  sincos(P.lat[5] * rad, &sg, &cg);
-  // G11 = a^2, G22 = b^2, G33 = c^2, G12 = ab cos(gamma), G13 = ac cos(beta), G23 = bc cos(alpha);
-  // off-diagonal entries appear twice in the full symmetric matrix.
-  const double g12 = 2.0 * Gb[0][1], g13 = 2.0 * Gb[0][2], g23 = 2.0 * Gb[1][2];
-  double *o = dlat + 6 * c;
-  o[0] = Gb[0][0] * 2.0 * a + g12 * b * cg + g13 * cc * cb;
-  o[1] = Gb[1][1] * 2.0 * b + g12 * a * cg + g23 * cc * ca;
-  o[2] = Gb[2][2] * 2.0 * cc + g13 * a * cb + g23 * b * ca;
-  o[3] = g23 * (-b * cc * sa * rad);
-  o[4] = g13 * (-a * cc * sb * rad);
-  o[5] = g12 * (-a * b * sg * rad);
-}
-
 GridArgs make_grid(double t0, double dt, int64_t n, double sigma, double window) {
   GridArgs g;
   g.t0 = t0;
@@ -462,9 +417,5 @@ void launch_broaden_adj(bool mixed, const int32_t *hchunk_crystal, int64_t n_hch
                        ent_idx, dy, g, w1, w2);
 }
 
-void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s) {
-  if (n_c <= 0) return;
-  hipLaunchKernelGGL(k_lattice_chain, dim3((unsigned)((n_c + 255) / 256)), dim3(256), 0, s, plan, n_c, part6, dlat);
-}
 
 }  // namespace xrd

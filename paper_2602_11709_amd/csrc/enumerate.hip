@@ -104,6 +104,42 @@ __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__re
   }
 }
 
+// Exclusive scan of the chunk counts and the crystal offsets in one block
+// (batches with up to kOneBlockChunks enumeration chunks).
+constexpr int kOneBlockChunks = 8192;
+__global__ __launch_bounds__(1024) void k_enum_scan1(const CrystalPlan *__restrict__ plan, int64_t n_c,
+                                                     int64_t n_chunks, const int32_t *__restrict__ counts,
+                                                     int64_t *__restrict__ prefix, int64_t *__restrict__ refl_offset) {
+  __shared__ int64_t wsum[1024 / 64];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  int64_t carry = 0;
+  for (int64_t c0 = 0; c0 < n_chunks; c0 += 1024) {
+    const int64_t i = c0 + threadIdx.x;
+    const int64_t v = i < n_chunks ? counts[i] : 0;
+    int64_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    __syncthreads();
+    if (lane == 63) wsum[wid] = inc;
+    __syncthreads();
+    int64_t before = 0, total = 0;
+#pragma unroll
+    for (int w = 0; w < 1024 / 64; ++w) {
+      before += w < wid ? wsum[w] : 0;
+      total += wsum[w];
+    }
+    if (i < n_chunks) prefix[i] = carry + before + inc - v;
+    carry += total;
+  }
+  if (threadIdx.x == 0) prefix[n_chunks] = carry;
+  __syncthreads();  // the block's prefix writes are visible to the whole block
+  for (int64_t c = threadIdx.x; c <= n_c; c += 1024)
+    refl_offset[c] = 2 * (c < n_c ? prefix[plan[c].enum_chunk_begin] : carry);
+}
+
 __global__ void k_enum_offsets(const CrystalPlan *__restrict__ plan, int64_t n_c, int64_t n_chunks,
                                const int64_t *__restrict__ prefix, int64_t *__restrict__ refl_offset) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -179,9 +215,13 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk
   if (n_chunks > 0)
     hipLaunchKernelGGL(k_enum_count, dim3((unsigned)n_chunks), dim3(kThreads), 0, s, plan, chunk_crystal, lambda,
                        counts);
-  launch_scan_i32(counts, n_chunks, nullptr, prefix, scan_part, s);
-  hipLaunchKernelGGL(k_enum_offsets, dim3((unsigned)((n_c + 1 + 255) / 256)), dim3(256), 0, s, plan, n_c, n_chunks,
-                     prefix, refl_offset);
+  if (n_chunks <= kOneBlockChunks) {
+    hipLaunchKernelGGL(k_enum_scan1, dim3(1), dim3(1024), 0, s, plan, n_c, n_chunks, counts, prefix, refl_offset);
+  } else {
+    launch_scan_i32(counts, n_chunks, nullptr, prefix, scan_part, s);
+    hipLaunchKernelGGL(k_enum_offsets, dim3((unsigned)((n_c + 1 + 255) / 256)), dim3(256), 0, s, plan, n_c, n_chunks,
+                       prefix, refl_offset);
+  }
   if (n_chunks > 0)
     hipLaunchKernelGGL(k_enum_fill, dim3((unsigned)n_chunks), dim3(kThreads), 0, s, plan, chunk_crystal, prefix,
                        lambda, h, k, l, q, tt, lp);

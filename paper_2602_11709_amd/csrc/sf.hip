@@ -179,6 +179,27 @@ __device__ __forceinline__ double wave_sum_to_63(double v) {
   return v;
 }
 
+// Sixteen per-lane values reduced over the wavefront at once: a butterfly
+// whose levels pair lanes l and l^15 (row mirror), l^7 (half-row mirror),
+// l^2 and l^1 (quad permutes), each lane keeping the half of its values whose
+// index bit matches its own lane bit, then l^16 and l^32 across rows.  On
+// return every lane holds the wave total of value (lane & 15).  Fifteen
+// exchanges and adds in the rows instead of four times six.
+__device__ __forceinline__ float wave_reduce16(const float (&v)[16], int lane) {
+  float w8[8], w4[4], w2[2];
+  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) w8[i] = (b3 ? v[8 + i] : v[i]) + dpp_f32<0x140, 0xf, false>(b3 ? v[i] : v[8 + i]);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) w4[i] = (b2 ? w8[4 + i] : w8[i]) + dpp_f32<0x141, 0xf, false>(b2 ? w8[i] : w8[4 + i]);
+#pragma unroll
+  for (int i = 0; i < 2; ++i) w2[i] = (b1 ? w4[2 + i] : w4[i]) + dpp_f32<0x4e, 0xf, false>(b1 ? w4[i] : w4[2 + i]);
+  float w = (b0 ? w2[1] : w2[0]) + dpp_f32<0xb1, 0xf, false>(b0 ? w2[0] : w2[1]);
+  w += __shfl_xor(w, 16, 64);
+  w += __shfl_xor(w, 32, 64);
+  return w;
+}
+
 // (s, e) += x with the rounding error of the addition carried in e (two-sum).
 __device__ __forceinline__ void two_sum_acc(float &s, float &e, float x) {
 #pragma clang fp contract(off)
@@ -203,8 +224,44 @@ __device__ __forceinline__ double fsc_f64(const double *__restrict__ c9, double 
   return f;
 }
 
+// Which part of the batch a wavefront takes.  Items (crystal, tile of kSfTile
+// evaluated reflections) come heavy first: the first n_heavy items get a block
+// each, whose four wavefronts split the crystal's atoms into contiguous
+// quarters (their sums are combined in LDS in wave order); the remaining
+// items go four to a block, one per wavefront.  The wavefront index is made
+// uniform so that everything derived from the item (crystal, runs, atom
+// records) is loaded once per wave into SGPRs.
+struct WaveWork {
+  int64_t item;
+  int part, nparts;
+  bool heavy;
+};
+__device__ __forceinline__ WaveWork wave_work(int64_t n_heavy) {
+  WaveWork w;
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  w.heavy = blockIdx.x < n_heavy;
+  if (w.heavy) {
+    w.item = blockIdx.x;
+    w.part = wid;
+    w.nparts = kThreads / 64;
+  } else {
+    w.item = n_heavy + (int64_t)(blockIdx.x - n_heavy) * (kThreads / 64) + wid;
+    w.part = 0;
+    w.nparts = 1;
+  }
+  return w;
+}
+
+// Atom range [wa, wb) of a wavefront's part of crystal P.
+__device__ __forceinline__ void part_range(const CrystalPlan &P, const WaveWork &w, int *wa, int *wb) {
+  const int na = (int)(P.atom_end - P.atom_begin);
+  const int q = (na + w.nparts - 1) / w.nparts;
+  *wa = (int)P.atom_begin + min(na, w.part * q);
+  *wb = (int)P.atom_begin + min(na, (w.part + 1) * q);
+}
+
 template <bool MIXED, bool FRIEDEL>
-__global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ items, int64_t n_items,
+__global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ items, int64_t n_items, int64_t n_heavy,
                                                  const CrystalPlan *__restrict__ plan,
                                                  const int64_t *__restrict__ refl_offset,
                                                  const int16_t *__restrict__ hh, const int16_t *__restrict__ kk,
@@ -215,20 +272,18 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
                                                  const double *__restrict__ coeff, void *__restrict__ Aout,
                                                  void *__restrict__ Bout, double *__restrict__ Iout) {
   constexpr int R = kSfRpt;
-  // the wavefront index is uniform; say so, so that everything derived from
-  // the item (crystal, runs, atom records) is loaded once per wave into SGPRs
-  const int64_t item =
-      (int64_t)blockIdx.x * (kThreads / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  if (item >= n_items) return;
-  const SfItem it = items[item];
+  // heavy blocks: per wave, value (4 floats or 2 doubles), reflection slot, lane
+  __shared__ double s_part[(kThreads / 64) * 2 * R * 64];
+  const WaveWork ww = wave_work(n_heavy);
+  if (ww.item >= n_items) return;  // light blocks only: a heavy block's item always exists
+  const SfItem it = items[ww.item];
   const int64_t r0 = refl_offset[it.crystal], r1 = refl_offset[it.crystal + 1];
   const int64_t nref = r1 - r0;
   const int64_t first = FRIEDEL ? r0 + nref / 2 : r0;
   const int64_t count = FRIEDEL ? nref / 2 : nref;
   const int64_t tbase = (int64_t)it.tile * kSfTile;
-  if (tbase >= count) return;
+  if (tbase >= count) return;  // uniform over a heavy block
   const int lane = threadIdx.x & 63;
-
   int64_t idx[R];
   bool valid[R];
   double h[R], k[R], l[R], s2d[R];
@@ -244,23 +299,27 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
     s2d[u] = 0.25 * qq[idx[u]];
     s2[u] = (float)s2d[u];
   }
-
   const CrystalPlan &P = plan[it.crystal];
   const SpeciesRun *cr = runs + P.run_begin;
   const int nr = run_count[it.crystal];
+  int wa, wb;
+  part_range(P, ww, &wa, &wb);
 
+  double A[R], B[R];
   if constexpr (MIXED) {
     float Sa[R], Ea[R], Sb[R], Eb[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) Sa[u] = Ea[u] = Sb[u] = Eb[u] = 0.f;
     for (int ir = 0; ir < nr; ++ir) {
       const SpeciesRun run = cr[ir];
+      const int rb = max(run.begin, wa), re = min(run.end, wb);
+      if (rb >= re) continue;
       const double *c9 = coeff + 9 * run.species;
       float f[R];
 #pragma unroll
       for (int u = 0; u < R; ++u) f[u] = fsc_f32(c9, s2[u]);
-      for (int j0 = run.begin; j0 < run.end; j0 += kAtomTile) {
-        const int j1 = min(j0 + kAtomTile, run.end);
+      for (int j0 = rb; j0 < re; j0 += kAtomTile) {
+        const int j1 = min(j0 + kAtomTile, re);
         float pa[R], pb[R];
 #pragma unroll
         for (int u = 0; u < R; ++u) pa[u] = pb[u] = 0.f;
@@ -293,22 +352,31 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
         }
       }
     }
+    if (ww.heavy) {
+      float *sp = reinterpret_cast<float *>(s_part);
+      auto at = [&](int w, int v, int u) -> float & { return sp[((w * 4 + v) * R + u) * 64 + lane]; };
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-      if (!valid[u]) continue;
-      const double A = (double)Sa[u] + (double)Ea[u];
-      const double B = (double)Sb[u] + (double)Eb[u];
-      const double I = (A * A + B * B) * lpp[idx[u]];
-      float *Af = (float *)Aout;
-      float *Bf = (float *)Bout;
-      Af[idx[u]] = (float)A;
-      Bf[idx[u]] = (float)B;
-      Iout[idx[u]] = I;
-      if (FRIEDEL) {
-        const int64_t m = r0 + r1 - 1 - idx[u];
-        Af[m] = (float)A;
-        Bf[m] = -(float)B;
-        Iout[m] = I;
+      for (int u = 0; u < R; ++u) {
+        at(ww.part, 0, u) = Sa[u];
+        at(ww.part, 1, u) = Ea[u];
+        at(ww.part, 2, u) = Sb[u];
+        at(ww.part, 3, u) = Eb[u];
+      }
+      __syncthreads();
+      if (ww.part != 0) return;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        A[u] = B[u] = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+          A[u] += (double)at(w, 0, u) + (double)at(w, 1, u);
+          B[u] += (double)at(w, 2, u) + (double)at(w, 3, u);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        A[u] = (double)Sa[u] + (double)Ea[u];
+        B[u] = (double)Sb[u] + (double)Eb[u];
       }
     }
   } else {
@@ -317,6 +385,8 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
     for (int u = 0; u < R; ++u) Sa[u] = Sb[u] = 0.0;
     for (int ir = 0; ir < nr; ++ir) {
       const SpeciesRun run = cr[ir];
+      const int rb = max(run.begin, wa), re = min(run.end, wb);
+      if (rb >= re) continue;
       const double *c9 = coeff + 9 * run.species;
       double f[R], pa[R], pb[R];
 #pragma unroll
@@ -324,7 +394,7 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
         f[u] = fsc_f64(c9, s2d[u]);
         pa[u] = pb[u] = 0.0;
       }
-      for (int j = run.begin; j < run.end; ++j) {
+      for (int j = rb; j < re; ++j) {
         const AtomRec a = atoms[j];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
@@ -343,20 +413,55 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
         Sb[u] = fma(f[u], pb[u], Sb[u]);
       }
     }
+    if (ww.heavy) {
+      auto at = [&](int w, int v, int u) -> double & { return s_part[((w * 2 + v) * R + u) * 64 + lane]; };
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-      if (!valid[u]) continue;
-      const double A = Sa[u], B = Sb[u];
-      const double I = (A * A + B * B) * lpp[idx[u]];
+      for (int u = 0; u < R; ++u) {
+        at(ww.part, 0, u) = Sa[u];
+        at(ww.part, 1, u) = Sb[u];
+      }
+      __syncthreads();
+      if (ww.part != 0) return;
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        A[u] = B[u] = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+          A[u] += at(w, 0, u);
+          B[u] += at(w, 1, u);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        A[u] = Sa[u];
+        B[u] = Sb[u];
+      }
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < R; ++u) {
+    if (!valid[u]) continue;
+    const double I = (A[u] * A[u] + B[u] * B[u]) * lpp[idx[u]];
+    Iout[idx[u]] = I;
+    const int64_t m = r0 + r1 - 1 - idx[u];
+    if constexpr (MIXED) {
+      float *Af = (float *)Aout;
+      float *Bf = (float *)Bout;
+      Af[idx[u]] = (float)A[u];
+      Bf[idx[u]] = (float)B[u];
+      if (FRIEDEL) {
+        Af[m] = (float)A[u];
+        Bf[m] = -(float)B[u];
+        Iout[m] = I;
+      }
+    } else {
       double *Ad = (double *)Aout;
       double *Bd = (double *)Bout;
-      Ad[idx[u]] = A;
-      Bd[idx[u]] = B;
-      Iout[idx[u]] = I;
+      Ad[idx[u]] = A[u];
+      Bd[idx[u]] = B[u];
       if (FRIEDEL) {
-        const int64_t m = r0 + r1 - 1 - idx[u];
-        Ad[m] = A;
-        Bd[m] = -B;
+        Ad[m] = A[u];
+        Bd[m] = -B[u];
         Iout[m] = I;
       }
     }
@@ -401,7 +506,7 @@ __device__ __forceinline__ void fsc_df_f64(const double *__restrict__ c9, double
 }
 
 template <bool MIXED>
-__global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ items, int64_t n_items, bool friedel,
+__global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ items, int64_t n_items, int64_t n_heavy, bool friedel,
                                                     const CrystalPlan *__restrict__ plan,
                                                     const int64_t *__restrict__ refl_offset,
                                                     const int16_t *__restrict__ hh, const int16_t *__restrict__ kk,
@@ -415,12 +520,11 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
                                                     double *__restrict__ gb, double *__restrict__ dq,
                                                     double4 *__restrict__ part_fused) {
   constexpr int R = kSfRpt;
-  // the wavefront index is uniform; say so, so that everything derived from
-  // the item (crystal, runs, atom records) is loaded once per wave into SGPRs
-  const int64_t item =
-      (int64_t)blockIdx.x * (kThreads / 64) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  if (item >= n_items) return;
-  const SfItem it = items[item];
+  // heavy blocks: per wave, value (8 floats or 4 doubles), reflection slot, lane
+  __shared__ double s_part[(kThreads / 64) * 4 * R * 64];
+  const WaveWork ww = wave_work(n_heavy);
+  if (ww.item >= n_items) return;  // light blocks only
+  const SfItem it = items[ww.item];
   const int64_t r0 = refl_offset[it.crystal], r1 = refl_offset[it.crystal + 1];
   const int64_t nref = r1 - r0;
   const int64_t first = friedel ? r0 + nref / 2 : r0;
@@ -446,6 +550,8 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
   const CrystalPlan &P = plan[it.crystal];
   const SpeciesRun *cr = runs + P.run_begin;
   const int nr = run_count[it.crystal];
+  int wa, wb;
+  part_range(P, ww, &wa, &wb);
   double A[R], B[R], dA[R], dB[R];
   if constexpr (MIXED) {
     float Sa[R], Ea[R], Sb[R], Eb[R], Sda[R], Eda[R], Sdb[R], Edb[R];
@@ -453,17 +559,18 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
     for (int u = 0; u < R; ++u) Sa[u] = Ea[u] = Sb[u] = Eb[u] = Sda[u] = Eda[u] = Sdb[u] = Edb[u] = 0.f;
     for (int ir = 0; ir < nr; ++ir) {
       const SpeciesRun run = cr[ir];
+      const int rb = max(run.begin, wa), re = min(run.end, wb);
+      if (rb >= re) continue;
       const double *c9 = coeff + 9 * run.species;
       float f[R], df[R];
 #pragma unroll
       for (int u = 0; u < R; ++u) fsc_df_f32(c9, s2[u], &f[u], &df[u]);
-      for (int j0 = run.begin; j0 < run.end; j0 += kAtomTile) {
-        const int j1 = min(j0 + kAtomTile, run.end);
+      for (int j0 = rb; j0 < re; j0 += kAtomTile) {
+        const int j1 = min(j0 + kAtomTile, re);
         float pa[R], pb[R], qa[R], qb[R];
 #pragma unroll
         for (int u = 0; u < R; ++u) pa[u] = pb[u] = qa[u] = qb[u] = 0.f;
-        for (int j = j0; j < j1; ++j) {
-          const AtomRec a = atoms[j];
+        auto term = [&](const AtomRec &a) {
           const float nb = -(float)a.bfac;
 #pragma unroll
           for (int u = 0; u < R; ++u) {
@@ -478,7 +585,17 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
             qa[u] = fmaf(nb, wc, qa[u]);
             qb[u] = fmaf(nb, ws, qb[u]);
           }
+        };
+        // four records per round: their scalar loads are issued together
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+          const AtomRec a0 = atoms[j], a1 = atoms[j + 1], a2 = atoms[j + 2], a3 = atoms[j + 3];
+          term(a0);
+          term(a1);
+          term(a2);
+          term(a3);
         }
+        for (; j < j1; ++j) term(atoms[j]);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
           two_sum_acc(Sa[u], Ea[u], f[u] * pa[u]);
@@ -488,18 +605,48 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
         }
       }
     }
+    if (ww.heavy) {
+      float *sp = reinterpret_cast<float *>(s_part);
+      auto at = [&](int w, int v, int u) -> float & { return sp[((w * 8 + v) * R + u) * 64 + lane]; };
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-      A[u] = (double)Sa[u] + (double)Ea[u];
-      B[u] = (double)Sb[u] + (double)Eb[u];
-      dA[u] = (double)Sda[u] + (double)Eda[u];
-      dB[u] = (double)Sdb[u] + (double)Edb[u];
+      for (int u = 0; u < R; ++u) {
+        at(ww.part, 0, u) = Sa[u];
+        at(ww.part, 1, u) = Ea[u];
+        at(ww.part, 2, u) = Sb[u];
+        at(ww.part, 3, u) = Eb[u];
+        at(ww.part, 4, u) = Sda[u];
+        at(ww.part, 5, u) = Eda[u];
+        at(ww.part, 6, u) = Sdb[u];
+        at(ww.part, 7, u) = Edb[u];
+      }
+      __syncthreads();
+      // every wave forms the same totals, in wave order
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        A[u] = B[u] = dA[u] = dB[u] = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+          A[u] += (double)at(w, 0, u) + (double)at(w, 1, u);
+          B[u] += (double)at(w, 2, u) + (double)at(w, 3, u);
+          dA[u] += (double)at(w, 4, u) + (double)at(w, 5, u);
+          dB[u] += (double)at(w, 6, u) + (double)at(w, 7, u);
+        }
+      }
+    } else {
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        A[u] = (double)Sa[u] + (double)Ea[u];
+        B[u] = (double)Sb[u] + (double)Eb[u];
+        dA[u] = (double)Sda[u] + (double)Eda[u];
+        dB[u] = (double)Sdb[u] + (double)Edb[u];
+      }
     }
   } else {
 #pragma unroll
     for (int u = 0; u < R; ++u) A[u] = B[u] = dA[u] = dB[u] = 0.0;
     for (int ir = 0; ir < nr; ++ir) {
       const SpeciesRun run = cr[ir];
+      const int rb = max(run.begin, wa), re = min(run.end, wb);
+      if (rb >= re) continue;
       const double *c9 = coeff + 9 * run.species;
       double f[R], df[R], pa[R], pb[R], qa[R], qb[R];
 #pragma unroll
@@ -507,7 +654,7 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
         fsc_df_f64(c9, s2d[u], &f[u], &df[u]);
         pa[u] = pb[u] = qa[u] = qb[u] = 0.0;
       }
-      for (int j = run.begin; j < run.end; ++j) {
+      for (int j = rb; j < re; ++j) {
         const AtomRec a = atoms[j];
 #pragma unroll
         for (int u = 0; u < R; ++u) {
@@ -529,6 +676,27 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
         B[u] = fma(f[u], pb[u], B[u]);
         dA[u] += df[u] * pa[u] + f[u] * qa[u];
         dB[u] += df[u] * pb[u] + f[u] * qb[u];
+      }
+    }
+    if (ww.heavy) {
+      auto at = [&](int w, int v, int u) -> double & { return s_part[((w * 4 + v) * R + u) * 64 + lane]; };
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        at(ww.part, 0, u) = A[u];
+        at(ww.part, 1, u) = B[u];
+        at(ww.part, 2, u) = dA[u];
+        at(ww.part, 3, u) = dB[u];
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        A[u] = B[u] = dA[u] = dB[u] = 0.0;
+        for (int w = 0; w < kThreads / 64; ++w) {
+          A[u] += at(w, 0, u);
+          B[u] += at(w, 1, u);
+          dA[u] += at(w, 2, u);
+          dB[u] += at(w, 3, u);
+        }
       }
     }
   }
@@ -553,6 +721,7 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
     const double gI = m * w1[i];
     gA[u] = 2.0 * lp * A[u] * gI;
     gB[u] = 2.0 * lp * B[u] * gI;
+    if (ww.part != 0) continue;
     if (!P.fused) {
       ga[i] = gA[u];
       gb[i] = gB[u];
@@ -568,6 +737,7 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
   double4 *out = part_fused + P.pf_begin + (int64_t)it.tile * (P.atom_end - P.atom_begin);
   for (int ir = 0; ir < nr; ++ir) {
     const SpeciesRun run = cr[ir];
+    if (max(run.begin, wa) >= min(run.end, wb)) continue;
     const double *c9 = coeff + 9 * run.species;
     if constexpr (MIXED) {
       float f[R], fA[R], fB[R], hf[R], kf[R], lf[R];
@@ -580,28 +750,43 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
         kf[u] = (float)k[u];
         lf[u] = (float)l[u];
       }
-      for (int j = run.begin; j < run.end; ++j) {
-        const AtomRec a = atoms[j];
-        float sx = 0.f, sy = 0.f, sz = 0.f, sb = 0.f;
+      // four atoms per round: their records load together, and the 16 sums
+      // (atom q, component c at index 4q + c) are reduced in one butterfly;
+      // lane 4q + c then writes component c of atom q (records past the
+      // range's end are re-read copies of its last atom and are not written)
+      const int rb = max(run.begin, wa), re = min(run.end, wb);
+      for (int j0 = rb; j0 < re; j0 += 4) {
+        AtomRec a4[4];
 #pragma unroll
-        for (int u = 0; u < R; ++u) {
-          const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
-          const float rho = (float)__builtin_amdgcn_fract(t);
-          const float sn = __builtin_amdgcn_sinf(rho);
-          const float cs = __builtin_amdgcn_cosf(rho);
-          const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
-          const float pP = w * (fB[u] * cs - fA[u] * sn);
-          const float pQ = w * (fA[u] * cs + fB[u] * sn);
-          sx = fmaf(hf[u], pP, sx);
-          sy = fmaf(kf[u], pP, sy);
-          sz = fmaf(lf[u], pP, sz);
-          sb = fmaf(s2[u], pQ, sb);
+        for (int q = 0; q < 4; ++q) a4[q] = atoms[min(j0 + q, re - 1)];
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const AtomRec &a = a4[q];
+          float sx = 0.f, sy = 0.f, sz = 0.f, sb = 0.f;
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+            const float rho = (float)__builtin_amdgcn_fract(t);
+            const float sn = __builtin_amdgcn_sinf(rho);
+            const float cs = __builtin_amdgcn_cosf(rho);
+            const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
+            const float pP = w * (fB[u] * cs - fA[u] * sn);
+            const float pQ = w * (fA[u] * cs + fB[u] * sn);
+            sx = fmaf(hf[u], pP, sx);
+            sy = fmaf(kf[u], pP, sy);
+            sz = fmaf(lf[u], pP, sz);
+            sb = fmaf(s2[u], pQ, sb);
+          }
+          v[4 * q + 0] = sx;
+          v[4 * q + 1] = sy;
+          v[4 * q + 2] = sz;
+          v[4 * q + 3] = sb;
         }
-        sx = wave_sum_to_63(sx);
-        sy = wave_sum_to_63(sy);
-        sz = wave_sum_to_63(sz);
-        sb = wave_sum_to_63(sb);
-        if (lane == 63) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
+        const float tot = wave_reduce16(v, lane);
+        const int q = lane >> 2;
+        if (lane < 16 && j0 + q < re)
+          reinterpret_cast<double *>(out + (j0 + q - P.atom_begin))[lane & 3] = (double)tot;
       }
     } else {
       double f[R], fA[R], fB[R];
@@ -611,7 +796,7 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
         fA[u] = gA[u] * f[u];
         fB[u] = gB[u] * f[u];
       }
-      for (int j = run.begin; j < run.end; ++j) {
+      for (int j = max(run.begin, wa); j < min(run.end, wb); ++j) {
         const AtomRec a = atoms[j];
         double sx = 0.0, sy = 0.0, sz = 0.0, sb = 0.0;
 #pragma unroll
@@ -825,6 +1010,47 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw_reduce(const AbItem *__res
   dbfac[o] = -sB;
 }
 
+// dL/dG* (6 unique entries, summed over n_rows partial rows in order) ->
+// dL/d(a, b, c, alpha, beta, gamma), angles in degrees.  q = sum_ij M_ij h_i h_j
+// with M = G*, so dL/dM_ij = U_ij for i == j and U_ij / 2 for i != j (the
+// unique entry appears twice); dL/dG = -M (dL/dM) M.
+__device__ void lattice_chain(const CrystalPlan &P, const double *__restrict__ rows, int n_rows,
+                              double *__restrict__ o) {
+  double U[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = 0; k < n_rows; ++k)
+    for (int e = 0; e < 6; ++e) U[e] += rows[k * 6 + e];
+  const double M[3][3] = {{P.gs[0], P.gs[3], P.gs[4]}, {P.gs[3], P.gs[1], P.gs[5]}, {P.gs[4], P.gs[5], P.gs[2]}};
+  const double D[3][3] = {{U[0], 0.5 * U[3], 0.5 * U[4]}, {0.5 * U[3], U[1], 0.5 * U[5]}, {0.5 * U[4], 0.5 * U[5], U[2]}};
+  double T[3][3], Gb[3][3];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int m = 0; m < 3; ++m) s += D[i][m] * M[m][j];
+      T[i][j] = s;
+    }
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) {
+      double s = 0.0;
+      for (int m = 0; m < 3; ++m) s += M[i][m] * T[m][j];
+      Gb[i][j] = -s;
+    }
+  const double a = P.lat[0], b = P.lat[1], cc = P.lat[2];
+  const double rad = 3.14159265358979323846 / 180.0;
+  double sa, ca, sb, cb, sg, cg;
+  sincos(P.lat[3] * rad, &sa, &ca);
+  sincos(P.lat[4] * rad, &sb, &cb);
+  sincos(P.lat[5] * rad, &sg, &cg);
+  // G11 = a^2, G22 = b^2, G33 = c^2, G12 = ab cos(gamma), G13 = ac cos(beta), G23 = bc cos(alpha);
+  // off-diagonal entries appear twice in the full symmetric matrix.
+  const double g12 = 2.0 * Gb[0][1], g13 = 2.0 * Gb[0][2], g23 = 2.0 * Gb[1][2];
+  o[0] = Gb[0][0] * 2.0 * a + g12 * b * cg + g13 * cc * cb;
+  o[1] = Gb[1][1] * 2.0 * b + g12 * a * cg + g23 * cc * ca;
+  o[2] = Gb[2][2] * 2.0 * cc + g13 * a * cb + g23 * b * ca;
+  o[3] = g23 * (-b * cc * sa * rad);
+  o[4] = g13 * (-a * cc * sb * rad);
+  o[5] = g12 * (-a * b * sg * rad);
+}
+
 // Per adjoint chunk: sum of dL/dq (h^2, k^2, l^2, 2hk, 2hl, 2kl), fixed-order block reduction.
 __global__ __launch_bounds__(kThreads) void k_gstar_part(const int32_t *__restrict__ hchunk_crystal, bool friedel,
                                                          const CrystalPlan *__restrict__ plan,
@@ -867,7 +1093,21 @@ __global__ __launch_bounds__(kThreads) void k_gstar_part(const int32_t *__restri
   }
 }
 
+// dL/d(lattice) of every crystal from its chunk rows.
+__global__ void k_lattice_chain(const CrystalPlan *__restrict__ plan, int64_t n_c, const double *__restrict__ part6,
+                                double *__restrict__ dlat) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_c) return;
+  const CrystalPlan &P = plan[c];
+  lattice_chain(P, part6 + (int64_t)P.hchunk_begin * 6, P.n_hchunks, dlat + 6 * c);
+}
+
 }  // namespace
+
+void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s) {
+  if (n_c <= 0) return;
+  hipLaunchKernelGGL(k_lattice_chain, dim3((unsigned)((n_c + 255) / 256)), dim3(256), 0, s, plan, n_c, part6, dlat);
+}
 
 void launch_atom_prep(const CrystalPlan *plan, int64_t n_c, int32_t n_species, const double *frac,
                       const int32_t *species, const double *occ, const double *bfac, AtomRec *atoms, int32_t *orig,
@@ -877,25 +1117,25 @@ void launch_atom_prep(const CrystalPlan *plan, int64_t n_c, int32_t n_species, c
                      n_species, frac, species, occ, bfac, atoms, orig, runs, run_count, err);
 }
 
-void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
+void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, int64_t n_heavy, const CrystalPlan *plan,
                const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
                const double *coeff, void *A, void *B, double *I, hipStream_t s) {
   if (n_items <= 0) return;
-  const dim3 grid((unsigned)((n_items + 3) / 4)), block(kThreads);
+  const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4)), block(kThreads);
   if (mixed) {
     if (friedel)
-      hipLaunchKernelGGL((k_sf<true, true>), grid, block, 0, s, items, n_items, plan, refl_offset, h, k, l, q, lp,
+      hipLaunchKernelGGL((k_sf<true, true>), grid, block, 0, s, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp,
                          atoms, runs, run_count, coeff, A, B, I);
     else
-      hipLaunchKernelGGL((k_sf<true, false>), grid, block, 0, s, items, n_items, plan, refl_offset, h, k, l, q, lp,
+      hipLaunchKernelGGL((k_sf<true, false>), grid, block, 0, s, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp,
                          atoms, runs, run_count, coeff, A, B, I);
   } else {
     if (friedel)
-      hipLaunchKernelGGL((k_sf<false, true>), grid, block, 0, s, items, n_items, plan, refl_offset, h, k, l, q, lp,
+      hipLaunchKernelGGL((k_sf<false, true>), grid, block, 0, s, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp,
                          atoms, runs, run_count, coeff, A, B, I);
     else
-      hipLaunchKernelGGL((k_sf<false, false>), grid, block, 0, s, items, n_items, plan, refl_offset, h, k, l, q, lp,
+      hipLaunchKernelGGL((k_sf<false, false>), grid, block, 0, s, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp,
                          atoms, runs, run_count, coeff, A, B, I);
   }
 }
@@ -904,19 +1144,20 @@ void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, c
 
 namespace xrd {
 
-void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
+void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items, int64_t n_heavy,
+                  const CrystalPlan *plan,
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
                   const int32_t *run_count, const double *coeff, const double *w1, const double *w2, double *ga,
                   double *gb, double *dq, double *part_fused, hipStream_t s) {
   if (n_items <= 0) return;
-  const dim3 grid((unsigned)((n_items + 3) / 4)), block(kThreads);
+  const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4)), block(kThreads);
   double4 *pf = (double4 *)part_fused;
   if (mixed)
-    hipLaunchKernelGGL(k_sf_bw<true>, grid, block, 0, s, items, n_items, friedel, plan, refl_offset, h, k, l, q, lp,
+    hipLaunchKernelGGL(k_sf_bw<true>, grid, block, 0, s, items, n_items, n_heavy, friedel, plan, refl_offset, h, k, l, q, lp,
                        lambda, atoms, runs, run_count, coeff, w1, w2, ga, gb, dq, pf);
   else
-    hipLaunchKernelGGL(k_sf_bw<false>, grid, block, 0, s, items, n_items, friedel, plan, refl_offset, h, k, l, q, lp,
+    hipLaunchKernelGGL(k_sf_bw<false>, grid, block, 0, s, items, n_items, n_heavy, friedel, plan, refl_offset, h, k, l, q, lp,
                        lambda, atoms, runs, run_count, coeff, w1, w2, ga, gb, dq, pf);
 }
 

@@ -351,8 +351,18 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
         const uint64_t k = (uint64_t)__double_as_longlong(tv[u]);
         const int b = bv[u];
         const int s0 = b ? cnt[b - 1] : 0, e0 = cnt[b];
+        // buckets hold a few elements: a window of 8 independent reads, then
+        // (rarely) more
         int r = s0;
-        for (int j = s0; j < e0; ++j) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int j = s0 + q;
+          if (j < e0) {
+            const uint64_t kj = key[j];
+            r += (kj < k || (kj == k && (int)pos[j] < i)) ? 1 : 0;
+          }
+        }
+        for (int j = s0 + 8; j < e0; ++j) {
           const uint64_t kj = key[j];
           r += (kj < k || (kj == k && (int)pos[j] < i)) ? 1 : 0;
         }

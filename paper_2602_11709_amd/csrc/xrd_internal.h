@@ -22,6 +22,7 @@ constexpr int kAtomBlock = 256;   // atoms per adjoint block
 constexpr int kSfRpt = 2;         // reflections per lane in the structure-factor kernels
 constexpr int kSfTile = 64 * kSfRpt;
 constexpr int kFusedMaxAtoms = 512;  // crystals up to this size take the fused atom-gradient path
+constexpr int kSplitAtoms = 24;      // crystals from this size get a block per structure-factor tile
 constexpr int kSmallSort = 4096;     // reflections sorted in LDS by one 256-thread block
 constexpr int kMidSort = 12288;      // reflections sorted in LDS by one 1024-thread block
 constexpr int kSpanPts = 64;         // grid points per wave of the broadening gather
@@ -114,7 +115,9 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk
 void launch_atom_prep(const CrystalPlan *plan, int64_t n_c, int32_t n_species, const double *frac,
                       const int32_t *species, const double *occ, const double *bfac, AtomRec *atoms, int32_t *orig,
                       SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s);
-void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
+// Items: the first n_heavy take a block each (atoms split over its four
+// wavefronts), the rest one wavefront each.
+void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, int64_t n_heavy, const CrystalPlan *plan,
                const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
                const double *coeff, void *A, void *B, double *I, hipStream_t s);
@@ -173,8 +176,8 @@ void launch_broaden_adj(bool mixed, const int32_t *hchunk_crystal, int64_t n_hch
                         bool friedel, const int64_t *refl_offset, const double *ent_key, const int32_t *ent_idx,
                         const double *dy, double t0, double dt, int64_t n, double sigma, double window, double *w1,
                         double *w2, hipStream_t s);
-void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s);
-void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items, const CrystalPlan *plan,
+void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items, int64_t n_heavy,
+                  const CrystalPlan *plan,
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
                   const int32_t *run_count, const double *coeff, const double *w1, const double *w2, double *ga,
@@ -188,8 +191,10 @@ void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_ite
 void launch_atom_bw_reduce(const AbItem *items, int64_t n_items, bool friedel, const CrystalPlan *plan,
                            const int64_t *refl_offset, const double *part, const double *part_fused,
                            const int32_t *orig, double *dfrac, double *dbfac, hipStream_t s);
+// Per-chunk dL/dG* rows, then the chain rule to dL/d(lattice) per crystal.
 void launch_gstar_part(const int32_t *hchunk_crystal, int64_t n_hchunks, bool friedel, const CrystalPlan *plan,
                        const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
                        const double *dq, double *part6, hipStream_t s);
+void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s);
 
 }  // namespace xrd
