@@ -33,7 +33,7 @@ struct xrd_batch {
   std::vector<BwItem> bw_items;
   std::vector<AbItem> ab_items;
   int64_t n_atoms = 0, refl_cap = 0, half_cap = 0, n_bins = 0, run_cap = 0, part_rows = 0, partf_rows = 0;
-  int64_t n_mid = 0;      // crystals whose reflection capacity exceeds kSmallSort
+  int64_t n_mid = 0;      // crystals whose reflection capacity exceeds 2 kSmallSort
   int64_t sf_heavy = 0;   // leading structure-factor items that take a block each
   int64_t grid_cap = 0;   // largest grid of a broadened-pattern call
   int64_t span_cap = 0;   // span-table entries per crystal: ceil(grid_cap / kSpanPts)
@@ -204,7 +204,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     }
     P.half_box = (box - 1) / 2;
     refl += 2 * P.half_box;
-    if (2 * P.half_box > kSmallSort) ++b->n_mid;
+    if (P.half_box > kSmallSort) ++b->n_mid;  // more than 2 kSmallSort reflections possible
     if (refl >= ((int64_t)1 << 31) - 1) {
       delete b;
       return fail(XRD_ERR_CAPACITY, "reflection capacity exceeds 2^31; split the batch");

@@ -130,19 +130,20 @@ __device__ void finish_crystal(const MergeOut &mo, int64_t c, int64_t r0, int np
   }
 }
 
-// Sort (and merge) of one crystal per block.  Crystals of at most CAP
-// reflections are sorted in LDS: R/2 exactly monotone buckets, count with LDS
-// atomics, scan, scatter with LDS atomics, then an insertion sort of each
-// bucket on (2theta bits, position).  The input is in lexicographic (h, k, l)
-// order, so ordering ties by position orders them by (h, k, l); positive
+// Sort (and merge) of one crystal per block.  Crystals of at most 2 CAP
+// reflections are sorted in LDS by their Friedel-positive half (the mates
+// follow from it exactly): H/2 exactly monotone buckets, count with LDS
+// atomics, scan, scatter with LDS atomics, then each element's rank within
+// its bucket on (2theta bits, index).  The input is in lexicographic (h, k, l)
+// order, so ordering ties by index orders them by (h, k, l); positive
 // doubles order like their bit patterns.  Two sizes are launched: CAP 4096
 // (256 threads, one block per crystal, ~48 KB of LDS) and CAP 12288 (512
 // threads, 144 KB of LDS, which gfx950 provides per workgroup; at most one
-// block per CU walking the crystals whose capacity exceeds 4096), which also
-// sorts the crystals beyond 12288 reflections, with the capacity-sized buckets
-// of the plan kept in global memory and the same steps (an insertion sort
-// within buckets there).  Crystals are taken in ``order``, heaviest first;
-// the first n_c of them are the kernel's.
+// block per CU walking the crystals whose capacity exceeds 8192), which also
+// sorts the crystals beyond 24576 reflections, all R of them, with the
+// capacity-sized buckets of the plan kept in global memory and an insertion
+// sort within buckets.  Crystals are taken in ``order``, heaviest first; the
+// first n_c of them are the kernel's.
 //
 // Outputs: skey/sidx, the crystal's 2theta keys and global reflection indices
 // in sorted order; with Friedel pairing (ent_key non-null), the entries of the
@@ -173,11 +174,11 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
       mo.pk_count[c] = 0;
       mo.cmax[c] = 0;
     }
-    if (R64 <= (LARGE ? kSmallSort : 0) || (!LARGE && R64 > CAP)) continue;
+    if (R64 <= (LARGE ? 2 * kSmallSort : 0) || (!LARGE && R64 > 2 * CAP)) continue;
     const int64_t e_base = r0 / 2;
     const CrystalPlan &P = plan[c];
     int total;
-    if (LARGE && R64 > CAP) {
+    if (LARGE && R64 > 2 * CAP) {
       // ---- global-memory path for the largest crystals ----
       const int64_t nb = P.n_bins;
       int32_t *__restrict__ bc = bin_count + P.bin_begin;
@@ -285,9 +286,15 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
       __syncthreads();
       continue;
     }
-    // ---- LDS path ----
+    // ---- LDS path: sort the evaluated half, expand to the full order ----
+    // Positives (local index H + i, i < H) and their mates (local H - 1 - i)
+    // share 2theta bit for bit.  Sort the H positives by (2theta, i); a run of
+    // equal keys [a, b] then expands, in (2theta, h, k, l) order, to the mates
+    // of b, b-1, .., a (their local indices ascend that way) followed by the
+    // positives a, .., b: full slots 2a + (b - j) and b + 1 + j for entry j.
     const int R = (int)R64;
-    const int B = R / 2 > 1 ? R / 2 : 1;
+    const int H = R / 2;
+    const int B = H / 2 > 1 ? H / 2 : 1;
     const double scale = (double)B / (P.tmax - P.tmin);
     constexpr int PER = CAP / T;
     for (int b = threadIdx.x; b < B; b += T) cnt[b] = 0;
@@ -297,7 +304,7 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = u * T + threadIdx.x;
-      tv[u] = i < R ? tt[r0 + i] : P.tmin;
+      tv[u] = i < H ? tt[r0 + H + i] : P.tmin;
     }
     __syncthreads();
 #pragma unroll
@@ -306,7 +313,7 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
       const int i = u * T + threadIdx.x;
       const double x = floor((tv[u] - P.tmin) * scale);
       bv[u] = x < 0.0 ? 0 : (x >= (double)(B - 1) ? B - 1 : (int)x);
-      if (i < R) atomicAdd(&cnt[bv[u]], 1);
+      if (i < H) atomicAdd(&cnt[bv[u]], 1);
     }
     __syncthreads();
     // exclusive scan of the bucket counts: each thread owns a contiguous run
@@ -330,7 +337,7 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = u * T + threadIdx.x;
-      if (i < R) {
+      if (i < H) {
         const int slot = atomicAdd(&cnt[bv[u]], 1);
         key[slot] = (uint64_t)__double_as_longlong(tv[u]);
         pos[slot] = (uint16_t)i;
@@ -339,7 +346,7 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
     __syncthreads();
     // cnt[b] is now the end of bucket b, and its start is the end of bucket b - 1.
     // Order within buckets: every element counts the members of its bucket
-    // that precede it in (2theta bits, position), all elements at once; then
+    // that precede it in (2theta bits, index), all elements at once; then
     // each moves to its rank (all reads happen before the barrier, and the
     // ranks of a bucket are a permutation of its slots).
     int rk[PER];
@@ -347,22 +354,11 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
     for (int u = 0; u < PER; ++u) {
       const int i = u * T + threadIdx.x;
       rk[u] = 0;
-      if (i < R) {
+      if (i < H) {
         const uint64_t k = (uint64_t)__double_as_longlong(tv[u]);
         const int b = bv[u];
-        const int s0 = b ? cnt[b - 1] : 0, e0 = cnt[b];
-        // buckets hold a few elements: a window of 8 independent reads, then
-        // (rarely) more
-        int r = s0;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int j = s0 + q;
-          if (j < e0) {
-            const uint64_t kj = key[j];
-            r += (kj < k || (kj == k && (int)pos[j] < i)) ? 1 : 0;
-          }
-        }
-        for (int j = s0 + 8; j < e0; ++j) {
+        int r = b ? cnt[b - 1] : 0;
+        for (int j = r, e0 = cnt[b]; j < e0; ++j) {
           const uint64_t kj = key[j];
           r += (kj < k || (kj == k && (int)pos[j] < i)) ? 1 : 0;
         }
@@ -373,94 +369,101 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = u * T + threadIdx.x;
-      if (i < R) {
+      if (i < H) {
         key[rk[u]] = (uint64_t)__double_as_longlong(tv[u]);
         pos[rk[u]] = (uint16_t)i;
       }
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < R; i += T) {
-      skey[r0 + i] = __longlong_as_double((long long)key[i]);
-      sidx[r0 + i] = (int32_t)(r0 + pos[i]);
-      if (merge) mo.perm[r0 + i] = r0 + pos[i];
-    }
-    // each thread owns a contiguous run of PER sorted positions below
-    const int i0 = threadIdx.x * PER;
-    if (ent_key) {
-      // evaluated half in sorted order
-      const int half = R / 2;
-      int n = 0;
-#pragma unroll
-      for (int u = 0; u < PER; ++u) n += (i0 + u < R && pos[i0 + u] >= half) ? 1 : 0;
-      int e = block_exclusive_scan<T>(n, wsum, &total);
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int i = i0 + u;
-        if (i < R && pos[i] >= half) {
-          ent_key[e_base + e] = __longlong_as_double((long long)key[i]);
-          ent_idx[e_base + e] = (int32_t)(r0 + pos[i]);
-          ++e;
-        }
+    // entries (the evaluated half in 2theta order) and the expanded full order
+    for (int j = threadIdx.x; j < H; j += T) {
+      const uint64_t kj = key[j];
+      const double tj = __longlong_as_double((long long)kj);
+      const int p = pos[j];
+      if (ent_key) {
+        ent_key[e_base + j] = tj;
+        ent_idx[e_base + j] = (int32_t)(r0 + H + p);
+      }
+      int ga = j, gb = j;
+      while (ga > 0 && key[ga - 1] == kj) --ga;
+      while (gb + 1 < H && key[gb + 1] == kj) ++gb;
+      const int fm = 2 * ga + (gb - j), fp = gb + 1 + j;
+      const int64_t im = r0 + H - 1 - p, ip = r0 + H + p;
+      skey[r0 + fm] = tj;
+      sidx[r0 + fm] = (int32_t)im;
+      skey[r0 + fp] = tj;
+      sidx[r0 + fp] = (int32_t)ip;
+      if (merge) {
+        mo.perm[r0 + fm] = im;
+        mo.perm[r0 + fp] = ip;
       }
     }
     if (merge) {
 #pragma clang fp contract(off)
-      // peak-start flags (one byte per position, in the bucket table's space)
-      for (int i = threadIdx.x; i < R; i += T) {
-        const double ti = __longlong_as_double((long long)key[i]);
-        if (i == 0 || ti - __longlong_as_double((long long)key[i - 1]) >= mo.tol) {
-          fl[i] = 1;
-          double anchor = ti, prev = ti;
-          for (int j = i + 1; j < R; ++j) {
-            const double tj = __longlong_as_double((long long)key[j]);
-            if (tj - prev >= mo.tol) break;
-            const bool open = (tj - anchor) >= mo.tol;
-            fl[j] = open ? 1 : 0;
-            if (open) anchor = tj;
-            prev = tj;
+      // peak-start flags on the half (one byte per entry, in the bucket
+      // table's space): mates never change the anchor walk, having the same
+      // 2theta as their partner, and a peak start always begins a key run
+      for (int j = threadIdx.x; j < H; j += T) {
+        const double tj = __longlong_as_double((long long)key[j]);
+        if (j == 0 || tj - __longlong_as_double((long long)key[j - 1]) >= mo.tol) {
+          fl[j] = 1;
+          double anchor = tj, prev = tj;
+          for (int m = j + 1; m < H; ++m) {
+            const double tm = __longlong_as_double((long long)key[m]);
+            if (tm - prev >= mo.tol) break;
+            const bool open = (tm - anchor) >= mo.tol;
+            fl[m] = open ? 1 : 0;
+            if (open) anchor = tm;
+            prev = tm;
           }
         }
       }
       __syncthreads();
+      // each thread owns a contiguous run of PER entries
+      const int i0 = threadIdx.x * PER;
       int ns = 0;
 #pragma unroll
-      for (int u = 0; u < PER; ++u) ns += (i0 + u < R && fl[i0 + u]) ? 1 : 0;
+      for (int u = 0; u < PER; ++u) ns += (i0 + u < H && fl[i0 + u]) ? 1 : 0;
       int p = block_exclusive_scan<T>(ns, wsum, &total);
       const int np = total;
-      // the run's intensities, loaded at once; a peak still open at the end
-      // of the run continues into the next runs
+      // the run's intensities (an entry and its mate), loaded at once; a peak
+      // still open at the end of the run continues into the next runs
       double iv[PER];
 #pragma unroll
-      for (int u = 0; u < PER; ++u) iv[u] = i0 + u < R ? mo.inten[r0 + pos[i0 + u]] : 0.0;
+      for (int u = 0; u < PER; ++u) {
+        const int q = i0 + u < H ? pos[i0 + u] : 0;
+        iv[u] = i0 + u < H ? mo.inten[r0 + H - 1 - q] + mo.inten[r0 + H + q] : 0.0;
+      }
       double mx = 0.0, sum = 0.0;
       int m = 0, start = -1;
       auto emit = [&]() {
         mo.t_tt[r0 + p] = __longlong_as_double((long long)key[start]);
         mo.t_i[r0 + p] = sum;
         mo.t_mult[r0 + p] = m;
-        mo.t_first[r0 + p] = r0 + start;
+        mo.t_first[r0 + p] = r0 + 2 * start;
         mx = fmax(mx, sum);
         ++p;
       };
 #pragma unroll
       for (int u = 0; u < PER; ++u) {
         const int i = i0 + u;
-        if (i < R) {
+        if (i < H) {
           if (fl[i]) {
             if (start >= 0) emit();
             start = i;
             sum = iv[u];
-            m = 1;
+            m = 2;
           } else if (start >= 0) {
             sum += iv[u];
-            ++m;
+            m += 2;
           }
         }
       }
       if (start >= 0) {
-        for (int j = i0 + PER; j < R && !fl[j]; ++j) {
-          sum += mo.inten[r0 + pos[j]];
-          ++m;
+        for (int j = i0 + PER; j < H && !fl[j]; ++j) {
+          const int q = pos[j];
+          sum += mo.inten[r0 + H - 1 - q] + mo.inten[r0 + H + q];
+          m += 2;
         }
         emit();
       }

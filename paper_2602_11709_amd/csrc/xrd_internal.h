@@ -23,8 +23,8 @@ constexpr int kSfRpt = 2;         // reflections per lane in the structure-facto
 constexpr int kSfTile = 64 * kSfRpt;
 constexpr int kFusedMaxAtoms = 512;  // crystals up to this size take the fused atom-gradient path
 constexpr int kSplitAtoms = 24;      // crystals from this size get a block per structure-factor tile
-constexpr int kSmallSort = 4096;     // reflections sorted in LDS by one 256-thread block
-constexpr int kMidSort = 12288;      // reflections sorted in LDS by one 1024-thread block
+constexpr int kSmallSort = 4096;     // Friedel-positive reflections sorted in LDS by one 256-thread block
+constexpr int kMidSort = 12288;      // ... by one 512-thread block
 constexpr int kSpanPts = 64;         // grid points per wave of the broadening gather
 
 // Per-crystal plan (device copy in the workspace), 256 bytes.
@@ -137,7 +137,7 @@ struct SortArgs {
   int32_t *sidx;
   int64_t *scan_part;
   const int32_t *order;  // [n_c] crystals by descending capacity
-  int64_t n_mid;         // leading entries of ``order`` with capacity above kSmallSort
+  int64_t n_mid;         // leading entries of ``order`` with capacity above 2 kSmallSort
   int32_t friedel;       // write the evaluated-half entries below
   double *ent_key;       // [half capacity] 2theta of the evaluated half, sorted per crystal
   int32_t *ent_idx;      // its global reflection indices
