@@ -40,10 +40,12 @@ N_CU = 256
 # lane-operations per CU per clock on gfx950 (measured with microbenchmarks
 # at 78% / 89% / 88-94% of these): FP32 VALU, FP64 VALU, transcendental
 RATE_F32, RATE_F64, RATE_TRANS = 128.0, 64.0, 32.0
-# per structure-factor term of the mixed kernel: phase h.x (3 FP64 FMA),
-# reduction mod 1 and conversion (2 FP64-rate ops), sin + cos + exp
-# (3 transcendental), weight exponent and two multiply-adds (3 FP32)
-TERM_OPS = dict(f64=5, trans=3, f32=3)
+# per structure-factor term of the mixed kernel as the step runs it (keeping
+# dF/ds^2 for the adjoint): phase h.x (3 FP64 FMA), reduction mod 1 and
+# conversion (2 FP64-rate ops), sin + cos + exp (3 transcendental), weight
+# exponent and two multiply-adds for F, one product and two multiply-adds for
+# dF/ds^2 (6 FP32)
+TERM_OPS = dict(f64=5, trans=3, f32=6)
 
 
 def term_peak_per_s():
@@ -86,7 +88,8 @@ class Pipeline:
         self.stream = torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
             t0 = time.perf_counter()
-            self.xb = XrdBatch(batch, precision=precision)
+            # the step differentiates the pattern: the forward keeps dF/ds^2
+            self.xb = XrdBatch(batch, precision=precision, keep_sf_derivs=True)
             self.plan_ms = (time.perf_counter() - t0) * 1e3
             xb = self.xb
             self.refl = xb.new_reflections()
@@ -277,7 +280,7 @@ def main():
         "stages_ms": mx["stages"],
         "host_plan_ms": round(mx["p"].plan_ms, 3),
         "roofline": {
-            "kernel": "k_sf (mixed, Friedel-halved)",
+            "kernel": "k_sf (mixed, Friedel-halved, keeping dF/ds^2)",
             "bound": "alu",
             "achieved": round(achieved / 1e9, 3),
             "peak": round(peak / 1e9, 3),

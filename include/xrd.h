@@ -78,6 +78,14 @@ typedef struct {
                                      the conjugate to its mate; 0: evaluate every reflection */
     int32_t grid_capacity;        /* largest n_points a broadened-pattern call on this batch
                                      will use; 0 selects 16384.  Sizes the workspace. */
+    int32_t keep_sf_derivs;       /* 1: xrd_structure_factors also keeps dF/d(s^2) of the
+                                     evaluated reflections in the workspace, and the next
+                                     xrd_pattern_backward on the same enumeration, workspace and
+                                     reflection arrays takes them from there instead of summing
+                                     over the atoms again (forward and adjoint of the pattern
+                                     share one pass over the atoms); 0: it does not.  Either way
+                                     the results are the same up to rounding. */
+    int32_t reserved;             /* set to 0 */
     const double *frac;           /* DEVICE [N*3]: fractional x, y, z per atom */
     const int32_t *species;       /* DEVICE [N]: row of sf_coeff, 0 <= species < n_species */
     const double *occ;            /* DEVICE [N]: occupancy, >= 0 */

@@ -77,12 +77,15 @@ class XrdBatch:
     ``frac``/``bfac`` may be given as device tensors (float64) to override
     the batch's arrays (the differentiable path does this).
     ``grid_capacity`` bounds the grid of broadened-pattern calls (0: 16384
-    points)."""
+    points).  With ``keep_sf_derivs`` the structure-factor call also keeps
+    dF/d(s^2) for a following ``pattern_backward`` on the same reflections,
+    which then skips its own pass over the atoms."""
 
     def __init__(self, batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
                  rel_threshold: float = 0.0, device="cuda", frac: Optional[torch.Tensor] = None,
                  bfac: Optional[torch.Tensor] = None, lattice: Optional[np.ndarray] = None,
-                 two_theta_range: Optional[tuple] = None, grid_capacity: int = 0):
+                 two_theta_range: Optional[tuple] = None, grid_capacity: int = 0,
+                 keep_sf_derivs: bool = False):
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         self.device = torch.device(device)
@@ -120,6 +123,7 @@ class XrdBatch:
         d.rel_threshold = rel_threshold
         d.friedel = 1 if self.friedel else 0
         d.grid_capacity = int(grid_capacity)
+        d.keep_sf_derivs = 1 if keep_sf_derivs else 0
         d.frac = _p(self.frac) if batch.n_atoms else None
         d.species = _p(self.species) if batch.n_atoms else None
         d.occ = _p(self.occ) if batch.n_atoms else None
@@ -279,7 +283,7 @@ class _PatternFn(torch.autograd.Function):
         xb = XrdBatch(spec["batch"], precision=spec["precision"], friedel=spec["friedel"], device=frac.device,
                       frac=frac.detach().to(torch.float64).contiguous(),
                       bfac=bfac.detach().to(torch.float64).contiguous(), lattice=lat,
-                      grid_capacity=spec["grid"].n_points)
+                      grid_capacity=spec["grid"].n_points, keep_sf_derivs=any(ctx.needs_input_grad[:3]))
         refl = xb.enumerate()
         _, _, I = xb.structure_factors(refl)
         y = xb.pattern_forward(refl, I, spec["grid"])

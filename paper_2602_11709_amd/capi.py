@@ -32,6 +32,7 @@ class xrd_batch_desc(C.Structure):
         ("lattice", _vp), ("atom_offset", _vp), ("two_theta_min", _vp), ("two_theta_max", _vp),
         ("wavelength", C.c_double), ("merge_tol", C.c_double), ("rel_threshold", C.c_double),
         ("friedel", C.c_int32), ("grid_capacity", C.c_int32),
+        ("keep_sf_derivs", C.c_int32), ("reserved", C.c_int32),
         ("frac", _vp), ("species", _vp), ("occ", _vp), ("bfac", _vp), ("sf_coeff", _vp),
         ("stream", _vp),
     ]

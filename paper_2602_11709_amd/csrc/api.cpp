@@ -45,6 +45,10 @@ struct xrd_batch {
   // a captured graph replays the same decision)
   const void *sorted_ws = nullptr;
   const double *sorted_tt = nullptr;
+  // derivatives kept by the last structure-factor call (keep_sf_derivs): the
+  // workspace and reflection arrays they belong to; cleared by enumeration
+  const void *deriv_ws = nullptr;
+  const int16_t *deriv_h = nullptr;
 };
 
 namespace {
@@ -138,6 +142,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   if (!(d->rel_threshold >= 0.0) || !std::isfinite(d->rel_threshold))
     return fail(XRD_ERR_INVALID_ARG, "rel_threshold must be >= 0");
   if (d->grid_capacity < 0) return fail(XRD_ERR_INVALID_ARG, "grid_capacity < 0");
+  if (d->keep_sf_derivs != 0 && d->keep_sf_derivs != 1)
+    return fail(XRD_ERR_INVALID_ARG, "keep_sf_derivs must be 0 or 1");
   if (nc > 0 && (!d->lattice || !d->atom_offset || !d->two_theta_min || !d->two_theta_max))
     return fail(XRD_ERR_INVALID_ARG, "host arrays must be non-NULL");
   if (!d->sf_coeff) return fail(XRD_ERR_INVALID_ARG, "sf_coeff is NULL");
@@ -353,6 +359,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.bw_part = take(32 * parts);
   L.bw_partf = take(32 * pfused);
   L.bw_part6 = take(48 * hc);
+  L.sf_deriv = d->keep_sf_derivs ? take((d->precision == XRD_MIXED ? 16 : 32) * rc) : -1;
   L.total = o;
   *out = b;
   g_err.clear();
@@ -408,6 +415,8 @@ int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r) {
   pack_atoms(b, ws);
   b->sorted_ws = nullptr;
   b->sorted_tt = nullptr;
+  b->deriv_ws = nullptr;
+  b->deriv_h = nullptr;
   launch_enumerate(at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, at<int32_t>(ws, L.enum_chunk_crystal),
                    (int64_t)b->enum_chunk_crystal.size(), b->desc.wavelength, at<int32_t>(ws, L.enum_count),
                    at<int64_t>(ws, L.enum_prefix), at<int64_t>(ws, L.scan_part), r->h, r->k, r->l, r->q,
@@ -430,10 +439,13 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
   if (int e = check_refl(r)) return e;
   if (!A || !B || !I) return fail(XRD_ERR_INVALID_ARG, "A, B and I must be non-NULL");
   const WsLayout &L = b->ws;
+  void *deriv = L.sf_deriv >= 0 ? at<char>(ws, L.sf_deriv) : nullptr;
   launch_sf(b->desc.precision == XRD_MIXED, b->desc.friedel != 0, at<SfItem>(ws, L.sf_items),
             (int64_t)b->sf_items.size(), b->sf_heavy, at<CrystalPlan>(ws, L.plan), r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
             at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), b->desc.sf_coeff, A, B,
-            I, stream_of(b));
+            I, deriv, stream_of(b));
+  b->deriv_ws = deriv ? ws : nullptr;
+  b->deriv_h = deriv ? r->h : nullptr;
   b->last_ws = ws;
   return hip_check("structure_factors");
 }
@@ -560,12 +572,13 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   double *w1 = at<double>(ws, L.bw_w1), *w2 = at<double>(ws, L.bw_w2);
   double *ga = at<double>(ws, L.bw_ga), *gb = at<double>(ws, L.bw_gb), *dq = at<double>(ws, L.bw_dq);
   ensure_sorted(b, ws, r);
+  const void *deriv = (L.sf_deriv >= 0 && b->deriv_ws == ws && b->deriv_h == r->h) ? at<char>(ws, L.sf_deriv) : nullptr;
   launch_broaden_adj(mixed, at<int32_t>(ws, L.hchunk_crystal), (int64_t)b->hchunk_crystal.size(), plan, friedel,
                      r->refl_offset, at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), dL_dy, g->t0, g->dt,
                      g->n_points, g->sigma, g->window_sigmas, w1, w2, s);
   launch_sf_bw(mixed, friedel, items, n_items, b->sf_heavy, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
                b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
-               b->desc.sf_coeff, w1, w2, ga, gb, dq, at<double>(ws, L.bw_partf), s);
+               b->desc.sf_coeff, deriv, w1, w2, ga, gb, dq, at<double>(ws, L.bw_partf), s);
   launch_atom_bw(mixed, friedel, at<BwItem>(ws, L.bw_items), (int64_t)b->bw_items.size(), plan, r->refl_offset,
                  r->h, r->k, r->l, r->q, ga, gb, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
                  at<int32_t>(ws, L.run_count), b->desc.sf_coeff, b->bw_tile, b->runs_cap_max,

@@ -30,7 +30,7 @@ namespace {
 constexpr double kPi = 3.14159265358979323846;
 
 struct GridArgs {
-  double t0, dt, sigma, half, norm, inv2s2;
+  double t0, dt, inv_dt, sigma, half, norm, inv2s2;
   int64_t n;
 };
 
@@ -39,9 +39,10 @@ struct GridArgs {
 // is monotone in g).  Empty when lo > hi.
 __device__ __forceinline__ void window_of(const GridArgs &g, double t, int64_t *lo, int64_t *hi) {
 #pragma clang fp contract(off)
-  int64_t a = (int64_t)ceil((t - g.half - g.t0) / g.dt);
-  int64_t b = (int64_t)floor((t + g.half - g.t0) / g.dt);
-  // the estimates are off by at most one step either way; settle them with the exact test
+  int64_t a = (int64_t)ceil((t - g.half - g.t0) * g.inv_dt);
+  int64_t b = (int64_t)floor((t + g.half - g.t0) * g.inv_dt);
+  // the estimates (a product with the rounded reciprocal) are off by at most
+  // one step either way; settle them with the exact test
   while (a > 0 && fabs(g.t0 + (double)(a - 1) * g.dt - t) <= g.half) --a;
   while (a <= b && fabs(g.t0 + (double)a * g.dt - t) > g.half) ++a;
   while (b + 1 < g.n && fabs(g.t0 + (double)(b + 1) * g.dt - t) <= g.half) ++b;
@@ -366,6 +367,7 @@ GridArgs make_grid(double t0, double dt, int64_t n, double sigma, double window)
   GridArgs g;
   g.t0 = t0;
   g.dt = dt;
+  g.inv_dt = 1.0 / dt;
   g.n = n;
   g.sigma = sigma;
   g.half = window * sigma;

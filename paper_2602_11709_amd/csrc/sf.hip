@@ -260,7 +260,257 @@ __device__ __forceinline__ void part_range(const CrystalPlan &P, const WaveWork 
   *wb = (int)P.atom_begin + min(na, (w.part + 1) * q);
 }
 
-template <bool MIXED, bool FRIEDEL>
+// d f / d(s^2) alongside f (single and double precision).
+__device__ __forceinline__ void fsc_df_f32(const double *__restrict__ c9, float s2, float *f, float *df) {
+  float a = (float)c9[8], d = 0.f;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const float ai = (float)c9[i], bi = (float)c9[4 + i];
+    const float e = __builtin_amdgcn_exp2f(-bi * kLog2e * s2);
+    a = fmaf(ai, e, a);
+    d = fmaf(-ai * bi, e, d);
+  }
+  *f = a;
+  *df = d;
+}
+
+__device__ __forceinline__ void fsc_df_f64(const double *__restrict__ c9, double s2, double *f, double *df) {
+  double a = c9[8], d = 0.0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double e = exp(-c9[4 + i] * s2);
+    a = fma(c9[i], e, a);
+    d = fma(-c9[i] * c9[4 + i], e, d);
+  }
+  *f = a;
+  *df = d;
+}
+
+// One tile's reflections (R per lane) summed over a wavefront's atom range
+// [wa, wb) of crystal runs cr[0, nr):
+//   A + iB = sum_t f_t S_t,                 S_t  = sum_{j in t} occ_j e^{-B_j s^2} e^{i phi_j}
+// and with DERIV also
+//   d(A + iB)/ds^2 = sum_t (f'_t S_t + f_t S'_t),  S'_t = sum_{j in t} (-B_j) occ_j e^{-B_j s^2} e^{i phi_j}
+// with f'_t = -sum_i a_i b_i e^{-b_i s^2} (t runs over species).  A and B take
+// the same operations with or without DERIV, so keeping the derivatives does
+// not change the structure factors.  Heavy items: the four wavefronts' sums
+// meet in LDS (s_part) and are added in wave order; returns false for the
+// waves that hold no totals afterwards (all but wave 0 unless all_waves).
+template <bool MIXED, bool DERIV>
+__device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const SpeciesRun *__restrict__ cr, int nr,
+                                             int wa, int wb, const AtomRec *__restrict__ atoms,
+                                             const double *__restrict__ coeff, const double (&h)[kSfRpt],
+                                             const double (&k)[kSfRpt], const double (&l)[kSfRpt],
+                                             const double (&s2d)[kSfRpt], const float (&s2)[kSfRpt],
+                                             double *s_part, bool all_waves, double (&A)[kSfRpt],
+                                             double (&B)[kSfRpt], double (&dA)[kSfRpt], double (&dB)[kSfRpt]) {
+  constexpr int R = kSfRpt;
+  if constexpr (MIXED) {
+    // per reflection: (sum, error) pairs of A, B and, with DERIV, dA, dB
+    constexpr int V = DERIV ? 8 : 4;
+    float acc[V][R];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int u = 0; u < R; ++u) acc[v][u] = 0.f;
+    for (int ir = 0; ir < nr; ++ir) {
+      const SpeciesRun run = cr[ir];
+      const int rb = max(run.begin, wa), re = min(run.end, wb);
+      if (rb >= re) continue;
+      const double *c9 = coeff + 9 * run.species;
+      float f[R], df[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        if constexpr (DERIV)
+          fsc_df_f32(c9, s2[u], &f[u], &df[u]);
+        else
+          f[u] = fsc_f32(c9, s2[u]);
+      }
+      for (int j0 = rb; j0 < re; j0 += kAtomTile) {
+        const int j1 = min(j0 + kAtomTile, re);
+        float pa[R], pb[R], qa[R], qb[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) pa[u] = pb[u] = qa[u] = qb[u] = 0.f;
+        auto term = [&](const AtomRec &a) {
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+            const float rho = (float)__builtin_amdgcn_fract(t);
+            const float sn = __builtin_amdgcn_sinf(rho);
+            const float cs = __builtin_amdgcn_cosf(rho);
+            const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
+            pa[u] = fmaf(w, cs, pa[u]);
+            pb[u] = fmaf(w, sn, pb[u]);
+            if constexpr (DERIV) {
+              const float nbw = -(float)a.bfac * w;
+              qa[u] = fmaf(nbw, cs, qa[u]);
+              qb[u] = fmaf(nbw, sn, qb[u]);
+            }
+          }
+        };
+        // four records per round: their scalar loads are issued together
+        int j = j0;
+        for (; j + 4 <= j1; j += 4) {
+          const AtomRec a0 = atoms[j], a1 = atoms[j + 1], a2 = atoms[j + 2], a3 = atoms[j + 3];
+          term(a0);
+          term(a1);
+          term(a2);
+          term(a3);
+        }
+        for (; j < j1; ++j) term(atoms[j]);
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          two_sum_acc(acc[0][u], acc[1][u], f[u] * pa[u]);
+          two_sum_acc(acc[2][u], acc[3][u], f[u] * pb[u]);
+          if constexpr (DERIV) {
+            two_sum_acc(acc[4][u], acc[5][u], fmaf(df[u], pa[u], f[u] * qa[u]));
+            two_sum_acc(acc[6][u], acc[7][u], fmaf(df[u], pb[u], f[u] * qb[u]));
+          }
+        }
+      }
+    }
+    double tot[V / 2][R];
+    if (ww.heavy) {
+      float *sp = reinterpret_cast<float *>(s_part);
+      auto at = [&](int w, int v, int u) -> float & { return sp[((w * V + v) * R + u) * 64 + lane]; };
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int u = 0; u < R; ++u) at(ww.part, v, u) = acc[v][u];
+      __syncthreads();
+      if (!all_waves && ww.part != 0) return false;
+#pragma unroll
+      for (int v = 0; v < V / 2; ++v)
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          tot[v][u] = 0.0;
+          for (int w = 0; w < kThreads / 64; ++w) tot[v][u] += (double)at(w, 2 * v, u) + (double)at(w, 2 * v + 1, u);
+        }
+    } else {
+#pragma unroll
+      for (int v = 0; v < V / 2; ++v)
+#pragma unroll
+        for (int u = 0; u < R; ++u) tot[v][u] = (double)acc[2 * v][u] + (double)acc[2 * v + 1][u];
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      A[u] = tot[0][u];
+      B[u] = tot[1][u];
+      if constexpr (DERIV) {
+        dA[u] = tot[2][u];
+        dB[u] = tot[3][u];
+      }
+    }
+  } else {
+    constexpr int V = DERIV ? 4 : 2;
+    double acc[V][R];
+#pragma unroll
+    for (int v = 0; v < V; ++v)
+#pragma unroll
+      for (int u = 0; u < R; ++u) acc[v][u] = 0.0;
+    for (int ir = 0; ir < nr; ++ir) {
+      const SpeciesRun run = cr[ir];
+      const int rb = max(run.begin, wa), re = min(run.end, wb);
+      if (rb >= re) continue;
+      const double *c9 = coeff + 9 * run.species;
+      double f[R], df[R], pa[R], pb[R], qa[R], qb[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        if constexpr (DERIV)
+          fsc_df_f64(c9, s2d[u], &f[u], &df[u]);
+        else
+          f[u] = fsc_f64(c9, s2d[u]);
+        pa[u] = pb[u] = qa[u] = qb[u] = 0.0;
+      }
+      for (int j = rb; j < re; ++j) {
+        const AtomRec a = atoms[j];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+          const double rho = t - rint(t);
+          double sn, cs;
+          sincospi(2.0 * rho, &sn, &cs);
+          const double w = a.occ * exp(-a.bfac * s2d[u]);
+          pa[u] = fma(w, cs, pa[u]);
+          pb[u] = fma(w, sn, pb[u]);
+          if constexpr (DERIV) {
+            const double nbw = -a.bfac * w;
+            qa[u] = fma(nbw, cs, qa[u]);
+            qb[u] = fma(nbw, sn, qb[u]);
+          }
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        acc[0][u] = fma(f[u], pa[u], acc[0][u]);
+        acc[1][u] = fma(f[u], pb[u], acc[1][u]);
+        if constexpr (DERIV) {
+          acc[2][u] += df[u] * pa[u] + f[u] * qa[u];
+          acc[3][u] += df[u] * pb[u] + f[u] * qb[u];
+        }
+      }
+    }
+    if (ww.heavy) {
+      auto at = [&](int w, int v, int u) -> double & { return s_part[((w * V + v) * R + u) * 64 + lane]; };
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int u = 0; u < R; ++u) at(ww.part, v, u) = acc[v][u];
+      __syncthreads();
+      if (!all_waves && ww.part != 0) return false;
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          acc[v][u] = 0.0;
+          for (int w = 0; w < kThreads / 64; ++w) acc[v][u] += at(w, v, u);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      A[u] = acc[0][u];
+      B[u] = acc[1][u];
+      if constexpr (DERIV) {
+        dA[u] = acc[2][u];
+        dB[u] = acc[3][u];
+      }
+    }
+  }
+  return true;
+}
+
+// Per-reflection values a later adjoint needs from the forward sums:
+// (A, B, dA/ds^2, dB/ds^2), float4 under mixed precision, else double4,
+// at the reflection's global index.
+template <bool MIXED>
+__device__ __forceinline__ void store_derivs(void *cache, int64_t i, double A, double B, double dA, double dB) {
+  if constexpr (MIXED)
+    reinterpret_cast<float4 *>(cache)[i] = make_float4((float)A, (float)B, (float)dA, (float)dB);
+  else
+    reinterpret_cast<double4 *>(cache)[i] = make_double4(A, B, dA, dB);
+}
+
+template <bool MIXED>
+__device__ __forceinline__ void load_derivs(const void *cache, int64_t i, double *A, double *B, double *dA, double *dB) {
+  if constexpr (MIXED) {
+    const float4 v = reinterpret_cast<const float4 *>(cache)[i];
+    *A = v.x;
+    *B = v.y;
+    *dA = v.z;
+    *dB = v.w;
+  } else {
+    const double4 v = reinterpret_cast<const double4 *>(cache)[i];
+    *A = v.x;
+    *B = v.y;
+    *dA = v.z;
+    *dB = v.w;
+  }
+}
+
+// Structure factors of one tile per wavefront (light items) or per block
+// (heavy items).  With DERIV the derivatives with respect to s^2 are also
+// summed and kept in ``cache`` for the adjoint.
+template <bool MIXED, bool FRIEDEL, bool DERIV>
 __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ items, int64_t n_items, int64_t n_heavy,
                                                  const CrystalPlan *__restrict__ plan,
                                                  const int64_t *__restrict__ refl_offset,
@@ -270,10 +520,12 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
                                                  const SpeciesRun *__restrict__ runs,
                                                  const int32_t *__restrict__ run_count,
                                                  const double *__restrict__ coeff, void *__restrict__ Aout,
-                                                 void *__restrict__ Bout, double *__restrict__ Iout) {
+                                                 void *__restrict__ Bout, double *__restrict__ Iout,
+                                                 void *__restrict__ cache) {
   constexpr int R = kSfRpt;
-  // heavy blocks: per wave, value (4 floats or 2 doubles), reflection slot, lane
-  __shared__ double s_part[(kThreads / 64) * 2 * R * 64];
+  // heavy blocks: per wave, the (sum, error) float pairs or the doubles of
+  // each value, per reflection slot and lane
+  __shared__ double s_part[(kThreads / 64) * (DERIV ? 4 : 2) * R * 64];
   const WaveWork ww = wave_work(n_heavy);
   if (ww.item >= n_items) return;  // light blocks only: a heavy block's item always exists
   const SfItem it = items[ww.item];
@@ -300,149 +552,18 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
     s2[u] = (float)s2d[u];
   }
   const CrystalPlan &P = plan[it.crystal];
-  const SpeciesRun *cr = runs + P.run_begin;
-  const int nr = run_count[it.crystal];
   int wa, wb;
   part_range(P, ww, &wa, &wb);
-
-  double A[R], B[R];
-  if constexpr (MIXED) {
-    float Sa[R], Ea[R], Sb[R], Eb[R];
-#pragma unroll
-    for (int u = 0; u < R; ++u) Sa[u] = Ea[u] = Sb[u] = Eb[u] = 0.f;
-    for (int ir = 0; ir < nr; ++ir) {
-      const SpeciesRun run = cr[ir];
-      const int rb = max(run.begin, wa), re = min(run.end, wb);
-      if (rb >= re) continue;
-      const double *c9 = coeff + 9 * run.species;
-      float f[R];
-#pragma unroll
-      for (int u = 0; u < R; ++u) f[u] = fsc_f32(c9, s2[u]);
-      for (int j0 = rb; j0 < re; j0 += kAtomTile) {
-        const int j1 = min(j0 + kAtomTile, re);
-        float pa[R], pb[R];
-#pragma unroll
-        for (int u = 0; u < R; ++u) pa[u] = pb[u] = 0.f;
-        auto term = [&](const AtomRec &a) {
-#pragma unroll
-          for (int u = 0; u < R; ++u) {
-            const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
-            const float rho = (float)__builtin_amdgcn_fract(t);
-            const float sn = __builtin_amdgcn_sinf(rho);
-            const float cs = __builtin_amdgcn_cosf(rho);
-            const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
-            pa[u] = fmaf(w, cs, pa[u]);
-            pb[u] = fmaf(w, sn, pb[u]);
-          }
-        };
-        // four records per round: their scalar loads are issued together
-        int j = j0;
-        for (; j + 4 <= j1; j += 4) {
-          const AtomRec a0 = atoms[j], a1 = atoms[j + 1], a2 = atoms[j + 2], a3 = atoms[j + 3];
-          term(a0);
-          term(a1);
-          term(a2);
-          term(a3);
-        }
-        for (; j < j1; ++j) term(atoms[j]);
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-          two_sum_acc(Sa[u], Ea[u], f[u] * pa[u]);
-          two_sum_acc(Sb[u], Eb[u], f[u] * pb[u]);
-        }
-      }
-    }
-    if (ww.heavy) {
-      float *sp = reinterpret_cast<float *>(s_part);
-      auto at = [&](int w, int v, int u) -> float & { return sp[((w * 4 + v) * R + u) * 64 + lane]; };
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        at(ww.part, 0, u) = Sa[u];
-        at(ww.part, 1, u) = Ea[u];
-        at(ww.part, 2, u) = Sb[u];
-        at(ww.part, 3, u) = Eb[u];
-      }
-      __syncthreads();
-      if (ww.part != 0) return;
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        A[u] = B[u] = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) {
-          A[u] += (double)at(w, 0, u) + (double)at(w, 1, u);
-          B[u] += (double)at(w, 2, u) + (double)at(w, 3, u);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        A[u] = (double)Sa[u] + (double)Ea[u];
-        B[u] = (double)Sb[u] + (double)Eb[u];
-      }
-    }
-  } else {
-    double Sa[R], Sb[R];
-#pragma unroll
-    for (int u = 0; u < R; ++u) Sa[u] = Sb[u] = 0.0;
-    for (int ir = 0; ir < nr; ++ir) {
-      const SpeciesRun run = cr[ir];
-      const int rb = max(run.begin, wa), re = min(run.end, wb);
-      if (rb >= re) continue;
-      const double *c9 = coeff + 9 * run.species;
-      double f[R], pa[R], pb[R];
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        f[u] = fsc_f64(c9, s2d[u]);
-        pa[u] = pb[u] = 0.0;
-      }
-      for (int j = rb; j < re; ++j) {
-        const AtomRec a = atoms[j];
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-          const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
-          const double rho = t - rint(t);
-          double sn, cs;
-          sincospi(2.0 * rho, &sn, &cs);
-          const double w = a.occ * exp(-a.bfac * s2d[u]);
-          pa[u] = fma(w, cs, pa[u]);
-          pb[u] = fma(w, sn, pb[u]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        Sa[u] = fma(f[u], pa[u], Sa[u]);
-        Sb[u] = fma(f[u], pb[u], Sb[u]);
-      }
-    }
-    if (ww.heavy) {
-      auto at = [&](int w, int v, int u) -> double & { return s_part[((w * 2 + v) * R + u) * 64 + lane]; };
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        at(ww.part, 0, u) = Sa[u];
-        at(ww.part, 1, u) = Sb[u];
-      }
-      __syncthreads();
-      if (ww.part != 0) return;
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        A[u] = B[u] = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) {
-          A[u] += at(w, 0, u);
-          B[u] += at(w, 1, u);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        A[u] = Sa[u];
-        B[u] = Sb[u];
-      }
-    }
-  }
+  double A[R], B[R], dA[R], dB[R];
+  if (!sf_tile_sums<MIXED, DERIV>(ww, lane, runs + P.run_begin, run_count[it.crystal], wa, wb, atoms, coeff, h, k, l,
+                                  s2d, s2, s_part, false, A, B, dA, dB))
+    return;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     if (!valid[u]) continue;
     const double I = (A[u] * A[u] + B[u] * B[u]) * lpp[idx[u]];
     Iout[idx[u]] = I;
+    if constexpr (DERIV) store_derivs<MIXED>(cache, idx[u], A[u], B[u], dA[u], dB[u]);
     const int64_t m = r0 + r1 - 1 - idx[u];
     if constexpr (MIXED) {
       float *Af = (float *)Aout;
@@ -471,41 +592,14 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
 
 // ---- adjoint ---------------------------------------------------------------
 //
-// Reflection-major pass: for each evaluated reflection recompute
-//   A + iB = sum_t f_t S_t,                 S_t  = sum_{j in t} occ_j e^{-B_j s^2} e^{i phi_j}
-//   d(A + iB)/ds^2 = sum_t (f'_t S_t + f_t S'_t),  S'_t = sum_{j in t} (-B_j) occ_j e^{-B_j s^2} e^{i phi_j}
-// with f'_t = -sum_i a_i b_i e^{-b_i s^2}; then, with gI = dL/dI summed over
-// the reflection and (when Friedel pairing is on) its mate,
+// Reflection-major pass: for each evaluated reflection take A, B and their
+// derivatives with respect to s^2 (kept by the forward, or summed again over
+// the atoms); then, with gI = dL/dI summed over the reflection and (when
+// Friedel pairing is on) its mate,
 //   gA = 2 LP A gI,  gB = 2 LP B gI,
 //   dL/dq = gI |F|^2 dLP/dq + (gA dA/ds^2 + gB dB/ds^2) / 4 + m w2 I d(2theta)/dq,
 // where w1, w2 come from the grid adjoint and m = 2 with pairing, else 1.
-
-__device__ __forceinline__ void fsc_df_f32(const double *__restrict__ c9, float s2, float *f, float *df) {
-  float a = (float)c9[8], d = 0.f;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const float ai = (float)c9[i], bi = (float)c9[4 + i];
-    const float e = __builtin_amdgcn_exp2f(-bi * kLog2e * s2);
-    a = fmaf(ai, e, a);
-    d = fmaf(-ai * bi, e, d);
-  }
-  *f = a;
-  *df = d;
-}
-
-__device__ __forceinline__ void fsc_df_f64(const double *__restrict__ c9, double s2, double *f, double *df) {
-  double a = c9[8], d = 0.0;
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const double e = exp(-c9[4 + i] * s2);
-    a = fma(c9[i], e, a);
-    d = fma(-c9[i] * c9[4 + i], e, d);
-  }
-  *f = a;
-  *df = d;
-}
-
-template <bool MIXED>
+template <bool MIXED, bool CACHED>
 __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ items, int64_t n_items, int64_t n_heavy, bool friedel,
                                                     const CrystalPlan *__restrict__ plan,
                                                     const int64_t *__restrict__ refl_offset,
@@ -515,13 +609,15 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
                                                     const AtomRec *__restrict__ atoms,
                                                     const SpeciesRun *__restrict__ runs,
                                                     const int32_t *__restrict__ run_count,
-                                                    const double *__restrict__ coeff, const double *__restrict__ w1,
+                                                    const double *__restrict__ coeff, const void *__restrict__ cache,
+                                                    const double *__restrict__ w1,
                                                     const double *__restrict__ w2, double *__restrict__ ga,
                                                     double *__restrict__ gb, double *__restrict__ dq,
                                                     double4 *__restrict__ part_fused) {
   constexpr int R = kSfRpt;
-  // heavy blocks: per wave, value (8 floats or 4 doubles), reflection slot, lane
-  __shared__ double s_part[(kThreads / 64) * 4 * R * 64];
+  // heavy blocks without the kept derivatives: per wave, value (8 floats or
+  // 4 doubles), reflection slot, lane
+  __shared__ double s_part[CACHED ? 1 : (kThreads / 64) * 4 * R * 64];
   const WaveWork ww = wave_work(n_heavy);
   if (ww.item >= n_items) return;  // light blocks only
   const SfItem it = items[ww.item];
@@ -553,152 +649,11 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
   int wa, wb;
   part_range(P, ww, &wa, &wb);
   double A[R], B[R], dA[R], dB[R];
-  if constexpr (MIXED) {
-    float Sa[R], Ea[R], Sb[R], Eb[R], Sda[R], Eda[R], Sdb[R], Edb[R];
+  if constexpr (CACHED) {
 #pragma unroll
-    for (int u = 0; u < R; ++u) Sa[u] = Ea[u] = Sb[u] = Eb[u] = Sda[u] = Eda[u] = Sdb[u] = Edb[u] = 0.f;
-    for (int ir = 0; ir < nr; ++ir) {
-      const SpeciesRun run = cr[ir];
-      const int rb = max(run.begin, wa), re = min(run.end, wb);
-      if (rb >= re) continue;
-      const double *c9 = coeff + 9 * run.species;
-      float f[R], df[R];
-#pragma unroll
-      for (int u = 0; u < R; ++u) fsc_df_f32(c9, s2[u], &f[u], &df[u]);
-      for (int j0 = rb; j0 < re; j0 += kAtomTile) {
-        const int j1 = min(j0 + kAtomTile, re);
-        float pa[R], pb[R], qa[R], qb[R];
-#pragma unroll
-        for (int u = 0; u < R; ++u) pa[u] = pb[u] = qa[u] = qb[u] = 0.f;
-        auto term = [&](const AtomRec &a) {
-          const float nb = -(float)a.bfac;
-#pragma unroll
-          for (int u = 0; u < R; ++u) {
-            const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
-            const float rho = (float)__builtin_amdgcn_fract(t);
-            const float sn = __builtin_amdgcn_sinf(rho);
-            const float cs = __builtin_amdgcn_cosf(rho);
-            const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
-            const float wc = w * cs, ws = w * sn;
-            pa[u] += wc;
-            pb[u] += ws;
-            qa[u] = fmaf(nb, wc, qa[u]);
-            qb[u] = fmaf(nb, ws, qb[u]);
-          }
-        };
-        // four records per round: their scalar loads are issued together
-        int j = j0;
-        for (; j + 4 <= j1; j += 4) {
-          const AtomRec a0 = atoms[j], a1 = atoms[j + 1], a2 = atoms[j + 2], a3 = atoms[j + 3];
-          term(a0);
-          term(a1);
-          term(a2);
-          term(a3);
-        }
-        for (; j < j1; ++j) term(atoms[j]);
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-          two_sum_acc(Sa[u], Ea[u], f[u] * pa[u]);
-          two_sum_acc(Sb[u], Eb[u], f[u] * pb[u]);
-          two_sum_acc(Sda[u], Eda[u], fmaf(df[u], pa[u], f[u] * qa[u]));
-          two_sum_acc(Sdb[u], Edb[u], fmaf(df[u], pb[u], f[u] * qb[u]));
-        }
-      }
-    }
-    if (ww.heavy) {
-      float *sp = reinterpret_cast<float *>(s_part);
-      auto at = [&](int w, int v, int u) -> float & { return sp[((w * 8 + v) * R + u) * 64 + lane]; };
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        at(ww.part, 0, u) = Sa[u];
-        at(ww.part, 1, u) = Ea[u];
-        at(ww.part, 2, u) = Sb[u];
-        at(ww.part, 3, u) = Eb[u];
-        at(ww.part, 4, u) = Sda[u];
-        at(ww.part, 5, u) = Eda[u];
-        at(ww.part, 6, u) = Sdb[u];
-        at(ww.part, 7, u) = Edb[u];
-      }
-      __syncthreads();
-      // every wave forms the same totals, in wave order
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        A[u] = B[u] = dA[u] = dB[u] = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) {
-          A[u] += (double)at(w, 0, u) + (double)at(w, 1, u);
-          B[u] += (double)at(w, 2, u) + (double)at(w, 3, u);
-          dA[u] += (double)at(w, 4, u) + (double)at(w, 5, u);
-          dB[u] += (double)at(w, 6, u) + (double)at(w, 7, u);
-        }
-      }
-    } else {
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        A[u] = (double)Sa[u] + (double)Ea[u];
-        B[u] = (double)Sb[u] + (double)Eb[u];
-        dA[u] = (double)Sda[u] + (double)Eda[u];
-        dB[u] = (double)Sdb[u] + (double)Edb[u];
-      }
-    }
+    for (int u = 0; u < R; ++u) load_derivs<MIXED>(cache, idx[u], &A[u], &B[u], &dA[u], &dB[u]);
   } else {
-#pragma unroll
-    for (int u = 0; u < R; ++u) A[u] = B[u] = dA[u] = dB[u] = 0.0;
-    for (int ir = 0; ir < nr; ++ir) {
-      const SpeciesRun run = cr[ir];
-      const int rb = max(run.begin, wa), re = min(run.end, wb);
-      if (rb >= re) continue;
-      const double *c9 = coeff + 9 * run.species;
-      double f[R], df[R], pa[R], pb[R], qa[R], qb[R];
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        fsc_df_f64(c9, s2d[u], &f[u], &df[u]);
-        pa[u] = pb[u] = qa[u] = qb[u] = 0.0;
-      }
-      for (int j = rb; j < re; ++j) {
-        const AtomRec a = atoms[j];
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-          const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
-          const double rho = t - rint(t);
-          double sn, cs;
-          sincospi(2.0 * rho, &sn, &cs);
-          const double w = a.occ * exp(-a.bfac * s2d[u]);
-          const double wc = w * cs, ws = w * sn;
-          pa[u] += wc;
-          pb[u] += ws;
-          qa[u] = fma(-a.bfac, wc, qa[u]);
-          qb[u] = fma(-a.bfac, ws, qb[u]);
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        A[u] = fma(f[u], pa[u], A[u]);
-        B[u] = fma(f[u], pb[u], B[u]);
-        dA[u] += df[u] * pa[u] + f[u] * qa[u];
-        dB[u] += df[u] * pb[u] + f[u] * qb[u];
-      }
-    }
-    if (ww.heavy) {
-      auto at = [&](int w, int v, int u) -> double & { return s_part[((w * 4 + v) * R + u) * 64 + lane]; };
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        at(ww.part, 0, u) = A[u];
-        at(ww.part, 1, u) = B[u];
-        at(ww.part, 2, u) = dA[u];
-        at(ww.part, 3, u) = dB[u];
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        A[u] = B[u] = dA[u] = dB[u] = 0.0;
-        for (int w = 0; w < kThreads / 64; ++w) {
-          A[u] += at(w, 0, u);
-          B[u] += at(w, 1, u);
-          dA[u] += at(w, 2, u);
-          dB[u] += at(w, 3, u);
-        }
-      }
-    }
+    sf_tile_sums<MIXED, true>(ww, lane, cr, nr, wa, wb, atoms, coeff, h, k, l, s2d, s2, s_part, true, A, B, dA, dB);
   }
   const double m = friedel ? 2.0 : 1.0;
   const double l2 = lambda * lambda;
@@ -1117,26 +1072,37 @@ void launch_atom_prep(const CrystalPlan *plan, int64_t n_c, int32_t n_species, c
                      n_species, frac, species, occ, bfac, atoms, orig, runs, run_count, err);
 }
 
+template <bool MIXED, bool FRIEDEL, bool DERIV>
+static void launch_sf_t(dim3 grid, const SfItem *items, int64_t n_items, int64_t n_heavy, const CrystalPlan *plan,
+                        const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
+                        const double *q, const double *lp, const AtomRec *atoms, const SpeciesRun *runs,
+                        const int32_t *run_count, const double *coeff, void *A, void *B, double *I, void *cache,
+                        hipStream_t s) {
+  hipLaunchKernelGGL((k_sf<MIXED, FRIEDEL, DERIV>), grid, dim3(kThreads), 0, s, items, n_items, n_heavy, plan,
+                     refl_offset, h, k, l, q, lp, atoms, runs, run_count, coeff, A, B, I, cache);
+}
+
 void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, int64_t n_heavy, const CrystalPlan *plan,
                const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
-               const double *coeff, void *A, void *B, double *I, hipStream_t s) {
+               const double *coeff, void *A, void *B, double *I, void *deriv_cache, hipStream_t s) {
   if (n_items <= 0) return;
-  const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4)), block(kThreads);
+  const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4));
+  auto go = [&](auto fn) {
+    fn(grid, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp, atoms, runs, run_count, coeff, A, B, I,
+       deriv_cache, s);
+  };
+  const bool d = deriv_cache != nullptr;
   if (mixed) {
     if (friedel)
-      hipLaunchKernelGGL((k_sf<true, true>), grid, block, 0, s, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp,
-                         atoms, runs, run_count, coeff, A, B, I);
+      d ? go(launch_sf_t<true, true, true>) : go(launch_sf_t<true, true, false>);
     else
-      hipLaunchKernelGGL((k_sf<true, false>), grid, block, 0, s, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp,
-                         atoms, runs, run_count, coeff, A, B, I);
+      d ? go(launch_sf_t<true, false, true>) : go(launch_sf_t<true, false, false>);
   } else {
     if (friedel)
-      hipLaunchKernelGGL((k_sf<false, true>), grid, block, 0, s, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp,
-                         atoms, runs, run_count, coeff, A, B, I);
+      d ? go(launch_sf_t<false, true, true>) : go(launch_sf_t<false, true, false>);
     else
-      hipLaunchKernelGGL((k_sf<false, false>), grid, block, 0, s, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp,
-                         atoms, runs, run_count, coeff, A, B, I);
+      d ? go(launch_sf_t<false, false, true>) : go(launch_sf_t<false, false, false>);
   }
 }
 
@@ -1148,17 +1114,26 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
                   const CrystalPlan *plan,
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
-                  const int32_t *run_count, const double *coeff, const double *w1, const double *w2, double *ga,
-                  double *gb, double *dq, double *part_fused, hipStream_t s) {
+                  const int32_t *run_count, const double *coeff, const void *deriv_cache, const double *w1,
+                  const double *w2, double *ga, double *gb, double *dq, double *part_fused, hipStream_t s) {
   if (n_items <= 0) return;
   const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4)), block(kThreads);
   double4 *pf = (double4 *)part_fused;
-  if (mixed)
-    hipLaunchKernelGGL(k_sf_bw<true>, grid, block, 0, s, items, n_items, n_heavy, friedel, plan, refl_offset, h, k, l, q, lp,
-                       lambda, atoms, runs, run_count, coeff, w1, w2, ga, gb, dq, pf);
-  else
-    hipLaunchKernelGGL(k_sf_bw<false>, grid, block, 0, s, items, n_items, n_heavy, friedel, plan, refl_offset, h, k, l, q, lp,
-                       lambda, atoms, runs, run_count, coeff, w1, w2, ga, gb, dq, pf);
+#define XRD_SF_BW(M, C)                                                                                          \
+  hipLaunchKernelGGL((k_sf_bw<M, C>), grid, block, 0, s, items, n_items, n_heavy, friedel, plan, refl_offset, h, k, \
+                     l, q, lp, lambda, atoms, runs, run_count, coeff, deriv_cache, w1, w2, ga, gb, dq, pf)
+  if (mixed) {
+    if (deriv_cache)
+      XRD_SF_BW(true, true);
+    else
+      XRD_SF_BW(true, false);
+  } else {
+    if (deriv_cache)
+      XRD_SF_BW(false, true);
+    else
+      XRD_SF_BW(false, false);
+  }
+#undef XRD_SF_BW
 }
 
 size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap) {

@@ -85,6 +85,7 @@ struct WsLayout {
   int64_t cmax, pk_count, tmp_tt, tmp_i, tmp_mult, tmp_first;
   int64_t scan_part;
   int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6, bw_partf;
+  int64_t sf_deriv;  // kept (A, B, dA/ds^2, dB/ds^2) per reflection, or -1
   int64_t total;
 };
 
@@ -116,11 +117,13 @@ void launch_atom_prep(const CrystalPlan *plan, int64_t n_c, int32_t n_species, c
                       const int32_t *species, const double *occ, const double *bfac, AtomRec *atoms, int32_t *orig,
                       SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s);
 // Items: the first n_heavy take a block each (atoms split over its four
-// wavefronts), the rest one wavefront each.
+// wavefronts), the rest one wavefront each.  A non-null deriv_cache
+// ([refl_cap] float4 under mixed precision, else double4) receives
+// (A, B, dA/ds^2, dB/ds^2) of every evaluated reflection.
 void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, int64_t n_heavy, const CrystalPlan *plan,
                const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
-               const double *coeff, void *A, void *B, double *I, hipStream_t s);
+               const double *coeff, void *A, void *B, double *I, void *deriv_cache, hipStream_t s);
 
 struct SortArgs {
   int64_t n_c;
@@ -180,8 +183,8 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
                   const CrystalPlan *plan,
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
-                  const int32_t *run_count, const double *coeff, const double *w1, const double *w2, double *ga,
-                  double *gb, double *dq, double *part_fused, hipStream_t s);
+                  const int32_t *run_count, const double *coeff, const void *deriv_cache, const double *w1,
+                  const double *w2, double *ga, double *gb, double *dq, double *part_fused, hipStream_t s);
 size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap);
 void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,
                     const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,

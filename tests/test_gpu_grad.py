@@ -195,3 +195,35 @@ def test_adjoint_dot_product_consistency(precision, bar):
     rel = abs(lhs - rhs) / abs(rhs)
     print(precision, "<v, J^T w>", lhs, "<J v, w>", rhs, "rel", rel, flush=True)
     assert rel <= bar
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_kept_derivatives_match_recomputed(precision):
+    """The adjoint with dF/ds^2 kept by the structure-factor call equals the
+    adjoint that sums over the atoms again: structure factors bit for bit
+    (the kept derivatives do not change them), gradients to 1e-12 (double)
+    or the mixed path's 1e-4 bar (the mixed copy keeps F and dF/ds^2 in
+    float).  Covers heavy items (atoms split over a block) and crystals above
+    the fused-gradient size."""
+    from paper_2602_11709_amd.api import Grid, XrdBatch
+    p = problem(4, 10, 700, seed=31)
+    grid = Grid(p.grid_t0, p.grid_dt, p.grid_n, p.sigma, p.window_sigmas)
+    dy = torch.randn(p.batch.n_crystals, p.grid_n, generator=torch.Generator().manual_seed(3),
+                     dtype=torch.float64).cuda()
+    outs = []
+    for keep in (False, True):
+        xb = XrdBatch(p.batch, precision=precision, grid_capacity=p.grid_n, keep_sf_derivs=keep)
+        refl = xb.enumerate()
+        A, B, I = xb.structure_factors(refl)
+        y = xb.pattern_forward(refl, I, grid)
+        g = xb.pattern_backward(refl, grid, dy)
+        torch.cuda.synchronize()
+        n = int(refl.refl_offset[-1])
+        outs.append([t[:n].cpu().numpy() for t in (A, B, I)] + [y.cpu().numpy()] + [t.cpu().numpy() for t in g])
+    for a, b in zip(outs[0][:4], outs[1][:4]):
+        np.testing.assert_array_equal(a, b)
+    bar = 1e-12 if precision == "fp64" else 1e-4
+    for name, a, b in zip(("dfrac", "dbfac", "dlattice"), outs[0][4:], outs[1][4:]):
+        rel = np.linalg.norm(a - b) / np.linalg.norm(a)
+        print(precision, name, "kept vs recomputed rel", rel, flush=True)
+        assert rel <= bar, name

@@ -107,3 +107,13 @@ def test_grid_capacity_is_enforced():
     y = xb.pattern_forward(refl, I, Grid(10.0, 0.08, 1000, 0.1, 8.0))
     torch.cuda.synchronize()
     assert torch.isfinite(y).all()
+
+
+def test_long_grid_uses_the_span_table_path():
+    """A 40001-point grid (more spans than one block keeps in LDS) takes the
+    path with the span tables in the workspace."""
+    from paper_2602_11709_amd.api import Grid
+    b = ragged_batch()
+    grid = Grid(10.0, 0.002, 40001, 0.02, 8.0)
+    y, ro, tt, I = gpu_pattern(b, "mixed", grid)
+    check_against_own_reflections(y, ro, tt, I, grid, "mixed", "long grid")
