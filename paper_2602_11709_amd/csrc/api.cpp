@@ -176,7 +176,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
 
   const bool friedel = d->friedel != 0;
   const double lam = d->wavelength;
-  int64_t ec = 0, sc = 0, hc = 0, bins = 0, runs = 0, parts = 0, pfused = 0, refl = 0;
+  int64_t ec = 0, sc = 0, hc = 0, bins = 0, runs = 0, parts = 0, pfused = 0, refl = 0, tiles_total = 0;
   int runs_cap_max = 1;
   for (int64_t c = 0; c < nc; ++c) {
     CrystalPlan &P = b->plan[c];
@@ -238,6 +238,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     P.hchunk_begin = hc;
     hc += P.n_hchunks;
     P.n_tiles = (int32_t)ceil_div(evalcap, kSfTile);
+    P.tile_begin = (int32_t)tiles_total;
+    tiles_total += P.n_tiles;
     P.fused = na <= kFusedMaxAtoms ? 1 : 0;
     if (P.fused) {
       P.pf_begin = pfused;
@@ -287,14 +289,11 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
     return (b->atom_offset[x + 1] - b->atom_offset[x]) > (b->atom_offset[y + 1] - b->atom_offset[y]);
   });
+  std::vector<int64_t> heavy, light;
   for (int64_t c : order) {
     const CrystalPlan &P = b->plan[c];
-    const int64_t evalcap = friedel ? P.half_box : 2 * P.half_box;
-    const int64_t tiles = ceil_div(evalcap, kSfTile);
-    for (int64_t t = 0; t < tiles; ++t) b->sf_items.push_back(SfItem{(int32_t)c, (int32_t)t});
     const int64_t na = P.atom_end - P.atom_begin;
-    // crystals in descending atom count: the heavy ones form the table's head
-    if (na >= kSplitAtoms) b->sf_heavy += tiles;
+    (na >= kSplitAtoms ? heavy : light).push_back(c);
     const int64_t ab = ceil_div(na, kAtomBlock);
     for (int64_t a = 0; a < ab; ++a) {
       b->ab_items.push_back(AbItem{(int32_t)c, (int32_t)a});
@@ -302,6 +301,35 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
         for (int32_t k = 0; k < P.n_hchunks; ++k) b->bw_items.push_back(BwItem{(int32_t)c, (int32_t)a, k, 0});
     }
   }
+  // structure-factor tiles, heavy crystals first (a block per tile).  Tiles
+  // are planned at capacity (the search box), and the later ones of a
+  // crystal are empty once its reflections run out; each group lists first
+  // the tiles the shell's expected reflection count fills, crystal by
+  // crystal (neighbouring waves share the crystal's atoms in cache), then
+  // the rest, which mostly find no work and end at once.
+  auto likely_tiles = [&](int64_t c) {
+    const CrystalPlan &P = b->plan[c];
+    const double *lat = b->lattice.data() + 6 * c;
+    const double r = kPi / 180.0, ca = std::cos(lat[3] * r), cb = std::cos(lat[4] * r), cg = std::cos(lat[5] * r);
+    const double vol = lat[0] * lat[1] * lat[2] * std::sqrt(std::max(0.0, 1 - ca * ca - cb * cb - cg * cg + 2 * ca * cb * cg));
+    const double ghi = std::sqrt(P.qhi), glo = std::sqrt(P.qlo);
+    const double shell = 4.0 * kPi / 3.0 * (ghi * ghi * ghi - glo * glo * glo) * vol;  // lattice points, both halves
+    const double eval = (friedel ? 0.5 : 1.0) * shell * 1.05 + kSfTile;
+    return (int32_t)std::min<double>(P.n_tiles, std::ceil(eval / kSfTile));
+  };
+  auto emit = [&](const std::vector<int64_t> &group) {
+    std::vector<int32_t> split(group.size());
+    for (size_t i = 0; i < group.size(); ++i) {
+      split[i] = likely_tiles(group[i]);
+      for (int32_t t = 0; t < split[i]; ++t) b->sf_items.push_back(SfItem{(int32_t)group[i], t});
+    }
+    for (size_t i = 0; i < group.size(); ++i)
+      for (int32_t t = split[i]; t < b->plan[group[i]].n_tiles; ++t)
+        b->sf_items.push_back(SfItem{(int32_t)group[i], t});
+  };
+  emit(heavy);
+  b->sf_heavy = (int64_t)b->sf_items.size();
+  emit(light);
   if ((int64_t)b->sf_items.size() >= ((int64_t)1 << 31) || (int64_t)b->bw_items.size() >= ((int64_t)1 << 31)) {
     delete b;
     return fail(XRD_ERR_CAPACITY, "launch tables exceed 2^31 entries");
@@ -333,13 +361,13 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.err_flag = take(4);
   L.bin_count = take(4 * bins);
   L.bin_start = take(8 * (bins + 1));
-  L.skey = take(8 * rc);
+  L.skey = take(8 * (rc + kEntSlack));
   L.sidx = take(4 * rc);
   // entries (evaluated reflections in 2theta order): their own arrays under
   // Friedel pairing, the full sorted list otherwise
-  L.ent_key = friedel ? take(8 * b->half_cap) : L.skey;
+  L.ent_key = friedel ? take(8 * (b->half_cap + kEntSlack)) : L.skey;
   L.ent_idx = friedel ? take(4 * b->half_cap) : L.sidx;
-  L.ent_w = take(8 * (friedel ? b->half_cap : rc));
+  L.ent_w = take(8 * ((friedel ? b->half_cap : rc) + kEntSlack));
   L.span_first = take(4 * nc * b->span_cap);
   L.span_last = take(4 * nc * b->span_cap);
   L.flags = take(4 * rc);
@@ -358,7 +386,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.bw_dq = take(8 * rc);
   L.bw_part = take(32 * parts);
   L.bw_partf = take(32 * pfused);
-  L.bw_part6 = take(48 * hc);
+  L.bw_part6 = take(48 * tiles_total);
   L.sf_deriv = d->keep_sf_derivs ? take((d->precision == XRD_MIXED ? 16 : 32) * rc) : -1;
   L.total = o;
   *out = b;
@@ -405,14 +433,12 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   return hip_check("upload");
 }
 
-static void pack_atoms(xrd_batch *b, void *ws);
 
 int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r) {
   if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
   if (int e = check_ws(b, ws)) return e;
   if (int e = check_refl(r)) return e;
   const WsLayout &L = b->ws;
-  pack_atoms(b, ws);
   b->sorted_ws = nullptr;
   b->sorted_tt = nullptr;
   b->deriv_ws = nullptr;
@@ -420,18 +446,14 @@ int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r) {
   launch_enumerate(at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, at<int32_t>(ws, L.enum_chunk_crystal),
                    (int64_t)b->enum_chunk_crystal.size(), b->desc.wavelength, at<int32_t>(ws, L.enum_count),
                    at<int64_t>(ws, L.enum_prefix), at<int64_t>(ws, L.scan_part), r->h, r->k, r->l, r->q,
-                   r->two_theta, r->lp, r->refl_offset, stream_of(b));
+                   r->two_theta, r->lp, r->refl_offset, b->desc.n_species, b->desc.frac, b->desc.species,
+                   b->desc.occ, b->desc.bfac, at<AtomRec>(ws, L.atoms), at<int32_t>(ws, L.atom_orig),
+                   at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), at<int32_t>(ws, L.err_flag),
+                   stream_of(b));
   b->last_ws = ws;
   return hip_check("enumerate");
 }
 
-static void pack_atoms(xrd_batch *b, void *ws) {
-  const WsLayout &L = b->ws;
-  launch_atom_prep(at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, b->desc.n_species, b->desc.frac,
-                   b->desc.species, b->desc.occ, b->desc.bfac, at<AtomRec>(ws, L.atoms), at<int32_t>(ws, L.atom_orig),
-                   at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), at<int32_t>(ws, L.err_flag),
-                   stream_of(b));
-}
 
 int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, void *B, double *I) {
   if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
@@ -578,17 +600,14 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
                      g->n_points, g->sigma, g->window_sigmas, w1, w2, s);
   launch_sf_bw(mixed, friedel, items, n_items, b->sf_heavy, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
                b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
-               b->desc.sf_coeff, deriv, w1, w2, ga, gb, dq, at<double>(ws, L.bw_partf), s);
+               b->desc.sf_coeff, deriv, w1, w2, ga, gb, dq, at<double>(ws, L.bw_part6), at<double>(ws, L.bw_partf), s);
   launch_atom_bw(mixed, friedel, at<BwItem>(ws, L.bw_items), (int64_t)b->bw_items.size(), plan, r->refl_offset,
                  r->h, r->k, r->l, r->q, ga, gb, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
                  at<int32_t>(ws, L.run_count), b->desc.sf_coeff, b->bw_tile, b->runs_cap_max,
                  at<double>(ws, L.bw_part), s);
-  launch_atom_bw_reduce(at<AbItem>(ws, L.ab_items), (int64_t)b->ab_items.size(), friedel, plan, r->refl_offset,
-                        at<double>(ws, L.bw_part), at<double>(ws, L.bw_partf), at<int32_t>(ws, L.atom_orig),
-                        dL_dfrac, dL_dbfac, s);
-  launch_gstar_part(at<int32_t>(ws, L.hchunk_crystal), (int64_t)b->hchunk_crystal.size(), friedel, plan,
-                    r->refl_offset, r->h, r->k, r->l, dq, at<double>(ws, L.bw_part6), s);
-  launch_lattice_chain(plan, b->desc.n_crystals, at<double>(ws, L.bw_part6), dL_dlattice, s);
+  launch_bw_finish(at<AbItem>(ws, L.ab_items), (int64_t)b->ab_items.size(), friedel, plan, b->desc.n_crystals,
+                   r->refl_offset, at<double>(ws, L.bw_part), at<double>(ws, L.bw_partf), at<int32_t>(ws, L.atom_orig),
+                   at<double>(ws, L.bw_part6), dL_dfrac, dL_dbfac, dL_dlattice, s);
   b->last_ws = ws;
   return hip_check("pattern_backward");
 }

@@ -56,7 +56,7 @@ __device__ __forceinline__ void window_of(const GridArgs &g, double t, int64_t *
 constexpr int kEntBlock = 1024;                // entries per block of the preparation and the adjoint
 constexpr int kEntSplit = kHalfChunk / kEntBlock;  // such blocks per chunk of kHalfChunk entries
 constexpr int kSegPts = 1024;                  // grid points per gather block (4 per thread)
-constexpr int kGTile = 1024;                   // entries per LDS tile of the gather
+static_assert(kEntSlack == 8, "the gather reads entries in batches of kEntSlack");
 constexpr int kAdjSpan = 4096;                 // grid points of dL/dy an adjoint block stages in LDS
 static_assert(kSegPts == 16 * kSpanPts, "a gather block covers 16 spans, four per wave");
 
@@ -171,11 +171,11 @@ __global__ __launch_bounds__(256) void k_entry_prep(const int32_t *__restrict__ 
 
 // Forward gather: a block owns kSegPts consecutive grid points of one
 // crystal, each lane four of them, 256 apart, so that wave w of the block
-// covers spans 4j + w (j = 0..3) of the segment.  The entries reaching the
-// segment (first of its first span .. last of its last span) are staged in
-// LDS in tiles; each wave walks, for each of its spans, that span's entry
-// range in 2theta order with wave-uniform LDS reads, and each lane adds
-// w K(x - 2theta) when its point lies in the entry's window (the same
+// covers spans 4j + w (j = 0..3) of the segment.  For each of its spans a
+// wave walks that span's entry range in 2theta order; the entries' keys and
+// weights are read at wave-uniform addresses (scalar loads into SGPRs, eight
+// entries per batch, so no LDS staging or barrier is needed) and each lane
+// adds w K(x - 2theta) when its point lies in the entry's window (the same
 // |x - 2theta| <= half test that defines the window), so every point sums
 // exactly its reflections, in sorted order, deterministically.  The offset
 // x - 2theta and the window test are double precision in both paths; under
@@ -193,11 +193,7 @@ __global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restric
                                                         GridArgs g, double *__restrict__ y) {
 #pragma clang fp contract(off)
   using real = typename std::conditional<MIXED, float, double>::type;
-  struct Ent {
-    double t;
-    real w;
-  };
-  __shared__ Ent s_ent[kGTile];
+  constexpr int kB = kEntSlack;  // entries per batch of scalar loads
   const int S = (int)((g.n + kSpanPts - 1) / kSpanPts);
   const int segs = (int)((g.n + kSegPts - 1) / kSegPts);
   const int64_t c = crystal_order[blockIdx.x / segs];
@@ -207,58 +203,78 @@ __global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restric
   const EntryRange er = entry_range(refl_offset, c, friedel);
   const int32_t *__restrict__ fs = span_first + c * span_cap;
   const int32_t *__restrict__ ls = span_last + c * span_cap;
-  // entry ranges of the wave's spans (empty for spans past the grid's end)
-  int f[4], l[4];
-#pragma unroll
+  const double *__restrict__ kp = ent_key + er.base;
+  const real *__restrict__ wp = reinterpret_cast<const real *>(ent_w) + er.base;
+  const float c2 = (float)(g.inv2s2 * 1.4426950408889634);
+  auto add = [&](double x, double t, real w, real &acc) {
+    const double d = x - t;
+    if (fabs(d) <= g.half) {
+      if constexpr (MIXED) {
+        const float df = (float)d;
+        acc = __builtin_fmaf(w, __builtin_amdgcn_exp2f(-(df * df) * c2), acc);
+      } else {
+        acc += w * exp(-(d * d) * g.inv2s2);
+      }
+    }
+  };
+#pragma unroll 1
   for (int j = 0; j < 4; ++j) {
     const int s = sb + 4 * j + wid;
-    f[j] = s <= se ? max(fs[s], 0) : 0;
-    l[j] = s <= se ? (int)min((int64_t)ls[s], er.count - 1) : -1;
-  }
-  const int E0 = max(fs[sb], 0);
-  const int E1 = (int)min((int64_t)ls[se], er.count - 1);
-  double x[4];
-  real acc[4];
+    if (s > se) break;
+    const int f = max(fs[s], 0);
+    const int l = (int)min((int64_t)ls[s], er.count - 1);
+    const int64_t p = (int64_t)s * kSpanPts + (threadIdx.x & 63);
+    const double x = g.t0 + (double)p * g.dt;
+    real acc = 0;
+    int e = f;
+    // full batches, the next one's loads issued before this one's arithmetic
+    if (e + kB - 1 <= l) {
+      double t[kB];
+      real w[kB];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    x[j] = g.t0 + (double)((int64_t)sb * kSpanPts + j * 256 + threadIdx.x) * g.dt;
-    acc[j] = 0;
-  }
-  const real *__restrict__ wts = reinterpret_cast<const real *>(ent_w);
-  const float c2 = (float)(g.inv2s2 * 1.4426950408889634);
-  for (int T0 = E0; T0 <= E1; T0 += kGTile) {
-    const int T1 = min(T0 + kGTile - 1, E1);
+      for (int i = 0; i < kB; ++i) {
+        t[i] = kp[e + i];
+        w[i] = wp[e + i];
+      }
+      for (;;) {
+        const bool next_full = e + 2 * kB - 1 <= l;
+        const int en = next_full ? e + kB : e;  // a full batch either way
+        double tn[kB];
+        real wn[kB];
 #pragma unroll
-    for (int k = 0; k < kGTile / 256; ++k) {
-      const int e = T0 + k * 256 + (int)threadIdx.x;
-      if (e <= T1) s_ent[e - T0] = Ent{ent_key[er.base + e], wts[er.base + e]};
-    }
-    __syncthreads();
+        for (int i = 0; i < kB; ++i) {
+          tn[i] = kp[en + i];
+          wn[i] = wp[en + i];
+        }
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int a = max(f[j], T0) - T0, b = min(l[j], T1) - T0;
-      real sacc = acc[j];
-#pragma unroll 8
-      for (int e = a; e <= b; ++e) {
-        const Ent ent = s_ent[e];
-        const double d = x[j] - ent.t;
-        if (fabs(d) <= g.half) {
-          if constexpr (MIXED) {
-            const float df = (float)d;
-            sacc = __builtin_fmaf(ent.w, __builtin_amdgcn_exp2f(-(df * df) * c2), sacc);
-          } else {
-            sacc += ent.w * exp(-(d * d) * g.inv2s2);
-          }
+        for (int i = 0; i < kB; ++i) add(x, t[i], w[i], acc);
+        e += kB;
+        if (!next_full) break;
+#pragma unroll
+        for (int i = 0; i < kB; ++i) {
+          t[i] = tn[i];
+          w[i] = wn[i];
         }
       }
-      acc[j] = sacc;
     }
-    __syncthreads();
-  }
+    // the last partial batch: the kB entries ending at l (from 0 if l is
+    // smaller; the entry arrays carry kB entries of slack at their end, so
+    // every read is in bounds), those before e or past l weighted zero,
+    // which adds exactly nothing (a key that is not a reflection of this
+    // crystal either fails the window test or meets a zero weight)
+    if (e <= l) {
+      const int tb = max(l - (kB - 1), 0);
+      double t[kB];
+      real w[kB];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int64_t p = (int64_t)sb * kSpanPts + j * 256 + threadIdx.x;
-    if (p < g.n) y[c * g.n + p] = (double)acc[j];
+      for (int i = 0; i < kB; ++i) {
+        t[i] = kp[tb + i];
+        w[i] = wp[tb + i];
+      }
+#pragma unroll
+      for (int i = 0; i < kB; ++i) add(x, t[i], (tb + i >= e && tb + i <= l) ? w[i] : (real)0, acc);
+    }
+    if (p < g.n) y[c * g.n + p] = (double)acc;
   }
 }
 

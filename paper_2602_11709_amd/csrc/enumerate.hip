@@ -25,6 +25,7 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kPer = kEnumChunk / kThreads;  // 8
 constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kFusedPackLds = 4096;  // largest cursor space the fused count-and-pack launch carries
 
 struct Hkl {
   int h, k, l;
@@ -78,9 +79,146 @@ __device__ __forceinline__ double lp_of(double tt) {
   return (1.0 + c2 * c2) / (st * st * ct);
 }
 
+// ---- atom packing ----------------------------------------------------------
+//
+// The structure-factor kernels read each crystal's atoms grouped by species
+// (so that the scattering factor is evaluated once per species and
+// reflection), as 48-byte records.  One wavefront packs one crystal: species
+// histogram in LDS, ascending-species runs, then a stable scatter (peeling one
+// species per step with a ballot).  The wavefront works alone: it orders its
+// LDS accesses with wavefront-scope fences, so several crystals can share a
+// block.
+
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan *__restrict__ plan,
+                             int32_t n_species, const double *__restrict__ frac,
+                             const int32_t *__restrict__ species, const double *__restrict__ occ,
+                             const double *__restrict__ bfac, AtomRec *__restrict__ atoms,
+                             int32_t *__restrict__ orig, SpeciesRun *__restrict__ runs,
+                             int32_t *__restrict__ run_count, int32_t *__restrict__ err) {
+  const CrystalPlan &P = plan[c];
+  const int64_t a0 = P.atom_begin, a1 = P.atom_end;
+  for (int t = lane; t < n_species; t += 64) cursor[t] = 0;
+  wave_sync();
+  for (int64_t j = a0 + lane; j < a1; j += 64) {
+    int sp = species[j];
+    if (sp < 0 || sp >= n_species) {
+      atomicOr(err, 1);
+      sp = 0;
+    }
+    atomicAdd(&cursor[sp], 1);
+  }
+  wave_sync();
+  // ascending-species runs and cursors (exclusive scan of the histogram)
+  int64_t running = a0;
+  int nruns = 0;
+  for (int t0 = 0; t0 < n_species; t0 += 64) {
+    const int t = t0 + lane;
+    const int v = t < n_species ? cursor[t] : 0;
+    int inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      int o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    const int tot = __shfl(inc, 63, 64);
+    const uint64_t nz = __ballot(v > 0);
+    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(nz >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nz, 0u));
+    const int64_t start = running + inc - v;
+    if (v > 0) {
+      SpeciesRun r;
+      r.begin = (int32_t)start;
+      r.end = (int32_t)(start + v);
+      r.species = t;
+      r.local = nruns + rank;
+      runs[P.run_begin + nruns + rank] = r;
+    }
+    if (t < n_species) cursor[t] = (int32_t)start;
+    wave_sync();
+    running += tot;
+    nruns += __popcll(nz);
+  }
+  if (lane == 0) run_count[c] = nruns;
+  for (int64_t base = a0; base < a1; base += 64) {
+    const int64_t j = base + lane;
+    bool active = j < a1;
+    int sp = -1;
+    if (active) {
+      sp = species[j];
+      if (sp < 0 || sp >= n_species) sp = 0;
+    }
+    while (true) {
+      const uint64_t act = __ballot(active);
+      if (act == 0) break;
+      const int leader = __builtin_ctzll(act);
+      const int t = __shfl(sp, leader, 64);
+      const uint64_t m = __ballot(active && sp == t);
+      const int base_pos = cursor[t];
+      wave_sync();
+      if (active && sp == t) {
+        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        const int pos = base_pos + rank;
+        AtomRec a;
+        a.x = frac[3 * j];
+        a.y = frac[3 * j + 1];
+        a.z = frac[3 * j + 2];
+        a.occ = occ[j];
+        a.bfac = bfac[j];
+        a.log2occ = __log2f((float)a.occ);
+        a.bl2e = (float)a.bfac * kLog2e;
+        atoms[pos] = a;
+        orig[pos] = (int32_t)j;
+        active = false;
+      }
+      if (lane == leader) cursor[t] = base_pos + __popcll(m);
+      wave_sync();
+    }
+  }
+}
+
+struct PackArgs {
+  int32_t n_species;
+  const double *frac;
+  const int32_t *species;
+  const double *occ;
+  const double *bfac;
+  AtomRec *atoms;
+  int32_t *orig;
+  SpeciesRun *runs;
+  int32_t *run_count;
+  int32_t *err;
+};
+
+// Atom packing alone, one wavefront per crystal.
+__global__ __launch_bounds__(64) void k_atom_pack(const CrystalPlan *__restrict__ plan, int64_t n_c, PackArgs a) {
+  extern __shared__ int32_t cursor[];  // n_species
+  pack_crystal(blockIdx.x, threadIdx.x, cursor, plan, a.n_species, a.frac, a.species, a.occ, a.bfac, a.atoms,
+               a.orig, a.runs, a.run_count, a.err);
+}
+
+// Survivor count per enumeration chunk.  With pack_blocks > 0 the launch
+// also packs the atoms (independent work): blocks from n_chunks on take four
+// crystals each, one per wavefront, with n_species LDS cursors per wavefront.
 __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__restrict__ plan,
                                                          const int32_t *__restrict__ chunk_crystal,
-                                                         double lambda, int32_t *__restrict__ counts) {
+                                                         int64_t n_chunks, int64_t n_c, double lambda,
+                                                         int32_t *__restrict__ counts, PackArgs pa) {
+  if (blockIdx.x >= n_chunks) {
+    extern __shared__ int32_t cursors[];  // 4 x n_species
+    const int wid = threadIdx.x >> 6;
+    const int64_t c = (int64_t)(blockIdx.x - n_chunks) * (kThreads / 64) + wid;
+    if (c < n_c)
+      pack_crystal((int)c, threadIdx.x & 63, cursors + wid * pa.n_species, plan, pa.n_species, pa.frac, pa.species,
+                   pa.occ, pa.bfac, pa.atoms, pa.orig, pa.runs, pa.run_count, pa.err);
+    return;
+  }
   const int chunk = blockIdx.x;
   const CrystalPlan &P = plan[chunk_crystal[chunk]];
   const int64_t p0 = (int64_t)(chunk - P.enum_chunk_begin) * kEnumChunk;
@@ -211,10 +349,21 @@ __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__res
 void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk_crystal, int64_t n_chunks,
                       double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h,
                       int16_t *k, int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset,
-                      hipStream_t s) {
-  if (n_chunks > 0)
-    hipLaunchKernelGGL(k_enum_count, dim3((unsigned)n_chunks), dim3(kThreads), 0, s, plan, chunk_crystal, lambda,
-                       counts);
+                      int32_t n_species, const double *frac, const int32_t *species, const double *occ,
+                      const double *bfac, AtomRec *atoms, int32_t *orig, SpeciesRun *runs, int32_t *run_count,
+                      int32_t *err, hipStream_t s) {
+  const PackArgs pa{n_species, frac, species, occ, bfac, atoms, orig, runs, run_count, err};
+  // the packing rides along in the count launch while its cursors stay small
+  const size_t fused_lds = (size_t)(kThreads / 64) * n_species * sizeof(int32_t);
+  const bool fuse = n_chunks > 0 && fused_lds <= kFusedPackLds;
+  if (!fuse && n_c > 0)
+    hipLaunchKernelGGL(k_atom_pack, dim3((unsigned)n_c), dim3(64), (size_t)n_species * sizeof(int32_t), s, plan, n_c,
+                       pa);
+  if (n_chunks > 0) {
+    const int64_t pack_blocks = fuse ? (n_c + kThreads / 64 - 1) / (kThreads / 64) : 0;
+    hipLaunchKernelGGL(k_enum_count, dim3((unsigned)(n_chunks + pack_blocks)), dim3(kThreads),
+                       fuse ? fused_lds : 0, s, plan, chunk_crystal, n_chunks, n_c, lambda, counts, pa);
+  }
   if (n_chunks <= kOneBlockChunks) {
     hipLaunchKernelGGL(k_enum_scan1, dim3(1), dim3(1024), 0, s, plan, n_c, n_chunks, counts, prefix, refl_offset);
   } else {

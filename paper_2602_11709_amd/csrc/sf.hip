@@ -41,100 +41,6 @@ constexpr int kThreads = 256;
 constexpr int kAtomTile = 64;  // atoms per single-precision partial sum
 constexpr float kLog2e = 1.4426950408889634f;
 
-// ---- atom packing ----------------------------------------------------------
-
-// One wavefront per crystal: species histogram in LDS, ascending-species
-// runs, then a stable scatter (peeling one species per step with a ballot).
-__global__ __launch_bounds__(64) void k_atom_prep(const CrystalPlan *__restrict__ plan, int32_t n_species,
-                                                  const double *__restrict__ frac, const int32_t *__restrict__ species,
-                                                  const double *__restrict__ occ, const double *__restrict__ bfac,
-                                                  AtomRec *__restrict__ atoms, int32_t *__restrict__ orig,
-                                                  SpeciesRun *__restrict__ runs, int32_t *__restrict__ run_count,
-                                                  int32_t *__restrict__ err) {
-  extern __shared__ int32_t cursor[];  // n_species
-  const int c = blockIdx.x;
-  const CrystalPlan &P = plan[c];
-  const int64_t a0 = P.atom_begin, a1 = P.atom_end;
-  const int lane = threadIdx.x;
-  for (int t = lane; t < n_species; t += 64) cursor[t] = 0;
-  __syncthreads();
-  for (int64_t j = a0 + lane; j < a1; j += 64) {
-    int sp = species[j];
-    if (sp < 0 || sp >= n_species) {
-      atomicOr(err, 1);
-      sp = 0;
-    }
-    atomicAdd(&cursor[sp], 1);
-  }
-  __syncthreads();
-  // ascending-species runs and cursors (exclusive scan of the histogram)
-  int64_t running = a0;
-  int nruns = 0;
-  for (int t0 = 0; t0 < n_species; t0 += 64) {
-    const int t = t0 + lane;
-    const int v = t < n_species ? cursor[t] : 0;
-    int inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      int o = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += o;
-    }
-    const int tot = __shfl(inc, 63, 64);
-    const uint64_t nz = __ballot(v > 0);
-    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(nz >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nz, 0u));
-    const int64_t start = running + inc - v;
-    if (v > 0) {
-      SpeciesRun r;
-      r.begin = (int32_t)start;
-      r.end = (int32_t)(start + v);
-      r.species = t;
-      r.local = nruns + rank;
-      runs[P.run_begin + nruns + rank] = r;
-    }
-    if (t < n_species) cursor[t] = (int32_t)start;
-    __syncthreads();
-    running += tot;
-    nruns += __popcll(nz);
-  }
-  if (lane == 0) run_count[c] = nruns;
-  __syncthreads();
-  for (int64_t base = a0; base < a1; base += 64) {
-    const int64_t j = base + lane;
-    bool active = j < a1;
-    int sp = -1;
-    if (active) {
-      sp = species[j];
-      if (sp < 0 || sp >= n_species) sp = 0;
-    }
-    while (true) {
-      const uint64_t act = __ballot(active);
-      if (act == 0) break;
-      const int leader = __builtin_ctzll(act);
-      const int t = __shfl(sp, leader, 64);
-      const uint64_t m = __ballot(active && sp == t);
-      const int base_pos = cursor[t];
-      __syncthreads();
-      if (active && sp == t) {
-        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        const int pos = base_pos + rank;
-        AtomRec a;
-        a.x = frac[3 * j];
-        a.y = frac[3 * j + 1];
-        a.z = frac[3 * j + 2];
-        a.occ = occ[j];
-        a.bfac = bfac[j];
-        a.log2occ = __log2f((float)a.occ);
-        a.bl2e = (float)a.bfac * kLog2e;
-        atoms[pos] = a;
-        orig[pos] = (int32_t)j;
-        active = false;
-      }
-      if (lane == leader) cursor[t] = base_pos + __popcll(m);
-      __syncthreads();
-    }
-  }
-}
-
 // ---- structure factors -----------------------------------------------------
 
 // Sum over the 64 lanes of a wavefront with DPP row shifts and row
@@ -613,7 +519,7 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
                                                     const double *__restrict__ w1,
                                                     const double *__restrict__ w2, double *__restrict__ ga,
                                                     double *__restrict__ gb, double *__restrict__ dq,
-                                                    double4 *__restrict__ part_fused) {
+                                                    double *__restrict__ part6, double4 *__restrict__ part_fused) {
   constexpr int R = kSfRpt;
   // heavy blocks without the kept derivatives: per wave, value (8 floats or
   // 4 doubles), reflection slot, lane
@@ -657,10 +563,10 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
   }
   const double m = friedel ? 2.0 : 1.0;
   const double l2 = lambda * lambda;
-  double gA[R], gB[R];
+  double gA[R], gB[R], dqv[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
-    gA[u] = gB[u] = 0.0;
+    gA[u] = gB[u] = dqv[u] = 0.0;
     if (!valid[u]) continue;
     const int64_t i = idx[u];
     const double q = qq[i], lp = lpp[i];
@@ -681,7 +587,32 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
       ga[i] = gA[u];
       gb[i] = gB[u];
     }
-    dq[i] = gI * f2 * dlp_dq + 0.25 * (gA[u] * dA[u] + gB[u] * dB[u]) + m * w2[i] * f2 * lp * dtt_dq;
+    dqv[u] = gI * f2 * dlp_dq + 0.25 * (gA[u] * dA[u] + gB[u] * dB[u]) + m * w2[i] * f2 * lp * dtt_dq;
+    dq[i] = dqv[u];
+  }
+  if (ww.part == 0) {
+    // the tile's row of dL/dG*: sum over its reflections of dL/dq times
+    // (h^2, k^2, l^2, 2hk, 2hl, 2kl), as q = sum_ij G*_ij h_i h_j
+    double r6[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) r6[e] = 0.0;
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      const double g = dqv[u];  // zero for lanes past the tile's end
+      r6[0] += g * h[u] * h[u];
+      r6[1] += g * k[u] * k[u];
+      r6[2] += g * l[u] * l[u];
+      r6[3] += 2.0 * g * h[u] * k[u];
+      r6[4] += 2.0 * g * h[u] * l[u];
+      r6[5] += 2.0 * g * k[u] * l[u];
+    }
+#pragma unroll
+    for (int e = 0; e < 6; ++e) r6[e] = wave_sum_to_63(r6[e]);
+    if (lane == 63) {
+      double *row = part6 + ((int64_t)P.tile_begin + it.tile) * 6;
+#pragma unroll
+      for (int e = 0; e < 6; ++e) row[e] = r6[e];
+    }
   }
   if (!P.fused) return;
   // Fused atom gradients (small crystals): walk the atoms again; for each atom
@@ -922,14 +853,12 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
 
 // Sum of the partials of each atom in a fixed order (tile order for fused
 // crystals, chunk order otherwise); scatter to the caller's atom order.
-__global__ __launch_bounds__(kThreads) void k_atom_bw_reduce(const AbItem *__restrict__ items, bool friedel,
-                                                             const CrystalPlan *__restrict__ plan,
-                                                             const int64_t *__restrict__ refl_offset,
-                                                             const double4 *__restrict__ part,
-                                                             const double4 *__restrict__ part_fused,
-                                                             const int32_t *__restrict__ orig,
-                                                             double *__restrict__ dfrac, double *__restrict__ dbfac) {
-  const AbItem it = items[blockIdx.x];
+__device__ __forceinline__ void atom_bw_reduce(const AbItem it, bool friedel, const CrystalPlan *__restrict__ plan,
+                                               const int64_t *__restrict__ refl_offset,
+                                               const double4 *__restrict__ part,
+                                               const double4 *__restrict__ part_fused,
+                                               const int32_t *__restrict__ orig, double *__restrict__ dfrac,
+                                               double *__restrict__ dbfac) {
   const CrystalPlan &P = plan[it.crystal];
   const int64_t na = P.atom_end - P.atom_begin;
   const int64_t ja = (int64_t)it.ablock * kAtomBlock + threadIdx.x;
@@ -1006,71 +935,34 @@ __device__ void lattice_chain(const CrystalPlan &P, const double *__restrict__ r
   o[5] = g12 * (-a * b * sg * rad);
 }
 
-// Per adjoint chunk: sum of dL/dq (h^2, k^2, l^2, 2hk, 2hl, 2kl), fixed-order block reduction.
-__global__ __launch_bounds__(kThreads) void k_gstar_part(const int32_t *__restrict__ hchunk_crystal, bool friedel,
-                                                         const CrystalPlan *__restrict__ plan,
-                                                         const int64_t *__restrict__ refl_offset,
-                                                         const int16_t *__restrict__ hh,
-                                                         const int16_t *__restrict__ kk,
-                                                         const int16_t *__restrict__ ll,
-                                                         const double *__restrict__ dq, double *__restrict__ part6) {
-  const int32_t c = hchunk_crystal[blockIdx.x];
-  const CrystalPlan &P = plan[c];
-  const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
-  const int64_t first = friedel ? r0 + (r1 - r0) / 2 : r0;
-  const int64_t count = friedel ? (r1 - r0) / 2 : r1 - r0;
-  const int64_t e0 = (int64_t)(blockIdx.x - P.hchunk_begin) * kHalfChunk;
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  for (int u = 0; u < kHalfChunk / kThreads; ++u) {
-    const int64_t e = e0 + u * kThreads + threadIdx.x;
-    if (e >= count) break;
-    const int64_t i = first + e;
-    const double g = dq[i], h = hh[i], k = kk[i], l = ll[i];
-    acc[0] += g * h * h;
-    acc[1] += g * k * k;
-    acc[2] += g * l * l;
-    acc[3] += 2.0 * g * h * k;
-    acc[4] += 2.0 * g * h * l;
-    acc[5] += 2.0 * g * k * l;
+// The last step of the adjoint, two independent parts in one launch: blocks
+// [0, n_ab) reduce the atom gradients (k_atom_bw_reduce's items), the rest
+// take one crystal per thread through the lattice chain rule, summing the
+// crystal's structure-factor tile rows of dL/dG* (the tiles that ran) in
+// order.
+__global__ __launch_bounds__(kThreads) void k_bw_finish(const AbItem *__restrict__ items, int64_t n_ab, bool friedel,
+                                                        const CrystalPlan *__restrict__ plan, int64_t n_c,
+                                                        const int64_t *__restrict__ refl_offset,
+                                                        const double4 *__restrict__ part,
+                                                        const double4 *__restrict__ part_fused,
+                                                        const int32_t *__restrict__ orig,
+                                                        const double *__restrict__ part6, double *__restrict__ dfrac,
+                                                        double *__restrict__ dbfac, double *__restrict__ dlat) {
+  if (blockIdx.x < n_ab) {
+    atom_bw_reduce(items[blockIdx.x], friedel, plan, refl_offset, part, part_fused, orig, dfrac, dbfac);
+    return;
   }
-  __shared__ double red[6][kThreads / 64];
-  for (int e = 0; e < 6; ++e) {
-    double v = acc[e];
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    if ((threadIdx.x & 63) == 0) red[e][threadIdx.x >> 6] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < 6) {
-    double v = 0.0;
-    for (int w = 0; w < kThreads / 64; ++w) v += red[threadIdx.x][w];
-    part6[(int64_t)blockIdx.x * 6 + threadIdx.x] = v;
-  }
-}
-
-// dL/d(lattice) of every crystal from its chunk rows.
-__global__ void k_lattice_chain(const CrystalPlan *__restrict__ plan, int64_t n_c, const double *__restrict__ part6,
-                                double *__restrict__ dlat) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = (int64_t)(blockIdx.x - n_ab) * kThreads + threadIdx.x;
   if (c >= n_c) return;
   const CrystalPlan &P = plan[c];
-  lattice_chain(P, part6 + (int64_t)P.hchunk_begin * 6, P.n_hchunks, dlat + 6 * c);
+  const int64_t nref = refl_offset[c + 1] - refl_offset[c];
+  const int64_t count = friedel ? nref / 2 : nref;
+  lattice_chain(P, part6 + (int64_t)P.tile_begin * 6, (int)((count + kSfTile - 1) / kSfTile), dlat + 6 * c);
 }
 
 }  // namespace
 
-void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s) {
-  if (n_c <= 0) return;
-  hipLaunchKernelGGL(k_lattice_chain, dim3((unsigned)((n_c + 255) / 256)), dim3(256), 0, s, plan, n_c, part6, dlat);
-}
 
-void launch_atom_prep(const CrystalPlan *plan, int64_t n_c, int32_t n_species, const double *frac,
-                      const int32_t *species, const double *occ, const double *bfac, AtomRec *atoms, int32_t *orig,
-                      SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s) {
-  if (n_c <= 0) return;
-  hipLaunchKernelGGL(k_atom_prep, dim3((unsigned)n_c), dim3(64), (size_t)n_species * sizeof(int32_t), s, plan,
-                     n_species, frac, species, occ, bfac, atoms, orig, runs, run_count, err);
-}
 
 template <bool MIXED, bool FRIEDEL, bool DERIV>
 static void launch_sf_t(dim3 grid, const SfItem *items, int64_t n_items, int64_t n_heavy, const CrystalPlan *plan,
@@ -1115,13 +1007,14 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
                   const int32_t *run_count, const double *coeff, const void *deriv_cache, const double *w1,
-                  const double *w2, double *ga, double *gb, double *dq, double *part_fused, hipStream_t s) {
+                  const double *w2, double *ga, double *gb, double *dq, double *part6, double *part_fused,
+                  hipStream_t s) {
   if (n_items <= 0) return;
   const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4)), block(kThreads);
   double4 *pf = (double4 *)part_fused;
 #define XRD_SF_BW(M, C)                                                                                          \
   hipLaunchKernelGGL((k_sf_bw<M, C>), grid, block, 0, s, items, n_items, n_heavy, friedel, plan, refl_offset, h, k, \
-                     l, q, lp, lambda, atoms, runs, run_count, coeff, deriv_cache, w1, w2, ga, gb, dq, pf)
+                     l, q, lp, lambda, atoms, runs, run_count, coeff, deriv_cache, w1, w2, ga, gb, dq, part6, pf)
   if (mixed) {
     if (deriv_cache)
       XRD_SF_BW(true, true);
@@ -1162,20 +1055,15 @@ void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_ite
                        (double4 *)part);
 }
 
-void launch_atom_bw_reduce(const AbItem *items, int64_t n_items, bool friedel, const CrystalPlan *plan,
-                           const int64_t *refl_offset, const double *part, const double *part_fused,
-                           const int32_t *orig, double *dfrac, double *dbfac, hipStream_t s) {
-  if (n_items <= 0) return;
-  hipLaunchKernelGGL(k_atom_bw_reduce, dim3((unsigned)n_items), dim3(kThreads), 0, s, items, friedel, plan,
-                     refl_offset, (const double4 *)part, (const double4 *)part_fused, orig, dfrac, dbfac);
+void launch_bw_finish(const AbItem *items, int64_t n_ab, bool friedel, const CrystalPlan *plan, int64_t n_c,
+                      const int64_t *refl_offset, const double *part, const double *part_fused, const int32_t *orig,
+                      const double *part6, double *dfrac, double *dbfac, double *dlat, hipStream_t s) {
+  const int64_t blocks = n_ab + (n_c + kThreads - 1) / kThreads;
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(k_bw_finish, dim3((unsigned)blocks), dim3(kThreads), 0, s, items, n_ab, friedel, plan, n_c,
+                     refl_offset, (const double4 *)part, (const double4 *)part_fused, orig, part6, dfrac, dbfac,
+                     dlat);
 }
 
-void launch_gstar_part(const int32_t *hchunk_crystal, int64_t n_hchunks, bool friedel, const CrystalPlan *plan,
-                       const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
-                       const double *dq, double *part6, hipStream_t s) {
-  if (n_hchunks <= 0) return;
-  hipLaunchKernelGGL(k_gstar_part, dim3((unsigned)n_hchunks), dim3(kThreads), 0, s, hchunk_crystal, friedel, plan,
-                     refl_offset, h, k, l, dq, part6);
-}
 
 }  // namespace xrd

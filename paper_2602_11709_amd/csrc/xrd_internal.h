@@ -26,6 +26,7 @@ constexpr int kSplitAtoms = 24;      // crystals from this size get a block per 
 constexpr int kSmallSort = 4096;     // Friedel-positive reflections sorted in LDS by one 256-thread block
 constexpr int kMidSort = 12288;      // ... by one 512-thread block
 constexpr int kSpanPts = 64;         // grid points per wave of the broadening gather
+constexpr int kEntSlack = 8;         // entries of slack after the sorted entry arrays (batched reads)
 
 // Per-crystal plan (device copy in the workspace), 256 bytes.
 struct alignas(16) CrystalPlan {
@@ -50,7 +51,7 @@ struct alignas(16) CrystalPlan {
   int32_t fused;       // 1: atom gradients reduced inside the reflection-major adjoint
   int64_t pf_begin;    // first row of the fused adjoint partials: rows = n_tiles * N
   int32_t n_tiles;     // structure-factor tiles at capacity
-  int32_t pad0;
+  int32_t tile_begin;  // first row of this crystal's per-tile dL/dG* rows
 };
 static_assert(sizeof(CrystalPlan) == 256, "CrystalPlan layout");
 
@@ -110,12 +111,14 @@ struct AbItem {
   int32_t crystal, ablock;
 };
 
+// Enumeration (count, scan, fill) and, in the same launches, the packing of
+// the atoms into species runs for the structure-factor kernels.
 void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk_crystal, int64_t n_chunks,
                       double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h, int16_t *k,
-                      int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset, hipStream_t s);
-void launch_atom_prep(const CrystalPlan *plan, int64_t n_c, int32_t n_species, const double *frac,
-                      const int32_t *species, const double *occ, const double *bfac, AtomRec *atoms, int32_t *orig,
-                      SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s);
+                      int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset, int32_t n_species,
+                      const double *frac, const int32_t *species, const double *occ, const double *bfac,
+                      AtomRec *atoms, int32_t *orig, SpeciesRun *runs, int32_t *run_count, int32_t *err,
+                      hipStream_t s);
 // Items: the first n_heavy take a block each (atoms split over its four
 // wavefronts), the rest one wavefront each.  A non-null deriv_cache
 // ([refl_cap] float4 under mixed precision, else double4) receives
@@ -184,20 +187,19 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
                   const int32_t *run_count, const double *coeff, const void *deriv_cache, const double *w1,
-                  const double *w2, double *ga, double *gb, double *dq, double *part_fused, hipStream_t s);
+                  const double *w2, double *ga, double *gb, double *dq, double *part6, double *part_fused,
+                  hipStream_t s);
 size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap);
 void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,
                     const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
                     const double *q, const double *ga, const double *gb, const AtomRec *atoms,
                     const SpeciesRun *runs, const int32_t *run_count, const double *coeff, int tile, int runs_cap,
                     double *part, hipStream_t s);
-void launch_atom_bw_reduce(const AbItem *items, int64_t n_items, bool friedel, const CrystalPlan *plan,
-                           const int64_t *refl_offset, const double *part, const double *part_fused,
-                           const int32_t *orig, double *dfrac, double *dbfac, hipStream_t s);
-// Per-chunk dL/dG* rows, then the chain rule to dL/d(lattice) per crystal.
-void launch_gstar_part(const int32_t *hchunk_crystal, int64_t n_hchunks, bool friedel, const CrystalPlan *plan,
-                       const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
-                       const double *dq, double *part6, hipStream_t s);
-void launch_lattice_chain(const CrystalPlan *plan, int64_t n_c, const double *part6, double *dlat, hipStream_t s);
+// Atom gradients reduced over their partial rows and scattered to the
+// caller's order, and, in the same launch, dL/d(lattice) of every crystal
+// from its per-tile dL/dG* rows (written by launch_sf_bw).
+void launch_bw_finish(const AbItem *items, int64_t n_ab, bool friedel, const CrystalPlan *plan, int64_t n_c,
+                      const int64_t *refl_offset, const double *part, const double *part_fused, const int32_t *orig,
+                      const double *part6, double *dfrac, double *dbfac, double *dlat, hipStream_t s);
 
 }  // namespace xrd

@@ -127,3 +127,16 @@ def test_threshold_drops_weak_peaks():
         assert np.max(np.abs(res.pk_two_theta[ps] - orc.pk_tt), initial=0) <= 1e-9
         np.testing.assert_allclose(res.pk_intensity[ps], orc.pk_i, rtol=1e-10)
         np.testing.assert_allclose(res.pk_scaled[ps], orc.pk_y, rtol=1e-10)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_many_species_packs_atoms_in_their_own_launch(precision):
+    """A species table of 300 rows (above what the enumeration launch carries
+    for packing the atoms) takes the separate packing launch; crystals draw
+    up to 40 species each, so their runs are short and many."""
+    b = synth.random_triclinic(41, 10, atoms_lo=20, atoms_hi=90, species_per_crystal=40, pool=300)
+    res = run(b, precision)
+    orcs = [oracle.pattern(b, c) for c in range(b.n_crystals)]
+    worst = compare_batch(res, b, orcs, precision, "many species")
+    assert worst["ambiguous"] == 0
+    print(precision, worst, flush=True)
