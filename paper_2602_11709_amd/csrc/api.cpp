@@ -361,13 +361,13 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.err_flag = take(4);
   L.bin_count = take(4 * bins);
   L.bin_start = take(8 * (bins + 1));
-  L.skey = take(8 * (rc + kEntSlack));
+  L.skey = take(8 * rc);
   L.sidx = take(4 * rc);
   // entries (evaluated reflections in 2theta order): their own arrays under
   // Friedel pairing, the full sorted list otherwise
-  L.ent_key = friedel ? take(8 * (b->half_cap + kEntSlack)) : L.skey;
+  L.ent_key = friedel ? take(8 * b->half_cap) : L.skey;
   L.ent_idx = friedel ? take(4 * b->half_cap) : L.sidx;
-  L.ent_w = take(8 * ((friedel ? b->half_cap : rc) + kEntSlack));
+  L.ent_w = take(8 * (friedel ? b->half_cap : rc));
   L.span_first = take(4 * nc * b->span_cap);
   L.span_last = take(4 * nc * b->span_cap);
   L.flags = take(4 * rc);

@@ -39,24 +39,25 @@ struct GridArgs {
 // is monotone in g).  Empty when lo > hi.
 __device__ __forceinline__ void window_of(const GridArgs &g, double t, int64_t *lo, int64_t *hi) {
 #pragma clang fp contract(off)
-  int64_t a = (int64_t)ceil((t - g.half - g.t0) * g.inv_dt);
-  int64_t b = (int64_t)floor((t + g.half - g.t0) * g.inv_dt);
+  // grid indices are carried as doubles (exact integers here): the
+  // estimates, clamped to [-2, n + 1] so that the settling steps stay few
+  const double n = (double)g.n;
+  double a = fmin(fmax(ceil((t - g.half - g.t0) * g.inv_dt), -2.0), n + 1.0);
+  double b = fmin(fmax(floor((t + g.half - g.t0) * g.inv_dt), -2.0), n + 1.0);
   // the estimates (a product with the rounded reciprocal) are off by at most
   // one step either way; settle them with the exact test
-  while (a > 0 && fabs(g.t0 + (double)(a - 1) * g.dt - t) <= g.half) --a;
-  while (a <= b && fabs(g.t0 + (double)a * g.dt - t) > g.half) ++a;
-  while (b + 1 < g.n && fabs(g.t0 + (double)(b + 1) * g.dt - t) <= g.half) ++b;
-  while (b >= a && fabs(g.t0 + (double)b * g.dt - t) > g.half) --b;
-  if (a < 0) a = 0;
-  if (b > g.n - 1) b = g.n - 1;
-  *lo = a;
-  *hi = b;
+  while (a > 0.0 && fabs(g.t0 + (a - 1.0) * g.dt - t) <= g.half) a -= 1.0;
+  while (a <= b && fabs(g.t0 + a * g.dt - t) > g.half) a += 1.0;
+  while (b + 1.0 < n && fabs(g.t0 + (b + 1.0) * g.dt - t) <= g.half) b += 1.0;
+  while (b >= a && fabs(g.t0 + b * g.dt - t) > g.half) b -= 1.0;
+  *lo = (int64_t)fmax(a, 0.0);
+  *hi = (int64_t)fmin(b, n - 1.0);
 }
 
 constexpr int kEntBlock = 1024;                // entries per block of the preparation and the adjoint
 constexpr int kEntSplit = kHalfChunk / kEntBlock;  // such blocks per chunk of kHalfChunk entries
 constexpr int kSegPts = 1024;                  // grid points per gather block (4 per thread)
-static_assert(kEntSlack == 8, "the gather reads entries in batches of kEntSlack");
+constexpr int kGTile = 1024;                   // entries per LDS tile of the gather
 constexpr int kAdjSpan = 4096;                 // grid points of dL/dy an adjoint block stages in LDS
 static_assert(kSegPts == 16 * kSpanPts, "a gather block covers 16 spans, four per wave");
 
@@ -82,11 +83,22 @@ __device__ __forceinline__ int2 window32(const GridArgs &g, double t) {
   return make_int2((int)min(lo, g.n), (int)max(hi, (int64_t)-1));
 }
 
+// A window one step wider on each side than window_of's, from the rounded
+// quotients alone (no exact tests), clamped like window32.  Nondecreasing in
+// t; the forward uses it only to choose which entries a span walks, and the
+// lanes' own |x - t| <= half test decides each point.
+__device__ __forceinline__ int2 window_wide(const GridArgs &g, double t) {
+  const double u = (t - g.t0) * g.inv_dt, hw = g.half * g.inv_dt, n = (double)g.n;
+  const double lo = fmin(fmax(floor(u - hw) - 1.0, 0.0), n);
+  const double hi = fmin(fmax(ceil(u + hw) + 1.0, -1.0), n - 1.0);
+  return make_int2((int)lo, (int)hi);
+}
+
 // Entry preparation, one block per kEntBlock entries of a crystal: the
 // weight w_e = m I norm of every entry, and the entry ranges of the
 // crystal's spans of kSpanPts grid points:
 //   first[s] = min{e : gh_e >= 64 s},  last[s] = max{e : gl_e <= 64 s + 63},
-// with [gl_e, gh_e] the (clamped) window of entry e.  Both ends are
+// with [gl_e, gh_e] the (clamped, one step wide) window of entry e.  Both ends are
 // nondecreasing in e, so entry e owns first[s] for s in
 // (gh_{e-1} / 64, gh_e / 64] and last[s] for s in [gl_e / 64, gl_{e+1} / 64)
 // (integer floors), the first and last entries also own the spans beyond;
@@ -132,13 +144,13 @@ __global__ __launch_bounds__(256) void k_entry_prep(const int32_t *__restrict__ 
   for (int u = 0; u < U; ++u) {
     const int64_t e = e0 + u * 256 + threadIdx.x;
     if (e < e1) {
-      const int2 w = window32(g, key[u]);
+      const int2 w = window_wide(g, key[u]);
       s_gl[e - e0 + 1] = w.x;
       s_gh[e - e0 + 1] = w.y;
     }
   }
   if (has_halo) {
-    const int2 w = window32(g, halo);
+    const int2 w = window_wide(g, halo);
     s_gl[eh - e0 + 1] = w.x;
     s_gh[eh - e0 + 1] = w.y;
   }
@@ -171,11 +183,11 @@ __global__ __launch_bounds__(256) void k_entry_prep(const int32_t *__restrict__ 
 
 // Forward gather: a block owns kSegPts consecutive grid points of one
 // crystal, each lane four of them, 256 apart, so that wave w of the block
-// covers spans 4j + w (j = 0..3) of the segment.  For each of its spans a
-// wave walks that span's entry range in 2theta order; the entries' keys and
-// weights are read at wave-uniform addresses (scalar loads into SGPRs, eight
-// entries per batch, so no LDS staging or barrier is needed) and each lane
-// adds w K(x - 2theta) when its point lies in the entry's window (the same
+// covers spans 4j + w (j = 0..3) of the segment.  The entries reaching the
+// segment (first of its first span .. last of its last span) are staged in
+// LDS in tiles; each wave walks, for each of its spans, that span's entry
+// range in 2theta order with wave-uniform LDS reads, and each lane adds
+// w K(x - 2theta) when its point lies in the entry's window (the same
 // |x - 2theta| <= half test that defines the window), so every point sums
 // exactly its reflections, in sorted order, deterministically.  The offset
 // x - 2theta and the window test are double precision in both paths; under
@@ -193,7 +205,11 @@ __global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restric
                                                         GridArgs g, double *__restrict__ y) {
 #pragma clang fp contract(off)
   using real = typename std::conditional<MIXED, float, double>::type;
-  constexpr int kB = kEntSlack;  // entries per batch of scalar loads
+  struct Ent {
+    double t;
+    real w;
+  };
+  __shared__ Ent s_ent[kGTile];
   const int S = (int)((g.n + kSpanPts - 1) / kSpanPts);
   const int segs = (int)((g.n + kSegPts - 1) / kSegPts);
   const int64_t c = crystal_order[blockIdx.x / segs];
@@ -203,78 +219,58 @@ __global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restric
   const EntryRange er = entry_range(refl_offset, c, friedel);
   const int32_t *__restrict__ fs = span_first + c * span_cap;
   const int32_t *__restrict__ ls = span_last + c * span_cap;
-  const double *__restrict__ kp = ent_key + er.base;
-  const real *__restrict__ wp = reinterpret_cast<const real *>(ent_w) + er.base;
-  const float c2 = (float)(g.inv2s2 * 1.4426950408889634);
-  auto add = [&](double x, double t, real w, real &acc) {
-    const double d = x - t;
-    if (fabs(d) <= g.half) {
-      if constexpr (MIXED) {
-        const float df = (float)d;
-        acc = __builtin_fmaf(w, __builtin_amdgcn_exp2f(-(df * df) * c2), acc);
-      } else {
-        acc += w * exp(-(d * d) * g.inv2s2);
-      }
-    }
-  };
-#pragma unroll 1
+  // entry ranges of the wave's spans (empty for spans past the grid's end)
+  int f[4], l[4];
+#pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int s = sb + 4 * j + wid;
-    if (s > se) break;
-    const int f = max(fs[s], 0);
-    const int l = (int)min((int64_t)ls[s], er.count - 1);
-    const int64_t p = (int64_t)s * kSpanPts + (threadIdx.x & 63);
-    const double x = g.t0 + (double)p * g.dt;
-    real acc = 0;
-    int e = f;
-    // full batches, the next one's loads issued before this one's arithmetic
-    if (e + kB - 1 <= l) {
-      double t[kB];
-      real w[kB];
+    f[j] = s <= se ? max(fs[s], 0) : 0;
+    l[j] = s <= se ? (int)min((int64_t)ls[s], er.count - 1) : -1;
+  }
+  const int E0 = max(fs[sb], 0);
+  const int E1 = (int)min((int64_t)ls[se], er.count - 1);
+  double x[4];
+  real acc[4];
 #pragma unroll
-      for (int i = 0; i < kB; ++i) {
-        t[i] = kp[e + i];
-        w[i] = wp[e + i];
-      }
-      for (;;) {
-        const bool next_full = e + 2 * kB - 1 <= l;
-        const int en = next_full ? e + kB : e;  // a full batch either way
-        double tn[kB];
-        real wn[kB];
+  for (int j = 0; j < 4; ++j) {
+    x[j] = g.t0 + (double)((int64_t)sb * kSpanPts + j * 256 + threadIdx.x) * g.dt;
+    acc[j] = 0;
+  }
+  const real *__restrict__ wts = reinterpret_cast<const real *>(ent_w);
+  const float c2 = (float)(g.inv2s2 * 1.4426950408889634);
+  for (int T0 = E0; T0 <= E1; T0 += kGTile) {
+    const int T1 = min(T0 + kGTile - 1, E1);
 #pragma unroll
-        for (int i = 0; i < kB; ++i) {
-          tn[i] = kp[en + i];
-          wn[i] = wp[en + i];
-        }
-#pragma unroll
-        for (int i = 0; i < kB; ++i) add(x, t[i], w[i], acc);
-        e += kB;
-        if (!next_full) break;
-#pragma unroll
-        for (int i = 0; i < kB; ++i) {
-          t[i] = tn[i];
-          w[i] = wn[i];
-        }
-      }
+    for (int k = 0; k < kGTile / 256; ++k) {
+      const int e = T0 + k * 256 + (int)threadIdx.x;
+      if (e <= T1) s_ent[e - T0] = Ent{ent_key[er.base + e], wts[er.base + e]};
     }
-    // the last partial batch: the kB entries ending at l (from 0 if l is
-    // smaller; the entry arrays carry kB entries of slack at their end, so
-    // every read is in bounds), those before e or past l weighted zero,
-    // which adds exactly nothing (a key that is not a reflection of this
-    // crystal either fails the window test or meets a zero weight)
-    if (e <= l) {
-      const int tb = max(l - (kB - 1), 0);
-      double t[kB];
-      real w[kB];
+    __syncthreads();
 #pragma unroll
-      for (int i = 0; i < kB; ++i) {
-        t[i] = kp[tb + i];
-        w[i] = wp[tb + i];
+    for (int j = 0; j < 4; ++j) {
+      const int a = max(f[j], T0) - T0, b = min(l[j], T1) - T0;
+      real sacc = acc[j];
+#pragma unroll 8
+      for (int e = a; e <= b; ++e) {
+        const Ent ent = s_ent[e];
+        const double d = x[j] - ent.t;
+        if (fabs(d) <= g.half) {
+          if constexpr (MIXED) {
+            const float df = (float)d;
+            sacc = __builtin_fmaf(ent.w, __builtin_amdgcn_exp2f(-(df * df) * c2), sacc);
+          } else {
+            sacc += ent.w * exp(-(d * d) * g.inv2s2);
+          }
+        }
       }
-#pragma unroll
-      for (int i = 0; i < kB; ++i) add(x, t[i], (tb + i >= e && tb + i <= l) ? w[i] : (real)0, acc);
+      acc[j] = sacc;
     }
-    if (p < g.n) y[c * g.n + p] = (double)acc;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t p = (int64_t)sb * kSpanPts + j * 256 + threadIdx.x;
+    if (p < g.n) y[c * g.n + p] = (double)acc[j];
   }
 }
 

@@ -26,7 +26,6 @@ constexpr int kSplitAtoms = 24;      // crystals from this size get a block per 
 constexpr int kSmallSort = 4096;     // Friedel-positive reflections sorted in LDS by one 256-thread block
 constexpr int kMidSort = 12288;      // ... by one 512-thread block
 constexpr int kSpanPts = 64;         // grid points per wave of the broadening gather
-constexpr int kEntSlack = 8;         // entries of slack after the sorted entry arrays (batched reads)
 
 // Per-crystal plan (device copy in the workspace), 256 bytes.
 struct alignas(16) CrystalPlan {
