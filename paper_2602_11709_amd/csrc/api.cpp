@@ -27,7 +27,8 @@ struct xrd_batch {
   std::vector<double> lattice, tmin, tmax;
   std::vector<int64_t> atom_offset;
   std::vector<CrystalPlan> plan;
-  std::vector<int32_t> enum_chunk_crystal, sort_chunk_crystal, hchunk_crystal;
+  std::vector<int32_t> enum_chunk_crystal, sort_chunk_crystal;
+  std::vector<HChunk> hchunks;  // entry chunks of the broadening (crystal, chunk)
   std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
   std::vector<SfItem> sf_items;
   std::vector<BwItem> bw_items;
@@ -216,7 +217,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
       return fail(XRD_ERR_CAPACITY, "reflection capacity exceeds 2^31; split the batch");
     }
     P.enum_chunk_begin = ec;
-    P.enum_chunks = (int32_t)ceil_div(P.half_box, kEnumChunk);
+    P.enum_chunks = (int32_t)ceil_div((int64_t)P.H * (2 * P.K + 1) + P.K + 1, kEnumRows);
     ec += P.enum_chunks;
     P.sort_chunk_begin = sc;
     P.sort_chunks = (int32_t)ceil_div(2 * P.half_box, kSortChunk);
@@ -270,18 +271,45 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   // launch tables
   b->enum_chunk_crystal.resize(ec);
   b->sort_chunk_crystal.resize(sc);
-  b->hchunk_crystal.resize(hc);
   for (int64_t c = 0; c < nc; ++c) {
     const CrystalPlan &P = b->plan[c];
     for (int32_t i = 0; i < P.enum_chunks; ++i) b->enum_chunk_crystal[P.enum_chunk_begin + i] = (int32_t)c;
     for (int32_t i = 0; i < P.sort_chunks; ++i) b->sort_chunk_crystal[P.sort_chunk_begin + i] = (int32_t)c;
-    for (int32_t i = 0; i < P.n_hchunks; ++i) b->hchunk_crystal[P.hchunk_begin + i] = (int32_t)c;
   }
+  // Capacities come from the search box; the reflections a crystal actually
+  // has are close to the lattice points of its spherical shell, (4 pi / 3)
+  // (g_max^3 - g_min^3) V (both halves).  The launch tables list first the
+  // work units this count (plus 5%) fills and then the rest, which mostly
+  // find nothing to do and end at once.
+  std::vector<double> expect_eval(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const CrystalPlan &P = b->plan[c];
+    const double *lat = b->lattice.data() + 6 * c;
+    const double r = kPi / 180.0, ca = std::cos(lat[3] * r), cb = std::cos(lat[4] * r), cg = std::cos(lat[5] * r);
+    const double vol =
+        lat[0] * lat[1] * lat[2] * std::sqrt(std::max(0.0, 1 - ca * ca - cb * cb - cg * cg + 2 * ca * cb * cg));
+    const double ghi = std::sqrt(P.qhi), glo = std::sqrt(P.qlo);
+    const double shell = 4.0 * kPi / 3.0 * (ghi * ghi * ghi - glo * glo * glo) * vol;
+    expect_eval[c] = (friedel ? 0.5 : 1.0) * shell * 1.05;
+  }
+  auto likely_units = [&](int64_t c, int64_t unit, int64_t cap) {
+    return (int32_t)std::min<double>((double)cap, std::ceil((expect_eval[c] + unit) / unit));
+  };
   // gather order: crystals by descending capacity (their broadening cost)
   b->crystal_order.resize(nc);
   for (int64_t c = 0; c < nc; ++c) b->crystal_order[c] = (int32_t)c;
   std::stable_sort(b->crystal_order.begin(), b->crystal_order.end(),
                    [&](int32_t x, int32_t y) { return b->plan[x].half_box > b->plan[y].half_box; });
+  // entry chunks, heaviest crystals first, expected-filled chunks before the rest
+  {
+    std::vector<int32_t> split(nc);
+    for (int32_t c : b->crystal_order) {
+      split[c] = likely_units(c, kHalfChunk, b->plan[c].n_hchunks);
+      for (int32_t i = 0; i < split[c]; ++i) b->hchunks.push_back(HChunk{c, i});
+    }
+    for (int32_t c : b->crystal_order)
+      for (int32_t i = split[c]; i < b->plan[c].n_hchunks; ++i) b->hchunks.push_back(HChunk{c, i});
+  }
   // structure-factor items: crystals in descending atom count (the cost of
   // one item), so the heaviest work is dispatched first
   std::vector<int64_t> order(nc);
@@ -301,22 +329,10 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
         for (int32_t k = 0; k < P.n_hchunks; ++k) b->bw_items.push_back(BwItem{(int32_t)c, (int32_t)a, k, 0});
     }
   }
-  // structure-factor tiles, heavy crystals first (a block per tile).  Tiles
-  // are planned at capacity (the search box), and the later ones of a
-  // crystal are empty once its reflections run out; each group lists first
-  // the tiles the shell's expected reflection count fills, crystal by
-  // crystal (neighbouring waves share the crystal's atoms in cache), then
-  // the rest, which mostly find no work and end at once.
-  auto likely_tiles = [&](int64_t c) {
-    const CrystalPlan &P = b->plan[c];
-    const double *lat = b->lattice.data() + 6 * c;
-    const double r = kPi / 180.0, ca = std::cos(lat[3] * r), cb = std::cos(lat[4] * r), cg = std::cos(lat[5] * r);
-    const double vol = lat[0] * lat[1] * lat[2] * std::sqrt(std::max(0.0, 1 - ca * ca - cb * cb - cg * cg + 2 * ca * cb * cg));
-    const double ghi = std::sqrt(P.qhi), glo = std::sqrt(P.qlo);
-    const double shell = 4.0 * kPi / 3.0 * (ghi * ghi * ghi - glo * glo * glo) * vol;  // lattice points, both halves
-    const double eval = (friedel ? 0.5 : 1.0) * shell * 1.05 + kSfTile;
-    return (int32_t)std::min<double>(P.n_tiles, std::ceil(eval / kSfTile));
-  };
+  // structure-factor tiles, heavy crystals first (a block per tile), each
+  // group listing the expected-filled tiles crystal by crystal (neighbouring
+  // waves share the crystal's atoms in cache), then the rest
+  auto likely_tiles = [&](int64_t c) { return likely_units(c, kSfTile, b->plan[c].n_tiles); };
   auto emit = [&](const std::vector<int64_t> &group) {
     std::vector<int32_t> split(group.size());
     for (size_t i = 0; i < group.size(); ++i) {
@@ -348,7 +364,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.enum_chunk_crystal = take(4 * ec);
   L.sf_items = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items.size());
   L.sort_chunk_crystal = take(4 * sc);
-  L.hchunk_crystal = take(4 * hc);
+  L.hchunks = take((int64_t)sizeof(HChunk) * hc);
   L.crystal_order = take(4 * nc);
   L.bw_items = take((int64_t)sizeof(BwItem) * (int64_t)b->bw_items.size());
   L.ab_items = take((int64_t)sizeof(AbItem) * (int64_t)b->ab_items.size());
@@ -419,7 +435,7 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   if (e == hipSuccess) e = up(L.enum_chunk_crystal, b->enum_chunk_crystal.data(), 4 * b->enum_chunk_crystal.size());
   if (e == hipSuccess) e = up(L.sf_items, b->sf_items.data(), sizeof(SfItem) * b->sf_items.size());
   if (e == hipSuccess) e = up(L.sort_chunk_crystal, b->sort_chunk_crystal.data(), 4 * b->sort_chunk_crystal.size());
-  if (e == hipSuccess) e = up(L.hchunk_crystal, b->hchunk_crystal.data(), 4 * b->hchunk_crystal.size());
+  if (e == hipSuccess) e = up(L.hchunks, b->hchunks.data(), sizeof(HChunk) * b->hchunks.size());
   if (e == hipSuccess) e = up(L.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
   if (e == hipSuccess) e = up(L.bw_items, b->bw_items.data(), sizeof(BwItem) * b->bw_items.size());
   if (e == hipSuccess) e = up(L.ab_items, b->ab_items.data(), sizeof(AbItem) * b->ab_items.size());
@@ -567,8 +583,8 @@ int xrd_pattern_forward(xrd_batch *b, void *ws, const xrd_refl *r, const double 
     return fail(XRD_ERR_INVALID_ARG, "n_points exceeds the batch's grid_capacity (" + std::to_string(b->grid_cap) + ")");
   ensure_sorted(b, ws, r);
   const WsLayout &L = b->ws;
-  launch_broaden_fwd(b->desc.precision == XRD_MIXED, at<int32_t>(ws, L.hchunk_crystal),
-                     (int64_t)b->hchunk_crystal.size(), at<CrystalPlan>(ws, L.plan),
+  launch_broaden_fwd(b->desc.precision == XRD_MIXED, at<HChunk>(ws, L.hchunks),
+                     (int64_t)b->hchunks.size(), at<CrystalPlan>(ws, L.plan),
                      at<int32_t>(ws, L.crystal_order), b->desc.n_crystals,
                      b->desc.friedel != 0, r->refl_offset, at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), I,
                      g->t0, g->dt, g->n_points, g->sigma, g->window_sigmas, b->span_cap, at<double>(ws, L.ent_w),
@@ -595,7 +611,7 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   double *ga = at<double>(ws, L.bw_ga), *gb = at<double>(ws, L.bw_gb), *dq = at<double>(ws, L.bw_dq);
   ensure_sorted(b, ws, r);
   const void *deriv = (L.sf_deriv >= 0 && b->deriv_ws == ws && b->deriv_h == r->h) ? at<char>(ws, L.sf_deriv) : nullptr;
-  launch_broaden_adj(mixed, at<int32_t>(ws, L.hchunk_crystal), (int64_t)b->hchunk_crystal.size(), plan, friedel,
+  launch_broaden_adj(mixed, at<HChunk>(ws, L.hchunks), (int64_t)b->hchunks.size(), plan, friedel,
                      r->refl_offset, at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), dL_dy, g->t0, g->dt,
                      g->n_points, g->sigma, g->window_sigmas, w1, w2, s);
   launch_sf_bw(mixed, friedel, items, n_items, b->sf_heavy, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,

@@ -104,7 +104,7 @@ __device__ __forceinline__ int2 window_wide(const GridArgs &g, double t) {
 // (integer floors), the first and last entries also own the spans beyond;
 // every span of a crystal with entries is written exactly once.
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_entry_prep(const int32_t *__restrict__ hchunk_crystal,
+__global__ __launch_bounds__(256) void k_entry_prep(const HChunk *__restrict__ hchunks,
                                                     const CrystalPlan *__restrict__ plan, bool friedel,
                                                     const int64_t *__restrict__ refl_offset,
                                                     const double *__restrict__ ent_key,
@@ -115,10 +115,10 @@ __global__ __launch_bounds__(256) void k_entry_prep(const int32_t *__restrict__ 
 #pragma clang fp contract(off)
   __shared__ int32_t s_gl[kEntBlock + 2], s_gh[kEntBlock + 2];
   const int hc = blockIdx.x / kEntSplit, sub = blockIdx.x % kEntSplit;
-  const int32_t c = hchunk_crystal[hc];
-  const CrystalPlan &P = plan[c];
+  const HChunk hk = hchunks[hc];
+  const int32_t c = hk.crystal;
   const EntryRange er = entry_range(refl_offset, c, friedel);
-  const int64_t e0 = (int64_t)(hc - P.hchunk_begin) * kHalfChunk + (int64_t)sub * kEntBlock;
+  const int64_t e0 = (int64_t)hk.chunk * kHalfChunk + (int64_t)sub * kEntBlock;
   if (e0 >= er.count) return;
   const int64_t e1 = min(e0 + (int64_t)kEntBlock, er.count);
   const int S = (int)((g.n + kSpanPts - 1) / kSpanPts);
@@ -309,7 +309,7 @@ __device__ __forceinline__ void adj_walk(const src_t *__restrict__ src, int off,
 }
 
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_broaden_adj(const int32_t *__restrict__ hchunk_crystal,
+__global__ __launch_bounds__(256) void k_broaden_adj(const HChunk *__restrict__ hchunks,
                                                      const CrystalPlan *__restrict__ plan, bool friedel,
                                                      const int64_t *__restrict__ refl_offset,
                                                      const double *__restrict__ ent_key,
@@ -322,10 +322,10 @@ __global__ __launch_bounds__(256) void k_broaden_adj(const int32_t *__restrict__
   __shared__ int32_t s_span[2];
   constexpr int U = kEntBlock / 256;
   const int hc = blockIdx.x / kEntSplit, sub = blockIdx.x % kEntSplit;
-  const int32_t c = hchunk_crystal[hc];
-  const CrystalPlan &P = plan[c];
+  const HChunk hk = hchunks[hc];
+  const int32_t c = hk.crystal;
   const EntryRange er = entry_range(refl_offset, c, friedel);
-  const int64_t e0 = (int64_t)(hc - P.hchunk_begin) * kHalfChunk + (int64_t)sub * kEntBlock;
+  const int64_t e0 = (int64_t)hk.chunk * kHalfChunk + (int64_t)sub * kEntBlock;
   if (e0 >= er.count) return;
   const int ne = (int)min((int64_t)kEntBlock, er.count - e0);
   double t[U];
@@ -390,7 +390,7 @@ GridArgs make_grid(double t0, double dt, int64_t n, double sigma, double window)
 
 }  // namespace
 
-void launch_broaden_fwd(bool mixed, const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan,
+void launch_broaden_fwd(bool mixed, const HChunk *hchunks, int64_t n_hchunks, const CrystalPlan *plan,
                         const int32_t *crystal_order, int64_t n_c, bool friedel, const int64_t *refl_offset, const double *ent_key,
                         const int32_t *ent_idx, const double *inten, double t0, double dt, int64_t n, double sigma,
                         double window, int64_t span_cap, double *ent_w, int32_t *span_first, int32_t *span_last,
@@ -399,12 +399,12 @@ void launch_broaden_fwd(bool mixed, const int32_t *hchunk_crystal, int64_t n_hch
   const GridArgs g = make_grid(t0, dt, n, sigma, window);
   if (n_hchunks > 0) {
     if (mixed)
-      hipLaunchKernelGGL(k_entry_prep<true>, dim3((unsigned)(n_hchunks * kEntSplit)), dim3(256), 0, s, hchunk_crystal,
+      hipLaunchKernelGGL(k_entry_prep<true>, dim3((unsigned)(n_hchunks * kEntSplit)), dim3(256), 0, s, hchunks,
                          plan, friedel, refl_offset, ent_key, ent_idx, inten, g, span_cap, ent_w, span_first,
                          span_last);
     else
       hipLaunchKernelGGL(k_entry_prep<false>, dim3((unsigned)(n_hchunks * kEntSplit)), dim3(256), 0, s,
-                         hchunk_crystal, plan, friedel, refl_offset, ent_key, ent_idx, inten, g, span_cap, ent_w,
+                         hchunks, plan, friedel, refl_offset, ent_key, ent_idx, inten, g, span_cap, ent_w,
                          span_first, span_last);
   }
   const dim3 grid((unsigned)(n_c * ((n + kSegPts - 1) / kSegPts))), block(256);
@@ -416,7 +416,7 @@ void launch_broaden_fwd(bool mixed, const int32_t *hchunk_crystal, int64_t n_hch
                        ent_w, span_first, span_last, span_cap, g, y);
 }
 
-void launch_broaden_adj(bool mixed, const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan,
+void launch_broaden_adj(bool mixed, const HChunk *hchunks, int64_t n_hchunks, const CrystalPlan *plan,
                         bool friedel, const int64_t *refl_offset, const double *ent_key, const int32_t *ent_idx,
                         const double *dy, double t0, double dt, int64_t n, double sigma, double window, double *w1,
                         double *w2, hipStream_t s) {
@@ -424,10 +424,10 @@ void launch_broaden_adj(bool mixed, const int32_t *hchunk_crystal, int64_t n_hch
   const GridArgs g = make_grid(t0, dt, n, sigma, window);
   const dim3 grid((unsigned)(n_hchunks * kEntSplit)), block(256);
   if (mixed)
-    hipLaunchKernelGGL(k_broaden_adj<true>, grid, block, 0, s, hchunk_crystal, plan, friedel, refl_offset, ent_key,
+    hipLaunchKernelGGL(k_broaden_adj<true>, grid, block, 0, s, hchunks, plan, friedel, refl_offset, ent_key,
                        ent_idx, dy, g, w1, w2);
   else
-    hipLaunchKernelGGL(k_broaden_adj<false>, grid, block, 0, s, hchunk_crystal, plan, friedel, refl_offset, ent_key,
+    hipLaunchKernelGGL(k_broaden_adj<false>, grid, block, 0, s, hchunks, plan, friedel, refl_offset, ent_key,
                        ent_idx, dy, g, w1, w2);
 }
 

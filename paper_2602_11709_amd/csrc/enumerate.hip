@@ -5,10 +5,14 @@
 //
 // Each crystal's search box [-H,H]x[-K,K]x[-L,L] is split at the origin; only
 // the points above it in lexicographic order are visited, since (h,k,l) and
-// (-h,-k,-l) share q, 2theta and LP bit for bit.  Two passes over fixed-size
-// chunks of that half box: count survivors per chunk, scan the counts, then
-// recompute the test and write each survivor and its Friedel mate.  The
-// output of a crystal is its full sphere shell in ascending (h, k, l) order:
+// (-h,-k,-l) share q, 2theta and LP bit for bit.  The half box is taken row
+// by row ((h, k) fixed, one row per thread), each row only over the l that
+// the quadratic q(l) can bring into the limiting sphere.  The rows are taken
+// in chunks of 64, one wavefront each: count the survivors per chunk, scan
+// the counts, then count again, rank and write (h, k, l) and q of each
+// survivor and its Friedel mate, and last 2theta and LP, one thread per
+// written reflection.  The output of a crystal is its full sphere shell in
+// ascending (h, k, l) order:
 // the positive half occupies the upper half of the segment and mate i sits at
 // the mirror position, so no sort is needed for the hkl listing.
 //
@@ -23,27 +27,13 @@ namespace xrd {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr int kPer = kEnumChunk / kThreads;  // 8
+static_assert(kEnumRows == 64, "one row per lane of a wavefront");
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kFusedPackLds = 4096;  // largest cursor space the fused count-and-pack launch carries
 
 struct Hkl {
   int h, k, l;
 };
-
-__device__ __forceinline__ Hkl decode(const CrystalPlan &P, int64_t p) {
-  // linear index of the full box (h outermost); the origin is the centre.
-  // The plan keeps boxes below 2^31 points, so 32-bit division suffices.
-  const uint32_t nl = 2 * P.L + 1, nk = 2 * P.K + 1;
-  const uint32_t i = (uint32_t)(P.half_box + 1 + p);
-  Hkl r;
-  const uint32_t t = i / nl;
-  r.l = (int)(i - t * nl) - P.L;
-  const uint32_t u = t / nk;
-  r.k = (int)(t - u * nk) - P.K;
-  r.h = (int)u - P.H;
-  return r;
-}
 
 __device__ __forceinline__ double q_of(const CrystalPlan &P, const Hkl &m) {
 #pragma clang fp contract(off)
@@ -60,23 +50,91 @@ __device__ __forceinline__ double two_theta_of(double q, double lambda) {
   return 2.0 * asin(s) * (180.0 / kPi);
 }
 
-__device__ __forceinline__ bool keep(const CrystalPlan &P, int64_t p, double lambda, Hkl *m, double *q,
-                                     double *tt) {
-  if (p >= P.half_box) return false;
-  *m = decode(P, p);
-  *q = q_of(P, *m);
-  if (*q < P.qlo || *q > P.qhi) return false;
-  *tt = two_theta_of(*q, lambda);
-  return *tt >= P.tmin && *tt <= P.tmax;
+// Row rho of a crystal's positive half: the half box above the origin in
+// lexicographic (h, k, l) order is the row (0, 0) with l in [1, L], the rows
+// (0, k) for k in [1, K], then (h, k) for h in [1, H], k in [-K, K], each with
+// l in [-L, L] (h outermost).  Rows in this order, l ascending within a row,
+// list the half in lexicographic order.
+struct Row {
+  int h, k, l0, l1;
+};
+__device__ __forceinline__ int64_t rows_of(const CrystalPlan &P) {
+  return (int64_t)P.H * (2 * P.K + 1) + P.K + 1;
+}
+__device__ __forceinline__ Row row_of(const CrystalPlan &P, int64_t rho) {
+  Row r;
+  if (rho <= P.K) {
+    r.h = 0;
+    r.k = (int)rho;
+  } else {
+    const uint32_t nk = 2 * P.K + 1, x = (uint32_t)(rho - (P.K + 1)), hq = x / nk;
+    r.h = 1 + (int)hq;
+    r.k = (int)(x - hq * nk) - P.K;
+  }
+  r.l0 = (r.h == 0 && r.k == 0) ? 1 : -P.L;
+  r.l1 = P.L;
+  return r;
 }
 
-__device__ __forceinline__ double lp_of(double tt) {
+// The l of a row that can lie in the limiting sphere: q(l) = G33 l^2 +
+// 2 (G13 h + G23 k) l + q(h, k, 0) is convex in l, so {q <= qhi} is an
+// interval, bounded by the roots of the quadratic (qhi widened by 1e-9, and
+// one more l on each side, so that rounding in the roots cannot drop a point;
+// every candidate then takes the exact test).
+__device__ __forceinline__ void row_candidates(const CrystalPlan &P, const Row &r, int *lo, int *hi) {
+  const double h = r.h, k = r.k;
+  const double A = P.gs[2];
+  const double B = 2.0 * (P.gs[4] * h + P.gs[5] * k);
+  const double C = P.gs[0] * h * h + P.gs[1] * k * k + 2.0 * P.gs[3] * h * k;
+  const double disc = B * B - 4.0 * A * (C - P.qhi * (1.0 + 1e-9));
+  if (!(disc >= 0.0)) {
+    *lo = 1;
+    *hi = 0;
+    return;
+  }
+  const double sq = sqrt(disc), lim = (double)P.L + 1.0;
+  const double r1 = fmin(fmax((-B - sq) / (2.0 * A), -lim), lim);
+  const double r2 = fmin(fmax((-B + sq) / (2.0 * A), -lim), lim);
+  *lo = max(r.l0, (int)floor(r1));
+  *hi = min(r.l1, (int)ceil(r2));
+}
+
+// The test that defines a reflection: q in the prefilter band and 2theta in
+// [tmin, tmax].  Inside the band narrowed by 3e-9 (relative) 2theta lies in
+// range with a margin far above its rounding error, so 2theta is evaluated
+// there only when wanted; the decision is the same either way, and the count
+// and the fill take it with this one function.
+__device__ __forceinline__ bool keep_point(const CrystalPlan &P, const Hkl &m, double lambda, bool want_tt, double *q,
+                                           double *tt) {
+  *q = q_of(P, m);
+  if (*q < P.qlo || *q > P.qhi) return false;
+  const bool inner = *q >= P.qlo * (1.0 + 3e-9) && *q <= P.qhi * (1.0 - 3e-9);
+  if (inner && !want_tt) return true;
+  *tt = two_theta_of(*q, lambda);
+  return inner || (*tt >= P.tmin && *tt <= P.tmax);
+}
+
+// Survivors of one row.
+__device__ __forceinline__ int row_count(const CrystalPlan &P, const Row &r, double lambda) {
+  int lo, hi;
+  row_candidates(P, r, &lo, &hi);
+  int n = 0;
+  for (int l = lo; l <= hi; ++l) {
+    double q, tt;
+    n += keep_point(P, Hkl{r.h, r.k, l}, lambda, false, &q, &tt) ? 1 : 0;
+  }
+  return n;
+}
+
+// LP = (1 + cos^2 2theta) / (sin^2 theta cos theta) from q directly:
+// sin^2 theta = lambda^2 q / 4 (Bragg's law), cos 2theta = 1 - 2 sin^2 theta,
+// cos theta = sqrt(1 - sin^2 theta); the same function of theta without the
+// trigonometric round trip.
+__device__ __forceinline__ double lp_of_q(double q, double lambda) {
 #pragma clang fp contract(off)
-  const double th = 0.5 * tt * (kPi / 180.0);
-  double st, ct;
-  sincos(th, &st, &ct);
-  const double c2 = cos(2.0 * th);
-  return (1.0 + c2 * c2) / (st * st * ct);
+  const double s2 = 0.25 * (lambda * lambda) * q;
+  const double c2 = 1.0 - 2.0 * s2;
+  return (1.0 + c2 * c2) / (s2 * sqrt(1.0 - s2));
 }
 
 // ---- atom packing ----------------------------------------------------------
@@ -203,43 +261,33 @@ __global__ __launch_bounds__(64) void k_atom_pack(const CrystalPlan *__restrict_
                a.orig, a.runs, a.run_count, a.err);
 }
 
-// Survivor count per enumeration chunk.  With pack_blocks > 0 the launch
-// also packs the atoms (independent work): blocks from n_chunks on take four
-// crystals each, one per wavefront, with n_species LDS cursors per wavefront.
+// Survivor count per enumeration chunk of kEnumRows rows, one wavefront per
+// chunk (lane = row), four chunks per block.  The launch also packs the
+// atoms (independent work) when pack is set: blocks from chunk_blocks on
+// take four crystals each, one per wavefront, with n_species LDS cursors per
+// wavefront.
 __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__restrict__ plan,
                                                          const int32_t *__restrict__ chunk_crystal,
                                                          int64_t n_chunks, int64_t n_c, double lambda,
                                                          int32_t *__restrict__ counts, PackArgs pa) {
-  if (blockIdx.x >= n_chunks) {
+  const int64_t chunk_blocks = (n_chunks + kThreads / 64 - 1) / (kThreads / 64);
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  if (blockIdx.x >= chunk_blocks) {
     extern __shared__ int32_t cursors[];  // 4 x n_species
-    const int wid = threadIdx.x >> 6;
-    const int64_t c = (int64_t)(blockIdx.x - n_chunks) * (kThreads / 64) + wid;
+    const int64_t c = (int64_t)(blockIdx.x - chunk_blocks) * (kThreads / 64) + wid;
     if (c < n_c)
-      pack_crystal((int)c, threadIdx.x & 63, cursors + wid * pa.n_species, plan, pa.n_species, pa.frac, pa.species,
-                   pa.occ, pa.bfac, pa.atoms, pa.orig, pa.runs, pa.run_count, pa.err);
+      pack_crystal((int)c, lane, cursors + wid * pa.n_species, plan, pa.n_species, pa.frac, pa.species, pa.occ,
+                   pa.bfac, pa.atoms, pa.orig, pa.runs, pa.run_count, pa.err);
     return;
   }
-  const int chunk = blockIdx.x;
+  const int64_t chunk = (int64_t)blockIdx.x * (kThreads / 64) + wid;
+  if (chunk >= n_chunks) return;
   const CrystalPlan &P = plan[chunk_crystal[chunk]];
-  const int64_t p0 = (int64_t)(chunk - P.enum_chunk_begin) * kEnumChunk;
-  int n = 0;
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    Hkl m;
-    double q, tt;
-    n += keep(P, p0 + u * kThreads + threadIdx.x, lambda, &m, &q, &tt) ? 1 : 0;
-  }
-  // block sum
+  const int64_t rho = (chunk - P.enum_chunk_begin) * kEnumRows + lane;
+  int n = rho < rows_of(P) ? row_count(P, row_of(P, rho), lambda) : 0;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) n += __shfl_xor(n, d, 64);
-  __shared__ int ws[kThreads / 64];
-  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = n;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int s = 0;
-    for (int w = 0; w < kThreads / 64; ++w) s += ws[w];
-    counts[chunk] = s;
-  }
+  if (lane == 0) counts[chunk] = n;
 }
 
 // Exclusive scan of the chunk counts and the crystal offsets in one block
@@ -285,62 +333,108 @@ __global__ void k_enum_offsets(const CrystalPlan *__restrict__ plan, int64_t n_c
   if (c == n_c) refl_offset[n_c] = 2 * prefix[n_chunks];
 }
 
+// One wavefront per chunk of kEnumRows rows (lane = row), four chunks per
+// block.  The chunk's rows are flattened into their candidate points in
+// lexicographic order; the wavefront then takes the points 64 at a time, one
+// per lane (a binary search over the rows' candidate offsets finds a point's
+// row), tests them, ranks the survivors with a ballot and writes each with
+// its Friedel mate: (h, k, l) and q.  2theta and LP follow in k_enum_geom.
 __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__restrict__ plan,
                                                         const int32_t *__restrict__ chunk_crystal,
-                                                        const int64_t *__restrict__ prefix, double lambda,
-                                                        int16_t *__restrict__ oh, int16_t *__restrict__ ok,
-                                                        int16_t *__restrict__ ol, double *__restrict__ oq,
-                                                        double *__restrict__ ott, double *__restrict__ olp) {
-  const int chunk = blockIdx.x;
+                                                        int64_t n_chunks, const int64_t *__restrict__ prefix,
+                                                        double lambda, int16_t *__restrict__ oh,
+                                                        int16_t *__restrict__ ok, int16_t *__restrict__ ol,
+                                                        double *__restrict__ oq) {
+  __shared__ int32_t s_off[kThreads / 64][kEnumRows + 1];  // candidate offsets of a wavefront's rows
+  __shared__ int32_t s_lo[kThreads / 64][kEnumRows], s_h[kThreads / 64][kEnumRows], s_k[kThreads / 64][kEnumRows];
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const int64_t chunk = (int64_t)blockIdx.x * (kThreads / 64) + wid;
+  if (chunk >= n_chunks) return;
   const CrystalPlan &P = plan[chunk_crystal[chunk]];
   const int64_t first_chunk = P.enum_chunk_begin;
   const int64_t c_begin = prefix[first_chunk];
   const int64_t rh = prefix[first_chunk + P.enum_chunks] - c_begin;  // positive-half count
   const int64_t seg = 2 * c_begin;                                     // crystal's first reflection
-  int64_t rank = prefix[chunk] - c_begin;
-  const int64_t p0 = (int64_t)(chunk - first_chunk) * kEnumChunk;
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  __shared__ int wcount[kPer][kThreads / 64];
-  Hkl m[kPer];
-  double q[kPer], tt[kPer];
-  bool kp[kPer];
-  int wrank[kPer];
-#pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    kp[u] = keep(P, p0 + u * kThreads + threadIdx.x, lambda, &m[u], &q[u], &tt[u]);
-    const uint64_t b = __ballot(kp[u]);
-    wrank[u] = __builtin_amdgcn_mbcnt_hi((uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
-    if (lane == 0) wcount[u][wid] = __popcll(b);
+  const int64_t rho = (chunk - first_chunk) * kEnumRows + lane;
+  int lo = 1, hi = 0;
+  Row r{0, 0, 1, 0};
+  if (rho < rows_of(P)) {
+    r = row_of(P, rho);
+    row_candidates(P, r, &lo, &hi);
   }
-  __syncthreads();
+  const int nc = max(hi - lo + 1, 0);
+  int inc = nc;
 #pragma unroll
-  for (int u = 0; u < kPer; ++u) {
-    int before = 0, total = 0;
-#pragma unroll
-    for (int w = 0; w < kThreads / 64; ++w) {
-      const int cnt = wcount[u][w];
-      before += w < wid ? cnt : 0;
-      total += cnt;
+  for (int d = 1; d < 64; d <<= 1) {
+    const int o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
+  }
+  const int total = __shfl(inc, 63, 64);
+  int32_t *off = s_off[wid];
+  off[lane] = inc - nc;
+  if (lane == 0) off[kEnumRows] = total;
+  s_lo[wid][lane] = lo;
+  s_h[wid][lane] = r.h;
+  s_k[wid][lane] = r.k;
+  wave_sync();
+  int64_t rank = prefix[chunk] - c_begin;
+  for (int base = 0; base < total; base += 64) {
+    const int ci = base + lane;
+    Hkl m{0, 0, 0};
+    double q = 0.0, tt = 0.0;
+    bool kp = false;
+    if (ci < total) {
+      int a = 0, b = kEnumRows - 1;  // last row whose offset is <= ci
+      while (a < b) {
+        const int mid = (a + b + 1) >> 1;
+        if (off[mid] <= ci) a = mid; else b = mid - 1;
+      }
+      m = Hkl{s_h[wid][a], s_k[wid][a], s_lo[wid][a] + (ci - off[a])};
+      kp = keep_point(P, m, lambda, false, &q, &tt);
     }
-    if (kp[u]) {
-      const int64_t r = rank + before + wrank[u];
-      const int64_t pos = seg + rh + r;
-      const int64_t mate = seg + rh - 1 - r;
-      const double lp = lp_of(tt[u]);
-      oh[pos] = (int16_t)m[u].h;
-      ok[pos] = (int16_t)m[u].k;
-      ol[pos] = (int16_t)m[u].l;
-      oh[mate] = (int16_t)(-m[u].h);
-      ok[mate] = (int16_t)(-m[u].k);
-      ol[mate] = (int16_t)(-m[u].l);
-      oq[pos] = q[u];
-      oq[mate] = q[u];
-      ott[pos] = tt[u];
-      ott[mate] = tt[u];
-      olp[pos] = lp;
-      olp[mate] = lp;
+    const uint64_t bal = __ballot(kp);
+    const int wrank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    const int64_t rk = rank + wrank;
+    if (kp && rk < rh) {  // rk < rh always: the count took the same decisions
+      const int64_t pos = seg + rh + rk;
+      const int64_t mate = seg + rh - 1 - rk;
+      oh[pos] = (int16_t)m.h;
+      ok[pos] = (int16_t)m.k;
+      ol[pos] = (int16_t)m.l;
+      oh[mate] = (int16_t)(-m.h);
+      ok[mate] = (int16_t)(-m.k);
+      ol[mate] = (int16_t)(-m.l);
+      oq[pos] = q;
+      oq[mate] = q;
     }
-    rank += total;
+    rank += __popcll(bal);
+  }
+}
+
+// 2theta and LP of the reflections a chunk wrote, one block per chunk, one
+// reflection per thread (positive half; the mate shares q, hence both).
+__global__ __launch_bounds__(kThreads) void k_enum_geom(const CrystalPlan *__restrict__ plan,
+                                                        const int32_t *__restrict__ chunk_crystal,
+                                                        const int64_t *__restrict__ prefix, double lambda,
+                                                        const double *__restrict__ oq, double *__restrict__ ott,
+                                                        double *__restrict__ olp) {
+  const int chunk = blockIdx.x;
+  const CrystalPlan &P = plan[chunk_crystal[chunk]];
+  const int64_t first_chunk = P.enum_chunk_begin;
+  const int64_t c_begin = prefix[first_chunk];
+  const int64_t rh = prefix[first_chunk + P.enum_chunks] - c_begin;
+  const int64_t seg = 2 * c_begin;
+  const int64_t r0 = prefix[chunk] - c_begin, n = prefix[chunk + 1] - prefix[chunk];
+  for (int64_t j = threadIdx.x; j < n; j += kThreads) {
+    const int64_t rk = r0 + j;
+    const int64_t pos = seg + rh + rk, mate = seg + rh - 1 - rk;
+    const double q = oq[pos];
+    const double tt = two_theta_of(q, lambda);
+    const double lp = lp_of_q(q, lambda);
+    ott[pos] = tt;
+    ott[mate] = tt;
+    olp[pos] = lp;
+    olp[mate] = lp;
   }
 }
 
@@ -360,8 +454,9 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk
     hipLaunchKernelGGL(k_atom_pack, dim3((unsigned)n_c), dim3(64), (size_t)n_species * sizeof(int32_t), s, plan, n_c,
                        pa);
   if (n_chunks > 0) {
+    const int64_t chunk_blocks = (n_chunks + kThreads / 64 - 1) / (kThreads / 64);
     const int64_t pack_blocks = fuse ? (n_c + kThreads / 64 - 1) / (kThreads / 64) : 0;
-    hipLaunchKernelGGL(k_enum_count, dim3((unsigned)(n_chunks + pack_blocks)), dim3(kThreads),
+    hipLaunchKernelGGL(k_enum_count, dim3((unsigned)(chunk_blocks + pack_blocks)), dim3(kThreads),
                        fuse ? fused_lds : 0, s, plan, chunk_crystal, n_chunks, n_c, lambda, counts, pa);
   }
   if (n_chunks <= kOneBlockChunks) {
@@ -371,9 +466,12 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk
     hipLaunchKernelGGL(k_enum_offsets, dim3((unsigned)((n_c + 1 + 255) / 256)), dim3(256), 0, s, plan, n_c, n_chunks,
                        prefix, refl_offset);
   }
-  if (n_chunks > 0)
-    hipLaunchKernelGGL(k_enum_fill, dim3((unsigned)n_chunks), dim3(kThreads), 0, s, plan, chunk_crystal, prefix,
-                       lambda, h, k, l, q, tt, lp);
+  if (n_chunks > 0) {
+    hipLaunchKernelGGL(k_enum_fill, dim3((unsigned)((n_chunks + kThreads / 64 - 1) / (kThreads / 64))),
+                       dim3(kThreads), 0, s, plan, chunk_crystal, n_chunks, prefix, lambda, h, k, l, q);
+    hipLaunchKernelGGL(k_enum_geom, dim3((unsigned)n_chunks), dim3(kThreads), 0, s, plan, chunk_crystal, prefix,
+                       lambda, q, tt, lp);
+  }
 }
 
 }  // namespace xrd

@@ -13,7 +13,7 @@
 namespace xrd {
 
 // Work granularity.
-constexpr int kEnumChunk = 2048;  // search-box points per enumeration block (256 threads x 8)
+constexpr int kEnumRows = 64;     // (h, k) rows of a half search box per enumeration chunk, one per lane
 constexpr int kSortChunk = 1024;  // reflections per sort/merge block (256 threads x 4)
 constexpr int kBinDiv = 4;        // merge-sort bins per crystal = capacity / kBinDiv
 constexpr int kHalfChunk = 2048;  // reflections per adjoint chunk
@@ -38,7 +38,7 @@ struct alignas(16) CrystalPlan {
   int32_t n_bins;
   int64_t half_box;   // points of the search box above the origin: ((2H+1)(2K+1)(2L+1)-1)/2
   int64_t enum_chunk_begin;
-  int32_t enum_chunks;
+  int32_t enum_chunks;  // blocks of kEnumRows rows of the half box
   int32_t n_hchunks;  // adjoint chunks at capacity
   int64_t atom_begin, atom_end;
   int64_t run_begin;  // first slot of this crystal's species-run table (capacity min(S, N))
@@ -68,6 +68,12 @@ struct alignas(16) SpeciesRun {
   int32_t begin, end, species, local;  // local = run index within the crystal
 };
 
+// Broadening work unit: chunk of kHalfChunk entries of one crystal.
+struct HChunk {
+  int32_t crystal;
+  int32_t chunk;
+};
+
 // Structure-factor work item: a tile of reflections of one crystal.
 struct SfItem {
   int32_t crystal;
@@ -76,7 +82,7 @@ struct SfItem {
 
 // Workspace byte offsets (all 256-aligned).
 struct WsLayout {
-  int64_t plan, enum_chunk_crystal, sf_items, sort_chunk_crystal, hchunk_crystal, crystal_order, bw_items, ab_items;
+  int64_t plan, enum_chunk_crystal, sf_items, sort_chunk_crystal, hchunks, crystal_order, bw_items, ab_items;
   int64_t enum_count, enum_prefix;
   int64_t atoms, atom_orig, runs, run_count, err_flag;
   int64_t bin_count, bin_start;
@@ -172,12 +178,12 @@ void launch_merge(const MergeArgs &a, hipStream_t s);
 // 2theta order).  The forward also fills ent_w (double weights, or float
 // weights in its first half under mixed precision) and the span tables;
 // crystal_order lists the crystals heaviest first.
-void launch_broaden_fwd(bool mixed, const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan,
+void launch_broaden_fwd(bool mixed, const HChunk *hchunks, int64_t n_hchunks, const CrystalPlan *plan,
                         const int32_t *crystal_order, int64_t n_c, bool friedel, const int64_t *refl_offset, const double *ent_key,
                         const int32_t *ent_idx, const double *inten, double t0, double dt, int64_t n, double sigma,
                         double window, int64_t span_cap, double *ent_w, int32_t *span_first, int32_t *span_last,
                         double *y, hipStream_t s);
-void launch_broaden_adj(bool mixed, const int32_t *hchunk_crystal, int64_t n_hchunks, const CrystalPlan *plan,
+void launch_broaden_adj(bool mixed, const HChunk *hchunks, int64_t n_hchunks, const CrystalPlan *plan,
                         bool friedel, const int64_t *refl_offset, const double *ent_key, const int32_t *ent_idx,
                         const double *dy, double t0, double dt, int64_t n, double sigma, double window, double *w1,
                         double *w2, hipStream_t s);
