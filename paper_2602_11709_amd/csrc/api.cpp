@@ -50,6 +50,11 @@ struct xrd_batch {
   // workspace and reflection arrays they belong to; cleared by enumeration
   const void *deriv_ws = nullptr;
   const int16_t *deriv_h = nullptr;
+  // side stream and events for work that runs beside the caller's stream
+  // inside one call, created at first use on the then-current device
+  int side_device = -1;
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 namespace {
@@ -490,11 +495,47 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
 
 static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r);
 
+static void release_side(xrd_batch *b) {
+  if (b->ev_fork) hipEventDestroy(b->ev_fork);
+  if (b->ev_join) hipEventDestroy(b->ev_join);
+  if (b->side) hipStreamDestroy(b->side);
+  b->side = nullptr;
+  b->ev_fork = b->ev_join = nullptr;
+  b->side_device = -1;
+}
+
+// The batch's side stream on the current device (default priority,
+// non-blocking), or none if it cannot be made (then everything runs on the
+// caller's stream).
+static Fork side_of(xrd_batch *b) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return Fork{nullptr, nullptr, nullptr};
+  if (b->side_device != dev) {
+    release_side(b);
+    hipStream_t st = nullptr;
+    hipEvent_t e1 = nullptr, e2 = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
+        hipEventCreateWithFlags(&e1, hipEventDisableTiming) == hipSuccess &&
+        hipEventCreateWithFlags(&e2, hipEventDisableTiming) == hipSuccess) {
+      b->side = st;
+      b->ev_fork = e1;
+      b->ev_join = e2;
+      b->side_device = dev;
+    } else {
+      if (e1) hipEventDestroy(e1);
+      if (st) hipStreamDestroy(st);
+      (void)hipGetLastError();
+      return Fork{nullptr, nullptr, nullptr};
+    }
+  }
+  return Fork{b->side, b->ev_fork, b->ev_join};
+}
+
 // Sort the reflections of ``r`` into the workspace unless this enumeration
 // has been sorted there already.
 static void ensure_sorted(xrd_batch *b, void *ws, const xrd_refl *r) {
   if (b->sorted_ws == ws && b->sorted_tt == r->two_theta) return;
-  launch_sort(sort_args(b, ws, r), stream_of(b));
+  launch_sort(sort_args(b, ws, r), side_of(b), stream_of(b));
   b->sorted_ws = ws;
   b->sorted_tt = r->two_theta;
 }
@@ -554,7 +595,7 @@ int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, 
   a.perm = p->perm;
   a.peak_offset = p->peak_offset;
   // the merge sorts as it goes, and leaves the sorted order behind
-  launch_merge(a, stream_of(b));
+  launch_merge(a, side_of(b), stream_of(b));
   b->sorted_ws = ws;
   b->sorted_tt = r->two_theta;
   b->last_ws = ws;
@@ -654,6 +695,10 @@ int xrd_read_counts(xrd_batch *b, const xrd_refl *r, const xrd_peaks *p, int64_t
   return XRD_OK;
 }
 
-void xrd_batch_destroy(xrd_batch *b) { delete b; }
+void xrd_batch_destroy(xrd_batch *b) {
+  if (!b) return;
+  release_side(b);
+  delete b;
+}
 
 }  // extern "C"

@@ -538,31 +538,42 @@ MergeOut merge_out(const MergeArgs *m) {
   return mo;
 }
 
-void sort_kernels(const SortArgs &a, const MergeOut &mo, hipStream_t s) {
+void sort_kernels(const SortArgs &a, const MergeOut &mo, const Fork &f, hipStream_t s) {
   if (a.n_c <= 0) return;
   double *ek = a.friedel ? a.ent_key : nullptr;
   int32_t *ei = a.friedel ? a.ent_idx : nullptr;
-  hipLaunchKernelGGL((k_sort_crystal<kSmallSort, 256, false>), dim3((unsigned)a.n_c), dim3(256), 0, s, a.n_c,
-                     a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count, a.bin_start, mo);
+  // the two sizes take disjoint crystals: the larger one runs beside the other
+  const bool fork = a.n_mid > 0 && f.side != nullptr;
+  if (fork) {
+    hipEventRecord(f.fork, s);
+    hipStreamWaitEvent(f.side, f.fork, 0);
+  }
   if (a.n_mid > 0) {
     const unsigned g = (unsigned)(a.n_mid < kMidBlocks ? a.n_mid : kMidBlocks);
-    hipLaunchKernelGGL((k_sort_crystal<kMidSort, kMidThreads, true>), dim3(g), dim3(kMidThreads), 0, s, a.n_mid,
-                       a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count, a.bin_start, mo);
+    hipLaunchKernelGGL((k_sort_crystal<kMidSort, kMidThreads, true>), dim3(g), dim3(kMidThreads), 0,
+                       fork ? f.side : s, a.n_mid, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei,
+                       a.bin_count, a.bin_start, mo);
+  }
+  hipLaunchKernelGGL((k_sort_crystal<kSmallSort, 256, false>), dim3((unsigned)a.n_c), dim3(256), 0, s, a.n_c,
+                     a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count, a.bin_start, mo);
+  if (fork) {
+    hipEventRecord(f.join, f.side);
+    hipStreamWaitEvent(s, f.join, 0);
   }
 }
 
 }  // namespace
 
-void launch_sort(const SortArgs &a, hipStream_t s) { sort_kernels(a, merge_out(nullptr), s); }
+void launch_sort(const SortArgs &a, const Fork &f, hipStream_t s) { sort_kernels(a, merge_out(nullptr), f, s); }
 
-void launch_merge(const MergeArgs &a, hipStream_t s) {
+void launch_merge(const MergeArgs &a, const Fork &f, hipStream_t s) {
   const SortArgs &o = a.sort;
   if (a.n_c <= 0) {
     launch_fill_u64(reinterpret_cast<uint64_t *>(a.peak_offset), 1, 0, s);
     return;
   }
   const MergeOut mo = merge_out(&a);
-  sort_kernels(o, mo, s);
+  sort_kernels(o, mo, f, s);
   hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, s, a.n_c, a.pk_count, a.peak_offset);
   if (o.n_chunks > 0)
     hipLaunchKernelGGL(k_peak_move, dim3((unsigned)o.n_chunks), dim3(kThreads), 0, s, o.plan, o.chunk_crystal,

@@ -153,7 +153,19 @@ struct SortArgs {
   double *ent_key;       // [half capacity] 2theta of the evaluated half, sorted per crystal
   int32_t *ent_idx;      // its global reflection indices
 };
-void launch_sort(const SortArgs &a, hipStream_t s);
+// A second stream for independent work inside one call: the caller's stream
+// records ``fork``, the side stream waits for it, runs its part and records
+// ``join``, which the caller's stream waits for before the call's next step
+// (the pattern graph capture follows across streams).  side == nullptr runs
+// everything on the caller's stream.
+struct Fork {
+  hipStream_t side;
+  hipEvent_t fork, join;
+};
+
+// The large-crystal sort (capacity above 2 kSmallSort) goes to the fork's
+// side stream, concurrent with the one-block-per-crystal sort.
+void launch_sort(const SortArgs &a, const Fork &f, hipStream_t s);
 
 struct MergeArgs {
   SortArgs sort;
@@ -172,7 +184,7 @@ struct MergeArgs {
   int32_t *pk_mult;
   int64_t *pk_first, *perm, *peak_offset;
 };
-void launch_merge(const MergeArgs &a, hipStream_t s);
+void launch_merge(const MergeArgs &a, const Fork &f, hipStream_t s);
 
 // Gaussian broadening over the sorted entries (evaluated reflections in
 // 2theta order).  The forward also fills ent_w (double weights, or float
