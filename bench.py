@@ -274,7 +274,7 @@ def main():
                         "sort/merge/scale + 4001-point broadened pattern + its adjoint",
             "crystals": n_c, "atoms": int(batch.n_atoms), "reflections": mx["n_refl"], "peaks": mx["n_peaks"],
             "sf_terms": mx["terms"], "precision": "mixed: FP64 phase reduction, q, 2theta, LP, keys and "
-            "intensities; FP32 sin/cos, scattering factors, weights, compensated sums",
+            "intensities; FP32 sin/cos, scattering factors, weights and per-species sums, double across species",
             "graph": graph, "parallelism": "single GPU"},
         "sf_terms_per_s": round(mx["terms"] / (mx["ms"] * 1e-3), 1),
         "stages_ms": mx["stages"],

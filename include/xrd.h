@@ -198,9 +198,9 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
 int xrd_read_counts(xrd_batch *b, const xrd_refl *r, const xrd_peaks *p,
                     int64_t *host_refl_offset, int64_t *host_peak_offset);
 
-/* Free the handle, and the stream and two events it keeps for work that runs
- * beside the caller's stream inside a call (created at the first sort on a
- * device; the batch's work must have completed).  NULL is ignored. */
+/* Free the handle, and the two streams and three events it keeps for work
+ * that runs beside the caller's stream inside a call (created at the first
+ * sort on a device; the batch's work must have completed).  NULL is ignored. */
 void xrd_batch_destroy(xrd_batch *b);
 
 /* Message of the last failed call on this thread ("" if none). */

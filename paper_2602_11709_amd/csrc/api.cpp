@@ -35,6 +35,8 @@ struct xrd_batch {
   std::vector<AbItem> ab_items;
   int64_t n_atoms = 0, refl_cap = 0, half_cap = 0, n_bins = 0, run_cap = 0, part_rows = 0, partf_rows = 0;
   int64_t n_mid = 0;      // crystals whose reflection capacity exceeds 2 kSmallSort
+  int64_t n_small = 0;    // crystals whose reflection capacity exceeds 2 kTinySort
+  int64_t n_large = 0;    // crystals whose reflection capacity exceeds 2 kMidSort
   int64_t sf_heavy = 0;   // leading structure-factor items that take a block each
   int64_t grid_cap = 0;   // largest grid of a broadened-pattern call
   int64_t span_cap = 0;   // span-table entries per crystal: ceil(grid_cap / kSpanPts)
@@ -53,8 +55,8 @@ struct xrd_batch {
   // side stream and events for work that runs beside the caller's stream
   // inside one call, created at first use on the then-current device
   int side_device = -1;
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipStream_t side = nullptr, side2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_join2 = nullptr;
 };
 
 namespace {
@@ -217,6 +219,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     P.half_box = (box - 1) / 2;
     refl += 2 * P.half_box;
     if (P.half_box > kSmallSort) ++b->n_mid;  // more than 2 kSmallSort reflections possible
+    if (P.half_box > kTinySort) ++b->n_small;
+    if (P.half_box > kMidSort) ++b->n_large;
     if (refl >= ((int64_t)1 << 31) - 1) {
       delete b;
       return fail(XRD_ERR_CAPACITY, "reflection capacity exceeds 2^31; split the batch");
@@ -496,43 +500,39 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
 static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r);
 
 static void release_side(xrd_batch *b) {
-  if (b->ev_fork) hipEventDestroy(b->ev_fork);
-  if (b->ev_join) hipEventDestroy(b->ev_join);
-  if (b->side) hipStreamDestroy(b->side);
-  b->side = nullptr;
-  b->ev_fork = b->ev_join = nullptr;
+  for (hipEvent_t e : {b->ev_fork, b->ev_join, b->ev_join2})
+    if (e) hipEventDestroy(e);
+  for (hipStream_t st : {b->side, b->side2})
+    if (st) hipStreamDestroy(st);
+  b->side = b->side2 = nullptr;
+  b->ev_fork = b->ev_join = b->ev_join2 = nullptr;
   b->side_device = -1;
 }
 
-// The batch's side stream on the current device (default priority,
-// non-blocking), or none if it cannot be made (then everything runs on the
+// The batch's side streams on the current device (default priority,
+// non-blocking), or none if they cannot be made (then everything runs on the
 // caller's stream).
 static Fork side_of(xrd_batch *b) {
+  const Fork none{nullptr, nullptr, nullptr, nullptr, nullptr};
   int dev = -1;
-  if (hipGetDevice(&dev) != hipSuccess) return Fork{nullptr, nullptr, nullptr};
+  if (hipGetDevice(&dev) != hipSuccess) return none;
   if (b->side_device != dev) {
     release_side(b);
-    hipStream_t st = nullptr;
-    hipEvent_t e1 = nullptr, e2 = nullptr;
-    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) == hipSuccess &&
-        hipEventCreateWithFlags(&e1, hipEventDisableTiming) == hipSuccess &&
-        hipEventCreateWithFlags(&e2, hipEventDisableTiming) == hipSuccess) {
-      b->side = st;
-      b->ev_fork = e1;
-      b->ev_join = e2;
-      b->side_device = dev;
-    } else {
-      if (e1) hipEventDestroy(e1);
-      if (st) hipStreamDestroy(st);
+    bool ok = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) == hipSuccess &&
+              hipStreamCreateWithFlags(&b->side2, hipStreamNonBlocking) == hipSuccess &&
+              hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) == hipSuccess &&
+              hipEventCreateWithFlags(&b->ev_join2, hipEventDisableTiming) == hipSuccess;
+    if (!ok) {
+      release_side(b);
       (void)hipGetLastError();
-      return Fork{nullptr, nullptr, nullptr};
+      return none;
     }
+    b->side_device = dev;
   }
-  return Fork{b->side, b->ev_fork, b->ev_join};
+  return Fork{b->side, b->side2, b->ev_fork, b->ev_join, b->ev_join2};
 }
 
-// Sort the reflections of ``r`` into the workspace unless this enumeration
-// has been sorted there already.
 static void ensure_sorted(xrd_batch *b, void *ws, const xrd_refl *r) {
   if (b->sorted_ws == ws && b->sorted_tt == r->two_theta) return;
   launch_sort(sort_args(b, ws, r), side_of(b), stream_of(b));
@@ -560,6 +560,8 @@ static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r) {
   a.scan_part = at<int64_t>(ws, L.scan_part);
   a.order = at<int32_t>(ws, L.crystal_order);
   a.n_mid = b->n_mid;
+  a.n_small = b->n_small;
+  a.n_large = b->n_large;
   a.friedel = b->desc.friedel != 0 ? 1 : 0;
   a.ent_key = at<double>(ws, L.ent_key);
   a.ent_idx = at<int32_t>(ws, L.ent_idx);

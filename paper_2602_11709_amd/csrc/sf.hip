@@ -20,9 +20,10 @@
 // in double (v_fract_f64), then sin/cos of the revolution in single precision
 // by v_sin_f32 / v_cos_f32 (which take revolutions); weights
 // occ exp(-B s^2) = exp2(log2(occ) - B log2(e) s^2) in single precision;
-// single-precision sums over runs of at most kAtomTile atoms, folded into a
-// compensated (two-sum) float accumulator.  Plain path (XRD_FP64): the same
-// loop in double with sincospi.
+// single-precision sums over runs of at most kAtomTile atoms of one species,
+// each multiplied by f_t and added in double (a product of two singles is
+// exact in double, so the only single-precision roundings are inside a run).
+// Plain path (XRD_FP64): the same loop in double with sincospi.
 //
 // Friedel: F(-h) = conj F(h) for real scattering factors, so with the option
 // on only the positive half of each crystal's shell is evaluated and the
@@ -104,15 +105,6 @@ __device__ __forceinline__ float wave_reduce16(const float (&v)[16], int lane) {
   w += __shfl_xor(w, 16, 64);
   w += __shfl_xor(w, 32, 64);
   return w;
-}
-
-// (s, e) += x with the rounding error of the addition carried in e (two-sum).
-__device__ __forceinline__ void two_sum_acc(float &s, float &e, float x) {
-#pragma clang fp contract(off)
-  const float t = s + x;
-  const float bp = t - s;
-  e += (s - (t - bp)) + (x - bp);
-  s = t;
 }
 
 // Cromer-Mann factor at s^2 in single precision via exp2.
@@ -212,25 +204,30 @@ __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const
                                              double (&B)[kSfRpt], double (&dA)[kSfRpt], double (&dB)[kSfRpt]) {
   constexpr int R = kSfRpt;
   if constexpr (MIXED) {
-    // per reflection: (sum, error) pairs of A, B and, with DERIV, dA, dB
-    constexpr int V = DERIV ? 8 : 4;
-    float acc[V][R];
+    // per reflection: A, B and, with DERIV, dA, dB in double; each chunk of
+    // up to kAtomTile atoms of a run is summed in single precision and added
+    // in double (the products of two singles are exact there)
+    constexpr int V = DERIV ? 4 : 2;
+    double acc[V][R];
 #pragma unroll
     for (int v = 0; v < V; ++v)
 #pragma unroll
-      for (int u = 0; u < R; ++u) acc[v][u] = 0.f;
+      for (int u = 0; u < R; ++u) acc[v][u] = 0.0;
     for (int ir = 0; ir < nr; ++ir) {
       const SpeciesRun run = cr[ir];
       const int rb = max(run.begin, wa), re = min(run.end, wb);
       if (rb >= re) continue;
       const double *c9 = coeff + 9 * run.species;
-      float f[R], df[R];
+      double f[R], df[R];
 #pragma unroll
       for (int u = 0; u < R; ++u) {
+        float ff, dd = 0.f;
         if constexpr (DERIV)
-          fsc_df_f32(c9, s2[u], &f[u], &df[u]);
+          fsc_df_f32(c9, s2[u], &ff, &dd);
         else
-          f[u] = fsc_f32(c9, s2[u]);
+          ff = fsc_f32(c9, s2[u]);
+        f[u] = ff;
+        df[u] = dd;
       }
       for (int j0 = rb; j0 < re; j0 += kAtomTile) {
         const int j1 = min(j0 + kAtomTile, re);
@@ -266,19 +263,17 @@ __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const
         for (; j < j1; ++j) term(atoms[j]);
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-          two_sum_acc(acc[0][u], acc[1][u], f[u] * pa[u]);
-          two_sum_acc(acc[2][u], acc[3][u], f[u] * pb[u]);
+          acc[0][u] = fma(f[u], (double)pa[u], acc[0][u]);
+          acc[1][u] = fma(f[u], (double)pb[u], acc[1][u]);
           if constexpr (DERIV) {
-            two_sum_acc(acc[4][u], acc[5][u], fmaf(df[u], pa[u], f[u] * qa[u]));
-            two_sum_acc(acc[6][u], acc[7][u], fmaf(df[u], pb[u], f[u] * qb[u]));
+            acc[2][u] = fma(df[u], (double)pa[u], fma(f[u], (double)qa[u], acc[2][u]));
+            acc[3][u] = fma(df[u], (double)pb[u], fma(f[u], (double)qb[u], acc[3][u]));
           }
         }
       }
     }
-    double tot[V / 2][R];
     if (ww.heavy) {
-      float *sp = reinterpret_cast<float *>(s_part);
-      auto at = [&](int w, int v, int u) -> float & { return sp[((w * V + v) * R + u) * 64 + lane]; };
+      auto at = [&](int w, int v, int u) -> double & { return s_part[((w * V + v) * R + u) * 64 + lane]; };
 #pragma unroll
       for (int v = 0; v < V; ++v)
 #pragma unroll
@@ -286,25 +281,20 @@ __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const
       __syncthreads();
       if (!all_waves && ww.part != 0) return false;
 #pragma unroll
-      for (int v = 0; v < V / 2; ++v)
+      for (int v = 0; v < V; ++v)
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-          tot[v][u] = 0.0;
-          for (int w = 0; w < kThreads / 64; ++w) tot[v][u] += (double)at(w, 2 * v, u) + (double)at(w, 2 * v + 1, u);
+          acc[v][u] = 0.0;
+          for (int w = 0; w < kThreads / 64; ++w) acc[v][u] += at(w, v, u);
         }
-    } else {
-#pragma unroll
-      for (int v = 0; v < V / 2; ++v)
-#pragma unroll
-        for (int u = 0; u < R; ++u) tot[v][u] = (double)acc[2 * v][u] + (double)acc[2 * v + 1][u];
     }
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      A[u] = tot[0][u];
-      B[u] = tot[1][u];
+      A[u] = acc[0][u];
+      B[u] = acc[1][u];
       if constexpr (DERIV) {
-        dA[u] = tot[2][u];
-        dB[u] = tot[3][u];
+        dA[u] = acc[2][u];
+        dB[u] = acc[3][u];
       }
     }
   } else {
@@ -429,8 +419,8 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
                                                  void *__restrict__ Bout, double *__restrict__ Iout,
                                                  void *__restrict__ cache) {
   constexpr int R = kSfRpt;
-  // heavy blocks: per wave, the (sum, error) float pairs or the doubles of
-  // each value, per reflection slot and lane
+  // heavy blocks: per wave, the doubles of each value (A, B and with DERIV
+  // dA, dB), per reflection slot and lane
   __shared__ double s_part[(kThreads / 64) * (DERIV ? 4 : 2) * R * 64];
   const WaveWork ww = wave_work(n_heavy);
   if (ww.item >= n_items) return;  // light blocks only: a heavy block's item always exists

@@ -31,8 +31,11 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kPer = kSortChunk / kThreads;  // 4
-constexpr int kMidBlocks = 256;              // blocks of the large-crystal sort (one per CU)
-constexpr int kMidThreads = 512;             // threads of a large-crystal sort block
+constexpr int kSmallThreads = 1024;          // threads of a block sorting up to 2 kSmallSort reflections
+constexpr int kMidThreads = 1024;            // ... up to 2 kMidSort reflections
+constexpr int kLargeBlocks = 256;            // blocks of the global-memory sort (crystals beyond 2 kMidSort)
+constexpr int kLargeThreads = 512;           // threads of a global-memory sort block
+constexpr int kGlobalCap = kLargeThreads;    // that kernel's LDS path is never taken (every crystal is larger)
 
 __device__ __forceinline__ int bin_of(const CrystalPlan &P, double tt) {
 #pragma clang fp contract(off)
@@ -150,7 +153,7 @@ __device__ void finish_crystal(const MergeOut &mo, int64_t c, int64_t r0, int np
 // evaluated half (local index >= R/2) in sorted order, at entry positions
 // starting at r0/2 (refl_offset values are even); with a merge, perm and the
 // crystal's staged peaks (MergeOut).
-template <int CAP, int T, bool LARGE>
+template <int CAP, int T, bool LARGE, int LO>
 __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *__restrict__ order,
                                                     const CrystalPlan *__restrict__ plan,
                                                     const int64_t *__restrict__ refl_offset,
@@ -170,11 +173,11 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
     const int64_t c = order[ci];
     const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
     const int64_t R64 = r1 - r0;
-    if (!LARGE && R64 == 0 && merge && threadIdx.x == 0) {
+    if (LO == 0 && R64 == 0 && merge && threadIdx.x == 0) {
       mo.pk_count[c] = 0;
       mo.cmax[c] = 0;
     }
-    if (R64 <= (LARGE ? 2 * kSmallSort : 0) || (!LARGE && R64 > 2 * CAP)) continue;
+    if (R64 <= LO || (!LARGE && R64 > 2 * CAP)) continue;  // another size's crystal
     const int64_t e_base = r0 / 2;
     const CrystalPlan &P = plan[c];
     int total;
@@ -538,27 +541,44 @@ MergeOut merge_out(const MergeArgs *m) {
   return mo;
 }
 
+// Sizes by a crystal's reflection count R (each kernel skips the other
+// sizes' crystals): R <= 2 kTinySort by 256 threads with 12 KB of LDS (eight
+// blocks per CU); R <= 2 kSmallSort and R <= 2 kMidSort by 1024 threads (a
+// short chain of phases for the larger crystals); beyond, the global-memory
+// path.  The three groups run on three streams (the caller's and two forked
+// ones), as they take disjoint crystals.
 void sort_kernels(const SortArgs &a, const MergeOut &mo, const Fork &f, hipStream_t s) {
   if (a.n_c <= 0) return;
   double *ek = a.friedel ? a.ent_key : nullptr;
   int32_t *ei = a.friedel ? a.ent_idx : nullptr;
-  // the two sizes take disjoint crystals: the larger one runs beside the other
-  const bool fork = a.n_mid > 0 && f.side != nullptr;
+  const bool fork = f.side != nullptr && (a.n_small > 0 || a.n_mid > 0);
+  hipStream_t s1 = fork ? f.side : s, s2 = fork ? f.side2 : s;
   if (fork) {
-    hipEventRecord(f.fork, s);
-    hipStreamWaitEvent(f.side, f.fork, 0);
+    (void)hipEventRecord(f.fork, s);
+    (void)hipStreamWaitEvent(f.side, f.fork, 0);
+    (void)hipStreamWaitEvent(f.side2, f.fork, 0);
   }
-  if (a.n_mid > 0) {
-    const unsigned g = (unsigned)(a.n_mid < kMidBlocks ? a.n_mid : kMidBlocks);
-    hipLaunchKernelGGL((k_sort_crystal<kMidSort, kMidThreads, true>), dim3(g), dim3(kMidThreads), 0,
-                       fork ? f.side : s, a.n_mid, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei,
-                       a.bin_count, a.bin_start, mo);
+  if (a.n_mid > 0)
+    hipLaunchKernelGGL((k_sort_crystal<kMidSort, kMidThreads, false, 2 * kSmallSort>), dim3((unsigned)a.n_mid),
+                       dim3(kMidThreads), 0, s2, a.n_mid, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek,
+                       ei, a.bin_count, a.bin_start, mo);
+  if (a.n_large > 0) {
+    const unsigned g = (unsigned)(a.n_large < kLargeBlocks ? a.n_large : kLargeBlocks);
+    hipLaunchKernelGGL((k_sort_crystal<kGlobalCap, kLargeThreads, true, 2 * kMidSort>), dim3(g), dim3(kLargeThreads),
+                       0, s2, a.n_large, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count,
+                       a.bin_start, mo);
   }
-  hipLaunchKernelGGL((k_sort_crystal<kSmallSort, 256, false>), dim3((unsigned)a.n_c), dim3(256), 0, s, a.n_c,
+  if (a.n_small > 0)
+    hipLaunchKernelGGL((k_sort_crystal<kSmallSort, kSmallThreads, false, 2 * kTinySort>), dim3((unsigned)a.n_small),
+                       dim3(kSmallThreads), 0, s1, a.n_small, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek,
+                       ei, a.bin_count, a.bin_start, mo);
+  hipLaunchKernelGGL((k_sort_crystal<kTinySort, 256, false, 0>), dim3((unsigned)a.n_c), dim3(256), 0, s, a.n_c,
                      a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count, a.bin_start, mo);
   if (fork) {
-    hipEventRecord(f.join, f.side);
-    hipStreamWaitEvent(s, f.join, 0);
+    (void)hipEventRecord(f.join, f.side);
+    (void)hipEventRecord(f.join2, f.side2);
+    (void)hipStreamWaitEvent(s, f.join, 0);
+    (void)hipStreamWaitEvent(s, f.join2, 0);
   }
 }
 

@@ -23,8 +23,9 @@ constexpr int kSfRpt = 2;         // reflections per lane in the structure-facto
 constexpr int kSfTile = 64 * kSfRpt;
 constexpr int kFusedMaxAtoms = 512;  // crystals up to this size take the fused atom-gradient path
 constexpr int kSplitAtoms = 24;      // crystals from this size get a block per structure-factor tile
-constexpr int kSmallSort = 4096;     // Friedel-positive reflections sorted in LDS by one 256-thread block
-constexpr int kMidSort = 12288;      // ... by one 512-thread block
+constexpr int kTinySort = 1024;      // Friedel-positive reflections sorted in LDS by one 256-thread block
+constexpr int kSmallSort = 4096;     // ... by one 1024-thread block
+constexpr int kMidSort = 8192;       // ... by one 1024-thread block; larger crystals sort in global memory
 constexpr int kSpanPts = 64;         // grid points per wave of the broadening gather
 
 // Per-crystal plan (device copy in the workspace), 256 bytes.
@@ -149,22 +150,24 @@ struct SortArgs {
   int64_t *scan_part;
   const int32_t *order;  // [n_c] crystals by descending capacity
   int64_t n_mid;         // leading entries of ``order`` with capacity above 2 kSmallSort
+  int64_t n_small;       // leading entries of ``order`` with capacity above 2 kTinySort
+  int64_t n_large;       // leading entries of ``order`` with capacity above 2 kMidSort
   int32_t friedel;       // write the evaluated-half entries below
   double *ent_key;       // [half capacity] 2theta of the evaluated half, sorted per crystal
   int32_t *ent_idx;      // its global reflection indices
 };
-// A second stream for independent work inside one call: the caller's stream
-// records ``fork``, the side stream waits for it, runs its part and records
-// ``join``, which the caller's stream waits for before the call's next step
-// (the pattern graph capture follows across streams).  side == nullptr runs
-// everything on the caller's stream.
+// Two more streams for independent work inside one call: the caller's stream
+// records ``fork``, the side streams wait for it, run their parts and record
+// ``join``/``join2``, which the caller's stream waits for before the call's
+// next step (the pattern graph capture follows across streams).
+// side == nullptr runs everything on the caller's stream.
 struct Fork {
-  hipStream_t side;
-  hipEvent_t fork, join;
+  hipStream_t side, side2;
+  hipEvent_t fork, join, join2;
 };
 
-// The large-crystal sort (capacity above 2 kSmallSort) goes to the fork's
-// side stream, concurrent with the one-block-per-crystal sort.
+// The sorts of the larger crystals go to the fork's side streams, concurrent
+// with the sort of the small ones.
 void launch_sort(const SortArgs &a, const Fork &f, hipStream_t s);
 
 struct MergeArgs {
