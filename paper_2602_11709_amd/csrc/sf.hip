@@ -843,6 +843,37 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
 
 // Sum of the partials of each atom in a fixed order (tile order for fused
 // crystals, chunk order otherwise); scatter to the caller's atom order.
+// Sum of rows p[0], p[stride], ... p[(n - 1) stride] in row order, eight
+// loads in flight at a time.
+__device__ __forceinline__ void sum_rows(const double4 *__restrict__ p, int64_t stride, int64_t n, double *sx,
+                                         double *sy, double *sz, double *sB) {
+  double ax = 0.0, ay = 0.0, az = 0.0, ab = 0.0;
+  int64_t t = 0;
+  for (; t + 8 <= n; t += 8) {
+    double4 v[8];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) v[i] = p[(t + i) * stride];
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      ax += v[i].x;
+      ay += v[i].y;
+      az += v[i].z;
+      ab += v[i].w;
+    }
+  }
+  for (; t < n; ++t) {
+    const double4 v = p[t * stride];
+    ax += v.x;
+    ay += v.y;
+    az += v.z;
+    ab += v.w;
+  }
+  *sx = ax;
+  *sy = ay;
+  *sz = az;
+  *sB = ab;
+}
+
 __device__ __forceinline__ void atom_bw_reduce(const AbItem it, bool friedel, const CrystalPlan *__restrict__ plan,
                                                const int64_t *__restrict__ refl_offset,
                                                const double4 *__restrict__ part,
@@ -859,22 +890,10 @@ __device__ __forceinline__ void atom_bw_reduce(const AbItem it, bool friedel, co
     const int64_t count = friedel ? nref / 2 : nref;
     const int64_t tiles = (count + kSfTile - 1) / kSfTile;  // tiles that ran
     const double4 *p = part_fused + P.pf_begin + ja;
-    for (int64_t t = 0; t < tiles; ++t) {
-      const double4 v = p[t * na];
-      sx += v.x;
-      sy += v.y;
-      sz += v.z;
-      sB += v.w;
-    }
+    sum_rows(p, na, tiles, &sx, &sy, &sz, &sB);
   } else {
     const double4 *p = part + P.part_begin + ja;
-    for (int k = 0; k < P.n_hchunks; ++k) {
-      const double4 v = p[(int64_t)k * na];
-      sx += v.x;
-      sy += v.y;
-      sz += v.z;
-      sB += v.w;
-    }
+    sum_rows(p, na, P.n_hchunks, &sx, &sy, &sz, &sB);
   }
   const double tp = 2.0 * 3.14159265358979323846;
   const int64_t o = orig[P.atom_begin + ja];
@@ -884,15 +903,11 @@ __device__ __forceinline__ void atom_bw_reduce(const AbItem it, bool friedel, co
   dbfac[o] = -sB;
 }
 
-// dL/dG* (6 unique entries, summed over n_rows partial rows in order) ->
+// dL/dG* (its 6 unique entries, U) ->
 // dL/d(a, b, c, alpha, beta, gamma), angles in degrees.  q = sum_ij M_ij h_i h_j
 // with M = G*, so dL/dM_ij = U_ij for i == j and U_ij / 2 for i != j (the
 // unique entry appears twice); dL/dG = -M (dL/dM) M.
-__device__ void lattice_chain(const CrystalPlan &P, const double *__restrict__ rows, int n_rows,
-                              double *__restrict__ o) {
-  double U[6] = {0, 0, 0, 0, 0, 0};
-  for (int k = 0; k < n_rows; ++k)
-    for (int e = 0; e < 6; ++e) U[e] += rows[k * 6 + e];
+__device__ void lattice_chain(const CrystalPlan &P, const double (&U)[6], double *__restrict__ o) {
   const double M[3][3] = {{P.gs[0], P.gs[3], P.gs[4]}, {P.gs[3], P.gs[1], P.gs[5]}, {P.gs[4], P.gs[5], P.gs[2]}};
   const double D[3][3] = {{U[0], 0.5 * U[3], 0.5 * U[4]}, {0.5 * U[3], U[1], 0.5 * U[5]}, {0.5 * U[4], 0.5 * U[5], U[2]}};
   double T[3][3], Gb[3][3];
@@ -926,10 +941,10 @@ __device__ void lattice_chain(const CrystalPlan &P, const double *__restrict__ r
 }
 
 // The last step of the adjoint, two independent parts in one launch: blocks
-// [0, n_ab) reduce the atom gradients (k_atom_bw_reduce's items), the rest
-// take one crystal per thread through the lattice chain rule, summing the
-// crystal's structure-factor tile rows of dL/dG* (the tiles that ran) in
-// order.
+// [0, n_ab) reduce the atom gradients (one thread per atom, its partial rows
+// in order), the rest take one crystal per wavefront through the lattice
+// chain rule, summing the crystal's structure-factor tile rows of dL/dG*
+// (the tiles that ran).
 __global__ __launch_bounds__(kThreads) void k_bw_finish(const AbItem *__restrict__ items, int64_t n_ab, bool friedel,
                                                         const CrystalPlan *__restrict__ plan, int64_t n_c,
                                                         const int64_t *__restrict__ refl_offset,
@@ -942,12 +957,24 @@ __global__ __launch_bounds__(kThreads) void k_bw_finish(const AbItem *__restrict
     atom_bw_reduce(items[blockIdx.x], friedel, plan, refl_offset, part, part_fused, orig, dfrac, dbfac);
     return;
   }
-  const int64_t c = (int64_t)(blockIdx.x - n_ab) * kThreads + threadIdx.x;
+  // one wavefront per crystal: lane i sums rows i, i + 64, ... in order, the
+  // wavefront adds the lanes' sums in a fixed pattern, lane 63 applies the
+  // chain rule
+  const int lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)(blockIdx.x - n_ab) * (kThreads / 64) + (threadIdx.x >> 6);
   if (c >= n_c) return;
   const CrystalPlan &P = plan[c];
   const int64_t nref = refl_offset[c + 1] - refl_offset[c];
   const int64_t count = friedel ? nref / 2 : nref;
-  lattice_chain(P, part6 + (int64_t)P.tile_begin * 6, (int)((count + kSfTile - 1) / kSfTile), dlat + 6 * c);
+  const int n_rows = (int)((count + kSfTile - 1) / kSfTile);
+  const double *rows = part6 + (int64_t)P.tile_begin * 6;
+  double U[6] = {0, 0, 0, 0, 0, 0};
+  for (int k = lane; k < n_rows; k += 64)
+#pragma unroll
+    for (int e = 0; e < 6; ++e) U[e] += rows[k * 6 + e];
+#pragma unroll
+  for (int e = 0; e < 6; ++e) U[e] = wave_sum_to_63(U[e]);
+  if (lane == 63) lattice_chain(P, U, dlat + 6 * c);
 }
 
 }  // namespace
@@ -1048,7 +1075,7 @@ void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_ite
 void launch_bw_finish(const AbItem *items, int64_t n_ab, bool friedel, const CrystalPlan *plan, int64_t n_c,
                       const int64_t *refl_offset, const double *part, const double *part_fused, const int32_t *orig,
                       const double *part6, double *dfrac, double *dbfac, double *dlat, hipStream_t s) {
-  const int64_t blocks = n_ab + (n_c + kThreads - 1) / kThreads;
+  const int64_t blocks = n_ab + (n_c + kThreads / 64 - 1) / (kThreads / 64);
   if (blocks <= 0) return;
   hipLaunchKernelGGL(k_bw_finish, dim3((unsigned)blocks), dim3(kThreads), 0, s, items, n_ab, friedel, plan, n_c,
                      refl_offset, (const double4 *)part, (const double4 *)part_fused, orig, part6, dfrac, dbfac,
