@@ -9,10 +9,10 @@
 // by row ((h, k) fixed, one row per thread), each row only over the l that
 // the quadratic q(l) can bring into the limiting sphere.  The rows are taken
 // in chunks of 64, one wavefront each: count the survivors per chunk, scan
-// the counts, then count again, rank and write (h, k, l) and q of each
-// survivor and its Friedel mate, and last 2theta and LP, one thread per
-// written reflection.  The output of a crystal is its full sphere shell in
-// ascending (h, k, l) order:
+// the counts, then flatten the chunk's rows into candidate points, test,
+// rank and write each survivor (h, k, l, q, 2theta, LP) and its Friedel
+// mate.  The output of a crystal is its full sphere shell in ascending
+// (h, k, l) order:
 // the positive half occupies the upper half of the segment and mate i sits at
 // the mirror position, so no sort is needed for the hkl listing.
 //
@@ -296,34 +296,57 @@ constexpr int kOneBlockChunks = 8192;
 __global__ __launch_bounds__(1024) void k_enum_scan1(const CrystalPlan *__restrict__ plan, int64_t n_c,
                                                      int64_t n_chunks, const int32_t *__restrict__ counts,
                                                      int64_t *__restrict__ prefix, int64_t *__restrict__ refl_offset) {
+  constexpr int PER = kOneBlockChunks / 1024;  // consecutive chunks per thread
+  __shared__ int64_t s_pre[kOneBlockChunks + 1];
   __shared__ int64_t wsum[1024 / 64];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  int64_t carry = 0;
-  for (int64_t c0 = 0; c0 < n_chunks; c0 += 1024) {
-    const int64_t i = c0 + threadIdx.x;
-    const int64_t v = i < n_chunks ? counts[i] : 0;
-    int64_t inc = v;
+  // every load first: the thread's chunk counts and its crystals' first chunks
+  // (n_c <= n_chunks <= kOneBlockChunks)
+  int32_t v[PER], cb[PER];
+  const int64_t i0 = (int64_t)threadIdx.x * PER;
 #pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const int64_t o = __shfl_up(inc, d, 64);
-      if (lane >= d) inc += o;
-    }
-    __syncthreads();
-    if (lane == 63) wsum[wid] = inc;
-    __syncthreads();
-    int64_t before = 0, total = 0;
+  for (int u = 0; u < PER; ++u) v[u] = i0 + u < n_chunks ? counts[i0 + u] : 0;
 #pragma unroll
-    for (int w = 0; w < 1024 / 64; ++w) {
-      before += w < wid ? wsum[w] : 0;
-      total += wsum[w];
-    }
-    if (i < n_chunks) prefix[i] = carry + before + inc - v;
-    carry += total;
+  for (int u = 0; u < PER; ++u) {
+    const int64_t c = threadIdx.x + (int64_t)u * 1024;
+    cb[u] = c < n_c ? (int32_t)plan[c].enum_chunk_begin : 0;
   }
-  if (threadIdx.x == 0) prefix[n_chunks] = carry;
-  __syncthreads();  // the block's prefix writes are visible to the whole block
-  for (int64_t c = threadIdx.x; c <= n_c; c += 1024)
-    refl_offset[c] = 2 * (c < n_c ? prefix[plan[c].enum_chunk_begin] : carry);
+  int64_t sum = 0;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) sum += v[u];
+  int64_t inc = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int64_t o = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += o;
+  }
+  if (lane == 63) wsum[wid] = inc;
+  __syncthreads();
+  int64_t run = inc - sum, total = 0;
+#pragma unroll
+  for (int w = 0; w < 1024 / 64; ++w) {
+    run += w < wid ? wsum[w] : 0;
+    total += wsum[w];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    if (i0 + u < n_chunks) {
+      s_pre[i0 + u] = run;
+      prefix[i0 + u] = run;
+    }
+    run += v[u];
+  }
+  if (threadIdx.x == 0) {
+    s_pre[n_chunks] = total;
+    prefix[n_chunks] = total;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int64_t c = threadIdx.x + (int64_t)u * 1024;
+    if (c < n_c) refl_offset[c] = 2 * s_pre[cb[u]];
+  }
+  if (threadIdx.x == 0) refl_offset[n_c] = 2 * total;
 }
 
 __global__ void k_enum_offsets(const CrystalPlan *__restrict__ plan, int64_t n_c, int64_t n_chunks,
@@ -338,13 +361,14 @@ __global__ void k_enum_offsets(const CrystalPlan *__restrict__ plan, int64_t n_c
 // lexicographic order; the wavefront then takes the points 64 at a time, one
 // per lane (a binary search over the rows' candidate offsets finds a point's
 // row), tests them, ranks the survivors with a ballot and writes each with
-// its Friedel mate: (h, k, l) and q.  2theta and LP follow in k_enum_geom.
+// its Friedel mate: (h, k, l), q, 2theta and LP.
 __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__restrict__ plan,
                                                         const int32_t *__restrict__ chunk_crystal,
                                                         int64_t n_chunks, const int64_t *__restrict__ prefix,
                                                         double lambda, int16_t *__restrict__ oh,
                                                         int16_t *__restrict__ ok, int16_t *__restrict__ ol,
-                                                        double *__restrict__ oq) {
+                                                        double *__restrict__ oq, double *__restrict__ ott,
+                                                        double *__restrict__ olp) {
   __shared__ int32_t s_off[kThreads / 64][kEnumRows + 1];  // candidate offsets of a wavefront's rows
   __shared__ int32_t s_lo[kThreads / 64][kEnumRows], s_h[kThreads / 64][kEnumRows], s_k[kThreads / 64][kEnumRows];
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
@@ -378,63 +402,53 @@ __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__res
   s_k[wid][lane] = r.k;
   wave_sync();
   int64_t rank = prefix[chunk] - c_begin;
-  for (int base = 0; base < total; base += 64) {
-    const int ci = base + lane;
-    Hkl m{0, 0, 0};
-    double q = 0.0, tt = 0.0;
-    bool kp = false;
-    if (ci < total) {
-      int a = 0, b = kEnumRows - 1;  // last row whose offset is <= ci
-      while (a < b) {
-        const int mid = (a + b + 1) >> 1;
-        if (off[mid] <= ci) a = mid; else b = mid - 1;
+  // four candidates per lane per round: their searches, tests and 2theta
+  // are independent, so their latencies overlap
+  constexpr int U = 4;
+  for (int base = 0; base < total; base += 64 * U) {
+    Hkl m[U];
+    double q[U], tt[U];
+    bool kp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int ci = base + u * 64 + lane;
+      m[u] = Hkl{0, 0, 0};
+      q[u] = tt[u] = 0.0;
+      kp[u] = false;
+      if (ci < total) {
+        int a = 0, b = kEnumRows - 1;  // last row whose offset is <= ci
+        while (a < b) {
+          const int mid = (a + b + 1) >> 1;
+          if (off[mid] <= ci) a = mid; else b = mid - 1;
+        }
+        m[u] = Hkl{s_h[wid][a], s_k[wid][a], s_lo[wid][a] + (ci - off[a])};
+        kp[u] = keep_point(P, m[u], lambda, true, &q[u], &tt[u]);
       }
-      m = Hkl{s_h[wid][a], s_k[wid][a], s_lo[wid][a] + (ci - off[a])};
-      kp = keep_point(P, m, lambda, false, &q, &tt);
     }
-    const uint64_t bal = __ballot(kp);
-    const int wrank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-    const int64_t rk = rank + wrank;
-    if (kp && rk < rh) {  // rk < rh always: the count took the same decisions
-      const int64_t pos = seg + rh + rk;
-      const int64_t mate = seg + rh - 1 - rk;
-      oh[pos] = (int16_t)m.h;
-      ok[pos] = (int16_t)m.k;
-      ol[pos] = (int16_t)m.l;
-      oh[mate] = (int16_t)(-m.h);
-      ok[mate] = (int16_t)(-m.k);
-      ol[mate] = (int16_t)(-m.l);
-      oq[pos] = q;
-      oq[mate] = q;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t bal = __ballot(kp[u]);
+      const int wrank = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      const int64_t rk = rank + wrank;
+      if (kp[u] && rk < rh) {  // rk < rh always: the count took the same decisions
+        const int64_t pos = seg + rh + rk;
+        const int64_t mate = seg + rh - 1 - rk;
+        const double lp = lp_of_q(q[u], lambda);
+        oh[pos] = (int16_t)m[u].h;
+        ok[pos] = (int16_t)m[u].k;
+        ol[pos] = (int16_t)m[u].l;
+        oh[mate] = (int16_t)(-m[u].h);
+        ok[mate] = (int16_t)(-m[u].k);
+        ol[mate] = (int16_t)(-m[u].l);
+        oq[pos] = q[u];
+        oq[mate] = q[u];
+        ott[pos] = tt[u];
+        ott[mate] = tt[u];
+        olp[pos] = lp;
+        olp[mate] = lp;
+      }
+      rank += __popcll(bal);
     }
-    rank += __popcll(bal);
-  }
-}
-
-// 2theta and LP of the reflections a chunk wrote, one block per chunk, one
-// reflection per thread (positive half; the mate shares q, hence both).
-__global__ __launch_bounds__(kThreads) void k_enum_geom(const CrystalPlan *__restrict__ plan,
-                                                        const int32_t *__restrict__ chunk_crystal,
-                                                        const int64_t *__restrict__ prefix, double lambda,
-                                                        const double *__restrict__ oq, double *__restrict__ ott,
-                                                        double *__restrict__ olp) {
-  const int chunk = blockIdx.x;
-  const CrystalPlan &P = plan[chunk_crystal[chunk]];
-  const int64_t first_chunk = P.enum_chunk_begin;
-  const int64_t c_begin = prefix[first_chunk];
-  const int64_t rh = prefix[first_chunk + P.enum_chunks] - c_begin;
-  const int64_t seg = 2 * c_begin;
-  const int64_t r0 = prefix[chunk] - c_begin, n = prefix[chunk + 1] - prefix[chunk];
-  for (int64_t j = threadIdx.x; j < n; j += kThreads) {
-    const int64_t rk = r0 + j;
-    const int64_t pos = seg + rh + rk, mate = seg + rh - 1 - rk;
-    const double q = oq[pos];
-    const double tt = two_theta_of(q, lambda);
-    const double lp = lp_of_q(q, lambda);
-    ott[pos] = tt;
-    ott[mate] = tt;
-    olp[pos] = lp;
-    olp[mate] = lp;
   }
 }
 
@@ -468,9 +482,7 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk
   }
   if (n_chunks > 0) {
     hipLaunchKernelGGL(k_enum_fill, dim3((unsigned)((n_chunks + kThreads / 64 - 1) / (kThreads / 64))),
-                       dim3(kThreads), 0, s, plan, chunk_crystal, n_chunks, prefix, lambda, h, k, l, q);
-    hipLaunchKernelGGL(k_enum_geom, dim3((unsigned)n_chunks), dim3(kThreads), 0, s, plan, chunk_crystal, prefix,
-                       lambda, q, tt, lp);
+                       dim3(kThreads), 0, s, plan, chunk_crystal, n_chunks, prefix, lambda, h, k, l, q, tt, lp);
   }
 }
 
