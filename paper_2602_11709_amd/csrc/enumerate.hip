@@ -208,9 +208,19 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
     const int64_t j = base + lane;
     bool active = j < a1;
     int sp = -1;
+    AtomRec a{};
     if (active) {
+      // the atom's record is read before the species peeling, whose steps
+      // then wait on LDS only
       sp = species[j];
       if (sp < 0 || sp >= n_species) sp = 0;
+      a.x = frac[3 * j];
+      a.y = frac[3 * j + 1];
+      a.z = frac[3 * j + 2];
+      a.occ = occ[j];
+      a.bfac = bfac[j];
+      a.log2occ = __log2f((float)a.occ);
+      a.bl2e = (float)a.bfac * kLog2e;
     }
     while (true) {
       const uint64_t act = __ballot(active);
@@ -223,14 +233,6 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
       if (active && sp == t) {
         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         const int pos = base_pos + rank;
-        AtomRec a;
-        a.x = frac[3 * j];
-        a.y = frac[3 * j + 1];
-        a.z = frac[3 * j + 2];
-        a.occ = occ[j];
-        a.bfac = bfac[j];
-        a.log2occ = __log2f((float)a.occ);
-        a.bl2e = (float)a.bfac * kLog2e;
         atoms[pos] = a;
         orig[pos] = (int32_t)j;
         active = false;
