@@ -27,7 +27,8 @@ struct xrd_batch {
   std::vector<double> lattice, tmin, tmax;
   std::vector<int64_t> atom_offset;
   std::vector<CrystalPlan> plan;
-  std::vector<int32_t> enum_chunk_crystal, sort_chunk_crystal;
+  std::vector<int32_t> enum_chunk_crystal;
+  std::vector<HChunk> peak_chunks;  // peak chunks of the merge (crystal, chunk)
   std::vector<HChunk> hchunks;  // entry chunks of the broadening (crystal, chunk)
   std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
   std::vector<SfItem> sf_items;
@@ -279,11 +280,9 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
 
   // launch tables
   b->enum_chunk_crystal.resize(ec);
-  b->sort_chunk_crystal.resize(sc);
   for (int64_t c = 0; c < nc; ++c) {
     const CrystalPlan &P = b->plan[c];
     for (int32_t i = 0; i < P.enum_chunks; ++i) b->enum_chunk_crystal[P.enum_chunk_begin + i] = (int32_t)c;
-    for (int32_t i = 0; i < P.sort_chunks; ++i) b->sort_chunk_crystal[P.sort_chunk_begin + i] = (int32_t)c;
   }
   // Capacities come from the search box; the reflections a crystal actually
   // has are close to the lattice points of its spherical shell, (4 pi / 3)
@@ -309,6 +308,17 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   for (int64_t c = 0; c < nc; ++c) b->crystal_order[c] = (int32_t)c;
   std::stable_sort(b->crystal_order.begin(), b->crystal_order.end(),
                    [&](int32_t x, int32_t y) { return b->plan[x].half_box > b->plan[y].half_box; });
+  // peak chunks: a crystal's peaks are about half its reflections (mates share 2theta)
+  {
+    std::vector<int32_t> split(nc);
+    for (int64_t c = 0; c < nc; ++c) {
+      const double refl = expect_eval[c] * (friedel ? 2.0 : 1.0);
+      split[c] = (int32_t)std::min<double>(b->plan[c].sort_chunks, std::ceil((0.5 * refl + kSortChunk) / kSortChunk));
+      for (int32_t i = 0; i < split[c]; ++i) b->peak_chunks.push_back(HChunk{(int32_t)c, i});
+    }
+    for (int64_t c = 0; c < nc; ++c)
+      for (int32_t i = split[c]; i < b->plan[c].sort_chunks; ++i) b->peak_chunks.push_back(HChunk{(int32_t)c, i});
+  }
   // entry chunks, heaviest crystals first, expected-filled chunks before the rest
   {
     std::vector<int32_t> split(nc);
@@ -372,7 +382,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.plan = take((int64_t)sizeof(CrystalPlan) * nc);
   L.enum_chunk_crystal = take(4 * ec);
   L.sf_items = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items.size());
-  L.sort_chunk_crystal = take(4 * sc);
+  L.peak_chunks = take((int64_t)sizeof(HChunk) * sc);
   L.hchunks = take((int64_t)sizeof(HChunk) * hc);
   L.crystal_order = take(4 * nc);
   L.bw_items = take((int64_t)sizeof(BwItem) * (int64_t)b->bw_items.size());
@@ -443,7 +453,7 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   if (e == hipSuccess) e = up(L.plan, b->plan.data(), sizeof(CrystalPlan) * b->plan.size());
   if (e == hipSuccess) e = up(L.enum_chunk_crystal, b->enum_chunk_crystal.data(), 4 * b->enum_chunk_crystal.size());
   if (e == hipSuccess) e = up(L.sf_items, b->sf_items.data(), sizeof(SfItem) * b->sf_items.size());
-  if (e == hipSuccess) e = up(L.sort_chunk_crystal, b->sort_chunk_crystal.data(), 4 * b->sort_chunk_crystal.size());
+  if (e == hipSuccess) e = up(L.peak_chunks, b->peak_chunks.data(), sizeof(HChunk) * b->peak_chunks.size());
   if (e == hipSuccess) e = up(L.hchunks, b->hchunks.data(), sizeof(HChunk) * b->hchunks.size());
   if (e == hipSuccess) e = up(L.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
   if (e == hipSuccess) e = up(L.bw_items, b->bw_items.data(), sizeof(BwItem) * b->bw_items.size());
@@ -545,8 +555,6 @@ static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r) {
   SortArgs a;
   a.n_c = b->desc.n_crystals;
   a.plan = at<CrystalPlan>(ws, L.plan);
-  a.chunk_crystal = at<int32_t>(ws, L.sort_chunk_crystal);
-  a.n_chunks = (int64_t)b->sort_chunk_crystal.size();
   a.refl_offset = r->refl_offset;
   a.tt = r->two_theta;
   a.h = r->h;
@@ -588,6 +596,8 @@ int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, 
   a.tmp_mult = at<int32_t>(ws, L.tmp_mult);
   a.tmp_first = at<int64_t>(ws, L.tmp_first);
   a.pk_count = at<int32_t>(ws, L.pk_count);
+  a.peak_chunks = at<HChunk>(ws, L.peak_chunks);
+  a.n_peak_chunks = (int64_t)b->peak_chunks.size();
   a.cmax = at<uint64_t>(ws, L.cmax);
   a.pk_tt = p->two_theta;
   a.pk_i = p->intensity;

@@ -496,20 +496,22 @@ __global__ __launch_bounds__(1024) void k_peak_scan(int64_t n_c, const int32_t *
 
 // Packs each crystal's staged peaks at peak_offset[c] and scales them:
 // scaled = 100 I / max I of the crystal (0 when that maximum is 0).  One block
-// per sort chunk (kSortChunk peak slots of one crystal).
-__global__ __launch_bounds__(kThreads) void k_peak_move(const CrystalPlan *__restrict__ plan,
-                                                        const int32_t *__restrict__ chunk_crystal,
+// per peak chunk (kSortChunk peak slots of one crystal, from a table of
+// (crystal, chunk) pairs).
+__global__ __launch_bounds__(kThreads) void k_peak_move(const HChunk *__restrict__ chunks,
                                                         const int64_t *__restrict__ refl_offset,
                                                         const int64_t *__restrict__ peak_offset, MergeOut mo,
                                                         double *__restrict__ pk_tt, double *__restrict__ pk_i,
                                                         double *__restrict__ pk_y, int32_t *__restrict__ pk_mult,
                                                         int64_t *__restrict__ pk_first) {
-  const int32_t c = chunk_crystal[blockIdx.x];
-  const int64_t k0 = (int64_t)(blockIdx.x - plan[c].sort_chunk_begin) * kSortChunk;
+  const HChunk ch = chunks[blockIdx.x];
+  const int32_t c = ch.crystal;
+  const int64_t k0 = (int64_t)ch.chunk * kSortChunk;
+  // the crystal's values, loaded together
   const int np = mo.pk_count[c];
-  if (k0 >= np) return;
   const int64_t r0 = refl_offset[c], o = peak_offset[c];
   const double mx = __longlong_as_double((long long)mo.cmax[c]);
+  if (k0 >= np) return;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int64_t k = k0 + u * kThreads + threadIdx.x;
@@ -595,8 +597,8 @@ void launch_merge(const MergeArgs &a, const Fork &f, hipStream_t s) {
   const MergeOut mo = merge_out(&a);
   sort_kernels(o, mo, f, s);
   hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, s, a.n_c, a.pk_count, a.peak_offset);
-  if (o.n_chunks > 0)
-    hipLaunchKernelGGL(k_peak_move, dim3((unsigned)o.n_chunks), dim3(kThreads), 0, s, o.plan, o.chunk_crystal,
+  if (a.n_peak_chunks > 0)
+    hipLaunchKernelGGL(k_peak_move, dim3((unsigned)a.n_peak_chunks), dim3(kThreads), 0, s, a.peak_chunks,
                        o.refl_offset, a.peak_offset, mo, a.pk_tt, a.pk_i, a.pk_y, a.pk_mult, a.pk_first);
 }
 

@@ -83,7 +83,7 @@ struct SfItem {
 
 // Workspace byte offsets (all 256-aligned).
 struct WsLayout {
-  int64_t plan, enum_chunk_crystal, sf_items, sort_chunk_crystal, hchunks, crystal_order, bw_items, ab_items;
+  int64_t plan, enum_chunk_crystal, sf_items, peak_chunks, hchunks, crystal_order, bw_items, ab_items;
   int64_t enum_count, enum_prefix;
   int64_t atoms, atom_orig, runs, run_count, err_flag;
   int64_t bin_count, bin_start;
@@ -137,8 +137,6 @@ void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, i
 struct SortArgs {
   int64_t n_c;
   const CrystalPlan *plan;
-  const int32_t *chunk_crystal;
-  int64_t n_chunks;
   const int64_t *refl_offset;
   const double *tt;
   const int16_t *h, *k, *l;
@@ -182,6 +180,8 @@ struct MergeArgs {
   int64_t *tmp_first;
   int32_t *pk_count;   // [n_c]
   uint64_t *cmax;      // [n_c]
+  const HChunk *peak_chunks;  // (crystal, chunk of kSortChunk peak slots), expected-filled first
+  int64_t n_peak_chunks;
   // outputs
   double *pk_tt, *pk_i, *pk_y;
   int32_t *pk_mult;
