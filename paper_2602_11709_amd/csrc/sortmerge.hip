@@ -148,11 +148,12 @@ __device__ void finish_crystal(const MergeOut &mo, int64_t c, int64_t r0, int np
 // sort within buckets.  Crystals are taken in ``order``, heaviest first; the
 // first n_c of them are the kernel's.
 //
-// Outputs: skey/sidx, the crystal's 2theta keys and global reflection indices
-// in sorted order; with Friedel pairing (ent_key non-null), the entries of the
-// evaluated half (local index >= R/2) in sorted order, at entry positions
-// starting at r0/2 (refl_offset values are even); with a merge, perm and the
-// crystal's staged peaks (MergeOut).
+// Outputs: without Friedel pairing, skey/sidx, the crystal's 2theta keys and
+// global reflection indices in sorted order (the entries of the broadening);
+// with it (ent_key non-null), the entries of the evaluated half (local index
+// >= R/2) in sorted order, at entry positions starting at r0/2 (refl_offset
+// values are even), and skey/sidx only as the global-memory path's working
+// storage; with a merge, perm and the crystal's staged peaks (MergeOut).
 template <int CAP, int T, bool LARGE, int LO>
 __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *__restrict__ order,
                                                     const CrystalPlan *__restrict__ plan,
@@ -387,18 +388,24 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
         ent_key[e_base + j] = tj;
         ent_idx[e_base + j] = (int32_t)(r0 + H + p);
       }
-      int ga = j, gb = j;
-      while (ga > 0 && key[ga - 1] == kj) --ga;
-      while (gb + 1 < H && key[gb + 1] == kj) ++gb;
-      const int fm = 2 * ga + (gb - j), fp = gb + 1 + j;
-      const int64_t im = r0 + H - 1 - p, ip = r0 + H + p;
-      skey[r0 + fm] = tj;
-      sidx[r0 + fm] = (int32_t)im;
-      skey[r0 + fp] = tj;
-      sidx[r0 + fp] = (int32_t)ip;
-      if (merge) {
-        mo.perm[r0 + fm] = im;
-        mo.perm[r0 + fp] = ip;
+      // the full order: as the merge's perm, and as the entries themselves
+      // without Friedel pairing (skey/sidx are the entries then)
+      if (!ent_key || merge) {
+        int ga = j, gb = j;
+        while (ga > 0 && key[ga - 1] == kj) --ga;
+        while (gb + 1 < H && key[gb + 1] == kj) ++gb;
+        const int fm = 2 * ga + (gb - j), fp = gb + 1 + j;
+        const int64_t im = r0 + H - 1 - p, ip = r0 + H + p;
+        if (!ent_key) {
+          skey[r0 + fm] = tj;
+          sidx[r0 + fm] = (int32_t)im;
+          skey[r0 + fp] = tj;
+          sidx[r0 + fp] = (int32_t)ip;
+        }
+        if (merge) {
+          mo.perm[r0 + fm] = im;
+          mo.perm[r0 + fp] = ip;
+        }
       }
     }
     if (merge) {
