@@ -205,11 +205,9 @@ __global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restric
                                                         GridArgs g, double *__restrict__ y) {
 #pragma clang fp contract(off)
   using real = typename std::conditional<MIXED, float, double>::type;
-  struct Ent {
-    double t;
-    real w;
-  };
-  __shared__ Ent s_ent[kGTile];
+  // an entry is 16 bytes (2theta, weight, padding under MIXED), read with one
+  // 128-bit LDS access
+  __shared__ double2 s_ent[kGTile];
   const int S = (int)((g.n + kSpanPts - 1) / kSpanPts);
   const int segs = (int)((g.n + kSegPts - 1) / kSegPts);
   const int64_t c = crystal_order[blockIdx.x / segs];
@@ -243,7 +241,15 @@ __global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restric
 #pragma unroll
     for (int k = 0; k < kGTile / 256; ++k) {
       const int e = T0 + k * 256 + (int)threadIdx.x;
-      if (e <= T1) s_ent[e - T0] = Ent{ent_key[er.base + e], wts[er.base + e]};
+      if (e <= T1) {
+        double2 v;
+        v.x = ent_key[er.base + e];
+        if constexpr (MIXED)
+          v.y = __hiloint2double(0, __float_as_int(wts[er.base + e]));
+        else
+          v.y = wts[er.base + e];
+        s_ent[e - T0] = v;
+      }
     }
     __syncthreads();
 #pragma unroll
@@ -252,14 +258,15 @@ __global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restric
       real sacc = acc[j];
 #pragma unroll 8
       for (int e = a; e <= b; ++e) {
-        const Ent ent = s_ent[e];
-        const double d = x[j] - ent.t;
+        const double2 ent = s_ent[e];
+        const double d = x[j] - ent.x;
         if (fabs(d) <= g.half) {
           if constexpr (MIXED) {
             const float df = (float)d;
-            sacc = __builtin_fmaf(ent.w, __builtin_amdgcn_exp2f(-(df * df) * c2), sacc);
+            const float w = __int_as_float(__double2loint(ent.y));
+            sacc = __builtin_fmaf(w, __builtin_amdgcn_exp2f(-(df * df) * c2), sacc);
           } else {
-            sacc += ent.w * exp(-(d * d) * g.inv2s2);
+            sacc += ent.y * exp(-(d * d) * g.inv2s2);
           }
         }
       }
