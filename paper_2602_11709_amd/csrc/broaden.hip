@@ -298,14 +298,24 @@ __device__ __forceinline__ void adj_walk(const src_t *__restrict__ src, int off,
   real a1 = 0, a2 = 0;
   if (wl <= wh) {
     const double d0 = g.t0 + (double)wl * g.dt - t;
-    real K = (real)(g.norm * exp(-(d0 * d0) * g.inv2s2));
-    real r = (real)exp(-(2.0 * d0 * g.dt + g.dt * g.dt) * g.inv2s2);
+    // the first kernel value and ratio: exponent arguments in double, the
+    // exponentials in the working precision (single: v_exp_f32 of the
+    // argument times log2 e)
+    const double e0 = -(d0 * d0) * g.inv2s2, e1 = -(2.0 * d0 * g.dt + g.dt * g.dt) * g.inv2s2;
+    real K, r;
+    if constexpr (sizeof(real) == 4) {
+      K = (real)g.norm * __builtin_amdgcn_exp2f((float)(e0 * 1.4426950408889634));
+      r = __builtin_amdgcn_exp2f((float)(e1 * 1.4426950408889634));
+    } else {
+      K = (real)(g.norm * exp(e0));
+      r = (real)exp(e1);
+    }
     real d = (real)d0;
 #pragma unroll 4
     for (int gi = wl; gi <= wh; ++gi) {
       const real kv = (real)src[gi - off] * K;
       a1 += kv;
-      a2 += kv * d;
+      a2 = fma(kv, d, a2);
       K *= r;
       r *= rho;
       d += dtr;
