@@ -27,7 +27,7 @@ namespace xrd {
 namespace {
 
 constexpr int kThreads = 256;
-static_assert(kEnumRows == 64, "one row per lane of a wavefront");
+static_assert(kEnumRows <= 64, "one row per lane of a wavefront");
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kFusedPackLds = 4096;  // largest cursor space the fused count-and-pack launch carries
 
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__re
   if (chunk >= n_chunks) return;
   const CrystalPlan &P = plan[chunk_crystal[chunk]];
   const int64_t rho = (chunk - P.enum_chunk_begin) * kEnumRows + lane;
-  int n = rho < rows_of(P) ? row_count(P, row_of(P, rho), lambda) : 0;
+  int n = lane < kEnumRows && rho < rows_of(P) ? row_count(P, row_of(P, rho), lambda) : 0;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) n += __shfl_xor(n, d, 64);
   if (lane == 0) counts[chunk] = n;
@@ -358,7 +358,8 @@ __global__ void k_enum_offsets(const CrystalPlan *__restrict__ plan, int64_t n_c
   if (c == n_c) refl_offset[n_c] = 2 * prefix[n_chunks];
 }
 
-// One wavefront per chunk of kEnumRows rows (lane = row), four chunks per
+// One wavefront per chunk of kEnumRows rows (lane = row, for the first
+// kEnumRows lanes), four chunks per
 // block.  The chunk's rows are flattened into their candidate points in
 // lexicographic order; the wavefront then takes the points 64 at a time, one
 // per lane (a binary search over the rows' candidate offsets finds a point's
@@ -384,7 +385,7 @@ __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__res
   const int64_t rho = (chunk - first_chunk) * kEnumRows + lane;
   int lo = 1, hi = 0;
   Row r{0, 0, 1, 0};
-  if (rho < rows_of(P)) {
+  if (lane < kEnumRows && rho < rows_of(P)) {
     r = row_of(P, rho);
     row_candidates(P, r, &lo, &hi);
   }
@@ -397,11 +398,13 @@ __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__res
   }
   const int total = __shfl(inc, 63, 64);
   int32_t *off = s_off[wid];
-  off[lane] = inc - nc;
+  if (lane < kEnumRows) {
+    off[lane] = inc - nc;
+    s_lo[wid][lane] = lo;
+    s_h[wid][lane] = r.h;
+    s_k[wid][lane] = r.k;
+  }
   if (lane == 0) off[kEnumRows] = total;
-  s_lo[wid][lane] = lo;
-  s_h[wid][lane] = r.h;
-  s_k[wid][lane] = r.k;
   wave_sync();
   int64_t rank = prefix[chunk] - c_begin;
   // four candidates per lane per round: their searches, tests and 2theta

@@ -13,7 +13,7 @@
 namespace xrd {
 
 // Work granularity.
-constexpr int kEnumRows = 64;     // (h, k) rows of a half search box per enumeration chunk, one per lane
+constexpr int kEnumRows = 32;     // (h, k) rows of a half search box per enumeration chunk, one per lane
 constexpr int kSortChunk = 1024;  // reflections per sort/merge block (256 threads x 4)
 constexpr int kBinDiv = 4;        // merge-sort bins per crystal = capacity / kBinDiv
 constexpr int kHalfChunk = 2048;  // reflections per adjoint chunk
