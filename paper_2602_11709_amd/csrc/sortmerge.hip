@@ -44,9 +44,27 @@ __device__ __forceinline__ int bin_of(const CrystalPlan &P, double tt) {
   return b;
 }
 
+// Barrier that orders LDS accesses only: the wavefronts' global stores may
+// still be in flight when it releases.  For phases whose threads exchange
+// data through LDS and never read each other's global writes.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Block barrier: LDS only (LDS_ONLY) or all memory.
+template <bool LDS_ONLY>
+__device__ __forceinline__ void block_barrier() {
+  if constexpr (LDS_ONLY)
+    lds_barrier();
+  else
+    __syncthreads();
+}
+
 // Exclusive block-wide scan of one int per thread (T threads); ``wsum`` holds
 // T/64 ints of LDS.  Every thread of the block must call it.
-template <int T>
+template <int T, bool LDS_ONLY = false>
 __device__ __forceinline__ int block_exclusive_scan(int v, int32_t *wsum, int *total) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   int inc = v;
@@ -55,9 +73,9 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int32_t *wsum, int *t
     const int o = __shfl_up(inc, d, 64);
     if (lane >= d) inc += o;
   }
-  __syncthreads();  // wsum may still be read from a previous call
+  block_barrier<LDS_ONLY>();  // wsum may still be read from a previous call
   if (lane == 63) wsum[wid] = inc;
-  __syncthreads();
+  block_barrier<LDS_ONLY>();
   int ex = inc - v, tot = 0;
 #pragma unroll
   for (int w = 0; w < T / 64; ++w) {
@@ -70,12 +88,17 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int32_t *wsum, int *t
 
 // Block-wide maximum of nonnegative doubles (their bit patterns order like
 // the values).  Every thread of the block must call it.
+template <bool LDS_ONLY = false>
 __device__ __forceinline__ double block_max_nonneg(double v, unsigned long long *slot) {
-  __syncthreads();
+  // the wavefront's maximum first, so that one LDS atomic per wavefront
+  // (not per thread) meets the shared slot
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
+  block_barrier<LDS_ONLY>();
   if (threadIdx.x == 0) *slot = 0ull;
-  __syncthreads();
-  atomicMax(slot, (unsigned long long)__double_as_longlong(v));
-  __syncthreads();
+  block_barrier<LDS_ONLY>();
+  if ((threadIdx.x & 63) == 0) atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+  block_barrier<LDS_ONLY>();
   return __longlong_as_double((long long)*slot);
 }
 
@@ -100,6 +123,7 @@ template <int T>
 __device__ void finish_crystal(const MergeOut &mo, int64_t c, int64_t r0, int np, double mx, int32_t *wsum) {
   int kept = np;
   if (mo.thr > 0.0) {
+    __syncthreads();  // the staged peaks of every thread are written
     const double cut = mo.thr * mx;
     kept = 0;
     for (int p0 = 0; p0 < np; p0 += T) {
@@ -310,7 +334,7 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
       const int i = u * T + threadIdx.x;
       tv[u] = i < H ? tt[r0 + H + i] : P.tmin;
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
 #pragma clang fp contract(off)
@@ -319,7 +343,7 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
       bv[u] = x < 0.0 ? 0 : (x >= (double)(B - 1) ? B - 1 : (int)x);
       if (i < H) atomicAdd(&cnt[bv[u]], 1);
     }
-    __syncthreads();
+    lds_barrier();
     // exclusive scan of the bucket counts: each thread owns a contiguous run
     {
       constexpr int per = (CAP / 2 + T - 1) / T;
@@ -330,14 +354,14 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
         v[u] = b0 + u < B ? cnt[b0 + u] : 0;
         sum += v[u];
       }
-      int ex = block_exclusive_scan<T>(sum, wsum, &total);
+      int ex = block_exclusive_scan<T, true>(sum, wsum, &total);
 #pragma unroll
       for (int u = 0; u < per; ++u) {
         if (b0 + u < B) cnt[b0 + u] = ex;
         ex += v[u];
       }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = u * T + threadIdx.x;
@@ -347,7 +371,7 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
         pos[slot] = (uint16_t)i;
       }
     }
-    __syncthreads();
+    lds_barrier();
     // cnt[b] is now the end of bucket b, and its start is the end of bucket b - 1.
     // Order within buckets: every element counts the members of its bucket
     // that precede it in (2theta bits, index), all elements at once; then
@@ -369,7 +393,7 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
         rk[u] = r;
       }
     }
-    __syncthreads();
+    lds_barrier();
 #pragma unroll
     for (int u = 0; u < PER; ++u) {
       const int i = u * T + threadIdx.x;
@@ -378,7 +402,7 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
         pos[rk[u]] = (uint16_t)i;
       }
     }
-    __syncthreads();
+    lds_barrier();
     // entries (the evaluated half in 2theta order) and the expanded full order
     for (int j = threadIdx.x; j < H; j += T) {
       const uint64_t kj = key[j];
@@ -428,13 +452,13 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
       // each thread owns a contiguous run of PER entries
       const int i0 = threadIdx.x * PER;
       int ns = 0;
 #pragma unroll
       for (int u = 0; u < PER; ++u) ns += (i0 + u < H && fl[i0 + u]) ? 1 : 0;
-      int p = block_exclusive_scan<T>(ns, wsum, &total);
+      int p = block_exclusive_scan<T, true>(ns, wsum, &total);
       const int np = total;
       // the run's intensities (an entry and its mate), loaded at once; a peak
       // still open at the end of the run continues into the next runs
@@ -477,10 +501,10 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
         }
         emit();
       }
-      mx = block_max_nonneg(mx, &smax);
+      mx = block_max_nonneg<true>(mx, &smax);
       finish_crystal<T>(mo, c, r0, np, mx, wsum);
     }
-    __syncthreads();  // LDS is reused by the next crystal
+    lds_barrier();  // LDS is reused by the next crystal
   }
 }
 
@@ -577,11 +601,13 @@ void sort_kernels(const SortArgs &a, const MergeOut &mo, const Fork &f, hipStrea
                        0, s2, a.n_large, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count,
                        a.bin_start, mo);
   }
+  // the longest chains (the 1024-thread sizes) start on the caller's stream
+  // and the side stream that holds the largest crystals
   if (a.n_small > 0)
     hipLaunchKernelGGL((k_sort_crystal<kSmallSort, kSmallThreads, false, 2 * kTinySort>), dim3((unsigned)a.n_small),
-                       dim3(kSmallThreads), 0, s1, a.n_small, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek,
+                       dim3(kSmallThreads), 0, s, a.n_small, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek,
                        ei, a.bin_count, a.bin_start, mo);
-  hipLaunchKernelGGL((k_sort_crystal<kTinySort, 256, false, 0>), dim3((unsigned)a.n_c), dim3(256), 0, s, a.n_c,
+  hipLaunchKernelGGL((k_sort_crystal<kTinySort, 256, false, 0>), dim3((unsigned)a.n_c), dim3(256), 0, s1, a.n_c,
                      a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count, a.bin_start, mo);
   if (fork) {
     (void)hipEventRecord(f.join, f.side);
