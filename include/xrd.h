@@ -157,9 +157,11 @@ int xrd_batch_upload(xrd_batch *b, void *ws);
  * the physically accessible sphere): every integer (h, k, l) != 0 with
  * two_theta_min <= 2theta <= two_theta_max, with q, 2theta and LP, written
  * into ``r`` together with refl_offset.  Also packs the batch's atoms
- * (species-sorted copy) into the workspace: xrd_structure_factors and
- * xrd_pattern_backward read that copy, so the device atom arrays are read
- * here and changes made to them later take effect at the next call. */
+ * (species-sorted copy) and, for XRD_MIXED, a single-precision copy of
+ * sf_coeff into the workspace: xrd_structure_factors and
+ * xrd_pattern_backward read those copies, so the device atom arrays (and
+ * sf_coeff under XRD_MIXED) are read here and changes made to them later
+ * take effect at the next call. */
 int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r);
 
 /* Structure factors (paper, Section 2: sum of atomic contributions for each

@@ -348,23 +348,20 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
         for (int32_t k = 0; k < P.n_hchunks; ++k) b->bw_items.push_back(BwItem{(int32_t)c, (int32_t)a, k, 0});
     }
   }
-  // structure-factor tiles, heavy crystals first (a block per tile), each
-  // group listing the expected-filled tiles crystal by crystal (neighbouring
-  // waves share the crystal's atoms in cache), then the rest
+  // structure-factor tiles: the expected-filled tiles of the heavy crystals
+  // (a block per tile), then those of the light crystals, crystal by crystal
+  // (neighbouring waves share the crystal's atoms in cache), then every
+  // remaining tile, one wavefront each: these mostly find no reflection and
+  // end at once, and the few that do are complete on a single wavefront
   auto likely_tiles = [&](int64_t c) { return likely_units(c, kSfTile, b->plan[c].n_tiles); };
-  auto emit = [&](const std::vector<int64_t> &group) {
-    std::vector<int32_t> split(group.size());
-    for (size_t i = 0; i < group.size(); ++i) {
-      split[i] = likely_tiles(group[i]);
-      for (int32_t t = 0; t < split[i]; ++t) b->sf_items.push_back(SfItem{(int32_t)group[i], t});
-    }
-    for (size_t i = 0; i < group.size(); ++i)
-      for (int32_t t = split[i]; t < b->plan[group[i]].n_tiles; ++t)
-        b->sf_items.push_back(SfItem{(int32_t)group[i], t});
-  };
-  emit(heavy);
+  for (int64_t c : heavy)
+    for (int32_t t = 0; t < likely_tiles(c); ++t) b->sf_items.push_back(SfItem{(int32_t)c, t});
   b->sf_heavy = (int64_t)b->sf_items.size();
-  emit(light);
+  for (int64_t c : light)
+    for (int32_t t = 0; t < likely_tiles(c); ++t) b->sf_items.push_back(SfItem{(int32_t)c, t});
+  for (const auto *group : {&heavy, &light})
+    for (int64_t c : *group)
+      for (int32_t t = likely_tiles(c); t < b->plan[c].n_tiles; ++t) b->sf_items.push_back(SfItem{(int32_t)c, t});
   if ((int64_t)b->sf_items.size() >= ((int64_t)1 << 31) || (int64_t)b->bw_items.size() >= ((int64_t)1 << 31)) {
     delete b;
     return fail(XRD_ERR_CAPACITY, "launch tables exceed 2^31 entries");
@@ -423,6 +420,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.bw_partf = take(32 * pfused);
   L.bw_part6 = take(48 * tiles_total);
   L.sf_deriv = d->keep_sf_derivs ? take((d->precision == XRD_MIXED ? 16 : 32) * rc) : -1;
+  L.coeff_f = take((int64_t)sizeof(CoeffF) * d->n_species);
   L.total = o;
   *out = b;
   g_err.clear();
@@ -482,7 +480,8 @@ int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r) {
                    (int64_t)b->enum_chunk_crystal.size(), b->desc.wavelength, at<int32_t>(ws, L.enum_count),
                    at<int64_t>(ws, L.enum_prefix), at<int64_t>(ws, L.scan_part), r->h, r->k, r->l, r->q,
                    r->two_theta, r->lp, r->refl_offset, b->desc.n_species, b->desc.frac, b->desc.species,
-                   b->desc.occ, b->desc.bfac, at<AtomRec>(ws, L.atoms), at<int32_t>(ws, L.atom_orig),
+                   b->desc.occ, b->desc.bfac, b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f),
+                   at<AtomRec>(ws, L.atoms), at<int32_t>(ws, L.atom_orig),
                    at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), at<int32_t>(ws, L.err_flag),
                    stream_of(b));
   b->last_ws = ws;
@@ -499,8 +498,8 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
   void *deriv = L.sf_deriv >= 0 ? at<char>(ws, L.sf_deriv) : nullptr;
   launch_sf(b->desc.precision == XRD_MIXED, b->desc.friedel != 0, at<SfItem>(ws, L.sf_items),
             (int64_t)b->sf_items.size(), b->sf_heavy, at<CrystalPlan>(ws, L.plan), r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
-            at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), b->desc.sf_coeff, A, B,
-            I, deriv, stream_of(b));
+            at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), b->desc.sf_coeff,
+            at<CoeffF>(ws, L.coeff_f), A, B, I, deriv, stream_of(b));
   b->deriv_ws = deriv ? ws : nullptr;
   b->deriv_h = deriv ? r->h : nullptr;
   b->last_ws = ws;
@@ -669,10 +668,11 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
                      g->n_points, g->sigma, g->window_sigmas, w1, w2, s);
   launch_sf_bw(mixed, friedel, items, n_items, b->sf_heavy, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
                b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
-               b->desc.sf_coeff, deriv, w1, w2, ga, gb, dq, at<double>(ws, L.bw_part6), at<double>(ws, L.bw_partf), s);
+               b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), deriv, w1, w2, ga, gb, dq, at<double>(ws, L.bw_part6),
+               at<double>(ws, L.bw_partf), s);
   launch_atom_bw(mixed, friedel, at<BwItem>(ws, L.bw_items), (int64_t)b->bw_items.size(), plan, r->refl_offset,
                  r->h, r->k, r->l, r->q, ga, gb, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
-                 at<int32_t>(ws, L.run_count), b->desc.sf_coeff, b->bw_tile, b->runs_cap_max,
+                 at<int32_t>(ws, L.run_count), b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), b->bw_tile, b->runs_cap_max,
                  at<double>(ws, L.bw_part), s);
   launch_bw_finish(at<AbItem>(ws, L.ab_items), (int64_t)b->ab_items.size(), friedel, plan, b->desc.n_crystals,
                    r->refl_offset, at<double>(ws, L.bw_part), at<double>(ws, L.bw_partf), at<int32_t>(ws, L.atom_orig),

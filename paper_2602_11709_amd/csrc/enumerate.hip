@@ -145,7 +145,8 @@ __device__ __forceinline__ double lp_of_q(double q, double lambda) {
 // histogram in LDS, ascending-species runs, then a stable scatter (peeling one
 // species per step with a ballot).  The wavefront works alone: it orders its
 // LDS accesses with wavefront-scope fences, so several crystals can share a
-// block.
+// block.  The wavefront of crystal 0 also writes the single-precision
+// coefficient table of the mixed path.
 
 constexpr float kLog2e = 1.4426950408889634f;
 
@@ -158,9 +159,26 @@ __device__ __forceinline__ void wave_sync() {
 __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan *__restrict__ plan,
                              int32_t n_species, const double *__restrict__ frac,
                              const int32_t *__restrict__ species, const double *__restrict__ occ,
-                             const double *__restrict__ bfac, AtomRec *__restrict__ atoms,
+                             const double *__restrict__ bfac, const double *__restrict__ coeff,
+                             CoeffF *__restrict__ coeff_f, AtomRec *__restrict__ atoms,
                              int32_t *__restrict__ orig, SpeciesRun *__restrict__ runs,
                              int32_t *__restrict__ run_count, int32_t *__restrict__ err) {
+  if (c == 0) {
+    // the single-precision coefficient table of the mixed path (one
+    // rounding from double of each stored product)
+    for (int t = lane; t < n_species; t += 64) {
+      const double *c9 = coeff + 9 * t;
+      CoeffF cf{};
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        cf.a[i] = (float)c9[i];
+        cf.nbl[i] = (float)(-c9[4 + i] * 1.4426950408889634);
+        cf.nab[i] = (float)(-c9[i] * c9[4 + i]);
+      }
+      cf.c = (float)c9[8];
+      coeff_f[t] = cf;
+    }
+  }
   const CrystalPlan &P = plan[c];
   const int64_t a0 = P.atom_begin, a1 = P.atom_end;
   for (int t = lane; t < n_species; t += 64) cursor[t] = 0;
@@ -249,6 +267,8 @@ struct PackArgs {
   const int32_t *species;
   const double *occ;
   const double *bfac;
+  const double *coeff;
+  CoeffF *coeff_f;
   AtomRec *atoms;
   int32_t *orig;
   SpeciesRun *runs;
@@ -259,8 +279,8 @@ struct PackArgs {
 // Atom packing alone, one wavefront per crystal.
 __global__ __launch_bounds__(64) void k_atom_pack(const CrystalPlan *__restrict__ plan, int64_t n_c, PackArgs a) {
   extern __shared__ int32_t cursor[];  // n_species
-  pack_crystal(blockIdx.x, threadIdx.x, cursor, plan, a.n_species, a.frac, a.species, a.occ, a.bfac, a.atoms,
-               a.orig, a.runs, a.run_count, a.err);
+  pack_crystal(blockIdx.x, threadIdx.x, cursor, plan, a.n_species, a.frac, a.species, a.occ, a.bfac, a.coeff,
+               a.coeff_f, a.atoms, a.orig, a.runs, a.run_count, a.err);
 }
 
 // Survivor count per enumeration chunk of kEnumRows rows, one wavefront per
@@ -279,7 +299,7 @@ __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__re
     const int64_t c = (int64_t)(blockIdx.x - chunk_blocks) * (kThreads / 64) + wid;
     if (c < n_c)
       pack_crystal((int)c, lane, cursors + wid * pa.n_species, plan, pa.n_species, pa.frac, pa.species, pa.occ,
-                   pa.bfac, pa.atoms, pa.orig, pa.runs, pa.run_count, pa.err);
+                   pa.bfac, pa.coeff, pa.coeff_f, pa.atoms, pa.orig, pa.runs, pa.run_count, pa.err);
     return;
   }
   const int64_t chunk = (int64_t)blockIdx.x * (kThreads / 64) + wid;
@@ -463,9 +483,9 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk
                       double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h,
                       int16_t *k, int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset,
                       int32_t n_species, const double *frac, const int32_t *species, const double *occ,
-                      const double *bfac, AtomRec *atoms, int32_t *orig, SpeciesRun *runs, int32_t *run_count,
-                      int32_t *err, hipStream_t s) {
-  const PackArgs pa{n_species, frac, species, occ, bfac, atoms, orig, runs, run_count, err};
+                      const double *bfac, const double *coeff, CoeffF *coeff_f, AtomRec *atoms, int32_t *orig,
+                      SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s) {
+  const PackArgs pa{n_species, frac, species, occ, bfac, coeff, coeff_f, atoms, orig, runs, run_count, err};
   // the packing rides along in the count launch while its cursors stay small
   const size_t fused_lds = (size_t)(kThreads / 64) * n_species * sizeof(int32_t);
   const bool fuse = n_chunks > 0 && fused_lds <= kFusedPackLds;

@@ -40,7 +40,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kAtomTile = 64;  // atoms per single-precision partial sum
-constexpr float kLog2e = 1.4426950408889634f;
+constexpr double kLn2 = 0.69314718055994530942;
 
 // ---- structure factors -----------------------------------------------------
 
@@ -107,11 +107,12 @@ __device__ __forceinline__ float wave_reduce16(const float (&v)[16], int lane) {
   return w;
 }
 
-// Cromer-Mann factor at s^2 in single precision via exp2.
-__device__ __forceinline__ float fsc_f32(const double *__restrict__ c9, float s2) {
-  float f = (float)c9[8];
+// Cromer-Mann factor at s^2 in single precision via exp2, from the
+// species' single-precision table.
+__device__ __forceinline__ float fsc_f32(const CoeffF &cf, float s2) {
+  float f = cf.c;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) f = fmaf((float)c9[i], __builtin_amdgcn_exp2f(-(float)c9[4 + i] * kLog2e * s2), f);
+  for (int i = 0; i < 4; ++i) f = fmaf(cf.a[i], __builtin_amdgcn_exp2f(cf.nbl[i] * s2), f);
   return f;
 }
 
@@ -158,15 +159,15 @@ __device__ __forceinline__ void part_range(const CrystalPlan &P, const WaveWork 
   *wb = (int)P.atom_begin + min(na, (w.part + 1) * q);
 }
 
-// d f / d(s^2) alongside f (single and double precision).
-__device__ __forceinline__ void fsc_df_f32(const double *__restrict__ c9, float s2, float *f, float *df) {
-  float a = (float)c9[8], d = 0.f;
+// d f / d(s^2) alongside f (single and double precision); f takes the same
+// operations as fsc_f32.
+__device__ __forceinline__ void fsc_df_f32(const CoeffF &cf, float s2, float *f, float *df) {
+  float a = cf.c, d = 0.f;
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    const float ai = (float)c9[i], bi = (float)c9[4 + i];
-    const float e = __builtin_amdgcn_exp2f(-bi * kLog2e * s2);
-    a = fmaf(ai, e, a);
-    d = fmaf(-ai * bi, e, d);
+    const float e = __builtin_amdgcn_exp2f(cf.nbl[i] * s2);
+    a = fmaf(cf.a[i], e, a);
+    d = fmaf(cf.nab[i], e, d);
   }
   *f = a;
   *df = d;
@@ -197,7 +198,8 @@ __device__ __forceinline__ void fsc_df_f64(const double *__restrict__ c9, double
 template <bool MIXED, bool DERIV>
 __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const SpeciesRun *__restrict__ cr, int nr,
                                              int wa, int wb, const AtomRec *__restrict__ atoms,
-                                             const double *__restrict__ coeff, const double (&h)[kSfRpt],
+                                             const double *__restrict__ coeff,
+                                             const CoeffF *__restrict__ coeff_f, const double (&h)[kSfRpt],
                                              const double (&k)[kSfRpt], const double (&l)[kSfRpt],
                                              const double (&s2d)[kSfRpt], const float (&s2)[kSfRpt],
                                              double *s_part, bool all_waves, double (&A)[kSfRpt],
@@ -206,7 +208,9 @@ __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const
   if constexpr (MIXED) {
     // per reflection: A, B and, with DERIV, dA, dB in double; each chunk of
     // up to kAtomTile atoms of a run is summed in single precision and added
-    // in double (the products of two singles are exact there)
+    // in double (the products of two singles are exact there).  The chunk
+    // sums for dF/ds^2 carry B log2(e) w in place of -B w (no per-atom
+    // conversion of B); the factor -ln 2 joins f when they are added.
     constexpr int V = DERIV ? 4 : 2;
     double acc[V][R];
 #pragma unroll
@@ -217,17 +221,18 @@ __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const
       const SpeciesRun run = cr[ir];
       const int rb = max(run.begin, wa), re = min(run.end, wb);
       if (rb >= re) continue;
-      const double *c9 = coeff + 9 * run.species;
-      double f[R], df[R];
+      const CoeffF cf = coeff_f[run.species];
+      double f[R], df[R], fq[R];
 #pragma unroll
       for (int u = 0; u < R; ++u) {
         float ff, dd = 0.f;
         if constexpr (DERIV)
-          fsc_df_f32(c9, s2[u], &ff, &dd);
+          fsc_df_f32(cf, s2[u], &ff, &dd);
         else
-          ff = fsc_f32(c9, s2[u]);
+          ff = fsc_f32(cf, s2[u]);
         f[u] = ff;
         df[u] = dd;
+        fq[u] = -kLn2 * f[u];
       }
       for (int j0 = rb; j0 < re; j0 += kAtomTile) {
         const int j1 = min(j0 + kAtomTile, re);
@@ -245,9 +250,9 @@ __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const
             pa[u] = fmaf(w, cs, pa[u]);
             pb[u] = fmaf(w, sn, pb[u]);
             if constexpr (DERIV) {
-              const float nbw = -(float)a.bfac * w;
-              qa[u] = fmaf(nbw, cs, qa[u]);
-              qb[u] = fmaf(nbw, sn, qb[u]);
+              const float bw = a.bl2e * w;
+              qa[u] = fmaf(bw, cs, qa[u]);
+              qb[u] = fmaf(bw, sn, qb[u]);
             }
           }
         };
@@ -266,8 +271,8 @@ __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const
           acc[0][u] = fma(f[u], (double)pa[u], acc[0][u]);
           acc[1][u] = fma(f[u], (double)pb[u], acc[1][u]);
           if constexpr (DERIV) {
-            acc[2][u] = fma(df[u], (double)pa[u], fma(f[u], (double)qa[u], acc[2][u]));
-            acc[3][u] = fma(df[u], (double)pb[u], fma(f[u], (double)qb[u], acc[3][u]));
+            acc[2][u] = fma(df[u], (double)pa[u], fma(fq[u], (double)qa[u], acc[2][u]));
+            acc[3][u] = fma(df[u], (double)pb[u], fma(fq[u], (double)qb[u], acc[3][u]));
           }
         }
       }
@@ -415,7 +420,8 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
                                                  const double *__restrict__ lpp, const AtomRec *__restrict__ atoms,
                                                  const SpeciesRun *__restrict__ runs,
                                                  const int32_t *__restrict__ run_count,
-                                                 const double *__restrict__ coeff, void *__restrict__ Aout,
+                                                 const double *__restrict__ coeff,
+                                                 const CoeffF *__restrict__ coeff_f, void *__restrict__ Aout,
                                                  void *__restrict__ Bout, double *__restrict__ Iout,
                                                  void *__restrict__ cache) {
   constexpr int R = kSfRpt;
@@ -451,8 +457,8 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
   int wa, wb;
   part_range(P, ww, &wa, &wb);
   double A[R], B[R], dA[R], dB[R];
-  if (!sf_tile_sums<MIXED, DERIV>(ww, lane, runs + P.run_begin, run_count[it.crystal], wa, wb, atoms, coeff, h, k, l,
-                                  s2d, s2, s_part, false, A, B, dA, dB))
+  if (!sf_tile_sums<MIXED, DERIV>(ww, lane, runs + P.run_begin, run_count[it.crystal], wa, wb, atoms, coeff, coeff_f,
+                                  h, k, l, s2d, s2, s_part, false, A, B, dA, dB))
     return;
 #pragma unroll
   for (int u = 0; u < R; ++u) {
@@ -505,7 +511,8 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
                                                     const AtomRec *__restrict__ atoms,
                                                     const SpeciesRun *__restrict__ runs,
                                                     const int32_t *__restrict__ run_count,
-                                                    const double *__restrict__ coeff, const void *__restrict__ cache,
+                                                    const double *__restrict__ coeff,
+                                                    const CoeffF *__restrict__ coeff_f, const void *__restrict__ cache,
                                                     const double *__restrict__ w1,
                                                     const double *__restrict__ w2, double *__restrict__ ga,
                                                     double *__restrict__ gb, double *__restrict__ dq,
@@ -549,7 +556,8 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
 #pragma unroll
     for (int u = 0; u < R; ++u) load_derivs<MIXED>(cache, idx[u], &A[u], &B[u], &dA[u], &dB[u]);
   } else {
-    sf_tile_sums<MIXED, true>(ww, lane, cr, nr, wa, wb, atoms, coeff, h, k, l, s2d, s2, s_part, true, A, B, dA, dB);
+    sf_tile_sums<MIXED, true>(ww, lane, cr, nr, wa, wb, atoms, coeff, coeff_f, h, k, l, s2d, s2, s_part, true, A, B,
+                              dA, dB);
   }
   const double m = friedel ? 2.0 : 1.0;
   const double l2 = lambda * lambda;
@@ -616,10 +624,11 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
     if (max(run.begin, wa) >= min(run.end, wb)) continue;
     const double *c9 = coeff + 9 * run.species;
     if constexpr (MIXED) {
+      const CoeffF cf = coeff_f[run.species];
       float f[R], fA[R], fB[R], hf[R], kf[R], lf[R];
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        f[u] = fsc_f32(c9, s2[u]);
+        f[u] = fsc_f32(cf, s2[u]);
         fA[u] = (float)gA[u] * f[u];
         fB[u] = (float)gB[u] * f[u];
         hf[u] = (float)h[u];
@@ -719,7 +728,8 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
                                                       const AtomRec *__restrict__ atoms,
                                                       const SpeciesRun *__restrict__ runs,
                                                       const int32_t *__restrict__ run_count,
-                                                      const double *__restrict__ coeff, int tile, int runs_cap,
+                                                      const double *__restrict__ coeff,
+                                                      const CoeffF *__restrict__ coeff_f, int tile, int runs_cap,
                                                       double4 *__restrict__ part) {
   using real = typename std::conditional<MIXED, float, double>::type;
   extern __shared__ __align__(16) unsigned char smem[];
@@ -730,7 +740,9 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
   real *tga = ts2 + tile;
   real *tgb = tga + tile;
   real *tf = tgb + tile;           // [tile][runs_cap]
-  real *tcoef = tf + tile * runs_cap;  // [runs_cap][9]: the crystal's species coefficients
+  // [runs_cap][9]: the crystal's species coefficients, (a_i, b_i, c) in
+  // double, (a_i, -b_i log2(e), c) from the single-precision table
+  real *tcoef = tf + tile * runs_cap;
 
   const BwItem it = items[blockIdx.x];
   const CrystalPlan &P = plan[it.crystal];
@@ -760,7 +772,12 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
     if (j >= cr[ir].begin && j < cr[ir].end) myrun = ir;
   for (int x = threadIdx.x; x < nr * 9; x += kThreads) {
     const int ir = x / 9, q9 = x - ir * 9;
-    tcoef[ir * 9 + q9] = (real)coeff[9 * cr[ir].species + q9];
+    if constexpr (MIXED) {
+      const CoeffF &cf = coeff_f[cr[ir].species];
+      tcoef[ir * 9 + q9] = q9 < 4 ? cf.a[q9] : q9 < 8 ? cf.nbl[q9 - 4] : cf.c;
+    } else {
+      tcoef[ir * 9 + q9] = coeff[9 * cr[ir].species + q9];
+    }
   }
   const AtomRec a = atoms[j];
   double sx = 0.0, sy = 0.0, sz = 0.0, sB = 0.0;
@@ -788,7 +805,7 @@ __global__ __launch_bounds__(kThreads) void k_atom_bw(const BwItem *__restrict__
       real f = c9[8];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        if constexpr (MIXED) f = fmaf(c9[i], __builtin_amdgcn_exp2f(-c9[4 + i] * kLog2e * ts2[r]), f);
+        if constexpr (MIXED) f = fmaf(c9[i], __builtin_amdgcn_exp2f(c9[4 + i] * ts2[r]), f);
         else f = fma(c9[i], exp(-c9[4 + i] * ts2[r]), f);
       }
       tf[r * runs_cap + ir] = f;
@@ -985,21 +1002,22 @@ template <bool MIXED, bool FRIEDEL, bool DERIV>
 static void launch_sf_t(dim3 grid, const SfItem *items, int64_t n_items, int64_t n_heavy, const CrystalPlan *plan,
                         const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
                         const double *q, const double *lp, const AtomRec *atoms, const SpeciesRun *runs,
-                        const int32_t *run_count, const double *coeff, void *A, void *B, double *I, void *cache,
-                        hipStream_t s) {
+                        const int32_t *run_count, const double *coeff, const CoeffF *coeff_f, void *A, void *B,
+                        double *I, void *cache, hipStream_t s) {
   hipLaunchKernelGGL((k_sf<MIXED, FRIEDEL, DERIV>), grid, dim3(kThreads), 0, s, items, n_items, n_heavy, plan,
-                     refl_offset, h, k, l, q, lp, atoms, runs, run_count, coeff, A, B, I, cache);
+                     refl_offset, h, k, l, q, lp, atoms, runs, run_count, coeff, coeff_f, A, B, I, cache);
 }
 
 void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, int64_t n_heavy, const CrystalPlan *plan,
                const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
-               const double *coeff, void *A, void *B, double *I, void *deriv_cache, hipStream_t s) {
+               const double *coeff, const CoeffF *coeff_f, void *A, void *B, double *I, void *deriv_cache,
+               hipStream_t s) {
   if (n_items <= 0) return;
   const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4));
   auto go = [&](auto fn) {
-    fn(grid, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp, atoms, runs, run_count, coeff, A, B, I,
-       deriv_cache, s);
+    fn(grid, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp, atoms, runs, run_count, coeff, coeff_f, A, B,
+       I, deriv_cache, s);
   };
   const bool d = deriv_cache != nullptr;
   if (mixed) {
@@ -1023,15 +1041,16 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
                   const CrystalPlan *plan,
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
-                  const int32_t *run_count, const double *coeff, const void *deriv_cache, const double *w1,
-                  const double *w2, double *ga, double *gb, double *dq, double *part6, double *part_fused,
-                  hipStream_t s) {
+                  const int32_t *run_count, const double *coeff, const CoeffF *coeff_f, const void *deriv_cache,
+                  const double *w1, const double *w2, double *ga, double *gb, double *dq, double *part6,
+                  double *part_fused, hipStream_t s) {
   if (n_items <= 0) return;
   const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4)), block(kThreads);
   double4 *pf = (double4 *)part_fused;
 #define XRD_SF_BW(M, C)                                                                                          \
   hipLaunchKernelGGL((k_sf_bw<M, C>), grid, block, 0, s, items, n_items, n_heavy, friedel, plan, refl_offset, h, k, \
-                     l, q, lp, lambda, atoms, runs, run_count, coeff, deriv_cache, w1, w2, ga, gb, dq, part6, pf)
+                     l, q, lp, lambda, atoms, runs, run_count, coeff, coeff_f, deriv_cache, w1, w2, ga, gb, dq,  \
+                     part6, pf)
   if (mixed) {
     if (deriv_cache)
       XRD_SF_BW(true, true);
@@ -1057,18 +1076,18 @@ size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap) {
 void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,
                     const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
                     const double *q, const double *ga, const double *gb, const AtomRec *atoms,
-                    const SpeciesRun *runs, const int32_t *run_count, const double *coeff, int tile, int runs_cap,
-                    double *part, hipStream_t s) {
+                    const SpeciesRun *runs, const int32_t *run_count, const double *coeff, const CoeffF *coeff_f,
+                    int tile, int runs_cap, double *part, hipStream_t s) {
   if (n_items <= 0) return;
   const size_t lds = atom_bw_lds_bytes(mixed, tile, runs_cap);
   const BwItem *it = items;
   if (mixed)
     hipLaunchKernelGGL(k_atom_bw<true>, dim3((unsigned)n_items), dim3(kThreads), lds, s, it, friedel, plan,
-                       refl_offset, h, k, l, q, ga, gb, atoms, runs, run_count, coeff, tile, runs_cap,
+                       refl_offset, h, k, l, q, ga, gb, atoms, runs, run_count, coeff, coeff_f, tile, runs_cap,
                        (double4 *)part);
   else
     hipLaunchKernelGGL(k_atom_bw<false>, dim3((unsigned)n_items), dim3(kThreads), lds, s, it, friedel, plan,
-                       refl_offset, h, k, l, q, ga, gb, atoms, runs, run_count, coeff, tile, runs_cap,
+                       refl_offset, h, k, l, q, ga, gb, atoms, runs, run_count, coeff, coeff_f, tile, runs_cap,
                        (double4 *)part);
 }
 

@@ -64,6 +64,16 @@ struct alignas(16) AtomRec {
 };
 static_assert(sizeof(AtomRec) == 48, "AtomRec layout");
 
+// Cromer-Mann coefficients of one species in single precision, in the form
+// the mixed-precision kernels evaluate them (64 bytes, one scalar load):
+//   f(s^2) = c + sum_i a_i 2^(nbl_i s^2),  df/ds^2 = sum_i nab_i 2^(nbl_i s^2),
+// with nbl_i = -b_i log2(e) and nab_i = -a_i b_i rounded once from double.
+struct alignas(16) CoeffF {
+  float a[4], nbl[4], nab[4];
+  float c, pad[3];
+};
+static_assert(sizeof(CoeffF) == 64, "CoeffF layout");
+
 // A run of same-species atoms: [begin, end) in the packed array.
 struct alignas(16) SpeciesRun {
   int32_t begin, end, species, local;  // local = run index within the crystal
@@ -93,6 +103,7 @@ struct WsLayout {
   int64_t scan_part;
   int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6, bw_partf;
   int64_t sf_deriv;  // kept (A, B, dA/ds^2, dB/ds^2) per reflection, or -1
+  int64_t coeff_f;   // [n_species] CoeffF
   int64_t total;
 };
 
@@ -123,8 +134,8 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk
                       double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h, int16_t *k,
                       int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset, int32_t n_species,
                       const double *frac, const int32_t *species, const double *occ, const double *bfac,
-                      AtomRec *atoms, int32_t *orig, SpeciesRun *runs, int32_t *run_count, int32_t *err,
-                      hipStream_t s);
+                      const double *coeff, CoeffF *coeff_f, AtomRec *atoms, int32_t *orig, SpeciesRun *runs,
+                      int32_t *run_count, int32_t *err, hipStream_t s);
 // Items: the first n_heavy take a block each (atoms split over its four
 // wavefronts), the rest one wavefront each.  A non-null deriv_cache
 // ([refl_cap] float4 under mixed precision, else double4) receives
@@ -132,7 +143,8 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk
 void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, int64_t n_heavy, const CrystalPlan *plan,
                const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
-               const double *coeff, void *A, void *B, double *I, void *deriv_cache, hipStream_t s);
+               const double *coeff, const CoeffF *coeff_f, void *A, void *B, double *I, void *deriv_cache,
+               hipStream_t s);
 
 struct SortArgs {
   int64_t n_c;
@@ -206,15 +218,16 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
                   const CrystalPlan *plan,
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
-                  const int32_t *run_count, const double *coeff, const void *deriv_cache, const double *w1,
+                  const int32_t *run_count, const double *coeff, const CoeffF *coeff_f, const void *deriv_cache,
+                  const double *w1,
                   const double *w2, double *ga, double *gb, double *dq, double *part6, double *part_fused,
                   hipStream_t s);
 size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap);
 void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,
                     const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
                     const double *q, const double *ga, const double *gb, const AtomRec *atoms,
-                    const SpeciesRun *runs, const int32_t *run_count, const double *coeff, int tile, int runs_cap,
-                    double *part, hipStream_t s);
+                    const SpeciesRun *runs, const int32_t *run_count, const double *coeff, const CoeffF *coeff_f,
+                    int tile, int runs_cap, double *part, hipStream_t s);
 // Atom gradients reduced over their partial rows and scattered to the
 // caller's order, and, in the same launch, dL/d(lattice) of every crystal
 // from its per-tile dL/dG* rows (written by launch_sf_bw).
