@@ -29,7 +29,7 @@ struct xrd_batch {
   std::vector<CrystalPlan> plan;
   std::vector<int32_t> enum_chunk_crystal;
   std::vector<HChunk> peak_chunks;  // peak chunks of the merge (crystal, chunk)
-  std::vector<HChunk> hchunks;  // entry chunks of the broadening (crystal, chunk)
+  std::vector<HChunk> eblocks;  // entry blocks of the broadening (crystal, block of kEntBlock entries)
   std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
   std::vector<SfItem> sf_items;
   std::vector<BwItem> bw_items;
@@ -319,15 +319,19 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     for (int64_t c = 0; c < nc; ++c)
       for (int32_t i = split[c]; i < b->plan[c].sort_chunks; ++i) b->peak_chunks.push_back(HChunk{(int32_t)c, i});
   }
-  // entry chunks, heaviest crystals first, expected-filled chunks before the rest
+  // entry blocks, heaviest crystals first, the expected-filled blocks of
+  // every crystal before all the rest (which mostly end at once), so that
+  // the blocks with work are the first to find a workgroup slot
   {
-    std::vector<int32_t> split(nc);
+    std::vector<int32_t> split(nc), n_eb(nc);
     for (int32_t c : b->crystal_order) {
-      split[c] = likely_units(c, kHalfChunk, b->plan[c].n_hchunks);
-      for (int32_t i = 0; i < split[c]; ++i) b->hchunks.push_back(HChunk{c, i});
+      const CrystalPlan &P = b->plan[c];
+      n_eb[c] = (int32_t)std::max<int64_t>(1, ceil_div(friedel ? P.half_box : 2 * P.half_box, kEntBlock));
+      split[c] = likely_units(c, kEntBlock, n_eb[c]);
+      for (int32_t i = 0; i < split[c]; ++i) b->eblocks.push_back(HChunk{c, i});
     }
     for (int32_t c : b->crystal_order)
-      for (int32_t i = split[c]; i < b->plan[c].n_hchunks; ++i) b->hchunks.push_back(HChunk{c, i});
+      for (int32_t i = split[c]; i < n_eb[c]; ++i) b->eblocks.push_back(HChunk{c, i});
   }
   // structure-factor items: crystals in descending atom count (the cost of
   // one item), so the heaviest work is dispatched first
@@ -380,7 +384,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.enum_chunk_crystal = take(4 * ec);
   L.sf_items = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items.size());
   L.peak_chunks = take((int64_t)sizeof(HChunk) * sc);
-  L.hchunks = take((int64_t)sizeof(HChunk) * hc);
+  L.eblocks = take((int64_t)sizeof(HChunk) * (int64_t)b->eblocks.size());
   L.crystal_order = take(4 * nc);
   L.bw_items = take((int64_t)sizeof(BwItem) * (int64_t)b->bw_items.size());
   L.ab_items = take((int64_t)sizeof(AbItem) * (int64_t)b->ab_items.size());
@@ -452,7 +456,7 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   if (e == hipSuccess) e = up(L.enum_chunk_crystal, b->enum_chunk_crystal.data(), 4 * b->enum_chunk_crystal.size());
   if (e == hipSuccess) e = up(L.sf_items, b->sf_items.data(), sizeof(SfItem) * b->sf_items.size());
   if (e == hipSuccess) e = up(L.peak_chunks, b->peak_chunks.data(), sizeof(HChunk) * b->peak_chunks.size());
-  if (e == hipSuccess) e = up(L.hchunks, b->hchunks.data(), sizeof(HChunk) * b->hchunks.size());
+  if (e == hipSuccess) e = up(L.eblocks, b->eblocks.data(), sizeof(HChunk) * b->eblocks.size());
   if (e == hipSuccess) e = up(L.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
   if (e == hipSuccess) e = up(L.bw_items, b->bw_items.data(), sizeof(BwItem) * b->bw_items.size());
   if (e == hipSuccess) e = up(L.ab_items, b->ab_items.data(), sizeof(AbItem) * b->ab_items.size());
@@ -635,8 +639,8 @@ int xrd_pattern_forward(xrd_batch *b, void *ws, const xrd_refl *r, const double 
     return fail(XRD_ERR_INVALID_ARG, "n_points exceeds the batch's grid_capacity (" + std::to_string(b->grid_cap) + ")");
   ensure_sorted(b, ws, r);
   const WsLayout &L = b->ws;
-  launch_broaden_fwd(b->desc.precision == XRD_MIXED, at<HChunk>(ws, L.hchunks),
-                     (int64_t)b->hchunks.size(), at<CrystalPlan>(ws, L.plan),
+  launch_broaden_fwd(b->desc.precision == XRD_MIXED, at<HChunk>(ws, L.eblocks),
+                     (int64_t)b->eblocks.size(), at<CrystalPlan>(ws, L.plan),
                      at<int32_t>(ws, L.crystal_order), b->desc.n_crystals,
                      b->desc.friedel != 0, r->refl_offset, at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), I,
                      g->t0, g->dt, g->n_points, g->sigma, g->window_sigmas, b->span_cap, at<double>(ws, L.ent_w),
@@ -663,7 +667,7 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   double *ga = at<double>(ws, L.bw_ga), *gb = at<double>(ws, L.bw_gb), *dq = at<double>(ws, L.bw_dq);
   ensure_sorted(b, ws, r);
   const void *deriv = (L.sf_deriv >= 0 && b->deriv_ws == ws && b->deriv_h == r->h) ? at<char>(ws, L.sf_deriv) : nullptr;
-  launch_broaden_adj(mixed, at<HChunk>(ws, L.hchunks), (int64_t)b->hchunks.size(), plan, friedel,
+  launch_broaden_adj(mixed, at<HChunk>(ws, L.eblocks), (int64_t)b->eblocks.size(), plan, friedel,
                      r->refl_offset, at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), dL_dy, g->t0, g->dt,
                      g->n_points, g->sigma, g->window_sigmas, w1, w2, s);
   launch_sf_bw(mixed, friedel, items, n_items, b->sf_heavy, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,

@@ -54,8 +54,6 @@ __device__ __forceinline__ void window_of(const GridArgs &g, double t, int64_t *
   *hi = (int64_t)fmin(b, n - 1.0);
 }
 
-constexpr int kEntBlock = 1024;                // entries per block of the preparation and the adjoint
-constexpr int kEntSplit = kHalfChunk / kEntBlock;  // such blocks per chunk of kHalfChunk entries
 constexpr int kSegPts = 1024;                  // grid points per gather block (4 per thread)
 constexpr int kGTile = 1024;                   // entries per LDS tile of the gather
 constexpr int kAdjSpan = 4096;                 // grid points of dL/dy an adjoint block stages in LDS
@@ -104,7 +102,7 @@ __device__ __forceinline__ int2 window_wide(const GridArgs &g, double t) {
 // (integer floors), the first and last entries also own the spans beyond;
 // every span of a crystal with entries is written exactly once.
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_entry_prep(const HChunk *__restrict__ hchunks,
+__global__ __launch_bounds__(256) void k_entry_prep(const HChunk *__restrict__ eblocks,
                                                     const CrystalPlan *__restrict__ plan, bool friedel,
                                                     const int64_t *__restrict__ refl_offset,
                                                     const double *__restrict__ ent_key,
@@ -114,11 +112,10 @@ __global__ __launch_bounds__(256) void k_entry_prep(const HChunk *__restrict__ h
                                                     int32_t *__restrict__ span_last) {
 #pragma clang fp contract(off)
   __shared__ int32_t s_gl[kEntBlock + 2], s_gh[kEntBlock + 2];
-  const int hc = blockIdx.x / kEntSplit, sub = blockIdx.x % kEntSplit;
-  const HChunk hk = hchunks[hc];
+  const HChunk hk = eblocks[blockIdx.x];
   const int32_t c = hk.crystal;
   const EntryRange er = entry_range(refl_offset, c, friedel);
-  const int64_t e0 = (int64_t)hk.chunk * kHalfChunk + (int64_t)sub * kEntBlock;
+  const int64_t e0 = (int64_t)hk.chunk * kEntBlock;
   if (e0 >= er.count) return;
   const int64_t e1 = min(e0 + (int64_t)kEntBlock, er.count);
   const int S = (int)((g.n + kSpanPts - 1) / kSpanPts);
@@ -326,7 +323,7 @@ __device__ __forceinline__ void adj_walk(const src_t *__restrict__ src, int off,
 }
 
 template <bool MIXED>
-__global__ __launch_bounds__(256) void k_broaden_adj(const HChunk *__restrict__ hchunks,
+__global__ __launch_bounds__(256) void k_broaden_adj(const HChunk *__restrict__ eblocks,
                                                      const CrystalPlan *__restrict__ plan, bool friedel,
                                                      const int64_t *__restrict__ refl_offset,
                                                      const double *__restrict__ ent_key,
@@ -338,11 +335,10 @@ __global__ __launch_bounds__(256) void k_broaden_adj(const HChunk *__restrict__ 
   __shared__ real s_dy[kAdjSpan];
   __shared__ int32_t s_span[2];
   constexpr int U = kEntBlock / 256;
-  const int hc = blockIdx.x / kEntSplit, sub = blockIdx.x % kEntSplit;
-  const HChunk hk = hchunks[hc];
+  const HChunk hk = eblocks[blockIdx.x];
   const int32_t c = hk.crystal;
   const EntryRange er = entry_range(refl_offset, c, friedel);
-  const int64_t e0 = (int64_t)hk.chunk * kHalfChunk + (int64_t)sub * kEntBlock;
+  const int64_t e0 = (int64_t)hk.chunk * kEntBlock;
   if (e0 >= er.count) return;
   const int ne = (int)min((int64_t)kEntBlock, er.count - e0);
   double t[U];
@@ -407,21 +403,21 @@ GridArgs make_grid(double t0, double dt, int64_t n, double sigma, double window)
 
 }  // namespace
 
-void launch_broaden_fwd(bool mixed, const HChunk *hchunks, int64_t n_hchunks, const CrystalPlan *plan,
+void launch_broaden_fwd(bool mixed, const HChunk *eblocks, int64_t n_eblocks, const CrystalPlan *plan,
                         const int32_t *crystal_order, int64_t n_c, bool friedel, const int64_t *refl_offset, const double *ent_key,
                         const int32_t *ent_idx, const double *inten, double t0, double dt, int64_t n, double sigma,
                         double window, int64_t span_cap, double *ent_w, int32_t *span_first, int32_t *span_last,
                         double *y, hipStream_t s) {
   if (n_c <= 0 || n <= 0) return;
   const GridArgs g = make_grid(t0, dt, n, sigma, window);
-  if (n_hchunks > 0) {
+  if (n_eblocks > 0) {
     if (mixed)
-      hipLaunchKernelGGL(k_entry_prep<true>, dim3((unsigned)(n_hchunks * kEntSplit)), dim3(256), 0, s, hchunks,
+      hipLaunchKernelGGL(k_entry_prep<true>, dim3((unsigned)n_eblocks), dim3(256), 0, s, eblocks,
                          plan, friedel, refl_offset, ent_key, ent_idx, inten, g, span_cap, ent_w, span_first,
                          span_last);
     else
-      hipLaunchKernelGGL(k_entry_prep<false>, dim3((unsigned)(n_hchunks * kEntSplit)), dim3(256), 0, s,
-                         hchunks, plan, friedel, refl_offset, ent_key, ent_idx, inten, g, span_cap, ent_w,
+      hipLaunchKernelGGL(k_entry_prep<false>, dim3((unsigned)n_eblocks), dim3(256), 0, s,
+                         eblocks, plan, friedel, refl_offset, ent_key, ent_idx, inten, g, span_cap, ent_w,
                          span_first, span_last);
   }
   const dim3 grid((unsigned)(n_c * ((n + kSegPts - 1) / kSegPts))), block(256);
@@ -433,18 +429,18 @@ void launch_broaden_fwd(bool mixed, const HChunk *hchunks, int64_t n_hchunks, co
                        ent_w, span_first, span_last, span_cap, g, y);
 }
 
-void launch_broaden_adj(bool mixed, const HChunk *hchunks, int64_t n_hchunks, const CrystalPlan *plan,
+void launch_broaden_adj(bool mixed, const HChunk *eblocks, int64_t n_eblocks, const CrystalPlan *plan,
                         bool friedel, const int64_t *refl_offset, const double *ent_key, const int32_t *ent_idx,
                         const double *dy, double t0, double dt, int64_t n, double sigma, double window, double *w1,
                         double *w2, hipStream_t s) {
-  if (n_hchunks <= 0 || n <= 0) return;
+  if (n_eblocks <= 0 || n <= 0) return;
   const GridArgs g = make_grid(t0, dt, n, sigma, window);
-  const dim3 grid((unsigned)(n_hchunks * kEntSplit)), block(256);
+  const dim3 grid((unsigned)n_eblocks), block(256);
   if (mixed)
-    hipLaunchKernelGGL(k_broaden_adj<true>, grid, block, 0, s, hchunks, plan, friedel, refl_offset, ent_key,
+    hipLaunchKernelGGL(k_broaden_adj<true>, grid, block, 0, s, eblocks, plan, friedel, refl_offset, ent_key,
                        ent_idx, dy, g, w1, w2);
   else
-    hipLaunchKernelGGL(k_broaden_adj<false>, grid, block, 0, s, hchunks, plan, friedel, refl_offset, ent_key,
+    hipLaunchKernelGGL(k_broaden_adj<false>, grid, block, 0, s, eblocks, plan, friedel, refl_offset, ent_key,
                        ent_idx, dy, g, w1, w2);
 }
 

@@ -17,6 +17,7 @@ constexpr int kEnumRows = 32;     // (h, k) rows of a half search box per enumer
 constexpr int kSortChunk = 1024;  // reflections per sort/merge block (256 threads x 4)
 constexpr int kBinDiv = 4;        // merge-sort bins per crystal = capacity / kBinDiv
 constexpr int kHalfChunk = 2048;  // reflections per adjoint chunk
+constexpr int kEntBlock = 1024;   // entries per block of the broadening's entry preparation and adjoint
 constexpr int kScanBlock = 2048;  // elements per scan block (256 threads x 8)
 constexpr int kAtomBlock = 256;   // atoms per adjoint block
 constexpr int kSfRpt = 2;         // reflections per lane in the structure-factor kernels
@@ -93,7 +94,7 @@ struct SfItem {
 
 // Workspace byte offsets (all 256-aligned).
 struct WsLayout {
-  int64_t plan, enum_chunk_crystal, sf_items, peak_chunks, hchunks, crystal_order, bw_items, ab_items;
+  int64_t plan, enum_chunk_crystal, sf_items, peak_chunks, eblocks, crystal_order, bw_items, ab_items;
   int64_t enum_count, enum_prefix;
   int64_t atoms, atom_orig, runs, run_count, err_flag;
   int64_t bin_count, bin_start;
@@ -204,13 +205,15 @@ void launch_merge(const MergeArgs &a, const Fork &f, hipStream_t s);
 // Gaussian broadening over the sorted entries (evaluated reflections in
 // 2theta order).  The forward also fills ent_w (double weights, or float
 // weights in its first half under mixed precision) and the span tables;
-// crystal_order lists the crystals heaviest first.
-void launch_broaden_fwd(bool mixed, const HChunk *hchunks, int64_t n_hchunks, const CrystalPlan *plan,
+// crystal_order lists the crystals heaviest first.  eblocks lists the
+// (crystal, block of kEntBlock entries) units of the entry preparation and
+// the adjoint, one workgroup each, the expected-filled ones first.
+void launch_broaden_fwd(bool mixed, const HChunk *eblocks, int64_t n_eblocks, const CrystalPlan *plan,
                         const int32_t *crystal_order, int64_t n_c, bool friedel, const int64_t *refl_offset, const double *ent_key,
                         const int32_t *ent_idx, const double *inten, double t0, double dt, int64_t n, double sigma,
                         double window, int64_t span_cap, double *ent_w, int32_t *span_first, int32_t *span_last,
                         double *y, hipStream_t s);
-void launch_broaden_adj(bool mixed, const HChunk *hchunks, int64_t n_hchunks, const CrystalPlan *plan,
+void launch_broaden_adj(bool mixed, const HChunk *eblocks, int64_t n_eblocks, const CrystalPlan *plan,
                         bool friedel, const int64_t *refl_offset, const double *ent_key, const int32_t *ent_idx,
                         const double *dy, double t0, double dt, int64_t n, double sigma, double window, double *w1,
                         double *w2, hipStream_t s);
