@@ -57,7 +57,7 @@ __device__ __forceinline__ void window_of(const GridArgs &g, double t, int64_t *
 constexpr int kSegPts = 1024;                  // grid points per gather block (4 per thread)
 constexpr int kGTile = 1024;                   // entries per LDS tile of the gather
 constexpr int kAdjSpan = 4096;                 // grid points of dL/dy an adjoint block stages in LDS
-static_assert(kSegPts == 16 * kSpanPts, "a gather block covers 16 spans, four per wave");
+static_assert(kSegPts == 64 * kSpanPts, "a gather block covers 64 spans, a quarter wavefront each");
 
 // Entries: the evaluated reflections of a crystal in ascending 2theta (both
 // mates of a Friedel pair share 2theta and I exactly, so with pairing one
@@ -95,10 +95,10 @@ __device__ __forceinline__ int2 window_wide(const GridArgs &g, double t) {
 // Entry preparation, one block per kEntBlock entries of a crystal: the
 // weight w_e = m I norm of every entry, and the entry ranges of the
 // crystal's spans of kSpanPts grid points:
-//   first[s] = min{e : gh_e >= 64 s},  last[s] = max{e : gl_e <= 64 s + 63},
-// with [gl_e, gh_e] the (clamped, one step wide) window of entry e.  Both ends are
-// nondecreasing in e, so entry e owns first[s] for s in
-// (gh_{e-1} / 64, gh_e / 64] and last[s] for s in [gl_e / 64, gl_{e+1} / 64)
+//   first[s] = min{e : gh_e >= P s},  last[s] = max{e : gl_e <= P s + P - 1},
+// P = kSpanPts, with [gl_e, gh_e] the (clamped, one step wide) window of
+// entry e.  Both ends are nondecreasing in e, so entry e owns first[s] for s
+// in (gh_{e-1} / P, gh_e / P] and last[s] for s in [gl_e / P, gl_{e+1} / P)
 // (integer floors), the first and last entries also own the spans beyond;
 // every span of a crystal with entries is written exactly once.
 template <bool MIXED>
@@ -179,14 +179,17 @@ __global__ __launch_bounds__(256) void k_entry_prep(const HChunk *__restrict__ e
 }
 
 // Forward gather: a block owns kSegPts consecutive grid points of one
-// crystal, each lane four of them, 256 apart, so that wave w of the block
-// covers spans 4j + w (j = 0..3) of the segment.  The entries reaching the
-// segment (first of its first span .. last of its last span) are staged in
-// LDS in tiles; each wave walks, for each of its spans, that span's entry
-// range in 2theta order with wave-uniform LDS reads, and each lane adds
+// crystal, each lane four of them, 256 apart; for its j-th point, the
+// sixteen lanes of quarter q of wave w cover span 16j + 4w + q of the
+// segment.  The entries reaching the segment (first of its first span ..
+// last of its last span) are staged in LDS in tiles; each quarter walks its
+// span's entry range in 2theta order (a quarter's lanes read the same LDS
+// entry; the wave runs as long as its longest range), and each lane adds
 // w K(x - 2theta) when its point lies in the entry's window (the same
 // |x - 2theta| <= half test that defines the window), so every point sums
-// exactly its reflections, in sorted order, deterministically.  The offset
+// exactly its reflections, in sorted order, deterministically.  Spans of a
+// quarter wavefront keep the share of entries that miss a lane's window
+// small (a span of P points walks the entries of P points plus a window).  The offset
 // x - 2theta and the window test are double precision in both paths; under
 // MIXED the weight, the exponential (v_exp_f32) and the sums are single
 // precision, otherwise double.  Blocks take the crystals heaviest first and
@@ -210,15 +213,14 @@ __global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restric
   const int64_t c = crystal_order[blockIdx.x / segs];
   const int sb = (segs - 1 - (int)(blockIdx.x % segs)) * (kSegPts / kSpanPts);
   const int se = min(sb + kSegPts / kSpanPts, S) - 1;  // last span of the block
-  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   const EntryRange er = entry_range(refl_offset, c, friedel);
   const int32_t *__restrict__ fs = span_first + c * span_cap;
   const int32_t *__restrict__ ls = span_last + c * span_cap;
-  // entry ranges of the wave's spans (empty for spans past the grid's end)
+  // entry ranges of the lane's spans (empty for spans past the grid's end)
   int f[4], l[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    const int s = sb + 4 * j + wid;
+    const int s = sb + 16 * j + (int)(threadIdx.x / kSpanPts);
     f[j] = s <= se ? max(fs[s], 0) : 0;
     l[j] = s <= se ? (int)min((int64_t)ls[s], er.count - 1) : -1;
   }
@@ -253,7 +255,7 @@ __global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restric
     for (int j = 0; j < 4; ++j) {
       const int a = max(f[j], T0) - T0, b = min(l[j], T1) - T0;
       real sacc = acc[j];
-#pragma unroll 8
+#pragma unroll 4
       for (int e = a; e <= b; ++e) {
         const double2 ent = s_ent[e];
         const double d = x[j] - ent.x;

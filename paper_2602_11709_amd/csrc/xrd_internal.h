@@ -27,7 +27,7 @@ constexpr int kSplitAtoms = 24;      // crystals from this size get a block per 
 constexpr int kTinySort = 1024;      // Friedel-positive reflections sorted in LDS by one 256-thread block
 constexpr int kSmallSort = 4096;     // ... by one 1024-thread block
 constexpr int kMidSort = 8192;       // ... by one 1024-thread block; larger crystals sort in global memory
-constexpr int kSpanPts = 64;         // grid points per wave of the broadening gather
+constexpr int kSpanPts = 16;         // grid points per span of the broadening gather (a quarter wavefront)
 
 // Per-crystal plan (device copy in the workspace), 256 bytes.
 struct alignas(16) CrystalPlan {
