@@ -358,14 +358,18 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   // remaining tile, one wavefront each: these mostly find no reflection and
   // end at once, and the few that do are complete on a single wavefront
   auto likely_tiles = [&](int64_t c) { return likely_units(c, kSfTile, b->plan[c].n_tiles); };
+  auto sf_item = [&](int64_t c, int32_t t) {
+    const CrystalPlan &P = b->plan[c];
+    return SfItem{(int32_t)c, t, (int32_t)P.atom_begin, (int32_t)P.atom_end, (int32_t)P.run_begin, {0, 0, 0}};
+  };
   for (int64_t c : heavy)
-    for (int32_t t = 0; t < likely_tiles(c); ++t) b->sf_items.push_back(SfItem{(int32_t)c, t});
+    for (int32_t t = 0; t < likely_tiles(c); ++t) b->sf_items.push_back(sf_item(c, t));
   b->sf_heavy = (int64_t)b->sf_items.size();
   for (int64_t c : light)
-    for (int32_t t = 0; t < likely_tiles(c); ++t) b->sf_items.push_back(SfItem{(int32_t)c, t});
+    for (int32_t t = 0; t < likely_tiles(c); ++t) b->sf_items.push_back(sf_item(c, t));
   for (const auto *group : {&heavy, &light})
     for (int64_t c : *group)
-      for (int32_t t = likely_tiles(c); t < b->plan[c].n_tiles; ++t) b->sf_items.push_back(SfItem{(int32_t)c, t});
+      for (int32_t t = likely_tiles(c); t < b->plan[c].n_tiles; ++t) b->sf_items.push_back(sf_item(c, t));
   if ((int64_t)b->sf_items.size() >= ((int64_t)1 << 31) || (int64_t)b->bw_items.size() >= ((int64_t)1 << 31)) {
     delete b;
     return fail(XRD_ERR_CAPACITY, "launch tables exceed 2^31 entries");

@@ -151,12 +151,12 @@ __device__ __forceinline__ WaveWork wave_work(int64_t n_heavy) {
   return w;
 }
 
-// Atom range [wa, wb) of a wavefront's part of crystal P.
-__device__ __forceinline__ void part_range(const CrystalPlan &P, const WaveWork &w, int *wa, int *wb) {
-  const int na = (int)(P.atom_end - P.atom_begin);
+// Atom range [wa, wb) of a wavefront's part of the item's crystal.
+__device__ __forceinline__ void part_range(const SfItem &it, const WaveWork &w, int *wa, int *wb) {
+  const int na = it.atom_end - it.atom_begin;
   const int q = (na + w.nparts - 1) / w.nparts;
-  *wa = (int)P.atom_begin + min(na, w.part * q);
-  *wb = (int)P.atom_begin + min(na, (w.part + 1) * q);
+  *wa = it.atom_begin + min(na, w.part * q);
+  *wb = it.atom_begin + min(na, (w.part + 1) * q);
 }
 
 // d f / d(s^2) alongside f (single and double precision); f takes the same
@@ -413,7 +413,6 @@ __device__ __forceinline__ void load_derivs(const void *cache, int64_t i, double
 // summed and kept in ``cache`` for the adjoint.
 template <bool MIXED, bool FRIEDEL, bool DERIV>
 __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ items, int64_t n_items, int64_t n_heavy,
-                                                 const CrystalPlan *__restrict__ plan,
                                                  const int64_t *__restrict__ refl_offset,
                                                  const int16_t *__restrict__ hh, const int16_t *__restrict__ kk,
                                                  const int16_t *__restrict__ ll, const double *__restrict__ qq,
@@ -453,11 +452,10 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
     s2d[u] = 0.25 * qq[idx[u]];
     s2[u] = (float)s2d[u];
   }
-  const CrystalPlan &P = plan[it.crystal];
   int wa, wb;
-  part_range(P, ww, &wa, &wb);
+  part_range(it, ww, &wa, &wb);
   double A[R], B[R], dA[R], dB[R];
-  if (!sf_tile_sums<MIXED, DERIV>(ww, lane, runs + P.run_begin, run_count[it.crystal], wa, wb, atoms, coeff, coeff_f,
+  if (!sf_tile_sums<MIXED, DERIV>(ww, lane, runs + it.run_begin, run_count[it.crystal], wa, wb, atoms, coeff, coeff_f,
                                   h, k, l, s2d, s2, s_part, false, A, B, dA, dB))
     return;
 #pragma unroll
@@ -547,10 +545,10 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
     s2[u] = (float)s2d[u];
   }
   const CrystalPlan &P = plan[it.crystal];
-  const SpeciesRun *cr = runs + P.run_begin;
+  const SpeciesRun *cr = runs + it.run_begin;
   const int nr = run_count[it.crystal];
   int wa, wb;
-  part_range(P, ww, &wa, &wb);
+  part_range(it, ww, &wa, &wb);
   double A[R], B[R], dA[R], dB[R];
   if constexpr (CACHED) {
 #pragma unroll
@@ -999,12 +997,12 @@ __global__ __launch_bounds__(kThreads) void k_bw_finish(const AbItem *__restrict
 
 
 template <bool MIXED, bool FRIEDEL, bool DERIV>
-static void launch_sf_t(dim3 grid, const SfItem *items, int64_t n_items, int64_t n_heavy, const CrystalPlan *plan,
+static void launch_sf_t(dim3 grid, const SfItem *items, int64_t n_items, int64_t n_heavy,
                         const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
                         const double *q, const double *lp, const AtomRec *atoms, const SpeciesRun *runs,
                         const int32_t *run_count, const double *coeff, const CoeffF *coeff_f, void *A, void *B,
                         double *I, void *cache, hipStream_t s) {
-  hipLaunchKernelGGL((k_sf<MIXED, FRIEDEL, DERIV>), grid, dim3(kThreads), 0, s, items, n_items, n_heavy, plan,
+  hipLaunchKernelGGL((k_sf<MIXED, FRIEDEL, DERIV>), grid, dim3(kThreads), 0, s, items, n_items, n_heavy,
                      refl_offset, h, k, l, q, lp, atoms, runs, run_count, coeff, coeff_f, A, B, I, cache);
 }
 
@@ -1016,7 +1014,7 @@ void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, i
   if (n_items <= 0) return;
   const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4));
   auto go = [&](auto fn) {
-    fn(grid, items, n_items, n_heavy, plan, refl_offset, h, k, l, q, lp, atoms, runs, run_count, coeff, coeff_f, A, B,
+    fn(grid, items, n_items, n_heavy, refl_offset, h, k, l, q, lp, atoms, runs, run_count, coeff, coeff_f, A, B,
        I, deriv_cache, s);
   };
   const bool d = deriv_cache != nullptr;

@@ -86,11 +86,17 @@ struct HChunk {
   int32_t chunk;
 };
 
-// Structure-factor work item: a tile of reflections of one crystal.
-struct SfItem {
+// Structure-factor work item: a tile of reflections of one crystal, with
+// the crystal's atom range and species-run slots (from the plan), so that a
+// wavefront's atom loads do not wait for the plan (32 bytes, one scalar load).
+struct alignas(32) SfItem {
   int32_t crystal;
   int32_t tile;
+  int32_t atom_begin, atom_end;  // packed atoms [atom_begin, atom_end)
+  int32_t run_begin;             // first slot of the crystal's species-run table
+  int32_t pad[3];
 };
+static_assert(sizeof(SfItem) == 32, "SfItem layout");
 
 // Workspace byte offsets (all 256-aligned).
 struct WsLayout {
