@@ -54,8 +54,10 @@ extern "C" {
 /* Arithmetic of the structure-factor, broadening and adjoint kernels. */
 #define XRD_FP64 0  /* plain path: every step in double precision */
 #define XRD_MIXED 1 /* phase h.x reduced mod 1 in double precision; sin/cos, scattering
-                       factors and weights in single precision with compensated
-                       accumulation; q, 2theta, LP, merge keys and intensities in double */
+                       factors and weights in single precision, summed in single
+                       precision over at most 64 atoms of one species and those
+                       partial sums added in double; q, 2theta, LP, merge keys and
+                       intensities in double */
 
 typedef struct xrd_batch xrd_batch; /* opaque */
 
@@ -194,6 +196,23 @@ int xrd_pattern_forward(xrd_batch *b, void *ws, const xrd_refl *r, const double 
 int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_grid *g,
                          const double *dL_dy, double *dL_dfrac, double *dL_dbfac,
                          double *dL_dlattice);
+
+/* Autotuner of the structure-factor launches (the batched execution of the
+ * paper's structure-factor loops, Section 2 and Section 4.2): a crystal with
+ * at least S atoms has each tile of its reflections summed by a block whose
+ * four wavefronts split the atoms (split-K, partial sums added in a fixed
+ * order), a smaller one by a single wavefront.  For the forward sum of
+ * xrd_structure_factors and for the atom pass of xrd_pattern_backward
+ * separately, times each candidate S (8 to 512, and no split) on this
+ * batch's current reflections ``r`` (median of five launches) and keeps the
+ * fastest in the batch and its launch tables in ``ws``.  Needs a prior
+ * xrd_enumerate_hkl on ``ws`` and ``r``.  Synchronises the batch's stream
+ * (a set-up call, not for graph capture); overwrites workspace scratch only,
+ * so structure factors kept for the adjoint (keep_sf_derivs) must be
+ * computed again.  The split changes only the summation order (results agree
+ * to rounding).  ``split_out`` (optional, host [2]) receives the chosen
+ * forward and adjoint S (INT32_MAX: no split). */
+int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out);
 
 /* Wait for the batch's stream and copy refl_offset and peak_offset
  * ([n_crystals+1] each; either may be NULL) to host memory. */

@@ -198,6 +198,11 @@ class XrdBatch:
         capi.xrd_structure_factors(self.handle, self.ws, refl.c(), A.data_ptr(), B.data_ptr(), I.data_ptr())
         return A, B, I
 
+    def autotune(self, refl: Reflections):
+        """Time the structure-factor split candidates on ``refl`` (enumerated on
+        this batch) and keep the fastest; returns (forward, adjoint) thresholds."""
+        return capi.xrd_autotune(self.handle, self.ws, refl.c())
+
     def merge(self, refl: Reflections, I: torch.Tensor, peaks: Optional[Peaks] = None) -> Peaks:
         peaks = peaks or self.new_peaks()
         capi.xrd_merge_peaks(self.handle, self.ws, refl.c(), I.data_ptr(), peaks.c())
@@ -259,10 +264,14 @@ class PatternResult:
 
 
 def simulate(batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
-             rel_threshold: float = 0.0, device="cuda") -> PatternResult:
-    """Enumerate, structure factors, merge for every crystal; host arrays back."""
+             rel_threshold: float = 0.0, device="cuda", autotune: bool = False) -> PatternResult:
+    """Enumerate, structure factors, merge for every crystal; host arrays back.
+    With ``autotune`` the structure-factor split is tuned on the enumerated
+    reflections first."""
     xb = XrdBatch(batch, precision=precision, friedel=friedel, rel_threshold=rel_threshold, device=device)
     refl = xb.enumerate()
+    if autotune:
+        xb.autotune(refl)
     A, B, I = xb.structure_factors(refl)
     pk = xb.merge(refl, I)
     ro, po = xb.read_counts(refl, pk)

@@ -76,6 +76,7 @@ SIGNATURES = {
     "xrd_merge_peaks": ([_vp, _vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_peaks)], C.c_int),
     "xrd_pattern_forward": ([_vp, _vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_grid), _vp], C.c_int),
     "xrd_pattern_backward": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(xrd_grid), _vp, _vp, _vp, _vp], C.c_int),
+    "xrd_autotune": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(C.c_int32)], C.c_int),
     "xrd_read_counts": ([_vp, C.POINTER(xrd_refl), C.POINTER(xrd_peaks), _vp, _vp], C.c_int),
     "xrd_batch_destroy": ([_vp], None),
     "xrd_last_error": ([], C.c_char_p),
@@ -140,6 +141,13 @@ def xrd_pattern_forward(batch, ws: int, refl: xrd_refl, I: int, grid: xrd_grid, 
 def xrd_pattern_backward(batch, ws: int, refl: xrd_refl, grid: xrd_grid, dy: int, dfrac: int, dbfac: int,
                          dlat: int):
     check(lib().xrd_pattern_backward(batch, ws, C.byref(refl), C.byref(grid), dy, dfrac, dbfac, dlat))
+
+
+def xrd_autotune(batch, ws: int, refl: xrd_refl):
+    """Chosen (forward, adjoint) split thresholds."""
+    out = (C.c_int32 * 2)()
+    check(lib().xrd_autotune(batch, ws, C.byref(refl), out))
+    return int(out[0]), int(out[1])
 
 
 def xrd_read_counts(batch, refl, peaks, host_refl_offset, host_peak_offset):

@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -31,14 +32,17 @@ struct xrd_batch {
   std::vector<HChunk> peak_chunks;  // peak chunks of the merge (crystal, chunk)
   std::vector<HChunk> eblocks;  // entry blocks of the broadening (crystal, block of kEntBlock entries)
   std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
-  std::vector<SfItem> sf_items;
+  std::vector<int32_t> sf_order;   // crystals by descending atom count
+  std::vector<int32_t> sf_likely;  // per crystal: tiles its expected reflection count fills
+  std::vector<SfItem> sf_items, sf_items_bw;  // launch orders of the forward sum and the adjoint
   std::vector<BwItem> bw_items;
   std::vector<AbItem> ab_items;
   int64_t n_atoms = 0, refl_cap = 0, half_cap = 0, n_bins = 0, run_cap = 0, part_rows = 0, partf_rows = 0;
   int64_t n_mid = 0;      // crystals whose reflection capacity exceeds 2 kSmallSort
   int64_t n_small = 0;    // crystals whose reflection capacity exceeds 2 kTinySort
   int64_t n_large = 0;    // crystals whose reflection capacity exceeds 2 kMidSort
-  int64_t sf_heavy = 0;   // leading structure-factor items that take a block each
+  int64_t sf_heavy = 0, sf_heavy_bw = 0;  // leading items that take a block each
+  int32_t split_fwd = kSplitFwd, split_bw = kSplitBw;
   int64_t grid_cap = 0;   // largest grid of a broadened-pattern call
   int64_t span_cap = 0;   // span-table entries per crystal: ceil(grid_cap / kSpanPts)
   int runs_cap_max = 1, bw_tile = 64;
@@ -125,6 +129,35 @@ int check_refl(const xrd_refl *r) {
   if (!r || !r->h || !r->k || !r->l || !r->q || !r->two_theta || !r->lp || !r->refl_offset)
     return fail(XRD_ERR_INVALID_ARG, "reflection arrays must be non-NULL");
   return XRD_OK;
+}
+
+// Structure-factor items in launch order for split threshold ``split``:
+// the expected-filled tiles of the crystals with at least ``split`` atoms (a
+// block per tile, atoms split over its wavefronts), then those of the other
+// crystals, crystal by crystal (neighbouring waves share the crystal's atoms
+// in cache), then every remaining tile, one wavefront each: these mostly find
+// no reflection and end at once, and the few that do are complete on a
+// single wavefront.  Crystals come in descending atom count, so the heaviest
+// work is dispatched first.  Returns the number of block-per-tile items.
+int64_t sf_table(const xrd_batch *b, int32_t split, std::vector<SfItem> *items) {
+  items->clear();
+  auto item = [&](int32_t c, int32_t t) {
+    const CrystalPlan &P = b->plan[c];
+    return SfItem{c, t, (int32_t)P.atom_begin, (int32_t)P.atom_end, (int32_t)P.run_begin, {0, 0, 0}};
+  };
+  auto heavy = [&](int32_t c) { return b->plan[c].atom_end - b->plan[c].atom_begin >= split; };
+  for (int32_t c : b->sf_order)
+    if (heavy(c))
+      for (int32_t t = 0; t < b->sf_likely[c]; ++t) items->push_back(item(c, t));
+  const int64_t n_heavy = (int64_t)items->size();
+  for (int32_t c : b->sf_order)
+    if (!heavy(c))
+      for (int32_t t = 0; t < b->sf_likely[c]; ++t) items->push_back(item(c, t));
+  for (int pass = 0; pass < 2; ++pass)
+    for (int32_t c : b->sf_order)
+      if (heavy(c) == (pass == 0))
+        for (int32_t t = b->sf_likely[c]; t < b->plan[c].n_tiles; ++t) items->push_back(item(c, t));
+  return n_heavy;
 }
 
 }  // namespace
@@ -335,16 +368,18 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   }
   // structure-factor items: crystals in descending atom count (the cost of
   // one item), so the heaviest work is dispatched first
-  std::vector<int64_t> order(nc);
-  for (int64_t c = 0; c < nc; ++c) order[c] = c;
-  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+  b->sf_order.resize(nc);
+  b->sf_likely.resize(nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    b->sf_order[c] = (int32_t)c;
+    b->sf_likely[c] = likely_units(c, kSfTile, b->plan[c].n_tiles);
+  }
+  std::stable_sort(b->sf_order.begin(), b->sf_order.end(), [&](int32_t x, int32_t y) {
     return (b->atom_offset[x + 1] - b->atom_offset[x]) > (b->atom_offset[y + 1] - b->atom_offset[y]);
   });
-  std::vector<int64_t> heavy, light;
-  for (int64_t c : order) {
+  for (int32_t c : b->sf_order) {
     const CrystalPlan &P = b->plan[c];
     const int64_t na = P.atom_end - P.atom_begin;
-    (na >= kSplitAtoms ? heavy : light).push_back(c);
     const int64_t ab = ceil_div(na, kAtomBlock);
     for (int64_t a = 0; a < ab; ++a) {
       b->ab_items.push_back(AbItem{(int32_t)c, (int32_t)a});
@@ -352,24 +387,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
         for (int32_t k = 0; k < P.n_hchunks; ++k) b->bw_items.push_back(BwItem{(int32_t)c, (int32_t)a, k, 0});
     }
   }
-  // structure-factor tiles: the expected-filled tiles of the heavy crystals
-  // (a block per tile), then those of the light crystals, crystal by crystal
-  // (neighbouring waves share the crystal's atoms in cache), then every
-  // remaining tile, one wavefront each: these mostly find no reflection and
-  // end at once, and the few that do are complete on a single wavefront
-  auto likely_tiles = [&](int64_t c) { return likely_units(c, kSfTile, b->plan[c].n_tiles); };
-  auto sf_item = [&](int64_t c, int32_t t) {
-    const CrystalPlan &P = b->plan[c];
-    return SfItem{(int32_t)c, t, (int32_t)P.atom_begin, (int32_t)P.atom_end, (int32_t)P.run_begin, {0, 0, 0}};
-  };
-  for (int64_t c : heavy)
-    for (int32_t t = 0; t < likely_tiles(c); ++t) b->sf_items.push_back(sf_item(c, t));
-  b->sf_heavy = (int64_t)b->sf_items.size();
-  for (int64_t c : light)
-    for (int32_t t = 0; t < likely_tiles(c); ++t) b->sf_items.push_back(sf_item(c, t));
-  for (const auto *group : {&heavy, &light})
-    for (int64_t c : *group)
-      for (int32_t t = likely_tiles(c); t < b->plan[c].n_tiles; ++t) b->sf_items.push_back(sf_item(c, t));
+  b->sf_heavy = sf_table(b, b->split_fwd, &b->sf_items);
+  b->sf_heavy_bw = sf_table(b, b->split_bw, &b->sf_items_bw);
   if ((int64_t)b->sf_items.size() >= ((int64_t)1 << 31) || (int64_t)b->bw_items.size() >= ((int64_t)1 << 31)) {
     delete b;
     return fail(XRD_ERR_CAPACITY, "launch tables exceed 2^31 entries");
@@ -387,6 +406,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.plan = take((int64_t)sizeof(CrystalPlan) * nc);
   L.enum_chunk_crystal = take(4 * ec);
   L.sf_items = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items.size());
+  L.sf_items_bw = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items_bw.size());
   L.peak_chunks = take((int64_t)sizeof(HChunk) * sc);
   L.eblocks = take((int64_t)sizeof(HChunk) * (int64_t)b->eblocks.size());
   L.crystal_order = take(4 * nc);
@@ -459,6 +479,7 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   if (e == hipSuccess) e = up(L.plan, b->plan.data(), sizeof(CrystalPlan) * b->plan.size());
   if (e == hipSuccess) e = up(L.enum_chunk_crystal, b->enum_chunk_crystal.data(), 4 * b->enum_chunk_crystal.size());
   if (e == hipSuccess) e = up(L.sf_items, b->sf_items.data(), sizeof(SfItem) * b->sf_items.size());
+  if (e == hipSuccess) e = up(L.sf_items_bw, b->sf_items_bw.data(), sizeof(SfItem) * b->sf_items_bw.size());
   if (e == hipSuccess) e = up(L.peak_chunks, b->peak_chunks.data(), sizeof(HChunk) * b->peak_chunks.size());
   if (e == hipSuccess) e = up(L.eblocks, b->eblocks.data(), sizeof(HChunk) * b->eblocks.size());
   if (e == hipSuccess) e = up(L.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
@@ -665,8 +686,8 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   hipStream_t s = stream_of(b);
   const bool mixed = b->desc.precision == XRD_MIXED, friedel = b->desc.friedel != 0;
   const CrystalPlan *plan = at<CrystalPlan>(ws, L.plan);
-  const SfItem *items = at<SfItem>(ws, L.sf_items);
-  const int64_t n_items = (int64_t)b->sf_items.size();
+  const SfItem *items = at<SfItem>(ws, L.sf_items_bw);
+  const int64_t n_items = (int64_t)b->sf_items_bw.size();
   double *w1 = at<double>(ws, L.bw_w1), *w2 = at<double>(ws, L.bw_w2);
   double *ga = at<double>(ws, L.bw_ga), *gb = at<double>(ws, L.bw_gb), *dq = at<double>(ws, L.bw_dq);
   ensure_sorted(b, ws, r);
@@ -674,7 +695,7 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   launch_broaden_adj(mixed, at<HChunk>(ws, L.eblocks), (int64_t)b->eblocks.size(), plan, friedel,
                      r->refl_offset, at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), dL_dy, g->t0, g->dt,
                      g->n_points, g->sigma, g->window_sigmas, w1, w2, s);
-  launch_sf_bw(mixed, friedel, items, n_items, b->sf_heavy, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
+  launch_sf_bw(mixed, friedel, items, n_items, b->sf_heavy_bw, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
                b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
                b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), deriv, w1, w2, ga, gb, dq, at<double>(ws, L.bw_part6),
                at<double>(ws, L.bw_partf), s);
@@ -687,6 +708,104 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
                    at<double>(ws, L.bw_part6), dL_dfrac, dL_dbfac, dL_dlattice, s);
   b->last_ws = ws;
   return hip_check("pattern_backward");
+}
+
+int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  if (int e = check_refl(r)) return e;
+  const WsLayout &L = b->ws;
+  hipStream_t s = stream_of(b);
+  const bool mixed = b->desc.precision == XRD_MIXED, friedel = b->desc.friedel != 0;
+  const CrystalPlan *plan = at<CrystalPlan>(ws, L.plan);
+  // outputs of the timing runs: A, B and I go to the reflection-gradient
+  // scratch (the adjoint rewrites it before reading it), derivatives (when
+  // kept) to their usual place
+  void *A = at<void>(ws, L.bw_ga), *B = at<void>(ws, L.bw_gb);
+  double *I = at<double>(ws, L.bw_dq);
+  void *deriv = L.sf_deriv >= 0 ? at<char>(ws, L.sf_deriv) : nullptr;
+  double *w1 = at<double>(ws, L.bw_w1), *w2 = at<double>(ws, L.bw_w2);
+  const int64_t n_items = (int64_t)b->sf_items.size();
+  auto run_fwd = [&](const std::vector<SfItem> &t, int64_t nh) {
+    launch_sf(mixed, friedel, at<SfItem>(ws, L.sf_items), (int64_t)t.size(), nh, plan, r->refl_offset, r->h, r->k,
+              r->l, r->q, r->lp, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
+              b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), A, B, I, deriv, s);
+  };
+  auto run_bw = [&](const std::vector<SfItem> &t, int64_t nh) {
+    launch_sf_bw(mixed, friedel, at<SfItem>(ws, L.sf_items_bw), (int64_t)t.size(), nh, plan, r->refl_offset, r->h,
+                 r->k, r->l, r->q, r->lp, b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
+                 at<int32_t>(ws, L.run_count), b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), deriv, w1, w2,
+                 at<double>(ws, L.bw_ga), at<double>(ws, L.bw_gb), at<double>(ws, L.bw_dq), at<double>(ws, L.bw_part6),
+                 at<double>(ws, L.bw_partf), s);
+  };
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipError_t e = hipEventCreate(&ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&ev[1]);
+  // median of five launches after one untimed launch
+  auto timed = [&](auto &&launch) -> float {
+    float t[5] = {0, 0, 0, 0, 0};
+    launch();
+    for (int i = 0; i < 5 && e == hipSuccess; ++i) {
+      e = hipEventRecord(ev[0], s);
+      launch();
+      if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+      if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+      if (e == hipSuccess) e = hipEventElapsedTime(&t[i], ev[0], ev[1]);
+    }
+    std::sort(t, t + 5);
+    return t[2];
+  };
+  // candidate thresholds; those giving the same table as an earlier one are skipped
+  const int32_t cand[] = {8, 16, 24, 32, 48, 64, 96, 128, 256, 512, INT32_MAX};
+  auto tune = [&](int64_t table_off, bool fwd, int32_t *best_split) {
+    std::vector<SfItem> t;
+    std::vector<int64_t> seen;
+    float best = 0.f;
+    for (int32_t c : cand) {
+      if (e != hipSuccess) break;
+      const int64_t nh = sf_table(b, c, &t);
+      if (std::find(seen.begin(), seen.end(), nh) != seen.end()) continue;
+      seen.push_back(nh);
+      e = hipMemcpyAsync(at<char>(ws, table_off), t.data(), sizeof(SfItem) * t.size(), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) break;
+      const float ms = fwd ? timed([&] { run_fwd(t, nh); }) : timed([&] { run_bw(t, nh); });
+      if (e == hipSuccess) e = hipGetLastError();
+      if (e == hipSuccess && (seen.size() == 1 || ms < best)) {
+        best = ms;
+        *best_split = c;
+      }
+    }
+  };
+  if (n_items > 0 && e == hipSuccess) {
+    tune(L.sf_items, true, &b->split_fwd);
+    b->sf_heavy = sf_table(b, b->split_fwd, &b->sf_items);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(at<char>(ws, L.sf_items), b->sf_items.data(), sizeof(SfItem) * n_items, hipMemcpyHostToDevice, s);
+    // the adjoint's inputs: derivatives of the chosen forward table, zero grid weights
+    if (e == hipSuccess) run_fwd(b->sf_items, b->sf_heavy);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(w1), b->refl_cap, 0, s);
+    launch_fill_u64(reinterpret_cast<uint64_t *>(w2), b->refl_cap, 0, s);
+    if (e == hipSuccess) e = hipGetLastError();
+    tune(L.sf_items_bw, false, &b->split_bw);
+    b->sf_heavy_bw = sf_table(b, b->split_bw, &b->sf_items_bw);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(at<char>(ws, L.sf_items_bw), b->sf_items_bw.data(), sizeof(SfItem) * n_items,
+                         hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  }
+  for (hipEvent_t x : ev)
+    if (x) (void)hipEventDestroy(x);
+  // the timing runs overwrote the kept derivatives' record of the last call
+  b->deriv_ws = nullptr;
+  b->deriv_h = nullptr;
+  b->last_ws = ws;
+  if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("autotune: ") + hipGetErrorString(e));
+  if (split_out) {
+    split_out[0] = b->split_fwd;
+    split_out[1] = b->split_bw;
+  }
+  return XRD_OK;
 }
 
 int xrd_read_counts(xrd_batch *b, const xrd_refl *r, const xrd_peaks *p, int64_t *host_refl_offset,

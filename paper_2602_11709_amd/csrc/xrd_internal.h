@@ -23,7 +23,12 @@ constexpr int kAtomBlock = 256;   // atoms per adjoint block
 constexpr int kSfRpt = 2;         // reflections per lane in the structure-factor kernels
 constexpr int kSfTile = 64 * kSfRpt;
 constexpr int kFusedMaxAtoms = 512;  // crystals up to this size take the fused atom-gradient path
-constexpr int kSplitAtoms = 24;      // crystals from this size get a block per structure-factor tile
+// Split-K of the structure-factor kernels: crystals with at least this many
+// atoms get a block per tile, whose four wavefronts split the atom sum; the
+// others a wavefront per tile.  Defaults for the forward sum and for the
+// adjoint's atom pass; xrd_autotune picks them per batch by timing.
+constexpr int kSplitFwd = 64;
+constexpr int kSplitBw = 32;
 constexpr int kTinySort = 1024;      // Friedel-positive reflections sorted in LDS by one 256-thread block
 constexpr int kSmallSort = 4096;     // ... by one 1024-thread block
 constexpr int kMidSort = 8192;       // ... by one 1024-thread block; larger crystals sort in global memory
@@ -111,6 +116,7 @@ struct WsLayout {
   int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6, bw_partf;
   int64_t sf_deriv;  // kept (A, B, dA/ds^2, dB/ds^2) per reflection, or -1
   int64_t coeff_f;   // [n_species] CoeffF
+  int64_t sf_items_bw;  // structure-factor items in the adjoint's launch order
   int64_t total;
 };
 
