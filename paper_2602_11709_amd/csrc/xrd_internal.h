@@ -28,7 +28,7 @@ constexpr int kFusedMaxAtoms = 512;  // crystals up to this size take the fused 
 // others a wavefront per tile.  Defaults for the forward sum and for the
 // adjoint's atom pass; xrd_autotune picks them per batch by timing.
 constexpr int kSplitFwd = 64;
-constexpr int kSplitBw = 32;
+constexpr int kSplitBw = 48;
 constexpr int kTinySort = 1024;      // Friedel-positive reflections sorted in LDS by one 256-thread block
 constexpr int kSmallSort = 4096;     // ... by one 1024-thread block
 constexpr int kMidSort = 8192;       // ... by one 1024-thread block; larger crystals sort in global memory
