@@ -28,7 +28,7 @@ struct xrd_batch {
   std::vector<double> lattice, tmin, tmax;
   std::vector<int64_t> atom_offset;
   std::vector<CrystalPlan> plan;
-  std::vector<int32_t> enum_chunk_crystal;
+  std::vector<EnumChunk> enum_chunks;  // enumeration chunks, crystal by crystal
   std::vector<HChunk> peak_chunks;  // peak chunks of the merge (crystal, chunk)
   std::vector<HChunk> eblocks;  // entry blocks of the broadening (crystal, block of kEntBlock entries)
   std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
@@ -111,6 +111,55 @@ bool reciprocal_metric(const double *lat, double gs[6]) {
 }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Cut a crystal's half box into enumeration chunks: runs of consecutive rows
+// (the lexicographic row order of the device enumeration: (0, 0), (0, k) for
+// k = 1..K, then (h, k) for h = 1..H, k = -K..K) of at most kEnumRows rows,
+// closed early when the next row would take the candidate count past
+// kEnumCand.  A row's candidates are the l between the roots of the convex
+// quadratic q(l) = qhi (one more on each side, clipped to the box), the same
+// bounds the kernels use; here they only balance the chunks, so the host's
+// rounding need not match the device's.  Appends to ``out``; returns the
+// number of chunks.
+int32_t enum_chunks_of(const CrystalPlan &P, int32_t c, std::vector<EnumChunk> *out) {
+  const int64_t rows = (int64_t)P.H * (2 * P.K + 1) + P.K + 1;
+  const double A = P.gs[2], lim = (double)P.L + 1.0;
+  auto candidates = [&](int64_t rho) -> int64_t {
+    int h, k;
+    if (rho <= P.K) {
+      h = 0;
+      k = (int)rho;
+    } else {
+      const int64_t x = rho - (P.K + 1), nk = 2 * P.K + 1;
+      h = 1 + (int)(x / nk);
+      k = (int)(x % nk) - P.K;
+    }
+    const double B = 2.0 * (P.gs[4] * h + P.gs[5] * k);
+    const double C = P.gs[0] * h * h + P.gs[1] * k * k + 2.0 * P.gs[3] * h * k;
+    const double disc = B * B - 4.0 * A * (C - P.qhi * (1.0 + 1e-9));
+    if (!(disc >= 0.0)) return 0;
+    const double sq = std::sqrt(disc);
+    const double r1 = std::fmin(std::fmax((-B - sq) / (2.0 * A), -lim), lim);
+    const double r2 = std::fmin(std::fmax((-B + sq) / (2.0 * A), -lim), lim);
+    const int64_t lo = std::max<int64_t>((h == 0 && k == 0) ? 1 : -P.L, (int64_t)std::floor(r1));
+    const int64_t hi = std::min<int64_t>(P.L, (int64_t)std::ceil(r2));
+    return std::max<int64_t>(0, hi - lo + 1);
+  };
+  int32_t n = 0;
+  int64_t start = 0, cand = 0;
+  for (int64_t rho = 0; rho < rows; ++rho) {
+    const int64_t m = candidates(rho);
+    if (rho > start && (rho - start == kEnumRows || cand + m > kEnumCand)) {
+      out->push_back(EnumChunk{c, (int32_t)start, (int32_t)(rho - start), 0});
+      ++n;
+      start = rho;
+      cand = 0;
+    }
+    cand += m;
+  }
+  out->push_back(EnumChunk{c, (int32_t)start, (int32_t)(rows - start), 0});
+  return n + 1;
+}
 
 template <class T>
 T *at(void *ws, int64_t off) {
@@ -260,7 +309,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
       return fail(XRD_ERR_CAPACITY, "reflection capacity exceeds 2^31; split the batch");
     }
     P.enum_chunk_begin = ec;
-    P.enum_chunks = (int32_t)ceil_div((int64_t)P.H * (2 * P.K + 1) + P.K + 1, kEnumRows);
+    P.enum_chunks = enum_chunks_of(P, (int32_t)c, &b->enum_chunks);
     ec += P.enum_chunks;
     P.sort_chunk_begin = sc;
     P.sort_chunks = (int32_t)ceil_div(2 * P.half_box, kSortChunk);
@@ -312,11 +361,6 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   }
 
   // launch tables
-  b->enum_chunk_crystal.resize(ec);
-  for (int64_t c = 0; c < nc; ++c) {
-    const CrystalPlan &P = b->plan[c];
-    for (int32_t i = 0; i < P.enum_chunks; ++i) b->enum_chunk_crystal[P.enum_chunk_begin + i] = (int32_t)c;
-  }
   // Capacities come from the search box; the reflections a crystal actually
   // has are close to the lattice points of its spherical shell, (4 pi / 3)
   // (g_max^3 - g_min^3) V (both halves).  The launch tables list first the
@@ -404,7 +448,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   };
   const int64_t rc = b->refl_cap;
   L.plan = take((int64_t)sizeof(CrystalPlan) * nc);
-  L.enum_chunk_crystal = take(4 * ec);
+  L.enum_chunk_tab = take((int64_t)sizeof(EnumChunk) * ec);
   L.sf_items = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items.size());
   L.sf_items_bw = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items_bw.size());
   L.peak_chunks = take((int64_t)sizeof(HChunk) * sc);
@@ -477,7 +521,7 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   };
   hipError_t e = hipSuccess;
   if (e == hipSuccess) e = up(L.plan, b->plan.data(), sizeof(CrystalPlan) * b->plan.size());
-  if (e == hipSuccess) e = up(L.enum_chunk_crystal, b->enum_chunk_crystal.data(), 4 * b->enum_chunk_crystal.size());
+  if (e == hipSuccess) e = up(L.enum_chunk_tab, b->enum_chunks.data(), sizeof(EnumChunk) * b->enum_chunks.size());
   if (e == hipSuccess) e = up(L.sf_items, b->sf_items.data(), sizeof(SfItem) * b->sf_items.size());
   if (e == hipSuccess) e = up(L.sf_items_bw, b->sf_items_bw.data(), sizeof(SfItem) * b->sf_items_bw.size());
   if (e == hipSuccess) e = up(L.peak_chunks, b->peak_chunks.data(), sizeof(HChunk) * b->peak_chunks.size());
@@ -505,8 +549,8 @@ int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r) {
   b->sorted_tt = nullptr;
   b->deriv_ws = nullptr;
   b->deriv_h = nullptr;
-  launch_enumerate(at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, at<int32_t>(ws, L.enum_chunk_crystal),
-                   (int64_t)b->enum_chunk_crystal.size(), b->desc.wavelength, at<int32_t>(ws, L.enum_count),
+  launch_enumerate(at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, at<EnumChunk>(ws, L.enum_chunk_tab),
+                   (int64_t)b->enum_chunks.size(), b->desc.wavelength, at<int32_t>(ws, L.enum_count),
                    at<int64_t>(ws, L.enum_prefix), at<int64_t>(ws, L.scan_part), r->h, r->k, r->l, r->q,
                    r->two_theta, r->lp, r->refl_offset, b->desc.n_species, b->desc.frac, b->desc.species,
                    b->desc.occ, b->desc.bfac, b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f),

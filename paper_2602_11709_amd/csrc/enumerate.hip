@@ -283,13 +283,13 @@ __global__ __launch_bounds__(64) void k_atom_pack(const CrystalPlan *__restrict_
                a.coeff_f, a.atoms, a.orig, a.runs, a.run_count, a.err);
 }
 
-// Survivor count per enumeration chunk of kEnumRows rows, one wavefront per
-// chunk (lane = row), four chunks per block.  The launch also packs the
+// Survivor count per enumeration chunk (at most kEnumRows rows), one
+// wavefront per chunk (lane = row), four chunks per block.  The launch also packs the
 // atoms (independent work) when pack is set: blocks from chunk_blocks on
 // take four crystals each, one per wavefront, with n_species LDS cursors per
 // wavefront.
 __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__restrict__ plan,
-                                                         const int32_t *__restrict__ chunk_crystal,
+                                                         const EnumChunk *__restrict__ chunks,
                                                          int64_t n_chunks, int64_t n_c, double lambda,
                                                          int32_t *__restrict__ counts, PackArgs pa) {
   const int64_t chunk_blocks = (n_chunks + kThreads / 64 - 1) / (kThreads / 64);
@@ -304,9 +304,9 @@ __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__re
   }
   const int64_t chunk = (int64_t)blockIdx.x * (kThreads / 64) + wid;
   if (chunk >= n_chunks) return;
-  const CrystalPlan &P = plan[chunk_crystal[chunk]];
-  const int64_t rho = (chunk - P.enum_chunk_begin) * kEnumRows + lane;
-  int n = lane < kEnumRows && rho < rows_of(P) ? row_count(P, row_of(P, rho), lambda) : 0;
+  const EnumChunk ch = chunks[chunk];
+  const CrystalPlan &P = plan[ch.crystal];
+  int n = lane < ch.n_rows ? row_count(P, row_of(P, (int64_t)ch.row_begin + lane), lambda) : 0;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) n += __shfl_xor(n, d, 64);
   if (lane == 0) counts[chunk] = n;
@@ -378,15 +378,14 @@ __global__ void k_enum_offsets(const CrystalPlan *__restrict__ plan, int64_t n_c
   if (c == n_c) refl_offset[n_c] = 2 * prefix[n_chunks];
 }
 
-// One wavefront per chunk of kEnumRows rows (lane = row, for the first
-// kEnumRows lanes), four chunks per
-// block.  The chunk's rows are flattened into their candidate points in
+// One wavefront per chunk (lane = row, for the chunk's first n_rows lanes),
+// four chunks per block.  The chunk's rows are flattened into their candidate points in
 // lexicographic order; the wavefront then takes the points 64 at a time, one
 // per lane (a binary search over the rows' candidate offsets finds a point's
 // row), tests them, ranks the survivors with a ballot and writes each with
 // its Friedel mate: (h, k, l), q, 2theta and LP.
 __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__restrict__ plan,
-                                                        const int32_t *__restrict__ chunk_crystal,
+                                                        const EnumChunk *__restrict__ chunks,
                                                         int64_t n_chunks, const int64_t *__restrict__ prefix,
                                                         double lambda, int16_t *__restrict__ oh,
                                                         int16_t *__restrict__ ok, int16_t *__restrict__ ol,
@@ -397,16 +396,16 @@ __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__res
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int64_t chunk = (int64_t)blockIdx.x * (kThreads / 64) + wid;
   if (chunk >= n_chunks) return;
-  const CrystalPlan &P = plan[chunk_crystal[chunk]];
+  const EnumChunk ch = chunks[chunk];
+  const CrystalPlan &P = plan[ch.crystal];
   const int64_t first_chunk = P.enum_chunk_begin;
   const int64_t c_begin = prefix[first_chunk];
   const int64_t rh = prefix[first_chunk + P.enum_chunks] - c_begin;  // positive-half count
   const int64_t seg = 2 * c_begin;                                     // crystal's first reflection
-  const int64_t rho = (chunk - first_chunk) * kEnumRows + lane;
   int lo = 1, hi = 0;
   Row r{0, 0, 1, 0};
-  if (lane < kEnumRows && rho < rows_of(P)) {
-    r = row_of(P, rho);
+  if (lane < ch.n_rows) {
+    r = row_of(P, (int64_t)ch.row_begin + lane);
     row_candidates(P, r, &lo, &hi);
   }
   const int nc = max(hi - lo + 1, 0);
@@ -479,7 +478,7 @@ __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__res
 
 }  // namespace
 
-void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk_crystal, int64_t n_chunks,
+void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const EnumChunk *chunks, int64_t n_chunks,
                       double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h,
                       int16_t *k, int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset,
                       int32_t n_species, const double *frac, const int32_t *species, const double *occ,
@@ -496,7 +495,7 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk
     const int64_t chunk_blocks = (n_chunks + kThreads / 64 - 1) / (kThreads / 64);
     const int64_t pack_blocks = fuse ? (n_c + kThreads / 64 - 1) / (kThreads / 64) : 0;
     hipLaunchKernelGGL(k_enum_count, dim3((unsigned)(chunk_blocks + pack_blocks)), dim3(kThreads),
-                       fuse ? fused_lds : 0, s, plan, chunk_crystal, n_chunks, n_c, lambda, counts, pa);
+                       fuse ? fused_lds : 0, s, plan, chunks, n_chunks, n_c, lambda, counts, pa);
   }
   if (n_chunks <= kOneBlockChunks) {
     hipLaunchKernelGGL(k_enum_scan1, dim3(1), dim3(1024), 0, s, plan, n_c, n_chunks, counts, prefix, refl_offset);
@@ -507,7 +506,7 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk
   }
   if (n_chunks > 0) {
     hipLaunchKernelGGL(k_enum_fill, dim3((unsigned)((n_chunks + kThreads / 64 - 1) / (kThreads / 64))),
-                       dim3(kThreads), 0, s, plan, chunk_crystal, n_chunks, prefix, lambda, h, k, l, q, tt, lp);
+                       dim3(kThreads), 0, s, plan, chunks, n_chunks, prefix, lambda, h, k, l, q, tt, lp);
   }
 }
 

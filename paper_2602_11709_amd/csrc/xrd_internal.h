@@ -13,7 +13,8 @@
 namespace xrd {
 
 // Work granularity.
-constexpr int kEnumRows = 32;     // (h, k) rows of a half search box per enumeration chunk, one per lane
+constexpr int kEnumRows = 32;     // most (h, k) rows of a half search box per enumeration chunk, one per lane
+constexpr int kEnumCand = 256;    // candidate points a chunk takes before the next chunk starts (one fill round)
 constexpr int kSortChunk = 1024;  // reflections per sort/merge block (256 threads x 4)
 constexpr int kBinDiv = 4;        // merge-sort bins per crystal = capacity / kBinDiv
 constexpr int kHalfChunk = 2048;  // reflections per adjoint chunk
@@ -45,7 +46,7 @@ struct alignas(16) CrystalPlan {
   int32_t n_bins;
   int64_t half_box;   // points of the search box above the origin: ((2H+1)(2K+1)(2L+1)-1)/2
   int64_t enum_chunk_begin;
-  int32_t enum_chunks;  // blocks of kEnumRows rows of the half box
+  int32_t enum_chunks;  // runs of consecutive rows of the half box (EnumChunk)
   int32_t n_hchunks;  // adjoint chunks at capacity
   int64_t atom_begin, atom_end;
   int64_t run_begin;  // first slot of this crystal's species-run table (capacity min(S, N))
@@ -85,6 +86,13 @@ struct alignas(16) SpeciesRun {
   int32_t begin, end, species, local;  // local = run index within the crystal
 };
 
+// Enumeration work unit: rows [row_begin, row_begin + n_rows) of a crystal's
+// half box (n_rows <= kEnumRows), cut so that the chunks' candidate counts
+// stay near kEnumCand.
+struct EnumChunk {
+  int32_t crystal, row_begin, n_rows, pad;
+};
+
 // Broadening work unit: chunk of kHalfChunk entries of one crystal.
 struct HChunk {
   int32_t crystal;
@@ -105,7 +113,7 @@ static_assert(sizeof(SfItem) == 32, "SfItem layout");
 
 // Workspace byte offsets (all 256-aligned).
 struct WsLayout {
-  int64_t plan, enum_chunk_crystal, sf_items, peak_chunks, eblocks, crystal_order, bw_items, ab_items;
+  int64_t plan, enum_chunk_tab, sf_items, peak_chunks, eblocks, crystal_order, bw_items, ab_items;
   int64_t enum_count, enum_prefix;
   int64_t atoms, atom_orig, runs, run_count, err_flag;
   int64_t bin_count, bin_start;
@@ -143,7 +151,7 @@ struct AbItem {
 
 // Enumeration (count, scan, fill) and, in the same launches, the packing of
 // the atoms into species runs for the structure-factor kernels.
-void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const int32_t *chunk_crystal, int64_t n_chunks,
+void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const EnumChunk *chunks, int64_t n_chunks,
                       double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h, int16_t *k,
                       int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset, int32_t n_species,
                       const double *frac, const int32_t *species, const double *occ, const double *bfac,
