@@ -289,8 +289,8 @@ __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const
       for (int v = 0; v < V; ++v)
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-          acc[v][u] = 0.0;
-          for (int w = 0; w < kThreads / 64; ++w) acc[v][u] += at(w, v, u);
+          acc[v][u] = at(0, v, u);
+          for (int w = 1; w < kThreads / 64; ++w) acc[v][u] += at(w, v, u);
         }
     }
 #pragma unroll
@@ -363,8 +363,8 @@ __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const
       for (int v = 0; v < V; ++v)
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-          acc[v][u] = 0.0;
-          for (int w = 0; w < kThreads / 64; ++w) acc[v][u] += at(w, v, u);
+          acc[v][u] = at(0, v, u);
+          for (int w = 1; w < kThreads / 64; ++w) acc[v][u] += at(w, v, u);
         }
     }
 #pragma unroll
@@ -439,7 +439,7 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
   const int lane = threadIdx.x & 63;
   int64_t idx[R];
   bool valid[R];
-  double h[R], k[R], l[R], s2d[R];
+  double h[R], k[R], l[R], s2d[R], lpv[R];
   float s2[R];
 #pragma unroll
   for (int u = 0; u < R; ++u) {
@@ -451,6 +451,7 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
     l[u] = ll[idx[u]];
     s2d[u] = 0.25 * qq[idx[u]];
     s2[u] = (float)s2d[u];
+    lpv[u] = lpp[idx[u]];  // loaded with the rest, not after the sums
   }
   int wa, wb;
   part_range(it, ww, &wa, &wb);
@@ -461,7 +462,7 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
 #pragma unroll
   for (int u = 0; u < R; ++u) {
     if (!valid[u]) continue;
-    const double I = (A[u] * A[u] + B[u] * B[u]) * lpp[idx[u]];
+    const double I = (A[u] * A[u] + B[u] * B[u]) * lpv[u];
     Iout[idx[u]] = I;
     if constexpr (DERIV) store_derivs<MIXED>(cache, idx[u], A[u], B[u], dA[u], dB[u]);
     const int64_t m = r0 + r1 - 1 - idx[u];
