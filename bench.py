@@ -62,6 +62,7 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the double-precision comparison path")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default structure-factor split thresholds")
+    ap.add_argument("--no-doublet", action="store_true", help="skip the Cu K-alpha doublet forward timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters), then exit")
     return ap.parse_args()
@@ -158,6 +159,46 @@ class Pipeline:
             e1.record(self.stream)
         e1.synchronize()
         return e0.elapsed_time(e1) / reps
+
+
+def doublet_ms(batch, reps=20):
+    """Forward patterns (peaks and the broadened pattern) of the workload under
+    Cu K-alpha1 and K-alpha2 (two lines of the calculator front-end): both
+    lines' enumerate, structure factors, merge and pattern captured in one
+    graph; average replay time in ms."""
+    import dataclasses
+    import torch
+    from paper_2602_11709_amd import frontend
+    from paper_2602_11709_amd.api import Grid, XrdBatch
+    grid = Grid(**GRID)
+    s = torch.cuda.Stream()
+    parts = []
+    with torch.cuda.stream(s):
+        for lam, _, _ in frontend.lines_of("CuKa12"):
+            xb = XrdBatch(dataclasses.replace(batch, wavelength=lam), precision="mixed")
+            parts.append((xb, xb.new_reflections(), xb.new_sf(), xb.new_peaks(),
+                          torch.empty(batch.n_crystals, grid.n_points, dtype=torch.float64, device="cuda")))
+
+    def step():
+        for xb, refl, sf, pk, y in parts:
+            xb.enumerate(refl)
+            xb.structure_factors(refl, sf)
+            xb.merge(refl, sf[2], pk)
+            xb.pattern_forward(refl, sf[2], grid, y)
+
+    with torch.cuda.stream(s):
+        step()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        step()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
 
 
 def timed(p: Pipeline, steps, warmup, graph):
@@ -257,6 +298,7 @@ def main():
 
     mx = res["mixed"]
     n_c = batch.n_crystals
+    dbl_ms = None if args.no_doublet else doublet_ms(batch)
     value = n_c / (mx["ms"] * 1e-3)
     eval_terms = mx["terms"] // 2 if mx["p"].xb.friedel else mx["terms"]
     achieved = eval_terms / (mx["sf_ms"] * 1e-3)
@@ -286,6 +328,10 @@ def main():
         "sf_terms_per_s": round(mx["terms"] / (mx["ms"] * 1e-3), 1),
         "stages_ms": mx["stages"],
         "host_plan_ms": round(mx["p"].plan_ms, 3),
+        "kalpha_doublet": None if dbl_ms is None else {
+            "ms_per_step": round(dbl_ms, 6), "patterns_per_s": round(n_c / (dbl_ms * 1e-3), 1),
+            "step": "Cu K-alpha1 + K-alpha2: enumerate, structure factors, merge, 4001-point pattern per line "
+                    "(no adjoint)"},
         "autotune": None if mx["p"].split is None else {
             "split_atoms_forward": mx["p"].split[0], "split_atoms_adjoint": mx["p"].split[1],
             "ms": round(mx["p"].tune_ms, 1)},

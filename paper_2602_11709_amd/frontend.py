@@ -1,0 +1,146 @@
+"""Calculator front-end over plain arrays, with X-ray tube doublets.
+
+The paper's calculator (Section 2, Fig. 1) takes a structure (lattice,
+fractional coordinates, species, occupancies, thermal factors), a wavelength,
+a 2theta range and a ``scaled`` flag, and returns the peaks with their 2theta,
+intensity, hkl lists and multiplicities.  ``get_pattern`` offers that call
+for one structure given as arrays, ``get_patterns`` for a whole
+``CrystalBatch``; both run on the GPU library (enumeration, structure
+factors, sort and merge).  A wavelength is a number in Angstrom or the name of
+an emission line; a doublet name ("CuKa12", "MoKa12") computes the K-alpha1
+and K-alpha2 lines separately, weights K-alpha2 by ``KA2_RATIO`` and lists the
+peaks of both lines in one 2theta-ordered pattern, scaled together.
+``broadened_pattern`` does the same on a grid (the sum of the two lines'
+broadened patterns).
+
+The hkl list of a peak holds its member reflections (every enumerated hkl,
+Friedel mates included), not families of symmetry-equivalent reflections.
+"""
+
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional, Sequence, Union
+
+import numpy as np
+
+from .synth import CrystalBatch
+
+# K-alpha1 and K-alpha2 emission lines (Angstrom; Deslattes et al., Rev. Mod.
+# Phys. 75, 35 (2003)); K-alpha is their 2:1 intensity-weighted mean.
+KA2_RATIO = 0.5
+_LINES = {"Cu": (1.5405929, 1.5444274), "Mo": (0.7093171, 0.7135900)}
+WAVELENGTHS = {}
+for _el, (_a1, _a2) in _LINES.items():
+    WAVELENGTHS[_el + "Ka1"] = _a1
+    WAVELENGTHS[_el + "Ka2"] = _a2
+    WAVELENGTHS[_el + "Ka"] = (_a1 + KA2_RATIO * _a2) / (1.0 + KA2_RATIO)
+
+
+def lines_of(wavelength: Union[float, str]):
+    """[(wavelength in Angstrom, intensity weight, line label)] of a wavelength spec."""
+    if isinstance(wavelength, str):
+        if wavelength.endswith("Ka12") and wavelength[:-4] in _LINES:
+            a1, a2 = _LINES[wavelength[:-4]]
+            return [(a1, 1.0, "a1"), (a2, KA2_RATIO, "a2")]
+        if wavelength in WAVELENGTHS:
+            return [(WAVELENGTHS[wavelength], 1.0, "")]
+        raise ValueError(f"unknown wavelength {wavelength!r}; known: {sorted(WAVELENGTHS)} and "
+                         f"{[e + 'Ka12' for e in _LINES]}")
+    lam = float(wavelength)
+    if not lam > 0.0:
+        raise ValueError("wavelength must be > 0")
+    return [(lam, 1.0, "")]
+
+
+@dataclasses.dataclass
+class DiffractionPattern:
+    """Peaks of one structure in ascending 2theta."""
+
+    x: np.ndarray        # 2theta (degrees)
+    y: np.ndarray        # intensity (0-100 when scaled)
+    mult: np.ndarray     # member reflections per peak
+    d_hkls: np.ndarray   # interplanar spacing (Angstrom)
+    hkls: list           # per peak: list of (h, k, l) of its members, in (2theta, h, k, l) order
+    line: np.ndarray     # per peak: emission line label ("" for a single line)
+
+
+def structure_batch(lattice: Sequence[float], frac, species, sf_coeff, occ=None, bfac=None,
+                    two_theta_range=(0.0, 90.0), merge_tol: float = 1e-5) -> CrystalBatch:
+    """A one-crystal CrystalBatch from plain arrays (validated here)."""
+    lat = np.asarray(lattice, dtype=np.float64).reshape(6)
+    frac = np.asarray(frac, dtype=np.float64).reshape(-1, 3)
+    n = frac.shape[0]
+    species = np.asarray(species, dtype=np.int32).reshape(n)
+    coeff = np.asarray(sf_coeff, dtype=np.float64).reshape(-1, 9)
+    occ = np.ones(n) if occ is None else np.asarray(occ, dtype=np.float64).reshape(n)
+    bfac = np.zeros(n) if bfac is None else np.asarray(bfac, dtype=np.float64).reshape(n)
+    if n and (species.min() < 0 or species.max() >= coeff.shape[0]):
+        raise ValueError("species index outside the coefficient table")
+    t0, t1 = (float(two_theta_range[0]), float(two_theta_range[1]))
+    if not (0.0 <= t0 < t1 < 180.0):
+        raise ValueError("two_theta_range must satisfy 0 <= min < max < 180")
+    return CrystalBatch("structure", lat[None, :].copy(), np.array([0, n], np.int64), frac, species, occ, bfac,
+                        coeff, 1.0, np.array([t0]), np.array([t1]), merge_tol)
+
+
+def get_patterns(batch: CrystalBatch, wavelength: Union[float, str] = "CuKa", scaled: bool = True,
+                 precision: str = "mixed", device="cuda") -> list:
+    """Peaks of every crystal of ``batch`` (its own wavelength is replaced by
+    ``wavelength``), one DiffractionPattern per crystal."""
+    from .api import simulate
+    parts = []
+    for lam, weight, label in lines_of(wavelength):
+        res = simulate(dataclasses.replace(batch, wavelength=lam), precision=precision, device=device)
+        parts.append((res, weight, label))
+    out = []
+    for c in range(batch.n_crystals):
+        xs, ys, ms, ds, hk, ls = [], [], [], [], [], []
+        for res, weight, label in parts:
+            rs, ps = res.crystal(c)
+            tt = res.pk_two_theta[ps]
+            xs.append(tt)
+            ys.append(weight * res.pk_intensity[ps])
+            ms.append(res.pk_mult[ps])
+            ls.append(np.full(len(tt), label))
+            for f, m in zip(res.pk_first[ps], res.pk_mult[ps]):
+                members = res.perm[f:f + m]
+                hk.append([tuple(int(v) for v in res.hkl[i]) for i in members])
+                ds.append(1.0 / np.sqrt(res.q[members[0]]))
+        x = np.concatenate(xs) if xs else np.zeros(0)
+        order = np.argsort(x, kind="stable")
+        y = np.concatenate(ys)[order]
+        if scaled and len(y) and y.max() > 0:
+            y = 100.0 * y / y.max()
+        out.append(DiffractionPattern(x=x[order], y=y, mult=np.concatenate(ms)[order],
+                                      d_hkls=np.asarray(ds, dtype=np.float64)[order] if ds else np.zeros(0),
+                                      hkls=[hk[i] for i in order], line=np.concatenate(ls)[order]))
+    return out
+
+
+def get_pattern(lattice, frac, species, sf_coeff, occ=None, bfac=None, wavelength: Union[float, str] = "CuKa",
+                scaled: bool = True, two_theta_range=(0.0, 90.0), merge_tol: float = 1e-5,
+                precision: str = "mixed", device="cuda") -> DiffractionPattern:
+    """Peaks of one structure given as arrays: lattice (a, b, c, alpha, beta,
+    gamma), fractional coordinates [N, 3], species rows of ``sf_coeff``
+    ([S, 9]: a1..a4, b1..b4, c), occupancies and B factors (default 1 and 0)."""
+    b = structure_batch(lattice, frac, species, sf_coeff, occ, bfac, two_theta_range, merge_tol)
+    return get_patterns(b, wavelength, scaled, precision, device)[0]
+
+
+def broadened_pattern(batch: CrystalBatch, grid, wavelength: Union[float, str] = "CuKa",
+                      precision: str = "mixed", device="cuda"):
+    """[n_crystals, n_points] broadened pattern of ``batch`` on ``grid``
+    (api.Grid): the weighted sum over the wavelength's emission lines."""
+    import torch
+    from .api import XrdBatch
+    y = None
+    for lam, weight, _ in lines_of(wavelength):
+        xb = XrdBatch(dataclasses.replace(batch, wavelength=lam), precision=precision, device=device,
+                      grid_capacity=grid.n_points)
+        refl = xb.enumerate()
+        _, _, I = xb.structure_factors(refl)
+        part = xb.pattern_forward(refl, I, grid)
+        y = weight * part if y is None else y + weight * part
+    torch.cuda.synchronize()
+    return y

@@ -1,0 +1,44 @@
+"""Calculator front-end, host side: emission lines and the argument checks
+made before any GPU work."""
+
+import numpy as np
+import pytest
+
+from paper_2602_11709_amd import frontend, synth
+
+
+def test_emission_lines():
+    for el in ("Cu", "Mo"):
+        a1, a2, ka = (frontend.WAVELENGTHS[el + s] for s in ("Ka1", "Ka2", "Ka"))
+        assert a1 < ka < a2
+        assert ka == pytest.approx((a1 + frontend.KA2_RATIO * a2) / (1 + frontend.KA2_RATIO), rel=1e-15)
+    # the weighted Cu K-alpha is the conventional 1.5418 A to within 1e-4 A
+    assert abs(frontend.WAVELENGTHS["CuKa"] - 1.5418) < 1e-4
+    assert frontend.lines_of("CuKa12") == [(frontend.WAVELENGTHS["CuKa1"], 1.0, "a1"),
+                                           (frontend.WAVELENGTHS["CuKa2"], frontend.KA2_RATIO, "a2")]
+    assert frontend.lines_of(1.2) == [(1.2, 1.0, "")]
+    assert frontend.lines_of("MoKa") == [(frontend.WAVELENGTHS["MoKa"], 1.0, "")]
+    for bad in ("XxKa", "CuKb", -1.0, 0.0):
+        with pytest.raises(ValueError):
+            frontend.lines_of(bad)
+
+
+def test_structure_batch_from_arrays():
+    rs = synth.rocksalt()
+    b = frontend.structure_batch(rs.lattice[0], rs.frac, rs.species, rs.sf_coeff, rs.occ, rs.bfac, (5.0, 80.0))
+    assert b.n_crystals == 1 and b.n_atoms == rs.n_atoms
+    assert b.two_theta_min[0] == 5.0 and b.two_theta_max[0] == 80.0
+    np.testing.assert_array_equal(b.frac, rs.frac)
+    d = frontend.structure_batch(rs.lattice[0], rs.frac, rs.species, rs.sf_coeff)
+    assert np.all(d.occ == 1.0) and np.all(d.bfac == 0.0)
+
+
+@pytest.mark.parametrize("kw", [dict(two_theta_range=(10.0, 5.0)), dict(two_theta_range=(0.0, 180.0)),
+                                dict(species_shift=100), dict(frac_shape=(2, 2))])
+def test_structure_batch_rejects(kw):
+    rs = synth.rocksalt()
+    species = rs.species + kw.get("species_shift", 0)
+    frac = rs.frac if "frac_shape" not in kw else np.zeros(kw["frac_shape"])
+    with pytest.raises(ValueError):
+        frontend.structure_batch(rs.lattice[0], frac, species, rs.sf_coeff,
+                                 two_theta_range=kw.get("two_theta_range", (0.0, 90.0)))
