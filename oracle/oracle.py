@@ -23,7 +23,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 __all__ = [
     "build", "cell", "q_of", "two_theta", "lp", "fsc", "enumerate_hkl",
     "structure_factors", "sort_order", "merge", "broaden", "OracleCrystal",
-    "pattern", "pattern_batch", "broadened", "loss",
+    "pattern", "pattern_batch", "broadened", "loss", "march_dollase", "splitmix64", "gauss", "noise",
 ]
 
 
@@ -98,6 +98,14 @@ def _get():
         lib.orc_pattern_batch.restype = None
         lib.orc_free_crystal.argtypes = [C.POINTER(_Crystal)]
         lib.orc_free_crystal.restype = None
+        lib.orc_march_dollase.argtypes = [_dp, C.c_int, C.c_int, C.c_int, _dp, C.c_double]
+        lib.orc_march_dollase.restype = C.c_double
+        lib.orc_splitmix64.argtypes = [C.c_uint64, C.c_uint64]
+        lib.orc_splitmix64.restype = C.c_uint64
+        lib.orc_gauss.argtypes = [C.c_uint64, C.c_uint64]
+        lib.orc_gauss.restype = C.c_double
+        lib.orc_noise.argtypes = [C.c_long, C.c_long, C.c_uint64, C.c_double, C.c_double, _dp]
+        lib.orc_noise.restype = None
         _lib = lib
     return _lib
 
@@ -314,3 +322,28 @@ def loss(batch, targets, t0, dt, npts, sigma, window, crystals=None):
         tot += float(np.dot(d, d))
         cnt += npts
     return tot / cnt
+
+
+# ---- augmentation of ML training patterns -----------------------------------
+
+def march_dollase(gs, h, k, l, hp, r):
+    """March-Dollase preferred-orientation factor of reflection (h, k, l)."""
+    return _get().orc_march_dollase(_f64(gs), int(h), int(k), int(l), _f64(hp), float(r))
+
+
+def splitmix64(seed, j):
+    """Output j (>= 1) of SplitMix64 seeded with ``seed``."""
+    return int(_get().orc_splitmix64(int(seed) & (2**64 - 1), int(j) & (2**64 - 1)))
+
+
+def gauss(seed, n):
+    """Standard normal variate n of stream ``seed``."""
+    return _get().orc_gauss(int(seed) & (2**64 - 1), int(n))
+
+
+def noise(y, seed, rel, abs_):
+    """y [n_c, n_pts] with noise added (a new array)."""
+    out = np.array(y, dtype=np.float64, order="C", copy=True)
+    n_c, n_pts = out.shape
+    _get().orc_noise(n_c, n_pts, int(seed) & (2**64 - 1), float(rel), float(abs_), out)
+    return out

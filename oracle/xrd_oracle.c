@@ -31,6 +31,7 @@
  * (no contraction, so every product and sum is rounded as written).
  */
 #include <math.h>
+#include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -354,4 +355,68 @@ void orc_pattern_batch(long nc, const double *lattice, const long *atom_offset,
         orc_pattern(lattice + 6 * c, lambda, tmin[c], tmax[c], tol, threshold, a1 - a0,
                     frac + 3 * a0, species + a0, occ + a0, bfac + a0, coeff, out + c);
     }
+}
+
+/* ---- augmentation of ML training patterns ------------------------------ */
+/*
+ * The paper's motivation (Section 1) is training data for ML models, built
+ * from simulated patterns modified with experimental effects such as
+ * preferred orientation and noise.  These are the plain definitions of two
+ * such effects.
+ */
+
+/* u^T G* v with G* given as [11, 22, 33, 12, 13, 23]. */
+static double orc_dot_gs(const double gs[6], const double u[3], const double v[3])
+{
+    return gs[0] * u[0] * v[0] + gs[1] * u[1] * v[1] + gs[2] * u[2] * v[2]
+         + gs[3] * (u[0] * v[1] + u[1] * v[0]) + gs[4] * (u[0] * v[2] + u[2] * v[0])
+         + gs[5] * (u[1] * v[2] + u[2] * v[1]);
+}
+
+/* March-Dollase preferred-orientation factor (Dollase, J. Appl. Cryst. 19
+ * (1986) 267) of reflection h for the preferred direction hp (a reciprocal-
+ * lattice vector in hkl components) and March parameter r:
+ *   cos(alpha) = h^T G* hp / (|h| |hp|),  |v| = sqrt(v^T G* v),
+ *   P = (r^2 cos^2(alpha) + sin^2(alpha) / r)^(-3/2).
+ * r = 1 is a random powder (P = 1). */
+double orc_march_dollase(const double gs[6], int h, int k, int l, const double hp[3], double r)
+{
+    const double hv[3] = {(double)h, (double)k, (double)l};
+    const double c = orc_dot_gs(gs, hv, hp) / (sqrt(orc_dot_gs(gs, hv, hv)) * sqrt(orc_dot_gs(gs, hp, hp)));
+    const double c2 = c * c;
+    return pow(r * r * c2 + (1.0 - c2) / r, -1.5);
+}
+
+/* SplitMix64 (Steele, Lea and Flood, OOPSLA 2014): the j-th output (j >= 1)
+ * of the generator seeded with ``seed`` is mix(seed + j * 0x9e3779b97f4a7c15)
+ * (arithmetic mod 2^64), mix being the generator's finaliser. */
+uint64_t orc_splitmix64(uint64_t seed, uint64_t j)
+{
+    uint64_t z = seed + j * 0x9e3779b97f4a7c15ULL;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+/* Standard normal variate number ``n`` of stream ``seed``: outputs 2n+1 and
+ * 2n+2 of SplitMix64 give uniforms u = (top 53 bits + 1/2) 2^-53 in (0, 1),
+ * and the Box-Muller transform sqrt(-2 ln u1) cos(2 pi u2). */
+double orc_gauss(uint64_t seed, uint64_t n)
+{
+    const double u1 = ((double)(orc_splitmix64(seed, 2 * n + 1) >> 11) + 0.5) * 0x1p-53;
+    const double u2 = ((double)(orc_splitmix64(seed, 2 * n + 2) >> 11) + 0.5) * 0x1p-53;
+    return sqrt(-2.0 * log(u1)) * cos(2.0 * ORC_PI * u2);
+}
+
+/* Noise on broadened patterns y [n_c][n_pts], in place:
+ *   y += (rel sqrt(max(y, 0)) + abs) z,  z = orc_gauss(seed, c n_pts + g)
+ * (a counting-statistics term and a flat background term). */
+void orc_noise(long n_c, long n_pts, uint64_t seed, double rel, double abs_, double *y)
+{
+    for (long c = 0; c < n_c; ++c)
+        for (long g = 0; g < n_pts; ++g) {
+            const long i = c * n_pts + g;
+            const double v = y[i];
+            y[i] = v + (rel * sqrt(v > 0.0 ? v : 0.0) + abs_) * orc_gauss(seed, (uint64_t)i);
+        }
 }

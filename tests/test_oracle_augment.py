@@ -1,0 +1,77 @@
+"""Pins of the oracle's augmentation functions (preferred orientation and
+noise): closed forms, the March-Dollase normalisation over the sphere, the
+published SplitMix64 sequence and the moments of the normal variates."""
+
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def cubic_gs(a=4.0):
+    return np.array([1 / a**2, 1 / a**2, 1 / a**2, 0.0, 0.0, 0.0])
+
+
+@pytest.mark.parametrize("r", [0.3, 0.7, 1.0, 1.6])
+def test_march_dollase_closed_forms(r):
+    gs = cubic_gs()
+    # parallel: P = r^-3; perpendicular: P = r^(3/2); r = 1: no texture
+    assert oracle.march_dollase(gs, 2, 0, 0, [1, 0, 0], r) == pytest.approx(r**-3, rel=1e-14)
+    assert oracle.march_dollase(gs, 0, 3, 0, [1, 0, 0], r) == pytest.approx(r**1.5, rel=1e-14)
+    assert oracle.march_dollase(gs, 1, 1, 0, [1, 0, 0], 1.0) == pytest.approx(1.0, rel=1e-14)
+    # 45 degrees in a cubic cell: cos^2 = 1/2
+    assert oracle.march_dollase(gs, 1, 1, 0, [1, 0, 0], r) == pytest.approx((0.5 * r * r + 0.5 / r) ** -1.5,
+                                                                           rel=1e-14)
+    # antiparallel equals parallel; the factor depends on direction only
+    assert oracle.march_dollase(gs, -2, 0, 0, [1, 0, 0], r) == pytest.approx(r**-3, rel=1e-14)
+    assert oracle.march_dollase(gs, 1, 0, 0, [5, 0, 0], r) == pytest.approx(r**-3, rel=1e-14)
+
+
+def test_march_dollase_metric():
+    """In a non-orthogonal cell the angle comes from G*: for a hexagonal cell
+    (gamma = 120) the reciprocal axes a* and b* meet at 60 degrees."""
+    _, gs, _ = oracle.cell([3.0, 3.0, 5.0, 90.0, 90.0, 120.0])
+    r = 0.6
+    want = (r * r * 0.25 + 0.75 / r) ** -1.5
+    assert oracle.march_dollase(gs, 0, 1, 0, [1, 0, 0], r) == pytest.approx(want, rel=1e-12)
+
+
+@pytest.mark.parametrize("r", [0.5, 1.4])
+def test_march_dollase_is_normalised(r):
+    """The March-Dollase distribution averages to 1 over the sphere; the
+    lattice directions of a cubic cell inside a large ball sample it evenly."""
+    gs = cubic_gs()
+    hp = np.array([1.0, 2.0, 2.0])
+    n = 24
+    vals = [oracle.march_dollase(gs, h, k, l, hp, r)
+            for h in range(-n, n + 1) for k in range(-n, n + 1) for l in range(-n, n + 1)
+            if 0 < h * h + k * k + l * l <= n * n]
+    assert np.mean(vals) == pytest.approx(1.0, abs=3e-3)
+
+
+def test_splitmix64_published_sequence():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "splitmix64_seed0.txt")) if not l.startswith("#")]
+    for j, v in rows:
+        assert oracle.splitmix64(0, int(j)) == int(v, 16)
+
+
+def test_gauss_moments_and_determinism():
+    z = np.array([oracle.gauss(12345, n) for n in range(200000)])
+    assert abs(z.mean()) < 0.01
+    assert z.var() == pytest.approx(1.0, abs=0.01)
+    assert np.mean(np.abs(z) < 1.0) == pytest.approx(0.6827, abs=0.005)
+    # the fourth moment of a standard normal is 3
+    assert np.mean(z**4) == pytest.approx(3.0, abs=0.06)
+    assert oracle.gauss(12345, 7) == z[7] and oracle.gauss(12346, 7) != z[7]
+
+
+def test_noise_definition():
+    y = np.abs(np.random.default_rng(3).normal(size=(3, 50))) * 10
+    out = oracle.noise(y, 99, 0.2, 0.05)
+    z = np.array([oracle.gauss(99, i) for i in range(y.size)]).reshape(y.shape)
+    np.testing.assert_allclose(out, y + (0.2 * np.sqrt(y) + 0.05) * z, rtol=1e-15, atol=0)
+    np.testing.assert_array_equal(oracle.noise(y, 99, 0.0, 0.0), y)
