@@ -201,6 +201,24 @@ def doublet_ms(batch, reps=20):
     return (time.perf_counter() - t0) * 1e3 / reps
 
 
+def augment_ms(p: Pipeline):
+    """Device time of the ML augmentations on the workload's reflections and
+    patterns (after every other measurement: they change the buffers)."""
+    import torch
+    from paper_2602_11709_amd import capi
+    n_c = p.xb.n_crystals
+    g = torch.Generator().manual_seed(11)
+    hp = torch.randn(n_c, 3, generator=g, dtype=torch.float64).cuda()
+    mr = (0.5 + torch.rand(n_c, generator=g, dtype=torch.float64)).cuda()
+    torch.cuda.synchronize()
+    po = p.time_call(lambda: capi.xrd_preferred_orientation(p.xb.handle, p.xb.ws, p.refl.c(), hp.data_ptr(),
+                                                            mr.data_ptr(), p.sf[2].data_ptr()), 20)
+    nz = p.time_call(lambda: capi.xrd_pattern_noise(p.xb.handle, p.y.shape[1], 12345, 0.05, 0.01,
+                                                    p.y.data_ptr()), 20)
+    return {"preferred_orientation_ms": round(po, 5), "noise_ms": round(nz, 5),
+            "noise_points": int(p.y.numel())}
+
+
 def timed(p: Pipeline, steps, warmup, graph):
     torch = p.torch
     for _ in range(warmup):
@@ -299,6 +317,7 @@ def main():
     mx = res["mixed"]
     n_c = batch.n_crystals
     dbl_ms = None if args.no_doublet else doublet_ms(batch)
+    aug = augment_ms(mx["p"])
     value = n_c / (mx["ms"] * 1e-3)
     eval_terms = mx["terms"] // 2 if mx["p"].xb.friedel else mx["terms"]
     achieved = eval_terms / (mx["sf_ms"] * 1e-3)
@@ -328,6 +347,7 @@ def main():
         "sf_terms_per_s": round(mx["terms"] / (mx["ms"] * 1e-3), 1),
         "stages_ms": mx["stages"],
         "host_plan_ms": round(mx["p"].plan_ms, 3),
+        "augmentation": aug,
         "kalpha_doublet": None if dbl_ms is None else {
             "ms_per_step": round(dbl_ms, 6), "patterns_per_s": round(n_c / (dbl_ms * 1e-3), 1),
             "step": "Cu K-alpha1 + K-alpha2: enumerate, structure factors, merge, 4001-point pattern per line "

@@ -214,6 +214,32 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
  * forward and adjoint S (INT32_MAX: no split). */
 int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out);
 
+/* Experimental effects for ML training patterns (paper, Section 1: the
+ * simulated patterns of ML training sets are modified with effects such as
+ * preferred orientation and noise).
+ *
+ * Preferred orientation (March-Dollase; Dollase, J. Appl. Cryst. 19 (1986)
+ * 267): multiplies each reflection's intensity I (in place, [refl_capacity])
+ * by P = (r^2 cos^2(alpha) + sin^2(alpha) / r)^(-3/2), where
+ * cos(alpha) = h^T G* hp / (|h| |hp|) and |v| = sqrt(v^T G* v).  hp (DEVICE
+ * [n_crystals*3]) is each crystal's preferred direction as a reciprocal-
+ * lattice vector in hkl components (need not be integer); march_r (DEVICE
+ * [n_crystals]) its March parameter (1: random powder, < 1 plates, > 1
+ * needles).  A crystal with march_r <= 0 or a zero hp is left unchanged.
+ * Apply it between xrd_structure_factors and xrd_merge_peaks or
+ * xrd_pattern_forward. */
+int xrd_preferred_orientation(xrd_batch *b, void *ws, const xrd_refl *r, const double *hp,
+                              const double *march_r, double *I);
+
+/* Noise on broadened patterns y (DEVICE [n_crystals*n_points], in place):
+ * y += (rel sqrt(max(y, 0)) + abs) z, a counting-statistics term and a flat
+ * term, with z the standard normal variate number n = c n_points + g of the
+ * stream ``seed``: outputs 2n+1 and 2n+2 of SplitMix64 (Steele, Lea and
+ * Flood, OOPSLA 2014) seeded with ``seed`` give u1, u2 = (top 53 bits + 1/2)
+ * 2^-53, and z = sqrt(-2 ln u1) cos(2 pi u2) (Box-Muller).  The same seed
+ * gives the same noise.  1 <= n_points <= grid_capacity; rel, abs >= 0. */
+int xrd_pattern_noise(xrd_batch *b, int64_t n_points, uint64_t seed, double rel, double abs, double *y);
+
 /* Wait for the batch's stream and copy refl_offset and peak_offset
  * ([n_crystals+1] each; either may be NULL) to host memory. */
 int xrd_read_counts(xrd_batch *b, const xrd_refl *r, const xrd_peaks *p,

@@ -203,6 +203,23 @@ class XrdBatch:
         this batch) and keep the fastest; returns (forward, adjoint) thresholds."""
         return capi.xrd_autotune(self.handle, self.ws, refl.c())
 
+    def preferred_orientation(self, refl: Reflections, I: torch.Tensor, hp, march_r) -> torch.Tensor:
+        """March-Dollase texture applied to I in place; hp [n_crystals, 3]
+        (hkl components) and march_r [n_crystals], arrays or tensors."""
+        f64 = dict(dtype=torch.float64, device=self.device)
+        self._hp = torch.as_tensor(np.asarray(hp, dtype=np.float64).reshape(self.n_crystals, 3), **f64).contiguous()
+        self._mr = torch.as_tensor(np.asarray(march_r, dtype=np.float64).reshape(self.n_crystals), **f64).contiguous()
+        capi.xrd_preferred_orientation(self.handle, self.ws, refl.c(), self._hp.data_ptr(), self._mr.data_ptr(),
+                                       I.data_ptr())
+        return I
+
+    def noise(self, y: torch.Tensor, seed: int, rel: float, abs_: float) -> torch.Tensor:
+        """Seeded noise added to the broadened patterns y in place."""
+        if y.dtype != torch.float64 or not y.is_contiguous() or y.shape[0] != self.n_crystals:
+            raise ValueError("y must be a contiguous float64 [n_crystals, n_points] tensor")
+        capi.xrd_pattern_noise(self.handle, y.shape[1], seed, rel, abs_, y.data_ptr())
+        return y
+
     def merge(self, refl: Reflections, I: torch.Tensor, peaks: Optional[Peaks] = None) -> Peaks:
         peaks = peaks or self.new_peaks()
         capi.xrd_merge_peaks(self.handle, self.ws, refl.c(), I.data_ptr(), peaks.c())

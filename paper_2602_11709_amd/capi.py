@@ -77,6 +77,8 @@ SIGNATURES = {
     "xrd_pattern_forward": ([_vp, _vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_grid), _vp], C.c_int),
     "xrd_pattern_backward": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(xrd_grid), _vp, _vp, _vp, _vp], C.c_int),
     "xrd_autotune": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(C.c_int32)], C.c_int),
+    "xrd_preferred_orientation": ([_vp, _vp, C.POINTER(xrd_refl), _vp, _vp, _vp], C.c_int),
+    "xrd_pattern_noise": ([_vp, C.c_int64, C.c_uint64, C.c_double, C.c_double, _vp], C.c_int),
     "xrd_read_counts": ([_vp, C.POINTER(xrd_refl), C.POINTER(xrd_peaks), _vp, _vp], C.c_int),
     "xrd_batch_destroy": ([_vp], None),
     "xrd_last_error": ([], C.c_char_p),
@@ -148,6 +150,14 @@ def xrd_autotune(batch, ws: int, refl: xrd_refl):
     out = (C.c_int32 * 2)()
     check(lib().xrd_autotune(batch, ws, C.byref(refl), out))
     return int(out[0]), int(out[1])
+
+
+def xrd_preferred_orientation(batch, ws: int, refl: xrd_refl, hp: int, march_r: int, I: int):
+    check(lib().xrd_preferred_orientation(batch, ws, C.byref(refl), hp, march_r, I))
+
+
+def xrd_pattern_noise(batch, n_points: int, seed: int, rel: float, abs_: float, y: int):
+    check(lib().xrd_pattern_noise(batch, int(n_points), int(seed) & (2**64 - 1), float(rel), float(abs_), y))
 
 
 def xrd_read_counts(batch, refl, peaks, host_refl_offset, host_peak_offset):

@@ -852,6 +852,31 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
   return XRD_OK;
 }
 
+int xrd_preferred_orientation(xrd_batch *b, void *ws, const xrd_refl *r, const double *hp, const double *march_r,
+                              double *I) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  if (int e = check_refl(r)) return e;
+  if (!I || (b->desc.n_crystals > 0 && (!hp || !march_r)))
+    return fail(XRD_ERR_INVALID_ARG, "hp, march_r and I must be non-NULL");
+  const WsLayout &L = b->ws;
+  launch_march_dollase(at<HChunk>(ws, L.peak_chunks), (int64_t)b->peak_chunks.size(), at<CrystalPlan>(ws, L.plan),
+                       r->refl_offset, r->h, r->k, r->l, hp, march_r, I, stream_of(b));
+  b->last_ws = ws;
+  return hip_check("preferred_orientation");
+}
+
+int xrd_pattern_noise(xrd_batch *b, int64_t n_points, uint64_t seed, double rel, double abs, double *y) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (!y) return fail(XRD_ERR_INVALID_ARG, "y is NULL");
+  if (n_points < 1 || n_points > b->grid_cap)
+    return fail(XRD_ERR_INVALID_ARG, "n_points must be in [1, grid_capacity]");
+  if (!(rel >= 0.0) || !(abs >= 0.0) || !std::isfinite(rel) || !std::isfinite(abs))
+    return fail(XRD_ERR_INVALID_ARG, "rel and abs must be finite and >= 0");
+  launch_noise(b->desc.n_crystals * n_points, seed, rel, abs, y, stream_of(b));
+  return hip_check("pattern_noise");
+}
+
 int xrd_read_counts(xrd_batch *b, const xrd_refl *r, const xrd_peaks *p, int64_t *host_refl_offset,
                     int64_t *host_peak_offset) {
   if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");

@@ -251,6 +251,12 @@ void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_ite
                     const double *q, const double *ga, const double *gb, const AtomRec *atoms,
                     const SpeciesRun *runs, const int32_t *run_count, const double *coeff, const CoeffF *coeff_f,
                     int tile, int runs_cap, double *part, hipStream_t s);
+// Preferred orientation (March-Dollase factor on I, in place; blocks from
+// the peak chunk table) and noise on broadened patterns (in place).
+void launch_march_dollase(const HChunk *chunks, int64_t n_chunks, const CrystalPlan *plan,
+                          const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
+                          const double *hp, const double *march_r, double *inten, hipStream_t s);
+void launch_noise(int64_t total, uint64_t seed, double rel, double abs_, double *y, hipStream_t s);
 // Atom gradients reduced over their partial rows and scattered to the
 // caller's order, and, in the same launch, dL/d(lattice) of every crystal
 // from its per-tile dL/dG* rows (written by launch_sf_bw).

@@ -1,0 +1,111 @@
+"""Preferred orientation and noise on the GPU against the oracle's
+definitions, element by element, and a textured pattern end to end."""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_11709_amd import synth
+from tests.test_gpu_forward import ragged_batch
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2602_11709_amd import capi
+    capi.lib()
+
+
+def texture(n_c, seed=5):
+    rng = np.random.default_rng(seed)
+    hp = rng.normal(size=(n_c, 3))
+    r = rng.uniform(0.4, 1.8, n_c)
+    return hp, r
+
+
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_march_dollase_per_reflection(precision):
+    from paper_2602_11709_amd.api import XrdBatch
+    b = ragged_batch()
+    hp, r = texture(b.n_crystals)
+    r[2] = 1.0          # random powder: unchanged
+    r[4] = -1.0         # switched off
+    hp[5] = 0.0         # no direction: switched off
+    hp[0] = [0.0, 0.0, 1.0]  # an integer direction
+    xb = XrdBatch(b, precision=precision)
+    refl = xb.enumerate()
+    _, _, I = xb.structure_factors(refl)
+    before = I.clone()
+    xb.preferred_orientation(refl, I, hp, r)
+    torch.cuda.synchronize()
+    ro, _ = xb.read_counts(refl)
+    n = int(ro[-1])
+    I0, I1 = before[:n].cpu().numpy(), I[:n].cpu().numpy()
+    hkl = np.stack([refl.h[:n].cpu().numpy(), refl.k[:n].cpu().numpy(), refl.l[:n].cpu().numpy()], axis=1)
+    for c in range(b.n_crystals):
+        sl = slice(int(ro[c]), int(ro[c + 1]))
+        if sl.stop == sl.start:
+            continue
+        if c in (2, 4, 5):
+            np.testing.assert_allclose(I1[sl], I0[sl], rtol=1e-15 if c == 2 else 0)
+            continue
+        _, gs, _ = oracle.cell(b.lattice[c])
+        P = np.array([oracle.march_dollase(gs, *m, hp[c], r[c]) for m in hkl[sl]])
+        np.testing.assert_allclose(I1[sl], I0[sl] * P, rtol=1e-12, err_msg=f"crystal {c}")
+
+
+def test_textured_pattern_end_to_end():
+    """Texture applied before the merge: every peak carries the sum of its
+    members' textured intensities."""
+    from paper_2602_11709_amd.api import XrdBatch
+    b = synth.random_triclinic(91, 8, atoms_hi=30)
+    hp, r = texture(b.n_crystals, 6)
+    xb = XrdBatch(b, precision="fp64")
+    refl = xb.enumerate()
+    _, _, I = xb.structure_factors(refl)
+    xb.preferred_orientation(refl, I, hp, r)
+    pk = xb.merge(refl, I)
+    ro, po = xb.read_counts(refl, pk)
+    pi = pk.intensity[:int(po[-1])].cpu().numpy()
+    for c in range(b.n_crystals):
+        o = oracle.pattern(b, c)
+        _, gs, _ = oracle.cell(b.lattice[c])
+        P = np.array([oracle.march_dollase(gs, *m, hp[c], r[c]) for m in o.hkl])
+        want = np.array([np.sum((o.inten * P)[o.perm[f:f + m]]) for f, m in zip(o.pk_first, o.pk_mult)])
+        got = pi[int(po[c]):int(po[c + 1])]
+        assert len(got) == len(want)
+        np.testing.assert_allclose(got, want, rtol=1e-10, atol=1e-12 * max(want.max(), 1e-300))
+
+
+def test_noise_matches_definition_and_seed():
+    from paper_2602_11709_amd.api import Grid, XrdBatch
+    b = synth.random_triclinic(92, 5, atoms_hi=30)
+    grid = Grid(10.0, 0.02, 4001, 0.1, 8.0)
+    xb = XrdBatch(b, precision="mixed", grid_capacity=grid.n_points)
+    refl = xb.enumerate()
+    _, _, I = xb.structure_factors(refl)
+    y = xb.pattern_forward(refl, I, grid)
+    torch.cuda.synchronize()
+    y0 = y.cpu().numpy().copy()
+    seed = 0xDEADBEEF12345
+    xb.noise(y, seed, 0.05, 0.01)
+    torch.cuda.synchronize()
+    got = y.cpu().numpy()
+    want = oracle.noise(y0, seed, 0.05, 0.01)
+    scale = 0.05 * np.sqrt(np.maximum(y0, 0)) + 0.01
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12 * float(np.max(np.abs(want))))
+    # the added noise has unit-normal shape once divided by its scale
+    z = (got - y0) / scale
+    assert abs(z.mean()) < 0.02 and abs(z.var() - 1.0) < 0.03
+    # same seed, same noise; another seed, other noise
+    y2 = torch.as_tensor(y0).cuda()
+    xb.noise(y2, seed, 0.05, 0.01)
+    torch.cuda.synchronize()
+    assert np.array_equal(y2.cpu().numpy(), got)
+    y3 = torch.as_tensor(y0).cuda()
+    xb.noise(y3, seed + 1, 0.05, 0.01)
+    torch.cuda.synchronize()
+    assert not np.array_equal(y3.cpu().numpy(), got)
