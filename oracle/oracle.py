@@ -24,6 +24,7 @@ __all__ = [
     "build", "cell", "q_of", "two_theta", "lp", "fsc", "enumerate_hkl",
     "structure_factors", "sort_order", "merge", "broaden", "OracleCrystal",
     "pattern", "pattern_batch", "broadened", "loss", "march_dollase", "splitmix64", "gauss", "noise",
+    "broaden_caglioti",
 ]
 
 
@@ -106,6 +107,9 @@ def _get():
         lib.orc_gauss.restype = C.c_double
         lib.orc_noise.argtypes = [C.c_long, C.c_long, C.c_uint64, C.c_double, C.c_double, _dp]
         lib.orc_noise.restype = None
+        lib.orc_broaden_caglioti.argtypes = [C.c_long, _dp, _dp, C.c_double, C.c_double, C.c_long, C.c_double,
+                                             C.c_double, C.c_double, C.c_double, _dp]
+        lib.orc_broaden_caglioti.restype = None
         _lib = lib
     return _lib
 
@@ -347,3 +351,12 @@ def noise(y, seed, rel, abs_):
     n_c, n_pts = out.shape
     _get().orc_noise(n_c, n_pts, int(seed) & (2**64 - 1), float(rel), float(abs_), out)
     return out
+
+
+def broaden_caglioti(tt, inten, t0, dt, npts, U, V, W, window):
+    """Broadened pattern with Caglioti widths FWHM^2 = U tan^2 + V tan + W."""
+    y = np.zeros(npts)
+    n = len(tt)
+    _get().orc_broaden_caglioti(n, _f64(tt) if n else np.zeros(1), _f64(inten) if n else np.zeros(1),
+                                float(t0), float(dt), int(npts), float(U), float(V), float(W), float(window), y)
+    return y

@@ -420,3 +420,33 @@ void orc_noise(long n_c, long n_pts, uint64_t seed, double rel, double abs_, dou
             y[i] = v + (rel * sqrt(v > 0.0 ? v : 0.0) + abs_) * orc_gauss(seed, (uint64_t)i);
         }
 }
+
+/* Broadening with 2theta-dependent widths (Caglioti, Paoletti and Ricci,
+ * Nucl. Instrum. 3 (1958) 223): each reflection is a unit-area Gaussian of
+ *   FWHM^2 = U tan^2(theta) + V tan(theta) + W   (degrees^2, theta = 2theta / 2),
+ * sigma = FWHM / (2 sqrt(2 ln 2)), over the grid points with
+ * |x - 2theta| <= window sigma.  A reflection with FWHM^2 <= 0 adds nothing.
+ * With U = V = 0 this is orc_broaden with sigma = sqrt(W) / (2 sqrt(2 ln 2)). */
+void orc_broaden_caglioti(long nr, const double *tt, const double *inten, double t0, double dt, long npts,
+                          double U, double V, double W, double window, double *y)
+{
+    for (long g = 0; g < npts; ++g) y[g] = 0.0;
+    for (long r = 0; r < nr; ++r) {
+        const double t = tan(0.5 * tt[r] * ORC_PI / 180.0);
+        const double f2 = U * t * t + V * t + W;
+        if (!(f2 > 0.0)) continue;
+        const double sigma = sqrt(f2) / (2.0 * sqrt(2.0 * log(2.0)));
+        const double half = window * sigma;
+        const double norm = 1.0 / (sigma * sqrt(2.0 * ORC_PI));
+        long glo = (long)floor((tt[r] - half - t0) / dt) - 1;
+        long ghi = (long)ceil((tt[r] + half - t0) / dt) + 1;
+        if (glo < 0) glo = 0;
+        if (ghi > npts - 1) ghi = npts - 1;
+        for (long g = glo; g <= ghi; ++g) {
+            const double x = t0 + (double)g * dt;
+            const double d = x - tt[r];
+            if (fabs(d) > half) continue;
+            y[g] += inten[r] * norm * exp(-(d * d) / (2.0 * sigma * sigma));
+        }
+    }
+}

@@ -75,3 +75,35 @@ def test_noise_definition():
     z = np.array([oracle.gauss(99, i) for i in range(y.size)]).reshape(y.shape)
     np.testing.assert_allclose(out, y + (0.2 * np.sqrt(y) + 0.05) * z, rtol=1e-15, atol=0)
     np.testing.assert_array_equal(oracle.noise(y, 99, 0.0, 0.0), y)
+
+
+def test_caglioti_reduces_to_constant_width():
+    rng = np.random.default_rng(8)
+    tt = np.sort(rng.uniform(15, 80, 40))
+    inten = rng.uniform(0.5, 5, 40)
+    W = 0.04
+    sigma = np.sqrt(W) / (2 * np.sqrt(2 * np.log(2)))
+    a = oracle.broaden_caglioti(tt, inten, 10.0, 0.01, 8001, 0.0, 0.0, W, 8.0)
+    b = oracle.broaden(tt, inten, 10.0, 0.01, 8001, sigma, 8.0)
+    np.testing.assert_allclose(a, b, rtol=1e-13, atol=1e-13 * b.max())
+
+
+@pytest.mark.parametrize("tt0", [20.0, 70.0, 120.0])
+def test_caglioti_width_and_area(tt0):
+    """A single line: unit area times its intensity, and the full width at
+    half maximum of the formula (found on a fine grid)."""
+    U, V, W = 0.02, -0.01, 0.005
+    th = np.radians(tt0 / 2)
+    fwhm = np.sqrt(U * np.tan(th) ** 2 + V * np.tan(th) + W)
+    dt = 1e-4
+    n = int(2.0 / dt) + 1
+    t0 = tt0 - 1.0
+    y = oracle.broaden_caglioti([tt0], [3.0], t0, dt, n, U, V, W, 8.0)
+    assert np.sum(y) * dt == pytest.approx(3.0, rel=1e-6)
+    above = np.nonzero(y >= 0.5 * y.max())[0]
+    assert (above[-1] - above[0]) * dt == pytest.approx(fwhm, abs=2 * dt)
+
+
+def test_caglioti_skips_nonpositive_widths():
+    y = oracle.broaden_caglioti([30.0, 60.0], [1.0, 1.0], 10.0, 0.01, 8001, 0.0, 0.0, -0.1, 8.0)
+    assert not y.any()
