@@ -215,8 +215,11 @@ def augment_ms(p: Pipeline):
                                                             mr.data_ptr(), p.sf[2].data_ptr()), 20)
     nz = p.time_call(lambda: capi.xrd_pattern_noise(p.xb.handle, p.y.shape[1], 12345, 0.05, 0.01,
                                                     p.y.data_ptr()), 20)
+    # Caglioti widths of a laboratory diffractometer (FWHM 0.06-0.2 degrees over the range)
+    cg = p.time_call(lambda: capi.xrd_pattern_caglioti(p.xb.handle, p.xb.ws, p.refl.c(), p.sf[2].data_ptr(),
+                                                       p.grid.c(), 0.02, -0.005, 0.004, p.y.data_ptr()), 20)
     return {"preferred_orientation_ms": round(po, 5), "noise_ms": round(nz, 5),
-            "noise_points": int(p.y.numel())}
+            "caglioti_pattern_ms": round(cg, 5), "noise_points": int(p.y.numel())}
 
 
 def timed(p: Pipeline, steps, warmup, graph):

@@ -231,6 +231,18 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out);
 int xrd_preferred_orientation(xrd_batch *b, void *ws, const xrd_refl *r, const double *hp,
                               const double *march_r, double *I);
 
+/* Broadened pattern y [n_crystals * n_points] with widths that grow with
+ * angle (Caglioti, Paoletti and Ricci, Nucl. Instrum. 3 (1958) 223): each
+ * reflection adds a unit-area Gaussian of FWHM^2 = U tan^2(theta) +
+ * V tan(theta) + W (degrees^2, theta = 2theta / 2), sigma = FWHM /
+ * (2 sqrt(2 ln 2)), times its intensity, at the grid points with
+ * |x - 2theta| <= window_sigmas sigma; a reflection with FWHM^2 <= 0 adds
+ * nothing.  The grid's t0, dt, n_points and window_sigmas apply; its sigma is
+ * not used (any positive value).  Sums in double precision, each point over
+ * its reflections in 2theta order (deterministic); forward only. */
+int xrd_pattern_caglioti(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, const xrd_grid *g,
+                         double U, double V, double W, double *y);
+
 /* Noise on broadened patterns y (DEVICE [n_crystals*n_points], in place):
  * y += (rel sqrt(max(y, 0)) + abs) z, a counting-statistics term and a flat
  * term, with z the standard normal variate number n = c n_points + g of the

@@ -213,6 +213,14 @@ class XrdBatch:
                                        I.data_ptr())
         return I
 
+    def pattern_caglioti(self, refl: Reflections, I: torch.Tensor, grid: Grid, U: float, V: float, W: float,
+                         y=None) -> torch.Tensor:
+        """Broadened pattern with widths FWHM^2 = U tan^2 + V tan + W (grid.sigma unused)."""
+        if y is None:
+            y = torch.empty(self.n_crystals, grid.n_points, dtype=torch.float64, device=self.device)
+        capi.xrd_pattern_caglioti(self.handle, self.ws, refl.c(), I.data_ptr(), grid.c(), U, V, W, y.data_ptr())
+        return y
+
     def noise(self, y: torch.Tensor, seed: int, rel: float, abs_: float) -> torch.Tensor:
         """Seeded noise added to the broadened patterns y in place."""
         if y.dtype != torch.float64 or not y.is_contiguous() or y.shape[0] != self.n_crystals:

@@ -79,6 +79,8 @@ SIGNATURES = {
     "xrd_autotune": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(C.c_int32)], C.c_int),
     "xrd_preferred_orientation": ([_vp, _vp, C.POINTER(xrd_refl), _vp, _vp, _vp], C.c_int),
     "xrd_pattern_noise": ([_vp, C.c_int64, C.c_uint64, C.c_double, C.c_double, _vp], C.c_int),
+    "xrd_pattern_caglioti": ([_vp, _vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_grid), C.c_double, C.c_double,
+                              C.c_double, _vp], C.c_int),
     "xrd_read_counts": ([_vp, C.POINTER(xrd_refl), C.POINTER(xrd_peaks), _vp, _vp], C.c_int),
     "xrd_batch_destroy": ([_vp], None),
     "xrd_last_error": ([], C.c_char_p),
@@ -154,6 +156,11 @@ def xrd_autotune(batch, ws: int, refl: xrd_refl):
 
 def xrd_preferred_orientation(batch, ws: int, refl: xrd_refl, hp: int, march_r: int, I: int):
     check(lib().xrd_preferred_orientation(batch, ws, C.byref(refl), hp, march_r, I))
+
+
+def xrd_pattern_caglioti(batch, ws: int, refl: xrd_refl, I: int, grid: xrd_grid, U: float, V: float, W: float,
+                         y: int):
+    check(lib().xrd_pattern_caglioti(batch, ws, C.byref(refl), I, C.byref(grid), float(U), float(V), float(W), y))
 
 
 def xrd_pattern_noise(batch, n_points: int, seed: int, rel: float, abs_: float, y: int):

@@ -866,6 +866,24 @@ int xrd_preferred_orientation(xrd_batch *b, void *ws, const xrd_refl *r, const d
   return hip_check("preferred_orientation");
 }
 
+int xrd_pattern_caglioti(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, const xrd_grid *g, double U,
+                         double V, double W, double *y) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  if (int e = check_refl(r)) return e;
+  if (int e = check_grid(g)) return e;
+  if (!I || !y) return fail(XRD_ERR_INVALID_ARG, "I and y must be non-NULL");
+  if (!std::isfinite(U) || !std::isfinite(V) || !std::isfinite(W))
+    return fail(XRD_ERR_INVALID_ARG, "U, V and W must be finite");
+  ensure_sorted(b, ws, r);
+  const WsLayout &L = b->ws;
+  launch_broaden_caglioti(at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, r->refl_offset, b->desc.friedel != 0,
+                          at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), I, g->t0, g->dt, g->n_points, U, V,
+                          W, g->window_sigmas, y, stream_of(b));
+  b->last_ws = ws;
+  return hip_check("pattern_caglioti");
+}
+
 int xrd_pattern_noise(xrd_batch *b, int64_t n_points, uint64_t seed, double rel, double abs, double *y) {
   if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
   if (!y) return fail(XRD_ERR_INVALID_ARG, "y is NULL");

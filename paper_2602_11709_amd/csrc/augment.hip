@@ -17,6 +17,10 @@
 // the Box-Muller transform sqrt(-2 ln u1) cos(2 pi u2) gives z.  A counter
 // rather than a sequential state, so every point draws its own variate in
 // parallel and a seed fixes the result.
+//
+// Peak widths that grow with angle (Caglioti, Paoletti and Ricci, Nucl.
+// Instrum. 3 (1958) 223): the broadened pattern with FWHM^2 = U tan^2(theta)
+// + V tan(theta) + W per reflection instead of one width.
 #include <math.h>
 
 #include "xrd_internal.h"
@@ -87,7 +91,109 @@ __global__ __launch_bounds__(kThreads) void k_noise(int64_t total, uint64_t seed
   }
 }
 
+// Smallest i in [0, n] with keys[i] >= target (STRICT: keys[i] > target), or
+// n, for keys sorted ascending; every thread of the block calls it.  Each
+// round samples the remaining range at 256 evenly spaced positions and keeps
+// the stretch between the last sample below the target and the first one
+// above it, so a range of n keys takes about log_256(n) rounds.
+template <bool STRICT>
+__device__ int64_t block_lower_bound(const double *__restrict__ keys, int64_t n, double target) {
+  int64_t lo = 0, hi = n;  // the answer lies in [lo, hi]
+  while (hi > lo) {
+    const int64_t stride = (hi - lo + kThreads - 1) / kThreads;
+    const int64_t i = lo + (int64_t)threadIdx.x * stride;
+    const bool below = i < hi && (STRICT ? !(keys[i] > target) : keys[i] < target);
+    const int nb = __syncthreads_count(below);  // the samples below form a prefix
+    if (nb == 0) {
+      hi = lo;
+    } else {
+      const int64_t last = lo + (int64_t)(nb - 1) * stride;  // below the target
+      hi = min(hi, last + stride);
+      lo = last + 1;
+    }
+  }
+  return lo;
+}
+
+// Gaussian broadening with Caglioti widths, FWHM^2 = U tan^2(theta) +
+// V tan(theta) + W (degrees^2), sigma = FWHM / (2 sqrt(2 ln 2)), over the
+// points with |x - 2theta| <= window sigma; entries with FWHM^2 <= 0 add
+// nothing.  A block owns 256 consecutive grid points of one crystal (a thread
+// each): it finds the entries within the largest half-width of its points
+// (the crystal's widest line, from the width's maximum over its 2theta
+// range) by two searches over the sorted entries, stages them 256 at a time
+// in LDS with their weight, exponent scale and half-width, and every thread
+// sums its lines in 2theta order (double precision throughout).
+__global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
+    const CrystalPlan *__restrict__ plan, const int64_t *__restrict__ refl_offset, bool friedel,
+    const double *__restrict__ ent_key, const int32_t *__restrict__ ent_idx, const double *__restrict__ inten,
+    double t0, double dt, int64_t n, double U, double V, double W, double window, double *__restrict__ y) {
+  __shared__ double4 s_ent[kThreads];  // 2theta, weight, 1 / (2 sigma^2), half-width
+  const int64_t blocks_per = (n + kThreads - 1) / kThreads;
+  const int64_t c = blockIdx.x / blocks_per;
+  const int64_t p = (blockIdx.x % blocks_per) * kThreads + threadIdx.x;
+  const CrystalPlan &P = plan[c];
+  const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
+  const int64_t base = friedel ? r0 / 2 : r0, count = friedel ? (r1 - r0) / 2 : r1 - r0;
+  const double m = friedel ? 2.0 : 1.0;
+  const double rad = 3.14159265358979323846 / 360.0;  // degrees of 2theta to radians of theta
+  const double fw = 1.0 / (2.0 * sqrt(2.0 * log(2.0)));
+  // the widest line of the crystal: FWHM^2 is a quadratic in tan(theta), so
+  // its maximum over the crystal's range lies at an end or at the vertex
+  const double ta = tan(P.tmin * rad), tb = tan(P.tmax * rad);
+  auto f2 = [&](double t) { return (U * t + V) * t + W; };
+  double f2max = fmax(f2(ta), f2(tb));
+  if (U < 0.0) {
+    const double tv = -V / (2.0 * U);
+    if (tv > ta && tv < tb) f2max = fmax(f2max, f2(tv));
+  }
+  const double hmax = f2max > 0.0 ? window * sqrt(f2max) * fw : 0.0;
+  const int64_t p0 = (blockIdx.x % blocks_per) * kThreads;
+  const int64_t p1 = min(p0 + kThreads, n) - 1;
+  const double x0 = t0 + (double)p0 * dt, x1 = t0 + (double)p1 * dt;
+  const double *keys = ent_key + base;
+  const int64_t e0 = block_lower_bound<false>(keys, count, x0 - hmax);
+  const int64_t e1 = block_lower_bound<true>(keys, count, x1 + hmax);
+  const double x = t0 + (double)p * dt;
+  double acc = 0.0;
+  for (int64_t t0e = e0; t0e < e1; t0e += kThreads) {
+    const int64_t e = t0e + threadIdx.x;
+    __syncthreads();  // the previous tile has been read
+    if (e < e1) {
+      const double t = keys[e];
+      const double tn = tan(t * rad);
+      const double q = f2(tn);
+      double4 v = make_double4(t, 0.0, 0.0, -1.0);
+      if (q > 0.0) {
+        const double sigma = sqrt(q) * fw;
+        v.y = m * inten[ent_idx[base + e]] / (sigma * sqrt(2.0 * 3.14159265358979323846));
+        v.z = 1.0 / (2.0 * sigma * sigma);
+        v.w = window * sigma;
+      }
+      s_ent[threadIdx.x] = v;
+    }
+    __syncthreads();
+    const int ne = (int)min((int64_t)kThreads, e1 - t0e);
+    for (int j = 0; j < ne; ++j) {
+      const double4 v = s_ent[j];
+      const double d = x - v.x;
+      if (fabs(d) <= v.w) acc += v.y * exp(-(d * d) * v.z);
+    }
+  }
+  if (p < n) y[c * n + p] = acc;
+}
+
 }  // namespace
+
+void launch_broaden_caglioti(const CrystalPlan *plan, int64_t n_c, const int64_t *refl_offset, bool friedel,
+                             const double *ent_key, const int32_t *ent_idx, const double *inten, double t0,
+                             double dt, int64_t n, double U, double V, double W, double window, double *y,
+                             hipStream_t s) {
+  if (n_c <= 0 || n <= 0) return;
+  const int64_t blocks = n_c * ((n + kThreads - 1) / kThreads);
+  hipLaunchKernelGGL(k_broaden_caglioti, dim3((unsigned)blocks), dim3(kThreads), 0, s, plan, refl_offset, friedel,
+                     ent_key, ent_idx, inten, t0, dt, n, U, V, W, window, y);
+}
 
 void launch_march_dollase(const HChunk *chunks, int64_t n_chunks, const CrystalPlan *plan,
                           const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,

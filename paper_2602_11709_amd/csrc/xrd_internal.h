@@ -257,6 +257,12 @@ void launch_march_dollase(const HChunk *chunks, int64_t n_chunks, const CrystalP
                           const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
                           const double *hp, const double *march_r, double *inten, hipStream_t s);
 void launch_noise(int64_t total, uint64_t seed, double rel, double abs_, double *y, hipStream_t s);
+// Broadened pattern with Caglioti widths over the sorted entries (the
+// evaluated half under Friedel pairing, weight 2, else every reflection).
+void launch_broaden_caglioti(const CrystalPlan *plan, int64_t n_c, const int64_t *refl_offset, bool friedel,
+                             const double *ent_key, const int32_t *ent_idx, const double *inten, double t0,
+                             double dt, int64_t n, double U, double V, double W, double window, double *y,
+                             hipStream_t s);
 // Atom gradients reduced over their partial rows and scattered to the
 // caller's order, and, in the same launch, dL/d(lattice) of every crystal
 // from its per-tile dL/dG* rows (written by launch_sf_bw).

@@ -109,3 +109,31 @@ def test_noise_matches_definition_and_seed():
     xb.noise(y3, seed + 1, 0.05, 0.01)
     torch.cuda.synchronize()
     assert not np.array_equal(y3.cpu().numpy(), got)
+
+
+@pytest.mark.parametrize("precision,friedel", [("mixed", True), ("fp64", False)])
+def test_caglioti_pattern(precision, friedel):
+    """Widths growing with angle, against the oracle's broadening of the GPU's
+    own reflections and intensities, on crystals of every sort size (the
+    largest sorted in global memory) and a grid cut at both ends."""
+    from paper_2602_11709_amd.api import Grid, XrdBatch
+    b = ragged_batch()
+    grid = Grid(12.0, 0.017, 4501, 1.0, 8.0)
+    U, V, W = 0.03, -0.01, 0.004
+    xb = XrdBatch(b, precision=precision, friedel=friedel)
+    refl = xb.enumerate()
+    _, _, I = xb.structure_factors(refl)
+    y = xb.pattern_caglioti(refl, I, grid, U, V, W)
+    torch.cuda.synchronize()
+    ro, _ = xb.read_counts(refl)
+    n = int(ro[-1])
+    tt, Ih, yh = refl.two_theta[:n].cpu().numpy(), I[:n].cpu().numpy(), y.cpu().numpy()
+    for c in range(b.n_crystals):
+        sl = slice(int(ro[c]), int(ro[c + 1]))
+        want = oracle.broaden_caglioti(tt[sl], Ih[sl], grid.t0, grid.dt, grid.n_points, U, V, W, grid.window_sigmas)
+        err = np.max(np.abs(yh[c] - want)) / max(np.max(np.abs(want)), 1e-300)
+        assert err <= 1e-12, f"crystal {c}: {err:.3e}"
+    # repeat: bit for bit
+    y2 = xb.pattern_caglioti(refl, I, grid, U, V, W)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y2)
