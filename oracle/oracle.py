@@ -24,8 +24,11 @@ __all__ = [
     "build", "cell", "q_of", "two_theta", "lp", "fsc", "enumerate_hkl",
     "structure_factors", "sort_order", "merge", "broaden", "OracleCrystal",
     "pattern", "pattern_batch", "broadened", "loss", "march_dollase", "splitmix64", "gauss", "noise",
-    "broaden_caglioti",
+    "broaden_caglioti", "FAM_INDICES", "FAM_LATTICE", "is_hexagonal", "lattice_ops", "peak_families",
 ]
+
+FAM_INDICES = 0
+FAM_LATTICE = 1
 
 
 def build(force: bool = True) -> str:
@@ -110,6 +113,12 @@ def _get():
         lib.orc_broaden_caglioti.argtypes = [C.c_long, _dp, _dp, C.c_double, C.c_double, C.c_long, C.c_double,
                                              C.c_double, C.c_double, C.c_double, _dp]
         lib.orc_broaden_caglioti.restype = None
+        lib.orc_is_hexagonal.argtypes = [_dp]
+        lib.orc_is_hexagonal.restype = C.c_int
+        lib.orc_lattice_ops.argtypes = [_dp, C.c_long, _ip]
+        lib.orc_lattice_ops.restype = C.c_long
+        lib.orc_peak_families.argtypes = [_dp, C.c_int, C.c_long, _lp, _lp, _ip, _lp, _lp, _ip, _lp]
+        lib.orc_peak_families.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -360,3 +369,38 @@ def broaden_caglioti(tt, inten, t0, dt, npts, U, V, W, window):
     _get().orc_broaden_caglioti(n, _f64(tt) if n else np.zeros(1), _f64(inten) if n else np.zeros(1),
                                 float(t0), float(dt), int(npts), float(U), float(V), float(W), float(window), y)
     return y
+
+
+def is_hexagonal(lattice) -> bool:
+    return bool(_get().orc_is_hexagonal(_f64(lattice)))
+
+
+def lattice_ops(lattice):
+    """Point operations of the lattice (integer matrices, entries in {-1, 0, 1})."""
+    ops = np.zeros((48, 9), dtype=np.int32)
+    n = _get().orc_lattice_ops(_f64(lattice), 48, ops)
+    if n < 0:
+        raise ValueError("invalid cell or more than 48 operations")
+    return ops[:n].reshape(n, 3, 3).copy()
+
+
+def peak_families(lattice, rule, first, mult, hkl):
+    """Families of one crystal's peaks.  hkl [n, 3] in peak member order; peak p
+    owns positions first[p] .. first[p] + mult[p] - 1.  Returns (fam [n],
+    n_fam [n_peaks], label [n, 3], fam_mult [n]); family f of peak p sits at
+    position first[p] + f of label and fam_mult."""
+    first = np.ascontiguousarray(first, dtype=np.int64)
+    mult = np.ascontiguousarray(mult, dtype=np.int64)
+    hkl = np.ascontiguousarray(np.asarray(hkl).reshape(-1, 3), dtype=np.int32)
+    n = max(len(hkl), 1)
+    fam = np.full(n, -1, dtype=np.int64)
+    n_fam = np.zeros(max(len(first), 1), dtype=np.int64)
+    label = np.zeros((n, 3), dtype=np.int32)
+    fam_mult = np.zeros(n, dtype=np.int64)
+    rc = _get().orc_peak_families(_f64(lattice), int(rule), len(first), first if len(first) else np.zeros(1, np.int64),
+                                  mult if len(mult) else np.zeros(1, np.int64), hkl if len(hkl) else np.zeros((1, 3), np.int32),
+                                  fam, n_fam, label, fam_mult)
+    if rc:
+        raise ValueError("invalid cell or rule")
+    m = len(hkl)
+    return fam[:m], n_fam[:len(first)], label[:m], fam_mult[:m]

@@ -450,3 +450,169 @@ void orc_broaden_caglioti(long nr, const double *tt, const double *inten, double
         }
     }
 }
+
+/* ---- families of symmetry-equivalent reflections ------------------------ */
+/*
+ * The paper lists, among the steps moved to compiled code (Section 2), the
+ * grouping of symmetry-equivalent reflections, and its example output
+ * (Section 3) gives each merged peak a list of families, each with a
+ * multiplicity.  The input here carries no space group, so two equivalences
+ * are defined (a reading: the paper states neither):
+ *
+ *   ORC_FAM_INDICES  equal multisets of absolute index values, taken in the
+ *                    3-index form (h, k, l), or in the 4-index form
+ *                    (h, k, -(h + k), l) on a hexagonal lattice; the usual
+ *                    labelling convention of the Python calculator the paper
+ *                    targets;
+ *   ORC_FAM_LATTICE  related by a point operation of the lattice: an integer
+ *                    matrix M with entries in {-1, 0, 1}, det M = +-1 and
+ *                    M^T G* M = G*, acting as hkl -> M hkl (so q is kept).
+ *
+ * Metric equalities hold within ORC_FAM_TOL times the largest diagonal entry
+ * of G*.  A lattice is hexagonal when G*11 = G*22, G*13 = G*23 = 0 and
+ * G*12 = G*11 / 2 (a = b, alpha = beta = 90, gamma = 120 degrees).
+ *
+ * Within a peak, members are taken in the peak's member order; a member
+ * joins the family of the earliest earlier member equivalent to it, or opens
+ * a new family.  A family's label is its lexicographically largest (h, k, l)
+ * member and its multiplicity the number of its members.
+ */
+#define ORC_FAM_INDICES 0
+#define ORC_FAM_LATTICE 1
+#define ORC_FAM_TOL 1e-6
+
+static int orc_fam_close(double x, double y, double scale)
+{
+    return fabs(x - y) <= ORC_FAM_TOL * scale;
+}
+
+static double orc_fam_scale(const double gs[6])
+{
+    double s = gs[0];
+    if (gs[1] > s) s = gs[1];
+    if (gs[2] > s) s = gs[2];
+    return s;
+}
+
+int orc_is_hexagonal(const double lat[6])
+{
+    double gs[6];
+    if (orc_cell(lat, NULL, gs, NULL)) return 0;
+    const double s = orc_fam_scale(gs);
+    return orc_fam_close(gs[0], gs[1], s) && orc_fam_close(gs[4], 0.0, s) && orc_fam_close(gs[5], 0.0, s)
+        && orc_fam_close(gs[3], 0.5 * gs[0], s);
+}
+
+/* Every point operation of the lattice, found by trying all 3^9 matrices with
+ * entries in {-1, 0, 1}; ops[n][9] row-major.  Returns their number (at most
+ * 48 for a lattice), or -1 if the cell is invalid or more than max_ops match. */
+long orc_lattice_ops(const double lat[6], long max_ops, int *ops)
+{
+    double gs[6];
+    if (orc_cell(lat, NULL, gs, NULL)) return -1;
+    const double G[3][3] = {{gs[0], gs[3], gs[4]}, {gs[3], gs[1], gs[5]}, {gs[4], gs[5], gs[2]}};
+    const double s = orc_fam_scale(gs);
+    long n = 0;
+    for (long code = 0; code < 19683; ++code) {
+        int M[3][3];
+        long c = code;
+        for (int e = 0; e < 9; ++e) { M[e / 3][e % 3] = (int)(c % 3) - 1; c /= 3; }
+        const long det = (long)M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1])
+                       - (long)M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0])
+                       + (long)M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+        if (det != 1 && det != -1) continue;
+        int keep = 1;
+        for (int i = 0; i < 3 && keep; ++i)
+            for (int j = 0; j < 3 && keep; ++j) {
+                double v = 0.0; /* (M^T G* M)_ij */
+                for (int p = 0; p < 3; ++p)
+                    for (int r = 0; r < 3; ++r) v += M[p][i] * G[p][r] * M[r][j];
+                keep = orc_fam_close(v, G[i][j], s);
+            }
+        if (!keep) continue;
+        if (n == max_ops) return -1;
+        for (int e = 0; e < 9; ++e) ops[n * 9 + e] = M[e / 3][e % 3];
+        ++n;
+    }
+    return n;
+}
+
+static int orc_fam_cmp_int(const void *a, const void *b)
+{
+    const int x = *(const int *)a, y = *(const int *)b;
+    return (x > y) - (x < y);
+}
+
+/* Whether reflections u and v are equivalent under the rule. */
+static int orc_fam_equiv(int rule, int hex, long n_ops, const int *ops, const int *u, const int *v)
+{
+    if (rule == ORC_FAM_INDICES) {
+        int a[4] = {abs(u[0]), abs(u[1]), abs(u[2]), abs(u[0] + u[1])};
+        int b[4] = {abs(v[0]), abs(v[1]), abs(v[2]), abs(v[0] + v[1])};
+        const int n = hex ? 4 : 3;
+        qsort(a, n, sizeof(int), orc_fam_cmp_int);
+        qsort(b, n, sizeof(int), orc_fam_cmp_int);
+        for (int i = 0; i < n; ++i)
+            if (a[i] != b[i]) return 0;
+        return 1;
+    }
+    for (long o = 0; o < n_ops; ++o) {
+        const int *M = ops + o * 9;
+        int same = 1;
+        for (int r = 0; r < 3 && same; ++r) same = M[r * 3] * u[0] + M[r * 3 + 1] * u[1] + M[r * 3 + 2] * u[2] == v[r];
+        if (same) return 1;
+    }
+    return 0;
+}
+
+static int orc_hkl_greater(const int *u, const int *v)
+{
+    if (u[0] != v[0]) return u[0] > v[0];
+    if (u[1] != v[1]) return u[1] > v[1];
+    return u[2] > v[2];
+}
+
+/* Families of the peaks of one crystal with lattice ``lat``.  hkl[n][3] lists
+ * the crystal's reflections in peak member order; peak p's members are
+ * positions first[p] .. first[p] + mult[p] - 1.  Writes, for every member
+ * position i, fam[i] = its family's number within its peak; for peak p,
+ * n_fam[p] families whose labels and multiplicities sit at positions
+ * first[p] + f of label[.][3] and fam_mult.  Returns 0, or 1 for an invalid
+ * cell, rule, or more than 48 lattice operations. */
+int orc_peak_families(const double lat[6], int rule, long n_peaks, const long *first, const long *mult,
+                      const int *hkl, long *fam, long *n_fam, int *label, long *fam_mult)
+{
+    int ops[48 * 9];
+    long n_ops = 0;
+    int hex = 0;
+    if (rule == ORC_FAM_LATTICE) {
+        n_ops = orc_lattice_ops(lat, 48, ops);
+        if (n_ops < 0) return 1;
+    } else if (rule == ORC_FAM_INDICES) {
+        double gs[6];
+        if (orc_cell(lat, NULL, gs, NULL)) return 1;
+        hex = orc_is_hexagonal(lat);
+    } else {
+        return 1;
+    }
+    for (long p = 0; p < n_peaks; ++p) {
+        const long b = first[p], m = mult[p];
+        long nf = 0;
+        for (long i = 0; i < m; ++i) {
+            const int *u = hkl + 3 * (b + i);
+            long f = -1;
+            for (long j = 0; j < i && f < 0; ++j)
+                if (orc_fam_equiv(rule, hex, n_ops, ops, hkl + 3 * (b + j), u)) f = fam[b + j];
+            if (f < 0) {
+                f = nf++;
+                fam_mult[b + f] = 0;
+                memcpy(label + 3 * (b + f), u, 3 * sizeof(int));
+            }
+            fam[b + i] = f;
+            fam_mult[b + f] += 1;
+            if (orc_hkl_greater(u, label + 3 * (b + f))) memcpy(label + 3 * (b + f), u, 3 * sizeof(int));
+        }
+        n_fam[p] = nf;
+    }
+    return 0;
+}
