@@ -222,6 +222,23 @@ def augment_ms(p: Pipeline):
             "caglioti_pattern_ms": round(cg, 5), "noise_points": int(p.y.numel())}
 
 
+def families_ms(p: Pipeline):
+    """Device time of the grouping of equivalent reflections over every merged
+    peak of the workload, per rule (outputs preallocated)."""
+    import torch
+    from paper_2602_11709_amd import capi
+    rc = max(p.xb.refl_capacity, 1)
+    dev = "cuda"
+    out = (torch.empty(rc, dtype=torch.int32, device=dev), torch.empty(rc, dtype=torch.int32, device=dev),
+           torch.empty(rc, dtype=torch.int64, device=dev), torch.empty(rc, dtype=torch.int32, device=dev))
+    ptrs = [t.data_ptr() for t in out]
+    res = {}
+    for name, rule in (("indices", 0), ("lattice", 1)):
+        res[name + "_ms"] = round(p.time_call(lambda: capi.xrd_peak_families(p.xb.handle, p.xb.ws, p.refl.c(),
+                                                                             p.pk.c(), rule, *ptrs), 20), 5)
+    return res
+
+
 def timed(p: Pipeline, steps, warmup, graph):
     torch = p.torch
     for _ in range(warmup):
@@ -320,6 +337,7 @@ def main():
     mx = res["mixed"]
     n_c = batch.n_crystals
     dbl_ms = None if args.no_doublet else doublet_ms(batch)
+    fam = families_ms(mx["p"])
     aug = augment_ms(mx["p"])
     value = n_c / (mx["ms"] * 1e-3)
     eval_terms = mx["terms"] // 2 if mx["p"].xb.friedel else mx["terms"]
@@ -350,6 +368,7 @@ def main():
         "sf_terms_per_s": round(mx["terms"] / (mx["ms"] * 1e-3), 1),
         "stages_ms": mx["stages"],
         "host_plan_ms": round(mx["p"].plan_ms, 3),
+        "peak_families": fam,
         "augmentation": aug,
         "kalpha_doublet": None if dbl_ms is None else {
             "ms_per_step": round(dbl_ms, 6), "patterns_per_s": round(n_c / (dbl_ms * 1e-3), 1),

@@ -231,6 +231,34 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out);
 int xrd_preferred_orientation(xrd_batch *b, void *ws, const xrd_refl *r, const double *hp,
                               const double *march_r, double *I);
 
+/* Equivalence rules of xrd_peak_families. */
+#define XRD_FAMILY_INDICES 0 /* equal multisets of |h|, |k|, |l|; of |h|, |k|, |h+k|, |l| on a
+                                hexagonal lattice (a = b, alpha = beta = 90, gamma = 120) */
+#define XRD_FAMILY_LATTICE 1 /* related by a point operation M of the lattice: hkl -> M hkl with
+                                M integer, entries in {-1, 0, 1}, det M = +-1, M^T G* M = G* */
+
+/* Families of symmetry-equivalent reflections in each merged peak (paper,
+ * Section 2: grouping of symmetry-equivalent reflections; Section 3: a
+ * peak's hkl list gives families with a multiplicity each).  The batch
+ * carries no space group, so ``rule`` picks the equivalence (XRD_FAMILY_*);
+ * metric equalities hold within 1e-6 of the largest diagonal entry of G*.
+ * Reads r's h, k, l and p's first, mult, perm and peak_offset from a
+ * completed xrd_merge_peaks.  Walking a peak's members in their order
+ * (positions first .. first + mult - 1 of perm), a member joins the family of
+ * an earlier equivalent member or opens the next family.  Outputs (DEVICE,
+ * caller-owned):
+ *   n_families [peak_capacity]: families of each peak;
+ *   family_of [refl_capacity]: at each member position, its family's number
+ *     within its peak (0-based);
+ *   family_label, family_mult [refl_capacity]: family f of the peak whose
+ *     first member sits at position first sits at position first + f: the
+ *     global reflection index of its lexicographically largest (h, k, l)
+ *     member, and its number of members.
+ * Positions of perm outside the kept peaks are left unchanged.  One thread
+ * per peak: cost grows with the square of the members per peak. */
+int xrd_peak_families(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_peaks *p, int32_t rule,
+                      int32_t *n_families, int32_t *family_of, int64_t *family_label, int32_t *family_mult);
+
 /* Broadened pattern y [n_crystals * n_points] with widths that grow with
  * angle (Caglioti, Paoletti and Ricci, Nucl. Instrum. 3 (1958) 223): each
  * reflection adds a unit-area Gaussian of FWHM^2 = U tan^2(theta) +

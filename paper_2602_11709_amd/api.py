@@ -228,6 +228,16 @@ class XrdBatch:
         capi.xrd_pattern_noise(self.handle, y.shape[1], seed, rel, abs_, y.data_ptr())
         return y
 
+    def families(self, refl: Reflections, peaks: Peaks, rule: int = 0):
+        """Families of equivalent reflections per peak (rule 0: indices, 1: lattice).
+        Returns (n_families [peak_cap] int32, family_of [refl_cap] int32,
+        family_label [refl_cap] int64, family_mult [refl_cap] int32)."""
+        dev, pc, rc = self.device, max(self.sizes.peak_capacity, 1), max(self.sizes.refl_capacity, 1)
+        out = (torch.zeros(pc, dtype=torch.int32, device=dev), torch.full((rc,), -1, dtype=torch.int32, device=dev),
+               torch.full((rc,), -1, dtype=torch.int64, device=dev), torch.zeros(rc, dtype=torch.int32, device=dev))
+        capi.xrd_peak_families(self.handle, self.ws, refl.c(), peaks.c(), rule, *(t.data_ptr() for t in out))
+        return out
+
     def merge(self, refl: Reflections, I: torch.Tensor, peaks: Optional[Peaks] = None) -> Peaks:
         peaks = peaks or self.new_peaks()
         capi.xrd_merge_peaks(self.handle, self.ws, refl.c(), I.data_ptr(), peaks.c())
@@ -281,6 +291,12 @@ class PatternResult:
     pk_mult: np.ndarray
     pk_first: np.ndarray
     perm: np.ndarray
+    # families of equivalent reflections (only with a family rule): per peak
+    # their number; at position first + f, family f's label (reflection
+    # index) and multiplicity
+    fam_n: Optional[np.ndarray] = None
+    fam_label: Optional[np.ndarray] = None
+    fam_mult: Optional[np.ndarray] = None
 
     def crystal(self, c):
         r0, r1 = int(self.refl_offset[c]), int(self.refl_offset[c + 1])
@@ -289,25 +305,29 @@ class PatternResult:
 
 
 def simulate(batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
-             rel_threshold: float = 0.0, device="cuda", autotune: bool = False) -> PatternResult:
+             rel_threshold: float = 0.0, device="cuda", autotune: bool = False,
+             family_rule: Optional[int] = None) -> PatternResult:
     """Enumerate, structure factors, merge for every crystal; host arrays back.
     With ``autotune`` the structure-factor split is tuned on the enumerated
-    reflections first."""
+    reflections first; with a ``family_rule`` (0: indices, 1: lattice) the
+    peaks' families of equivalent reflections come back too."""
     xb = XrdBatch(batch, precision=precision, friedel=friedel, rel_threshold=rel_threshold, device=device)
     refl = xb.enumerate()
     if autotune:
         xb.autotune(refl)
     A, B, I = xb.structure_factors(refl)
     pk = xb.merge(refl, I)
+    fam = xb.families(refl, pk, family_rule) if family_rule is not None else None
     ro, po = xb.read_counts(refl, pk)
     n, m = int(ro[-1]), int(po[-1])
     cpu = lambda t, k: t[:k].cpu().numpy()
+    extra = {} if fam is None else dict(fam_n=cpu(fam[0], m), fam_label=cpu(fam[2], n), fam_mult=cpu(fam[3], n))
     hkl = np.stack([cpu(refl.h, n), cpu(refl.k, n), cpu(refl.l, n)], axis=1).astype(np.int32)
     return PatternResult(refl_offset=ro, hkl=hkl, q=cpu(refl.q, n), two_theta=cpu(refl.two_theta, n),
                          lp=cpu(refl.lp, n), A=cpu(A, n).astype(np.float64), B=cpu(B, n).astype(np.float64),
                          I=cpu(I, n), peak_offset=po, pk_two_theta=cpu(pk.two_theta, m),
                          pk_intensity=cpu(pk.intensity, m), pk_scaled=cpu(pk.scaled, m), pk_mult=cpu(pk.mult, m),
-                         pk_first=cpu(pk.first, m), perm=cpu(pk.perm, n))
+                         pk_first=cpu(pk.first, m), perm=cpu(pk.perm, n), **extra)
 
 
 class _PatternFn(torch.autograd.Function):

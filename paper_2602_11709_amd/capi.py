@@ -79,6 +79,8 @@ SIGNATURES = {
     "xrd_autotune": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(C.c_int32)], C.c_int),
     "xrd_preferred_orientation": ([_vp, _vp, C.POINTER(xrd_refl), _vp, _vp, _vp], C.c_int),
     "xrd_pattern_noise": ([_vp, C.c_int64, C.c_uint64, C.c_double, C.c_double, _vp], C.c_int),
+    "xrd_peak_families": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(xrd_peaks), C.c_int32, _vp, _vp, _vp, _vp],
+                          C.c_int),
     "xrd_pattern_caglioti": ([_vp, _vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_grid), C.c_double, C.c_double,
                               C.c_double, _vp], C.c_int),
     "xrd_read_counts": ([_vp, C.POINTER(xrd_refl), C.POINTER(xrd_peaks), _vp, _vp], C.c_int),
@@ -156,6 +158,12 @@ def xrd_autotune(batch, ws: int, refl: xrd_refl):
 
 def xrd_preferred_orientation(batch, ws: int, refl: xrd_refl, hp: int, march_r: int, I: int):
     check(lib().xrd_preferred_orientation(batch, ws, C.byref(refl), hp, march_r, I))
+
+
+def xrd_peak_families(batch, ws: int, refl: xrd_refl, peaks: xrd_peaks, rule: int, n_families: int,
+                      family_of: int, family_label: int, family_mult: int):
+    check(lib().xrd_peak_families(batch, ws, C.byref(refl), C.byref(peaks), int(rule), n_families, family_of,
+                                  family_label, family_mult))
 
 
 def xrd_pattern_caglioti(batch, ws: int, refl: xrd_refl, I: int, grid: xrd_grid, U: float, V: float, W: float,

@@ -37,6 +37,7 @@ struct xrd_batch {
   std::vector<SfItem> sf_items, sf_items_bw;  // launch orders of the forward sum and the adjoint
   std::vector<BwItem> bw_items;
   std::vector<AbItem> ab_items;
+  std::vector<FamOps> fam_ops;  // lattice point operations per crystal
   int64_t n_atoms = 0, refl_cap = 0, half_cap = 0, n_bins = 0, run_cap = 0, part_rows = 0, partf_rows = 0;
   int64_t n_mid = 0;      // crystals whose reflection capacity exceeds 2 kSmallSort
   int64_t n_small = 0;    // crystals whose reflection capacity exceeds 2 kTinySort
@@ -111,6 +112,61 @@ bool reciprocal_metric(const double *lat, double gs[6]) {
 }
 
 int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Point operations of a lattice for the grouping of equivalent reflections:
+// integer matrices M with entries in {-1, 0, 1}, det M = +-1 and
+// M^T G* M = G* within 1e-6 of the largest diagonal entry of G*, acting as
+// hkl -> M hkl.  Column j of such an M is a vector v with v^T G* v = G*_jj,
+// so the search takes the candidate columns of each length first and then
+// the triples whose cross terms match.  Also flags a hexagonal lattice
+// (G*11 = G*22, G*13 = G*23 = 0, G*12 = G*11 / 2).
+FamOps family_ops(const double gs[6]) {
+  FamOps fo{};
+  const double G[3][3] = {{gs[0], gs[3], gs[4]}, {gs[3], gs[1], gs[5]}, {gs[4], gs[5], gs[2]}};
+  const double tol = 1e-6 * std::max(gs[0], std::max(gs[1], gs[2]));
+  auto close = [&](double x, double y) { return std::fabs(x - y) <= tol; };
+  auto form = [&](const int *u, const int *v) {
+    double s = 0.0;
+    for (int p = 0; p < 3; ++p)
+      for (int r = 0; r < 3; ++r) s += u[p] * G[p][r] * v[r];
+    return s;
+  };
+  int vec[26][3], nv = 0;
+  for (int a = -1; a <= 1; ++a)
+    for (int b = -1; b <= 1; ++b)
+      for (int c = -1; c <= 1; ++c)
+        if (a || b || c) {
+          vec[nv][0] = a;
+          vec[nv][1] = b;
+          vec[nv][2] = c;
+          ++nv;
+        }
+  std::vector<int> cand[3];
+  for (int j = 0; j < 3; ++j)
+    for (int v = 0; v < nv; ++v)
+      if (close(form(vec[v], vec[v]), G[j][j])) cand[j].push_back(v);
+  for (int x : cand[0])
+    for (int y : cand[1]) {
+      if (!close(form(vec[x], vec[y]), G[0][1])) continue;
+      for (int z : cand[2]) {
+        if (!close(form(vec[x], vec[z]), G[0][2]) || !close(form(vec[y], vec[z]), G[1][2])) continue;
+        const int *c0 = vec[x], *c1 = vec[y], *c2 = vec[z];  // columns of M
+        const int det = c0[0] * (c1[1] * c2[2] - c1[2] * c2[1]) - c1[0] * (c0[1] * c2[2] - c0[2] * c2[1]) +
+                        c2[0] * (c0[1] * c1[2] - c0[2] * c1[1]);
+        if (det != 1 && det != -1) continue;
+        if (fo.n_ops == 48) continue;  // a lattice has at most 48; tolerance artefacts beyond are dropped
+        uint32_t code = 0;
+        for (int r = 0; r < 3; ++r) {
+          code |= (uint32_t)(c0[r] + 1) << (6 * r);
+          code |= (uint32_t)(c1[r] + 1) << (6 * r + 2);
+          code |= (uint32_t)(c2[r] + 1) << (6 * r + 4);
+        }
+        fo.op[fo.n_ops++] = code;
+      }
+    }
+  fo.hex = close(gs[0], gs[1]) && close(gs[4], 0.0) && close(gs[5], 0.0) && close(gs[3], 0.5 * gs[0]);
+  return fo;
+}
 
 // Cut a crystal's half box into enumeration chunks: runs of consecutive rows
 // (the lexicographic row order of the device enumeration: (0, 0), (0, k) for
@@ -264,6 +320,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   b->desc.two_theta_max = b->tmax.data();
   b->n_atoms = n_atoms;
   b->plan.resize(nc);
+  b->fam_ops.resize(nc);
 
   const bool friedel = d->friedel != 0;
   const double lam = d->wavelength;
@@ -278,6 +335,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
       return fail(XRD_ERR_INVALID_CELL, "crystal " + std::to_string(c) + ": invalid cell");
     }
     for (int i = 0; i < 6; ++i) P.lat[i] = lat[i];
+    b->fam_ops[c] = family_ops(P.gs);
     P.tmin = b->tmin[c];
     P.tmax = b->tmax[c];
     const double gmax = 2.0 * std::sin(0.5 * P.tmax * kPi / 180.0) / lam;
@@ -493,6 +551,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.bw_part6 = take(48 * tiles_total);
   L.sf_deriv = d->keep_sf_derivs ? take((d->precision == XRD_MIXED ? 16 : 32) * rc) : -1;
   L.coeff_f = take((int64_t)sizeof(CoeffF) * d->n_species);
+  L.fam_ops = take((int64_t)sizeof(FamOps) * nc);
   L.total = o;
   *out = b;
   g_err.clear();
@@ -529,6 +588,7 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   if (e == hipSuccess) e = up(L.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
   if (e == hipSuccess) e = up(L.bw_items, b->bw_items.data(), sizeof(BwItem) * b->bw_items.size());
   if (e == hipSuccess) e = up(L.ab_items, b->ab_items.data(), sizeof(AbItem) * b->ab_items.size());
+  if (e == hipSuccess) e = up(L.fam_ops, b->fam_ops.data(), sizeof(FamOps) * b->fam_ops.size());
   if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("upload: ") + hipGetErrorString(e));
   launch_fill_i32(at<int32_t>(ws, L.err_flag), 1, 0, s);
   // pageable copies complete before return, but the tables stay owned by the
@@ -864,6 +924,23 @@ int xrd_preferred_orientation(xrd_batch *b, void *ws, const xrd_refl *r, const d
                        r->refl_offset, r->h, r->k, r->l, hp, march_r, I, stream_of(b));
   b->last_ws = ws;
   return hip_check("preferred_orientation");
+}
+
+int xrd_peak_families(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_peaks *p, int32_t rule,
+                      int32_t *n_families, int32_t *family_of, int64_t *family_label, int32_t *family_mult) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  if (int e = check_refl(r)) return e;
+  if (!p || !p->mult || !p->first || !p->perm || !p->peak_offset)
+    return fail(XRD_ERR_INVALID_ARG, "peak arrays must be non-NULL");
+  if (rule != XRD_FAMILY_INDICES && rule != XRD_FAMILY_LATTICE) return fail(XRD_ERR_INVALID_ARG, "unknown rule");
+  if (!n_families || !family_of || !family_label || !family_mult)
+    return fail(XRD_ERR_INVALID_ARG, "family arrays must be non-NULL");
+  launch_peak_families(at<FamOps>(ws, b->ws.fam_ops), p->peak_offset, b->desc.n_crystals, b->refl_cap, p->first,
+                       p->mult, p->perm, r->h, r->k, r->l, rule, n_families, family_of, family_label, family_mult,
+                       stream_of(b));
+  b->last_ws = ws;
+  return hip_check("peak_families");
 }
 
 int xrd_pattern_caglioti(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, const xrd_grid *g, double U,

@@ -75,6 +75,14 @@ static_assert(sizeof(AtomRec) == 48, "AtomRec layout");
 // the mixed-precision kernels evaluate them (64 bytes, one scalar load):
 //   f(s^2) = c + sum_i a_i 2^(nbl_i s^2),  df/ds^2 = sum_i nab_i 2^(nbl_i s^2),
 // with nbl_i = -b_i log2(e) and nab_i = -a_i b_i rounded once from double.
+// Point operations of one crystal's lattice for the grouping of equivalent
+// reflections: op[o] packs the 3x3 matrix M (entries in {-1, 0, 1}, row r,
+// column j at bits 6r + 2j as M_rj + 1); hex is 1 on a hexagonal lattice.
+struct alignas(16) FamOps {
+  int32_t n_ops, hex, pad[2];
+  uint32_t op[48];
+};
+
 struct alignas(16) CoeffF {
   float a[4], nbl[4], nab[4];
   float c, pad[3];
@@ -125,10 +133,17 @@ struct WsLayout {
   int64_t sf_deriv;  // kept (A, B, dA/ds^2, dB/ds^2) per reflection, or -1
   int64_t coeff_f;   // [n_species] CoeffF
   int64_t sf_items_bw;  // structure-factor items in the adjoint's launch order
+  int64_t fam_ops;      // [n_crystals] FamOps
   int64_t total;
 };
 
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
+
+// Families of equivalent reflections per merged peak (rule 0: indices, 1: lattice).
+void launch_peak_families(const FamOps *fam_ops, const int64_t *peak_offset, int64_t n_c, int64_t peak_cap,
+                          const int64_t *first, const int32_t *mult, const int64_t *perm, const int16_t *h,
+                          const int16_t *k, const int16_t *l, int rule, int32_t *n_fam, int32_t *fam_of,
+                          int64_t *fam_label, int32_t *fam_mult, hipStream_t s);
 void launch_fill_u64(uint64_t *p, int64_t n, uint64_t v, hipStream_t s);
 
 // Exclusive scan of int32 in[0, n) into int64 out[0, n] (out[n] = total).

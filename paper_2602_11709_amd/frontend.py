@@ -13,8 +13,14 @@ peaks of both lines in one 2theta-ordered pattern, scaled together.
 ``broadened_pattern`` does the same on a grid (the sum of the two lines'
 broadened patterns).
 
-The hkl list of a peak holds its member reflections (every enumerated hkl,
-Friedel mates included), not families of symmetry-equivalent reflections.
+A peak's ``hkls`` lists its families of symmetry-equivalent reflections
+(paper, Section 2: grouping of equivalent reflections; Section 3: each entry
+an hkl with a multiplicity), each as {"hkl": label, "multiplicity": m}, the
+label being the family's lexicographically largest member; ``family_rule``
+"indices" groups equal multisets of absolute indices (4-index form on
+hexagonal lattices), "lattice" groups reflections related by a point
+operation of the lattice.  ``members`` lists every member reflection
+(Friedel mates included) in (2theta, h, k, l) order.
 """
 
 from __future__ import annotations
@@ -59,10 +65,11 @@ class DiffractionPattern:
 
     x: np.ndarray        # 2theta (degrees)
     y: np.ndarray        # intensity (0-100 when scaled)
-    mult: np.ndarray     # member reflections per peak
+    mult: np.ndarray     # member reflections per peak (the sum of its family multiplicities)
     d_hkls: np.ndarray   # interplanar spacing (Angstrom)
-    hkls: list           # per peak: list of (h, k, l) of its members, in (2theta, h, k, l) order
+    hkls: list           # per peak: its families, [{"hkl": (h, k, l), "multiplicity": m}, ...]
     line: np.ndarray     # per peak: emission line label ("" for a single line)
+    members: list        # per peak: (h, k, l) of its members, in (2theta, h, k, l) order
 
 
 def structure_batch(lattice: Sequence[float], frac, species, sf_coeff, occ=None, bfac=None,
@@ -84,18 +91,24 @@ def structure_batch(lattice: Sequence[float], frac, species, sf_coeff, occ=None,
                         coeff, 1.0, np.array([t0]), np.array([t1]), merge_tol)
 
 
+FAMILY_RULES = {"indices": 0, "lattice": 1}
+
+
 def get_patterns(batch: CrystalBatch, wavelength: Union[float, str] = "CuKa", scaled: bool = True,
-                 precision: str = "mixed", device="cuda") -> list:
+                 precision: str = "mixed", device="cuda", family_rule: str = "indices") -> list:
     """Peaks of every crystal of ``batch`` (its own wavelength is replaced by
     ``wavelength``), one DiffractionPattern per crystal."""
     from .api import simulate
+    if family_rule not in FAMILY_RULES:
+        raise ValueError(f"family_rule must be one of {sorted(FAMILY_RULES)}")
     parts = []
     for lam, weight, label in lines_of(wavelength):
-        res = simulate(dataclasses.replace(batch, wavelength=lam), precision=precision, device=device)
+        res = simulate(dataclasses.replace(batch, wavelength=lam), precision=precision, device=device,
+                       family_rule=FAMILY_RULES[family_rule])
         parts.append((res, weight, label))
     out = []
     for c in range(batch.n_crystals):
-        xs, ys, ms, ds, hk, ls = [], [], [], [], [], []
+        xs, ys, ms, ds, hk, fm, ls = [], [], [], [], [], [], []
         for res, weight, label in parts:
             rs, ps = res.crystal(c)
             tt = res.pk_two_theta[ps]
@@ -103,9 +116,11 @@ def get_patterns(batch: CrystalBatch, wavelength: Union[float, str] = "CuKa", sc
             ys.append(weight * res.pk_intensity[ps])
             ms.append(res.pk_mult[ps])
             ls.append(np.full(len(tt), label))
-            for f, m in zip(res.pk_first[ps], res.pk_mult[ps]):
+            for f, m, nf in zip(res.pk_first[ps], res.pk_mult[ps], res.fam_n[ps]):
                 members = res.perm[f:f + m]
                 hk.append([tuple(int(v) for v in res.hkl[i]) for i in members])
+                fm.append([{"hkl": tuple(int(v) for v in res.hkl[res.fam_label[f + j]]),
+                            "multiplicity": int(res.fam_mult[f + j])} for j in range(nf)])
                 ds.append(1.0 / np.sqrt(res.q[members[0]]))
         x = np.concatenate(xs) if xs else np.zeros(0)
         order = np.argsort(x, kind="stable")
@@ -114,18 +129,19 @@ def get_patterns(batch: CrystalBatch, wavelength: Union[float, str] = "CuKa", sc
             y = 100.0 * y / y.max()
         out.append(DiffractionPattern(x=x[order], y=y, mult=np.concatenate(ms)[order],
                                       d_hkls=np.asarray(ds, dtype=np.float64)[order] if ds else np.zeros(0),
-                                      hkls=[hk[i] for i in order], line=np.concatenate(ls)[order]))
+                                      hkls=[fm[i] for i in order], line=np.concatenate(ls)[order],
+                                      members=[hk[i] for i in order]))
     return out
 
 
 def get_pattern(lattice, frac, species, sf_coeff, occ=None, bfac=None, wavelength: Union[float, str] = "CuKa",
                 scaled: bool = True, two_theta_range=(0.0, 90.0), merge_tol: float = 1e-5,
-                precision: str = "mixed", device="cuda") -> DiffractionPattern:
+                precision: str = "mixed", device="cuda", family_rule: str = "indices") -> DiffractionPattern:
     """Peaks of one structure given as arrays: lattice (a, b, c, alpha, beta,
     gamma), fractional coordinates [N, 3], species rows of ``sf_coeff``
     ([S, 9]: a1..a4, b1..b4, c), occupancies and B factors (default 1 and 0)."""
     b = structure_batch(lattice, frac, species, sf_coeff, occ, bfac, two_theta_range, merge_tol)
-    return get_patterns(b, wavelength, scaled, precision, device)[0]
+    return get_patterns(b, wavelength, scaled, precision, device, family_rule)[0]
 
 
 def broadened_pattern(batch: CrystalBatch, grid, wavelength: Union[float, str] = "CuKa",

@@ -42,3 +42,11 @@ def test_structure_batch_rejects(kw):
     with pytest.raises(ValueError):
         frontend.structure_batch(rs.lattice[0], frac, species, rs.sf_coeff,
                                  two_theta_range=kw.get("two_theta_range", (0.0, 90.0)))
+
+
+def test_family_rule_is_checked():
+    from paper_2602_11709_amd import frontend
+    import numpy as np
+    with pytest.raises(ValueError):
+        frontend.get_patterns(frontend.structure_batch([4, 4, 4, 90, 90, 90], np.zeros((1, 3)), [0],
+                                                       np.ones((1, 9))), family_rule="spacegroup")

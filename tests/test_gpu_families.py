@@ -1,0 +1,124 @@
+"""Families of symmetry-equivalent reflections per merged peak, GPU against
+the oracle's pairwise grouping of the same peaks (integer work: exact)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2602_11709_amd import synth
+from tests.test_gpu_forward import concat, ragged_batch
+
+pytestmark = pytest.mark.gpu
+
+LATTICES = [
+    [4.0, 4.0, 4.0, 90.0, 90.0, 90.0], [3.7, 3.7, 5.3, 90.0, 90.0, 90.0], [3.1, 3.1, 5.2, 90.0, 90.0, 120.0],
+    [4.1, 4.1, 4.1, 71.0, 71.0, 71.0], [3.1, 4.3, 5.7, 90.0, 90.0, 90.0], [3.1, 4.3, 5.7, 90.0, 101.0, 90.0],
+    [7.9, 7.9, 7.9, 90.0, 90.0, 90.0], [6.2, 6.2, 9.1, 90.0, 90.0, 120.0],
+]
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2602_11709_amd import capi
+    capi.lib()
+
+
+def symmetric_batch(seed=8):
+    """Cells of every lattice system (atoms at random sites, so only the
+    lattice is symmetric), then the ragged triclinic batch."""
+    rng = np.random.default_rng(seed)
+    rag = ragged_batch()
+    atoms = []
+    for _ in LATTICES:
+        n = int(rng.integers(1, 9))
+        atoms.append((rng.uniform(size=(n, 3)), rng.integers(0, rag.sf_coeff.shape[0], n), np.ones(n),
+                      rng.uniform(0.2, 1.0, n)))
+    sym = synth._assemble("sym", LATTICES, atoms, rag.sf_coeff, rag.wavelength, 5.0, 150.0)
+    return concat([sym, rag])
+
+
+def check_families(xb, b, rule):
+    refl = xb.enumerate()
+    _, _, I = xb.structure_factors(refl)
+    peaks = xb.merge(refl, I)
+    n_fam, fam_of, label, fmult = xb.families(refl, peaks, rule)
+    torch.cuda.synchronize()
+    ro, po = xb.read_counts(refl, peaks)
+    h = [t.cpu().numpy() for t in (refl.h, refl.k, refl.l)]
+    hkl = np.stack(h, axis=1).astype(np.int64)
+    perm, first, mult = peaks.perm.cpu().numpy(), peaks.first.cpu().numpy(), peaks.mult.cpu().numpy()
+    n_fam, fam_of, label, fmult = (t.cpu().numpy() for t in (n_fam, fam_of, label, fmult))
+    checked = 0
+    for c in range(b.n_crystals):
+        r0, r1, p0, p1 = int(ro[c]), int(ro[c + 1]), int(po[c]), int(po[c + 1])
+        if p1 == p0:
+            continue
+        f, m = first[p0:p1], mult[p0:p1].astype(np.int64)
+        assert f.min() >= r0 and (f + m).max() <= r1
+        members = hkl[perm[r0:r1]]
+        w_of, w_n, w_label, w_mult = oracle.peak_families(b.lattice[c], rule, f - r0, m, members)
+        assert np.array_equal(n_fam[p0:p1], w_n), f"crystal {c}: family counts"
+        covered = np.concatenate([np.arange(a, a + k) for a, k in zip(f, m)])
+        assert np.array_equal(fam_of[covered], w_of[covered - r0]), f"crystal {c}: family of members"
+        slots = np.concatenate([np.arange(a, a + k) for a, k in zip(f, w_n)])
+        assert np.array_equal(fmult[slots], w_mult[slots - r0]), f"crystal {c}: multiplicities"
+        assert np.array_equal(hkl[label[slots]], w_label[slots - r0]), f"crystal {c}: labels"
+        # a label is a member of its own peak
+        owner = np.repeat(np.arange(p1 - p0), w_n)
+        pos_of = np.empty(r1 - r0, np.int64)
+        pos_of[perm[r0:r1] - r0] = np.arange(r0, r1)
+        lp = pos_of[label[slots] - r0]
+        assert ((lp >= f[owner]) & (lp < f[owner] + m[owner])).all()
+        checked += int(w_n.sum())
+    return checked
+
+
+@pytest.mark.parametrize("precision,friedel", [("mixed", True), ("fp64", False)])
+@pytest.mark.parametrize("rule", [0, 1])
+def test_families_vs_oracle(precision, friedel, rule):
+    from paper_2602_11709_amd.api import XrdBatch
+    b = symmetric_batch()
+    xb = XrdBatch(b, precision=precision, friedel=friedel)
+    assert check_families(xb, b, rule) > 1000
+
+
+def test_cubic_multiplicities_on_gpu():
+    """The {100}, {110}, {111} lines of a cubic cell: one family each, of 6, 12
+    and 8 members, labelled (1,0,0), (1,1,0), (1,1,1)."""
+    from paper_2602_11709_amd.api import XrdBatch
+    rs = synth.rocksalt()
+    b = synth._assemble("sc", [[4.0, 4.0, 4.0, 90.0, 90.0, 90.0]],
+                        [(np.zeros((1, 3)), np.zeros(1, np.int32), np.ones(1), np.full(1, 0.5))],
+                        rs.sf_coeff, rs.wavelength, 5.0, 90.0)
+    xb = XrdBatch(b, precision="fp64")
+    refl = xb.enumerate()
+    _, _, I = xb.structure_factors(refl)
+    peaks = xb.merge(refl, I)
+    n_fam, _, label, fmult = xb.families(refl, peaks, 1)
+    torch.cuda.synchronize()
+    first = peaks.first.cpu().numpy()
+    hkl = np.stack([t.cpu().numpy() for t in (refl.h, refl.k, refl.l)], axis=1)
+    got = [(tuple(hkl[label.cpu().numpy()[first[p]]]), int(fmult.cpu().numpy()[first[p]]), int(n_fam[p]))
+           for p in range(3)]
+    assert got == [((1, 0, 0), 6, 1), ((1, 1, 0), 12, 1), ((1, 1, 1), 8, 1)]
+
+
+def test_families_full_workload():
+    """The 1024-crystal triclinic workload: every peak against the oracle."""
+    from paper_2602_11709_amd.api import XrdBatch
+    b = synth.triclinic_1024()
+    xb = XrdBatch(b, precision="mixed", friedel=True)
+    assert check_families(xb, b, 1) > 500_000
+
+
+def test_families_rejects_bad_rule():
+    from paper_2602_11709_amd.api import XrdBatch
+    from paper_2602_11709_amd.capi import XrdError
+    b = synth.rocksalt()
+    xb = XrdBatch(b, precision="fp64")
+    refl = xb.enumerate()
+    _, _, I = xb.structure_factors(refl)
+    peaks = xb.merge(refl, I)
+    with pytest.raises(XrdError):
+        xb.families(refl, peaks, 5)

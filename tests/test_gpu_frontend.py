@@ -44,28 +44,42 @@ def oracle_pattern(batch, c, wavelength, scaled=True):
         np.concatenate(ls)[order]
 
 
-def check(got, want, precision):
+def check(got, want, precision, lattice, rule="indices"):
     x, y, m, hk, d, ln = want
     np.testing.assert_allclose(got.x, x, rtol=0, atol=1e-9)
     np.testing.assert_array_equal(got.mult, m)
     np.testing.assert_array_equal(got.line, ln)
     # member sets: within a peak the members' 2theta may differ in the last
     # bits between the device and host evaluations, which can reorder them
-    assert [sorted(a) for a in got.hkls] == [sorted(b) for b in hk]
+    assert [sorted(a) for a in got.members] == [sorted(b) for b in hk]
+    # families: labels and multiplicities do not depend on the member order
+    code = frontend.FAMILY_RULES[rule]
+    for fams, mem in zip(got.hkls, hk):
+        _, n_fam, label, fmult = oracle.peak_families(lattice, code, [0], [len(mem)], mem)
+        want_f = sorted((tuple(int(v) for v in label[f]), int(fmult[f])) for f in range(int(n_fam[0])))
+        assert sorted((e["hkl"], e["multiplicity"]) for e in fams) == want_f
+    assert [sum(e["multiplicity"] for e in fams) for fams in got.hkls] == list(got.mult)
     np.testing.assert_allclose(got.d_hkls, d, rtol=1e-13)
     strong = y >= 1e-3 * (y.max() if len(y) else 0)
     tol = 1e-4 if precision == "mixed" else 1e-10
     np.testing.assert_allclose(got.y[strong], y[strong], rtol=tol)
 
 
-@pytest.mark.parametrize("wavelength", ["CuKa", "CuKa12", "MoKa12", 1.3])
+@pytest.mark.parametrize("wavelength,rule", [("CuKa", "indices"), ("CuKa12", "lattice"), ("MoKa12", "indices"),
+                                             (1.3, "lattice")])
 @pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_get_pattern_rocksalt(wavelength, precision):
+def test_get_pattern_rocksalt(wavelength, rule, precision):
     rs = synth.rocksalt()
     got = frontend.get_pattern(rs.lattice[0], rs.frac, rs.species, rs.sf_coeff, rs.occ, rs.bfac,
-                               wavelength=wavelength, two_theta_range=(0.0, 90.0), precision=precision)
+                               wavelength=wavelength, two_theta_range=(0.0, 90.0), precision=precision,
+                               family_rule=rule)
     b = frontend.structure_batch(rs.lattice[0], rs.frac, rs.species, rs.sf_coeff, rs.occ, rs.bfac, (0.0, 90.0))
-    check(got, oracle_pattern(b, 0, wavelength), precision)
+    check(got, oracle_pattern(b, 0, wavelength), precision, rs.lattice[0], rule)
+    # the first three lines of a cubic cell (the fcc-extinct ones are kept at
+    # zero intensity): one family each, of the textbook multiplicities
+    if wavelength == "CuKa":
+        assert got.hkls[:3] == [[{"hkl": (1, 0, 0), "multiplicity": 6}], [{"hkl": (1, 1, 0), "multiplicity": 12}],
+                                [{"hkl": (1, 1, 1), "multiplicity": 8}]]
     if isinstance(wavelength, str) and wavelength.endswith("12"):
         # each K-alpha2 peak lies slightly above its K-alpha1 partner (the longer
         # wavelength; partners near the range's top may fall outside it)
@@ -78,7 +92,7 @@ def test_get_patterns_batch_and_unscaled():
     b = ragged_batch()
     pats = frontend.get_patterns(b, "CuKa12", scaled=False)
     for c in (0, 3, 6, 13):
-        check(pats[c], oracle_pattern(b, c, "CuKa12", scaled=False), "mixed")
+        check(pats[c], oracle_pattern(b, c, "CuKa12", scaled=False), "mixed", b.lattice[c])
 
 
 def test_broadened_doublet():
