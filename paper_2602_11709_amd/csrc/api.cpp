@@ -936,7 +936,8 @@ int xrd_peak_families(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_peaks
   if (rule != XRD_FAMILY_INDICES && rule != XRD_FAMILY_LATTICE) return fail(XRD_ERR_INVALID_ARG, "unknown rule");
   if (!n_families || !family_of || !family_label || !family_mult)
     return fail(XRD_ERR_INVALID_ARG, "family arrays must be non-NULL");
-  launch_peak_families(at<FamOps>(ws, b->ws.fam_ops), p->peak_offset, b->desc.n_crystals, b->refl_cap, p->first,
+  launch_peak_families(at<HChunk>(ws, b->ws.peak_chunks), (int64_t)b->peak_chunks.size(), at<FamOps>(ws, b->ws.fam_ops),
+                       p->peak_offset, p->first,
                        p->mult, p->perm, r->h, r->k, r->l, rule, n_families, family_of, family_label, family_mult,
                        stream_of(b));
   b->last_ws = ws;

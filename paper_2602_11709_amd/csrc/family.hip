@@ -17,11 +17,13 @@
 //
 // One thread per peak: peaks hold a handful of members (a Friedel pair in a
 // triclinic cell, up to 48 for a general cubic reflection), and a thread
-// walks them in order with no synchronisation.  Each peak's families are
-// written into the peak's own stretch of member positions, in place: family
-// f of a peak is created by a member at position >= f, so the slot the
-// family's key (and later its label) occupies never holds anything still
-// needed.
+// walks them in order with no synchronisation.  Up to kRegFam families of a
+// peak live in registers (key, label, count); a peak with more families is
+// redone by the general walk, which keeps the families in the peak's own
+// stretch of the output arrays, in place: family f of a peak is created by a
+// member at position >= f, so the slot holding the family's key (and later
+// its label) never holds anything still needed.  Blocks follow the merge's
+// peak chunks (crystal, 1024 peak slots), the expected-filled ones first.
 #include "xrd_internal.h"
 
 namespace xrd {
@@ -70,31 +72,26 @@ __device__ __forceinline__ uint64_t lattice_key(int h, int k, int l, const FamOp
   return best;
 }
 
-__global__ void __launch_bounds__(kThreads) k_peak_families(
-    const FamOps *__restrict__ fam_ops, const int64_t *__restrict__ peak_offset, int64_t n_c,
-    const int64_t *__restrict__ first, const int32_t *__restrict__ mult, const int64_t *__restrict__ perm,
-    const int16_t *__restrict__ hh, const int16_t *__restrict__ kk, const int16_t *__restrict__ ll, int rule,
-    int32_t *__restrict__ n_fam, int32_t *__restrict__ fam_of, int64_t *__restrict__ fam_label,
-    int32_t *__restrict__ fam_mult) {
-  const int64_t p = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  if (p >= peak_offset[n_c]) return;
-  // crystal of peak p: the last c with peak_offset[c] <= p
-  int64_t lo = 0, hi = n_c;
-  while (hi - lo > 1) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (peak_offset[mid] <= p) lo = mid;
-    else hi = mid;
-  }
-  const FamOps &fo = fam_ops[lo];
-  const bool lattice = rule == 1;
+__device__ __forceinline__ uint64_t key_of(int h, int k, int l, bool lattice, const FamOps &fo) {
+  return lattice ? lattice_key(h, k, l, fo) : index_key(h, k, l, fo.hex != 0);
+}
+
+constexpr int kRegFam = 4;
+
+// The general walk over peak p's members (any number of families).
+__device__ void families_in_place(int64_t p, const FamOps &fo, bool lattice, const int64_t *__restrict__ first,
+                                  const int32_t *__restrict__ mult, const int64_t *__restrict__ perm,
+                                  const int16_t *__restrict__ hh, const int16_t *__restrict__ kk,
+                                  const int16_t *__restrict__ ll, int32_t *__restrict__ n_fam,
+                                  int32_t *__restrict__ fam_of, int64_t *__restrict__ fam_label,
+                                  int32_t *__restrict__ fam_mult) {
   const int64_t b = first[p];
   const int32_t m = mult[p];
   // pass 1: family of every member; keys of the open families at b + f
   int32_t nf = 0;
   for (int32_t i = 0; i < m; ++i) {
     const int64_t r = perm[b + i];
-    const int h = hh[r], k = kk[r], l = ll[r];
-    const uint64_t key = lattice ? lattice_key(h, k, l, fo) : index_key(h, k, l, fo.hex != 0);
+    const uint64_t key = key_of(hh[r], kk[r], ll[r], lattice, fo);
     int32_t f = 0;
     while (f < nf && (uint64_t)fam_label[b + f] != key) ++f;
     if (f == nf) {
@@ -121,16 +118,85 @@ __global__ void __launch_bounds__(kThreads) k_peak_families(
   n_fam[p] = nf;
 }
 
+__global__ void __launch_bounds__(kThreads) k_peak_families(
+    const HChunk *__restrict__ chunks, const FamOps *__restrict__ fam_ops, const int64_t *__restrict__ peak_offset,
+    const int64_t *__restrict__ first, const int32_t *__restrict__ mult, const int64_t *__restrict__ perm,
+    const int16_t *__restrict__ hh, const int16_t *__restrict__ kk, const int16_t *__restrict__ ll, int rule,
+    int32_t *__restrict__ n_fam, int32_t *__restrict__ fam_of, int64_t *__restrict__ fam_label,
+    int32_t *__restrict__ fam_mult) {
+  const HChunk ch = chunks[blockIdx.x];
+  const int64_t p1 = peak_offset[ch.crystal + 1];
+  const int64_t p0 = peak_offset[ch.crystal] + (int64_t)ch.chunk * kSortChunk;
+  if (p0 >= p1) return;
+  const FamOps &fo = fam_ops[ch.crystal];
+  const bool lattice = rule == 1;
+  for (int u = 0; u < kSortChunk / kThreads; ++u) {
+    const int64_t p = p0 + u * kThreads + threadIdx.x;
+    if (p >= p1) break;
+    const int64_t b = first[p];
+    const int32_t m = mult[p];
+    uint64_t fk[kRegFam] = {}, lab[kRegFam] = {};
+    int64_t li[kRegFam] = {};
+    int32_t cnt[kRegFam] = {};
+    int32_t nf = 0;
+    bool spill = false;
+    for (int32_t i = 0; i < m; ++i) {
+      const int64_t r = perm[b + i];
+      const int h = hh[r], k = kk[r], l = ll[r];
+      const uint64_t key = key_of(h, k, l, lattice, fo);
+      const uint64_t ph = pack_hkl(h, k, l);
+      int32_t f = -1;
+#pragma unroll
+      for (int g = 0; g < kRegFam; ++g)
+        if (f < 0 && g < nf && fk[g] == key) f = g;
+      if (f < 0) {
+        if (nf == kRegFam) {
+          spill = true;
+          break;
+        }
+        f = nf++;
+#pragma unroll
+        for (int g = 0; g < kRegFam; ++g)
+          if (g == f) {
+            fk[g] = key;
+            lab[g] = ph;
+            li[g] = r;
+          }
+      }
+#pragma unroll
+      for (int g = 0; g < kRegFam; ++g)
+        if (g == f) {
+          cnt[g] += 1;
+          if (ph > lab[g]) {
+            lab[g] = ph;
+            li[g] = r;
+          }
+        }
+      fam_of[b + i] = f;
+    }
+    if (spill) {
+      families_in_place(p, fo, lattice, first, mult, perm, hh, kk, ll, n_fam, fam_of, fam_label, fam_mult);
+      continue;
+    }
+#pragma unroll
+    for (int g = 0; g < kRegFam; ++g)
+      if (g < nf) {
+        fam_label[b + g] = li[g];
+        fam_mult[b + g] = cnt[g];
+      }
+    n_fam[p] = nf;
+  }
+}
+
 }  // namespace
 
-void launch_peak_families(const FamOps *fam_ops, const int64_t *peak_offset, int64_t n_c, int64_t peak_cap,
+void launch_peak_families(const HChunk *chunks, int64_t n_chunks, const FamOps *fam_ops, const int64_t *peak_offset,
                           const int64_t *first, const int32_t *mult, const int64_t *perm, const int16_t *h,
                           const int16_t *k, const int16_t *l, int rule, int32_t *n_fam, int32_t *fam_of,
                           int64_t *fam_label, int32_t *fam_mult, hipStream_t s) {
-  if (n_c <= 0 || peak_cap <= 0) return;
-  const int64_t blocks = (peak_cap + kThreads - 1) / kThreads;
-  hipLaunchKernelGGL(k_peak_families, dim3((unsigned)blocks), dim3(kThreads), 0, s, fam_ops, peak_offset, n_c, first,
-                     mult, perm, h, k, l, rule, n_fam, fam_of, fam_label, fam_mult);
+  if (n_chunks <= 0) return;
+  hipLaunchKernelGGL(k_peak_families, dim3((unsigned)n_chunks), dim3(kThreads), 0, s, chunks, fam_ops, peak_offset,
+                     first, mult, perm, h, k, l, rule, n_fam, fam_of, fam_label, fam_mult);
 }
 
 }  // namespace xrd

@@ -140,7 +140,7 @@ struct WsLayout {
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 
 // Families of equivalent reflections per merged peak (rule 0: indices, 1: lattice).
-void launch_peak_families(const FamOps *fam_ops, const int64_t *peak_offset, int64_t n_c, int64_t peak_cap,
+void launch_peak_families(const HChunk *chunks, int64_t n_chunks, const FamOps *fam_ops, const int64_t *peak_offset,
                           const int64_t *first, const int32_t *mult, const int64_t *perm, const int16_t *h,
                           const int16_t *k, const int16_t *l, int rule, int32_t *n_fam, int32_t *fam_of,
                           int64_t *fam_label, int32_t *fam_mult, hipStream_t s);

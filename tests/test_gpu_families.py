@@ -122,3 +122,23 @@ def test_families_rejects_bad_rule():
     peaks = xb.merge(refl, I)
     with pytest.raises(XrdError):
         xb.families(refl, peaks, 5)
+
+
+@pytest.mark.parametrize("rule", [0, 1])
+def test_many_families_per_peak(rule):
+    """A wide merge tolerance on large cubic and hexagonal cells puts several
+    families into one peak (beyond the ones held in registers)."""
+    from paper_2602_11709_amd.api import XrdBatch
+    rag = ragged_batch()
+    rng = np.random.default_rng(12)
+    lats = [[11.3, 11.3, 11.3, 90.0, 90.0, 90.0], [9.7, 9.7, 12.9, 90.0, 90.0, 120.0]]
+    atoms = [(rng.uniform(size=(3, 3)), np.zeros(3, np.int32), np.ones(3), np.full(3, 0.4)) for _ in lats]
+    b = synth._assemble("wide", lats, atoms, rag.sf_coeff, rag.wavelength, 20.0, 120.0, tol=0.08)
+    xb = XrdBatch(b, precision="fp64")
+    assert check_families(xb, b, rule) > 100
+    refl = xb.enumerate()
+    _, _, I = xb.structure_factors(refl)
+    peaks = xb.merge(refl, I)
+    n_fam = xb.families(refl, peaks, rule)[0]
+    _, po = xb.read_counts(refl, peaks)
+    assert int(n_fam[:int(po[-1])].max()) > 4
