@@ -267,7 +267,9 @@ int xrd_peak_families(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_peaks
  * |x - 2theta| <= window_sigmas sigma; a reflection with FWHM^2 <= 0 adds
  * nothing.  The grid's t0, dt, n_points and window_sigmas apply; its sigma is
  * not used (any positive value).  Sums in double precision, each point over
- * its reflections in 2theta order (deterministic); forward only. */
+ * its reflections in 2theta order (deterministic); forward only.  Under
+ * XRD_MIXED each Gaussian value is a single-precision exp2 (relative error
+ * below 1e-5 per term), as in xrd_pattern_forward; under XRD_FP64 all double. */
 int xrd_pattern_caglioti(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, const xrd_grid *g,
                          double U, double V, double W, double *y);
 

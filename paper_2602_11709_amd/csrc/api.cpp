@@ -955,7 +955,7 @@ int xrd_pattern_caglioti(xrd_batch *b, void *ws, const xrd_refl *r, const double
     return fail(XRD_ERR_INVALID_ARG, "U, V and W must be finite");
   ensure_sorted(b, ws, r);
   const WsLayout &L = b->ws;
-  launch_broaden_caglioti(at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, r->refl_offset, b->desc.friedel != 0,
+  launch_broaden_caglioti(b->desc.precision == XRD_MIXED, at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, r->refl_offset, b->desc.friedel != 0,
                           at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), I, g->t0, g->dt, g->n_points, U, V,
                           W, g->window_sigmas, y, stream_of(b));
   b->last_ws = ws;

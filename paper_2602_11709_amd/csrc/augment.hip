@@ -123,12 +123,23 @@ __device__ int64_t block_lower_bound(const double *__restrict__ keys, int64_t n,
 // (the crystal's widest line, from the width's maximum over its 2theta
 // range) by two searches over the sorted entries, stages them 256 at a time
 // in LDS with their weight, exponent scale and half-width, and every thread
-// sums its lines in 2theta order (double precision throughout).
+// sums its lines in 2theta order, in double precision.  Under MIXED the
+// Gaussian itself is the single-precision exp2 of -d^2 log2(e) / (2 sigma^2)
+// with d = x - 2theta rounded to single after the double subtraction (about
+// 4e-6 relative per term at the window's edge, less nearer the centre), as in
+// the constant-width gather; otherwise exp in double.
+struct CagEnt {
+  double t, w;   // 2theta, intensity / (sigma sqrt(2 pi)) (0: no line)
+  double z;      // 1 / (2 sigma^2), times log2(e) under MIXED
+  double half;   // window * sigma (-1: no line)
+};
+
+template <bool MIXED>
 __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
     const CrystalPlan *__restrict__ plan, const int64_t *__restrict__ refl_offset, bool friedel,
     const double *__restrict__ ent_key, const int32_t *__restrict__ ent_idx, const double *__restrict__ inten,
     double t0, double dt, int64_t n, double U, double V, double W, double window, double *__restrict__ y) {
-  __shared__ double4 s_ent[kThreads];  // 2theta, weight, 1 / (2 sigma^2), half-width
+  __shared__ CagEnt s_ent[kThreads];
   const int64_t blocks_per = (n + kThreads - 1) / kThreads;
   const int64_t c = blockIdx.x / blocks_per;
   const int64_t p = (blockIdx.x % blocks_per) * kThreads + threadIdx.x;
@@ -155,6 +166,9 @@ __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
   const int64_t e0 = block_lower_bound<false>(keys, count, x0 - hmax);
   const int64_t e1 = block_lower_bound<true>(keys, count, x1 + hmax);
   const double x = t0 + (double)p * dt;
+  const int lane = threadIdx.x & 63;
+  const int64_t pw0 = p0 + (threadIdx.x & ~63), pw1 = min(pw0 + 64, n) - 1;
+  const double xw_lo = t0 + (double)pw0 * dt - hmax, xw_hi = t0 + (double)max(pw1, pw0) * dt + hmax;
   double acc = 0.0;
   for (int64_t t0e = e0; t0e < e1; t0e += kThreads) {
     const int64_t e = t0e + threadIdx.x;
@@ -163,21 +177,40 @@ __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
       const double t = keys[e];
       const double tn = tan(t * rad);
       const double q = f2(tn);
-      double4 v = make_double4(t, 0.0, 0.0, -1.0);
+      CagEnt v{t, 0.0, 0.0, -1.0};
       if (q > 0.0) {
         const double sigma = sqrt(q) * fw;
-        v.y = m * inten[ent_idx[base + e]] / (sigma * sqrt(2.0 * 3.14159265358979323846));
+        v.w = m * inten[ent_idx[base + e]] / (sigma * sqrt(2.0 * 3.14159265358979323846));
         v.z = 1.0 / (2.0 * sigma * sigma);
-        v.w = window * sigma;
+        if constexpr (MIXED) v.z *= 1.44269504088896340736;  // log2(e)
+        v.half = window * sigma;
       }
       s_ent[threadIdx.x] = v;
     }
     __syncthreads();
     const int ne = (int)min((int64_t)kThreads, e1 - t0e);
-    for (int j = 0; j < ne; ++j) {
-      const double4 v = s_ent[j];
-      const double d = x - v.x;
-      if (fabs(d) <= v.w) acc += v.y * exp(-(d * d) * v.z);
+    // the wavefront's own stretch of the sorted tile: entries within hmax of
+    // its 64 points (counted by ballots; the rest cannot reach them)
+    int j0 = 0, j1 = 0;
+#pragma unroll
+    for (int q = 0; q < kThreads; q += 64) {
+      const int j = q + lane;
+      const bool in = j < ne;
+      const double t = in ? s_ent[j].t : 0.0;
+      j0 += __popcll(__ballot(in && t < xw_lo));
+      j1 += __popcll(__ballot(in && !(t > xw_hi)));
+    }
+    for (int j = j0; j < j1; ++j) {
+      const CagEnt v = s_ent[j];
+      const double d = x - v.t;
+      if (fabs(d) <= v.half) {
+        if constexpr (MIXED) {
+          const float df = (float)d;
+          acc = fma(v.w, (double)__builtin_amdgcn_exp2f(-(df * df) * (float)v.z), acc);
+        } else {
+          acc += v.w * exp(-(d * d) * v.z);
+        }
+      }
     }
   }
   if (p < n) y[c * n + p] = acc;
@@ -185,14 +218,18 @@ __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
 
 }  // namespace
 
-void launch_broaden_caglioti(const CrystalPlan *plan, int64_t n_c, const int64_t *refl_offset, bool friedel,
-                             const double *ent_key, const int32_t *ent_idx, const double *inten, double t0,
-                             double dt, int64_t n, double U, double V, double W, double window, double *y,
+void launch_broaden_caglioti(bool mixed, const CrystalPlan *plan, int64_t n_c, const int64_t *refl_offset,
+                             bool friedel, const double *ent_key, const int32_t *ent_idx, const double *inten,
+                             double t0, double dt, int64_t n, double U, double V, double W, double window, double *y,
                              hipStream_t s) {
   if (n_c <= 0 || n <= 0) return;
   const int64_t blocks = n_c * ((n + kThreads - 1) / kThreads);
-  hipLaunchKernelGGL(k_broaden_caglioti, dim3((unsigned)blocks), dim3(kThreads), 0, s, plan, refl_offset, friedel,
-                     ent_key, ent_idx, inten, t0, dt, n, U, V, W, window, y);
+  if (mixed)
+    hipLaunchKernelGGL(k_broaden_caglioti<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s, plan, refl_offset,
+                       friedel, ent_key, ent_idx, inten, t0, dt, n, U, V, W, window, y);
+  else
+    hipLaunchKernelGGL(k_broaden_caglioti<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s, plan, refl_offset,
+                       friedel, ent_key, ent_idx, inten, t0, dt, n, U, V, W, window, y);
 }
 
 void launch_march_dollase(const HChunk *chunks, int64_t n_chunks, const CrystalPlan *plan,

@@ -274,7 +274,7 @@ void launch_march_dollase(const HChunk *chunks, int64_t n_chunks, const CrystalP
 void launch_noise(int64_t total, uint64_t seed, double rel, double abs_, double *y, hipStream_t s);
 // Broadened pattern with Caglioti widths over the sorted entries (the
 // evaluated half under Friedel pairing, weight 2, else every reflection).
-void launch_broaden_caglioti(const CrystalPlan *plan, int64_t n_c, const int64_t *refl_offset, bool friedel,
+void launch_broaden_caglioti(bool mixed, const CrystalPlan *plan, int64_t n_c, const int64_t *refl_offset, bool friedel,
                              const double *ent_key, const int32_t *ent_idx, const double *inten, double t0,
                              double dt, int64_t n, double U, double V, double W, double window, double *y,
                              hipStream_t s);

@@ -132,7 +132,8 @@ def test_caglioti_pattern(precision, friedel):
         sl = slice(int(ro[c]), int(ro[c + 1]))
         want = oracle.broaden_caglioti(tt[sl], Ih[sl], grid.t0, grid.dt, grid.n_points, U, V, W, grid.window_sigmas)
         err = np.max(np.abs(yh[c] - want)) / max(np.max(np.abs(want)), 1e-300)
-        assert err <= 1e-12, f"crystal {c}: {err:.3e}"
+        tol = 1e-12 if precision == "fp64" else 1e-5  # single-precision exponentials under mixed
+        assert err <= tol, f"crystal {c}: {err:.3e}"
     # repeat: bit for bit
     y2 = xb.pattern_caglioti(refl, I, grid, U, V, W)
     torch.cuda.synchronize()
