@@ -134,6 +134,18 @@ struct CagEnt {
   double half;   // window * sigma (-1: no line)
 };
 
+// Logical block of a launch of g blocks such that consecutive logical blocks
+// share an XCD: workgroups go to the eight XCDs round-robin by blockIdx, and
+// each XCD has its own L2, so neighbouring work (one crystal's blocks) should
+// land on one of them.  A bijection of [0, g): XCD x (= blockIdx mod 8) takes
+// a contiguous range of logical blocks, ceil(g / 8) or one fewer.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t g) {
+  constexpr int64_t kXcd = 8;
+  const int64_t per = (g + kXcd - 1) / kXcd, tall = g - (per - 1) * kXcd;  // XCDs taking ``per`` blocks
+  const int64_t x = b % kXcd, i = b / kXcd;
+  return x < tall ? x * per + i : tall * per + (x - tall) * (per - 1) + i;
+}
+
 template <bool MIXED>
 __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
     const CrystalPlan *__restrict__ plan, const int64_t *__restrict__ refl_offset, bool friedel,
@@ -141,8 +153,9 @@ __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
     double t0, double dt, int64_t n, double U, double V, double W, double window, double *__restrict__ y) {
   __shared__ CagEnt s_ent[kThreads];
   const int64_t blocks_per = (n + kThreads - 1) / kThreads;
-  const int64_t c = blockIdx.x / blocks_per;
-  const int64_t p = (blockIdx.x % blocks_per) * kThreads + threadIdx.x;
+  const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
+  const int64_t c = lb / blocks_per;
+  const int64_t p = (lb % blocks_per) * kThreads + threadIdx.x;
   const CrystalPlan &P = plan[c];
   const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
   const int64_t base = friedel ? r0 / 2 : r0, count = friedel ? (r1 - r0) / 2 : r1 - r0;
@@ -159,7 +172,7 @@ __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
     if (tv > ta && tv < tb) f2max = fmax(f2max, f2(tv));
   }
   const double hmax = f2max > 0.0 ? window * sqrt(f2max) * fw : 0.0;
-  const int64_t p0 = (blockIdx.x % blocks_per) * kThreads;
+  const int64_t p0 = (lb % blocks_per) * kThreads;
   const int64_t p1 = min(p0 + kThreads, n) - 1;
   const double x0 = t0 + (double)p0 * dt, x1 = t0 + (double)p1 * dt;
   const double *keys = ent_key + base;
