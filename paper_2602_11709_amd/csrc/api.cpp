@@ -244,6 +244,60 @@ int check_refl(const xrd_refl *r) {
 // no reflection and end at once, and the few that do are complete on a
 // single wavefront.  Crystals come in descending atom count, so the heaviest
 // work is dispatched first.  Returns the number of block-per-tile items.
+// Reorder a structure-factor work list so that a crystal's items run on one
+// XCD (one L2 holds its atoms and reflections).  Workgroups reach the eight
+// XCDs round-robin by block index, so block i runs on XCD i mod 8.  Crystals
+// are spread over the XCDs by expected work (largest first, onto the least
+// loaded), and each XCD's items keep their relative order (expected-filled
+// tiles first).  The first n_heavy items take a block each and the rest four
+// to a block, so slot i of the heavy part and the four slots of light block j
+// draw from the queue of the XCD their block lands on; when that queue is
+// empty, from the longest other one.
+void xcd_group(const xrd_batch *b, int64_t n_heavy, std::vector<SfItem> *items) {
+  constexpr int kXcd = 8;
+  const int64_t nc = (int64_t)b->plan.size();
+  std::vector<int> xcd_of(nc, 0);
+  {
+    std::vector<std::pair<double, int32_t>> work;
+    for (int32_t c = 0; c < nc; ++c) {
+      const CrystalPlan &P = b->plan[c];
+      work.push_back({(double)b->sf_likely[c] * (double)std::max<int64_t>(P.atom_end - P.atom_begin, 1), c});
+    }
+    std::stable_sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
+    double load[kXcd] = {};
+    for (const auto &w : work) {
+      int best = 0;
+      for (int x = 1; x < kXcd; ++x)
+        if (load[x] < load[best]) best = x;
+      xcd_of[w.second] = best;
+      load[best] += w.first;
+    }
+  }
+  auto regroup = [&](int64_t lo, int64_t hi, int per_block, int64_t first_block) {
+    std::vector<std::vector<SfItem>> q(kXcd);
+    for (int64_t i = lo; i < hi; ++i) q[xcd_of[(*items)[i].crystal]].push_back((*items)[i]);
+    std::vector<size_t> head(kXcd, 0);
+    int64_t o = lo;
+    for (int64_t blk = first_block; o < hi; ++blk) {
+      const int x = (int)(blk % kXcd);
+      for (int k = 0; k < per_block && o < hi; ++k) {
+        int from = x;
+        if (head[from] == q[from].size()) {
+          size_t most = 0;
+          for (int y = 0; y < kXcd; ++y)
+            if (q[y].size() - head[y] > most) {
+              most = q[y].size() - head[y];
+              from = y;
+            }
+        }
+        (*items)[o++] = q[from][head[from]++];
+      }
+    }
+  };
+  regroup(0, n_heavy, 1, 0);
+  regroup(n_heavy, (int64_t)items->size(), 4, n_heavy);  // four wavefronts to a light block
+}
+
 int64_t sf_table(const xrd_batch *b, int32_t split, std::vector<SfItem> *items) {
   items->clear();
   auto item = [&](int32_t c, int32_t t) {
@@ -262,6 +316,7 @@ int64_t sf_table(const xrd_batch *b, int32_t split, std::vector<SfItem> *items) 
     for (int32_t c : b->sf_order)
       if (heavy(c) == (pass == 0))
         for (int32_t t = b->sf_likely[c]; t < b->plan[c].n_tiles; ++t) items->push_back(item(c, t));
+  xcd_group(b, n_heavy, items);
   return n_heavy;
 }
 
