@@ -263,16 +263,26 @@ def workload_stats(batch, refl_offset):
     return int(refl.sum()), int((refl * counts).sum())
 
 
-def traffic_record(kernel_src):
+TRAFFIC_SOURCES = ("sf.hip", "api.cpp")  # the kernel, and the host code that orders its work
+
+
+def sources_sha256():
+    h = hashlib.sha256()
+    for name in TRAFFIC_SOURCES:
+        h.update(open(os.path.join(HERE, "paper_2602_11709_amd", "csrc", name), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_record():
     """HBM bytes per launch of the dominant kernel from the committed counter
-    summary, valid only while the kernel source is unchanged."""
+    summary, valid only while the kernel source and its work ordering are
+    unchanged."""
     path = os.path.join(HERE, "profiles", "sf_mixed_triclinic_1024_traffic.json")
     try:
         rec = json.load(open(path))
     except (OSError, ValueError):
         return None
-    src = open(os.path.join(HERE, "paper_2602_11709_amd", "csrc", kernel_src), "rb").read()
-    if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
+    if rec.get("sources_sha256") != sources_sha256():
         return None
     return rec.get("bytes_per_launch")
 
@@ -390,7 +400,7 @@ def main():
             "peak": round(peak / 1e9, 3),
             "unit": "Gterm/s",
             "frac": round(achieved / peak, 4),
-            "traffic": traffic_record("sf.hip"),
+            "traffic": traffic_record(),
             "per_launch_terms": eval_terms,
             "avg_launch_ms": round(mx["sf_ms"], 5),
         },
