@@ -111,15 +111,20 @@ def test_noise_matches_definition_and_seed():
     assert not np.array_equal(y3.cpu().numpy(), got)
 
 
-@pytest.mark.parametrize("precision,friedel", [("mixed", True), ("fp64", False)])
-def test_caglioti_pattern(precision, friedel):
+@pytest.mark.parametrize("precision,friedel,uvw", [
+    ("mixed", True, (0.03, -0.01, 0.004)), ("fp64", False, (0.03, -0.01, 0.004)),
+    # FWHM^2 <= 0 below 2theta ~ 11.4 deg: those lines add nothing
+    ("fp64", True, (0.05, 0.0, -0.0005)),
+    # widest line at the quadratic's vertex (tan theta = 0.75, 2theta ~ 73.7 deg), not at an end
+    ("mixed", False, (-0.02, 0.03, 0.002))])
+def test_caglioti_pattern(precision, friedel, uvw):
     """Widths growing with angle, against the oracle's broadening of the GPU's
     own reflections and intensities, on crystals of every sort size (the
     largest sorted in global memory) and a grid cut at both ends."""
     from paper_2602_11709_amd.api import Grid, XrdBatch
     b = ragged_batch()
     grid = Grid(12.0, 0.017, 4501, 1.0, 8.0)
-    U, V, W = 0.03, -0.01, 0.004
+    U, V, W = uvw
     xb = XrdBatch(b, precision=precision, friedel=friedel)
     refl = xb.enumerate()
     _, _, I = xb.structure_factors(refl)

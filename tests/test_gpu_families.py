@@ -83,6 +83,15 @@ def test_families_vs_oracle(precision, friedel, rule):
     assert check_families(xb, b, rule) > 1000
 
 
+def test_families_with_threshold():
+    """Peaks dropped by the relative threshold are not grouped; the kept ones
+    match the oracle."""
+    from paper_2602_11709_amd.api import XrdBatch
+    b = symmetric_batch(seed=9)
+    xb = XrdBatch(b, precision="mixed", friedel=True, rel_threshold=0.02)
+    assert check_families(xb, b, 1) > 100
+
+
 def test_cubic_multiplicities_on_gpu():
     """The {100}, {110}, {111} lines of a cubic cell: one family each, of 6, 12
     and 8 members, labelled (1,0,0), (1,1,0), (1,1,1)."""
