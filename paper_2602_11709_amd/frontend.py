@@ -19,8 +19,11 @@ an hkl with a multiplicity), each as {"hkl": label, "multiplicity": m}, the
 label being the family's lexicographically largest member; ``family_rule``
 "indices" groups equal multisets of absolute indices (4-index form on
 hexagonal lattices), "lattice" groups reflections related by a point
-operation of the lattice.  ``members`` lists every member reflection
-(Friedel mates included) in (2theta, h, k, l) order.
+operation of the lattice.  On a hexagonal lattice (a = b, alpha = beta =
+90, gamma = 120 degrees) family labels are written as Miller-Bravais
+4-tuples (h, k, -(h + k), l), as the Python calculator the paper targets
+writes them.  ``members`` lists every member reflection (Friedel mates
+included) in (2theta, h, k, l) order.
 """
 
 from __future__ import annotations
@@ -67,7 +70,7 @@ class DiffractionPattern:
     y: np.ndarray        # intensity (0-100 when scaled)
     mult: np.ndarray     # member reflections per peak (the sum of its family multiplicities)
     d_hkls: np.ndarray   # interplanar spacing (Angstrom)
-    hkls: list           # per peak: its families, [{"hkl": (h, k, l), "multiplicity": m}, ...]
+    hkls: list           # per peak: its families, [{"hkl": (h, k, l) or (h, k, i, l), "multiplicity": m}, ...]
     line: np.ndarray     # per peak: emission line label ("" for a single line)
     members: list        # per peak: (h, k, l) of its members, in (2theta, h, k, l) order
 
@@ -94,6 +97,18 @@ def structure_batch(lattice: Sequence[float], frac, species, sf_coeff, occ=None,
 FAMILY_RULES = {"indices": 0, "lattice": 1}
 
 
+def is_hexagonal(lattice, tol: float = 1e-6) -> bool:
+    """a = b, alpha = beta = 90, gamma = 120 degrees (relative / absolute tolerance)."""
+    a, b, _, al, be, ga = (float(v) for v in np.asarray(lattice, dtype=np.float64).reshape(6))
+    return abs(a - b) <= tol * max(a, b) and abs(al - 90.0) <= 1e3 * tol and abs(be - 90.0) <= 1e3 * tol \
+        and abs(ga - 120.0) <= 1e3 * tol
+
+
+def _label(hkl, hexagonal: bool):
+    h, k, l = (int(v) for v in hkl)
+    return (h, k, -(h + k), l) if hexagonal else (h, k, l)
+
+
 def get_patterns(batch: CrystalBatch, wavelength: Union[float, str] = "CuKa", scaled: bool = True,
                  precision: str = "mixed", device="cuda", family_rule: str = "indices") -> list:
     """Peaks of every crystal of ``batch`` (its own wavelength is replaced by
@@ -108,6 +123,7 @@ def get_patterns(batch: CrystalBatch, wavelength: Union[float, str] = "CuKa", sc
         parts.append((res, weight, label))
     out = []
     for c in range(batch.n_crystals):
+        hexagonal = is_hexagonal(batch.lattice[c])
         xs, ys, ms, ds, hk, fm, ls = [], [], [], [], [], [], []
         for res, weight, label in parts:
             rs, ps = res.crystal(c)
@@ -119,7 +135,7 @@ def get_patterns(batch: CrystalBatch, wavelength: Union[float, str] = "CuKa", sc
             for f, m, nf in zip(res.pk_first[ps], res.pk_mult[ps], res.fam_n[ps]):
                 members = res.perm[f:f + m]
                 hk.append([tuple(int(v) for v in res.hkl[i]) for i in members])
-                fm.append([{"hkl": tuple(int(v) for v in res.hkl[res.fam_label[f + j]]),
+                fm.append([{"hkl": _label(res.hkl[res.fam_label[f + j]], hexagonal),
                             "multiplicity": int(res.fam_mult[f + j])} for j in range(nf)])
                 ds.append(1.0 / np.sqrt(res.q[members[0]]))
         x = np.concatenate(xs) if xs else np.zeros(0)

@@ -50,3 +50,12 @@ def test_family_rule_is_checked():
     with pytest.raises(ValueError):
         frontend.get_patterns(frontend.structure_batch([4, 4, 4, 90, 90, 90], np.zeros((1, 3)), [0],
                                                        np.ones((1, 9))), family_rule="spacegroup")
+
+
+def test_hexagonal_detection_for_labels():
+    from paper_2602_11709_amd import frontend
+    assert frontend.is_hexagonal([3.1, 3.1, 5.2, 90, 90, 120])
+    assert not frontend.is_hexagonal([3.1, 3.1, 5.2, 90, 90, 60])
+    assert not frontend.is_hexagonal([3.1, 3.2, 5.2, 90, 90, 120])
+    assert frontend._label((2, -1, 3), True) == (2, -1, -1, 3)
+    assert frontend._label((2, -1, 3), False) == (2, -1, 3)

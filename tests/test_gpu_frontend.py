@@ -106,3 +106,14 @@ def test_broadened_doublet():
                    for lam, w, _ in frontend.lines_of("CuKa12"))
         err = np.max(np.abs(y[c] - want)) / max(np.max(np.abs(want)), 1e-300)
         assert err <= 2e-5, f"crystal {c}: {err:.3e}"
+
+
+def test_hexagonal_family_labels():
+    """Hexagonal cell: {100} and {110} lines of 6 members each, labelled in
+    Miller-Bravais form; their members stay 3-index."""
+    rs = synth.rocksalt()
+    got = frontend.get_pattern([3.1, 3.1, 5.2, 90.0, 90.0, 120.0], np.zeros((1, 3)), [0], rs.sf_coeff,
+                               wavelength="CuKa", two_theta_range=(5.0, 90.0), family_rule="lattice")
+    by_hkl = {e["hkl"]: e["multiplicity"] for fams in got.hkls for e in fams}
+    assert by_hkl[(1, 0, -1, 0)] == 6 and by_hkl[(2, -1, -1, 0)] == 6 and by_hkl[(0, 0, 0, 1)] == 2
+    assert all(len(t) == 3 for mem in got.members for t in mem)
