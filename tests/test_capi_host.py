@@ -169,3 +169,31 @@ def test_device_calls_reject_null_workspace():
             capi.XRD_ERR_INVALID_ARG
     finally:
         capi.xrd_batch_destroy(h)
+
+
+def test_new_device_calls_validate_before_any_launch():
+    """Families, Caglioti widths, texture and noise reject bad arguments on the
+    host (every case fails validation before a kernel would be launched)."""
+    b = synth.rocksalt()
+    keep = []
+    h = capi.xrd_batch_create(make_desc(b, keep))
+    lib = capi.lib()
+    fake = 0x1000  # never dereferenced: each call below fails validation first
+    try:
+        r = capi.xrd_refl(*([fake] * 7))
+        p = capi.xrd_peaks(*([fake] * 7))
+        pnull = capi.xrd_peaks(*([fake] * 5 + [None, fake]))  # perm missing
+        ok = capi.XRD_ERR_INVALID_ARG
+        assert lib.xrd_peak_families(h, fake, C.byref(r), C.byref(p), 7, fake, fake, fake, fake) == ok
+        assert lib.xrd_peak_families(h, fake, C.byref(r), C.byref(pnull), 1, fake, fake, fake, fake) == ok
+        assert lib.xrd_peak_families(h, fake, C.byref(r), C.byref(p), 1, fake, None, fake, fake) == ok
+        assert lib.xrd_peak_families(h, fake, C.byref(r), None, 1, fake, fake, fake, fake) == ok
+        g = capi.xrd_grid(10.0, 0.02, 100, 0.1, 8.0)
+        assert lib.xrd_pattern_caglioti(h, fake, C.byref(r), fake, C.byref(g), float("nan"), 0.0, 0.01, fake) == ok
+        assert lib.xrd_pattern_caglioti(h, fake, C.byref(r), None, C.byref(g), 0.0, 0.0, 0.01, fake) == ok
+        bad = capi.xrd_grid(10.0, 0.0, 100, 0.1, 8.0)  # dt = 0
+        assert lib.xrd_pattern_caglioti(h, fake, C.byref(r), fake, C.byref(bad), 0.0, 0.0, 0.01, fake) == ok
+        assert lib.xrd_preferred_orientation(h, fake, C.byref(r), None, fake, fake) == ok
+        assert "non-NULL" in lib.xrd_last_error().decode() or lib.xrd_last_error()
+    finally:
+        capi.xrd_batch_destroy(h)
