@@ -111,7 +111,7 @@ def _get():
         lib.orc_noise.argtypes = [C.c_long, C.c_long, C.c_uint64, C.c_double, C.c_double, _dp]
         lib.orc_noise.restype = None
         lib.orc_broaden_caglioti.argtypes = [C.c_long, _dp, _dp, C.c_double, C.c_double, C.c_long, C.c_double,
-                                             C.c_double, C.c_double, C.c_double, _dp]
+                                             C.c_double, C.c_double, C.c_double, C.c_double, _dp]
         lib.orc_broaden_caglioti.restype = None
         lib.orc_is_hexagonal.argtypes = [_dp]
         lib.orc_is_hexagonal.restype = C.c_int
@@ -362,12 +362,14 @@ def noise(y, seed, rel, abs_):
     return out
 
 
-def broaden_caglioti(tt, inten, t0, dt, npts, U, V, W, window):
-    """Broadened pattern with Caglioti widths FWHM^2 = U tan^2 + V tan + W."""
+def broaden_caglioti(tt, inten, t0, dt, npts, U, V, W, window, eta=0.0):
+    """Broadened pattern with Caglioti widths FWHM^2 = U tan^2 + V tan + W and
+    pseudo-Voigt profiles of Lorentzian share eta (0: Gaussian)."""
     y = np.zeros(npts)
     n = len(tt)
     _get().orc_broaden_caglioti(n, _f64(tt) if n else np.zeros(1), _f64(inten) if n else np.zeros(1),
-                                float(t0), float(dt), int(npts), float(U), float(V), float(W), float(window), y)
+                                float(t0), float(dt), int(npts), float(U), float(V), float(W), float(eta),
+                                float(window), y)
     return y
 
 

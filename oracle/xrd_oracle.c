@@ -422,20 +422,26 @@ void orc_noise(long n_c, long n_pts, uint64_t seed, double rel, double abs_, dou
 }
 
 /* Broadening with 2theta-dependent widths (Caglioti, Paoletti and Ricci,
- * Nucl. Instrum. 3 (1958) 223): each reflection is a unit-area Gaussian of
- *   FWHM^2 = U tan^2(theta) + V tan(theta) + W   (degrees^2, theta = 2theta / 2),
- * sigma = FWHM / (2 sqrt(2 ln 2)), over the grid points with
- * |x - 2theta| <= window sigma.  A reflection with FWHM^2 <= 0 adds nothing.
- * With U = V = 0 this is orc_broaden with sigma = sqrt(W) / (2 sqrt(2 ln 2)). */
+ * Nucl. Instrum. 3 (1958) 223) and pseudo-Voigt profiles: each reflection is
+ *   eta L(d) + (1 - eta) G(d),  d = x - 2theta,
+ * a unit-area Lorentzian L(d) = (2 / (pi Gam)) / (1 + (2 d / Gam)^2) and a
+ * unit-area Gaussian G of the same full width at half maximum Gam,
+ *   Gam^2 = U tan^2(theta) + V tan(theta) + W   (degrees^2, theta = 2theta / 2),
+ *   sigma = Gam / (2 sqrt(2 ln 2)),
+ * summed over the grid points with |d| <= window sigma (both components cut
+ * there).  A reflection with Gam^2 <= 0 adds nothing.  eta = 0 is the
+ * Gaussian broadening (with U = V = 0, orc_broaden with sigma =
+ * sqrt(W) / (2 sqrt(2 ln 2))). */
 void orc_broaden_caglioti(long nr, const double *tt, const double *inten, double t0, double dt, long npts,
-                          double U, double V, double W, double window, double *y)
+                          double U, double V, double W, double eta, double window, double *y)
 {
     for (long g = 0; g < npts; ++g) y[g] = 0.0;
     for (long r = 0; r < nr; ++r) {
         const double t = tan(0.5 * tt[r] * ORC_PI / 180.0);
         const double f2 = U * t * t + V * t + W;
         if (!(f2 > 0.0)) continue;
-        const double sigma = sqrt(f2) / (2.0 * sqrt(2.0 * log(2.0)));
+        const double gam = sqrt(f2);
+        const double sigma = gam / (2.0 * sqrt(2.0 * log(2.0)));
         const double half = window * sigma;
         const double norm = 1.0 / (sigma * sqrt(2.0 * ORC_PI));
         long glo = (long)floor((tt[r] - half - t0) / dt) - 1;
@@ -446,7 +452,10 @@ void orc_broaden_caglioti(long nr, const double *tt, const double *inten, double
             const double x = t0 + (double)g * dt;
             const double d = x - tt[r];
             if (fabs(d) > half) continue;
-            y[g] += inten[r] * norm * exp(-(d * d) / (2.0 * sigma * sigma));
+            const double gauss = norm * exp(-(d * d) / (2.0 * sigma * sigma));
+            const double u = 2.0 * d / gam;
+            const double lorentz = 2.0 / (ORC_PI * gam) / (1.0 + u * u);
+            y[g] += inten[r] * (eta * lorentz + (1.0 - eta) * gauss);
         }
     }
 }

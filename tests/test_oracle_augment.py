@@ -107,3 +107,41 @@ def test_caglioti_width_and_area(tt0):
 def test_caglioti_skips_nonpositive_widths():
     y = oracle.broaden_caglioti([30.0, 60.0], [1.0, 1.0], 10.0, 0.01, 8001, 0.0, 0.0, -0.1, 8.0)
     assert not y.any()
+
+
+def test_pseudo_voigt_lorentzian_area_is_truncated_arctangent():
+    """eta = 1: a unit-area Lorentzian of FWHM Gam cut at |d| <= h has area
+    (2 / pi) atan(2 h / Gam); times the intensity, on a fine grid."""
+    W, window = 0.01, 8.0
+    gam = np.sqrt(W)
+    h = window * gam / (2 * np.sqrt(2 * np.log(2)))
+    dt = 1e-5
+    n = int(2 * 1.0 / dt) + 1
+    y = oracle.broaden_caglioti([40.0], [2.0], 39.0, dt, n, 0.0, 0.0, W, window, eta=1.0)
+    # the rectangle sum misses at most one grid step of the cut-off tail on
+    # each side: 2 dt I L(h), with L(h) = (2 / (pi Gam)) / (1 + (2 h / Gam)^2)
+    edge = 2 * dt * 2.0 * (2 / (np.pi * gam)) / (1 + (2 * h / gam) ** 2)
+    assert abs(np.sum(y) * dt - 2.0 * (2 / np.pi) * np.arctan(2 * h / gam)) <= edge + 1e-9
+
+
+@pytest.mark.parametrize("eta", [0.0, 0.3, 1.0])
+def test_pseudo_voigt_peak_value_and_half_maximum(eta):
+    """At the line centre the profile is eta 2/(pi Gam) + (1 - eta)/(sigma
+    sqrt(2 pi)); at d = +-Gam/2 both components, hence the sum, are halved."""
+    gam, dt = 0.1, 0.01  # Gam / 2 = 5 grid steps
+    sigma = gam / (2 * np.sqrt(2 * np.log(2)))
+    y = oracle.broaden_caglioti([30.0], [1.5], 29.0, dt, 201, 0.0, 0.0, gam * gam, 30.0, eta=eta)
+    c = 100  # x = 30.0
+    peak = 1.5 * (eta * 2 / (np.pi * gam) + (1 - eta) / (sigma * np.sqrt(2 * np.pi)))
+    assert y[c] == pytest.approx(peak, rel=1e-12)
+    assert y[c - 5] == pytest.approx(0.5 * peak, rel=1e-9) and y[c + 5] == pytest.approx(0.5 * peak, rel=1e-9)
+
+
+def test_pseudo_voigt_is_linear_in_eta():
+    rng = np.random.default_rng(9)
+    tt = np.sort(rng.uniform(15, 80, 30))
+    inten = rng.uniform(0.5, 5, 30)
+    args = (tt, inten, 10.0, 0.01, 8001, 0.02, -0.005, 0.004, 12.0)
+    g, l = oracle.broaden_caglioti(*args, eta=0.0), oracle.broaden_caglioti(*args, eta=1.0)
+    m = oracle.broaden_caglioti(*args, eta=0.25)
+    np.testing.assert_allclose(m, 0.25 * l + 0.75 * g, rtol=1e-12, atol=1e-14 * g.max())
