@@ -224,8 +224,10 @@ def augment_ms(p: Pipeline):
     # Caglioti widths of a laboratory diffractometer (FWHM 0.06-0.2 degrees over the range)
     cg = p.time_call(lambda: capi.xrd_pattern_caglioti(p.xb.handle, p.xb.ws, p.refl.c(), p.sf[2].data_ptr(),
                                                        p.grid.c(), 0.02, -0.005, 0.004, p.y.data_ptr()), 20)
+    pv = p.time_call(lambda: capi.xrd_pattern_caglioti(p.xb.handle, p.xb.ws, p.refl.c(), p.sf[2].data_ptr(),
+                                                       p.grid.c(), 0.02, -0.005, 0.004, p.y.data_ptr(), 0.5), 20)
     return {"preferred_orientation_ms": round(po, 5), "noise_ms": round(nz, 5),
-            "caglioti_pattern_ms": round(cg, 5), "noise_points": int(p.y.numel())}
+            "caglioti_pattern_ms": round(cg, 5), "pseudo_voigt_pattern_ms": round(pv, 5), "noise_points": int(p.y.numel())}
 
 
 def families_ms(p: Pipeline):

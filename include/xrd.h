@@ -260,18 +260,22 @@ int xrd_peak_families(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_peaks
                       int32_t *n_families, int32_t *family_of, int64_t *family_label, int32_t *family_mult);
 
 /* Broadened pattern y [n_crystals * n_points] with widths that grow with
- * angle (Caglioti, Paoletti and Ricci, Nucl. Instrum. 3 (1958) 223): each
- * reflection adds a unit-area Gaussian of FWHM^2 = U tan^2(theta) +
- * V tan(theta) + W (degrees^2, theta = 2theta / 2), sigma = FWHM /
- * (2 sqrt(2 ln 2)), times its intensity, at the grid points with
- * |x - 2theta| <= window_sigmas sigma; a reflection with FWHM^2 <= 0 adds
- * nothing.  The grid's t0, dt, n_points and window_sigmas apply; its sigma is
+ * angle (Caglioti, Paoletti and Ricci, Nucl. Instrum. 3 (1958) 223) and
+ * pseudo-Voigt profiles (paper, Section 1: peak broadening among the
+ * experimental effects of ML training patterns): each reflection adds its
+ * intensity times eta L + (1 - eta) G, a unit-area Lorentzian L and a
+ * unit-area Gaussian G of one FWHM, FWHM^2 = U tan^2(theta) + V tan(theta)
+ * + W (degrees^2, theta = 2theta / 2), sigma = FWHM / (2 sqrt(2 ln 2)), at
+ * the grid points with |x - 2theta| <= window_sigmas sigma (both components
+ * cut there); a reflection with FWHM^2 <= 0 adds nothing.  0 <= eta <= 1
+ * (0: Gaussian).  The grid's t0, dt, n_points and window_sigmas apply; its sigma is
  * not used (any positive value).  Sums in double precision, each point over
  * its reflections in 2theta order (deterministic); forward only.  Under
- * XRD_MIXED each Gaussian value is a single-precision exp2 (relative error
- * below 1e-5 per term), as in xrd_pattern_forward; under XRD_FP64 all double. */
+ * XRD_MIXED each profile value is a single-precision exp2 and reciprocal
+ * (relative error below 1e-5 per term), as in xrd_pattern_forward; under
+ * XRD_FP64 all double. */
 int xrd_pattern_caglioti(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, const xrd_grid *g,
-                         double U, double V, double W, double *y);
+                         double U, double V, double W, double eta, double *y);
 
 /* Noise on broadened patterns y (DEVICE [n_crystals*n_points], in place):
  * y += (rel sqrt(max(y, 0)) + abs) z, a counting-statistics term and a flat

@@ -214,11 +214,12 @@ class XrdBatch:
         return I
 
     def pattern_caglioti(self, refl: Reflections, I: torch.Tensor, grid: Grid, U: float, V: float, W: float,
-                         y=None) -> torch.Tensor:
-        """Broadened pattern with widths FWHM^2 = U tan^2 + V tan + W (grid.sigma unused)."""
+                         y=None, eta: float = 0.0) -> torch.Tensor:
+        """Broadened pattern with widths FWHM^2 = U tan^2 + V tan + W (grid.sigma
+        unused) and pseudo-Voigt profiles of Lorentzian share eta (0: Gaussian)."""
         if y is None:
             y = torch.empty(self.n_crystals, grid.n_points, dtype=torch.float64, device=self.device)
-        capi.xrd_pattern_caglioti(self.handle, self.ws, refl.c(), I.data_ptr(), grid.c(), U, V, W, y.data_ptr())
+        capi.xrd_pattern_caglioti(self.handle, self.ws, refl.c(), I.data_ptr(), grid.c(), U, V, W, y.data_ptr(), eta)
         return y
 
     def noise(self, y: torch.Tensor, seed: int, rel: float, abs_: float) -> torch.Tensor:

@@ -82,7 +82,7 @@ SIGNATURES = {
     "xrd_peak_families": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(xrd_peaks), C.c_int32, _vp, _vp, _vp, _vp],
                           C.c_int),
     "xrd_pattern_caglioti": ([_vp, _vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_grid), C.c_double, C.c_double,
-                              C.c_double, _vp], C.c_int),
+                              C.c_double, C.c_double, _vp], C.c_int),
     "xrd_read_counts": ([_vp, C.POINTER(xrd_refl), C.POINTER(xrd_peaks), _vp, _vp], C.c_int),
     "xrd_batch_destroy": ([_vp], None),
     "xrd_last_error": ([], C.c_char_p),
@@ -167,8 +167,9 @@ def xrd_peak_families(batch, ws: int, refl: xrd_refl, peaks: xrd_peaks, rule: in
 
 
 def xrd_pattern_caglioti(batch, ws: int, refl: xrd_refl, I: int, grid: xrd_grid, U: float, V: float, W: float,
-                         y: int):
-    check(lib().xrd_pattern_caglioti(batch, ws, C.byref(refl), I, C.byref(grid), float(U), float(V), float(W), y))
+                         y: int, eta: float = 0.0):
+    check(lib().xrd_pattern_caglioti(batch, ws, C.byref(refl), I, C.byref(grid), float(U), float(V), float(W),
+                                     float(eta), y))
 
 
 def xrd_pattern_noise(batch, n_points: int, seed: int, rel: float, abs_: float, y: int):

@@ -1000,7 +1000,7 @@ int xrd_peak_families(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_peaks
 }
 
 int xrd_pattern_caglioti(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, const xrd_grid *g, double U,
-                         double V, double W, double *y) {
+                         double V, double W, double eta, double *y) {
   if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
   if (int e = check_ws(b, ws)) return e;
   if (int e = check_refl(r)) return e;
@@ -1008,11 +1008,12 @@ int xrd_pattern_caglioti(xrd_batch *b, void *ws, const xrd_refl *r, const double
   if (!I || !y) return fail(XRD_ERR_INVALID_ARG, "I and y must be non-NULL");
   if (!std::isfinite(U) || !std::isfinite(V) || !std::isfinite(W))
     return fail(XRD_ERR_INVALID_ARG, "U, V and W must be finite");
+  if (!(eta >= 0.0 && eta <= 1.0)) return fail(XRD_ERR_INVALID_ARG, "eta must lie in [0, 1]");
   ensure_sorted(b, ws, r);
   const WsLayout &L = b->ws;
   launch_broaden_caglioti(b->desc.precision == XRD_MIXED, at<CrystalPlan>(ws, L.plan), b->desc.n_crystals, r->refl_offset, b->desc.friedel != 0,
                           at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), I, g->t0, g->dt, g->n_points, U, V,
-                          W, g->window_sigmas, y, stream_of(b));
+                          W, eta, g->window_sigmas, y, stream_of(b));
   b->last_ws = ws;
   return hip_check("pattern_caglioti");
 }

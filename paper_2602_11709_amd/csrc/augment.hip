@@ -20,7 +20,9 @@
 //
 // Peak widths that grow with angle (Caglioti, Paoletti and Ricci, Nucl.
 // Instrum. 3 (1958) 223): the broadened pattern with FWHM^2 = U tan^2(theta)
-// + V tan(theta) + W per reflection instead of one width.
+// + V tan(theta) + W per reflection instead of one width, and pseudo-Voigt
+// profiles eta L + (1 - eta) G: a unit-area Lorentzian and a unit-area
+// Gaussian of that FWHM, both cut at the window.
 #include <math.h>
 
 #include "xrd_internal.h"
@@ -129,9 +131,11 @@ __device__ int64_t block_lower_bound(const double *__restrict__ keys, int64_t n,
 // 4e-6 relative per term at the window's edge, less nearer the centre), as in
 // the constant-width gather; otherwise exp in double.
 struct CagEnt {
-  double t, w;   // 2theta, intensity / (sigma sqrt(2 pi)) (0: no line)
+  double t, w;   // 2theta, (1 - eta) intensity / (sigma sqrt(2 pi)) (0: no line)
   double z;      // 1 / (2 sigma^2), times log2(e) under MIXED
   double half;   // window * sigma (-1: no line)
+  double wl;     // eta intensity 2 / (pi FWHM): the Lorentzian's peak
+  double ql;     // (2 / FWHM)^2
 };
 
 // Logical block of a launch of g blocks such that consecutive logical blocks
@@ -150,7 +154,8 @@ template <bool MIXED>
 __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
     const CrystalPlan *__restrict__ plan, const int64_t *__restrict__ refl_offset, bool friedel,
     const double *__restrict__ ent_key, const int32_t *__restrict__ ent_idx, const double *__restrict__ inten,
-    double t0, double dt, int64_t n, double U, double V, double W, double window, double *__restrict__ y) {
+    double t0, double dt, int64_t n, double U, double V, double W, double eta, double window,
+    double *__restrict__ y) {
   __shared__ CagEnt s_ent[kThreads];
   const int64_t blocks_per = (n + kThreads - 1) / kThreads;
   const int64_t lb = xcd_block(blockIdx.x, gridDim.x);
@@ -190,13 +195,16 @@ __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
       const double t = keys[e];
       const double tn = tan(t * rad);
       const double q = f2(tn);
-      CagEnt v{t, 0.0, 0.0, -1.0};
+      CagEnt v{t, 0.0, 0.0, -1.0, 0.0, 0.0};
       if (q > 0.0) {
-        const double sigma = sqrt(q) * fw;
-        v.w = m * inten[ent_idx[base + e]] / (sigma * sqrt(2.0 * 3.14159265358979323846));
+        const double gam = sqrt(q), sigma = gam * fw;
+        const double mi = m * inten[ent_idx[base + e]];
+        v.w = (1.0 - eta) * mi / (sigma * sqrt(2.0 * 3.14159265358979323846));
         v.z = 1.0 / (2.0 * sigma * sigma);
         if constexpr (MIXED) v.z *= 1.44269504088896340736;  // log2(e)
         v.half = window * sigma;
+        v.wl = eta * mi * 2.0 / (3.14159265358979323846 * gam);
+        v.ql = 4.0 / q;
       }
       s_ent[threadIdx.x] = v;
     }
@@ -213,15 +221,32 @@ __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
       j0 += __popcll(__ballot(in && t < xw_lo));
       j1 += __popcll(__ballot(in && !(t > xw_hi)));
     }
-    for (int j = j0; j < j1; ++j) {
-      const CagEnt v = s_ent[j];
-      const double d = x - v.t;
-      if (fabs(d) <= v.half) {
-        if constexpr (MIXED) {
-          const float df = (float)d;
-          acc = fma(v.w, (double)__builtin_amdgcn_exp2f(-(df * df) * (float)v.z), acc);
-        } else {
-          acc += v.w * exp(-(d * d) * v.z);
+    if (eta == 0.0) {
+      for (int j = j0; j < j1; ++j) {
+        const CagEnt v = s_ent[j];
+        const double d = x - v.t;
+        if (fabs(d) <= v.half) {
+          if constexpr (MIXED) {
+            const float df = (float)d;
+            acc = fma(v.w, (double)__builtin_amdgcn_exp2f(-(df * df) * (float)v.z), acc);
+          } else {
+            acc += v.w * exp(-(d * d) * v.z);
+          }
+        }
+      }
+    } else {
+      for (int j = j0; j < j1; ++j) {
+        const CagEnt v = s_ent[j];
+        const double d = x - v.t;
+        if (fabs(d) <= v.half) {
+          if constexpr (MIXED) {
+            const float df = (float)d, d2 = df * df;
+            const float g = __builtin_amdgcn_exp2f(-d2 * (float)v.z);
+            const float lz = __builtin_amdgcn_rcpf(fmaf(d2, (float)v.ql, 1.0f));
+            acc = fma(v.w, (double)g, fma(v.wl, (double)lz, acc));
+          } else {
+            acc += v.wl / (1.0 + (d * d) * v.ql) + v.w * exp(-(d * d) * v.z);
+          }
         }
       }
     }
@@ -233,16 +258,16 @@ __global__ __launch_bounds__(kThreads) void k_broaden_caglioti(
 
 void launch_broaden_caglioti(bool mixed, const CrystalPlan *plan, int64_t n_c, const int64_t *refl_offset,
                              bool friedel, const double *ent_key, const int32_t *ent_idx, const double *inten,
-                             double t0, double dt, int64_t n, double U, double V, double W, double window, double *y,
-                             hipStream_t s) {
+                             double t0, double dt, int64_t n, double U, double V, double W, double eta, double window,
+                             double *y, hipStream_t s) {
   if (n_c <= 0 || n <= 0) return;
   const int64_t blocks = n_c * ((n + kThreads - 1) / kThreads);
   if (mixed)
     hipLaunchKernelGGL(k_broaden_caglioti<true>, dim3((unsigned)blocks), dim3(kThreads), 0, s, plan, refl_offset,
-                       friedel, ent_key, ent_idx, inten, t0, dt, n, U, V, W, window, y);
+                       friedel, ent_key, ent_idx, inten, t0, dt, n, U, V, W, eta, window, y);
   else
     hipLaunchKernelGGL(k_broaden_caglioti<false>, dim3((unsigned)blocks), dim3(kThreads), 0, s, plan, refl_offset,
-                       friedel, ent_key, ent_idx, inten, t0, dt, n, U, V, W, window, y);
+                       friedel, ent_key, ent_idx, inten, t0, dt, n, U, V, W, eta, window, y);
 }
 
 void launch_march_dollase(const HChunk *chunks, int64_t n_chunks, const CrystalPlan *plan,

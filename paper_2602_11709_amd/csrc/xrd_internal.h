@@ -276,8 +276,8 @@ void launch_noise(int64_t total, uint64_t seed, double rel, double abs_, double 
 // evaluated half under Friedel pairing, weight 2, else every reflection).
 void launch_broaden_caglioti(bool mixed, const CrystalPlan *plan, int64_t n_c, const int64_t *refl_offset, bool friedel,
                              const double *ent_key, const int32_t *ent_idx, const double *inten, double t0,
-                             double dt, int64_t n, double U, double V, double W, double window, double *y,
-                             hipStream_t s);
+                             double dt, int64_t n, double U, double V, double W, double eta, double window,
+                             double *y, hipStream_t s);
 // Atom gradients reduced over their partial rows and scattered to the
 // caller's order, and, in the same launch, dL/d(lattice) of every crystal
 // from its per-tile dL/dG* rows (written by launch_sf_bw).

@@ -189,10 +189,11 @@ def test_new_device_calls_validate_before_any_launch():
         assert lib.xrd_peak_families(h, fake, C.byref(r), C.byref(p), 1, fake, None, fake, fake) == ok
         assert lib.xrd_peak_families(h, fake, C.byref(r), None, 1, fake, fake, fake, fake) == ok
         g = capi.xrd_grid(10.0, 0.02, 100, 0.1, 8.0)
-        assert lib.xrd_pattern_caglioti(h, fake, C.byref(r), fake, C.byref(g), float("nan"), 0.0, 0.01, fake) == ok
-        assert lib.xrd_pattern_caglioti(h, fake, C.byref(r), None, C.byref(g), 0.0, 0.0, 0.01, fake) == ok
+        assert lib.xrd_pattern_caglioti(h, fake, C.byref(r), fake, C.byref(g), float("nan"), 0.0, 0.01, 0.0, fake) == ok
+        assert lib.xrd_pattern_caglioti(h, fake, C.byref(r), None, C.byref(g), 0.0, 0.0, 0.01, 0.0, fake) == ok
+        assert lib.xrd_pattern_caglioti(h, fake, C.byref(r), fake, C.byref(g), 0.0, 0.0, 0.01, 1.5, fake) == ok
         bad = capi.xrd_grid(10.0, 0.0, 100, 0.1, 8.0)  # dt = 0
-        assert lib.xrd_pattern_caglioti(h, fake, C.byref(r), fake, C.byref(bad), 0.0, 0.0, 0.01, fake) == ok
+        assert lib.xrd_pattern_caglioti(h, fake, C.byref(r), fake, C.byref(bad), 0.0, 0.0, 0.01, 0.0, fake) == ok
         assert lib.xrd_preferred_orientation(h, fake, C.byref(r), None, fake, fake) == ok
         assert "non-NULL" in lib.xrd_last_error().decode() or lib.xrd_last_error()
     finally:

@@ -111,13 +111,15 @@ def test_noise_matches_definition_and_seed():
     assert not np.array_equal(y3.cpu().numpy(), got)
 
 
-@pytest.mark.parametrize("precision,friedel,uvw", [
-    ("mixed", True, (0.03, -0.01, 0.004)), ("fp64", False, (0.03, -0.01, 0.004)),
+@pytest.mark.parametrize("precision,friedel,uvw,eta", [
+    ("mixed", True, (0.03, -0.01, 0.004), 0.0), ("fp64", False, (0.03, -0.01, 0.004), 0.0),
     # FWHM^2 <= 0 below 2theta ~ 11.4 deg: those lines add nothing
-    ("fp64", True, (0.05, 0.0, -0.0005)),
+    ("fp64", True, (0.05, 0.0, -0.0005), 0.0),
     # widest line at the quadratic's vertex (tan theta = 0.75, 2theta ~ 73.7 deg), not at an end
-    ("mixed", False, (-0.02, 0.03, 0.002))])
-def test_caglioti_pattern(precision, friedel, uvw):
+    ("mixed", False, (-0.02, 0.03, 0.002), 0.0),
+    # pseudo-Voigt profiles
+    ("mixed", True, (0.03, -0.01, 0.004), 0.4), ("fp64", True, (0.03, -0.01, 0.004), 1.0)])
+def test_caglioti_pattern(precision, friedel, uvw, eta):
     """Widths growing with angle, against the oracle's broadening of the GPU's
     own reflections and intensities, on crystals of every sort size (the
     largest sorted in global memory) and a grid cut at both ends."""
@@ -128,18 +130,19 @@ def test_caglioti_pattern(precision, friedel, uvw):
     xb = XrdBatch(b, precision=precision, friedel=friedel)
     refl = xb.enumerate()
     _, _, I = xb.structure_factors(refl)
-    y = xb.pattern_caglioti(refl, I, grid, U, V, W)
+    y = xb.pattern_caglioti(refl, I, grid, U, V, W, eta=eta)
     torch.cuda.synchronize()
     ro, _ = xb.read_counts(refl)
     n = int(ro[-1])
     tt, Ih, yh = refl.two_theta[:n].cpu().numpy(), I[:n].cpu().numpy(), y.cpu().numpy()
     for c in range(b.n_crystals):
         sl = slice(int(ro[c]), int(ro[c + 1]))
-        want = oracle.broaden_caglioti(tt[sl], Ih[sl], grid.t0, grid.dt, grid.n_points, U, V, W, grid.window_sigmas)
+        want = oracle.broaden_caglioti(tt[sl], Ih[sl], grid.t0, grid.dt, grid.n_points, U, V, W, grid.window_sigmas,
+                                       eta=eta)
         err = np.max(np.abs(yh[c] - want)) / max(np.max(np.abs(want)), 1e-300)
         tol = 1e-12 if precision == "fp64" else 1e-5  # single-precision exponentials under mixed
         assert err <= tol, f"crystal {c}: {err:.3e}"
     # repeat: bit for bit
-    y2 = xb.pattern_caglioti(refl, I, grid, U, V, W)
+    y2 = xb.pattern_caglioti(refl, I, grid, U, V, W, eta=eta)
     torch.cuda.synchronize()
     assert torch.equal(y, y2)
