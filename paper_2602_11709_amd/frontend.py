@@ -161,9 +161,15 @@ def get_pattern(lattice, frac, species, sf_coeff, occ=None, bfac=None, wavelengt
 
 
 def broadened_pattern(batch: CrystalBatch, grid, wavelength: Union[float, str] = "CuKa",
-                      precision: str = "mixed", device="cuda"):
+                      precision: str = "mixed", device="cuda", widths: Optional[Sequence[float]] = None,
+                      eta: float = 0.0):
     """[n_crystals, n_points] broadened pattern of ``batch`` on ``grid``
-    (api.Grid): the weighted sum over the wavelength's emission lines."""
+    (api.Grid): the weighted sum over the wavelength's emission lines.  With
+    ``widths`` = (U, V, W) each line has the angle-dependent FWHM^2 = U tan^2
+    + V tan + W (Caglioti) and a pseudo-Voigt profile of Lorentzian share
+    ``eta``, instead of the grid's one Gaussian width."""
+    if widths is None and eta != 0.0:
+        raise ValueError("eta needs widths (U, V, W)")
     import torch
     from .api import XrdBatch
     y = None
@@ -172,7 +178,11 @@ def broadened_pattern(batch: CrystalBatch, grid, wavelength: Union[float, str] =
                       grid_capacity=grid.n_points)
         refl = xb.enumerate()
         _, _, I = xb.structure_factors(refl)
-        part = xb.pattern_forward(refl, I, grid)
+        if widths is None:
+            part = xb.pattern_forward(refl, I, grid)
+        else:
+            U, V, W = (float(v) for v in widths)
+            part = xb.pattern_caglioti(refl, I, grid, U, V, W, eta=eta)
         y = weight * part if y is None else y + weight * part
     torch.cuda.synchronize()
     return y

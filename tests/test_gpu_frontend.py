@@ -108,6 +108,32 @@ def test_broadened_doublet():
         assert err <= 2e-5, f"crystal {c}: {err:.3e}"
 
 
+def test_broadened_doublet_pseudo_voigt():
+    """K-alpha1 + K-alpha2 with Caglioti widths and pseudo-Voigt profiles,
+    against the oracle's reflections broadened the same way per line."""
+    from paper_2602_11709_amd.api import Grid
+    b = synth.random_triclinic(82, 5, atoms_hi=40)
+    grid = Grid(10.0, 0.02, 4001, 0.1, 12.0)
+    uvw, eta = (0.02, -0.005, 0.004), 0.3
+    y = frontend.broadened_pattern(b, grid, "CuKa12", precision="fp64", widths=uvw, eta=eta).cpu().numpy()
+    for c in range(b.n_crystals):
+        want = 0.0
+        for lam, w, _ in frontend.lines_of("CuKa12"):
+            bl = dataclasses.replace(b, wavelength=lam)
+            hkl, q, tt, _ = oracle.enumerate_hkl(bl.lattice[c], lam, float(bl.two_theta_min[c]),
+                                                 float(bl.two_theta_max[c]))
+            sl = bl.atoms_of(c)
+            fr, fi, _ = oracle.structure_factors(hkl, q, bl.frac[sl], bl.species[sl], bl.occ[sl], bl.bfac[sl],
+                                                 bl.sf_coeff)
+            inten = (fr * fr + fi * fi) * np.array([oracle.lp(t) for t in tt])
+            want = want + w * oracle.broaden_caglioti(tt, inten, grid.t0, grid.dt, grid.n_points, *uvw,
+                                                      grid.window_sigmas, eta=eta)
+        err = np.max(np.abs(y[c] - want)) / max(np.max(np.abs(want)), 1e-300)
+        assert err <= 1e-10, f"crystal {c}: {err:.3e}"
+    with pytest.raises(ValueError):
+        frontend.broadened_pattern(b, grid, "CuKa", eta=0.5)
+
+
 def test_hexagonal_family_labels():
     """Hexagonal cell: {100} and {110} lines of 6 members each, labelled in
     Miller-Bravais form; their members stay 3-index."""
