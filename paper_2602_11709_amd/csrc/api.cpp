@@ -16,6 +16,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/xrd.h"
@@ -252,8 +253,10 @@ int check_refl(const xrd_refl *r) {
 // tiles first).  The first n_heavy items take a block each and the rest four
 // to a block, so slot i of the heavy part and the four slots of light block j
 // draw from the queue of the XCD their block lands on; when that queue is
-// empty, from the longest other one.
-void xcd_group(const xrd_batch *b, int64_t n_heavy, std::vector<SfItem> *items) {
+// empty, from the longest other one.  Only the expected-filled items
+// [0, n_expected) are regrouped: the tail of capacity tiles, which mostly find
+// no reflection and end at once, keeps its order.
+void xcd_group(const xrd_batch *b, int64_t n_heavy, int64_t n_expected, std::vector<SfItem> *items) {
   constexpr int kXcd = 8;
   const int64_t nc = (int64_t)b->plan.size();
   std::vector<int> xcd_of(nc, 0);
@@ -295,11 +298,14 @@ void xcd_group(const xrd_batch *b, int64_t n_heavy, std::vector<SfItem> *items) 
     }
   };
   regroup(0, n_heavy, 1, 0);
-  regroup(n_heavy, (int64_t)items->size(), 4, n_heavy);  // four wavefronts to a light block
+  regroup(n_heavy, n_expected, 4, n_heavy);  // four wavefronts to a light block
 }
 
 int64_t sf_table(const xrd_batch *b, int32_t split, std::vector<SfItem> *items) {
   items->clear();
+  int64_t cap = 0;
+  for (const CrystalPlan &P : b->plan) cap += P.n_tiles;
+  items->reserve((size_t)cap);
   auto item = [&](int32_t c, int32_t t) {
     const CrystalPlan &P = b->plan[c];
     return SfItem{c, t, (int32_t)P.atom_begin, (int32_t)P.atom_end, (int32_t)P.run_begin, {0, 0, 0}};
@@ -312,11 +318,12 @@ int64_t sf_table(const xrd_batch *b, int32_t split, std::vector<SfItem> *items) 
   for (int32_t c : b->sf_order)
     if (!heavy(c))
       for (int32_t t = 0; t < b->sf_likely[c]; ++t) items->push_back(item(c, t));
+  const int64_t n_expected = (int64_t)items->size();
   for (int pass = 0; pass < 2; ++pass)
     for (int32_t c : b->sf_order)
       if (heavy(c) == (pass == 0))
         for (int32_t t = b->sf_likely[c]; t < b->plan[c].n_tiles; ++t) items->push_back(item(c, t));
-  xcd_group(b, n_heavy, items);
+  xcd_group(b, n_heavy, n_expected, items);
   return n_heavy;
 }
 
@@ -390,7 +397,6 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
       return fail(XRD_ERR_INVALID_CELL, "crystal " + std::to_string(c) + ": invalid cell");
     }
     for (int i = 0; i < 6; ++i) P.lat[i] = lat[i];
-    b->fam_ops[c] = family_ops(P.gs);
     P.tmin = b->tmin[c];
     P.tmax = b->tmax[c];
     const double gmax = 2.0 * std::sin(0.5 * P.tmax * kPi / 180.0) / lam;
@@ -421,9 +427,6 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
       delete b;
       return fail(XRD_ERR_CAPACITY, "reflection capacity exceeds 2^31; split the batch");
     }
-    P.enum_chunk_begin = ec;
-    P.enum_chunks = enum_chunks_of(P, (int32_t)c, &b->enum_chunks);
-    ec += P.enum_chunks;
     P.sort_chunk_begin = sc;
     P.sort_chunks = (int32_t)ceil_div(2 * P.half_box, kSortChunk);
     sc += P.sort_chunks;
@@ -453,6 +456,37 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     } else {
       P.part_begin = parts;
       parts += (int64_t)P.n_hchunks * na;
+    }
+  }
+  // the enumeration chunks (a pass over every row of a crystal's search box)
+  // and the lattice operations, crystal by crystal on up to 16 host threads,
+  // then concatenated in crystal order
+  {
+    std::vector<std::vector<EnumChunk>> chunks_of(nc);
+    const int64_t nt = std::max<int64_t>(
+        1, std::min<int64_t>({(int64_t)std::thread::hardware_concurrency(), 16, (nc + 63) / 64}));
+    auto work = [&](int64_t t) {
+      for (int64_t c = t; c < nc; c += nt) {
+        enum_chunks_of(b->plan[c], (int32_t)c, &chunks_of[c]);
+        b->fam_ops[c] = family_ops(b->plan[c].gs);
+      }
+    };
+    std::vector<std::thread> pool;
+    int64_t started = 1;
+    try {
+      for (; started < nt; ++started) pool.emplace_back(work, started);
+    } catch (...) {
+      // no more threads: the shares left over run here
+    }
+    work(0);
+    for (auto &th : pool) th.join();
+    for (int64_t t = started; t < nt; ++t) work(t);
+    for (int64_t c = 0; c < nc; ++c) {
+      CrystalPlan &P = b->plan[c];
+      P.enum_chunk_begin = ec;
+      P.enum_chunks = (int32_t)chunks_of[c].size();
+      ec += P.enum_chunks;
+      b->enum_chunks.insert(b->enum_chunks.end(), chunks_of[c].begin(), chunks_of[c].end());
     }
   }
   b->refl_cap = refl;
