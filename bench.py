@@ -390,7 +390,8 @@ def main():
             "graph": graph, "parallelism": "single GPU"},
         "sf_terms_per_s": round(mx["terms"] / (mx["ms"] * 1e-3), 1),
         "stages_ms": mx["stages"],
-        "host_plan_ms": round(mx["p"].plan_ms, 3),
+        "host_plan_ms": round(mx["p"].xb.plan_ms, 3),
+        "batch_setup_ms": round(mx["p"].plan_ms, 3),
         "peak_families": fam,
         "augmentation": aug,
         "kalpha_doublet": None if dbl_ms is None else {

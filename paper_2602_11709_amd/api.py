@@ -11,6 +11,7 @@ whose backward is the library's hand-written adjoint.
 from __future__ import annotations
 
 import dataclasses
+import time
 from typing import Optional
 
 import numpy as np
@@ -132,7 +133,9 @@ class XrdBatch:
         d.stream = self.stream.cuda_stream
         self.desc = d
         self.handle = None
+        t_plan = time.perf_counter()
         self.handle = capi.xrd_batch_create(d)
+        self.plan_ms = (time.perf_counter() - t_plan) * 1e3  # host planning alone
         self.sizes = capi.xrd_batch_sizes(self.handle)
         nb = int(self.sizes.workspace_bytes)
         self._ws_raw = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
