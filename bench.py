@@ -311,7 +311,7 @@ def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the batch would shard by "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the batch would shard by "
               "crystal with no exchange); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
