@@ -21,7 +21,7 @@ _SRC = os.path.join(_HERE, "xrd_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 __all__ = [
-    "build", "cell", "q_of", "two_theta", "lp", "fsc", "enumerate_hkl",
+    "build", "cell", "q_of", "two_theta", "lp", "lp_many", "fsc", "enumerate_hkl",
     "structure_factors", "sort_order", "merge", "broaden", "OracleCrystal",
     "pattern", "pattern_batch", "broadened", "loss", "march_dollase", "splitmix64", "gauss", "noise",
     "broaden_caglioti", "FAM_INDICES", "FAM_LATTICE", "is_hexagonal", "lattice_ops", "peak_families",
@@ -77,6 +77,8 @@ def _get():
         lib.orc_two_theta.restype = C.c_double
         lib.orc_lp.argtypes = [C.c_double]
         lib.orc_lp.restype = C.c_double
+        lib.orc_lp_many.argtypes = [C.c_long, _dp, _dp]
+        lib.orc_lp_many.restype = None
         lib.orc_fsc.argtypes = [_dp, C.c_double]
         lib.orc_fsc.restype = C.c_double
         lib.orc_enumerate.argtypes = [_dp, C.c_double, C.c_double, C.c_double, C.c_long,
@@ -152,6 +154,14 @@ def two_theta(q, wavelength):
 
 def lp(two_theta_deg):
     return _get().orc_lp(float(two_theta_deg))
+
+
+def lp_many(two_theta_deg):
+    """lp of every angle of an array."""
+    tt = _f64(two_theta_deg).reshape(-1)
+    out = np.zeros(max(len(tt), 1))
+    _get().orc_lp_many(len(tt), tt if len(tt) else np.zeros(1), out)
+    return out[:len(tt)]
 
 
 def fsc(coeff, s2):
@@ -319,7 +329,7 @@ def broadened(batch, c: int, t0: float, dt: float, npts: int, sigma: float, wind
     sl = batch.atoms_of(c)
     fr, fi, _ = structure_factors(hkl, q, batch.frac[sl], batch.species[sl], batch.occ[sl],
                                   batch.bfac[sl], batch.sf_coeff)
-    inten = (fr * fr + fi * fi) * np.array([lp(t) for t in tt])
+    inten = (fr * fr + fi * fi) * lp_many(tt)
     return broaden(tt, inten, t0, dt, npts, sigma, window)
 
 

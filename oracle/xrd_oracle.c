@@ -96,6 +96,12 @@ double orc_lp(double two_theta)
     return (1.0 + c2 * c2) / (st * st * ct);
 }
 
+/* orc_lp of each of n angles (a loop, for callers holding arrays). */
+void orc_lp_many(long n, const double *two_theta, double *out)
+{
+    for (long i = 0; i < n; ++i) out[i] = orc_lp(two_theta[i]);
+}
+
 /* Cromer-Mann scattering factor at s^2 = (sin(theta)/lambda)^2. */
 double orc_fsc(const double coeff[9], double s2)
 {

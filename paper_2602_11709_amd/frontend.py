@@ -36,14 +36,18 @@ import numpy as np
 from .synth import CrystalBatch
 
 # K-alpha1 and K-alpha2 emission lines (Angstrom; Deslattes et al., Rev. Mod.
-# Phys. 75, 35 (2003)); K-alpha is their 2:1 intensity-weighted mean.
+# Phys. 75, 35 (2003)), K-alpha2 weighted by KA2_RATIO.  The single-line
+# names "CuKa" and "MoKa" are the conventional single K-alpha wavelengths
+# 1.54184 and 0.71073 Angstrom (the values the synthetic workloads use), not
+# computed from the doublet.
 KA2_RATIO = 0.5
 _LINES = {"Cu": (1.5405929, 1.5444274), "Mo": (0.7093171, 0.7135900)}
+_SINGLE = {"Cu": 1.54184, "Mo": 0.71073}
 WAVELENGTHS = {}
 for _el, (_a1, _a2) in _LINES.items():
     WAVELENGTHS[_el + "Ka1"] = _a1
     WAVELENGTHS[_el + "Ka2"] = _a2
-    WAVELENGTHS[_el + "Ka"] = (_a1 + KA2_RATIO * _a2) / (1.0 + KA2_RATIO)
+    WAVELENGTHS[_el + "Ka"] = _SINGLE[_el]
 
 
 def lines_of(wavelength: Union[float, str]):

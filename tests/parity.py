@@ -114,3 +114,59 @@ def compare_batch(res, batch, orcs, precision, label=""):
                 worst[k] = max(worst.get(k, 0.0), v)
         worst["ambiguous"] += st.get("ambiguous", 0)
     return worst
+
+
+def compare_crystal_sampled(res, c, batch, precision, rng, n_sample=400, n_strong=60, label=""):
+    """Parity of crystal ``c`` of a PatternResult when the oracle cannot sum
+    every structure factor in seconds: the reflection list and the peak
+    partition exactly (partition against the oracle's sort and merge of the
+    GPU's own 2theta, and against the oracle's 2theta away from ambiguous
+    comparisons), structure factors on ``n_sample`` random reflections and
+    intensities of ``n_strong`` random strong peaks summed from the oracle's
+    member structure factors."""
+    tag = f"{label} crystal {c}"
+    rs, ps = res.crystal(c)
+    sl = batch.atoms_of(c)
+    hkl, q, tt, amb = oracle.enumerate_hkl(batch.lattice[c], batch.wavelength, float(batch.two_theta_min[c]),
+                                           float(batch.two_theta_max[c]))
+    n = len(tt)
+    assert rs.stop - rs.start == n, f"{tag}: {rs.stop - rs.start} reflections vs oracle {n}"
+    np.testing.assert_array_equal(res.hkl[rs], hkl, err_msg=f"{tag}: hkl list")
+    assert np.max(np.abs(res.two_theta[rs] - tt)) <= 1e-9, f"{tag}: 2theta"
+    tt_g = res.two_theta[rs]
+    hkl_g = res.hkl[rs]
+    perm = res.perm[rs] - rs.start
+    np.testing.assert_array_equal(perm, oracle.sort_order(tt_g, hkl_g), err_msg=f"{tag}: sorted order")
+    g_tt, _, g_m, g_f, _ = oracle.merge(tt_g[perm], np.zeros(n), batch.merge_tol)
+    first = res.pk_first[ps] - rs.start
+    np.testing.assert_array_equal(res.pk_mult[ps], g_m, err_msg=f"{tag}: multiplicity")
+    np.testing.assert_array_equal(first, g_f, err_msg=f"{tag}: peak first member")
+    np.testing.assert_array_equal(res.pk_two_theta[ps], g_tt, err_msg=f"{tag}: peak 2theta")
+    po = oracle.sort_order(tt, hkl)
+    _, _, _, o_f, amb_gap = oracle.merge(tt[po], np.zeros(n), batch.merge_tol)
+    if amb_gap == 0 and amb == 0:
+        np.testing.assert_array_equal(first, o_f, err_msg=f"{tag}: partition vs oracle 2theta")
+    else:
+        differ = len(set(first.tolist()) ^ set(o_f.tolist()))
+        assert differ <= 2 * (amb_gap + amb), f"{tag}: partition differs beyond the ambiguous comparisons"
+    args = (batch.frac[sl], batch.species[sl], batch.occ[sl], batch.bfac[sl], batch.sf_coeff)
+    pick = rng.choice(n, size=min(n_sample, n), replace=False)
+    fr, fi, aw = oracle.structure_factors(hkl[pick], q[pick], *args)
+    bound = F_REL[precision] * aw
+    eA = np.abs(res.A[rs][pick] - fr)
+    eB = np.abs(res.B[rs][pick] - fi)
+    assert np.all(eA <= bound) and np.all(eB <= bound), f"{tag}: sampled F"
+    stats = {"n_refl": n, "F_err_over_absw": float(np.max(np.maximum(eA, eB) / aw))}
+    pki = res.pk_intensity[ps]
+    if len(pki) and pki.max() > 0:
+        strong = np.nonzero(pki >= 1e-3 * pki.max())[0]
+        worst = 0.0
+        for p in rng.choice(strong, size=min(n_strong, len(strong)), replace=False):
+            mem = perm[first[p]: first[p] + res.pk_mult[ps][p]]
+            fr, fi, _ = oracle.structure_factors(hkl[mem], q[mem], *args)
+            lpv = np.array([oracle.lp(t) for t in tt[mem]])
+            want = float(((fr * fr + fi * fi) * lpv).sum())
+            worst = max(worst, abs(pki[p] - want) / want)
+        assert worst <= (1e-4 if precision == "mixed" else 1e-10), f"{tag}: strong peaks {worst:.3g}"
+        stats["peak_rel_err"] = worst
+    return stats

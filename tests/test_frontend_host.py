@@ -8,16 +8,20 @@ from paper_2602_11709_amd import frontend, synth
 
 
 def test_emission_lines():
+    # published values, written out here rather than read from the package
+    assert frontend.WAVELENGTHS["CuKa1"] == 1.5405929 and frontend.WAVELENGTHS["CuKa2"] == 1.5444274
+    assert frontend.WAVELENGTHS["MoKa1"] == 0.7093171 and frontend.WAVELENGTHS["MoKa2"] == 0.7135900
+    # the single K-alpha lines are the conventional values the workloads use
+    assert frontend.WAVELENGTHS["CuKa"] == 1.54184 == synth.CU_KA
+    assert frontend.WAVELENGTHS["MoKa"] == 0.71073 == synth.MO_KA
+    assert frontend.KA2_RATIO == 0.5
     for el in ("Cu", "Mo"):
         a1, a2, ka = (frontend.WAVELENGTHS[el + s] for s in ("Ka1", "Ka2", "Ka"))
         assert a1 < ka < a2
-        assert ka == pytest.approx((a1 + frontend.KA2_RATIO * a2) / (1 + frontend.KA2_RATIO), rel=1e-15)
-    # the weighted Cu K-alpha is the conventional 1.5418 A to within 1e-4 A
-    assert abs(frontend.WAVELENGTHS["CuKa"] - 1.5418) < 1e-4
-    assert frontend.lines_of("CuKa12") == [(frontend.WAVELENGTHS["CuKa1"], 1.0, "a1"),
-                                           (frontend.WAVELENGTHS["CuKa2"], frontend.KA2_RATIO, "a2")]
+    assert frontend.lines_of("CuKa12") == [(1.5405929, 1.0, "a1"), (1.5444274, 0.5, "a2")]
+    assert frontend.lines_of("MoKa12") == [(0.7093171, 1.0, "a1"), (0.7135900, 0.5, "a2")]
     assert frontend.lines_of(1.2) == [(1.2, 1.0, "")]
-    assert frontend.lines_of("MoKa") == [(frontend.WAVELENGTHS["MoKa"], 1.0, "")]
+    assert frontend.lines_of("MoKa") == [(0.71073, 1.0, "")]
     for bad in ("XxKa", "CuKb", -1.0, 0.0):
         with pytest.raises(ValueError):
             frontend.lines_of(bad)

@@ -61,8 +61,9 @@ def sse(b, c, target, p):
     return float(d @ d)
 
 
-def fd(p, targets, c, kind, idx, direction=None):
+def fd(p, targets, c, kind, idx, direction=None, h=None):
     """Central difference of the loss in one parameter (or a direction)."""
+    H = globals()["H"] if h is None else h
     scale = 1.0 / (p.batch.n_crystals * p.grid_n)
     vals = []
     for sgn in (+1, -1):
@@ -227,3 +228,150 @@ def test_kept_derivatives_match_recomputed(precision):
         rel = np.linalg.norm(a - b) / np.linalg.norm(a)
         print(precision, name, "kept vs recomputed rel", rel, flush=True)
         assert rel <= bar, name
+
+
+def _fd_direction_pool(p, targets, crystals, directions, threads=16, h=None):
+    """Central differences of each crystal's SSE along its direction, crystals
+    in parallel on host threads (the oracle releases the GIL in its C calls)."""
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda c: fd(p, targets, c, "direction", None, directions[c], h), crystals))
+
+
+def _targets_pool(p, threads=16):
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(max_workers=threads) as ex:
+        return list(ex.map(lambda c: oracle.broadened(p.target, c, *grid_args(p)), range(p.target.n_crystals)))
+
+
+def _directions(p, seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(p.batch.n_crystals):
+        sl = p.batch.atoms_of(c)
+        n = sl.stop - sl.start
+        out.append((rng.normal(size=(n, 3)), rng.normal(size=6), rng.normal(size=n)))
+    return out
+
+
+def _batch_grads(p, targets, precision, keep):
+    """dL/d(frac, lattice, B) of the MSE loss through the library's calls
+    directly, with or without the structure-factor derivatives kept by the
+    forward (the adjoint then takes them from the workspace, or sums over the
+    atoms again)."""
+    from paper_2602_11709_amd.api import Grid, XrdBatch
+    grid = Grid(p.grid_t0, p.grid_dt, p.grid_n, p.sigma, p.window_sigmas)
+    xb = XrdBatch(p.batch, precision=precision, grid_capacity=p.grid_n, keep_sf_derivs=keep)
+    refl = xb.enumerate()
+    _, _, I = xb.structure_factors(refl)
+    y = xb.pattern_forward(refl, I, grid)
+    T = torch.tensor(np.stack(targets), device="cuda")
+    dy = (2.0 / (p.batch.n_crystals * p.grid_n)) * (y - T)
+    gf, gb, gl = xb.pattern_backward(refl, grid, dy.contiguous())
+    torch.cuda.synchronize()
+    return gf.cpu().numpy(), gl.cpu().numpy(), gb.cpu().numpy()
+
+
+def _directional(p, grads, directions, c):
+    gf, gl, gb = grads
+    sl = p.batch.atoms_of(c)
+    dfr, dla, dbf = directions[c]
+    return float((gf[sl] * dfr).sum() + (gl[c] * dla).sum() + (gb[sl] * dbf).sum())
+
+
+@pytest.fixture(scope="module")
+def large_atom_problem():
+    """Two crystals above the fused-gradient size (600-1200 atoms: 1019 and
+    690), so their atom gradients take the atom-major adjoint pass (several
+    atom blocks, the last one ragged and sliced over the block's threads);
+    a coarse 801-point grid keeps the oracle's finite differences short."""
+    p = problem(2, 600, 1200, grid_n=801, seed=41)
+    targets = _targets_pool(p)
+    directions = _directions(p, 2)
+    want = _fd_direction_pool(p, targets, range(2), directions)
+    return p, targets, directions, want
+
+
+@pytest.mark.parametrize("keep", [True, False])
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-7), ("mixed", 1e-4)])
+def test_atom_major_adjoint_matches_finite_differences(large_atom_problem, precision, bar, keep):
+    p, targets, directions, want = large_atom_problem
+    sizes = np.diff(p.batch.atom_offset)
+    assert np.all(sizes > 512) and np.any(sizes % 256 != 0)
+    grads = _batch_grads(p, targets, precision, keep)
+    for c in range(p.batch.n_crystals):
+        got = _directional(p, grads, directions, c)
+        rel = abs(got - want[c]) / abs(want[c])
+        print(precision, "keep", keep, "crystal", c, "atoms", int(sizes[c]), "directional rel err", rel, flush=True)
+        assert rel <= bar
+    # and single components: a few atoms' coordinates and B of the larger crystal
+    gf, gl, gb = grads
+    rng = np.random.default_rng(3)
+    sl = p.batch.atoms_of(0)
+    got, exp = [], []
+    for j in rng.choice(np.arange(sl.start, sl.stop), size=3, replace=False):
+        d = int(rng.integers(3))
+        got += [gf[j, d], gb[j]]
+        exp += [fd(p, targets, 0, "frac", (j, d)), fd(p, targets, 0, "bfac", j)]
+    err = np.linalg.norm(np.array(got) - np.array(exp)) / np.linalg.norm(exp)
+    print(precision, "keep", keep, "component rel err", err, flush=True)
+    assert err <= bar
+
+
+@pytest.fixture(scope="module")
+def differentiation_workload():
+    """The full differentiation workload (256 crystals of 50-500 atoms, 4001
+    grid points): targets and the oracle's central differences along one
+    random direction per crystal at h = 1e-6, and at h/2 and 2h to bound the
+    differences' own error, computed once for both precisions."""
+    p = synth.gradient_problem()
+    targets = _targets_pool(p)
+    directions = _directions(p, 9)
+    crystals = range(p.batch.n_crystals)
+    fds = [np.array(_fd_direction_pool(p, targets, crystals, directions, h=f * H)) for f in (1.0, 0.5, 2.0)]
+    return p, targets, directions, fds
+
+
+@pytest.mark.parametrize("precision,bar", [("fp64", 1e-7), ("mixed", 1e-4)])
+def test_directional_derivative_every_crystal_of_full_workload(differentiation_workload, precision, bar):
+    """All 256 crystals: the adjoint's derivative along a random direction of
+    each crystal's parameters (frac, lattice, B) against central differences
+    of the oracle's loss (h = 1e-6).  Over the batch, ||g - g_FD|| / ||g_FD||
+    (norm over the 256 crystals) and the median per-crystal relative error
+    meet the bar.
+
+    Per crystal, two effects make the directional derivative itself a poor
+    denominator on a few crystals, where a random direction is nearly
+    orthogonal to the gradient (|g.v| ~1e-3 of its typical size): the
+    central differences carry their own error (rounding in a loss of ~1e17,
+    truncation), bounded here by their largest change when the step is
+    halved or doubled; and the adjoint's error scales with the gradient, not
+    with one projection of it.  So per crystal
+      |g.v - FD| <= bar (|FD| + ||g|| ||v|| / sqrt(n)) + 3 (FD uncertainty),
+    with ||g|| ||v|| / sqrt(n) the root-mean-square size of g.v over random
+    directions v of this norm (n parameters)."""
+    p, targets, directions, fds = differentiation_workload
+    want = fds[0]
+    grads = _batch_grads(p, targets, precision, keep=True)
+    gf, gl, gb = grads
+    got = np.array([_directional(p, grads, directions, c) for c in range(p.batch.n_crystals)])
+    scale = np.empty(p.batch.n_crystals)
+    for c in range(p.batch.n_crystals):
+        sl = p.batch.atoms_of(c)
+        g = np.concatenate([gf[sl].ravel(), gl[c], gb[sl]])
+        v = np.concatenate([d.ravel() for d in directions[c]])
+        scale[c] = np.linalg.norm(g) * np.linalg.norm(v) / np.sqrt(len(v))
+    err = np.abs(got - want)
+    unc = np.maximum(np.abs(fds[1] - want), np.abs(fds[2] - want))
+    rel = err / np.abs(want)
+    total = np.linalg.norm(got - want) / np.linalg.norm(want)
+    sizes = np.diff(p.batch.atom_offset)
+    w = int(np.argmax(rel))
+    ratio = err / (bar * (np.abs(want) + scale) + 3.0 * unc)
+    print(precision, "256 crystals: directional rel err norm", total, "median", np.median(rel), "max", rel.max(),
+          "at crystal", w, "atoms", int(sizes[w]), "|g.v| / rms scale there", abs(want[w]) / scale[w],
+          "its FD uncertainty", unc[w] / abs(want[w]), "crystals above the bar", int(np.sum(rel > bar)),
+          "max err / allowed", float(ratio.max()), "at crystal", int(np.argmax(ratio)), flush=True)
+    assert total <= bar
+    assert np.median(rel) <= bar
+    assert np.all(ratio <= 1.0)

@@ -77,6 +77,28 @@ def test_noise_definition():
     np.testing.assert_array_equal(oracle.noise(y, 99, 0.0, 0.0), y)
 
 
+def test_noise_moments():
+    """Noise added to flat rows: zero mean and the variance of the stated
+    model, (rel sqrt(max(y, 0)) + abs)^2, per row, with the counting term
+    growing with the level and absent below zero, and no correlation between
+    rows.  Pins the definition by its statistics rather than its formula."""
+    n = 100000
+    levels = np.array([25.0, 4.0, -3.0, 0.0])
+    rel, abs_ = 0.1, 0.02
+    y = np.repeat(levels[:, None], n, axis=1)
+    e = oracle.noise(y, 2024, rel, abs_) - y
+    for row, v in enumerate(levels):
+        sd = rel * np.sqrt(max(v, 0.0)) + abs_
+        assert abs(e[row].mean()) <= 5 * sd / np.sqrt(n), row
+        assert e[row].var() == pytest.approx(sd * sd, rel=0.02), row
+        # fourth moment of a normal: 3 sd^4
+        assert np.mean(e[row] ** 4) == pytest.approx(3 * sd ** 4, rel=0.06), row
+    # the -3 and 0 rows both carry only the flat term
+    assert e[2].std() == pytest.approx(abs_, rel=0.02) and e[3].std() == pytest.approx(abs_, rel=0.02)
+    z = e / (rel * np.sqrt(np.maximum(levels, 0.0)) + abs_)[:, None]
+    assert abs(np.corrcoef(z[0], z[1])[0, 1]) < 0.02
+
+
 def test_caglioti_reduces_to_constant_width():
     rng = np.random.default_rng(8)
     tt = np.sort(rng.uniform(15, 80, 40))
