@@ -103,6 +103,8 @@ typedef struct {
     int64_t peak_capacity;   /* == refl_capacity */
     int64_t workspace_bytes; /* device workspace the batch needs, 256-byte aligned base */
     int64_t half_capacity;   /* upper bound on one-per-Friedel-pair reflections */
+    int64_t noalloc_merge_bytes; /* scratch xrd_merge_peaks_noalloc needs for this batch (it
+                                    runs only while this is <= XRD_NOALLOC_SCRATCH_BYTES) */
 } xrd_sizes;
 
 /* Reflection arrays (caller-owned device memory, capacity refl_capacity).
@@ -178,6 +180,28 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
  * them keeping a peak open while 2theta - 2theta(first member) < merge_tol;
  * scale to 0-100 and apply rel_threshold. */
 int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, xrd_peaks *p);
+
+/* Size of the fixed device scratch of xrd_merge_peaks_noalloc (64 MiB per GPU). */
+#define XRD_NOALLOC_SCRATCH_BYTES 67108864
+
+/* xrd_merge_peaks without a workspace argument and without any device
+ * allocation, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same inputs, outputs and results as xrd_merge_peaks.  Its working storage
+ * is a fixed scratch array of XRD_NOALLOC_SCRATCH_BYTES that the library
+ * keeps on each GPU it runs on until the process ends; a batch whose merge
+ * needs more than that (xrd_sizes.noalloc_merge_bytes, about 55 bytes per
+ * reflection of capacity) is rejected with XRD_ERR_CAPACITY before any work is
+ * enqueued.  Each call first copies the batch's merge tables into the scratch
+ * (asynchronous copies from the handle's host memory on the batch's stream)
+ * and runs every kernel on the batch's stream (no side streams).  All calls on
+ * one GPU share that GPU's scratch, which keeps the last call's contents:
+ * calls that overlap on one GPU (several host threads, or several streams
+ * with work in flight) race and give wrong results; serialise them.  A later
+ * xrd_pattern_forward / xrd_pattern_caglioti / xrd_pattern_backward on the
+ * batch sorts again in its own workspace.  The first call on a device looks
+ * up the scratch's device address (no allocation). */
+int xrd_merge_peaks_noalloc(xrd_batch *b, const xrd_refl *r, const double *I, xrd_peaks *p);
 
 /* Gaussian-broadened pattern y [n_crystals * n_points] (row per crystal) of
  * the reflections in ``r`` with intensities I; every reflection contributes

@@ -17,7 +17,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxrd.so")
-SOURCES = ["api.cpp", "scan.hip", "enumerate.hip", "sf.hip", "sortmerge.hip", "broaden.hip", "augment.hip", "family.hip"]
+SOURCES = ["api.cpp", "scan.hip", "enumerate.hip", "sf.hip", "sortmerge.hip", "broaden.hip", "augment.hip", "family.hip",
+           "noalloc.hip"]
 ARCH = "gfx950"
 
 

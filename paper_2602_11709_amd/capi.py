@@ -22,6 +22,7 @@ XRD_ERR_HIP = -4
 XRD_ERR_UNSUPPORTED = -5
 XRD_FP64 = 0
 XRD_MIXED = 1
+XRD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _vp = C.c_void_p
 
@@ -40,7 +41,8 @@ class xrd_batch_desc(C.Structure):
 
 class xrd_sizes(C.Structure):
     _fields_ = [("n_crystals", C.c_int64), ("n_atoms", C.c_int64), ("refl_capacity", C.c_int64),
-                ("peak_capacity", C.c_int64), ("workspace_bytes", C.c_int64), ("half_capacity", C.c_int64)]
+                ("peak_capacity", C.c_int64), ("workspace_bytes", C.c_int64), ("half_capacity", C.c_int64),
+                ("noalloc_merge_bytes", C.c_int64)]
 
 
 class xrd_refl(C.Structure):
@@ -74,6 +76,7 @@ SIGNATURES = {
     "xrd_enumerate_hkl": ([_vp, _vp, C.POINTER(xrd_refl)], C.c_int),
     "xrd_structure_factors": ([_vp, _vp, C.POINTER(xrd_refl), _vp, _vp, _vp], C.c_int),
     "xrd_merge_peaks": ([_vp, _vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_peaks)], C.c_int),
+    "xrd_merge_peaks_noalloc": ([_vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_peaks)], C.c_int),
     "xrd_pattern_forward": ([_vp, _vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_grid), _vp], C.c_int),
     "xrd_pattern_backward": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(xrd_grid), _vp, _vp, _vp, _vp], C.c_int),
     "xrd_autotune": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(C.c_int32)], C.c_int),
@@ -138,6 +141,10 @@ def xrd_structure_factors(batch, ws: int, refl: xrd_refl, A: int, B: int, I: int
 
 def xrd_merge_peaks(batch, ws: int, refl: xrd_refl, I: int, peaks: xrd_peaks):
     check(lib().xrd_merge_peaks(batch, ws, C.byref(refl), I, C.byref(peaks)))
+
+
+def xrd_merge_peaks_noalloc(batch, refl: xrd_refl, I: int, peaks: xrd_peaks):
+    check(lib().xrd_merge_peaks_noalloc(batch, C.byref(refl), I, C.byref(peaks)))
 
 
 def xrd_pattern_forward(batch, ws: int, refl: xrd_refl, I: int, grid: xrd_grid, y: int):

@@ -49,6 +49,7 @@ struct xrd_batch {
   int64_t span_cap = 0;   // span-table entries per crystal: ceil(grid_cap / kSpanPts)
   int runs_cap_max = 1, bw_tile = 64;
   WsLayout ws{};
+  WsLayout mws{};  // the merge's part only, packed (scratch of xrd_merge_peaks_noalloc)
   void *last_ws = nullptr;
   // the (2theta, hkl) order in a workspace is computed once per enumeration:
   // merge and broadening share it (host-side record of the call sequence, so
@@ -642,6 +643,29 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.coeff_f = take((int64_t)sizeof(CoeffF) * d->n_species);
   L.fam_ops = take((int64_t)sizeof(FamOps) * nc);
   L.total = o;
+  // the merge's own tables and scratch, packed on their own for the
+  // allocation-free merge (fields it does not use stay 0)
+  {
+    WsLayout &M = b->mws;
+    o = 0;
+    M.plan = take((int64_t)sizeof(CrystalPlan) * nc);
+    M.peak_chunks = take((int64_t)sizeof(HChunk) * sc);
+    M.crystal_order = take(4 * nc);
+    M.bin_count = take(4 * bins);
+    M.bin_start = take(8 * (bins + 1));
+    M.skey = take(8 * rc);
+    M.sidx = take(4 * rc);
+    M.ent_key = friedel ? take(8 * b->half_cap) : M.skey;
+    M.ent_idx = friedel ? take(4 * b->half_cap) : M.sidx;
+    M.flags = take(4 * rc);
+    M.cmax = take(8 * nc);
+    M.pk_count = take(4 * nc);
+    M.tmp_tt = take(8 * rc);
+    M.tmp_i = take(8 * rc);
+    M.tmp_mult = take(4 * rc);
+    M.tmp_first = take(8 * rc);
+    M.total = o;
+  }
   *out = b;
   g_err.clear();
   return XRD_OK;
@@ -655,6 +679,7 @@ int xrd_batch_sizes(const xrd_batch *b, xrd_sizes *out) {
   out->peak_capacity = b->refl_cap;
   out->workspace_bytes = b->ws.total;
   out->half_capacity = b->half_cap;
+  out->noalloc_merge_bytes = b->mws.total;
   return XRD_OK;
 }
 
@@ -728,7 +753,7 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
   return hip_check("structure_factors");
 }
 
-static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r);
+static SortArgs sort_args(xrd_batch *b, void *ws, const WsLayout &L, const xrd_refl *r);
 
 static void release_side(xrd_batch *b) {
   for (hipEvent_t e : {b->ev_fork, b->ev_join, b->ev_join2})
@@ -766,13 +791,12 @@ static Fork side_of(xrd_batch *b) {
 
 static void ensure_sorted(xrd_batch *b, void *ws, const xrd_refl *r) {
   if (b->sorted_ws == ws && b->sorted_tt == r->two_theta) return;
-  launch_sort(sort_args(b, ws, r), side_of(b), stream_of(b));
+  launch_sort(sort_args(b, ws, b->ws, r), side_of(b), stream_of(b));
   b->sorted_ws = ws;
   b->sorted_tt = r->two_theta;
 }
 
-static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r) {
-  const WsLayout &L = b->ws;
+static SortArgs sort_args(xrd_batch *b, void *ws, const WsLayout &L, const xrd_refl *r) {
   SortArgs a;
   a.n_c = b->desc.n_crystals;
   a.plan = at<CrystalPlan>(ws, L.plan);
@@ -786,7 +810,6 @@ static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r) {
   a.n_bins = b->n_bins;
   a.skey = at<double>(ws, L.skey);
   a.sidx = at<int32_t>(ws, L.sidx);
-  a.scan_part = at<int64_t>(ws, L.scan_part);
   a.order = at<int32_t>(ws, L.crystal_order);
   a.n_mid = b->n_mid;
   a.n_small = b->n_small;
@@ -797,16 +820,20 @@ static SortArgs sort_args(xrd_batch *b, void *ws, const xrd_refl *r) {
   return a;
 }
 
-int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, xrd_peaks *p) {
-  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
-  if (int e = check_ws(b, ws)) return e;
+static int check_merge_args(const xrd_refl *r, const double *I, const xrd_peaks *p) {
   if (int e = check_refl(r)) return e;
   if (!I || !p || !p->two_theta || !p->intensity || !p->scaled || !p->mult || !p->first || !p->perm ||
       !p->peak_offset)
     return fail(XRD_ERR_INVALID_ARG, "peak arrays and I must be non-NULL");
-  const WsLayout &L = b->ws;
+  return XRD_OK;
+}
+
+// Arguments of the merge kernels with the batch's tables and scratch at
+// layout L in ``ws``.
+static MergeArgs merge_args(xrd_batch *b, void *ws, const WsLayout &L, const xrd_refl *r, const double *I,
+                            xrd_peaks *p) {
   MergeArgs a;
-  a.sort = sort_args(b, ws, r);
+  a.sort = sort_args(b, ws, L, r);
   a.n_c = b->desc.n_crystals;
   a.tol = b->desc.merge_tol;
   a.thr = b->desc.rel_threshold;
@@ -827,12 +854,48 @@ int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, 
   a.pk_first = p->first;
   a.perm = p->perm;
   a.peak_offset = p->peak_offset;
+  return a;
+}
+
+int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, xrd_peaks *p) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  if (int e = check_merge_args(r, I, p)) return e;
   // the merge sorts as it goes, and leaves the sorted order behind
-  launch_merge(a, side_of(b), stream_of(b));
+  launch_merge(merge_args(b, ws, b->ws, r, I, p), side_of(b), stream_of(b));
   b->sorted_ws = ws;
   b->sorted_tt = r->two_theta;
   b->last_ws = ws;
   return hip_check("merge_peaks");
+}
+
+int xrd_merge_peaks_noalloc(xrd_batch *b, const xrd_refl *r, const double *I, xrd_peaks *p) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  if (int e = check_merge_args(r, I, p)) return e;
+  const WsLayout &M = b->mws;
+  if (M.total > kNoallocBytes)
+    return fail(XRD_ERR_CAPACITY, "the merge of this batch needs " + std::to_string(M.total) +
+                                      " bytes of scratch; the fixed scratch holds " + std::to_string(kNoallocBytes));
+  void *sp = nullptr;
+  hipError_t e = noalloc_scratch(&sp);
+  if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("scratch address: ") + hipGetErrorString(e));
+  // the batch's merge tables into this device's scratch (another call may have
+  // left other contents there), then the merge on the caller's stream only
+  hipStream_t s = stream_of(b);
+  auto up = [&](int64_t off, const void *src, size_t bytes) -> hipError_t {
+    if (bytes == 0) return hipSuccess;
+    return hipMemcpyAsync(at<char>(sp, off), src, bytes, hipMemcpyHostToDevice, s);
+  };
+  e = up(M.plan, b->plan.data(), sizeof(CrystalPlan) * b->plan.size());
+  if (e == hipSuccess) e = up(M.peak_chunks, b->peak_chunks.data(), sizeof(HChunk) * b->peak_chunks.size());
+  if (e == hipSuccess) e = up(M.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
+  if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("scratch tables: ") + hipGetErrorString(e));
+  const Fork none{nullptr, nullptr, nullptr, nullptr, nullptr};
+  launch_merge(merge_args(b, sp, M, r, I, p), none, s);
+  // the sorted order went to the scratch, which later calls may overwrite
+  b->sorted_ws = nullptr;
+  b->sorted_tt = nullptr;
+  return hip_check("merge_peaks_noalloc");
 }
 
 static int check_grid(const xrd_grid *g) {

@@ -34,6 +34,8 @@ constexpr int kTinySort = 1024;      // Friedel-positive reflections sorted in L
 constexpr int kSmallSort = 4096;     // ... by one 1024-thread block
 constexpr int kMidSort = 8192;       // ... by one 1024-thread block; larger crystals sort in global memory
 constexpr int kSpanPts = 16;         // grid points per span of the broadening gather (a quarter wavefront)
+// Device scratch of the allocation-free merge entry point (one array per GPU).
+constexpr int64_t kNoallocBytes = (int64_t)64 << 20;
 
 // Per-crystal plan (device copy in the workspace), 256 bytes.
 struct alignas(16) CrystalPlan {
@@ -139,6 +141,10 @@ struct WsLayout {
 
 void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 
+// Device address of the fixed scratch array (kNoallocBytes, 256-byte
+// aligned) on the current device, looked up on the first call per device.
+hipError_t noalloc_scratch(void **out);
+
 // Families of equivalent reflections per merged peak (rule 0: indices, 1: lattice).
 void launch_peak_families(const HChunk *chunks, int64_t n_chunks, const FamOps *fam_ops, const int64_t *peak_offset,
                           const int64_t *first, const int32_t *mult, const int64_t *perm, const int16_t *h,
@@ -193,7 +199,6 @@ struct SortArgs {
   int64_t n_bins;
   double *skey;
   int32_t *sidx;
-  int64_t *scan_part;
   const int32_t *order;  // [n_c] crystals by descending capacity
   int64_t n_mid;         // leading entries of ``order`` with capacity above 2 kSmallSort
   int64_t n_small;       // leading entries of ``order`` with capacity above 2 kTinySort

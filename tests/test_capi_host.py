@@ -198,3 +198,34 @@ def test_new_device_calls_validate_before_any_launch():
         assert "non-NULL" in lib.xrd_last_error().decode() or lib.xrd_last_error()
     finally:
         capi.xrd_batch_destroy(h)
+
+
+def test_noalloc_merge_scratch_size_and_rejection():
+    """The allocation-free merge's scratch need is reported per batch, is part
+    of the workspace's size, and a batch above the fixed scratch is refused
+    before any HIP call (so this runs without a GPU)."""
+    keep = []
+    small = synth.random_triclinic(22, 20, atoms_hi=30)
+    h = capi.xrd_batch_create(make_desc(small, keep))
+    try:
+        s = capi.xrd_batch_sizes(h)
+        assert 0 < s.noalloc_merge_bytes < s.workspace_bytes
+        assert s.noalloc_merge_bytes <= capi.XRD_NOALLOC_SCRATCH_BYTES
+        assert s.noalloc_merge_bytes % 256 == 0
+    finally:
+        capi.xrd_batch_destroy(h)
+    big = synth.random_triclinic(75, 1, atoms_lo=2, atoms_hi=2, len_lo=60.0, len_hi=62.0)
+    h = capi.xrd_batch_create(make_desc(big, keep))
+    try:
+        s = capi.xrd_batch_sizes(h)
+        assert s.noalloc_merge_bytes > capi.XRD_NOALLOC_SCRATCH_BYTES
+        fake = 0x10000
+        refl = capi.xrd_refl(*([fake] * 7))
+        peaks = capi.xrd_peaks(*([fake] * 7))
+        rc = capi.lib().xrd_merge_peaks_noalloc(h, C.byref(refl), fake, C.byref(peaks))
+        assert rc == capi.XRD_ERR_CAPACITY
+        assert "scratch" in capi.xrd_last_error()
+        rc = capi.lib().xrd_merge_peaks_noalloc(h, C.byref(refl), None, C.byref(peaks))
+        assert rc == capi.XRD_ERR_INVALID_ARG
+    finally:
+        capi.xrd_batch_destroy(h)
