@@ -17,6 +17,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxrd.so")
+RATES = os.path.join(HERE, "xrd_rates")  # instruction-rate microbenchmark program
 SOURCES = ["api.cpp", "scan.hip", "enumerate.hip", "sf.hip", "sortmerge.hip", "broaden.hip", "augment.hip", "family.hip",
            "noalloc.hip"]
 ARCH = "gfx950"
@@ -65,6 +66,14 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", *objs, "-o", tmp]
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    # the instruction-rate microbenchmark (a standalone program)
+    tmp = RATES + ".tmp"
+    cmd = [hipcc(), *[f for f in flags() if f != "-fPIC"], "-x", "hip", os.path.join(CSRC, "rates.hip"), "-o", tmp]
+    out = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    if out.returncode != 0:
+        print(out.stdout, file=sys.stderr)
+        raise RuntimeError("hipcc failed for rates.hip")
+    os.replace(tmp, RATES)
     return LIB
 
 

@@ -756,10 +756,11 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
 static SortArgs sort_args(xrd_batch *b, void *ws, const WsLayout &L, const xrd_refl *r);
 
 static void release_side(xrd_batch *b) {
+  // teardown: a failure here leaves nothing to recover, so it is dropped
   for (hipEvent_t e : {b->ev_fork, b->ev_join, b->ev_join2})
-    if (e) hipEventDestroy(e);
+    if (e) (void)hipEventDestroy(e);
   for (hipStream_t st : {b->side, b->side2})
-    if (st) hipStreamDestroy(st);
+    if (st) (void)hipStreamDestroy(st);
   b->side = b->side2 = nullptr;
   b->ev_fork = b->ev_join = b->ev_join2 = nullptr;
   b->side_device = -1;
