@@ -205,14 +205,14 @@ class Forward:
     paper's calculator) of one batch and precision, captured in a HIP graph
     on a stream of its own."""
 
-    def __init__(self, batch, precision, friedel=None):
+    def __init__(self, batch, precision, friedel=None, sf_method="direct"):
         import torch
         from paper_2602_11709_amd.api import XrdBatch
         self.torch = torch
         self.batch = batch
         self.stream = torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
-            self.xb = XrdBatch(batch, precision=precision, friedel=friedel)
+            self.xb = XrdBatch(batch, precision=precision, friedel=friedel, sf_method=sf_method)
             self.refl = self.xb.new_reflections()
             self.sf = self.xb.new_sf()
             self.pk = self.xb.new_peaks()
@@ -313,6 +313,32 @@ def host_threads():
     """Oracle threads: the host cores this process may use, at most 16 (one
     GPU's share of the host)."""
     return max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def leg_recurrence(batch, reps):
+    """Structure factors by the row recurrence against the direct sum on one
+    workload, both precisions (Friedel-halved, so both evaluate the same
+    reflections): device time of the structure-factor call (the recurrence's
+    includes building its segments), evaluated terms per second, the
+    recurrence kernel's own time, and the forward step (enumerate, structure
+    factors, merge) per replay."""
+    import torch
+    out = {}
+    for precision in ("mixed", "fp64"):
+        r = {}
+        for method in ("direct", "recurrence"):
+            f = Forward(batch, precision, True, sf_method=method)
+            ms = f.sf_ms(reps)
+            _, ev = f.terms()
+            r[method] = {"sf_call_ms": round(ms, 5), "sf_terms_per_s": round(ev / (ms * 1e-3), 1),
+                         "forward_ms": round(f.replay_ms(5), 5)}
+            if method == "recurrence":
+                kus = kernel_device_us(torch, f.stream, f.structure_factors, 3, ["k_sf_rec<", "k_seg_"])
+                r[method]["kernel_us"] = {k.rstrip("<_"): round(v, 2) for k, v in kus.items()}
+            del f
+        r["speedup_sf_call"] = round(r["direct"]["sf_call_ms"] / r["recurrence"]["sf_call_ms"], 3)
+        out[precision] = r
+    return out
 
 
 def leg_rocksalt(steps):
@@ -874,6 +900,9 @@ def main():
     for key in list(res):
         if key != "mixed":
             del res[key]["p"]
+    if not args.no_configs:
+        line["recurrence"] = {"triclinic_1024": leg_recurrence(batch, 10),
+                              "large_cells": leg_recurrence(synth.large_cells(), 3)}
     if not args.no_configs:
         line["configs"] = {"rocksalt": leg_rocksalt(20), "large_cells": leg_large_cells(3),
                            "gradient_256": leg_gradients(5)}

@@ -59,6 +59,23 @@ extern "C" {
                        partial sums added in double; q, 2theta, LP, merge keys and
                        intensities in double */
 
+/* How xrd_structure_factors evaluates the sums over atoms (paper, Section 5
+ * names reciprocal-space partitioning as the next step for large cells).
+ * Both give the same structure factors up to rounding (within the bounds of
+ * the precision). */
+#define XRD_SF_DIRECT 0     /* every term e^{2 pi i (h x + k y + l z)} by sin/cos of its phase */
+#define XRD_SF_RECURRENCE 1 /* along each row of constant (h, k) the reflections are cut into
+                               segments of at most 8 consecutive l; per atom and segment the
+                               weighted phasor occ e^{-B s^2} e^{2 pi i h.x} is evaluated exactly
+                               at the first reflection and stepped to the next ones by a complex
+                               product with r(l) e^{2 pi i z}, r(l) = e^{-B (q(l+1) - q(l))/4},
+                               itself stepped by the constant ratio e^{-B G*33 / 2}; the segments
+                               are rebuilt from the reflections by each call (workspace only) */
+#define XRD_SF_AUTO 2       /* per crystal: the recurrence for crystals of at least 256 atoms whose
+                               search box reaches |l| >= 12 (long rows), the direct sum for the
+                               others (the two run concurrently); xrd_autotune picks the atom
+                               threshold by timing */
+
 typedef struct xrd_batch xrd_batch; /* opaque */
 
 /* A batch of crystals.  Host arrays are read during xrd_batch_create only;
@@ -87,7 +104,7 @@ typedef struct {
                                      over the atoms again (forward and adjoint of the pattern
                                      share one pass over the atoms); 0: it does not.  Either way
                                      the results are the same up to rounding. */
-    int32_t reserved;             /* set to 0 */
+    int32_t sf_method;            /* XRD_SF_DIRECT, XRD_SF_RECURRENCE or XRD_SF_AUTO */
     const double *frac;           /* DEVICE [N*3]: fractional x, y, z per atom */
     const int32_t *species;       /* DEVICE [N]: row of sf_coeff, 0 <= species < n_species */
     const double *occ;            /* DEVICE [N]: occupancy, >= 0 */
@@ -235,7 +252,10 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
  * so structure factors kept for the adjoint (keep_sf_derivs) must be
  * computed again.  The split changes only the summation order (results agree
  * to rounding).  ``split_out`` (optional, host [2]) receives the chosen
- * forward and adjoint S (INT32_MAX: no split). */
+ * forward and adjoint S (INT32_MAX: no split).  Under XRD_SF_AUTO it first
+ * times the per-crystal choice of the recurrence for atom thresholds of 64 to
+ * 1024 (and never) and keeps the fastest; split_out must then hold 3 values,
+ * the third the chosen atom threshold. */
 int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out);
 
 /* Experimental effects for ML training patterns (paper, Section 1: the

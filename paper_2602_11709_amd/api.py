@@ -21,6 +21,7 @@ from . import capi
 from .synth import CrystalBatch
 
 PRECISIONS = {"fp64": capi.XRD_FP64, "mixed": capi.XRD_MIXED}
+SF_METHODS = {"direct": capi.XRD_SF_DIRECT, "recurrence": capi.XRD_SF_RECURRENCE, "auto": capi.XRD_SF_AUTO}
 
 
 def _p(t: Optional[torch.Tensor]):
@@ -80,15 +81,21 @@ class XrdBatch:
     ``grid_capacity`` bounds the grid of broadened-pattern calls (0: 16384
     points).  With ``keep_sf_derivs`` the structure-factor call also keeps
     dF/d(s^2) for a following ``pattern_backward`` on the same reflections,
-    which then skips its own pass over the atoms."""
+    which then skips its own pass over the atoms.  ``sf_method`` picks how the
+    structure factors sum over the atoms: "direct" (sin/cos of every term),
+    "recurrence" (stepped along reciprocal-lattice rows from exact seeds) or
+    "auto" (the recurrence for crystals with many atoms and long rows)."""
 
     def __init__(self, batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
                  rel_threshold: float = 0.0, device="cuda", frac: Optional[torch.Tensor] = None,
                  bfac: Optional[torch.Tensor] = None, lattice: Optional[np.ndarray] = None,
                  two_theta_range: Optional[tuple] = None, grid_capacity: int = 0,
-                 keep_sf_derivs: bool = False):
+                 keep_sf_derivs: bool = False, sf_method: str = "direct"):
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
+        if sf_method not in SF_METHODS:
+            raise ValueError(f"sf_method must be one of {list(SF_METHODS)}")
+        self.sf_method = sf_method
         self.device = torch.device(device)
         if self.device.type != "cuda":
             raise RuntimeError("XrdBatch needs a GPU device; there is no CPU path")
@@ -125,6 +132,7 @@ class XrdBatch:
         d.friedel = 1 if self.friedel else 0
         d.grid_capacity = int(grid_capacity)
         d.keep_sf_derivs = 1 if keep_sf_derivs else 0
+        d.sf_method = SF_METHODS[sf_method]
         d.frac = _p(self.frac) if batch.n_atoms else None
         d.species = _p(self.species) if batch.n_atoms else None
         d.occ = _p(self.occ) if batch.n_atoms else None
@@ -203,7 +211,8 @@ class XrdBatch:
 
     def autotune(self, refl: Reflections):
         """Time the structure-factor split candidates on ``refl`` (enumerated on
-        this batch) and keep the fastest; returns (forward, adjoint) thresholds."""
+        this batch) and keep the fastest; returns (forward, adjoint) thresholds
+        and, for sf_method "auto", the atom threshold of the recurrence (else -1)."""
         return capi.xrd_autotune(self.handle, self.ws, refl.c())
 
     def preferred_orientation(self, refl: Reflections, I: torch.Tensor, hp, march_r) -> torch.Tensor:
@@ -310,12 +319,13 @@ class PatternResult:
 
 def simulate(batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
              rel_threshold: float = 0.0, device="cuda", autotune: bool = False,
-             family_rule: Optional[int] = None) -> PatternResult:
+             family_rule: Optional[int] = None, sf_method: str = "direct") -> PatternResult:
     """Enumerate, structure factors, merge for every crystal; host arrays back.
     With ``autotune`` the structure-factor split is tuned on the enumerated
     reflections first; with a ``family_rule`` (0: indices, 1: lattice) the
     peaks' families of equivalent reflections come back too."""
-    xb = XrdBatch(batch, precision=precision, friedel=friedel, rel_threshold=rel_threshold, device=device)
+    xb = XrdBatch(batch, precision=precision, friedel=friedel, rel_threshold=rel_threshold, device=device,
+                  sf_method=sf_method)
     refl = xb.enumerate()
     if autotune:
         xb.autotune(refl)

@@ -22,6 +22,9 @@ XRD_ERR_HIP = -4
 XRD_ERR_UNSUPPORTED = -5
 XRD_FP64 = 0
 XRD_MIXED = 1
+XRD_SF_DIRECT = 0
+XRD_SF_RECURRENCE = 1
+XRD_SF_AUTO = 2
 XRD_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 _vp = C.c_void_p
@@ -33,7 +36,7 @@ class xrd_batch_desc(C.Structure):
         ("lattice", _vp), ("atom_offset", _vp), ("two_theta_min", _vp), ("two_theta_max", _vp),
         ("wavelength", C.c_double), ("merge_tol", C.c_double), ("rel_threshold", C.c_double),
         ("friedel", C.c_int32), ("grid_capacity", C.c_int32),
-        ("keep_sf_derivs", C.c_int32), ("reserved", C.c_int32),
+        ("keep_sf_derivs", C.c_int32), ("sf_method", C.c_int32),
         ("frac", _vp), ("species", _vp), ("occ", _vp), ("bfac", _vp), ("sf_coeff", _vp),
         ("stream", _vp),
     ]
@@ -157,10 +160,11 @@ def xrd_pattern_backward(batch, ws: int, refl: xrd_refl, grid: xrd_grid, dy: int
 
 
 def xrd_autotune(batch, ws: int, refl: xrd_refl):
-    """Chosen (forward, adjoint) split thresholds."""
-    out = (C.c_int32 * 2)()
+    """Chosen (forward, adjoint) split thresholds, and the atom threshold of the
+    recurrence under XRD_SF_AUTO (else -1)."""
+    out = (C.c_int32 * 3)(0, 0, -1)
     check(lib().xrd_autotune(batch, ws, C.byref(refl), out))
-    return int(out[0]), int(out[1])
+    return int(out[0]), int(out[1]), int(out[2])
 
 
 def xrd_preferred_orientation(batch, ws: int, refl: xrd_refl, hp: int, march_r: int, I: int):

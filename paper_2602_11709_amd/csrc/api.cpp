@@ -36,6 +36,13 @@ struct xrd_batch {
   std::vector<int32_t> sf_order;   // crystals by descending atom count
   std::vector<int32_t> sf_likely;  // per crystal: tiles its expected reflection count fills
   std::vector<SfItem> sf_items, sf_items_bw;  // launch orders of the forward sum and the adjoint
+  std::vector<int32_t> rec_tiles, rec_likely;  // row recurrence: segment tiles per crystal (capacity, expected)
+  std::vector<SfItem> sf_items_rec;            // launch order of the row-recurrence forward sum
+  int64_t sf_heavy_rec = 0;
+  bool rec = false;                            // the recurrence is available (sf_method not direct)
+  int32_t rec_min_atoms = kRecMinAtoms;        // XRD_SF_AUTO: threshold of the per-crystal choice
+  std::vector<int32_t> use_rec;                // per crystal: 1 if its forward sum takes the recurrence
+  int64_t n_rec = 0;                           // crystals whose forward sum takes the recurrence
   std::vector<BwItem> bw_items;
   std::vector<AbItem> ab_items;
   std::vector<FamOps> fam_ops;  // lattice point operations per crystal
@@ -302,10 +309,18 @@ void xcd_group(const xrd_batch *b, int64_t n_heavy, int64_t n_expected, std::vec
   regroup(n_heavy, n_expected, 4, n_heavy);  // four wavefronts to a light block
 }
 
-int64_t sf_table(const xrd_batch *b, int32_t split, std::vector<SfItem> *items) {
+// ``rec``: the row-recurrence tiles (64 segments each) instead of the direct
+// kernel's (kSfTile reflections each).  ``forward``: only the crystals whose
+// forward sum takes that method (the adjoint's table lists every crystal).
+int64_t sf_table(const xrd_batch *b, int32_t split, std::vector<SfItem> *items, bool rec = false,
+                 bool forward = false) {
   items->clear();
+  const int64_t nc = (int64_t)b->plan.size();
+  auto listed = [&](int32_t c) { return !forward || b->use_rec.empty() || (b->use_rec[c] != 0) == rec; };
+  auto tiles = [&](int32_t c) { return !listed(c) ? 0 : rec ? b->rec_tiles[c] : b->plan[c].n_tiles; };
+  auto likely = [&](int32_t c) { return !listed(c) ? 0 : rec ? b->rec_likely[c] : b->sf_likely[c]; };
   int64_t cap = 0;
-  for (const CrystalPlan &P : b->plan) cap += P.n_tiles;
+  for (int32_t c = 0; c < nc; ++c) cap += tiles(c);
   items->reserve((size_t)cap);
   auto item = [&](int32_t c, int32_t t) {
     const CrystalPlan &P = b->plan[c];
@@ -314,18 +329,41 @@ int64_t sf_table(const xrd_batch *b, int32_t split, std::vector<SfItem> *items) 
   auto heavy = [&](int32_t c) { return b->plan[c].atom_end - b->plan[c].atom_begin >= split; };
   for (int32_t c : b->sf_order)
     if (heavy(c))
-      for (int32_t t = 0; t < b->sf_likely[c]; ++t) items->push_back(item(c, t));
+      for (int32_t t = 0; t < likely(c); ++t) items->push_back(item(c, t));
   const int64_t n_heavy = (int64_t)items->size();
   for (int32_t c : b->sf_order)
     if (!heavy(c))
-      for (int32_t t = 0; t < b->sf_likely[c]; ++t) items->push_back(item(c, t));
+      for (int32_t t = 0; t < likely(c); ++t) items->push_back(item(c, t));
   const int64_t n_expected = (int64_t)items->size();
   for (int pass = 0; pass < 2; ++pass)
     for (int32_t c : b->sf_order)
       if (heavy(c) == (pass == 0))
-        for (int32_t t = b->sf_likely[c]; t < b->plan[c].n_tiles; ++t) items->push_back(item(c, t));
+        for (int32_t t = likely(c); t < tiles(c); ++t) items->push_back(item(c, t));
   xcd_group(b, n_heavy, n_expected, items);
   return n_heavy;
+}
+
+// XRD_SF_AUTO's per-crystal choice: the recurrence for crystals with at
+// least rec_min_atoms atoms whose rows along l are long (the search box
+// reaches |l| >= kRecMinRow, so rows of the shell hold a few segments);
+// every crystal under XRD_SF_RECURRENCE, none under XRD_SF_DIRECT.  Then the
+// forward tables of both methods.
+void choose_methods(xrd_batch *b) {
+  const int64_t nc = (int64_t)b->plan.size();
+  b->use_rec.assign(nc, 0);
+  b->n_rec = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    const CrystalPlan &P = b->plan[c];
+    bool r = false;
+    if (b->desc.sf_method == XRD_SF_RECURRENCE)
+      r = true;
+    else if (b->desc.sf_method == XRD_SF_AUTO)
+      r = P.atom_end - P.atom_begin >= b->rec_min_atoms && P.L >= kRecMinRow;
+    b->use_rec[c] = r ? 1 : 0;
+    b->n_rec += r ? 1 : 0;
+  }
+  b->sf_heavy = sf_table(b, b->split_fwd, &b->sf_items, false, true);
+  if (b->rec) b->sf_heavy_rec = sf_table(b, b->split_fwd, &b->sf_items_rec, true, true);
 }
 
 }  // namespace
@@ -354,6 +392,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   if (d->grid_capacity < 0) return fail(XRD_ERR_INVALID_ARG, "grid_capacity < 0");
   if (d->keep_sf_derivs != 0 && d->keep_sf_derivs != 1)
     return fail(XRD_ERR_INVALID_ARG, "keep_sf_derivs must be 0 or 1");
+  if (d->sf_method != XRD_SF_DIRECT && d->sf_method != XRD_SF_RECURRENCE && d->sf_method != XRD_SF_AUTO)
+    return fail(XRD_ERR_INVALID_ARG, "unknown sf_method");
   if (nc > 0 && (!d->lattice || !d->atom_offset || !d->two_theta_min || !d->two_theta_max))
     return fail(XRD_ERR_INVALID_ARG, "host arrays must be non-NULL");
   if (!d->sf_coeff) return fail(XRD_ERR_INVALID_ARG, "sf_coeff is NULL");
@@ -579,9 +619,24 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
         for (int32_t k = 0; k < P.n_hchunks; ++k) b->bw_items.push_back(BwItem{(int32_t)c, (int32_t)a, k, 0});
     }
   }
-  b->sf_heavy = sf_table(b, b->split_fwd, &b->sf_items);
   b->sf_heavy_bw = sf_table(b, b->split_bw, &b->sf_items_bw);
-  if ((int64_t)b->sf_items.size() >= ((int64_t)1 << 31) || (int64_t)b->bw_items.size() >= ((int64_t)1 << 31)) {
+  b->rec = d->sf_method != XRD_SF_DIRECT;
+  if (b->rec) {
+    // segments: at most one per evaluated reflection (capacity); expected
+    // about one per kRecLen - 2 reflections (runs end mid-segment)
+    b->rec_tiles.resize(nc);
+    b->rec_likely.resize(nc);
+    for (int64_t c = 0; c < nc; ++c) {
+      const CrystalPlan &P = b->plan[c];
+      const int64_t ecap = friedel ? P.half_box : 2 * P.half_box;
+      b->rec_tiles[c] = (int32_t)ceil_div(ecap, 64);
+      b->rec_likely[c] = (int32_t)std::min<double>((double)b->rec_tiles[c],
+                                                   std::ceil((expect_eval[c] / (kRecLen - 2) + 64) / 64));
+    }
+  }
+  choose_methods(b);
+  if ((int64_t)b->sf_items.size() >= ((int64_t)1 << 31) || (int64_t)b->bw_items.size() >= ((int64_t)1 << 31) ||
+      (int64_t)b->sf_items_rec.size() >= ((int64_t)1 << 31)) {
     delete b;
     return fail(XRD_ERR_CAPACITY, "launch tables exceed 2^31 entries");
   }
@@ -597,7 +652,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   const int64_t rc = b->refl_cap;
   L.plan = take((int64_t)sizeof(CrystalPlan) * nc);
   L.enum_chunk_tab = take((int64_t)sizeof(EnumChunk) * ec);
-  L.sf_items = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items.size());
+  L.sf_items = take((int64_t)sizeof(SfItem) * tiles_total);  // every crystal's tiles (the choice may change)
   L.sf_items_bw = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items_bw.size());
   L.peak_chunks = take((int64_t)sizeof(HChunk) * sc);
   L.eblocks = take((int64_t)sizeof(HChunk) * (int64_t)b->eblocks.size());
@@ -642,6 +697,20 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.sf_deriv = d->keep_sf_derivs ? take((d->precision == XRD_MIXED ? 16 : 32) * rc) : -1;
   L.coeff_f = take((int64_t)sizeof(CoeffF) * d->n_species);
   L.fam_ops = take((int64_t)sizeof(FamOps) * nc);
+  L.rot = take((int64_t)sizeof(AtomRot) * n_atoms);
+  L.seg_cnt = L.seg_index = L.seg_part = L.seg_start = L.n_entries = L.sf_items_rec = L.rec_of = -1;
+  if (b->rec) {
+    const int64_t ecap = friedel ? b->half_cap : rc;
+    L.seg_cnt = take(4 * ecap);
+    L.seg_index = take(8 * (ecap + 1));
+    L.seg_part = take(8 * scan_part_elems(ecap));
+    L.seg_start = take(4 * ecap);
+    L.n_entries = take(8);
+    int64_t rt = 0;
+    for (int32_t t : b->rec_tiles) rt += t;
+    L.sf_items_rec = take((int64_t)sizeof(SfItem) * rt);
+    L.rec_of = take(4 * nc);
+  }
   L.total = o;
   // the merge's own tables and scratch, packed on their own for the
   // allocation-free merge (fields it does not use stay 0)
@@ -703,6 +772,10 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   if (e == hipSuccess) e = up(L.bw_items, b->bw_items.data(), sizeof(BwItem) * b->bw_items.size());
   if (e == hipSuccess) e = up(L.ab_items, b->ab_items.data(), sizeof(AbItem) * b->ab_items.size());
   if (e == hipSuccess) e = up(L.fam_ops, b->fam_ops.data(), sizeof(FamOps) * b->fam_ops.size());
+  if (e == hipSuccess && b->rec) {
+    e = up(L.sf_items_rec, b->sf_items_rec.data(), sizeof(SfItem) * b->sf_items_rec.size());
+    if (e == hipSuccess) e = up(L.rec_of, b->use_rec.data(), 4 * b->use_rec.size());
+  }
   if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("upload: ") + hipGetErrorString(e));
   launch_fill_i32(at<int32_t>(ws, L.err_flag), 1, 0, s);
   // pageable copies complete before return, but the tables stay owned by the
@@ -728,13 +801,82 @@ int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r) {
                    at<int64_t>(ws, L.enum_prefix), at<int64_t>(ws, L.scan_part), r->h, r->k, r->l, r->q,
                    r->two_theta, r->lp, r->refl_offset, b->desc.n_species, b->desc.frac, b->desc.species,
                    b->desc.occ, b->desc.bfac, b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f),
-                   at<AtomRec>(ws, L.atoms), at<int32_t>(ws, L.atom_orig),
+                   at<AtomRec>(ws, L.atoms), at<AtomRot>(ws, L.rot), at<int32_t>(ws, L.atom_orig),
                    at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), at<int32_t>(ws, L.err_flag),
                    stream_of(b));
   b->last_ws = ws;
   return hip_check("enumerate");
 }
 
+
+// Arguments of the row-recurrence launch for items ``items`` (device) of
+// which the first n_heavy take a block each.
+static SfRecArgs rec_args(const xrd_batch *b, void *ws, const xrd_refl *r, const SfItem *items, int64_t n_items,
+                          int64_t n_heavy) {
+  const WsLayout &L = b->ws;
+  SfRecArgs a;
+  a.n_c = b->desc.n_crystals;
+  a.items = items;
+  a.n_items = n_items;
+  a.n_heavy = n_heavy;
+  a.eblocks = at<HChunk>(ws, L.eblocks);
+  a.n_eblocks = (int64_t)b->eblocks.size();
+  a.entry_cap = b->desc.friedel ? b->half_cap : b->refl_cap;
+  a.plan = at<CrystalPlan>(ws, L.plan);
+  a.refl_offset = r->refl_offset;
+  a.h = r->h;
+  a.k = r->k;
+  a.l = r->l;
+  a.q = r->q;
+  a.lp = r->lp;
+  a.atoms = at<AtomRec>(ws, L.atoms);
+  a.rot = at<AtomRot>(ws, L.rot);
+  a.runs = at<SpeciesRun>(ws, L.runs);
+  a.run_count = at<int32_t>(ws, L.run_count);
+  a.coeff = b->desc.sf_coeff;
+  a.coeff_f = at<CoeffF>(ws, L.coeff_f);
+  a.seg_cnt = at<int32_t>(ws, L.seg_cnt);
+  a.seg_index = at<int64_t>(ws, L.seg_index);
+  a.seg_part = at<int64_t>(ws, L.seg_part);
+  a.seg_start = at<int32_t>(ws, L.seg_start);
+  a.n_entries = at<int64_t>(ws, L.n_entries);
+  a.rec_of = at<int32_t>(ws, L.rec_of);
+  return a;
+}
+
+static Fork side_of(xrd_batch *b);
+
+// The forward sums of the batch's current tables: the recurrence for its
+// crystals (on the caller's stream) and the direct sum for the others (on a
+// side stream when both run, joined before the call returns).
+static void launch_forward_sums(xrd_batch *b, void *ws, const xrd_refl *r, void *A, void *B, double *I,
+                                void *deriv) {
+  const WsLayout &L = b->ws;
+  hipStream_t s = stream_of(b);
+  const bool mixed = b->desc.precision == XRD_MIXED, friedel = b->desc.friedel != 0;
+  const int64_t nc = b->desc.n_crystals;
+  const bool any_rec = b->n_rec > 0, any_direct = b->n_rec < nc;
+  Fork f{nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (any_rec && any_direct) f = side_of(b);
+  hipStream_t sd = f.side ? f.side : s;
+  if (f.side) {
+    (void)hipEventRecord(f.fork, s);
+    (void)hipStreamWaitEvent(f.side, f.fork, 0);
+  }
+  if (any_rec)
+    launch_sf_rec(mixed, friedel,
+                  rec_args(b, ws, r, at<SfItem>(ws, L.sf_items_rec), (int64_t)b->sf_items_rec.size(), b->sf_heavy_rec),
+                  A, B, I, deriv, s);
+  if (any_direct)
+    launch_sf(mixed, friedel, at<SfItem>(ws, L.sf_items), (int64_t)b->sf_items.size(), b->sf_heavy,
+              at<CrystalPlan>(ws, L.plan), r->refl_offset, r->h, r->k, r->l, r->q, r->lp, at<AtomRec>(ws, L.atoms),
+              at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f),
+              A, B, I, deriv, sd);
+  if (f.side) {
+    (void)hipEventRecord(f.join, f.side);
+    (void)hipStreamWaitEvent(s, f.join, 0);
+  }
+}
 
 int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, void *B, double *I) {
   if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
@@ -743,10 +885,7 @@ int xrd_structure_factors(xrd_batch *b, void *ws, const xrd_refl *r, void *A, vo
   if (!A || !B || !I) return fail(XRD_ERR_INVALID_ARG, "A, B and I must be non-NULL");
   const WsLayout &L = b->ws;
   void *deriv = L.sf_deriv >= 0 ? at<char>(ws, L.sf_deriv) : nullptr;
-  launch_sf(b->desc.precision == XRD_MIXED, b->desc.friedel != 0, at<SfItem>(ws, L.sf_items),
-            (int64_t)b->sf_items.size(), b->sf_heavy, at<CrystalPlan>(ws, L.plan), r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
-            at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), b->desc.sf_coeff,
-            at<CoeffF>(ws, L.coeff_f), A, B, I, deriv, stream_of(b));
+  launch_forward_sums(b, ws, r, A, B, I, deriv);
   b->deriv_ws = deriv ? ws : nullptr;
   b->deriv_h = deriv ? r->h : nullptr;
   b->last_ws = ws;
@@ -982,12 +1121,7 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
   double *I = at<double>(ws, L.bw_dq);
   void *deriv = L.sf_deriv >= 0 ? at<char>(ws, L.sf_deriv) : nullptr;
   double *w1 = at<double>(ws, L.bw_w1), *w2 = at<double>(ws, L.bw_w2);
-  const int64_t n_items = (int64_t)b->sf_items.size();
-  auto run_fwd = [&](const std::vector<SfItem> &t, int64_t nh) {
-    launch_sf(mixed, friedel, at<SfItem>(ws, L.sf_items), (int64_t)t.size(), nh, plan, r->refl_offset, r->h, r->k,
-              r->l, r->q, r->lp, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
-              b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), A, B, I, deriv, s);
-  };
+  const int64_t nc = b->desc.n_crystals;
   auto run_bw = [&](const std::vector<SfItem> &t, int64_t nh) {
     launch_sf_bw(mixed, friedel, at<SfItem>(ws, L.sf_items_bw), (int64_t)t.size(), nh, plan, r->refl_offset, r->h,
                  r->k, r->l, r->q, r->lp, b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
@@ -1012,42 +1146,99 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
     std::sort(t, t + 5);
     return t[2];
   };
-  // candidate thresholds; those giving the same table as an earlier one are skipped
-  const int32_t cand[] = {8, 16, 24, 32, 48, 64, 96, 128, 256, 512, INT32_MAX};
-  auto tune = [&](int64_t table_off, bool fwd, int32_t *best_split) {
-    std::vector<SfItem> t;
-    std::vector<int64_t> seen;
-    float best = 0.f;
-    for (int32_t c : cand) {
-      if (e != hipSuccess) break;
-      const int64_t nh = sf_table(b, c, &t);
-      if (std::find(seen.begin(), seen.end(), nh) != seen.end()) continue;
-      seen.push_back(nh);
-      e = hipMemcpyAsync(at<char>(ws, table_off), t.data(), sizeof(SfItem) * t.size(), hipMemcpyHostToDevice, s);
-      if (e == hipSuccess) e = hipStreamSynchronize(s);
-      if (e != hipSuccess) break;
-      const float ms = fwd ? timed([&] { run_fwd(t, nh); }) : timed([&] { run_bw(t, nh); });
-      if (e == hipSuccess) e = hipGetLastError();
-      if (e == hipSuccess && (seen.size() == 1 || ms < best)) {
-        best = ms;
-        *best_split = c;
-      }
-    }
+  // the forward tables (both methods) and the per-crystal choice into the workspace
+  auto upload_fwd = [&]() {
+    if (e == hipSuccess && !b->sf_items.empty())
+      e = hipMemcpyAsync(at<char>(ws, L.sf_items), b->sf_items.data(), sizeof(SfItem) * b->sf_items.size(),
+                         hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && b->rec && !b->sf_items_rec.empty())
+      e = hipMemcpyAsync(at<char>(ws, L.sf_items_rec), b->sf_items_rec.data(),
+                         sizeof(SfItem) * b->sf_items_rec.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && b->rec)
+      e = hipMemcpyAsync(at<char>(ws, L.rec_of), b->use_rec.data(), 4 * b->use_rec.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
   };
-  if (n_items > 0 && e == hipSuccess) {
-    tune(L.sf_items, true, &b->split_fwd);
-    b->sf_heavy = sf_table(b, b->split_fwd, &b->sf_items);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(at<char>(ws, L.sf_items), b->sf_items.data(), sizeof(SfItem) * n_items, hipMemcpyHostToDevice, s);
-    // the adjoint's inputs: derivatives of the chosen forward table, zero grid weights
-    if (e == hipSuccess) run_fwd(b->sf_items, b->sf_heavy);
+  auto time_fwd = [&]() -> float {
+    upload_fwd();
+    if (e != hipSuccess) return 0.f;
+    const float ms = timed([&] { launch_forward_sums(b, ws, r, A, B, I, deriv); });
+    if (e == hipSuccess) e = hipGetLastError();
+    return ms;
+  };
+  // candidate thresholds; those giving the same tables as an earlier one are skipped
+  const int32_t cand[] = {8, 16, 24, 32, 48, 64, 96, 128, 256, 512, INT32_MAX};
+  if (nc > 0 && e == hipSuccess) {
+    // (XRD_SF_AUTO) which crystals take the recurrence: atom thresholds
+    if (b->desc.sf_method == XRD_SF_AUTO) {
+      const int32_t rcand[] = {64, 128, 256, 512, 1024, INT32_MAX};
+      std::vector<int64_t> seen;
+      float best = 0.f;
+      int32_t best_t = b->rec_min_atoms;
+      for (int32_t t : rcand) {
+        if (e != hipSuccess) break;
+        b->rec_min_atoms = t;
+        choose_methods(b);
+        if (std::find(seen.begin(), seen.end(), b->n_rec) != seen.end()) continue;
+        seen.push_back(b->n_rec);
+        const float ms = time_fwd();
+        if (e == hipSuccess && (seen.size() == 1 || ms < best)) {
+          best = ms;
+          best_t = t;
+        }
+      }
+      b->rec_min_atoms = best_t;
+      choose_methods(b);
+    }
+    // split-K of the forward sums
+    {
+      std::vector<std::pair<int64_t, int64_t>> seen;
+      float best = 0.f;
+      int32_t best_split = b->split_fwd;
+      for (int32_t c : cand) {
+        if (e != hipSuccess) break;
+        b->split_fwd = c;
+        choose_methods(b);
+        const std::pair<int64_t, int64_t> key{b->sf_heavy, b->sf_heavy_rec};
+        if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
+        seen.push_back(key);
+        const float ms = time_fwd();
+        if (e == hipSuccess && (seen.size() == 1 || ms < best)) {
+          best = ms;
+          best_split = c;
+        }
+      }
+      b->split_fwd = best_split;
+      choose_methods(b);
+      upload_fwd();
+    }
+    // the adjoint's inputs: derivatives of the chosen forward tables, zero grid weights
+    if (e == hipSuccess) launch_forward_sums(b, ws, r, A, B, I, deriv);
     launch_fill_u64(reinterpret_cast<uint64_t *>(w1), b->refl_cap, 0, s);
     launch_fill_u64(reinterpret_cast<uint64_t *>(w2), b->refl_cap, 0, s);
     if (e == hipSuccess) e = hipGetLastError();
-    tune(L.sf_items_bw, false, &b->split_bw);
+    {
+      std::vector<SfItem> t;
+      std::vector<int64_t> seen;
+      float best = 0.f;
+      for (int32_t c : cand) {
+        if (e != hipSuccess) break;
+        const int64_t nh = sf_table(b, c, &t);
+        if (std::find(seen.begin(), seen.end(), nh) != seen.end()) continue;
+        seen.push_back(nh);
+        e = hipMemcpyAsync(at<char>(ws, L.sf_items_bw), t.data(), sizeof(SfItem) * t.size(), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) break;
+        const float ms = timed([&] { run_bw(t, nh); });
+        if (e == hipSuccess) e = hipGetLastError();
+        if (e == hipSuccess && (seen.size() == 1 || ms < best)) {
+          best = ms;
+          b->split_bw = c;
+        }
+      }
+    }
     b->sf_heavy_bw = sf_table(b, b->split_bw, &b->sf_items_bw);
     if (e == hipSuccess)
-      e = hipMemcpyAsync(at<char>(ws, L.sf_items_bw), b->sf_items_bw.data(), sizeof(SfItem) * n_items,
+      e = hipMemcpyAsync(at<char>(ws, L.sf_items_bw), b->sf_items_bw.data(), sizeof(SfItem) * b->sf_items_bw.size(),
                          hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
@@ -1061,6 +1252,7 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
   if (split_out) {
     split_out[0] = b->split_fwd;
     split_out[1] = b->split_bw;
+    if (b->desc.sf_method == XRD_SF_AUTO) split_out[2] = b->rec_min_atoms;
   }
   return XRD_OK;
 }

@@ -161,7 +161,7 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
                              const int32_t *__restrict__ species, const double *__restrict__ occ,
                              const double *__restrict__ bfac, const double *__restrict__ coeff,
                              CoeffF *__restrict__ coeff_f, AtomRec *__restrict__ atoms,
-                             int32_t *__restrict__ orig, SpeciesRun *__restrict__ runs,
+                             AtomRot *__restrict__ rot, int32_t *__restrict__ orig, SpeciesRun *__restrict__ runs,
                              int32_t *__restrict__ run_count, int32_t *__restrict__ err) {
   if (c == 0) {
     // the single-precision coefficient table of the mixed path (one
@@ -227,6 +227,7 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
     bool active = j < a1;
     int sp = -1;
     AtomRec a{};
+    AtomRot z{};
     if (active) {
       // the atom's record is read before the species peeling, whose steps
       // then wait on LDS only
@@ -239,6 +240,12 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
       a.bfac = bfac[j];
       a.log2occ = __log2f((float)a.occ);
       a.bl2e = (float)a.bfac * kLog2e;
+      // the row recurrence's factors: e^{2 pi i z} and e^{-B G*33 / 2}
+      sincospi(2.0 * a.z, &z.zs, &z.zc);
+      z.rho = exp(-0.5 * a.bfac * P.gs[2]);
+      z.zcf = (float)z.zc;
+      z.zsf = (float)z.zs;
+      z.rhof = (float)z.rho;
     }
     while (true) {
       const uint64_t act = __ballot(active);
@@ -252,6 +259,7 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
         const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         const int pos = base_pos + rank;
         atoms[pos] = a;
+        rot[pos] = z;
         orig[pos] = (int32_t)j;
         active = false;
       }
@@ -270,6 +278,7 @@ struct PackArgs {
   const double *coeff;
   CoeffF *coeff_f;
   AtomRec *atoms;
+  AtomRot *rot;
   int32_t *orig;
   SpeciesRun *runs;
   int32_t *run_count;
@@ -280,7 +289,7 @@ struct PackArgs {
 __global__ __launch_bounds__(64) void k_atom_pack(const CrystalPlan *__restrict__ plan, int64_t n_c, PackArgs a) {
   extern __shared__ int32_t cursor[];  // n_species
   pack_crystal(blockIdx.x, threadIdx.x, cursor, plan, a.n_species, a.frac, a.species, a.occ, a.bfac, a.coeff,
-               a.coeff_f, a.atoms, a.orig, a.runs, a.run_count, a.err);
+               a.coeff_f, a.atoms, a.rot, a.orig, a.runs, a.run_count, a.err);
 }
 
 // Survivor count per enumeration chunk (at most kEnumRows rows), one
@@ -299,7 +308,7 @@ __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__re
     const int64_t c = (int64_t)(blockIdx.x - chunk_blocks) * (kThreads / 64) + wid;
     if (c < n_c)
       pack_crystal((int)c, lane, cursors + wid * pa.n_species, plan, pa.n_species, pa.frac, pa.species, pa.occ,
-                   pa.bfac, pa.coeff, pa.coeff_f, pa.atoms, pa.orig, pa.runs, pa.run_count, pa.err);
+                   pa.bfac, pa.coeff, pa.coeff_f, pa.atoms, pa.rot, pa.orig, pa.runs, pa.run_count, pa.err);
     return;
   }
   const int64_t chunk = (int64_t)blockIdx.x * (kThreads / 64) + wid;
@@ -482,9 +491,9 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const EnumChunk *chu
                       double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h,
                       int16_t *k, int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset,
                       int32_t n_species, const double *frac, const int32_t *species, const double *occ,
-                      const double *bfac, const double *coeff, CoeffF *coeff_f, AtomRec *atoms, int32_t *orig,
-                      SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s) {
-  const PackArgs pa{n_species, frac, species, occ, bfac, coeff, coeff_f, atoms, orig, runs, run_count, err};
+                      const double *bfac, const double *coeff, CoeffF *coeff_f, AtomRec *atoms, AtomRot *rot,
+                      int32_t *orig, SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s) {
+  const PackArgs pa{n_species, frac, species, occ, bfac, coeff, coeff_f, atoms, rot, orig, runs, run_count, err};
   // the packing rides along in the count launch while its cursors stay small
   const size_t fused_lds = (size_t)(kThreads / 64) * n_species * sizeof(int32_t);
   const bool fuse = n_chunks > 0 && fused_lds <= kFusedPackLds;

@@ -34,6 +34,9 @@ constexpr int kTinySort = 1024;      // Friedel-positive reflections sorted in L
 constexpr int kSmallSort = 4096;     // ... by one 1024-thread block
 constexpr int kMidSort = 8192;       // ... by one 1024-thread block; larger crystals sort in global memory
 constexpr int kSpanPts = 16;         // grid points per span of the broadening gather (a quarter wavefront)
+constexpr int kRecLen = 8;           // reflections per segment of the row-recurrence structure factors
+constexpr int kRecMinAtoms = 256;    // XRD_SF_AUTO: default atom threshold of the recurrence
+constexpr int kRecMinRow = 12;       // XRD_SF_AUTO: the recurrence needs |l| up to at least this in the search box
 // Device scratch of the allocation-free merge entry point (one array per GPU).
 constexpr int64_t kNoallocBytes = (int64_t)64 << 20;
 
@@ -72,6 +75,16 @@ struct alignas(16) AtomRec {
   float bl2e;      // B * log2(e)
 };
 static_assert(sizeof(AtomRec) == 48, "AtomRec layout");
+
+// Per-atom factors of the row recurrence (48 bytes, parallel to AtomRec):
+// the phase step e^{2 pi i z} = (zc, zs) along l and rho = e^{-B G*33 / 2},
+// the ratio of successive Debye-Waller steps along l, in double and single
+// precision.
+struct alignas(16) AtomRot {
+  double zc, zs, rho;
+  float zcf, zsf, rhof, pad;
+};
+static_assert(sizeof(AtomRot) == 48, "AtomRot layout");
 
 // Cromer-Mann coefficients of one species in single precision, in the form
 // the mixed-precision kernels evaluate them (64 bytes, one scalar load):
@@ -136,6 +149,10 @@ struct WsLayout {
   int64_t coeff_f;   // [n_species] CoeffF
   int64_t sf_items_bw;  // structure-factor items in the adjoint's launch order
   int64_t fam_ops;      // [n_crystals] FamOps
+  int64_t rot;          // [N] AtomRot
+  // row-recurrence structure factors: segment counts per entry, their scan,
+  // segment starts, the entry count, the work items (or -1)
+  int64_t seg_cnt, seg_index, seg_part, seg_start, n_entries, sf_items_rec, rec_of;
   int64_t total;
 };
 
@@ -176,8 +193,8 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const EnumChunk *chu
                       double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h, int16_t *k,
                       int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset, int32_t n_species,
                       const double *frac, const int32_t *species, const double *occ, const double *bfac,
-                      const double *coeff, CoeffF *coeff_f, AtomRec *atoms, int32_t *orig, SpeciesRun *runs,
-                      int32_t *run_count, int32_t *err, hipStream_t s);
+                      const double *coeff, CoeffF *coeff_f, AtomRec *atoms, AtomRot *rot, int32_t *orig,
+                      SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s);
 // Items: the first n_heavy take a block each (atoms split over its four
 // wavefronts), the rest one wavefront each.  A non-null deriv_cache
 // ([refl_cap] float4 under mixed precision, else double4) receives
@@ -187,6 +204,36 @@ void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, i
                const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
                const double *coeff, const CoeffF *coeff_f, void *A, void *B, double *I, void *deriv_cache,
                hipStream_t s);
+
+// Structure factors by the row recurrence (sfrec.hip): the segments of the
+// current reflections are built first (kRecLen consecutive reflections of a
+// row at most), then one lane per segment.
+struct SfRecArgs {
+  int64_t n_c;
+  const SfItem *items;  // (crystal, tile of 64 segments), heavy items first
+  int64_t n_items, n_heavy;
+  const HChunk *eblocks;  // (crystal, block of kEntBlock evaluated reflections) at capacity
+  int64_t n_eblocks;
+  int64_t entry_cap;      // evaluated-reflection capacity of the batch
+  const CrystalPlan *plan;
+  const int64_t *refl_offset;
+  const int16_t *h, *k, *l;
+  const double *q, *lp;
+  const AtomRec *atoms;
+  const AtomRot *rot;
+  const SpeciesRun *runs;
+  const int32_t *run_count;
+  const double *coeff;
+  const CoeffF *coeff_f;
+  int32_t *seg_cnt;       // [entry_cap]
+  int64_t *seg_index;     // [entry_cap + 1]
+  int64_t *seg_part;      // scan_part_elems(entry_cap)
+  int32_t *seg_start;     // [entry_cap]
+  int64_t *n_entries;     // [1]
+  const int32_t *rec_of;  // [n_c] 1: the crystal takes the recurrence (only those get segments)
+};
+void launch_sf_rec(bool mixed, bool friedel, const SfRecArgs &a, void *A, void *B, double *I, void *deriv_cache,
+                   hipStream_t s);
 
 struct SortArgs {
   int64_t n_c;

@@ -229,3 +229,19 @@ def test_noalloc_merge_scratch_size_and_rejection():
         assert rc == capi.XRD_ERR_INVALID_ARG
     finally:
         capi.xrd_batch_destroy(h)
+
+
+def test_sf_method_is_validated_and_sizes_the_workspace():
+    keep = []
+    b = synth.random_triclinic(23, 12, atoms_hi=40)
+    h = capi.xrd_batch_create(make_desc(b, keep))
+    direct = capi.xrd_batch_sizes(h).workspace_bytes
+    capi.xrd_batch_destroy(h)
+    h = capi.xrd_batch_create(make_desc(b, keep, sf_method=capi.XRD_SF_RECURRENCE))
+    rec = capi.xrd_batch_sizes(h)
+    capi.xrd_batch_destroy(h)
+    # segment counts, their scan and starts: at most one segment per evaluated reflection
+    assert rec.workspace_bytes >= direct + 16 * rec.half_capacity
+    with pytest.raises(capi.XrdError) as ei:
+        capi.xrd_batch_create(make_desc(b, keep, sf_method=3))
+    assert ei.value.code == capi.XRD_ERR_INVALID_ARG

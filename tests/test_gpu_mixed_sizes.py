@@ -57,14 +57,18 @@ def mixed_batch():
     return concat_species(parts), parts
 
 
-@pytest.mark.parametrize("precision", ["mixed", "fp64"])
-def test_mixed_size_launch_against_oracle(precision):
+@pytest.mark.parametrize("precision,method", [("mixed", "direct"), ("fp64", "direct"), ("mixed", "auto"),
+                                              ("fp64", "auto")])
+def test_mixed_size_launch_against_oracle(precision, method):
+    """With sf_method "auto" the two large cells take the row recurrence and
+    the small ones the direct sum, in the same call (two concurrent launches),
+    after the autotuner has chosen the threshold."""
     from paper_2602_11709_amd.api import simulate
     b, parts = mixed_batch()
     sizes = np.diff(b.atom_offset)
     big = [c for c in range(b.n_crystals) if sizes[c] >= 2000]
     assert len(big) == 2 and sizes.min() == 0 and 1 in sizes
-    res = simulate(b, precision=precision)
+    res = simulate(b, precision=precision, sf_method=method, autotune=method == "auto")
     small = [c for c in range(b.n_crystals) if c not in big]
     worst_small = {}
     for c in small:
