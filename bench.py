@@ -341,6 +341,56 @@ def leg_recurrence(batch, reps):
     return out
 
 
+def leg_database(chunk=8192, planners=6):
+    """The database-scale stream: 100 000 synthetic crystals shaped like the
+    structure databases of the paper's benchmarks (Mo K-alpha, 2theta 2-60),
+    forward patterns (enumerate, structure factors, merge, scaled peaks) in
+    chunks planned on host threads while the GPU computes; peaks stay on the
+    device.  Also per bin of reflection count (the paper's Fig. 8 bins), the
+    bins' crystals streamed on their own."""
+    import oracle
+    from paper_2602_11709_amd import synth
+    from paper_2602_11709_amd.stream import DatabaseStream
+    t0 = time.perf_counter()
+    b = synth.database_stream()
+    gen_s = time.perf_counter() - t0
+    out = {"workload": "database_stream: 100000 crystals, atoms log-normal (median 20, sigma_log 1, 1-1000), "
+                       "lengths 2.6 A N^(1/3) U(0.8,1.2), angles U(60,120), Mo 0.71073 A, 2theta 2-60, seed 3",
+           "chunk": chunk, "planners": planners, "generate_s": round(gen_s, 2)}
+    counts = np.zeros(b.n_crystals, np.int64)
+
+    def keep_counts(cp):
+        counts[cp.first:cp.first + cp.n_crystals] = np.diff(cp.refl_offset)
+
+    for precision in ("mixed", "fp64"):
+        st = DatabaseStream(b, chunk=chunk, precision=precision, planners=planners).run(
+            keep_counts if precision == "mixed" else None)
+        out[precision] = {k: (round(v, 4) if isinstance(v, float) else v) for k, v in st.items()}
+    bins = {}
+    for lo, hi, name in ((0, 10, "<=10"), (10, 100, "10-100"), (100, 100000, "100-1e5"), (100000, None, ">1e5")):
+        idx = np.nonzero((counts > lo) & ((counts <= hi) if hi is not None else True))[0]
+        if lo == 0:
+            idx = np.nonzero(counts <= 10)[0]
+        entry = {"crystals": int(len(idx)), "reflections": int(counts[idx].sum())}
+        if len(idx):
+            st = DatabaseStream(b.subset(idx), chunk=chunk, planners=planners).run()
+            entry.update(patterns_per_s=round(st["patterns_per_s"], 1),
+                         patterns_per_s_device=round(st["patterns_per_s_device"], 1), wall_s=round(st["wall_s"], 4))
+        bins[name] = entry
+    out["bins_mixed"] = bins
+    # oracle: the first 2000 crystals on the host threads
+    threads = host_threads()
+    sub = b.subset(range(2000))
+    t0 = time.perf_counter()
+    oracle.pattern_batch(sub, threads=threads, keep=False)
+    wall = time.perf_counter() - t0
+    out["cpu_oracle"] = {"patterns_per_s": round(2000 / wall, 1), "threads": threads,
+                         "wall_s_100000_extrapolated": round(wall * 50, 1),
+                         "sample": f"oracle forward patterns of the first 2000 crystals on {threads} threads, "
+                                   f"{wall:.2f} s; the whole stream extrapolated x50"}
+    return out
+
+
 def leg_rocksalt(steps):
     """The single rock-salt cell (the closed-form pin case), plain FP64 path
     as the configuration names it, and the mixed path: forward pattern."""
@@ -905,7 +955,7 @@ def main():
                               "large_cells": leg_recurrence(synth.large_cells(), 3)}
     if not args.no_configs:
         line["configs"] = {"rocksalt": leg_rocksalt(20), "large_cells": leg_large_cells(3),
-                           "gradient_256": leg_gradients(5)}
+                           "gradient_256": leg_gradients(5), "database_stream": leg_database()}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(batch)
     print(json.dumps(line), flush=True)

@@ -111,6 +111,11 @@ typedef struct {
     const double *bfac;           /* DEVICE [N]: isotropic B */
     const double *sf_coeff;       /* DEVICE [n_species*9]: a1..a4, b1..b4, c */
     void *stream;                 /* hipStream_t; NULL = the null stream */
+    int32_t forward_only;         /* 1: the batch never calls xrd_pattern_backward: its adjoint tables
+                                     and buffers are neither built nor part of the workspace (a
+                                     smaller plan and workspace for streams of forward patterns);
+                                     xrd_pattern_backward then fails with XRD_ERR_UNSUPPORTED */
+    int32_t reserved;             /* set to 0 */
 } xrd_batch_desc;
 
 typedef struct {
@@ -166,6 +171,23 @@ int xrd_batch_create(const xrd_batch_desc *desc, xrd_batch **out);
 
 /* Capacities and workspace size of a created batch (host only). */
 int xrd_batch_sizes(const xrd_batch *b, xrd_sizes *out);
+
+/* Change the cells of a planned batch (``lattice`` HOST [n_crystals*6], as in
+ * the descriptor) without planning it again, for loops that refine the
+ * lattice: each crystal keeps its search box, capacities and launch tables,
+ * and takes the new inverse metric; the plan is copied into ``ws`` on the
+ * batch's stream (enqueued, not waited for).  Fails with XRD_ERR_CAPACITY,
+ * changing nothing, when a new cell needs a larger search box than the
+ * batch was planned with (then create a new batch), and with
+ * XRD_ERR_INVALID_CELL for an invalid cell.  The next device call must be
+ * xrd_enumerate_hkl. */
+int xrd_batch_set_lattice(xrd_batch *b, const double *lattice, void *ws);
+
+/* Make ``stream`` (hipStream_t; NULL = the null stream) the batch's stream
+ * for the calls that follow (host only).  Work already enqueued stays on the
+ * previous stream; the caller orders the two (for instance, upload a batch's
+ * tables on a copy stream, then set the compute stream). */
+int xrd_batch_set_stream(xrd_batch *b, void *stream);
 
 /* Copy the batch's launch tables into the workspace ``ws`` (device memory of
  * at least workspace_bytes, 256-byte aligned) on the batch's stream, and

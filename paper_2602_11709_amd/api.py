@@ -84,13 +84,15 @@ class XrdBatch:
     which then skips its own pass over the atoms.  ``sf_method`` picks how the
     structure factors sum over the atoms: "direct" (sin/cos of every term),
     "recurrence" (stepped along reciprocal-lattice rows from exact seeds) or
-    "auto" (the recurrence for crystals with many atoms and long rows)."""
+    "auto" (the recurrence for crystals with many atoms and long rows).
+    ``forward_only`` leaves out the adjoint's tables and buffers (no
+    ``pattern_backward`` on this batch)."""
 
     def __init__(self, batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
                  rel_threshold: float = 0.0, device="cuda", frac: Optional[torch.Tensor] = None,
                  bfac: Optional[torch.Tensor] = None, lattice: Optional[np.ndarray] = None,
                  two_theta_range: Optional[tuple] = None, grid_capacity: int = 0,
-                 keep_sf_derivs: bool = False, sf_method: str = "direct"):
+                 keep_sf_derivs: bool = False, sf_method: str = "direct", forward_only: bool = False):
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         if sf_method not in SF_METHODS:
@@ -133,6 +135,7 @@ class XrdBatch:
         d.grid_capacity = int(grid_capacity)
         d.keep_sf_derivs = 1 if keep_sf_derivs else 0
         d.sf_method = SF_METHODS[sf_method]
+        d.forward_only = 1 if forward_only else 0
         d.frac = _p(self.frac) if batch.n_atoms else None
         d.species = _p(self.species) if batch.n_atoms else None
         d.occ = _p(self.occ) if batch.n_atoms else None
@@ -344,24 +347,80 @@ def simulate(batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bo
                          pk_first=cpu(pk.first, m), perm=cpu(pk.perm, n), **extra)
 
 
+class _Slot:
+    """A planned batch with its reflection and structure-factor buffers, kept
+    between calls of the differentiable pattern on the same inputs."""
+
+    def __init__(self, xb, lattice):
+        self.xb = xb
+        self.refl = xb.new_reflections()
+        self.sf = xb.new_sf()
+        self.lattice = lattice.copy()
+        self.busy = False  # a forward's state awaits its backward
+        self.gen = 0       # forward calls served
+
+
+# batches of the differentiable pattern, reused across calls: per (batch
+# object, precision, friedel, grid size, device) a few slots
+_POOL = {}
+_POOL_SLOTS = 2
+
+
+def _slot_for(spec, frac, bfac, lat, needs_grad):
+    """A planned batch for this call: a free pooled one (its frac and B
+    refreshed in place, its cells changed in place when the search boxes
+    allow), or a new one."""
+    batch, grid = spec["batch"], spec["grid"]
+    key = (id(batch), spec["precision"], spec["friedel"], int(grid.n_points), str(frac.device))
+    slots = [s for s in _POOL.get(key, []) if s.xb.batch is batch]
+    _POOL[key] = slots
+    for slot in slots:
+        if slot.busy:
+            continue
+        xb = slot.xb
+        if not np.array_equal(slot.lattice, lat):
+            lat_c = np.ascontiguousarray(lat, dtype=np.float64)
+            if capi.xrd_batch_set_lattice(xb.handle, lat_c.ctypes.data, xb.ws) != capi.XRD_OK:
+                continue  # a cell outgrew its search box: plan anew below
+            slot.lattice = lat_c.copy()
+        xb.frac.copy_(frac.detach().to(torch.float64))
+        xb.bfac.copy_(bfac.detach().to(torch.float64))
+        break
+    else:
+        xb = XrdBatch(batch, precision=spec["precision"], friedel=spec["friedel"], device=frac.device,
+                      frac=frac.detach().to(torch.float64).clone().contiguous(),
+                      bfac=bfac.detach().to(torch.float64).clone().contiguous(), lattice=lat,
+                      grid_capacity=grid.n_points, keep_sf_derivs=True)
+        slot = _Slot(xb, lat)
+        if len(slots) < _POOL_SLOTS:
+            slots.append(slot)
+    slot.gen += 1
+    slot.busy = needs_grad
+    return slot
+
+
 class _PatternFn(torch.autograd.Function):
     @staticmethod
     def forward(ctx, frac, lattice, bfac, spec):
         lat = lattice.detach().to("cpu", torch.float64).numpy()
-        xb = XrdBatch(spec["batch"], precision=spec["precision"], friedel=spec["friedel"], device=frac.device,
-                      frac=frac.detach().to(torch.float64).contiguous(),
-                      bfac=bfac.detach().to(torch.float64).contiguous(), lattice=lat,
-                      grid_capacity=spec["grid"].n_points, keep_sf_derivs=any(ctx.needs_input_grad[:3]))
-        refl = xb.enumerate()
-        _, _, I = xb.structure_factors(refl)
-        y = xb.pattern_forward(refl, I, spec["grid"])
-        ctx.xb, ctx.refl, ctx.grid = xb, refl, spec["grid"]
+        slot = _slot_for(spec, frac, bfac, lat, any(ctx.needs_input_grad[:3]))
+        xb = slot.xb
+        xb.enumerate(slot.refl)
+        _, _, I = xb.structure_factors(slot.refl, slot.sf)
+        y = xb.pattern_forward(slot.refl, I, spec["grid"])
+        ctx.slot, ctx.gen, ctx.grid = slot, slot.gen, spec["grid"]
         ctx.lat_device, ctx.lat_dtype = lattice.device, lattice.dtype
         return y
 
     @staticmethod
     def backward(ctx, dy):
-        dfrac, dbfac, dlat = ctx.xb.pattern_backward(ctx.refl, ctx.grid, dy)
+        slot = ctx.slot
+        if slot.gen != ctx.gen:
+            raise RuntimeError("the pattern's forward state was reused by a later call; call backward before "
+                               "evaluating the pattern again")
+        dfrac, dbfac, dlat = slot.xb.pattern_backward(slot.refl, ctx.grid, dy)
+        dfrac, dbfac, dlat = dfrac.clone(), dbfac.clone(), dlat.clone()
+        slot.busy = False
         return dfrac, dlat.to(ctx.lat_device, ctx.lat_dtype), dbfac, None
 
 
@@ -374,7 +433,11 @@ def xrd_pattern(frac: torch.Tensor, lattice: torch.Tensor, bfac: torch.Tensor, b
     occupancies, scattering factors, wavelength and the enumeration range come
     from ``batch`` (whose 2theta range should cover the grid widened by the
     window).  Gradients flow to frac, lattice (per degree for angles) and bfac
-    through the library's adjoint; the reflection set is held fixed."""
+    through the library's adjoint; the reflection set is held fixed.  The
+    planned batch and its device buffers are kept between calls on the same
+    ``batch`` (a new cell takes the old plan when its search box allows), so
+    a refinement loop does not plan and allocate on every step; call
+    backward before the pattern of the same inputs is evaluated again."""
     spec = {"batch": batch, "grid": grid, "precision": precision,
             "friedel": (precision == "mixed") if friedel is None else friedel}
     return _PatternFn.apply(frac, lattice, bfac, spec)

@@ -38,7 +38,7 @@ class xrd_batch_desc(C.Structure):
         ("friedel", C.c_int32), ("grid_capacity", C.c_int32),
         ("keep_sf_derivs", C.c_int32), ("sf_method", C.c_int32),
         ("frac", _vp), ("species", _vp), ("occ", _vp), ("bfac", _vp), ("sf_coeff", _vp),
-        ("stream", _vp),
+        ("stream", _vp), ("forward_only", C.c_int32), ("reserved", C.c_int32),
     ]
 
 
@@ -76,6 +76,8 @@ SIGNATURES = {
     "xrd_batch_create": ([C.POINTER(xrd_batch_desc), C.POINTER(_vp)], C.c_int),
     "xrd_batch_sizes": ([_vp, C.POINTER(xrd_sizes)], C.c_int),
     "xrd_batch_upload": ([_vp, _vp], C.c_int),
+    "xrd_batch_set_stream": ([_vp, _vp], C.c_int),
+    "xrd_batch_set_lattice": ([_vp, _vp, _vp], C.c_int),
     "xrd_enumerate_hkl": ([_vp, _vp, C.POINTER(xrd_refl)], C.c_int),
     "xrd_structure_factors": ([_vp, _vp, C.POINTER(xrd_refl), _vp, _vp, _vp], C.c_int),
     "xrd_merge_peaks": ([_vp, _vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_peaks)], C.c_int),
@@ -128,6 +130,19 @@ def xrd_batch_sizes(batch) -> xrd_sizes:
     s = xrd_sizes()
     check(lib().xrd_batch_sizes(batch, C.byref(s)))
     return s
+
+
+def xrd_batch_set_lattice(batch, lattice_ptr: int, ws: int) -> int:
+    """Status code (XRD_OK or XRD_ERR_CAPACITY when a search box would grow;
+    other errors raise)."""
+    code = lib().xrd_batch_set_lattice(batch, lattice_ptr, ws)
+    if code not in (XRD_OK, XRD_ERR_CAPACITY):
+        check(code)
+    return code
+
+
+def xrd_batch_set_stream(batch, stream: int):
+    check(lib().xrd_batch_set_stream(batch, stream))
 
 
 def xrd_batch_upload(batch, ws: int):

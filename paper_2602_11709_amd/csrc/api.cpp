@@ -248,31 +248,47 @@ int check_refl(const xrd_refl *r) {
 // Structure-factor items in launch order for split threshold ``split``:
 // the expected-filled tiles of the crystals with at least ``split`` atoms (a
 // block per tile, atoms split over its wavefronts), then those of the other
-// crystals, crystal by crystal (neighbouring waves share the crystal's atoms
-// in cache), then every remaining tile, one wavefront each: these mostly find
-// no reflection and end at once, and the few that do are complete on a
-// single wavefront.  Crystals come in descending atom count, so the heaviest
-// work is dispatched first.  Returns the number of block-per-tile items.
-// Reorder a structure-factor work list so that a crystal's items run on one
+// crystals (one wavefront per tile), then per crystal one item for its
+// remaining capacity tiles, which a single wavefront walks in order: they
+// mostly hold no reflection, and the few that do are complete on one
+// wavefront.  Crystals come in descending atom count, so the heaviest work is
+// dispatched first.
+//
+// The expected-filled items are placed so that a crystal's items run on one
 // XCD (one L2 holds its atoms and reflections).  Workgroups reach the eight
 // XCDs round-robin by block index, so block i runs on XCD i mod 8.  Crystals
 // are spread over the XCDs by expected work (largest first, onto the least
-// loaded), and each XCD's items keep their relative order (expected-filled
-// tiles first).  The first n_heavy items take a block each and the rest four
-// to a block, so slot i of the heavy part and the four slots of light block j
-// draw from the queue of the XCD their block lands on; when that queue is
-// empty, from the longest other one.  Only the expected-filled items
-// [0, n_expected) are regrouped: the tail of capacity tiles, which mostly find
-// no reflection and end at once, keeps its order.
-void xcd_group(const xrd_batch *b, int64_t n_heavy, int64_t n_expected, std::vector<SfItem> *items) {
+// loaded); each XCD keeps a queue of its crystals in the order above.  The
+// heavy items take a block each and the light ones four to a block, so slot
+// i of the heavy part and the four slots of light block j draw the next tile
+// of the queue of the XCD their block lands on; when that queue is empty,
+// from the longest other one.  The items are written in that order directly.
+//
+// ``rec``: the row-recurrence tiles (64 segments each) instead of the direct
+// kernel's (kSfTile reflections each).  ``forward``: only the crystals whose
+// forward sum takes that method (the adjoint's table lists every crystal).
+// Returns the number of block-per-tile items.
+int64_t sf_table(const xrd_batch *b, int32_t split, std::vector<SfItem> *items, bool rec = false,
+                 bool forward = false) {
   constexpr int kXcd = 8;
+  items->clear();
   const int64_t nc = (int64_t)b->plan.size();
-  std::vector<int> xcd_of(nc, 0);
+  auto listed = [&](int32_t c) { return !forward || b->use_rec.empty() || (b->use_rec[c] != 0) == rec; };
+  auto tiles = [&](int32_t c) -> int32_t { return !listed(c) ? 0 : rec ? b->rec_tiles[c] : b->plan[c].n_tiles; };
+  auto likely = [&](int32_t c) -> int32_t { return !listed(c) ? 0 : rec ? b->rec_likely[c] : b->sf_likely[c]; };
+  auto item = [&](int32_t c, int32_t t, int32_t tail) {
+    const CrystalPlan &P = b->plan[c];
+    return SfItem{c, t, (int32_t)P.atom_begin, (int32_t)P.atom_end, (int32_t)P.run_begin, tail, {0, 0}};
+  };
+  auto heavy = [&](int32_t c) { return b->plan[c].atom_end - b->plan[c].atom_begin >= split; };
+  // XCD of each crystal: by expected work, largest first, onto the least loaded
+  std::vector<int8_t> xcd_of(nc, 0);
   {
     std::vector<std::pair<double, int32_t>> work;
+    work.reserve(nc);
     for (int32_t c = 0; c < nc; ++c) {
       const CrystalPlan &P = b->plan[c];
-      work.push_back({(double)b->sf_likely[c] * (double)std::max<int64_t>(P.atom_end - P.atom_begin, 1), c});
+      work.push_back({(double)likely(c) * (double)std::max<int64_t>(P.atom_end - P.atom_begin, 1), c});
     }
     std::stable_sort(work.begin(), work.end(), [](const auto &x, const auto &y) { return x.first > y.first; });
     double load[kXcd] = {};
@@ -280,66 +296,58 @@ void xcd_group(const xrd_batch *b, int64_t n_heavy, int64_t n_expected, std::vec
       int best = 0;
       for (int x = 1; x < kXcd; ++x)
         if (load[x] < load[best]) best = x;
-      xcd_of[w.second] = best;
+      xcd_of[w.second] = (int8_t)best;
       load[best] += w.first;
     }
   }
-  auto regroup = [&](int64_t lo, int64_t hi, int per_block, int64_t first_block) {
-    std::vector<std::vector<SfItem>> q(kXcd);
-    for (int64_t i = lo; i < hi; ++i) q[xcd_of[(*items)[i].crystal]].push_back((*items)[i]);
-    std::vector<size_t> head(kXcd, 0);
-    int64_t o = lo;
-    for (int64_t blk = first_block; o < hi; ++blk) {
+  int64_t cap = 0;
+  for (int32_t c = 0; c < nc; ++c) cap += likely(c) + (likely(c) < tiles(c) ? 1 : 0);
+  items->reserve((size_t)cap);
+  // one part (heavy or light): per-XCD queues of crystals with a cursor
+  auto emit_part = [&](bool want_heavy, int per_block, int64_t first_block) {
+    struct Queue {
+      std::vector<int32_t> cr;
+      size_t ci = 0;
+      int32_t t = 0;
+      int64_t left = 0;
+    } q[kXcd];
+    for (int32_t c : b->sf_order)
+      if (heavy(c) == want_heavy && likely(c) > 0) {
+        q[xcd_of[c]].cr.push_back(c);
+        q[xcd_of[c]].left += likely(c);
+      }
+    int64_t remaining = 0;
+    for (int x = 0; x < kXcd; ++x) remaining += q[x].left;
+    for (int64_t blk = first_block; remaining > 0; ++blk) {
       const int x = (int)(blk % kXcd);
-      for (int k = 0; k < per_block && o < hi; ++k) {
+      for (int k = 0; k < per_block && remaining > 0; ++k) {
         int from = x;
-        if (head[from] == q[from].size()) {
-          size_t most = 0;
+        if (q[from].left == 0) {
+          int64_t most = 0;
           for (int y = 0; y < kXcd; ++y)
-            if (q[y].size() - head[y] > most) {
-              most = q[y].size() - head[y];
+            if (q[y].left > most) {
+              most = q[y].left;
               from = y;
             }
         }
-        (*items)[o++] = q[from][head[from]++];
+        Queue &Q = q[from];
+        const int32_t c = Q.cr[Q.ci];
+        items->push_back(item(c, Q.t, 0));
+        if (++Q.t == likely(c)) {
+          Q.t = 0;
+          ++Q.ci;
+        }
+        --Q.left;
+        --remaining;
       }
     }
   };
-  regroup(0, n_heavy, 1, 0);
-  regroup(n_heavy, n_expected, 4, n_heavy);  // four wavefronts to a light block
-}
-
-// ``rec``: the row-recurrence tiles (64 segments each) instead of the direct
-// kernel's (kSfTile reflections each).  ``forward``: only the crystals whose
-// forward sum takes that method (the adjoint's table lists every crystal).
-int64_t sf_table(const xrd_batch *b, int32_t split, std::vector<SfItem> *items, bool rec = false,
-                 bool forward = false) {
-  items->clear();
-  const int64_t nc = (int64_t)b->plan.size();
-  auto listed = [&](int32_t c) { return !forward || b->use_rec.empty() || (b->use_rec[c] != 0) == rec; };
-  auto tiles = [&](int32_t c) { return !listed(c) ? 0 : rec ? b->rec_tiles[c] : b->plan[c].n_tiles; };
-  auto likely = [&](int32_t c) { return !listed(c) ? 0 : rec ? b->rec_likely[c] : b->sf_likely[c]; };
-  int64_t cap = 0;
-  for (int32_t c = 0; c < nc; ++c) cap += tiles(c);
-  items->reserve((size_t)cap);
-  auto item = [&](int32_t c, int32_t t) {
-    const CrystalPlan &P = b->plan[c];
-    return SfItem{c, t, (int32_t)P.atom_begin, (int32_t)P.atom_end, (int32_t)P.run_begin, {0, 0, 0}};
-  };
-  auto heavy = [&](int32_t c) { return b->plan[c].atom_end - b->plan[c].atom_begin >= split; };
-  for (int32_t c : b->sf_order)
-    if (heavy(c))
-      for (int32_t t = 0; t < likely(c); ++t) items->push_back(item(c, t));
+  emit_part(true, 1, 0);
   const int64_t n_heavy = (int64_t)items->size();
-  for (int32_t c : b->sf_order)
-    if (!heavy(c))
-      for (int32_t t = 0; t < likely(c); ++t) items->push_back(item(c, t));
-  const int64_t n_expected = (int64_t)items->size();
+  emit_part(false, 4, n_heavy);  // four wavefronts to a light block
   for (int pass = 0; pass < 2; ++pass)
     for (int32_t c : b->sf_order)
-      if (heavy(c) == (pass == 0))
-        for (int32_t t = likely(c); t < tiles(c); ++t) items->push_back(item(c, t));
-  xcd_group(b, n_heavy, n_expected, items);
+      if (heavy(c) == (pass == 0) && likely(c) < tiles(c)) items->push_back(item(c, likely(c), 1));
   return n_heavy;
 }
 
@@ -368,6 +376,24 @@ void choose_methods(xrd_batch *b) {
 
 }  // namespace
 
+// Host-side sizes shared with the kernels' launch code.
+int64_t xrd::scan_part_elems(int64_t n) {
+  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  return (nb > 0 ? nb : 1) + 1;
+}
+
+// LDS of the atom-major adjoint block: the staged reflection tile (h, k, l in
+// double; s^2, gA, gB and the species' scattering factors in the working
+// precision) and the species coefficients, or the slice reduction (one
+// double4 per thread) that reuses the space, whichever is larger.
+size_t xrd::atom_bw_lds_bytes(bool mixed, int tile, int runs_cap) {
+  const size_t rs = mixed ? sizeof(float) : sizeof(double);
+  const size_t tiles = (size_t)tile * 3 * sizeof(double) + (size_t)tile * 3 * rs + (size_t)tile * runs_cap * rs +
+                       (size_t)runs_cap * 9 * rs;
+  const size_t red = (size_t)kSfThreads * 4 * sizeof(double);
+  return tiles > red ? tiles : red;
+}
+
 extern "C" {
 
 const char *xrd_last_error(void) { return g_err.c_str(); }
@@ -394,6 +420,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     return fail(XRD_ERR_INVALID_ARG, "keep_sf_derivs must be 0 or 1");
   if (d->sf_method != XRD_SF_DIRECT && d->sf_method != XRD_SF_RECURRENCE && d->sf_method != XRD_SF_AUTO)
     return fail(XRD_ERR_INVALID_ARG, "unknown sf_method");
+  if (d->forward_only != 0 && d->forward_only != 1) return fail(XRD_ERR_INVALID_ARG, "forward_only must be 0 or 1");
   if (nc > 0 && (!d->lattice || !d->atom_offset || !d->two_theta_min || !d->two_theta_max))
     return fail(XRD_ERR_INVALID_ARG, "host arrays must be non-NULL");
   if (!d->sf_coeff) return fail(XRD_ERR_INVALID_ARG, "sf_coeff is NULL");
@@ -609,7 +636,9 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   std::stable_sort(b->sf_order.begin(), b->sf_order.end(), [&](int32_t x, int32_t y) {
     return (b->atom_offset[x + 1] - b->atom_offset[x]) > (b->atom_offset[y + 1] - b->atom_offset[y]);
   });
+  const bool adjoint = d->forward_only == 0;
   for (int32_t c : b->sf_order) {
+    if (!adjoint) break;
     const CrystalPlan &P = b->plan[c];
     const int64_t na = P.atom_end - P.atom_begin;
     const int64_t ab = ceil_div(na, kAtomBlock);
@@ -619,7 +648,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
         for (int32_t k = 0; k < P.n_hchunks; ++k) b->bw_items.push_back(BwItem{(int32_t)c, (int32_t)a, k, 0});
     }
   }
-  b->sf_heavy_bw = sf_table(b, b->split_bw, &b->sf_items_bw);
+  if (adjoint) b->sf_heavy_bw = sf_table(b, b->split_bw, &b->sf_items_bw);
   b->rec = d->sf_method != XRD_SF_DIRECT;
   if (b->rec) {
     // segments: at most one per evaluated reflection (capacity); expected
@@ -686,14 +715,17 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.tmp_first = take(8 * rc);
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(ec, bins), rc);
   L.scan_part = take(8 * scan_part_elems(scan_n));
-  L.bw_w1 = take(8 * rc);
-  L.bw_w2 = take(8 * rc);
-  L.bw_ga = take(8 * rc);
-  L.bw_gb = take(8 * rc);
-  L.bw_dq = take(8 * rc);
-  L.bw_part = take(32 * parts);
-  L.bw_partf = take(32 * pfused);
-  L.bw_part6 = take(48 * tiles_total);
+  L.bw_w1 = L.bw_w2 = L.bw_ga = L.bw_gb = L.bw_dq = L.bw_part = L.bw_partf = L.bw_part6 = -1;
+  if (adjoint) {
+    L.bw_w1 = take(8 * rc);
+    L.bw_w2 = take(8 * rc);
+    L.bw_ga = take(8 * rc);
+    L.bw_gb = take(8 * rc);
+    L.bw_dq = take(8 * rc);
+    L.bw_part = take(32 * parts);
+    L.bw_partf = take(32 * pfused);
+    L.bw_part6 = take(48 * tiles_total);
+  }
   L.sf_deriv = d->keep_sf_derivs ? take((d->precision == XRD_MIXED ? 16 : 32) * rc) : -1;
   L.coeff_f = take((int64_t)sizeof(CoeffF) * d->n_species);
   L.fam_ops = take((int64_t)sizeof(FamOps) * nc);
@@ -749,6 +781,52 @@ int xrd_batch_sizes(const xrd_batch *b, xrd_sizes *out) {
   out->workspace_bytes = b->ws.total;
   out->half_capacity = b->half_cap;
   out->noalloc_merge_bytes = b->mws.total;
+  return XRD_OK;
+}
+
+int xrd_batch_set_lattice(xrd_batch *b, const double *lattice, void *ws) {
+  if (!b || !lattice) return fail(XRD_ERR_INVALID_ARG, "batch or lattice is NULL");
+  if (int e = check_ws(b, ws)) return e;
+  const int64_t nc = b->desc.n_crystals;
+  const double lam = b->desc.wavelength;
+  std::vector<double> gs(6 * nc);
+  for (int64_t c = 0; c < nc; ++c) {
+    const double *lat = lattice + 6 * c;
+    if (!reciprocal_metric(lat, gs.data() + 6 * c))
+      return fail(XRD_ERR_INVALID_CELL, "crystal " + std::to_string(c) + ": invalid cell");
+    const CrystalPlan &P = b->plan[c];
+    const double gmax = 2.0 * std::sin(0.5 * P.tmax * kPi / 180.0) / lam;
+    if (std::floor(gmax * lat[0] * (1.0 + 1e-9)) > P.H || std::floor(gmax * lat[1] * (1.0 + 1e-9)) > P.K ||
+        std::floor(gmax * lat[2] * (1.0 + 1e-9)) > P.L)
+      return fail(XRD_ERR_CAPACITY, "crystal " + std::to_string(c) + ": the new cell needs a larger search box");
+  }
+  // every crystal fits its box: take the new metric (the boxes, capacities
+  // and launch tables stay; the kernels bound each row from the metric)
+  for (int64_t c = 0; c < nc; ++c) {
+    CrystalPlan &P = b->plan[c];
+    for (int i = 0; i < 6; ++i) {
+      P.gs[i] = gs[6 * c + i];
+      P.lat[i] = lattice[6 * c + i];
+      b->lattice[6 * c + i] = lattice[6 * c + i];
+    }
+    b->fam_ops[c] = family_ops(P.gs);
+  }
+  hipStream_t s = stream_of(b);
+  const WsLayout &L = b->ws;
+  hipError_t e = hipMemcpyAsync(at<char>(ws, L.plan), b->plan.data(), sizeof(CrystalPlan) * nc, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(at<char>(ws, L.fam_ops), b->fam_ops.data(), sizeof(FamOps) * nc, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("set_lattice: ") + hipGetErrorString(e));
+  b->sorted_ws = nullptr;
+  b->sorted_tt = nullptr;
+  b->deriv_ws = nullptr;
+  b->deriv_h = nullptr;
+  return XRD_OK;
+}
+
+int xrd_batch_set_stream(xrd_batch *b, void *stream) {
+  if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");
+  b->desc.stream = stream;
   return XRD_OK;
 }
 
@@ -1078,6 +1156,7 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   if (int e = check_grid(g)) return e;
   if (!dL_dy || !dL_dlattice || (b->n_atoms > 0 && (!dL_dfrac || !dL_dbfac)))
     return fail(XRD_ERR_INVALID_ARG, "gradient buffers must be non-NULL");
+  if (b->desc.forward_only) return fail(XRD_ERR_UNSUPPORTED, "the batch was created forward_only (no adjoint tables)");
   const WsLayout &L = b->ws;
   hipStream_t s = stream_of(b);
   const bool mixed = b->desc.precision == XRD_MIXED, friedel = b->desc.friedel != 0;
@@ -1114,13 +1193,14 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
   hipStream_t s = stream_of(b);
   const bool mixed = b->desc.precision == XRD_MIXED, friedel = b->desc.friedel != 0;
   const CrystalPlan *plan = at<CrystalPlan>(ws, L.plan);
-  // outputs of the timing runs: A, B and I go to the reflection-gradient
-  // scratch (the adjoint rewrites it before reading it), derivatives (when
-  // kept) to their usual place
-  void *A = at<void>(ws, L.bw_ga), *B = at<void>(ws, L.bw_gb);
-  double *I = at<double>(ws, L.bw_dq);
+  // outputs of the timing runs: A, B and I go to the merge's staging scratch
+  // (each merge rewrites it before reading it), derivatives (when kept) to
+  // their usual place
+  void *A = at<void>(ws, L.tmp_tt), *B = at<void>(ws, L.tmp_i);
+  double *I = at<double>(ws, L.tmp_first);
   void *deriv = L.sf_deriv >= 0 ? at<char>(ws, L.sf_deriv) : nullptr;
-  double *w1 = at<double>(ws, L.bw_w1), *w2 = at<double>(ws, L.bw_w2);
+  const bool adjoint = !b->desc.forward_only;
+  double *w1 = adjoint ? at<double>(ws, L.bw_w1) : nullptr, *w2 = adjoint ? at<double>(ws, L.bw_w2) : nullptr;
   const int64_t nc = b->desc.n_crystals;
   auto run_bw = [&](const std::vector<SfItem> &t, int64_t nh) {
     launch_sf_bw(mixed, friedel, at<SfItem>(ws, L.sf_items_bw), (int64_t)t.size(), nh, plan, r->refl_offset, r->h,
@@ -1212,11 +1292,13 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
       upload_fwd();
     }
     // the adjoint's inputs: derivatives of the chosen forward tables, zero grid weights
-    if (e == hipSuccess) launch_forward_sums(b, ws, r, A, B, I, deriv);
-    launch_fill_u64(reinterpret_cast<uint64_t *>(w1), b->refl_cap, 0, s);
-    launch_fill_u64(reinterpret_cast<uint64_t *>(w2), b->refl_cap, 0, s);
-    if (e == hipSuccess) e = hipGetLastError();
-    {
+    if (adjoint && e == hipSuccess) {
+      launch_forward_sums(b, ws, r, A, B, I, deriv);
+      launch_fill_u64(reinterpret_cast<uint64_t *>(w1), b->refl_cap, 0, s);
+      launch_fill_u64(reinterpret_cast<uint64_t *>(w2), b->refl_cap, 0, s);
+      e = hipGetLastError();
+    }
+    if (adjoint) {
       std::vector<SfItem> t;
       std::vector<int64_t> seen;
       float best = 0.f;
@@ -1236,10 +1318,12 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
         }
       }
     }
-    b->sf_heavy_bw = sf_table(b, b->split_bw, &b->sf_items_bw);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(at<char>(ws, L.sf_items_bw), b->sf_items_bw.data(), sizeof(SfItem) * b->sf_items_bw.size(),
-                         hipMemcpyHostToDevice, s);
+    if (adjoint) {
+      b->sf_heavy_bw = sf_table(b, b->split_bw, &b->sf_items_bw);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(at<char>(ws, L.sf_items_bw), b->sf_items_bw.data(), sizeof(SfItem) * b->sf_items_bw.size(),
+                           hipMemcpyHostToDevice, s);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
   }
   for (hipEvent_t x : ev)

@@ -120,11 +120,6 @@ int fill_grid(int64_t n) {
 
 }  // namespace
 
-int64_t scan_part_elems(int64_t n) {
-  const int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-  return (nb > 0 ? nb : 1) + 1;
-}
-
 void launch_scan_i32(const int32_t *in, int64_t n, const int64_t *n_dev, int64_t *out, int64_t *part,
                      hipStream_t s) {
   int64_t nb = (n + kScanBlock - 1) / kScanBlock;

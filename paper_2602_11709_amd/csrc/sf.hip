@@ -38,7 +38,7 @@ namespace xrd {
 
 namespace {
 
-constexpr int kThreads = 256;
+constexpr int kThreads = kSfThreads;
 constexpr int kAtomTile = 64;  // atoms per single-precision partial sum
 constexpr double kLn2 = 0.69314718055994530942;
 
@@ -434,59 +434,66 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
   const int64_t nref = r1 - r0;
   const int64_t first = FRIEDEL ? r0 + nref / 2 : r0;
   const int64_t count = FRIEDEL ? nref / 2 : nref;
-  const int64_t tbase = (int64_t)it.tile * kSfTile;
-  if (tbase >= count) return;  // uniform over a heavy block
-  const int lane = threadIdx.x & 63;
-  int64_t idx[R];
-  bool valid[R];
-  double h[R], k[R], l[R], s2d[R], lpv[R];
-  float s2[R];
+  // a tail item walks the crystal's tiles from its first one on (the tiles
+  // beyond the expected reflection count, which are mostly empty)
+  auto tile_body = [&](int32_t tile) -> bool {
+    const int64_t tbase = (int64_t)tile * kSfTile;
+    if (tbase >= count) return false;  // uniform over a heavy block
+    const int lane = threadIdx.x & 63;
+    int64_t idx[R];
+    bool valid[R];
+    double h[R], k[R], l[R], s2d[R], lpv[R];
+    float s2[R];
 #pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int64_t t = tbase + u * 64 + lane;
-    valid[u] = t < count;
-    idx[u] = first + (valid[u] ? t : 0);
-    h[u] = hh[idx[u]];
-    k[u] = kk[idx[u]];
-    l[u] = ll[idx[u]];
-    s2d[u] = 0.25 * qq[idx[u]];
-    s2[u] = (float)s2d[u];
-    lpv[u] = lpp[idx[u]];  // loaded with the rest, not after the sums
-  }
-  int wa, wb;
-  part_range(it, ww, &wa, &wb);
-  double A[R], B[R], dA[R], dB[R];
-  if (!sf_tile_sums<MIXED, DERIV>(ww, lane, runs + it.run_begin, run_count[it.crystal], wa, wb, atoms, coeff, coeff_f,
-                                  h, k, l, s2d, s2, s_part, false, A, B, dA, dB))
-    return;
+    for (int u = 0; u < R; ++u) {
+      const int64_t t = tbase + u * 64 + lane;
+      valid[u] = t < count;
+      idx[u] = first + (valid[u] ? t : 0);
+      h[u] = hh[idx[u]];
+      k[u] = kk[idx[u]];
+      l[u] = ll[idx[u]];
+      s2d[u] = 0.25 * qq[idx[u]];
+      s2[u] = (float)s2d[u];
+      lpv[u] = lpp[idx[u]];  // loaded with the rest, not after the sums
+    }
+    int wa, wb;
+    part_range(it, ww, &wa, &wb);
+    double A[R], B[R], dA[R], dB[R];
+    if (!sf_tile_sums<MIXED, DERIV>(ww, lane, runs + it.run_begin, run_count[it.crystal], wa, wb, atoms, coeff, coeff_f,
+                                    h, k, l, s2d, s2, s_part, false, A, B, dA, dB))
+      return false;
 #pragma unroll
-  for (int u = 0; u < R; ++u) {
-    if (!valid[u]) continue;
-    const double I = (A[u] * A[u] + B[u] * B[u]) * lpv[u];
-    Iout[idx[u]] = I;
-    if constexpr (DERIV) store_derivs<MIXED>(cache, idx[u], A[u], B[u], dA[u], dB[u]);
-    const int64_t m = r0 + r1 - 1 - idx[u];
-    if constexpr (MIXED) {
-      float *Af = (float *)Aout;
-      float *Bf = (float *)Bout;
-      Af[idx[u]] = (float)A[u];
-      Bf[idx[u]] = (float)B[u];
-      if (FRIEDEL) {
-        Af[m] = (float)A[u];
-        Bf[m] = -(float)B[u];
-        Iout[m] = I;
-      }
-    } else {
-      double *Ad = (double *)Aout;
-      double *Bd = (double *)Bout;
-      Ad[idx[u]] = A[u];
-      Bd[idx[u]] = B[u];
-      if (FRIEDEL) {
-        Ad[m] = A[u];
-        Bd[m] = -B[u];
-        Iout[m] = I;
+    for (int u = 0; u < R; ++u) {
+      if (!valid[u]) continue;
+      const double I = (A[u] * A[u] + B[u] * B[u]) * lpv[u];
+      Iout[idx[u]] = I;
+      if constexpr (DERIV) store_derivs<MIXED>(cache, idx[u], A[u], B[u], dA[u], dB[u]);
+      const int64_t m = r0 + r1 - 1 - idx[u];
+      if constexpr (MIXED) {
+        float *Af = (float *)Aout;
+        float *Bf = (float *)Bout;
+        Af[idx[u]] = (float)A[u];
+        Bf[idx[u]] = (float)B[u];
+        if (FRIEDEL) {
+          Af[m] = (float)A[u];
+          Bf[m] = -(float)B[u];
+          Iout[m] = I;
+        }
+      } else {
+        double *Ad = (double *)Aout;
+        double *Bd = (double *)Bout;
+        Ad[idx[u]] = A[u];
+        Bd[idx[u]] = B[u];
+        if (FRIEDEL) {
+          Ad[m] = A[u];
+          Bd[m] = -B[u];
+          Iout[m] = I;
+        }
       }
     }
+    return true;
+  };
+  for (int32_t tile = it.tile; tile_body(tile) && it.tail; ++tile) {
   }
 }
 
@@ -527,183 +534,189 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
   const int64_t nref = r1 - r0;
   const int64_t first = friedel ? r0 + nref / 2 : r0;
   const int64_t count = friedel ? nref / 2 : nref;
-  const int64_t tbase = (int64_t)it.tile * kSfTile;
-  if (tbase >= count) return;
-  const int lane = threadIdx.x & 63;
-  int64_t idx[R];
-  bool valid[R];
-  double h[R], k[R], l[R], s2d[R];
-  float s2[R];
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int64_t t = tbase + u * 64 + lane;
-    valid[u] = t < count;
-    idx[u] = first + (valid[u] ? t : 0);
-    h[u] = hh[idx[u]];
-    k[u] = kk[idx[u]];
-    l[u] = ll[idx[u]];
-    s2d[u] = 0.25 * qq[idx[u]];
-    s2[u] = (float)s2d[u];
-  }
-  const CrystalPlan &P = plan[it.crystal];
-  const SpeciesRun *cr = runs + it.run_begin;
-  const int nr = run_count[it.crystal];
-  int wa, wb;
-  part_range(it, ww, &wa, &wb);
-  double A[R], B[R], dA[R], dB[R];
-  if constexpr (CACHED) {
-#pragma unroll
-    for (int u = 0; u < R; ++u) load_derivs<MIXED>(cache, idx[u], &A[u], &B[u], &dA[u], &dB[u]);
-  } else {
-    sf_tile_sums<MIXED, true>(ww, lane, cr, nr, wa, wb, atoms, coeff, coeff_f, h, k, l, s2d, s2, s_part, true, A, B,
-                              dA, dB);
-  }
-  const double m = friedel ? 2.0 : 1.0;
-  const double l2 = lambda * lambda;
-  double gA[R], gB[R], dqv[R];
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    gA[u] = gB[u] = dqv[u] = 0.0;
-    if (!valid[u]) continue;
-    const int64_t i = idx[u];
-    const double q = qq[i], lp = lpp[i];
-    const double us = 0.25 * l2 * q;  // sin^2(theta)
-    const double sq = sqrt(1.0 - us);
-    const double num = 1.0 + (1.0 - 2.0 * us) * (1.0 - 2.0 * us);
-    const double den = us * sq;
-    const double dnum = -4.0 * (1.0 - 2.0 * us);
-    const double dden = (2.0 - 3.0 * us) / (2.0 * sq);
-    const double dlp_dq = (dnum * den - num * dden) / (den * den) * (0.25 * l2);
-    const double dtt_dq = (360.0 / 3.14159265358979323846) * lambda / (4.0 * sqrt(q) * sq);
-    const double f2 = A[u] * A[u] + B[u] * B[u];
-    const double gI = m * w1[i];
-    gA[u] = 2.0 * lp * A[u] * gI;
-    gB[u] = 2.0 * lp * B[u] * gI;
-    if (ww.part != 0) continue;
-    if (!P.fused) {
-      ga[i] = gA[u];
-      gb[i] = gB[u];
-    }
-    dqv[u] = gI * f2 * dlp_dq + 0.25 * (gA[u] * dA[u] + gB[u] * dB[u]) + m * w2[i] * f2 * lp * dtt_dq;
-    dq[i] = dqv[u];
-  }
-  if (ww.part == 0) {
-    // the tile's row of dL/dG*: sum over its reflections of dL/dq times
-    // (h^2, k^2, l^2, 2hk, 2hl, 2kl), as q = sum_ij G*_ij h_i h_j
-    double r6[6];
-#pragma unroll
-    for (int e = 0; e < 6; ++e) r6[e] = 0.0;
+  // a tail item walks the crystal's tiles from its first one on
+  auto tile_body = [&](int32_t tile) -> bool {
+    const int64_t tbase = (int64_t)tile * kSfTile;
+    if (tbase >= count) return false;
+    const int lane = threadIdx.x & 63;
+    int64_t idx[R];
+    bool valid[R];
+    double h[R], k[R], l[R], s2d[R];
+    float s2[R];
 #pragma unroll
     for (int u = 0; u < R; ++u) {
-      const double g = dqv[u];  // zero for lanes past the tile's end
-      r6[0] += g * h[u] * h[u];
-      r6[1] += g * k[u] * k[u];
-      r6[2] += g * l[u] * l[u];
-      r6[3] += 2.0 * g * h[u] * k[u];
-      r6[4] += 2.0 * g * h[u] * l[u];
-      r6[5] += 2.0 * g * k[u] * l[u];
+      const int64_t t = tbase + u * 64 + lane;
+      valid[u] = t < count;
+      idx[u] = first + (valid[u] ? t : 0);
+      h[u] = hh[idx[u]];
+      k[u] = kk[idx[u]];
+      l[u] = ll[idx[u]];
+      s2d[u] = 0.25 * qq[idx[u]];
+      s2[u] = (float)s2d[u];
     }
+    const CrystalPlan &P = plan[it.crystal];
+    const SpeciesRun *cr = runs + it.run_begin;
+    const int nr = run_count[it.crystal];
+    int wa, wb;
+    part_range(it, ww, &wa, &wb);
+    double A[R], B[R], dA[R], dB[R];
+    if constexpr (CACHED) {
 #pragma unroll
-    for (int e = 0; e < 6; ++e) r6[e] = wave_sum_to_63(r6[e]);
-    if (lane == 63) {
-      double *row = part6 + ((int64_t)P.tile_begin + it.tile) * 6;
-#pragma unroll
-      for (int e = 0; e < 6; ++e) row[e] = r6[e];
+      for (int u = 0; u < R; ++u) load_derivs<MIXED>(cache, idx[u], &A[u], &B[u], &dA[u], &dB[u]);
+    } else {
+      sf_tile_sums<MIXED, true>(ww, lane, cr, nr, wa, wb, atoms, coeff, coeff_f, h, k, l, s2d, s2, s_part, true, A, B,
+                                dA, dB);
     }
-  }
-  if (!P.fused) return;
-  // Fused atom gradients (small crystals): walk the atoms again; for each atom
-  // the lanes' contributions from this tile's reflections are summed across
-  // the wavefront and written as one partial row (tile, atom):
-  //   (sum h P, sum k P, sum l P, sum s^2 Q),  P = w (gB cos - gA sin),
-  //   Q = w (gA cos + gB sin),  w = occ f e^{-B s^2}.
-  double4 *out = part_fused + P.pf_begin + (int64_t)it.tile * (P.atom_end - P.atom_begin);
-  for (int ir = 0; ir < nr; ++ir) {
-    const SpeciesRun run = cr[ir];
-    if (max(run.begin, wa) >= min(run.end, wb)) continue;
-    const double *c9 = coeff + 9 * run.species;
-    if constexpr (MIXED) {
-      const CoeffF cf = coeff_f[run.species];
-      float f[R], fA[R], fB[R], hf[R], kf[R], lf[R];
+    const double m = friedel ? 2.0 : 1.0;
+    const double l2 = lambda * lambda;
+    double gA[R], gB[R], dqv[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      gA[u] = gB[u] = dqv[u] = 0.0;
+      if (!valid[u]) continue;
+      const int64_t i = idx[u];
+      const double q = qq[i], lp = lpp[i];
+      const double us = 0.25 * l2 * q;  // sin^2(theta)
+      const double sq = sqrt(1.0 - us);
+      const double num = 1.0 + (1.0 - 2.0 * us) * (1.0 - 2.0 * us);
+      const double den = us * sq;
+      const double dnum = -4.0 * (1.0 - 2.0 * us);
+      const double dden = (2.0 - 3.0 * us) / (2.0 * sq);
+      const double dlp_dq = (dnum * den - num * dden) / (den * den) * (0.25 * l2);
+      const double dtt_dq = (360.0 / 3.14159265358979323846) * lambda / (4.0 * sqrt(q) * sq);
+      const double f2 = A[u] * A[u] + B[u] * B[u];
+      const double gI = m * w1[i];
+      gA[u] = 2.0 * lp * A[u] * gI;
+      gB[u] = 2.0 * lp * B[u] * gI;
+      if (ww.part != 0) continue;
+      if (!P.fused) {
+        ga[i] = gA[u];
+        gb[i] = gB[u];
+      }
+      dqv[u] = gI * f2 * dlp_dq + 0.25 * (gA[u] * dA[u] + gB[u] * dB[u]) + m * w2[i] * f2 * lp * dtt_dq;
+      dq[i] = dqv[u];
+    }
+    if (ww.part == 0) {
+      // the tile's row of dL/dG*: sum over its reflections of dL/dq times
+      // (h^2, k^2, l^2, 2hk, 2hl, 2kl), as q = sum_ij G*_ij h_i h_j
+      double r6[6];
+#pragma unroll
+      for (int e = 0; e < 6; ++e) r6[e] = 0.0;
 #pragma unroll
       for (int u = 0; u < R; ++u) {
-        f[u] = fsc_f32(cf, s2[u]);
-        fA[u] = (float)gA[u] * f[u];
-        fB[u] = (float)gB[u] * f[u];
-        hf[u] = (float)h[u];
-        kf[u] = (float)k[u];
-        lf[u] = (float)l[u];
+        const double g = dqv[u];  // zero for lanes past the tile's end
+        r6[0] += g * h[u] * h[u];
+        r6[1] += g * k[u] * k[u];
+        r6[2] += g * l[u] * l[u];
+        r6[3] += 2.0 * g * h[u] * k[u];
+        r6[4] += 2.0 * g * h[u] * l[u];
+        r6[5] += 2.0 * g * k[u] * l[u];
       }
-      // four atoms per round: their records load together, and the 16 sums
-      // (atom q, component c at index 4q + c) are reduced in one butterfly;
-      // lane 4q + c then writes component c of atom q (records past the
-      // range's end are re-read copies of its last atom and are not written)
-      const int rb = max(run.begin, wa), re = min(run.end, wb);
-      for (int j0 = rb; j0 < re; j0 += 4) {
-        AtomRec a4[4];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a4[q] = atoms[min(j0 + q, re - 1)];
-        float v[16];
+      for (int e = 0; e < 6; ++e) r6[e] = wave_sum_to_63(r6[e]);
+      if (lane == 63) {
+        double *row = part6 + ((int64_t)P.tile_begin + tile) * 6;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const AtomRec &a = a4[q];
-          float sx = 0.f, sy = 0.f, sz = 0.f, sb = 0.f;
+        for (int e = 0; e < 6; ++e) row[e] = r6[e];
+      }
+    }
+    if (!P.fused) return true;
+    // Fused atom gradients (small crystals): walk the atoms again; for each atom
+    // the lanes' contributions from this tile's reflections are summed across
+    // the wavefront and written as one partial row (tile, atom):
+    //   (sum h P, sum k P, sum l P, sum s^2 Q),  P = w (gB cos - gA sin),
+    //   Q = w (gA cos + gB sin),  w = occ f e^{-B s^2}.
+    double4 *out = part_fused + P.pf_begin + (int64_t)tile * (P.atom_end - P.atom_begin);
+    for (int ir = 0; ir < nr; ++ir) {
+      const SpeciesRun run = cr[ir];
+      if (max(run.begin, wa) >= min(run.end, wb)) continue;
+      const double *c9 = coeff + 9 * run.species;
+      if constexpr (MIXED) {
+        const CoeffF cf = coeff_f[run.species];
+        float f[R], fA[R], fB[R], hf[R], kf[R], lf[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          f[u] = fsc_f32(cf, s2[u]);
+          fA[u] = (float)gA[u] * f[u];
+          fB[u] = (float)gB[u] * f[u];
+          hf[u] = (float)h[u];
+          kf[u] = (float)k[u];
+          lf[u] = (float)l[u];
+        }
+        // four atoms per round: their records load together, and the 16 sums
+        // (atom q, component c at index 4q + c) are reduced in one butterfly;
+        // lane 4q + c then writes component c of atom q (records past the
+        // range's end are re-read copies of its last atom and are not written)
+        const int rb = max(run.begin, wa), re = min(run.end, wb);
+        for (int j0 = rb; j0 < re; j0 += 4) {
+          AtomRec a4[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a4[q] = atoms[min(j0 + q, re - 1)];
+          float v[16];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const AtomRec &a = a4[q];
+            float sx = 0.f, sy = 0.f, sz = 0.f, sb = 0.f;
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+              const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+              const float rho = (float)__builtin_amdgcn_fract(t);
+              const float sn = __builtin_amdgcn_sinf(rho);
+              const float cs = __builtin_amdgcn_cosf(rho);
+              const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
+              const float pP = w * (fB[u] * cs - fA[u] * sn);
+              const float pQ = w * (fA[u] * cs + fB[u] * sn);
+              sx = fmaf(hf[u], pP, sx);
+              sy = fmaf(kf[u], pP, sy);
+              sz = fmaf(lf[u], pP, sz);
+              sb = fmaf(s2[u], pQ, sb);
+            }
+            v[4 * q + 0] = sx;
+            v[4 * q + 1] = sy;
+            v[4 * q + 2] = sz;
+            v[4 * q + 3] = sb;
+          }
+          const float tot = wave_reduce16(v, lane);
+          const int q = lane >> 2;
+          if (lane < 16 && j0 + q < re)
+            reinterpret_cast<double *>(out + (j0 + q - P.atom_begin))[lane & 3] = (double)tot;
+        }
+      } else {
+        double f[R], fA[R], fB[R];
+#pragma unroll
+        for (int u = 0; u < R; ++u) {
+          f[u] = fsc_f64(c9, s2d[u]);
+          fA[u] = gA[u] * f[u];
+          fB[u] = gB[u] * f[u];
+        }
+        for (int j = max(run.begin, wa); j < min(run.end, wb); ++j) {
+          const AtomRec a = atoms[j];
+          double sx = 0.0, sy = 0.0, sz = 0.0, sb = 0.0;
 #pragma unroll
           for (int u = 0; u < R; ++u) {
             const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
-            const float rho = (float)__builtin_amdgcn_fract(t);
-            const float sn = __builtin_amdgcn_sinf(rho);
-            const float cs = __builtin_amdgcn_cosf(rho);
-            const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
-            const float pP = w * (fB[u] * cs - fA[u] * sn);
-            const float pQ = w * (fA[u] * cs + fB[u] * sn);
-            sx = fmaf(hf[u], pP, sx);
-            sy = fmaf(kf[u], pP, sy);
-            sz = fmaf(lf[u], pP, sz);
-            sb = fmaf(s2[u], pQ, sb);
+            const double rho = t - rint(t);
+            double sn, cs;
+            sincospi(2.0 * rho, &sn, &cs);
+            const double w = a.occ * exp(-a.bfac * s2d[u]);
+            const double pP = w * (fB[u] * cs - fA[u] * sn);
+            const double pQ = w * (fA[u] * cs + fB[u] * sn);
+            sx = fma(h[u], pP, sx);
+            sy = fma(k[u], pP, sy);
+            sz = fma(l[u], pP, sz);
+            sb = fma(s2d[u], pQ, sb);
           }
-          v[4 * q + 0] = sx;
-          v[4 * q + 1] = sy;
-          v[4 * q + 2] = sz;
-          v[4 * q + 3] = sb;
+          sx = wave_sum_to_63(sx);
+          sy = wave_sum_to_63(sy);
+          sz = wave_sum_to_63(sz);
+          sb = wave_sum_to_63(sb);
+          if (lane == 63) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
         }
-        const float tot = wave_reduce16(v, lane);
-        const int q = lane >> 2;
-        if (lane < 16 && j0 + q < re)
-          reinterpret_cast<double *>(out + (j0 + q - P.atom_begin))[lane & 3] = (double)tot;
-      }
-    } else {
-      double f[R], fA[R], fB[R];
-#pragma unroll
-      for (int u = 0; u < R; ++u) {
-        f[u] = fsc_f64(c9, s2d[u]);
-        fA[u] = gA[u] * f[u];
-        fB[u] = gB[u] * f[u];
-      }
-      for (int j = max(run.begin, wa); j < min(run.end, wb); ++j) {
-        const AtomRec a = atoms[j];
-        double sx = 0.0, sy = 0.0, sz = 0.0, sb = 0.0;
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-          const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
-          const double rho = t - rint(t);
-          double sn, cs;
-          sincospi(2.0 * rho, &sn, &cs);
-          const double w = a.occ * exp(-a.bfac * s2d[u]);
-          const double pP = w * (fB[u] * cs - fA[u] * sn);
-          const double pQ = w * (fA[u] * cs + fB[u] * sn);
-          sx = fma(h[u], pP, sx);
-          sy = fma(k[u], pP, sy);
-          sz = fma(l[u], pP, sz);
-          sb = fma(s2d[u], pQ, sb);
-        }
-        sx = wave_sum_to_63(sx);
-        sy = wave_sum_to_63(sy);
-        sz = wave_sum_to_63(sz);
-        sb = wave_sum_to_63(sb);
-        if (lane == 63) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
       }
     }
+    return true;
+  };
+  for (int32_t tile = it.tile; tile_body(tile) && it.tail; ++tile) {
   }
 }
 
@@ -1062,14 +1075,6 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
       XRD_SF_BW(false, false);
   }
 #undef XRD_SF_BW
-}
-
-size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap) {
-  const size_t rs = mixed ? sizeof(float) : sizeof(double);
-  const size_t tiles = (size_t)tile * 3 * sizeof(double) + (size_t)tile * 3 * rs + (size_t)tile * runs_cap * rs +
-                       (size_t)runs_cap * 9 * rs;
-  const size_t red = (size_t)kThreads * sizeof(double4);  // slice reduction reuses the space
-  return tiles > red ? tiles : red;
 }
 
 void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,

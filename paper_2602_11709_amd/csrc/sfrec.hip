@@ -345,80 +345,86 @@ __global__ __launch_bounds__(kThreads) void k_sf_rec(
   const SfItem it = items[ww.item];
   const Entries en = entries_of(refl_offset, it.crystal, FRIEDEL);
   const int64_t sb = seg_index[en.base], se = seg_index[en.base + en.count];
-  const int64_t s0 = sb + (int64_t)it.tile * 64;
-  if (s0 >= se) return;  // uniform over a heavy block
-  const int lane = threadIdx.x & 63;
-  const int64_t s = s0 + lane;
-  const bool seg_ok = s < se;
-  const int64_t i0 = seg_ok ? seg_start[s] : en.first;
-  const int64_t i1 = seg_ok ? (s + 1 < se ? (int64_t)seg_start[s + 1] : en.first + en.count) : en.first + 1;
-  const int len = (int)(i1 - i0);  // 1 .. kRecLen
-  const CrystalPlan &P = plan[it.crystal];
-  const double h = hh[i0], k = kk[i0], l0 = ll[i0];
-  double s2d[R], lpv[R];
+  // a tail item walks the crystal's segment tiles from its first one on
+  auto tile_body = [&](int32_t tile) -> bool {
+    const int64_t s0 = sb + (int64_t)tile * 64;
+    if (s0 >= se) return false;  // uniform over a heavy block
+    const int lane = threadIdx.x & 63;
+    const int64_t s = s0 + lane;
+    const bool seg_ok = s < se;
+    const int64_t i0 = seg_ok ? seg_start[s] : en.first;
+    const int64_t i1 = seg_ok ? (s + 1 < se ? (int64_t)seg_start[s + 1] : en.first + en.count) : en.first + 1;
+    const int len = (int)(i1 - i0);  // 1 .. kRecLen
+    const CrystalPlan &P = plan[it.crystal];
+    const double h = hh[i0], k = kk[i0], l0 = ll[i0];
+    double s2d[R], lpv[R];
 #pragma unroll
-  for (int u = 0; u < R; ++u) {
-    const int64_t i = i0 + min(u, len - 1);
-    s2d[u] = 0.25 * qq[i];
-    lpv[u] = lpp[i];
-  }
-  // q(l0 + 1) - q(l0) from the metric (exact for the row, also past its end)
-  const double dq0 = P.gs[2] * (2.0 * l0 + 1.0) + 2.0 * (P.gs[4] * h + P.gs[5] * k);
-  const int na = it.atom_end - it.atom_begin;
-  const int qn = (na + ww.nparts - 1) / ww.nparts;
-  const int wa = it.atom_begin + min(na, ww.part * qn), wb = it.atom_begin + min(na, (ww.part + 1) * qn);
-  double acc[V][R];
-  rec_sums<MIXED, DERIV>(runs + it.run_begin, run_count[it.crystal], wa, wb, atoms, rot, coeff, coeff_f, h, k, l0,
-                         s2d, dq0, acc);
-  if (ww.heavy) {
-    auto at = [&](int v, int u) -> double & { return s_red[(v * R + u) * 64 + lane]; };
-    for (int w = ww.nparts - 1; w >= 1; --w) {
-      if (ww.part == w) {
-#pragma unroll
-        for (int v = 0; v < V; ++v)
-#pragma unroll
-          for (int u = 0; u < R; ++u) at(v, u) = w == ww.nparts - 1 ? acc[v][u] : at(v, u) + acc[v][u];
-      }
-      __syncthreads();
+    for (int u = 0; u < R; ++u) {
+      const int64_t i = i0 + min(u, len - 1);
+      s2d[u] = 0.25 * qq[i];
+      lpv[u] = lpp[i];
     }
-    if (ww.part != 0) return;
+    // q(l0 + 1) - q(l0) from the metric (exact for the row, also past its end)
+    const double dq0 = P.gs[2] * (2.0 * l0 + 1.0) + 2.0 * (P.gs[4] * h + P.gs[5] * k);
+    const int na = it.atom_end - it.atom_begin;
+    const int qn = (na + ww.nparts - 1) / ww.nparts;
+    const int wa = it.atom_begin + min(na, ww.part * qn), wb = it.atom_begin + min(na, (ww.part + 1) * qn);
+    double acc[V][R];
+    rec_sums<MIXED, DERIV>(runs + it.run_begin, run_count[it.crystal], wa, wb, atoms, rot, coeff, coeff_f, h, k, l0,
+                           s2d, dq0, acc);
+    if (ww.heavy) {
+      auto at = [&](int v, int u) -> double & { return s_red[(v * R + u) * 64 + lane]; };
+      for (int w = ww.nparts - 1; w >= 1; --w) {
+        if (ww.part == w) {
 #pragma unroll
-    for (int v = 0; v < V; ++v)
+          for (int v = 0; v < V; ++v)
 #pragma unroll
-      for (int u = 0; u < R; ++u) acc[v][u] = at(v, u) + acc[v][u];
-  }
-  if (!seg_ok) return;
-  const int64_t r0 = refl_offset[it.crystal], r1 = refl_offset[it.crystal + 1];
-#pragma unroll
-  for (int u = 0; u < R; ++u) {
-    if (u >= len) break;
-    const int64_t i = i0 + u;
-    const double A = acc[0][u], B = acc[1][u];
-    const double I = (A * A + B * B) * lpv[u];
-    Iout[i] = I;
-    if constexpr (DERIV) store_derivs<MIXED>(cache, i, A, B, acc[2][u], acc[3][u]);
-    const int64_t m = r0 + r1 - 1 - i;
-    if constexpr (MIXED) {
-      float *Af = (float *)Aout;
-      float *Bf = (float *)Bout;
-      Af[i] = (float)A;
-      Bf[i] = (float)B;
-      if (FRIEDEL) {
-        Af[m] = (float)A;
-        Bf[m] = -(float)B;
-        Iout[m] = I;
+            for (int u = 0; u < R; ++u) at(v, u) = w == ww.nparts - 1 ? acc[v][u] : at(v, u) + acc[v][u];
+        }
+        __syncthreads();
       }
-    } else {
-      double *Ad = (double *)Aout;
-      double *Bd = (double *)Bout;
-      Ad[i] = A;
-      Bd[i] = B;
-      if (FRIEDEL) {
-        Ad[m] = A;
-        Bd[m] = -B;
-        Iout[m] = I;
+      if (ww.part != 0) return false;
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+#pragma unroll
+        for (int u = 0; u < R; ++u) acc[v][u] = at(v, u) + acc[v][u];
+    }
+    if (!seg_ok) return true;
+    const int64_t r0 = refl_offset[it.crystal], r1 = refl_offset[it.crystal + 1];
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+      if (u >= len) break;
+      const int64_t i = i0 + u;
+      const double A = acc[0][u], B = acc[1][u];
+      const double I = (A * A + B * B) * lpv[u];
+      Iout[i] = I;
+      if constexpr (DERIV) store_derivs<MIXED>(cache, i, A, B, acc[2][u], acc[3][u]);
+      const int64_t m = r0 + r1 - 1 - i;
+      if constexpr (MIXED) {
+        float *Af = (float *)Aout;
+        float *Bf = (float *)Bout;
+        Af[i] = (float)A;
+        Bf[i] = (float)B;
+        if (FRIEDEL) {
+          Af[m] = (float)A;
+          Bf[m] = -(float)B;
+          Iout[m] = I;
+        }
+      } else {
+        double *Ad = (double *)Aout;
+        double *Bd = (double *)Bout;
+        Ad[i] = A;
+        Bd[i] = B;
+        if (FRIEDEL) {
+          Ad[m] = A;
+          Bd[m] = -B;
+          Iout[m] = I;
+        }
       }
     }
+    return true;
+  };
+  for (int32_t tile = it.tile; tile_body(tile) && it.tail; ++tile) {
   }
 }
 

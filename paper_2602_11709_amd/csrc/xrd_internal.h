@@ -21,6 +21,7 @@ constexpr int kHalfChunk = 2048;  // reflections per adjoint chunk
 constexpr int kEntBlock = 1024;   // entries per block of the broadening's entry preparation and adjoint
 constexpr int kScanBlock = 2048;  // elements per scan block (256 threads x 8)
 constexpr int kAtomBlock = 256;   // atoms per adjoint block
+constexpr int kSfThreads = 256;   // threads per block of the structure-factor kernels
 constexpr int kSfRpt = 2;         // reflections per lane in the structure-factor kernels
 constexpr int kSfTile = 64 * kSfRpt;
 constexpr int kFusedMaxAtoms = 512;  // crystals up to this size take the fused atom-gradient path
@@ -130,7 +131,8 @@ struct alignas(32) SfItem {
   int32_t tile;
   int32_t atom_begin, atom_end;  // packed atoms [atom_begin, atom_end)
   int32_t run_begin;             // first slot of the crystal's species-run table
-  int32_t pad[3];
+  int32_t tail;                  // 1: take tiles tile, tile + 1, ... up to the crystal's last one
+  int32_t pad[2];
 };
 static_assert(sizeof(SfItem) == 32, "SfItem layout");
 

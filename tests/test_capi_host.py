@@ -245,3 +245,24 @@ def test_sf_method_is_validated_and_sizes_the_workspace():
     with pytest.raises(capi.XrdError) as ei:
         capi.xrd_batch_create(make_desc(b, keep, sf_method=3))
     assert ei.value.code == capi.XRD_ERR_INVALID_ARG
+
+
+def test_set_lattice_validates_before_any_device_work():
+    """A cell needing a larger search box, or an invalid cell, is refused
+    before anything is copied (host only)."""
+    keep = []
+    b = synth.random_triclinic(24, 3, atoms_hi=10)
+    h = capi.xrd_batch_create(make_desc(b, keep))
+    try:
+        fake_ws = 0x100000  # 256-aligned, never touched on these paths
+        bigger = np.ascontiguousarray(b.lattice.copy())
+        bigger[1, 0] *= 1.5
+        assert capi.xrd_batch_set_lattice(h, bigger.ctypes.data, fake_ws) == capi.XRD_ERR_CAPACITY
+        assert "larger search box" in capi.xrd_last_error()
+        flat = np.ascontiguousarray(b.lattice.copy())
+        flat[0, 3:] = 120.0
+        with pytest.raises(capi.XrdError) as ei:
+            capi.xrd_batch_set_lattice(h, flat.ctypes.data, fake_ws)
+        assert ei.value.code == capi.XRD_ERR_INVALID_CELL
+    finally:
+        capi.xrd_batch_destroy(h)

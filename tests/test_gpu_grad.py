@@ -375,3 +375,66 @@ def test_directional_derivative_every_crystal_of_full_workload(differentiation_w
     assert total <= bar
     assert np.median(rel) <= bar
     assert np.all(ratio <= 1.0)
+
+
+def test_pattern_reuses_its_plan_across_refinement_steps():
+    """A refinement loop: the differentiable pattern keeps its planned batch
+    between calls (frac and B refreshed in place, small cell changes taken
+    by the same plan, a large one planned anew); every step's pattern and
+    gradients equal those of a batch planned from scratch for that step."""
+    from paper_2602_11709_amd import api
+    from paper_2602_11709_amd.api import Grid, XrdBatch, xrd_pattern
+    p = problem(3, 20, 60, grid_n=1001, seed=44)
+    b = p.batch
+    grid = Grid(p.grid_t0, p.grid_dt, p.grid_n, p.sigma, p.window_sigmas)
+    rng = np.random.default_rng(6)
+    frac0, lat0, bf0 = b.frac.copy(), b.lattice.copy(), b.bfac.copy()
+    for step in range(4):
+        frac_s = np.mod(frac0 + rng.normal(0, 0.003, frac0.shape), 1.0)
+        lat_s = lat0.copy()
+        lat_s[:, :3] *= 1.0 - 0.002 * step if step < 3 else 1.2  # the last step needs larger boxes
+        bf_s = np.maximum(bf0 + rng.normal(0, 0.02, bf0.shape), 0.0)
+        frac = torch.tensor(frac_s, device="cuda", requires_grad=True)
+        lat = torch.tensor(lat_s, requires_grad=True)
+        bf = torch.tensor(bf_s, device="cuda", requires_grad=True)
+        y = xrd_pattern(frac, lat, bf, b, grid, precision="mixed")
+        w = torch.linspace(-1, 1, y.numel(), dtype=torch.float64, device="cuda").reshape(y.shape)
+        (y * w).sum().backward()
+        # reference: a batch planned for this step alone
+        xb = XrdBatch(b, precision="mixed", frac=torch.tensor(frac_s, device="cuda"),
+                      bfac=torch.tensor(bf_s, device="cuda"), lattice=lat_s, grid_capacity=grid.n_points,
+                      keep_sf_derivs=True)
+        refl = xb.enumerate()
+        _, _, I = xb.structure_factors(refl)
+        y_ref = xb.pattern_forward(refl, I, grid)
+        g_ref = xb.pattern_backward(refl, grid, w.contiguous())
+        torch.cuda.synchronize()
+        assert torch.equal(y.detach(), y_ref), f"step {step}: pattern"
+        for got, ref in zip((frac.grad, bf.grad, lat.grad), g_ref):
+            np.testing.assert_array_equal(got.cpu().numpy(), ref.cpu().numpy()[: got.shape[0]])
+    key = [k for k in api._POOL if k[0] == id(b)]
+    assert key and 1 <= len(api._POOL[key[0]]) <= api._POOL_SLOTS
+
+
+def test_pattern_backward_after_reuse_is_refused():
+    """Two forwards before the first backward take two pooled batches; a
+    backward whose batch was reused by a later forward is refused instead of
+    returning another call's gradients."""
+    from paper_2602_11709_amd.api import Grid, xrd_pattern
+    p = problem(2, 10, 30, grid_n=801, seed=45)
+    b = p.batch
+    grid = Grid(p.grid_t0, p.grid_dt, p.grid_n, p.sigma, p.window_sigmas)
+    mk = lambda: (torch.tensor(b.frac, device="cuda", requires_grad=True), torch.tensor(b.lattice, requires_grad=True),
+                  torch.tensor(b.bfac, device="cuda", requires_grad=True))
+    a, c = mk(), mk()
+    ya = xrd_pattern(*a, b, grid)
+    yc = xrd_pattern(*c, b, grid)  # a second slot: the first is still awaiting its backward
+    ya.sum().backward()
+    yc.sum().backward()
+    np.testing.assert_array_equal(a[0].grad.cpu().numpy(), c[0].grad.cpu().numpy())
+    d = mk()
+    yd = xrd_pattern(*d, b, grid)
+    yd.sum().backward(retain_graph=True)
+    xrd_pattern(*mk(), b, grid).sum().backward()  # reuses d's batch
+    with pytest.raises(RuntimeError, match="reused"):
+        yd.sum().backward()
