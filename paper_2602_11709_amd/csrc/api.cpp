@@ -33,6 +33,7 @@ struct xrd_batch {
   std::vector<HChunk> peak_chunks;  // peak chunks of the merge (crystal, chunk)
   std::vector<HChunk> eblocks;  // entry blocks of the broadening (crystal, block of kEntBlock entries)
   std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
+  std::vector<int32_t> sort_items;     // the sort launch's two crystal lists (n_small + n_crystals)
   std::vector<int32_t> sf_order;   // crystals by descending atom count
   std::vector<int32_t> sf_likely;  // per crystal: tiles its expected reflection count fills
   std::vector<SfItem> sf_items, sf_items_bw;  // launch orders of the forward sum and the adjoint
@@ -47,9 +48,7 @@ struct xrd_batch {
   std::vector<AbItem> ab_items;
   std::vector<FamOps> fam_ops;  // lattice point operations per crystal
   int64_t n_atoms = 0, refl_cap = 0, half_cap = 0, n_bins = 0, run_cap = 0, part_rows = 0, partf_rows = 0;
-  int64_t n_mid = 0;      // crystals whose reflection capacity exceeds 2 kSmallSort
   int64_t n_small = 0;    // crystals whose reflection capacity exceeds 2 kTinySort
-  int64_t n_large = 0;    // crystals whose reflection capacity exceeds 2 kMidSort
   int64_t sf_heavy = 0, sf_heavy_bw = 0;  // leading items that take a block each
   int32_t split_fwd = kSplitFwd, split_bw = kSplitBw;
   int64_t grid_cap = 0;   // largest grid of a broadened-pattern call
@@ -488,9 +487,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     }
     P.half_box = (box - 1) / 2;
     refl += 2 * P.half_box;
-    if (P.half_box > kSmallSort) ++b->n_mid;  // more than 2 kSmallSort reflections possible
     if (P.half_box > kTinySort) ++b->n_small;
-    if (P.half_box > kMidSort) ++b->n_large;
     if (refl >= ((int64_t)1 << 31) - 1) {
       delete b;
       return fail(XRD_ERR_CAPACITY, "reflection capacity exceeds 2^31; split the batch");
@@ -600,6 +597,26 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   for (int64_t c = 0; c < nc; ++c) b->crystal_order[c] = (int32_t)c;
   std::stable_sort(b->crystal_order.begin(), b->crystal_order.end(),
                    [&](int32_t x, int32_t y) { return b->plan[x].half_box > b->plan[y].half_box; });
+  // sort launch lists, each expected-heaviest first: the crystals whose
+  // capacity exceeds 2 kTinySort reflections (a block each), then every
+  // crystal for the blocks that sort four small ones at a time, those
+  // expected at or below 2 kTinySort first (a group finds the others taken
+  // by their own block and idles; four such groups end their block at once)
+  {
+    const double fr = friedel ? 2.0 / 1.05 : 1.0 / 1.05;  // expected reflections per expect_eval
+    std::vector<int32_t> by_expect(nc);
+    for (int64_t c = 0; c < nc; ++c) by_expect[c] = (int32_t)c;
+    std::stable_sort(by_expect.begin(), by_expect.end(),
+                     [&](int32_t x, int32_t y) { return expect_eval[x] > expect_eval[y]; });
+    b->sort_items.clear();
+    b->sort_items.reserve(b->n_small + nc);
+    for (int32_t c : by_expect)
+      if (b->plan[c].half_box > kTinySort) b->sort_items.push_back(c);
+    for (int32_t c : by_expect)
+      if (fr * expect_eval[c] <= 2 * kTinySort) b->sort_items.push_back(c);
+    for (int32_t c : by_expect)
+      if (fr * expect_eval[c] > 2 * kTinySort) b->sort_items.push_back(c);
+  }
   // peak chunks: a crystal's peaks are about half its reflections (mates share 2theta)
   {
     std::vector<int32_t> split(nc);
@@ -713,6 +730,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.tmp_i = take(8 * rc);
   L.tmp_mult = take(4 * rc);
   L.tmp_first = take(8 * rc);
+  L.sort_items = take(4 * (b->n_small + nc));
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(ec, bins), rc);
   L.scan_part = take(8 * scan_part_elems(scan_n));
   L.bw_w1 = L.bw_w2 = L.bw_ga = L.bw_gb = L.bw_dq = L.bw_part = L.bw_partf = L.bw_part6 = -1;
@@ -765,6 +783,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     M.tmp_i = take(8 * rc);
     M.tmp_mult = take(4 * rc);
     M.tmp_first = take(8 * rc);
+    M.sort_items = take(4 * (b->n_small + nc));
     M.total = o;
   }
   *out = b;
@@ -847,6 +866,7 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   if (e == hipSuccess) e = up(L.peak_chunks, b->peak_chunks.data(), sizeof(HChunk) * b->peak_chunks.size());
   if (e == hipSuccess) e = up(L.eblocks, b->eblocks.data(), sizeof(HChunk) * b->eblocks.size());
   if (e == hipSuccess) e = up(L.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
+  if (e == hipSuccess) e = up(L.sort_items, b->sort_items.data(), 4 * b->sort_items.size());
   if (e == hipSuccess) e = up(L.bw_items, b->bw_items.data(), sizeof(BwItem) * b->bw_items.size());
   if (e == hipSuccess) e = up(L.ab_items, b->ab_items.data(), sizeof(AbItem) * b->ab_items.size());
   if (e == hipSuccess) e = up(L.fam_ops, b->fam_ops.data(), sizeof(FamOps) * b->fam_ops.size());
@@ -1009,7 +1029,7 @@ static Fork side_of(xrd_batch *b) {
 
 static void ensure_sorted(xrd_batch *b, void *ws, const xrd_refl *r) {
   if (b->sorted_ws == ws && b->sorted_tt == r->two_theta) return;
-  launch_sort(sort_args(b, ws, b->ws, r), side_of(b), stream_of(b));
+  launch_sort(sort_args(b, ws, b->ws, r), stream_of(b));
   b->sorted_ws = ws;
   b->sorted_tt = r->two_theta;
 }
@@ -1029,9 +1049,8 @@ static SortArgs sort_args(xrd_batch *b, void *ws, const WsLayout &L, const xrd_r
   a.skey = at<double>(ws, L.skey);
   a.sidx = at<int32_t>(ws, L.sidx);
   a.order = at<int32_t>(ws, L.crystal_order);
-  a.n_mid = b->n_mid;
   a.n_small = b->n_small;
-  a.n_large = b->n_large;
+  a.items = at<int32_t>(ws, L.sort_items);
   a.friedel = b->desc.friedel != 0 ? 1 : 0;
   a.ent_key = at<double>(ws, L.ent_key);
   a.ent_idx = at<int32_t>(ws, L.ent_idx);
@@ -1080,7 +1099,7 @@ int xrd_merge_peaks(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, 
   if (int e = check_ws(b, ws)) return e;
   if (int e = check_merge_args(r, I, p)) return e;
   // the merge sorts as it goes, and leaves the sorted order behind
-  launch_merge(merge_args(b, ws, b->ws, r, I, p), side_of(b), stream_of(b));
+  launch_merge(merge_args(b, ws, b->ws, r, I, p), stream_of(b));
   b->sorted_ws = ws;
   b->sorted_tt = r->two_theta;
   b->last_ws = ws;
@@ -1107,9 +1126,9 @@ int xrd_merge_peaks_noalloc(xrd_batch *b, const xrd_refl *r, const double *I, xr
   e = up(M.plan, b->plan.data(), sizeof(CrystalPlan) * b->plan.size());
   if (e == hipSuccess) e = up(M.peak_chunks, b->peak_chunks.data(), sizeof(HChunk) * b->peak_chunks.size());
   if (e == hipSuccess) e = up(M.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
+  if (e == hipSuccess) e = up(M.sort_items, b->sort_items.data(), 4 * b->sort_items.size());
   if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("scratch tables: ") + hipGetErrorString(e));
-  const Fork none{nullptr, nullptr, nullptr, nullptr, nullptr};
-  launch_merge(merge_args(b, sp, M, r, I, p), none, s);
+  launch_merge(merge_args(b, sp, M, r, I, p), s);
   // the sorted order went to the scratch, which later calls may overwrite
   b->sorted_ws = nullptr;
   b->sorted_tt = nullptr;

@@ -2,14 +2,12 @@
 // peaks (paper, Section 2: merging of reflections within specified angular
 // tolerances; grouping of reflections into peaks), fused per crystal.
 //
-// Sort: one block per crystal, in LDS up to 12288 reflections and through
-// global memory beyond.  A bucket sort with exactly monotone buckets: the
-// bucket of a reflection is floor((2theta - tmin) * buckets_per_degree),
-// clamped; a subtraction, a product with a positive constant and floor are
-// each monotone in IEEE arithmetic, so bucket order never contradicts key
-// order and equal keys share a bucket.  Count (atomics), scan, scatter
-// (atomics), then a per-bucket insertion sort on the full key (2theta,
-// h, k, l), which removes the scatter's order dependence.
+// Sort: a classification pass splits the crystals by their reflection
+// count; one launch then sorts each crystal of more than 2048 reflections with
+// a 1024-thread block (in LDS up to 16384 reflections, through global memory
+// beyond) and the smaller ones four to a block.  In LDS, a bucket sort with
+// exactly monotone buckets, then each element's rank within its bucket on the
+// full key (2theta, h, k, l), which removes the scatter's order dependence.
 //
 // Merge (anchor rule): walking the sorted order, a reflection joins the open
 // peak while 2theta - 2theta(peak's first member) < tol.  A gap >= tol between
@@ -31,11 +29,6 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kPer = kSortChunk / kThreads;  // 4
-constexpr int kSmallThreads = 1024;          // threads of a block sorting up to 2 kSmallSort reflections
-constexpr int kMidThreads = 1024;            // ... up to 2 kMidSort reflections
-constexpr int kLargeBlocks = 256;            // blocks of the global-memory sort (crystals beyond 2 kMidSort)
-constexpr int kLargeThreads = 512;           // threads of a global-memory sort block
-constexpr int kGlobalCap = kLargeThreads;    // that kernel's LDS path is never taken (every crystal is larger)
 
 __device__ __forceinline__ int bin_of(const CrystalPlan &P, double tt) {
 #pragma clang fp contract(off)
@@ -62,11 +55,13 @@ __device__ __forceinline__ void block_barrier() {
     __syncthreads();
 }
 
-// Exclusive block-wide scan of one int per thread (T threads); ``wsum`` holds
-// T/64 ints of LDS.  Every thread of the block must call it.
+// Exclusive scan of one int per thread over a group of T threads (``gt``:
+// the thread's index in the group; ``wsum``: the group's T/64 ints of LDS).
+// Its barriers are block-wide: every thread of the block calls it, as many
+// times as the others.
 template <int T, bool LDS_ONLY = false>
-__device__ __forceinline__ int block_exclusive_scan(int v, int32_t *wsum, int *total) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+__device__ __forceinline__ int group_exclusive_scan(int v, int gt, int32_t *wsum, int *total) {
+  const int lane = gt & 63, wid = gt >> 6;
   int inc = v;
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
@@ -86,18 +81,24 @@ __device__ __forceinline__ int block_exclusive_scan(int v, int32_t *wsum, int *t
   return ex;
 }
 
-// Block-wide maximum of nonnegative doubles (their bit patterns order like
-// the values).  Every thread of the block must call it.
+// The same over the whole block (T threads).
+template <int T, bool LDS_ONLY = false>
+__device__ __forceinline__ int block_exclusive_scan(int v, int32_t *wsum, int *total) {
+  return group_exclusive_scan<T, LDS_ONLY>(v, (int)threadIdx.x, wsum, total);
+}
+
+// Maximum of nonnegative doubles over a group (their bit patterns order like
+// the values); block-wide barriers as above.
 template <bool LDS_ONLY = false>
-__device__ __forceinline__ double block_max_nonneg(double v, unsigned long long *slot) {
+__device__ __forceinline__ double group_max_nonneg(double v, int gt, unsigned long long *slot) {
   // the wavefront's maximum first, so that one LDS atomic per wavefront
   // (not per thread) meets the shared slot
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) v = fmax(v, __shfl_xor(v, d, 64));
   block_barrier<LDS_ONLY>();
-  if (threadIdx.x == 0) *slot = 0ull;
+  if (gt == 0) *slot = 0ull;
   block_barrier<LDS_ONLY>();
-  if ((threadIdx.x & 63) == 0) atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+  if ((gt & 63) == 0) atomicMax(slot, (unsigned long long)__double_as_longlong(v));
   block_barrier<LDS_ONLY>();
   return __longlong_as_double((long long)*slot);
 }
@@ -115,19 +116,22 @@ struct MergeOut {
   int64_t *perm;        // [refl_cap] global reflection index in sorted order
 };
 
-// Applies the relative threshold to peaks [0, np) of a crystal staged at r0,
-// compacting them in place (chunk by chunk: a chunk is read completely before
-// any of it is written, and writes go to positions below the chunk's start or
-// to its own slots), and records the count and maximum.
+// Applies the relative threshold to peaks [0, np) of a crystal staged at r0
+// (c < 0: the group has no crystal), compacting them in place (chunk by
+// chunk: a chunk is read completely before any of it is written, and writes
+// go to positions below the chunk's start or to its own slots), and records
+// the count and maximum.  ``iters`` chunks of T are walked (>= np / T, the
+// same for every group of the block, so that the barriers match).
 template <int T>
-__device__ void finish_crystal(const MergeOut &mo, int64_t c, int64_t r0, int np, double mx, int32_t *wsum) {
+__device__ void finish_crystal(const MergeOut &mo, int64_t c, int64_t r0, int np, double mx, int gt, int iters,
+                               int32_t *wsum) {
   int kept = np;
   if (mo.thr > 0.0) {
     __syncthreads();  // the staged peaks of every thread are written
     const double cut = mo.thr * mx;
     kept = 0;
-    for (int p0 = 0; p0 < np; p0 += T) {
-      const int p = p0 + (int)threadIdx.x;
+    for (int it = 0; it < iters; ++it) {
+      const int p = it * T + gt;
       const bool live = p < np;
       double tt = 0.0, iv = 0.0;
       int32_t m = 0;
@@ -140,7 +144,7 @@ __device__ void finish_crystal(const MergeOut &mo, int64_t c, int64_t r0, int np
       }
       const bool keep = live && iv >= cut;
       int total;
-      const int ex = block_exclusive_scan<T>(keep ? 1 : 0, wsum, &total);  // its barriers order reads before writes
+      const int ex = group_exclusive_scan<T>(keep ? 1 : 0, gt, wsum, &total);  // its barriers order reads before writes
       if (keep) {
         mo.t_tt[r0 + kept + ex] = tt;
         mo.t_i[r0 + kept + ex] = iv;
@@ -151,293 +155,317 @@ __device__ void finish_crystal(const MergeOut &mo, int64_t c, int64_t r0, int np
       __syncthreads();
     }
   }
-  if (threadIdx.x == 0) {
+  if (gt == 0 && c >= 0) {
     mo.pk_count[c] = kept;
     mo.cmax[c] = (uint64_t)__double_as_longlong(mx);
   }
 }
 
-// Sort (and merge) of one crystal per block.  Crystals of at most 2 CAP
-// reflections are sorted in LDS by their Friedel-positive half (the mates
-// follow from it exactly): H/2 exactly monotone buckets, count with LDS
-// atomics, scan, scatter with LDS atomics, then each element's rank within
-// its bucket on (2theta bits, index).  The input is in lexicographic (h, k, l)
-// order, so ordering ties by index orders them by (h, k, l); positive
-// doubles order like their bit patterns.  Two sizes are launched: CAP 4096
-// (256 threads, one block per crystal, ~48 KB of LDS) and CAP 12288 (512
-// threads, 144 KB of LDS, which gfx950 provides per workgroup; at most one
-// block per CU walking the crystals whose capacity exceeds 8192), which also
-// sorts the crystals beyond 24576 reflections, all R of them, with the
-// capacity-sized buckets of the plan kept in global memory and an insertion
-// sort within buckets.  Crystals are taken in ``order``, heaviest first; the
-// first n_c of them are the kernel's.
+// Global-memory sort and merge of one crystal by the whole block (T
+// threads): the capacity-sized buckets of the plan, counted, scanned and
+// filled with global atomics, then an insertion sort within buckets on
+// (2theta, global index).  For crystals beyond the LDS sizes.
+template <int T>
+__device__ void sort_global(int64_t c, const CrystalPlan *__restrict__ plan, const int64_t *__restrict__ refl_offset,
+                            const double *__restrict__ tt, double *__restrict__ skey, int32_t *__restrict__ sidx,
+                            double *__restrict__ ent_key, int32_t *__restrict__ ent_idx, int32_t *__restrict__ bin_count,
+                            int64_t *__restrict__ bin_start, const MergeOut &mo, int32_t *wsum,
+                            unsigned long long *smax) {
+  const bool merge = mo.inten != nullptr;
+  const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
+  const int64_t R64 = r1 - r0;
+  const int64_t e_base = r0 / 2;
+  const CrystalPlan &P = plan[c];
+  int total;
+  const int64_t nb = P.n_bins;
+  int32_t *__restrict__ bc = bin_count + P.bin_begin;
+  int64_t *__restrict__ bs = bin_start + P.bin_begin;
+  for (int64_t b = threadIdx.x; b < nb; b += T) bc[b] = 0;
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < R64; i += T) atomicAdd(&bc[bin_of(P, tt[r0 + i])], 1);
+  __syncthreads();
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += T) {
+    const int64_t b = b0 + threadIdx.x;
+    const int v = b < nb ? bc[b] : 0;
+    const int ex = block_exclusive_scan<T>(v, wsum, &total);
+    if (b < nb) bs[b] = carry + ex;
+    carry += total;
+  }
+  __syncthreads();
+  for (int64_t i = threadIdx.x; i < R64; i += T) {
+    const double t = tt[r0 + i];
+    const int b = bin_of(P, t);
+    const int64_t slot = r0 + bs[b] + atomicSub(&bc[b], 1) - 1;
+    skey[slot] = t;
+    sidx[slot] = (int32_t)(r0 + i);
+  }
+  __syncthreads();
+  // ties by global index, which is lexicographic (h, k, l) order
+  for (int64_t b = threadIdx.x; b < nb; b += T) {
+    const int64_t s0 = r0 + bs[b], e0 = b + 1 < nb ? r0 + bs[b + 1] : r1;
+    for (int64_t x = s0 + 1; x < e0; ++x) {
+      const double kx = skey[x];
+      const int32_t ix = sidx[x];
+      int64_t j = x - 1;
+      while (j >= s0) {
+        const double kj = skey[j];
+        const int32_t ij = sidx[j];
+        if (!(kj > kx || (kj == kx && ij > ix))) break;
+        skey[j + 1] = kj;
+        sidx[j + 1] = ij;
+        --j;
+      }
+      skey[j + 1] = kx;
+      sidx[j + 1] = ix;
+    }
+  }
+  __syncthreads();
+  if (ent_key) {
+    const int64_t mid = r0 + R64 / 2;
+    int64_t done = 0;
+    for (int64_t j0 = 0; j0 < R64; j0 += T) {
+      const int64_t j = j0 + threadIdx.x;
+      const bool f = j < R64 && sidx[r0 + j] >= mid;
+      const int ex = block_exclusive_scan<T>(f ? 1 : 0, wsum, &total);
+      if (f) {
+        ent_key[e_base + done + ex] = skey[r0 + j];
+        ent_idx[e_base + done + ex] = sidx[r0 + j];
+      }
+      done += total;
+    }
+  }
+  if (merge) {
+#pragma clang fp contract(off)
+    // peak-start flags: one walker per component
+    for (int64_t i = threadIdx.x; i < R64; i += T) {
+      mo.perm[r0 + i] = sidx[r0 + i];
+      const double ti = skey[r0 + i];
+      if (i == 0 || ti - skey[r0 + i - 1] >= mo.tol) {
+        mo.flags[r0 + i] = 1;
+        double anchor = ti, prev = ti;
+        for (int64_t j = i + 1; j < R64; ++j) {
+          const double tj = skey[r0 + j];
+          if (tj - prev >= mo.tol) break;
+          const bool open = (tj - anchor) >= mo.tol;
+          mo.flags[r0 + j] = open ? 1 : 0;
+          if (open) anchor = tj;
+          prev = tj;
+        }
+      }
+    }
+    __syncthreads();
+    int64_t done = 0;
+    double mx = 0.0;
+    for (int64_t j0 = 0; j0 < R64; j0 += T) {
+      const int64_t j = j0 + threadIdx.x;
+      const bool f = j < R64 && mo.flags[r0 + j];
+      const int ex = block_exclusive_scan<T>(f ? 1 : 0, wsum, &total);
+      if (f) {
+        const int64_t p = done + ex;
+        double s = mo.inten[sidx[r0 + j]];
+        int m = 1;
+        for (int64_t x = j + 1; x < R64 && !mo.flags[r0 + x]; ++x) {
+          s += mo.inten[sidx[r0 + x]];
+          ++m;
+        }
+        mo.t_tt[r0 + p] = skey[r0 + j];
+        mo.t_i[r0 + p] = s;
+        mo.t_mult[r0 + p] = m;
+        mo.t_first[r0 + p] = r0 + j;
+        mx = fmax(mx, s);
+      }
+      done += total;
+    }
+    mx = group_max_nonneg(mx, (int)threadIdx.x, smax);
+    finish_crystal<T>(mo, c, r0, (int)done, mx, (int)threadIdx.x, (int)((done + T - 1) / T), wsum);
+  }
+}
+
+// LDS sort and merge of one crystal of at most 2 CAP reflections by a group
+// of T threads (``gt``: index in the group; c < 0: no crystal, the group only
+// keeps step with the block's barriers).  The group's LDS: key[CAP],
+// pos[CAP], cnt[CAP / 2], wsum[T / 64], one max slot.
+//
+// The crystal's Friedel-positive half is sorted (the mates follow from it
+// exactly).  Buckets: H/2 of them, exactly monotone in 2theta (a product of
+// nonnegative numbers, a subtraction, a product with a positive constant and
+// floor each preserve order in IEEE arithmetic, so bucket order never
+// contradicts key order and equal keys share a bucket); the cube of 2theta
+// spreads the reflections evenly, their number growing about as the cube of
+// the radius in reciprocal space.  Count with LDS atomics, scan, scatter with
+// LDS atomics, then each element's rank within its bucket on (2theta bits,
+// index).  The input is in lexicographic (h, k, l) order, so ordering ties by
+// index orders them by (h, k, l); positive doubles order like their bit
+// patterns.  The pair intensities (an entry and its mate) are loaded in input
+// order, coalesced, and moved to their sorted slots in LDS (over the keys,
+// once those are consumed), so the merge sums them without a gather; the
+// peak starts are listed in LDS and one thread per peak sums and writes it.
 //
 // Outputs: without Friedel pairing, skey/sidx, the crystal's 2theta keys and
 // global reflection indices in sorted order (the entries of the broadening);
 // with it (ent_key non-null), the entries of the evaluated half (local index
 // >= R/2) in sorted order, at entry positions starting at r0/2 (refl_offset
-// values are even), and skey/sidx only as the global-memory path's working
-// storage; with a merge, perm and the crystal's staged peaks (MergeOut).
-template <int CAP, int T, bool LARGE, int LO>
-__global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *__restrict__ order,
-                                                    const CrystalPlan *__restrict__ plan,
-                                                    const int64_t *__restrict__ refl_offset,
-                                                    const double *__restrict__ tt, double *__restrict__ skey,
-                                                    int32_t *__restrict__ sidx, double *__restrict__ ent_key,
-                                                    int32_t *__restrict__ ent_idx, int32_t *__restrict__ bin_count,
-                                                    int64_t *__restrict__ bin_start, MergeOut mo) {
-  __shared__ uint64_t key[CAP];
-  __shared__ uint16_t pos[CAP];
-  __shared__ int32_t cnt[CAP / 2];  // bucket offsets, then the merge's peak-start flags (one byte each)
-  __shared__ int32_t wsum[T / 64];
-  __shared__ unsigned long long smax;
-  uint8_t *const fl = reinterpret_cast<uint8_t *>(cnt);
+// values are even); with a merge, perm and the crystal's staged peaks.
+template <int CAP, int T>
+__device__ void sort_lds(int64_t c, int gt, uint64_t *key, uint16_t *pos, int32_t *cnt, int32_t *wsum,
+                         unsigned long long *smax, const CrystalPlan *__restrict__ plan,
+                         const int64_t *__restrict__ refl_offset, const double *__restrict__ tt,
+                         double *__restrict__ skey, int32_t *__restrict__ sidx, double *__restrict__ ent_key,
+                         int32_t *__restrict__ ent_idx, const MergeOut &mo) {
+  constexpr int PER = CAP / T;
   const bool merge = mo.inten != nullptr;
-  const int64_t c_step = LARGE ? gridDim.x : n_c;
-  for (int64_t ci = blockIdx.x; ci < n_c; ci += c_step) {
-    const int64_t c = order[ci];
-    const int64_t r0 = refl_offset[c], r1 = refl_offset[c + 1];
-    const int64_t R64 = r1 - r0;
-    if (LO == 0 && R64 == 0 && merge && threadIdx.x == 0) {
-      mo.pk_count[c] = 0;
-      mo.cmax[c] = 0;
+  uint8_t *const fl = reinterpret_cast<uint8_t *>(cnt);
+  double *const ival = reinterpret_cast<double *>(key);
+  int64_t r0 = 0;
+  int H = 0;
+  double tmin = 0.0, tmax = 1.0;
+  if (c >= 0) {
+    r0 = refl_offset[c];
+    H = (int)((refl_offset[c + 1] - r0) / 2);
+    tmin = plan[c].tmin;
+    tmax = plan[c].tmax;
+  }
+  const int64_t e_base = r0 / 2;
+  int total;
+  // Positives (local index H + i, i < H) and their mates (local H - 1 - i)
+  // share 2theta bit for bit.  Sort the H positives by (2theta, i); a run of
+  // equal keys [a, b] then expands, in (2theta, h, k, l) order, to the mates
+  // of b, b-1, .., a (their local indices ascend that way) followed by the
+  // positives a, .., b: full slots 2a + (b - j) and b + 1 + j for entry j.
+  const int B = H / 2 > 1 ? H / 2 : 1;
+  double lo, scale;
+  {
+#pragma clang fp contract(off)
+    lo = tmin * tmin * tmin;
+    const double span = tmax * tmax * tmax - lo;
+    scale = span > 0.0 ? (double)B / span : 0.0;  // one bucket if the range's cubes coincide
+  }
+  auto bucket = [&](double t) {
+#pragma clang fp contract(off)
+    const double x = floor((t * t * t - lo) * scale);
+    return x < 0.0 ? 0 : (x >= (double)(B - 1) ? B - 1 : (int)x);
+  };
+  for (int b = gt; b < B; b += T) cnt[b] = 0;
+  // every thread's keys are loaded at once and kept in registers
+  double tv[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = u * T + gt;
+    tv[u] = i < H ? tt[r0 + H + i] : tmin;
+  }
+  lds_barrier();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = u * T + gt;
+    if (i < H) atomicAdd(&cnt[bucket(tv[u])], 1);
+  }
+  lds_barrier();
+  // exclusive scan of the bucket counts: each thread owns a contiguous run
+  {
+    constexpr int per = (CAP / 2 + T - 1) / T;
+    const int b0 = gt * per;
+    int v[per], sum = 0;
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+      v[u] = b0 + u < B ? cnt[b0 + u] : 0;
+      sum += v[u];
     }
-    if (R64 <= LO || (!LARGE && R64 > 2 * CAP)) continue;  // another size's crystal
-    const int64_t e_base = r0 / 2;
-    const CrystalPlan &P = plan[c];
-    int total;
-    if (LARGE && R64 > 2 * CAP) {
-      // ---- global-memory path for the largest crystals ----
-      const int64_t nb = P.n_bins;
-      int32_t *__restrict__ bc = bin_count + P.bin_begin;
-      int64_t *__restrict__ bs = bin_start + P.bin_begin;
-      for (int64_t b = threadIdx.x; b < nb; b += T) bc[b] = 0;
-      __syncthreads();
-      for (int64_t i = threadIdx.x; i < R64; i += T) atomicAdd(&bc[bin_of(P, tt[r0 + i])], 1);
-      __syncthreads();
-      int64_t carry = 0;
-      for (int64_t b0 = 0; b0 < nb; b0 += T) {
-        const int64_t b = b0 + threadIdx.x;
-        const int v = b < nb ? bc[b] : 0;
-        const int ex = block_exclusive_scan<T>(v, wsum, &total);
-        if (b < nb) bs[b] = carry + ex;
-        carry += total;
+    int ex = group_exclusive_scan<T, true>(sum, gt, wsum, &total);
+#pragma unroll
+    for (int u = 0; u < per; ++u) {
+      if (b0 + u < B) cnt[b0 + u] = ex;
+      ex += v[u];
+    }
+  }
+  lds_barrier();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = u * T + gt;
+    if (i < H) {
+      const int slot = atomicAdd(&cnt[bucket(tv[u])], 1);
+      key[slot] = (uint64_t)__double_as_longlong(tv[u]);
+      pos[slot] = (uint16_t)i;
+    }
+  }
+  lds_barrier();
+  // cnt[b] is now the end of bucket b, and its start is the end of bucket b - 1.
+  // Order within buckets: every element counts the members of its bucket
+  // that precede it in (2theta bits, index), all elements at once; then
+  // each moves to its rank (all reads happen before the barrier, and the
+  // ranks of a bucket are a permutation of its slots).
+  int rk[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = u * T + gt;
+    rk[u] = 0;
+    if (i < H) {
+      const uint64_t k = (uint64_t)__double_as_longlong(tv[u]);
+      const int b = bucket(tv[u]);
+      int r = b ? cnt[b - 1] : 0;
+      for (int j = r, e0 = cnt[b]; j < e0; ++j) {
+        const uint64_t kj = key[j];
+        r += (kj < k || (kj == k && (int)pos[j] < i)) ? 1 : 0;
       }
-      __syncthreads();
-      for (int64_t i = threadIdx.x; i < R64; i += T) {
-        const double t = tt[r0 + i];
-        const int b = bin_of(P, t);
-        const int64_t slot = r0 + bs[b] + atomicSub(&bc[b], 1) - 1;
-        skey[slot] = t;
-        sidx[slot] = (int32_t)(r0 + i);
-      }
-      __syncthreads();
-      // ties by global index, which is lexicographic (h, k, l) order
-      for (int64_t b = threadIdx.x; b < nb; b += T) {
-        const int64_t s0 = r0 + bs[b], e0 = b + 1 < nb ? r0 + bs[b + 1] : r1;
-        for (int64_t x = s0 + 1; x < e0; ++x) {
-          const double kx = skey[x];
-          const int32_t ix = sidx[x];
-          int64_t j = x - 1;
-          while (j >= s0) {
-            const double kj = skey[j];
-            const int32_t ij = sidx[j];
-            if (!(kj > kx || (kj == kx && ij > ix))) break;
-            skey[j + 1] = kj;
-            sidx[j + 1] = ij;
-            --j;
-          }
-          skey[j + 1] = kx;
-          sidx[j + 1] = ix;
-        }
-      }
-      __syncthreads();
-      if (ent_key) {
-        const int64_t mid = r0 + R64 / 2;
-        int64_t done = 0;
-        for (int64_t j0 = 0; j0 < R64; j0 += T) {
-          const int64_t j = j0 + threadIdx.x;
-          const bool f = j < R64 && sidx[r0 + j] >= mid;
-          const int ex = block_exclusive_scan<T>(f ? 1 : 0, wsum, &total);
-          if (f) {
-            ent_key[e_base + done + ex] = skey[r0 + j];
-            ent_idx[e_base + done + ex] = sidx[r0 + j];
-          }
-          done += total;
-        }
+      rk[u] = r;
+    }
+  }
+  lds_barrier();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int i = u * T + gt;
+    if (i < H) {
+      key[rk[u]] = (uint64_t)__double_as_longlong(tv[u]);
+      pos[rk[u]] = (uint16_t)i;
+    }
+  }
+  lds_barrier();
+  // the pair intensities (an entry and its mate) in input order, coalesced;
+  // they land while the entries are written
+  double iv[PER];
+  if (merge) {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = u * T + gt;
+      iv[u] = i < H ? mo.inten[r0 + H - 1 - i] + mo.inten[r0 + H + i] : 0.0;
+    }
+  }
+  // entries (the evaluated half in 2theta order) and the expanded full order
+  for (int j = gt; j < H; j += T) {
+    const uint64_t kj = key[j];
+    const double tj = __longlong_as_double((long long)kj);
+    const int p = pos[j];
+    if (ent_key) {
+      ent_key[e_base + j] = tj;
+      ent_idx[e_base + j] = (int32_t)(r0 + H + p);
+    }
+    // the full order: as the merge's perm, and as the entries themselves
+    // without Friedel pairing (skey/sidx are the entries then)
+    if (!ent_key || merge) {
+      int ga = j, gb = j;
+      while (ga > 0 && key[ga - 1] == kj) --ga;
+      while (gb + 1 < H && key[gb + 1] == kj) ++gb;
+      const int fm = 2 * ga + (gb - j), fp = gb + 1 + j;
+      const int64_t im = r0 + H - 1 - p, ip = r0 + H + p;
+      if (!ent_key) {
+        skey[r0 + fm] = tj;
+        sidx[r0 + fm] = (int32_t)im;
+        skey[r0 + fp] = tj;
+        sidx[r0 + fp] = (int32_t)ip;
       }
       if (merge) {
-#pragma clang fp contract(off)
-        // peak-start flags: one walker per component
-        for (int64_t i = threadIdx.x; i < R64; i += T) {
-          mo.perm[r0 + i] = sidx[r0 + i];
-          const double ti = skey[r0 + i];
-          if (i == 0 || ti - skey[r0 + i - 1] >= mo.tol) {
-            mo.flags[r0 + i] = 1;
-            double anchor = ti, prev = ti;
-            for (int64_t j = i + 1; j < R64; ++j) {
-              const double tj = skey[r0 + j];
-              if (tj - prev >= mo.tol) break;
-              const bool open = (tj - anchor) >= mo.tol;
-              mo.flags[r0 + j] = open ? 1 : 0;
-              if (open) anchor = tj;
-              prev = tj;
-            }
-          }
-        }
-        __syncthreads();
-        int64_t done = 0;
-        double mx = 0.0;
-        for (int64_t j0 = 0; j0 < R64; j0 += T) {
-          const int64_t j = j0 + threadIdx.x;
-          const bool f = j < R64 && mo.flags[r0 + j];
-          const int ex = block_exclusive_scan<T>(f ? 1 : 0, wsum, &total);
-          if (f) {
-            const int64_t p = done + ex;
-            double s = mo.inten[sidx[r0 + j]];
-            int m = 1;
-            for (int64_t x = j + 1; x < R64 && !mo.flags[r0 + x]; ++x) {
-              s += mo.inten[sidx[r0 + x]];
-              ++m;
-            }
-            mo.t_tt[r0 + p] = skey[r0 + j];
-            mo.t_i[r0 + p] = s;
-            mo.t_mult[r0 + p] = m;
-            mo.t_first[r0 + p] = r0 + j;
-            mx = fmax(mx, s);
-          }
-          done += total;
-        }
-        mx = block_max_nonneg(mx, &smax);
-        finish_crystal<T>(mo, c, r0, (int)done, mx, wsum);
+        mo.perm[r0 + fm] = im;
+        mo.perm[r0 + fp] = ip;
       }
-      __syncthreads();
-      continue;
     }
-    // ---- LDS path: sort the evaluated half, expand to the full order ----
-    // Positives (local index H + i, i < H) and their mates (local H - 1 - i)
-    // share 2theta bit for bit.  Sort the H positives by (2theta, i); a run of
-    // equal keys [a, b] then expands, in (2theta, h, k, l) order, to the mates
-    // of b, b-1, .., a (their local indices ascend that way) followed by the
-    // positives a, .., b: full slots 2a + (b - j) and b + 1 + j for entry j.
-    const int R = (int)R64;
-    const int H = R / 2;
-    const int B = H / 2 > 1 ? H / 2 : 1;
-    const double scale = (double)B / (P.tmax - P.tmin);
-    constexpr int PER = CAP / T;
-    for (int b = threadIdx.x; b < B; b += T) cnt[b] = 0;
-    // every thread's keys are loaded at once and kept in registers
-    double tv[PER];
-    int bv[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = u * T + threadIdx.x;
-      tv[u] = i < H ? tt[r0 + H + i] : P.tmin;
-    }
-    lds_barrier();
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-#pragma clang fp contract(off)
-      const int i = u * T + threadIdx.x;
-      const double x = floor((tv[u] - P.tmin) * scale);
-      bv[u] = x < 0.0 ? 0 : (x >= (double)(B - 1) ? B - 1 : (int)x);
-      if (i < H) atomicAdd(&cnt[bv[u]], 1);
-    }
-    lds_barrier();
-    // exclusive scan of the bucket counts: each thread owns a contiguous run
+  }
+  if (merge) {
     {
-      constexpr int per = (CAP / 2 + T - 1) / T;
-      const int b0 = threadIdx.x * per;
-      int v[per], sum = 0;
-#pragma unroll
-      for (int u = 0; u < per; ++u) {
-        v[u] = b0 + u < B ? cnt[b0 + u] : 0;
-        sum += v[u];
-      }
-      int ex = block_exclusive_scan<T, true>(sum, wsum, &total);
-#pragma unroll
-      for (int u = 0; u < per; ++u) {
-        if (b0 + u < B) cnt[b0 + u] = ex;
-        ex += v[u];
-      }
-    }
-    lds_barrier();
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = u * T + threadIdx.x;
-      if (i < H) {
-        const int slot = atomicAdd(&cnt[bv[u]], 1);
-        key[slot] = (uint64_t)__double_as_longlong(tv[u]);
-        pos[slot] = (uint16_t)i;
-      }
-    }
-    lds_barrier();
-    // cnt[b] is now the end of bucket b, and its start is the end of bucket b - 1.
-    // Order within buckets: every element counts the members of its bucket
-    // that precede it in (2theta bits, index), all elements at once; then
-    // each moves to its rank (all reads happen before the barrier, and the
-    // ranks of a bucket are a permutation of its slots).
-    int rk[PER];
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = u * T + threadIdx.x;
-      rk[u] = 0;
-      if (i < H) {
-        const uint64_t k = (uint64_t)__double_as_longlong(tv[u]);
-        const int b = bv[u];
-        int r = b ? cnt[b - 1] : 0;
-        for (int j = r, e0 = cnt[b]; j < e0; ++j) {
-          const uint64_t kj = key[j];
-          r += (kj < k || (kj == k && (int)pos[j] < i)) ? 1 : 0;
-        }
-        rk[u] = r;
-      }
-    }
-    lds_barrier();
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = u * T + threadIdx.x;
-      if (i < H) {
-        key[rk[u]] = (uint64_t)__double_as_longlong(tv[u]);
-        pos[rk[u]] = (uint16_t)i;
-      }
-    }
-    lds_barrier();
-    // entries (the evaluated half in 2theta order) and the expanded full order
-    for (int j = threadIdx.x; j < H; j += T) {
-      const uint64_t kj = key[j];
-      const double tj = __longlong_as_double((long long)kj);
-      const int p = pos[j];
-      if (ent_key) {
-        ent_key[e_base + j] = tj;
-        ent_idx[e_base + j] = (int32_t)(r0 + H + p);
-      }
-      // the full order: as the merge's perm, and as the entries themselves
-      // without Friedel pairing (skey/sidx are the entries then)
-      if (!ent_key || merge) {
-        int ga = j, gb = j;
-        while (ga > 0 && key[ga - 1] == kj) --ga;
-        while (gb + 1 < H && key[gb + 1] == kj) ++gb;
-        const int fm = 2 * ga + (gb - j), fp = gb + 1 + j;
-        const int64_t im = r0 + H - 1 - p, ip = r0 + H + p;
-        if (!ent_key) {
-          skey[r0 + fm] = tj;
-          sidx[r0 + fm] = (int32_t)im;
-          skey[r0 + fp] = tj;
-          sidx[r0 + fp] = (int32_t)ip;
-        }
-        if (merge) {
-          mo.perm[r0 + fm] = im;
-          mo.perm[r0 + fp] = ip;
-        }
-      }
-    }
-    if (merge) {
 #pragma clang fp contract(off)
       // peak-start flags on the half (one byte per entry, in the bucket
       // table's space): mates never change the anchor walk, having the same
       // 2theta as their partner, and a peak start always begins a key run
-      for (int j = threadIdx.x; j < H; j += T) {
+      for (int j = gt; j < H; j += T) {
         const double tj = __longlong_as_double((long long)key[j]);
         if (j == 0 || tj - __longlong_as_double((long long)key[j - 1]) >= mo.tol) {
           fl[j] = 1;
@@ -452,77 +480,129 @@ __global__ __launch_bounds__(T) void k_sort_crystal(int64_t n_c, const int32_t *
           }
         }
       }
-      lds_barrier();
-      // each thread owns a contiguous run of PER entries
-      const int i0 = threadIdx.x * PER;
-      int ns = 0;
-#pragma unroll
-      for (int u = 0; u < PER; ++u) ns += (i0 + u < H && fl[i0 + u]) ? 1 : 0;
-      int p = block_exclusive_scan<T, true>(ns, wsum, &total);
-      const int np = total;
-      // the run's intensities (an entry and its mate), loaded at once; a peak
-      // still open at the end of the run continues into the next runs
-      double iv[PER];
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int q = i0 + u < H ? pos[i0 + u] : 0;
-        iv[u] = i0 + u < H ? mo.inten[r0 + H - 1 - q] + mo.inten[r0 + H + q] : 0.0;
-      }
-      double mx = 0.0, sum = 0.0;
-      int m = 0, start = -1;
-      auto emit = [&]() {
-        mo.t_tt[r0 + p] = __longlong_as_double((long long)key[start]);
-        mo.t_i[r0 + p] = sum;
-        mo.t_mult[r0 + p] = m;
-        mo.t_first[r0 + p] = r0 + 2 * start;
-        mx = fmax(mx, sum);
-        ++p;
-      };
-#pragma unroll
-      for (int u = 0; u < PER; ++u) {
-        const int i = i0 + u;
-        if (i < H) {
-          if (fl[i]) {
-            if (start >= 0) emit();
-            start = i;
-            sum = iv[u];
-            m = 2;
-          } else if (start >= 0) {
-            sum += iv[u];
-            m += 2;
-          }
-        }
-      }
-      if (start >= 0) {
-        for (int j = i0 + PER; j < H && !fl[j]; ++j) {
-          const int q = pos[j];
-          sum += mo.inten[r0 + H - 1 - q] + mo.inten[r0 + H + q];
-          m += 2;
-        }
-        emit();
-      }
-      mx = block_max_nonneg<true>(mx, &smax);
-      finish_crystal<T>(mo, c, r0, np, mx, wsum);
     }
-    lds_barrier();  // LDS is reused by the next crystal
+    lds_barrier();  // every read of the keys is done: their space takes the pair intensities
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = u * T + gt;
+      if (i < H) ival[rk[u]] = iv[u];
+    }
+    // number the peaks: each thread counts the starts in its run of PER
+    // entries and lists them (in the sorted positions' space) at their numbers
+    const int i0 = gt * PER;
+    int ns = 0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) ns += (i0 + u < H && fl[i0 + u]) ? 1 : 0;
+    int p = group_exclusive_scan<T, true>(ns, gt, wsum, &total);
+    const int np = total;
+    uint16_t *const pstart = pos;
+#pragma unroll
+    for (int u = 0; u < PER; ++u)
+      if (i0 + u < H && fl[i0 + u]) pstart[p++] = (uint16_t)(i0 + u);
+    // the starts and intensities in LDS, the entries' keys in global memory
+    __syncthreads();
+    // one thread per peak: its members' intensities summed in sorted order;
+    // its 2theta is its first member's, the entry at its start (full-order
+    // slot 2 start without Friedel pairing)
+    double mx = 0.0;
+    for (int q = gt; q < np; q += T) {
+      const int a = pstart[q], e = q + 1 < np ? pstart[q + 1] : H;
+      double sum = ival[a];
+      for (int j = a + 1; j < e; ++j) sum += ival[j];
+      mo.t_tt[r0 + q] = ent_key ? ent_key[e_base + a] : skey[r0 + 2 * a];
+      mo.t_i[r0 + q] = sum;
+      mo.t_mult[r0 + q] = 2 * (e - a);
+      mo.t_first[r0 + q] = r0 + 2 * a;
+      mx = fmax(mx, sum);
+    }
+    mx = group_max_nonneg<true>(mx, gt, smax);
+    finish_crystal<T>(mo, c, r0, np, mx, gt, PER, wsum);
   }
 }
 
-// Exclusive scan of the per-crystal peak counts into peak_offset[0..n_c], by
-// one block.
+// Exclusive scan of the per-crystal peak counts into peak_offset[0..n_c] by
+// one block of 1024 threads, each taking kScanPer consecutive counts.
+constexpr int kScanPer = 8;
 __global__ __launch_bounds__(1024) void k_peak_scan(int64_t n_c, const int32_t *__restrict__ cnt,
                                                     int64_t *__restrict__ peak_offset) {
   __shared__ int32_t wsum[1024 / 64];
   int64_t carry = 0;
-  for (int64_t c0 = 0; c0 < n_c; c0 += 1024) {
-    const int64_t c = c0 + threadIdx.x;
-    const int v = c < n_c ? cnt[c] : 0;
+  for (int64_t c0 = 0; c0 < n_c; c0 += 1024 * kScanPer) {
+    const int64_t i0 = c0 + (int64_t)threadIdx.x * kScanPer;
+    int v[kScanPer], sum = 0;
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      v[u] = i0 + u < n_c ? cnt[i0 + u] : 0;
+      sum += v[u];
+    }
     int total;
-    const int ex = block_exclusive_scan<1024>(v, wsum, &total);
-    if (c < n_c) peak_offset[c] = carry + ex;
+    int ex = block_exclusive_scan<1024>(sum, wsum, &total);
+#pragma unroll
+    for (int u = 0; u < kScanPer; ++u) {
+      if (i0 + u < n_c) peak_offset[i0 + u] = carry + ex;
+      ex += v[u];
+    }
     carry += total;
   }
   if (threadIdx.x == 0) peak_offset[n_c] = carry;
+}
+
+// Sort (and merge) of every crystal in one launch of 1024-thread blocks.
+// items[0, n_big) are the crystals whose capacity exceeds 2 kTinySort
+// reflections: block b < n_big takes items[b] if it really has more than
+// 2 kTinySort (the LDS sizes up to 2 CAPMAX reflections, the global-memory
+// path beyond).  items[n_big, n_big + n_c) lists every crystal once more:
+// each later block takes four of them, one per 256-thread group with a
+// quarter of the LDS, and sorts those with at most 2 kTinySort.  Blocks
+// with nothing to sort end at once.
+template <int CAPMAX>
+__global__ __launch_bounds__(1024, 8) void k_sort_merge(int64_t n_c, int64_t n_big, const int32_t *__restrict__ items,
+                                                        const CrystalPlan *__restrict__ plan,
+                                                        const int64_t *__restrict__ refl_offset,
+                                                        const double *__restrict__ tt, double *__restrict__ skey,
+                                                        int32_t *__restrict__ sidx, double *__restrict__ ent_key,
+                                                        int32_t *__restrict__ ent_idx, int32_t *__restrict__ bin_count,
+                                                        int64_t *__restrict__ bin_start, MergeOut mo) {
+  static_assert(CAPMAX >= 4 * kTinySort, "four small crystals share the block's LDS");
+  __shared__ uint64_t key[CAPMAX];
+  __shared__ uint16_t pos[CAPMAX];
+  __shared__ int32_t cnt[CAPMAX / 2];
+  __shared__ int32_t wsum[1024 / 64];
+  __shared__ unsigned long long smax[4];
+  const int64_t blk = blockIdx.x;
+  if (blk < n_big) {
+    const int64_t c = items[blk];
+    const int64_t R = refl_offset[c + 1] - refl_offset[c];
+    if (R > 2 * (int64_t)CAPMAX)
+      sort_global<1024>(c, plan, refl_offset, tt, skey, sidx, ent_key, ent_idx, bin_count, bin_start, mo, wsum, smax);
+    else if (R > 2 * kSmallSort)
+      sort_lds<CAPMAX, 1024>(c, (int)threadIdx.x, key, pos, cnt, wsum, smax, plan, refl_offset, tt, skey, sidx,
+                             ent_key, ent_idx, mo);
+    else if (R > 2 * kTinySort)
+      sort_lds<kSmallSort, 1024>(c, (int)threadIdx.x, key, pos, cnt, wsum, smax, plan, refl_offset, tt, skey, sidx,
+                                 ent_key, ent_idx, mo);
+  } else {
+    // the four crystals of this block (every thread reads all four, so the
+    // decision to skip is the block's)
+    const int64_t first = (blk - n_big) * 4;
+    int64_t cg[4];
+    bool any = false;
+#pragma unroll
+    for (int g = 0; g < 4; ++g) {
+      cg[g] = -1;
+      if (first + g < n_c) {
+        const int64_t c = items[n_big + first + g];
+        if (refl_offset[c + 1] - refl_offset[c] <= 2 * kTinySort) cg[g] = c;
+      }
+      any = any || cg[g] >= 0;
+    }
+    if (any) {
+      const int g = (int)(threadIdx.x >> 8);
+      sort_lds<kTinySort, 256>(cg[g], (int)(threadIdx.x & 255), key + g * kTinySort, pos + g * kTinySort,
+                               cnt + g * (kTinySort / 2), wsum + g * 4, smax + g, plan, refl_offset, tt, skey, sidx,
+                               ent_key, ent_idx, mo);
+    }
+  }
 }
 
 // Packs each crystal's staged peaks at peak_offset[c] and scales them:
@@ -574,61 +654,30 @@ MergeOut merge_out(const MergeArgs *m) {
   return mo;
 }
 
-// Sizes by a crystal's reflection count R (each kernel skips the other
-// sizes' crystals): R <= 2 kTinySort by 256 threads with 12 KB of LDS (eight
-// blocks per CU); R <= 2 kSmallSort and R <= 2 kMidSort by 1024 threads (a
-// short chain of phases for the larger crystals); beyond, the global-memory
-// path.  The three groups run on three streams (the caller's and two forked
-// ones), as they take disjoint crystals.
-void sort_kernels(const SortArgs &a, const MergeOut &mo, const Fork &f, hipStream_t s) {
+// The one sort launch: its grid covers every crystal that can exceed
+// 2 kTinySort reflections (by capacity) plus every crystal again, four to a
+// block.
+void sort_kernels(const SortArgs &a, const MergeOut &mo, hipStream_t s) {
   if (a.n_c <= 0) return;
   double *ek = a.friedel ? a.ent_key : nullptr;
   int32_t *ei = a.friedel ? a.ent_idx : nullptr;
-  const bool fork = f.side != nullptr && (a.n_small > 0 || a.n_mid > 0);
-  hipStream_t s1 = fork ? f.side : s, s2 = fork ? f.side2 : s;
-  if (fork) {
-    (void)hipEventRecord(f.fork, s);
-    (void)hipStreamWaitEvent(f.side, f.fork, 0);
-    (void)hipStreamWaitEvent(f.side2, f.fork, 0);
-  }
-  if (a.n_mid > 0)
-    hipLaunchKernelGGL((k_sort_crystal<kMidSort, kMidThreads, false, 2 * kSmallSort>), dim3((unsigned)a.n_mid),
-                       dim3(kMidThreads), 0, s2, a.n_mid, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek,
-                       ei, a.bin_count, a.bin_start, mo);
-  if (a.n_large > 0) {
-    const unsigned g = (unsigned)(a.n_large < kLargeBlocks ? a.n_large : kLargeBlocks);
-    hipLaunchKernelGGL((k_sort_crystal<kGlobalCap, kLargeThreads, true, 2 * kMidSort>), dim3(g), dim3(kLargeThreads),
-                       0, s2, a.n_large, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count,
-                       a.bin_start, mo);
-  }
-  // the longest chains (the 1024-thread sizes) start on the caller's stream
-  // and the side stream that holds the largest crystals
-  if (a.n_small > 0)
-    hipLaunchKernelGGL((k_sort_crystal<kSmallSort, kSmallThreads, false, 2 * kTinySort>), dim3((unsigned)a.n_small),
-                       dim3(kSmallThreads), 0, s, a.n_small, a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek,
-                       ei, a.bin_count, a.bin_start, mo);
-  hipLaunchKernelGGL((k_sort_crystal<kTinySort, 256, false, 0>), dim3((unsigned)a.n_c), dim3(256), 0, s1, a.n_c,
-                     a.order, a.plan, a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count, a.bin_start, mo);
-  if (fork) {
-    (void)hipEventRecord(f.join, f.side);
-    (void)hipEventRecord(f.join2, f.side2);
-    (void)hipStreamWaitEvent(s, f.join, 0);
-    (void)hipStreamWaitEvent(s, f.join2, 0);
-  }
+  const unsigned grid = (unsigned)(a.n_small + (a.n_c + 3) / 4);
+  hipLaunchKernelGGL(k_sort_merge<kMidSort>, dim3(grid), dim3(1024), 0, s, a.n_c, a.n_small, a.items, a.plan,
+                     a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count, a.bin_start, mo);
 }
 
 }  // namespace
 
-void launch_sort(const SortArgs &a, const Fork &f, hipStream_t s) { sort_kernels(a, merge_out(nullptr), f, s); }
+void launch_sort(const SortArgs &a, hipStream_t s) { sort_kernels(a, merge_out(nullptr), s); }
 
-void launch_merge(const MergeArgs &a, const Fork &f, hipStream_t s) {
+void launch_merge(const MergeArgs &a, hipStream_t s) {
   const SortArgs &o = a.sort;
   if (a.n_c <= 0) {
     launch_fill_u64(reinterpret_cast<uint64_t *>(a.peak_offset), 1, 0, s);
     return;
   }
   const MergeOut mo = merge_out(&a);
-  sort_kernels(o, mo, f, s);
+  sort_kernels(o, mo, s);
   hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, s, a.n_c, a.pk_count, a.peak_offset);
   if (a.n_peak_chunks > 0)
     hipLaunchKernelGGL(k_peak_move, dim3((unsigned)a.n_peak_chunks), dim3(kThreads), 0, s, a.peak_chunks,

@@ -33,7 +33,7 @@ constexpr int kSplitFwd = 64;
 constexpr int kSplitBw = 48;
 constexpr int kTinySort = 1024;      // Friedel-positive reflections sorted in LDS by one 256-thread block
 constexpr int kSmallSort = 4096;     // ... by one 1024-thread block
-constexpr int kMidSort = 8192;       // ... by one 1024-thread block; larger crystals sort in global memory
+constexpr int kMidSort = 6144;       // ... by one 1024-thread block; larger crystals sort in global memory
 constexpr int kSpanPts = 16;         // grid points per span of the broadening gather (a quarter wavefront)
 constexpr int kRecLen = 8;           // reflections per segment of the row-recurrence structure factors
 constexpr int kRecMinAtoms = 256;    // XRD_SF_AUTO: default atom threshold of the recurrence
@@ -145,6 +145,7 @@ struct WsLayout {
   int64_t skey, sidx, ent_key, ent_idx, ent_w, span_first, span_last;
   int64_t flags;
   int64_t cmax, pk_count, tmp_tt, tmp_i, tmp_mult, tmp_first;
+  int64_t sort_items;  // the sort launch's crystal lists
   int64_t scan_part;
   int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6, bw_partf;
   int64_t sf_deriv;  // kept (A, B, dA/ds^2, dB/ds^2) per reflection, or -1
@@ -249,9 +250,9 @@ struct SortArgs {
   double *skey;
   int32_t *sidx;
   const int32_t *order;  // [n_c] crystals by descending capacity
-  int64_t n_mid;         // leading entries of ``order`` with capacity above 2 kSmallSort
   int64_t n_small;       // leading entries of ``order`` with capacity above 2 kTinySort
-  int64_t n_large;       // leading entries of ``order`` with capacity above 2 kMidSort
+  const int32_t *items;  // [n_small + n_c] the sort launch's crystals: those that may exceed
+                         // 2 kTinySort reflections, then every crystal (four per block)
   int32_t friedel;       // write the evaluated-half entries below
   double *ent_key;       // [half capacity] 2theta of the evaluated half, sorted per crystal
   int32_t *ent_idx;      // its global reflection indices
@@ -266,9 +267,8 @@ struct Fork {
   hipEvent_t fork, join, join2;
 };
 
-// The sorts of the larger crystals go to the fork's side streams, concurrent
-// with the sort of the small ones.
-void launch_sort(const SortArgs &a, const Fork &f, hipStream_t s);
+// Every sort of a call runs in one launch on the caller's stream.
+void launch_sort(const SortArgs &a, hipStream_t s);
 
 struct MergeArgs {
   SortArgs sort;
@@ -289,7 +289,7 @@ struct MergeArgs {
   int32_t *pk_mult;
   int64_t *pk_first, *perm, *peak_offset;
 };
-void launch_merge(const MergeArgs &a, const Fork &f, hipStream_t s);
+void launch_merge(const MergeArgs &a, hipStream_t s);
 
 // Gaussian broadening over the sorted entries (evaluated reflections in
 // 2theta order).  The forward also fills ent_w (double weights, or float
