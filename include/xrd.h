@@ -115,7 +115,10 @@ typedef struct {
                                      and buffers are neither built nor part of the workspace (a
                                      smaller plan and workspace for streams of forward patterns);
                                      xrd_pattern_backward then fails with XRD_ERR_UNSUPPORTED */
-    int32_t reserved;             /* set to 0 */
+    int32_t sf_rpt;               /* tile shape of the direct structure-factor sums: reflections
+                                     per lane, 1, 2 or 4 (a wavefront sums a tile of 64 times
+                                     that); 0 selects 2 and lets xrd_autotune choose.  The
+                                     workspace is sized for any shape. */
 } xrd_batch_desc;
 
 typedef struct {
@@ -277,8 +280,15 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
  * forward and adjoint S (INT32_MAX: no split).  Under XRD_SF_AUTO it first
  * times the per-crystal choice of the recurrence for atom thresholds of 64 to
  * 1024 (and never) and keeps the fastest; split_out must then hold 3 values,
- * the third the chosen atom threshold. */
+ * the third the chosen atom threshold.  Unless the batch fixed its tile
+ * shape (sf_rpt != 0), all of this is done for each shape (1, 2 and 4
+ * reflections per lane) and the shape with the fastest forward plus adjoint
+ * sum is kept with its splits; xrd_batch_get_sf_rpt reports it. */
 int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out);
+
+/* The batch's current tile shape of the direct structure-factor sums
+ * (reflections per lane: 1, 2 or 4) into ``*rpt`` (host). */
+int xrd_batch_get_sf_rpt(const xrd_batch *b, int32_t *rpt);
 
 /* Experimental effects for ML training patterns (paper, Section 1: the
  * simulated patterns of ML training sets are modified with effects such as

@@ -86,13 +86,18 @@ class XrdBatch:
     "recurrence" (stepped along reciprocal-lattice rows from exact seeds) or
     "auto" (the recurrence for crystals with many atoms and long rows).
     ``forward_only`` leaves out the adjoint's tables and buffers (no
-    ``pattern_backward`` on this batch)."""
+    ``pattern_backward`` on this batch).  ``sf_rpt`` fixes the tile shape of
+    the direct sums (reflections per lane: 1, 2 or 4); 0 starts at 2 and lets
+    ``autotune`` choose."""
 
     def __init__(self, batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
                  rel_threshold: float = 0.0, device="cuda", frac: Optional[torch.Tensor] = None,
                  bfac: Optional[torch.Tensor] = None, lattice: Optional[np.ndarray] = None,
                  two_theta_range: Optional[tuple] = None, grid_capacity: int = 0,
-                 keep_sf_derivs: bool = False, sf_method: str = "direct", forward_only: bool = False):
+                 keep_sf_derivs: bool = False, sf_method: str = "direct", forward_only: bool = False,
+                 sf_rpt: int = 0):
+        if sf_rpt not in (0, 1, 2, 4):
+            raise ValueError("sf_rpt must be 0, 1, 2 or 4")
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         if sf_method not in SF_METHODS:
@@ -136,6 +141,7 @@ class XrdBatch:
         d.keep_sf_derivs = 1 if keep_sf_derivs else 0
         d.sf_method = SF_METHODS[sf_method]
         d.forward_only = 1 if forward_only else 0
+        d.sf_rpt = sf_rpt
         d.frac = _p(self.frac) if batch.n_atoms else None
         d.species = _p(self.species) if batch.n_atoms else None
         d.occ = _p(self.occ) if batch.n_atoms else None
@@ -214,9 +220,16 @@ class XrdBatch:
 
     def autotune(self, refl: Reflections):
         """Time the structure-factor split candidates on ``refl`` (enumerated on
-        this batch) and keep the fastest; returns (forward, adjoint) thresholds
-        and, for sf_method "auto", the atom threshold of the recurrence (else -1)."""
+        this batch), at each tile shape unless the batch fixed one, and keep the
+        fastest; returns (forward, adjoint) thresholds and, for sf_method
+        "auto", the atom threshold of the recurrence (else -1).  The chosen
+        shape is ``sf_rpt``."""
         return capi.xrd_autotune(self.handle, self.ws, refl.c())
+
+    @property
+    def sf_rpt(self) -> int:
+        """Current tile shape of the direct structure-factor sums (reflections per lane)."""
+        return capi.xrd_batch_get_sf_rpt(self.handle)
 
     def preferred_orientation(self, refl: Reflections, I: torch.Tensor, hp, march_r) -> torch.Tensor:
         """March-Dollase texture applied to I in place; hp [n_crystals, 3]
@@ -322,13 +335,13 @@ class PatternResult:
 
 def simulate(batch: CrystalBatch, precision: str = "mixed", friedel: Optional[bool] = None,
              rel_threshold: float = 0.0, device="cuda", autotune: bool = False,
-             family_rule: Optional[int] = None, sf_method: str = "direct") -> PatternResult:
+             family_rule: Optional[int] = None, sf_method: str = "direct", sf_rpt: int = 0) -> PatternResult:
     """Enumerate, structure factors, merge for every crystal; host arrays back.
-    With ``autotune`` the structure-factor split is tuned on the enumerated
-    reflections first; with a ``family_rule`` (0: indices, 1: lattice) the
-    peaks' families of equivalent reflections come back too."""
+    With ``autotune`` the structure-factor tile shape and split are tuned on
+    the enumerated reflections first; with a ``family_rule`` (0: indices, 1:
+    lattice) the peaks' families of equivalent reflections come back too."""
     xb = XrdBatch(batch, precision=precision, friedel=friedel, rel_threshold=rel_threshold, device=device,
-                  sf_method=sf_method)
+                  sf_method=sf_method, sf_rpt=sf_rpt)
     refl = xb.enumerate()
     if autotune:
         xb.autotune(refl)

@@ -38,7 +38,7 @@ class xrd_batch_desc(C.Structure):
         ("friedel", C.c_int32), ("grid_capacity", C.c_int32),
         ("keep_sf_derivs", C.c_int32), ("sf_method", C.c_int32),
         ("frac", _vp), ("species", _vp), ("occ", _vp), ("bfac", _vp), ("sf_coeff", _vp),
-        ("stream", _vp), ("forward_only", C.c_int32), ("reserved", C.c_int32),
+        ("stream", _vp), ("forward_only", C.c_int32), ("sf_rpt", C.c_int32),
     ]
 
 
@@ -85,6 +85,7 @@ SIGNATURES = {
     "xrd_pattern_forward": ([_vp, _vp, C.POINTER(xrd_refl), _vp, C.POINTER(xrd_grid), _vp], C.c_int),
     "xrd_pattern_backward": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(xrd_grid), _vp, _vp, _vp, _vp], C.c_int),
     "xrd_autotune": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(C.c_int32)], C.c_int),
+    "xrd_batch_get_sf_rpt": ([_vp, C.POINTER(C.c_int32)], C.c_int),
     "xrd_preferred_orientation": ([_vp, _vp, C.POINTER(xrd_refl), _vp, _vp, _vp], C.c_int),
     "xrd_pattern_noise": ([_vp, C.c_int64, C.c_uint64, C.c_double, C.c_double, _vp], C.c_int),
     "xrd_peak_families": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(xrd_peaks), C.c_int32, _vp, _vp, _vp, _vp],
@@ -180,6 +181,13 @@ def xrd_autotune(batch, ws: int, refl: xrd_refl):
     out = (C.c_int32 * 3)(0, 0, -1)
     check(lib().xrd_autotune(batch, ws, C.byref(refl), out))
     return int(out[0]), int(out[1]), int(out[2])
+
+
+def xrd_batch_get_sf_rpt(batch) -> int:
+    """The batch's tile shape of the direct structure-factor sums (reflections per lane)."""
+    out = C.c_int32(0)
+    check(lib().xrd_batch_get_sf_rpt(batch, C.byref(out)))
+    return int(out.value)
 
 
 def xrd_preferred_orientation(batch, ws: int, refl: xrd_refl, hp: int, march_r: int, I: int):

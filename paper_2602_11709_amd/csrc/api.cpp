@@ -51,6 +51,8 @@ struct xrd_batch {
   int64_t n_small = 0;    // crystals whose reflection capacity exceeds 2 kTinySort
   int64_t sf_heavy = 0, sf_heavy_bw = 0;  // leading items that take a block each
   int32_t split_fwd = kSplitFwd, split_bw = kSplitBw;
+  int32_t rpt = kSfRptDefault;      // reflections per lane of the direct structure-factor kernels
+  std::vector<double> expect_eval;  // per crystal: expected evaluated reflections
   int64_t grid_cap = 0;   // largest grid of a broadened-pattern call
   int64_t span_cap = 0;   // span-table entries per crystal: ceil(grid_cap / kSpanPts)
   int runs_cap_max = 1, bw_tile = 64;
@@ -373,6 +375,33 @@ void choose_methods(xrd_batch *b) {
   if (b->rec) b->sf_heavy_rec = sf_table(b, b->split_fwd, &b->sf_items_rec, true, true);
 }
 
+// Tile shape of the direct structure-factor kernels: ``rpt`` reflections per
+// lane, tiles of 64 rpt reflections.  Places each crystal's tiles, its rows
+// of the per-tile tables (packed from the start of the workspace's arrays,
+// which are sized for the finest shape) and its expected-filled tile count.
+// The work tables (choose_methods, the adjoint's sf_table) are built after.
+void set_tiles(xrd_batch *b, int32_t rpt) {
+  b->rpt = rpt;
+  const int64_t tile = 64 * (int64_t)rpt;
+  const bool friedel = b->desc.friedel != 0;
+  const int64_t nc = (int64_t)b->plan.size();
+  b->sf_likely.resize(nc);
+  int64_t tb = 0, pf = 0;
+  for (int64_t c = 0; c < nc; ++c) {
+    CrystalPlan &P = b->plan[c];
+    const int64_t evalcap = friedel ? P.half_box : 2 * P.half_box;
+    P.sf_tile = (int16_t)tile;
+    P.n_tiles = (int32_t)ceil_div(evalcap, tile);
+    P.tile_begin = (int32_t)tb;
+    tb += P.n_tiles;
+    if (P.fused) {
+      P.pf_begin = pf;
+      pf += (int64_t)P.n_tiles * (P.atom_end - P.atom_begin);
+    }
+    b->sf_likely[c] = (int32_t)std::min<double>((double)P.n_tiles, std::ceil((b->expect_eval[c] + tile) / tile));
+  }
+}
+
 }  // namespace
 
 // Host-side sizes shared with the kernels' launch code.
@@ -417,6 +446,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   if (d->grid_capacity < 0) return fail(XRD_ERR_INVALID_ARG, "grid_capacity < 0");
   if (d->keep_sf_derivs != 0 && d->keep_sf_derivs != 1)
     return fail(XRD_ERR_INVALID_ARG, "keep_sf_derivs must be 0 or 1");
+  if (d->sf_rpt != 0 && d->sf_rpt != 1 && d->sf_rpt != 2 && d->sf_rpt != 4)
+    return fail(XRD_ERR_INVALID_ARG, "sf_rpt must be 0, 1, 2 or 4");
   if (d->sf_method != XRD_SF_DIRECT && d->sf_method != XRD_SF_RECURRENCE && d->sf_method != XRD_SF_AUTO)
     return fail(XRD_ERR_INVALID_ARG, "unknown sf_method");
   if (d->forward_only != 0 && d->forward_only != 1) return fail(XRD_ERR_INVALID_ARG, "forward_only must be 0 or 1");
@@ -511,13 +542,14 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     P.n_hchunks = (int32_t)std::max<int64_t>(1, ceil_div(evalcap, kHalfChunk));
     P.hchunk_begin = hc;
     hc += P.n_hchunks;
-    P.n_tiles = (int32_t)ceil_div(evalcap, kSfTile);
-    P.tile_begin = (int32_t)tiles_total;
-    tiles_total += P.n_tiles;
+    // structure-factor tiles at the finest shape, for which the per-tile
+    // tables of the workspace are sized (set_tiles places them for the
+    // batch's shape)
+    const int64_t fine_tiles = ceil_div(evalcap, 64 * kSfRptMin);
+    tiles_total += fine_tiles;
     P.fused = na <= kFusedMaxAtoms ? 1 : 0;
     if (P.fused) {
-      P.pf_begin = pfused;
-      pfused += (int64_t)P.n_tiles * na;
+      pfused += fine_tiles * na;
     } else {
       P.part_begin = parts;
       parts += (int64_t)P.n_hchunks * na;
@@ -645,11 +677,9 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   // structure-factor items: crystals in descending atom count (the cost of
   // one item), so the heaviest work is dispatched first
   b->sf_order.resize(nc);
-  b->sf_likely.resize(nc);
-  for (int64_t c = 0; c < nc; ++c) {
-    b->sf_order[c] = (int32_t)c;
-    b->sf_likely[c] = likely_units(c, kSfTile, b->plan[c].n_tiles);
-  }
+  for (int64_t c = 0; c < nc; ++c) b->sf_order[c] = (int32_t)c;
+  b->expect_eval = expect_eval;
+  set_tiles(b, d->sf_rpt == 0 ? kSfRptDefault : d->sf_rpt);
   std::stable_sort(b->sf_order.begin(), b->sf_order.end(), [&](int32_t x, int32_t y) {
     return (b->atom_offset[x + 1] - b->atom_offset[x]) > (b->atom_offset[y + 1] - b->atom_offset[y]);
   });
@@ -681,7 +711,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     }
   }
   choose_methods(b);
-  if ((int64_t)b->sf_items.size() >= ((int64_t)1 << 31) || (int64_t)b->bw_items.size() >= ((int64_t)1 << 31) ||
+  if (tiles_total + nc >= ((int64_t)1 << 31) || (int64_t)b->bw_items.size() >= ((int64_t)1 << 31) ||
       (int64_t)b->sf_items_rec.size() >= ((int64_t)1 << 31)) {
     delete b;
     return fail(XRD_ERR_CAPACITY, "launch tables exceed 2^31 entries");
@@ -698,8 +728,10 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   const int64_t rc = b->refl_cap;
   L.plan = take((int64_t)sizeof(CrystalPlan) * nc);
   L.enum_chunk_tab = take((int64_t)sizeof(EnumChunk) * ec);
-  L.sf_items = take((int64_t)sizeof(SfItem) * tiles_total);  // every crystal's tiles (the choice may change)
-  L.sf_items_bw = take((int64_t)sizeof(SfItem) * (int64_t)b->sf_items_bw.size());
+  // every crystal's tiles and one tail item each, at the finest tile shape
+  // (the shape, split and methods may change)
+  L.sf_items = take((int64_t)sizeof(SfItem) * (tiles_total + nc));
+  L.sf_items_bw = take(adjoint ? (int64_t)sizeof(SfItem) * (tiles_total + nc) : 0);
   L.peak_chunks = take((int64_t)sizeof(HChunk) * sc);
   L.eblocks = take((int64_t)sizeof(HChunk) * (int64_t)b->eblocks.size());
   L.crystal_order = take(4 * nc);
@@ -969,7 +1001,7 @@ static void launch_forward_sums(xrd_batch *b, void *ws, const xrd_refl *r, void 
     launch_sf(mixed, friedel, at<SfItem>(ws, L.sf_items), (int64_t)b->sf_items.size(), b->sf_heavy,
               at<CrystalPlan>(ws, L.plan), r->refl_offset, r->h, r->k, r->l, r->q, r->lp, at<AtomRec>(ws, L.atoms),
               at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f),
-              A, B, I, deriv, sd);
+              A, B, I, deriv, b->rpt, sd);
   if (f.side) {
     (void)hipEventRecord(f.join, f.side);
     (void)hipStreamWaitEvent(s, f.join, 0);
@@ -1192,7 +1224,7 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   launch_sf_bw(mixed, friedel, items, n_items, b->sf_heavy_bw, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
                b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
                b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), deriv, w1, w2, ga, gb, dq, at<double>(ws, L.bw_part6),
-               at<double>(ws, L.bw_partf), s);
+               at<double>(ws, L.bw_partf), b->rpt, s);
   launch_atom_bw(mixed, friedel, at<BwItem>(ws, L.bw_items), (int64_t)b->bw_items.size(), plan, r->refl_offset,
                  r->h, r->k, r->l, r->q, ga, gb, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
                  at<int32_t>(ws, L.run_count), b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), b->bw_tile, b->runs_cap_max,
@@ -1226,7 +1258,7 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
                  r->k, r->l, r->q, r->lp, b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
                  at<int32_t>(ws, L.run_count), b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), deriv, w1, w2,
                  at<double>(ws, L.bw_ga), at<double>(ws, L.bw_gb), at<double>(ws, L.bw_dq), at<double>(ws, L.bw_part6),
-                 at<double>(ws, L.bw_partf), s);
+                 at<double>(ws, L.bw_partf), b->rpt, s);
   };
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipError_t e = hipEventCreate(&ev[0]);
@@ -1266,7 +1298,12 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
   };
   // candidate thresholds; those giving the same tables as an earlier one are skipped
   const int32_t cand[] = {8, 16, 24, 32, 48, 64, 96, 128, 256, 512, INT32_MAX};
-  if (nc > 0 && e == hipSuccess) {
+  // At the current tile shape: the recurrence threshold (XRD_SF_AUTO) and the
+  // forward split, then the adjoint's split; leaves the best of each in the
+  // batch and returns the sum of the two times (the forward's alone without
+  // an adjoint).
+  auto tune_shape = [&]() -> float {
+    float fwd_best = 0.f, bw_best = 0.f;
     // (XRD_SF_AUTO) which crystals take the recurrence: atom thresholds
     if (b->desc.sf_method == XRD_SF_AUTO) {
       const int32_t rcand[] = {64, 128, 256, 512, 1024, INT32_MAX};
@@ -1291,7 +1328,6 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
     // split-K of the forward sums
     {
       std::vector<std::pair<int64_t, int64_t>> seen;
-      float best = 0.f;
       int32_t best_split = b->split_fwd;
       for (int32_t c : cand) {
         if (e != hipSuccess) break;
@@ -1301,8 +1337,8 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
         if (std::find(seen.begin(), seen.end(), key) != seen.end()) continue;
         seen.push_back(key);
         const float ms = time_fwd();
-        if (e == hipSuccess && (seen.size() == 1 || ms < best)) {
-          best = ms;
+        if (e == hipSuccess && (seen.size() == 1 || ms < fwd_best)) {
+          fwd_best = ms;
           best_split = c;
         }
       }
@@ -1310,33 +1346,66 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
       choose_methods(b);
       upload_fwd();
     }
+    if (!adjoint) return fwd_best;
     // the adjoint's inputs: derivatives of the chosen forward tables, zero grid weights
-    if (adjoint && e == hipSuccess) {
+    if (e == hipSuccess) {
       launch_forward_sums(b, ws, r, A, B, I, deriv);
       launch_fill_u64(reinterpret_cast<uint64_t *>(w1), b->refl_cap, 0, s);
       launch_fill_u64(reinterpret_cast<uint64_t *>(w2), b->refl_cap, 0, s);
       e = hipGetLastError();
     }
-    if (adjoint) {
-      std::vector<SfItem> t;
-      std::vector<int64_t> seen;
-      float best = 0.f;
-      for (int32_t c : cand) {
-        if (e != hipSuccess) break;
-        const int64_t nh = sf_table(b, c, &t);
-        if (std::find(seen.begin(), seen.end(), nh) != seen.end()) continue;
-        seen.push_back(nh);
-        e = hipMemcpyAsync(at<char>(ws, L.sf_items_bw), t.data(), sizeof(SfItem) * t.size(), hipMemcpyHostToDevice, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) break;
-        const float ms = timed([&] { run_bw(t, nh); });
-        if (e == hipSuccess) e = hipGetLastError();
-        if (e == hipSuccess && (seen.size() == 1 || ms < best)) {
-          best = ms;
-          b->split_bw = c;
-        }
+    std::vector<SfItem> t;
+    std::vector<int64_t> seen;
+    for (int32_t c : cand) {
+      if (e != hipSuccess) break;
+      const int64_t nh = sf_table(b, c, &t);
+      if (std::find(seen.begin(), seen.end(), nh) != seen.end()) continue;
+      seen.push_back(nh);
+      e = hipMemcpyAsync(at<char>(ws, L.sf_items_bw), t.data(), sizeof(SfItem) * t.size(), hipMemcpyHostToDevice, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) break;
+      const float ms = timed([&] { run_bw(t, nh); });
+      if (e == hipSuccess) e = hipGetLastError();
+      if (e == hipSuccess && (seen.size() == 1 || ms < bw_best)) {
+        bw_best = ms;
+        b->split_bw = c;
       }
     }
+    return fwd_best + bw_best;
+  };
+  // the tile shape (reflections per lane), unless the batch fixed it: each
+  // shape with its own best splits, the fastest forward plus adjoint kept
+  auto upload_plan = [&]() {
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(at<char>(ws, L.plan), b->plan.data(), sizeof(CrystalPlan) * b->plan.size(),
+                         hipMemcpyHostToDevice, s);
+  };
+  if (nc > 0 && e == hipSuccess) {
+    std::vector<int32_t> shapes = {1, 2, 4};
+    if (b->desc.sf_rpt != 0) shapes = {b->desc.sf_rpt};
+    struct Choice {
+      int32_t rpt, split_fwd, split_bw, rec_min_atoms;
+    } best{b->rpt, b->split_fwd, b->split_bw, b->rec_min_atoms};
+    float best_ms = 0.f;
+    bool first = true;
+    for (int32_t rpt : shapes) {
+      if (e != hipSuccess) break;
+      set_tiles(b, rpt);
+      upload_plan();
+      const float ms = tune_shape();
+      if (e == hipSuccess && (first || ms < best_ms)) {
+        best_ms = ms;
+        best = Choice{rpt, b->split_fwd, b->split_bw, b->rec_min_atoms};
+        first = false;
+      }
+    }
+    set_tiles(b, best.rpt);
+    b->split_fwd = best.split_fwd;
+    b->split_bw = best.split_bw;
+    b->rec_min_atoms = best.rec_min_atoms;
+    choose_methods(b);
+    upload_plan();
+    upload_fwd();
     if (adjoint) {
       b->sf_heavy_bw = sf_table(b, b->split_bw, &b->sf_items_bw);
       if (e == hipSuccess)
@@ -1357,6 +1426,12 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
     split_out[1] = b->split_bw;
     if (b->desc.sf_method == XRD_SF_AUTO) split_out[2] = b->rec_min_atoms;
   }
+  return XRD_OK;
+}
+
+int xrd_batch_get_sf_rpt(const xrd_batch *b, int32_t *rpt) {
+  if (!b || !rpt) return fail(XRD_ERR_INVALID_ARG, "batch or rpt is NULL");
+  *rpt = b->rpt;
   return XRD_OK;
 }
 

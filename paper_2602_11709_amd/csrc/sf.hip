@@ -10,11 +10,12 @@
 // (reflection, species) and multiplies a partial sum over that species'
 // atoms instead of every term.
 //
-// One wavefront owns one work item: 64 x kSfRpt reflections of one crystal.
+// One wavefront owns one work item: a tile of 64 x R reflections of one
+// crystal (R, the reflections per lane, is the batch's tile shape: 1, 2 or 4).
 // It walks the crystal's atoms in order; the atom index is uniform across the
 // wavefront, so the atom records stream through the scalar cache into SGPRs
 // and are broadcast to every lane with no LDS traffic and no barrier.  Each
-// lane keeps kSfRpt reflections in registers.
+// lane keeps R reflections in registers.
 //
 // Mixed precision (XRD_MIXED): t = h x + k y + l z in double, reduced mod 1
 // in double (v_fract_f64), then sin/cos of the revolution in single precision
@@ -123,7 +124,7 @@ __device__ __forceinline__ double fsc_f64(const double *__restrict__ c9, double 
   return f;
 }
 
-// Which part of the batch a wavefront takes.  Items (crystal, tile of kSfTile
+// Which part of the batch a wavefront takes.  Items (crystal, tile of 64 R
 // evaluated reflections) come heavy first: the first n_heavy items get a block
 // each, whose four wavefronts split the crystal's atoms into contiguous
 // quarters (their sums are combined in LDS in wave order); the remaining
@@ -195,16 +196,15 @@ __device__ __forceinline__ void fsc_df_f64(const double *__restrict__ c9, double
 // not change the structure factors.  Heavy items: the four wavefronts' sums
 // meet in LDS (s_part) and are added in wave order; returns false for the
 // waves that hold no totals afterwards (all but wave 0 unless all_waves).
-template <bool MIXED, bool DERIV>
+template <bool MIXED, bool DERIV, int R>
 __device__ __forceinline__ bool sf_tile_sums(const WaveWork &ww, int lane, const SpeciesRun *__restrict__ cr, int nr,
                                              int wa, int wb, const AtomRec *__restrict__ atoms,
                                              const double *__restrict__ coeff,
-                                             const CoeffF *__restrict__ coeff_f, const double (&h)[kSfRpt],
-                                             const double (&k)[kSfRpt], const double (&l)[kSfRpt],
-                                             const double (&s2d)[kSfRpt], const float (&s2)[kSfRpt],
-                                             double *s_part, bool all_waves, double (&A)[kSfRpt],
-                                             double (&B)[kSfRpt], double (&dA)[kSfRpt], double (&dB)[kSfRpt]) {
-  constexpr int R = kSfRpt;
+                                             const CoeffF *__restrict__ coeff_f, const double (&h)[R],
+                                             const double (&k)[R], const double (&l)[R],
+                                             const double (&s2d)[R], const float (&s2)[R],
+                                             double *s_part, bool all_waves, double (&A)[R],
+                                             double (&B)[R], double (&dA)[R], double (&dB)[R]) {
   if constexpr (MIXED) {
     // per reflection: A, B and, with DERIV, dA, dB in double; each chunk of
     // up to kAtomTile atoms of a run is summed in single precision and added
@@ -411,7 +411,7 @@ __device__ __forceinline__ void load_derivs(const void *cache, int64_t i, double
 // Structure factors of one tile per wavefront (light items) or per block
 // (heavy items).  With DERIV the derivatives with respect to s^2 are also
 // summed and kept in ``cache`` for the adjoint.
-template <bool MIXED, bool FRIEDEL, bool DERIV>
+template <bool MIXED, bool FRIEDEL, bool DERIV, int R>
 __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ items, int64_t n_items, int64_t n_heavy,
                                                  const int64_t *__restrict__ refl_offset,
                                                  const int16_t *__restrict__ hh, const int16_t *__restrict__ kk,
@@ -423,7 +423,6 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
                                                  const CoeffF *__restrict__ coeff_f, void *__restrict__ Aout,
                                                  void *__restrict__ Bout, double *__restrict__ Iout,
                                                  void *__restrict__ cache) {
-  constexpr int R = kSfRpt;
   // heavy blocks: per wave, the doubles of each value (A, B and with DERIV
   // dA, dB), per reflection slot and lane
   __shared__ double s_part[(kThreads / 64) * (DERIV ? 4 : 2) * R * 64];
@@ -437,7 +436,7 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
   // a tail item walks the crystal's tiles from its first one on (the tiles
   // beyond the expected reflection count, which are mostly empty)
   auto tile_body = [&](int32_t tile) -> bool {
-    const int64_t tbase = (int64_t)tile * kSfTile;
+    const int64_t tbase = (int64_t)tile * (64 * R);
     if (tbase >= count) return false;  // uniform over a heavy block
     const int lane = threadIdx.x & 63;
     int64_t idx[R];
@@ -459,7 +458,7 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
     int wa, wb;
     part_range(it, ww, &wa, &wb);
     double A[R], B[R], dA[R], dB[R];
-    if (!sf_tile_sums<MIXED, DERIV>(ww, lane, runs + it.run_begin, run_count[it.crystal], wa, wb, atoms, coeff, coeff_f,
+    if (!sf_tile_sums<MIXED, DERIV, R>(ww, lane, runs + it.run_begin, run_count[it.crystal], wa, wb, atoms, coeff, coeff_f,
                                     h, k, l, s2d, s2, s_part, false, A, B, dA, dB))
       return false;
 #pragma unroll
@@ -507,7 +506,7 @@ __global__ __launch_bounds__(kThreads) void k_sf(const SfItem *__restrict__ item
 //   gA = 2 LP A gI,  gB = 2 LP B gI,
 //   dL/dq = gI |F|^2 dLP/dq + (gA dA/ds^2 + gB dB/ds^2) / 4 + m w2 I d(2theta)/dq,
 // where w1, w2 come from the grid adjoint and m = 2 with pairing, else 1.
-template <bool MIXED, bool CACHED>
+template <bool MIXED, bool CACHED, int R>
 __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ items, int64_t n_items, int64_t n_heavy, bool friedel,
                                                     const CrystalPlan *__restrict__ plan,
                                                     const int64_t *__restrict__ refl_offset,
@@ -523,7 +522,6 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
                                                     const double *__restrict__ w2, double *__restrict__ ga,
                                                     double *__restrict__ gb, double *__restrict__ dq,
                                                     double *__restrict__ part6, double4 *__restrict__ part_fused) {
-  constexpr int R = kSfRpt;
   // heavy blocks without the kept derivatives: per wave, value (8 floats or
   // 4 doubles), reflection slot, lane
   __shared__ double s_part[CACHED ? 1 : (kThreads / 64) * 4 * R * 64];
@@ -536,7 +534,7 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
   const int64_t count = friedel ? nref / 2 : nref;
   // a tail item walks the crystal's tiles from its first one on
   auto tile_body = [&](int32_t tile) -> bool {
-    const int64_t tbase = (int64_t)tile * kSfTile;
+    const int64_t tbase = (int64_t)tile * (64 * R);
     if (tbase >= count) return false;
     const int lane = threadIdx.x & 63;
     int64_t idx[R];
@@ -564,7 +562,7 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
 #pragma unroll
       for (int u = 0; u < R; ++u) load_derivs<MIXED>(cache, idx[u], &A[u], &B[u], &dA[u], &dB[u]);
     } else {
-      sf_tile_sums<MIXED, true>(ww, lane, cr, nr, wa, wb, atoms, coeff, coeff_f, h, k, l, s2d, s2, s_part, true, A, B,
+      sf_tile_sums<MIXED, true, R>(ww, lane, cr, nr, wa, wb, atoms, coeff, coeff_f, h, k, l, s2d, s2, s_part, true, A, B,
                                 dA, dB);
     }
     const double m = friedel ? 2.0 : 1.0;
@@ -917,7 +915,7 @@ __device__ __forceinline__ void atom_bw_reduce(const AbItem it, bool friedel, co
   if (P.fused) {
     const int64_t nref = refl_offset[it.crystal + 1] - refl_offset[it.crystal];
     const int64_t count = friedel ? nref / 2 : nref;
-    const int64_t tiles = (count + kSfTile - 1) / kSfTile;  // tiles that ran
+    const int64_t tiles = (count + P.sf_tile - 1) / P.sf_tile;  // tiles that ran
     const double4 *p = part_fused + P.pf_begin + ja;
     sum_rows(p, na, tiles, &sx, &sy, &sz, &sB);
   } else {
@@ -995,7 +993,7 @@ __global__ __launch_bounds__(kThreads) void k_bw_finish(const AbItem *__restrict
   const CrystalPlan &P = plan[c];
   const int64_t nref = refl_offset[c + 1] - refl_offset[c];
   const int64_t count = friedel ? nref / 2 : nref;
-  const int n_rows = (int)((count + kSfTile - 1) / kSfTile);
+  const int n_rows = (int)((count + P.sf_tile - 1) / P.sf_tile);
   const double *rows = part6 + (int64_t)P.tile_begin * 6;
   double U[6] = {0, 0, 0, 0, 0, 0};
   for (int k = lane; k < n_rows; k += 64)
@@ -1010,13 +1008,13 @@ __global__ __launch_bounds__(kThreads) void k_bw_finish(const AbItem *__restrict
 
 
 
-template <bool MIXED, bool FRIEDEL, bool DERIV>
+template <bool MIXED, bool FRIEDEL, bool DERIV, int R>
 static void launch_sf_t(dim3 grid, const SfItem *items, int64_t n_items, int64_t n_heavy,
                         const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,
                         const double *q, const double *lp, const AtomRec *atoms, const SpeciesRun *runs,
                         const int32_t *run_count, const double *coeff, const CoeffF *coeff_f, void *A, void *B,
                         double *I, void *cache, hipStream_t s) {
-  hipLaunchKernelGGL((k_sf<MIXED, FRIEDEL, DERIV>), grid, dim3(kThreads), 0, s, items, n_items, n_heavy,
+  hipLaunchKernelGGL((k_sf<MIXED, FRIEDEL, DERIV, R>), grid, dim3(kThreads), 0, s, items, n_items, n_heavy,
                      refl_offset, h, k, l, q, lp, atoms, runs, run_count, coeff, coeff_f, A, B, I, cache);
 }
 
@@ -1024,7 +1022,7 @@ void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, i
                const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
                const double *coeff, const CoeffF *coeff_f, void *A, void *B, double *I, void *deriv_cache,
-               hipStream_t s) {
+               int rpt, hipStream_t s) {
   if (n_items <= 0) return;
   const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4));
   auto go = [&](auto fn) {
@@ -1032,17 +1030,21 @@ void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, i
        I, deriv_cache, s);
   };
   const bool d = deriv_cache != nullptr;
+  // the instantiation for (precision, Friedel pairing, kept derivatives, R)
+  auto by_r = [&](auto f1, auto f2, auto f4) { rpt == 1 ? go(f1) : rpt == 4 ? go(f4) : go(f2); };
+#define XRD_SF_R(M, F, D) by_r(launch_sf_t<M, F, D, 1>, launch_sf_t<M, F, D, 2>, launch_sf_t<M, F, D, 4>)
   if (mixed) {
     if (friedel)
-      d ? go(launch_sf_t<true, true, true>) : go(launch_sf_t<true, true, false>);
+      d ? XRD_SF_R(true, true, true) : XRD_SF_R(true, true, false);
     else
-      d ? go(launch_sf_t<true, false, true>) : go(launch_sf_t<true, false, false>);
+      d ? XRD_SF_R(true, false, true) : XRD_SF_R(true, false, false);
   } else {
     if (friedel)
-      d ? go(launch_sf_t<false, true, true>) : go(launch_sf_t<false, true, false>);
+      d ? XRD_SF_R(false, true, true) : XRD_SF_R(false, true, false);
     else
-      d ? go(launch_sf_t<false, false, true>) : go(launch_sf_t<false, false, false>);
+      d ? XRD_SF_R(false, false, true) : XRD_SF_R(false, false, false);
   }
+#undef XRD_SF_R
 }
 
 }  // namespace xrd
@@ -1055,25 +1057,35 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
                   const int32_t *run_count, const double *coeff, const CoeffF *coeff_f, const void *deriv_cache,
                   const double *w1, const double *w2, double *ga, double *gb, double *dq, double *part6,
-                  double *part_fused, hipStream_t s) {
+                  double *part_fused, int rpt, hipStream_t s) {
   if (n_items <= 0) return;
   const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4)), block(kThreads);
   double4 *pf = (double4 *)part_fused;
-#define XRD_SF_BW(M, C)                                                                                          \
-  hipLaunchKernelGGL((k_sf_bw<M, C>), grid, block, 0, s, items, n_items, n_heavy, friedel, plan, refl_offset, h, k, \
-                     l, q, lp, lambda, atoms, runs, run_count, coeff, coeff_f, deriv_cache, w1, w2, ga, gb, dq,  \
+#define XRD_SF_BW(M, C, R)                                                                                          \
+  hipLaunchKernelGGL((k_sf_bw<M, C, R>), grid, block, 0, s, items, n_items, n_heavy, friedel, plan, refl_offset, h, \
+                     k, l, q, lp, lambda, atoms, runs, run_count, coeff, coeff_f, deriv_cache, w1, w2, ga, gb, dq,  \
                      part6, pf)
+#define XRD_SF_BW_R(M, C)   \
+  if (rpt == 1)             \
+    XRD_SF_BW(M, C, 1);     \
+  else if (rpt == 4)        \
+    XRD_SF_BW(M, C, 4);     \
+  else                      \
+    XRD_SF_BW(M, C, 2)
   if (mixed) {
-    if (deriv_cache)
-      XRD_SF_BW(true, true);
-    else
-      XRD_SF_BW(true, false);
+    if (deriv_cache) {
+      XRD_SF_BW_R(true, true);
+    } else {
+      XRD_SF_BW_R(true, false);
+    }
   } else {
-    if (deriv_cache)
-      XRD_SF_BW(false, true);
-    else
-      XRD_SF_BW(false, false);
+    if (deriv_cache) {
+      XRD_SF_BW_R(false, true);
+    } else {
+      XRD_SF_BW_R(false, false);
+    }
   }
+#undef XRD_SF_BW_R
 #undef XRD_SF_BW
 }
 

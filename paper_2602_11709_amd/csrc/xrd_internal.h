@@ -22,8 +22,11 @@ constexpr int kEntBlock = 1024;   // entries per block of the broadening's entry
 constexpr int kScanBlock = 2048;  // elements per scan block (256 threads x 8)
 constexpr int kAtomBlock = 256;   // atoms per adjoint block
 constexpr int kSfThreads = 256;   // threads per block of the structure-factor kernels
-constexpr int kSfRpt = 2;         // reflections per lane in the structure-factor kernels
-constexpr int kSfTile = 64 * kSfRpt;
+// Tile shape of the direct structure-factor kernels: reflections per lane
+// (1, 2 or 4; a tile is 64 times that), per batch; the default, and the
+// finest one, for which the workspace's per-tile tables are sized.
+constexpr int kSfRptDefault = 2;
+constexpr int kSfRptMin = 1;
 constexpr int kFusedMaxAtoms = 512;  // crystals up to this size take the fused atom-gradient path
 // Split-K of the structure-factor kernels: crystals with at least this many
 // atoms get a block per tile, whose four wavefronts split the atom sum; the
@@ -61,7 +64,8 @@ struct alignas(16) CrystalPlan {
   int64_t hchunk_begin;  // first adjoint chunk (global id)
   int64_t part_begin;    // first adjoint partial row: rows = n_hchunks * N
   int32_t sort_chunks;
-  int32_t fused;       // 1: atom gradients reduced inside the reflection-major adjoint
+  int16_t fused;       // 1: atom gradients reduced inside the reflection-major adjoint
+  int16_t sf_tile;     // reflections per structure-factor tile (64 x reflections per lane)
   int64_t pf_begin;    // first row of the fused adjoint partials: rows = n_tiles * N
   int32_t n_tiles;     // structure-factor tiles at capacity
   int32_t tile_begin;  // first row of this crystal's per-tile dL/dG* rows
@@ -206,7 +210,7 @@ void launch_sf(bool mixed, bool friedel, const SfItem *items, int64_t n_items, i
                const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                const double *lp, const AtomRec *atoms, const SpeciesRun *runs, const int32_t *run_count,
                const double *coeff, const CoeffF *coeff_f, void *A, void *B, double *I, void *deriv_cache,
-               hipStream_t s);
+               int rpt, hipStream_t s);
 
 // Structure factors by the row recurrence (sfrec.hip): the segments of the
 // current reflections are built first (kRecLen consecutive reflections of a
@@ -313,7 +317,7 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
                   const int32_t *run_count, const double *coeff, const CoeffF *coeff_f, const void *deriv_cache,
                   const double *w1,
                   const double *w2, double *ga, double *gb, double *dq, double *part6, double *part_fused,
-                  hipStream_t s);
+                  int rpt, hipStream_t s);
 size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap);
 void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,
                     const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l,

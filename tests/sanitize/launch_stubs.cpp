@@ -31,7 +31,7 @@ void launch_enumerate(const CrystalPlan *, int64_t, const EnumChunk *, int64_t, 
 }
 void launch_sf(bool, bool, const SfItem *, int64_t, int64_t, const CrystalPlan *, const int64_t *, const int16_t *,
                const int16_t *, const int16_t *, const double *, const double *, const AtomRec *, const SpeciesRun *,
-               const int32_t *, const double *, const CoeffF *, void *, void *, double *, void *, hipStream_t) {
+               const int32_t *, const double *, const CoeffF *, void *, void *, double *, void *, int, hipStream_t) {
   reached("sf");
 }
 void launch_sf_rec(bool, bool, const SfRecArgs &, void *, void *, double *, void *, hipStream_t) { reached("sf_rec"); }
@@ -50,7 +50,7 @@ void launch_broaden_adj(bool, const HChunk *, int64_t, const CrystalPlan *, bool
 void launch_sf_bw(bool, bool, const SfItem *, int64_t, int64_t, const CrystalPlan *, const int64_t *, const int16_t *,
                   const int16_t *, const int16_t *, const double *, const double *, double, const AtomRec *,
                   const SpeciesRun *, const int32_t *, const double *, const CoeffF *, const void *, const double *,
-                  const double *, double *, double *, double *, double *, double *, hipStream_t) {
+                  const double *, double *, double *, double *, double *, double *, int, hipStream_t) {
   reached("sf_bw");
 }
 void launch_atom_bw(bool, bool, const BwItem *, int64_t, const CrystalPlan *, const int64_t *, const int16_t *,

@@ -247,6 +247,27 @@ def test_sf_method_is_validated_and_sizes_the_workspace():
     assert ei.value.code == capi.XRD_ERR_INVALID_ARG
 
 
+def test_tile_shape_is_validated_and_reported():
+    """sf_rpt: 0 selects 2 reflections per lane, 1/2/4 are kept as given,
+    anything else is refused; the workspace does not depend on it (it is
+    sized for the finest shape)."""
+    keep = []
+    b = synth.random_triclinic(25, 9, atoms_hi=60)
+    sizes = {}
+    for rpt, expect in ((0, 2), (1, 1), (2, 2), (4, 4)):
+        h = capi.xrd_batch_create(make_desc(b, keep, sf_rpt=rpt))
+        try:
+            assert capi.xrd_batch_get_sf_rpt(h) == expect
+            sizes[rpt] = capi.xrd_batch_sizes(h).workspace_bytes
+        finally:
+            capi.xrd_batch_destroy(h)
+    assert len(set(sizes.values())) == 1, sizes
+    for bad in (3, 8, -1):
+        with pytest.raises(capi.XrdError) as ei:
+            capi.xrd_batch_create(make_desc(b, keep, sf_rpt=bad))
+        assert ei.value.code == capi.XRD_ERR_INVALID_ARG
+
+
 def test_set_lattice_validates_before_any_device_work():
     """A cell needing a larger search box, or an invalid cell, is refused
     before anything is copied (host only)."""
