@@ -205,17 +205,24 @@ class Forward:
     paper's calculator) of one batch and precision, captured in a HIP graph
     on a stream of its own."""
 
-    def __init__(self, batch, precision, friedel=None, sf_method="direct"):
+    def __init__(self, batch, precision, friedel=None, sf_method="direct", autotune=False):
         import torch
         from paper_2602_11709_amd.api import XrdBatch
         self.torch = torch
         self.batch = batch
         self.stream = torch.cuda.Stream()
         with torch.cuda.stream(self.stream):
-            self.xb = XrdBatch(batch, precision=precision, friedel=friedel, sf_method=sf_method)
+            self.xb = XrdBatch(batch, precision=precision, friedel=friedel, sf_method=sf_method, forward_only=True)
             self.refl = self.xb.new_reflections()
             self.sf = self.xb.new_sf()
             self.pk = self.xb.new_peaks()
+            self.tuned = None
+            if autotune:
+                # set-up: tile shape and split-K of the forward sums on the enumerated reflections
+                self.xb.enumerate(self.refl)
+                fwd, _, rec = self.xb.autotune(self.refl)
+                self.tuned = {"reflections_per_lane": self.xb.sf_rpt, "split_atoms": fwd,
+                              "recurrence_min_atoms": rec if rec >= 0 else None}
             self.step()
         torch.cuda.synchronize()
         self.n_refl = int(self.refl.refl_offset[-1])
@@ -451,14 +458,14 @@ def leg_large_cells(steps):
     peaks = {}
     for name, precision, friedel in (("mixed", "mixed", True), ("fp64", "fp64", False),
                                      ("fp64_friedel", "fp64", True)):
-        f = Forward(b, precision, friedel)
+        f = Forward(b, precision, friedel, autotune=True)
         ms = f.replay_ms(steps)
         sf = f.sf_ms(3)
         full, ev = f.terms()
         out[name] = {"ms_per_step": round(ms, 4), "patterns_per_s": round(b.n_crystals / (ms * 1e-3), 2),
                      "sf_kernel_ms": round(sf, 4), "sf_terms_per_s": round(ev / (sf * 1e-3), 1),
                      "sf_terms_per_s_effective": round(full / (sf * 1e-3), 1), "evaluated_terms": ev,
-                     "reflections": f.n_refl, "peaks": f.n_peaks}
+                     "reflections": f.n_refl, "peaks": f.n_peaks, "autotune": f.tuned}
         peaks[name] = f.peaks()
         del f
     po, got, m1 = peaks["mixed"]
@@ -804,8 +811,9 @@ def main():
     for name, precision, friedel in legs:
         p = Pipeline(batch, precision, friedel=friedel)
         with torch.cuda.stream(p.stream):
-            # batch set-up, outside the timed region: the split-K autotuner
-            # times the structure-factor kernels on the enumerated reflections
+            # batch set-up, outside the timed region: the autotuner times the
+            # structure-factor kernels' tile shapes and split-K thresholds on
+            # the enumerated reflections
             p.enumerate()
             t0 = time.perf_counter()
             p.split = None if args.no_autotune else p.xb.autotune(p.refl)
@@ -889,7 +897,7 @@ def main():
                     "(no adjoint)"},
         "autotune": None if mx["p"].split is None else {
             "split_atoms_forward": mx["p"].split[0], "split_atoms_adjoint": mx["p"].split[1],
-            "ms": round(mx["p"].tune_ms, 1)},
+            "reflections_per_lane": mx["p"].xb.sf_rpt, "ms": round(mx["p"].tune_ms, 1)},
         "roofline": {
             "kernel": "k_sf (mixed, Friedel-halved, keeping dF/ds^2)",
             "bound": "alu",
