@@ -524,7 +524,9 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
       return fail(XRD_ERR_CAPACITY, "reflection capacity exceeds 2^31; split the batch");
     }
     P.sort_chunk_begin = sc;
-    P.sort_chunks = (int32_t)ceil_div(2 * P.half_box, kSortChunk);
+    // at least one, so that every crystal has a block of the peak move (which
+    // also writes its peak offset)
+    P.sort_chunks = (int32_t)std::max<int64_t>(1, ceil_div(2 * P.half_box, kSortChunk));
     sc += P.sort_chunks;
     P.n_bins = (int32_t)std::max<int64_t>(1, 2 * P.half_box / kBinDiv);
     P.bin_begin = bins;

@@ -29,6 +29,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kPer = kSortChunk / kThreads;  // 4
+constexpr int64_t kPrefixCrystals = 4096;    // batches up to this size number their peaks in the move kernel
 
 __device__ __forceinline__ int bin_of(const CrystalPlan &P, double tt) {
 #pragma clang fp contract(off)
@@ -605,23 +606,57 @@ __global__ __launch_bounds__(1024, 8) void k_sort_merge(int64_t n_c, int64_t n_b
   }
 }
 
-// Packs each crystal's staged peaks at peak_offset[c] and scales them:
+// Sum over the block (kThreads threads) of one value per thread; ``red``
+// holds kThreads / 64 values of LDS.  Every thread of the block must call it.
+__device__ __forceinline__ int64_t block_sum_i64(int64_t v, int64_t *red) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  __syncthreads();  // red may still be read from a previous call
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int64_t t = 0;
+#pragma unroll
+  for (int w = 0; w < kThreads / 64; ++w) t += red[w];
+  return t;
+}
+
+// Packs each crystal's staged peaks at its peak offset and scales them:
 // scaled = 100 I / max I of the crystal (0 when that maximum is 0).  One block
 // per peak chunk (kSortChunk peak slots of one crystal, from a table of
-// (crystal, chunk) pairs).
-__global__ __launch_bounds__(kThreads) void k_peak_move(const HChunk *__restrict__ chunks,
+// (crystal, chunk) pairs in which every crystal has at least its chunk 0).
+// With ``prefix`` the block computes its crystal's offset itself, the sum of
+// the counts of the crystals before it, and the block of a crystal's chunk 0
+// writes it to peak_offset (block 0 also writes the total); otherwise the
+// offsets come from a scan launched before.
+__global__ __launch_bounds__(kThreads) void k_peak_move(const HChunk *__restrict__ chunks, int64_t n_c, bool prefix,
                                                         const int64_t *__restrict__ refl_offset,
-                                                        const int64_t *__restrict__ peak_offset, MergeOut mo,
+                                                        int64_t *__restrict__ peak_offset, MergeOut mo,
                                                         double *__restrict__ pk_tt, double *__restrict__ pk_i,
                                                         double *__restrict__ pk_y, int32_t *__restrict__ pk_mult,
                                                         int64_t *__restrict__ pk_first) {
+  __shared__ int64_t red[kThreads / 64];
   const HChunk ch = chunks[blockIdx.x];
   const int32_t c = ch.crystal;
   const int64_t k0 = (int64_t)ch.chunk * kSortChunk;
   // the crystal's values, loaded together
   const int np = mo.pk_count[c];
-  const int64_t r0 = refl_offset[c], o = peak_offset[c];
+  const int64_t r0 = refl_offset[c];
   const double mx = __longlong_as_double((long long)mo.cmax[c]);
+  int64_t o;
+  if (prefix) {
+    int64_t part = 0;
+    for (int64_t i = threadIdx.x; i < c; i += kThreads) part += mo.pk_count[i];
+    o = block_sum_i64(part, red);
+    if (ch.chunk == 0 && threadIdx.x == 0) peak_offset[c] = o;
+    if (blockIdx.x == 0) {
+      int64_t all = 0;
+      for (int64_t i = threadIdx.x; i < n_c; i += kThreads) all += mo.pk_count[i];
+      all = block_sum_i64(all, red);
+      if (threadIdx.x == 0) peak_offset[n_c] = all;
+    }
+  } else {
+    o = peak_offset[c];
+  }
   if (k0 >= np) return;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
@@ -678,10 +713,13 @@ void launch_merge(const MergeArgs &a, hipStream_t s) {
   }
   const MergeOut mo = merge_out(&a);
   sort_kernels(o, mo, s);
-  hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, s, a.n_c, a.pk_count, a.peak_offset);
-  if (a.n_peak_chunks > 0)
-    hipLaunchKernelGGL(k_peak_move, dim3((unsigned)a.n_peak_chunks), dim3(kThreads), 0, s, a.peak_chunks,
-                       o.refl_offset, a.peak_offset, mo, a.pk_tt, a.pk_i, a.pk_y, a.pk_mult, a.pk_first);
+  // up to kPrefixCrystals crystals, each move block sums the counts before
+  // its crystal (at most that many loads from L2) instead of waiting for a
+  // one-block scan
+  const bool prefix = a.n_c <= kPrefixCrystals;
+  if (!prefix) hipLaunchKernelGGL(k_peak_scan, dim3(1), dim3(1024), 0, s, a.n_c, a.pk_count, a.peak_offset);
+  hipLaunchKernelGGL(k_peak_move, dim3((unsigned)a.n_peak_chunks), dim3(kThreads), 0, s, a.peak_chunks, a.n_c, prefix,
+                     o.refl_offset, a.peak_offset, mo, a.pk_tt, a.pk_i, a.pk_y, a.pk_mult, a.pk_first);
 }
 
 }  // namespace xrd

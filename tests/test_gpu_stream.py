@@ -64,3 +64,25 @@ def test_stream_device_hand_over_and_empty_chunks():
     assert len(dev) == len(host) == 3
     for a, c in zip(dev, host):
         np.testing.assert_array_equal(a, c)
+
+
+def test_peak_numbering_with_and_without_the_scan():
+    """Batches of up to 4096 crystals number their peaks inside the move
+    kernel, larger ones with a scan first: 5000 crystals as one batch (scan)
+    and as two chunks of 2500 (in-kernel sums) give the same offsets and
+    peaks bit for bit."""
+    from paper_2602_11709_amd.api import simulate
+    from paper_2602_11709_amd.stream import DatabaseStream
+    b = synth.database_stream(n_crystals=5000)
+    got = {}
+    DatabaseStream(b, chunk=2500, precision="mixed", planners=2).run(lambda cp: got.__setitem__(cp.first, cp),
+                                                                     to_host=True)
+    whole = simulate(b, precision="mixed")
+    assert sorted(got) == [0, 2500]
+    for c0, cp in got.items():
+        p0 = int(whole.peak_offset[c0])
+        np.testing.assert_array_equal(cp.peak_offset, whole.peak_offset[c0:c0 + cp.n_crystals + 1] - p0)
+        p1 = int(whole.peak_offset[c0 + cp.n_crystals])
+        np.testing.assert_array_equal(cp.two_theta.numpy(), whole.pk_two_theta[p0:p1])
+        np.testing.assert_array_equal(cp.intensity.numpy(), whole.pk_intensity[p0:p1])
+        np.testing.assert_array_equal(cp.mult.numpy(), whole.pk_mult[p0:p1])
