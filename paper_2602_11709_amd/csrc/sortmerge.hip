@@ -421,19 +421,14 @@ __device__ void sort_lds(int64_t c, int gt, uint64_t *key, uint16_t *pos, int32_
     }
   }
   lds_barrier();
-  // the pair intensities (an entry and its mate) in input order, coalesced;
-  // they land while the entries are written
-  double iv[PER];
-  if (merge) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int i = u * T + gt;
-      iv[u] = i < H ? mo.inten[r0 + H - 1 - i] + mo.inten[r0 + H + i] : 0.0;
-    }
-  }
-  // entries (the evaluated half in 2theta order) and the expanded full order
+  // entries (the evaluated half in 2theta order), the expanded full order
+  // and, with a merge, the peak-start flags, in one pass: each entry's key
+  // and its neighbours' are read once (a key run longer than one, rare,
+  // reads further)
   for (int j = gt; j < H; j += T) {
     const uint64_t kj = key[j];
+    const uint64_t kp = j > 0 ? key[j - 1] : 0ull;
+    const uint64_t kn = j + 1 < H ? key[j + 1] : 0ull;
     const double tj = __longlong_as_double((long long)kj);
     const int p = pos[j];
     if (ent_key) {
@@ -444,8 +439,14 @@ __device__ void sort_lds(int64_t c, int gt, uint64_t *key, uint16_t *pos, int32_
     // without Friedel pairing (skey/sidx are the entries then)
     if (!ent_key || merge) {
       int ga = j, gb = j;
-      while (ga > 0 && key[ga - 1] == kj) --ga;
-      while (gb + 1 < H && key[gb + 1] == kj) ++gb;
+      if (j > 0 && kp == kj) {
+        ga = j - 1;
+        while (ga > 0 && key[ga - 1] == kj) --ga;
+      }
+      if (j + 1 < H && kn == kj) {
+        gb = j + 1;
+        while (gb + 1 < H && key[gb + 1] == kj) ++gb;
+      }
       const int fm = 2 * ga + (gb - j), fp = gb + 1 + j;
       const int64_t im = r0 + H - 1 - p, ip = r0 + H + p;
       if (!ent_key) {
@@ -459,28 +460,33 @@ __device__ void sort_lds(int64_t c, int gt, uint64_t *key, uint16_t *pos, int32_
         mo.perm[r0 + fp] = ip;
       }
     }
-  }
-  if (merge) {
-    {
+    if (merge) {
 #pragma clang fp contract(off)
       // peak-start flags on the half (one byte per entry, in the bucket
-      // table's space): mates never change the anchor walk, having the same
-      // 2theta as their partner, and a peak start always begins a key run
-      for (int j = gt; j < H; j += T) {
-        const double tj = __longlong_as_double((long long)key[j]);
-        if (j == 0 || tj - __longlong_as_double((long long)key[j - 1]) >= mo.tol) {
-          fl[j] = 1;
-          double anchor = tj, prev = tj;
-          for (int m = j + 1; m < H; ++m) {
-            const double tm = __longlong_as_double((long long)key[m]);
-            if (tm - prev >= mo.tol) break;
-            const bool open = (tm - anchor) >= mo.tol;
-            fl[m] = open ? 1 : 0;
-            if (open) anchor = tm;
-            prev = tm;
-          }
+      // table's space): one walker per component (a gap >= tol opens one);
+      // mates never change the anchor walk, having the same 2theta as their
+      // partner, and a peak start always begins a key run
+      if (j == 0 || tj - __longlong_as_double((long long)kp) >= mo.tol) {
+        fl[j] = 1;
+        double anchor = tj, prev = tj;
+        for (int m = j + 1; m < H; ++m) {
+          const double tm = __longlong_as_double((long long)(m == j + 1 ? kn : key[m]));
+          if (tm - prev >= mo.tol) break;
+          const bool open = (tm - anchor) >= mo.tol;
+          fl[m] = open ? 1 : 0;
+          if (open) anchor = tm;
+          prev = tm;
         }
       }
+    }
+  }
+  if (merge) {
+    // the pair intensities (an entry and its mate) in input order, coalesced
+    double iv[PER];
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int i = u * T + gt;
+      iv[u] = i < H ? mo.inten[r0 + H - 1 - i] + mo.inten[r0 + H + i] : 0.0;
     }
     lds_barrier();  // every read of the keys is done: their space takes the pair intensities
 #pragma unroll
