@@ -87,24 +87,41 @@ __device__ __forceinline__ double wave_sum_to_63(double v) {
   return v;
 }
 
-// Sixteen per-lane values reduced over the wavefront at once: a butterfly
-// whose levels pair lanes l and l^15 (row mirror), l^7 (half-row mirror),
-// l^2 and l^1 (quad permutes), each lane keeping the half of its values whose
-// index bit matches its own lane bit, then l^16 and l^32 across rows.  On
-// return every lane holds the wave total of value (lane & 15).  Fifteen
-// exchanges and adds in the rows instead of four times six.
+// Sixteen per-lane values reduced over the wavefront at once, with no
+// selects for the two cross-row levels: v_permlane32_swap exchanges the upper
+// half-wave of one register with the lower half of another, so pairing
+// values (2i, 2i+1) and adding leaves value 2i + (lane >= 32) summed over
+// lanes l and l ^ 32; v_permlane16_swap does the same with odd and even rows
+// (pairs of those sums), leaving in row r value 4i + {0, 2, 1, 3}[r] summed
+// over the four rows.  Within rows, a mirror and a half-mirror butterfly
+// (each lane keeping the half whose index bit matches its lane bit 3, then
+// bit 2) and two quad exchanges finish the sum.  On return lane l holds the
+// wave total of value 4 ((l >> 2) & 3) + {0, 2, 1, 3}[l >> 4] (the same in
+// the four lanes of its quad).
+__device__ __forceinline__ int wave_reduce16_index(int lane) {
+  const int rv = (lane >> 4) == 1 ? 2 : (lane >> 4) == 2 ? 1 : (lane >> 4);
+  return 4 * ((lane >> 2) & 3) + rv;
+}
 __device__ __forceinline__ float wave_reduce16(const float (&v)[16], int lane) {
-  float w8[8], w4[4], w2[2];
-  const bool b3 = lane & 8, b2 = lane & 4, b1 = lane & 2, b0 = lane & 1;
+  float a[8], b[4], c[2];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) w8[i] = (b3 ? v[8 + i] : v[i]) + dpp_f32<0x140, 0xf, false>(b3 ? v[i] : v[8 + i]);
+  for (int i = 0; i < 8; ++i) {
+    const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v[2 * i]), __float_as_uint(v[2 * i + 1]), false,
+                                                    false);
+    a[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) w4[i] = (b2 ? w8[4 + i] : w8[i]) + dpp_f32<0x141, 0xf, false>(b2 ? w8[i] : w8[4 + i]);
+  for (int i = 0; i < 4; ++i) {
+    const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(a[2 * i]), __float_as_uint(a[2 * i + 1]), false,
+                                                    false);
+    b[i] = __uint_as_float(r[0]) + __uint_as_float(r[1]);
+  }
+  const bool b3 = lane & 8, b2 = lane & 4;
 #pragma unroll
-  for (int i = 0; i < 2; ++i) w2[i] = (b1 ? w4[2 + i] : w4[i]) + dpp_f32<0x4e, 0xf, false>(b1 ? w4[i] : w4[2 + i]);
-  float w = (b0 ? w2[1] : w2[0]) + dpp_f32<0xb1, 0xf, false>(b0 ? w2[0] : w2[1]);
-  w += __shfl_xor(w, 16, 64);
-  w += __shfl_xor(w, 32, 64);
+  for (int j = 0; j < 2; ++j) c[j] = (b3 ? b[2 + j] : b[j]) + dpp_f32<0x140, 0xf, false>(b3 ? b[j] : b[2 + j]);
+  float w = (b2 ? c[1] : c[0]) + dpp_f32<0x141, 0xf, false>(b2 ? c[0] : c[1]);
+  w += dpp_f32<0xb1, 0xf, false>(w);  // quad_perm [1, 0, 3, 2]
+  w += dpp_f32<0x4e, 0xf, false>(w);  // quad_perm [2, 3, 0, 1]
   return w;
 }
 
@@ -675,9 +692,9 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
             v[4 * q + 3] = sb;
           }
           const float tot = wave_reduce16(v, lane);
-          const int q = lane >> 2;
-          if (lane < 16 && j0 + q < re)
-            reinterpret_cast<double *>(out + (j0 + q - P.atom_begin))[lane & 3] = (double)tot;
+          const int vi = wave_reduce16_index(lane), q = vi >> 2;
+          if ((lane & 3) == 0 && j0 + q < re)
+            reinterpret_cast<double *>(out + (j0 + q - P.atom_begin))[vi & 3] = (double)tot;
         }
       } else {
         double f[R], fA[R], fB[R];
