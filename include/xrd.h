@@ -335,6 +335,41 @@ int xrd_preferred_orientation(xrd_batch *b, void *ws, const xrd_refl *r, const d
 int xrd_peak_families(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_peaks *p, int32_t rule,
                       int32_t *n_families, int32_t *family_of, int64_t *family_label, int32_t *family_mult);
 
+/* One emission line's peaks for xrd_combine_lines: ``peaks`` from a
+ * completed xrd_merge_peaks (two_theta, intensity, mult, first, perm and
+ * peak_offset are read; DEVICE) on a batch of that line's wavelength, ``q``
+ * (DEVICE) the reflections' q of the same batch, ``weight`` the line's
+ * relative intensity. */
+typedef struct {
+    const xrd_peaks *peaks;
+    const double *q;
+    double weight;
+} xrd_line;
+
+/* Combined peak list of one or two emission lines (all DEVICE, caller-owned,
+ * capacity >= the two lines' peaks together). */
+typedef struct {
+    double *two_theta;     /* degrees, ascending within each crystal */
+    double *intensity;     /* weight x the line's peak intensity */
+    double *scaled;        /* 100 x intensity / the crystal's largest over both lines (0 if that is 0) */
+    int32_t *mult;         /* member reflections of the peak */
+    double *d;             /* interplanar spacing 1 / sqrt(q) of the peak's first member, Angstrom */
+    int32_t *line;         /* 0: line0, 1: line1 */
+    int64_t *source;       /* the peak's index in its line's peak arrays */
+    int64_t *peak_offset;  /* [n_crystals + 1]: the two lines' offsets added */
+} xrd_line_peaks;
+
+/* The calculator's peak list for a doublet (paper, Section 2: the peaks'
+ * 2theta, intensity, interplanar spacing and multiplicity, scaled to 0-100 on
+ * request; the K-alpha1 and K-alpha2 lines are computed as two batches): per
+ * crystal, the peaks of line0 and of line1 (NULL: line0 alone) in one list in
+ * ascending 2theta (at equal 2theta line0's first, each line's own order
+ * kept), intensities weighted, scaled jointly by the crystal's largest
+ * weighted intensity, with d and the source of each peak.  Enqueued on
+ * ``stream`` (hipStream_t; NULL = the null stream).  No workspace. */
+int xrd_combine_lines(int64_t n_crystals, const xrd_line *line0, const xrd_line *line1, xrd_line_peaks *out,
+                      void *stream);
+
 /* Broadened pattern y [n_crystals * n_points] with widths that grow with
  * angle (Caglioti, Paoletti and Ricci, Nucl. Instrum. 3 (1958) 223) and
  * pseudo-Voigt profiles (paper, Section 1: peak broadening among the

@@ -19,7 +19,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libxrd.so")
 RATES = os.path.join(HERE, "xrd_rates")  # instruction-rate microbenchmark program
 SOURCES = ["api.cpp", "scan.hip", "enumerate.hip", "sf.hip", "sortmerge.hip", "broaden.hip", "augment.hip", "family.hip",
-           "noalloc.hip", "sfrec.hip"]
+           "noalloc.hip", "sfrec.hip", "lines.hip"]
 ARCH = "gfx950"
 
 

@@ -58,6 +58,15 @@ class xrd_peaks(C.Structure):
                 ("perm", _vp), ("peak_offset", _vp)]
 
 
+class xrd_line(C.Structure):
+    _fields_ = [("peaks", C.POINTER(xrd_peaks)), ("q", _vp), ("weight", C.c_double)]
+
+
+class xrd_line_peaks(C.Structure):
+    _fields_ = [("two_theta", _vp), ("intensity", _vp), ("scaled", _vp), ("mult", _vp), ("d", _vp), ("line", _vp),
+                ("source", _vp), ("peak_offset", _vp)]
+
+
 class xrd_grid(C.Structure):
     _fields_ = [("t0", C.c_double), ("dt", C.c_double), ("n_points", C.c_int64), ("sigma", C.c_double),
                 ("window_sigmas", C.c_double)]
@@ -86,6 +95,8 @@ SIGNATURES = {
     "xrd_pattern_backward": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(xrd_grid), _vp, _vp, _vp, _vp], C.c_int),
     "xrd_autotune": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(C.c_int32)], C.c_int),
     "xrd_batch_get_sf_rpt": ([_vp, C.POINTER(C.c_int32)], C.c_int),
+    "xrd_combine_lines": ([C.c_int64, C.POINTER(xrd_line), C.POINTER(xrd_line), C.POINTER(xrd_line_peaks), _vp],
+                          C.c_int),
     "xrd_preferred_orientation": ([_vp, _vp, C.POINTER(xrd_refl), _vp, _vp, _vp], C.c_int),
     "xrd_pattern_noise": ([_vp, C.c_int64, C.c_uint64, C.c_double, C.c_double, _vp], C.c_int),
     "xrd_peak_families": ([_vp, _vp, C.POINTER(xrd_refl), C.POINTER(xrd_peaks), C.c_int32, _vp, _vp, _vp, _vp],
@@ -188,6 +199,12 @@ def xrd_batch_get_sf_rpt(batch) -> int:
     out = C.c_int32(0)
     check(lib().xrd_batch_get_sf_rpt(batch, C.byref(out)))
     return int(out.value)
+
+
+def xrd_combine_lines(n_crystals: int, line0: xrd_line, line1, out: xrd_line_peaks, stream: int):
+    """line1 None: line0 alone."""
+    check(lib().xrd_combine_lines(n_crystals, C.byref(line0), C.byref(line1) if line1 is not None else None,
+                                  C.byref(out), stream))
 
 
 def xrd_preferred_orientation(batch, ws: int, refl: xrd_refl, hp: int, march_r: int, I: int):

@@ -1469,6 +1469,36 @@ int xrd_peak_families(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_peaks
   return hip_check("peak_families");
 }
 
+int xrd_combine_lines(int64_t n_crystals, const xrd_line *line0, const xrd_line *line1, xrd_line_peaks *out,
+                      void *stream) {
+  if (n_crystals < 0) return fail(XRD_ERR_INVALID_ARG, "n_crystals < 0");
+  if (!line0 || !out) return fail(XRD_ERR_INVALID_ARG, "line0 and out must be non-NULL");
+  auto check_line = [](const xrd_line *l) -> int {
+    const xrd_peaks *p = l->peaks;
+    if (!p || !l->q || !p->two_theta || !p->intensity || !p->mult || !p->first || !p->perm || !p->peak_offset)
+      return fail(XRD_ERR_INVALID_ARG, "a line's peak arrays and q must be non-NULL");
+    if (!std::isfinite(l->weight) || l->weight < 0.0) return fail(XRD_ERR_INVALID_ARG, "line weights must be >= 0");
+    return XRD_OK;
+  };
+  if (int e = check_line(line0)) return e;
+  if (line1)
+    if (int e = check_line(line1)) return e;
+  if (!out->two_theta || !out->intensity || !out->scaled || !out->mult || !out->d || !out->line || !out->source ||
+      !out->peak_offset)
+    return fail(XRD_ERR_INVALID_ARG, "output arrays must be non-NULL");
+  auto lp = [](const xrd_line *l) {
+    const xrd_peaks *p = l->peaks;
+    return LinePeaks{p->two_theta, p->intensity, l->q, p->mult, p->first, p->perm, p->peak_offset, l->weight};
+  };
+  const LinePeaks p0 = lp(line0);
+  LinePeaks p1{};
+  if (line1) p1 = lp(line1);
+  const LineOut o{out->two_theta, out->intensity, out->scaled, out->mult,
+                  out->d,         out->line,      out->source, out->peak_offset};
+  launch_combine_lines(n_crystals, p0, line1 ? &p1 : nullptr, o, reinterpret_cast<hipStream_t>(stream));
+  return hip_check("combine_lines");
+}
+
 int xrd_pattern_caglioti(xrd_batch *b, void *ws, const xrd_refl *r, const double *I, const xrd_grid *g, double U,
                          double V, double W, double eta, double *y) {
   if (!b) return fail(XRD_ERR_INVALID_ARG, "batch is NULL");

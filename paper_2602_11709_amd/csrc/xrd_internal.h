@@ -169,6 +169,22 @@ void launch_fill_i32(int32_t *p, int64_t n, int32_t v, hipStream_t s);
 // aligned) on the current device, looked up on the first call per device.
 hipError_t noalloc_scratch(void **out);
 
+// Two emission lines' peaks in one list per crystal (lines.hip).
+struct LinePeaks {
+  const double *two_theta, *intensity, *q;
+  const int32_t *mult;
+  const int64_t *first, *perm, *peak_offset;
+  double weight;
+};
+struct LineOut {
+  double *two_theta, *intensity, *scaled;
+  int32_t *mult;
+  double *d;
+  int32_t *line;
+  int64_t *source, *peak_offset;
+};
+void launch_combine_lines(int64_t n_c, const LinePeaks &p0, const LinePeaks *p1, const LineOut &out, hipStream_t s);
+
 // Families of equivalent reflections per merged peak (rule 0: indices, 1: lattice).
 void launch_peak_families(const HChunk *chunks, int64_t n_chunks, const FamOps *fam_ops, const int64_t *peak_offset,
                           const int64_t *first, const int32_t *mult, const int64_t *perm, const int16_t *h,

@@ -6,8 +6,8 @@ a 2theta range and a ``scaled`` flag, and returns the peaks with their 2theta,
 intensity, hkl lists and multiplicities.  ``get_pattern`` offers that call
 for one structure given as arrays, ``get_patterns`` for a whole
 ``CrystalBatch``; both run on the GPU library (enumeration, structure
-factors, sort and merge).  A wavelength is a number in Angstrom or the name of
-an emission line; a doublet name ("CuKa12", "MoKa12") computes the K-alpha1
+factors, sort and merge, and the combination of the lines' peaks).  A
+wavelength is a number in Angstrom or the name of an emission line; a doublet name ("CuKa12", "MoKa12") computes the K-alpha1
 and K-alpha2 lines separately, weights K-alpha2 by ``KA2_RATIO`` and lists the
 peaks of both lines in one 2theta-ordered pattern, scaled together.
 ``broadened_pattern`` does the same on a grid (the sum of the two lines'
@@ -113,45 +113,81 @@ def _label(hkl, hexagonal: bool):
     return (h, k, -(h + k), l) if hexagonal else (h, k, l)
 
 
+def _line_peaks(batch: CrystalBatch, lam: float, precision: str, device, rule: int):
+    """One emission line on the GPU: enumeration, structure factors, merge and
+    families; the batch, its reflections, peaks and families (device)."""
+    from .api import XrdBatch
+    xb = XrdBatch(dataclasses.replace(batch, wavelength=lam), precision=precision, device=device,
+                  forward_only=True)
+    refl = xb.enumerate()
+    _, _, I = xb.structure_factors(refl)
+    pk = xb.merge(refl, I)
+    fam = xb.families(refl, pk, rule)
+    return xb, refl, pk, fam
+
+
 def get_patterns(batch: CrystalBatch, wavelength: Union[float, str] = "CuKa", scaled: bool = True,
                  precision: str = "mixed", device="cuda", family_rule: str = "indices") -> list:
     """Peaks of every crystal of ``batch`` (its own wavelength is replaced by
-    ``wavelength``), one DiffractionPattern per crystal."""
-    from .api import simulate
+    ``wavelength``), one DiffractionPattern per crystal.  The lines' peaks are
+    combined on the GPU (xrd_combine_lines: weights, joint 0-100 scale,
+    interplanar spacings); the host only gathers each peak's hkl lists."""
+    import ctypes
+    import torch
+    from . import capi
     if family_rule not in FAMILY_RULES:
         raise ValueError(f"family_rule must be one of {sorted(FAMILY_RULES)}")
-    parts = []
-    for lam, weight, label in lines_of(wavelength):
-        res = simulate(dataclasses.replace(batch, wavelength=lam), precision=precision, device=device,
-                       family_rule=FAMILY_RULES[family_rule])
-        parts.append((res, weight, label))
-    out = []
-    for c in range(batch.n_crystals):
+    lines = lines_of(wavelength)
+    runs = [_line_peaks(batch, lam, precision, device, FAMILY_RULES[family_rule]) for lam, _, _ in lines]
+    n_c = batch.n_crystals
+    dev = runs[0][0].device
+    cap = max(sum(xb.refl_capacity for xb, _, _, _ in runs), 1)
+    e = lambda dt: torch.empty(cap, dtype=dt, device=dev)
+    out_t = dict(two_theta=e(torch.float64), intensity=e(torch.float64), scaled=e(torch.float64),
+                 mult=e(torch.int32), d=e(torch.float64), line=e(torch.int32), source=e(torch.int64),
+                 peak_offset=torch.empty(n_c + 1, dtype=torch.int64, device=dev))
+    out = capi.xrd_line_peaks(*(out_t[k].data_ptr() for k in ("two_theta", "intensity", "scaled", "mult", "d",
+                                                               "line", "source", "peak_offset")))
+    pks = [pk.c() for _, _, pk, _ in runs]  # kept alive across the call
+    ln = [capi.xrd_line(ctypes.pointer(pc), refl.q.data_ptr(), float(w))
+          for pc, (_, refl, _, _), (_, w, _) in zip(pks, runs, lines)]
+    stream = runs[0][0].stream
+    for xb, _, _, _ in runs[1:]:
+        stream.wait_stream(xb.stream)
+    with torch.cuda.stream(stream):
+        capi.xrd_combine_lines(n_c, ln[0], ln[1] if len(ln) > 1 else None, out, stream.cuda_stream)
+    torch.cuda.synchronize(dev)
+    po = out_t["peak_offset"].cpu().numpy()
+    m = int(po[-1])
+    host = {k: out_t[k][:m].cpu().numpy() for k in ("two_theta", "intensity", "scaled", "mult", "d", "line",
+                                                    "source")}
+    # per line, what the hkl lists need: members (perm), indices and families
+    per_line = []
+    for xb, refl, pk, fam in runs:
+        ro, lpo = xb.read_counts(refl, pk)
+        n, mp = int(ro[-1]), int(lpo[-1])
+        cpu = lambda t, k: t[:k].cpu().numpy()
+        hkl = np.stack([cpu(refl.h, n), cpu(refl.k, n), cpu(refl.l, n)], axis=1).astype(np.int32)
+        per_line.append(dict(hkl=hkl, perm=cpu(pk.perm, n), first=cpu(pk.first, mp), mult=cpu(pk.mult, mp),
+                             fam_n=cpu(fam[0], mp), fam_label=cpu(fam[2], n), fam_mult=cpu(fam[3], n)))
+    labels = np.array([label for _, _, label in lines])
+    y_all = host["scaled"] if scaled else host["intensity"]
+    result = []
+    for c in range(n_c):
+        p0, p1 = int(po[c]), int(po[c + 1])
         hexagonal = is_hexagonal(batch.lattice[c])
-        xs, ys, ms, ds, hk, fm, ls = [], [], [], [], [], [], []
-        for res, weight, label in parts:
-            rs, ps = res.crystal(c)
-            tt = res.pk_two_theta[ps]
-            xs.append(tt)
-            ys.append(weight * res.pk_intensity[ps])
-            ms.append(res.pk_mult[ps])
-            ls.append(np.full(len(tt), label))
-            for f, m, nf in zip(res.pk_first[ps], res.pk_mult[ps], res.fam_n[ps]):
-                members = res.perm[f:f + m]
-                hk.append([tuple(int(v) for v in res.hkl[i]) for i in members])
-                fm.append([{"hkl": _label(res.hkl[res.fam_label[f + j]], hexagonal),
-                            "multiplicity": int(res.fam_mult[f + j])} for j in range(nf)])
-                ds.append(1.0 / np.sqrt(res.q[members[0]]))
-        x = np.concatenate(xs) if xs else np.zeros(0)
-        order = np.argsort(x, kind="stable")
-        y = np.concatenate(ys)[order]
-        if scaled and len(y) and y.max() > 0:
-            y = 100.0 * y / y.max()
-        out.append(DiffractionPattern(x=x[order], y=y, mult=np.concatenate(ms)[order],
-                                      d_hkls=np.asarray(ds, dtype=np.float64)[order] if ds else np.zeros(0),
-                                      hkls=[fm[i] for i in order], line=np.concatenate(ls)[order],
-                                      members=[hk[i] for i in order]))
-    return out
+        hk, fm = [], []
+        for li, src in zip(host["line"][p0:p1], host["source"][p0:p1]):
+            L = per_line[li]
+            f, mlt, nf = int(L["first"][src]), int(L["mult"][src]), int(L["fam_n"][src])
+            members = L["perm"][f:f + mlt]
+            hk.append([tuple(int(v) for v in L["hkl"][i]) for i in members])
+            fm.append([{"hkl": _label(L["hkl"][L["fam_label"][f + j]], hexagonal),
+                        "multiplicity": int(L["fam_mult"][f + j])} for j in range(nf)])
+        result.append(DiffractionPattern(x=host["two_theta"][p0:p1].copy(), y=y_all[p0:p1].copy(),
+                                         mult=host["mult"][p0:p1].copy(), d_hkls=host["d"][p0:p1].copy(),
+                                         hkls=fm, line=labels[host["line"][p0:p1]], members=hk))
+    return result
 
 
 def get_pattern(lattice, frac, species, sf_coeff, occ=None, bfac=None, wavelength: Union[float, str] = "CuKa",

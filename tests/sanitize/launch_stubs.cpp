@@ -36,6 +36,9 @@ void launch_sf(bool, bool, const SfItem *, int64_t, int64_t, const CrystalPlan *
 }
 void launch_sf_rec(bool, bool, const SfRecArgs &, void *, void *, double *, void *, hipStream_t) { reached("sf_rec"); }
 void launch_sort(const SortArgs &, hipStream_t) { reached("sort"); }
+void launch_combine_lines(int64_t, const LinePeaks &, const LinePeaks *, const LineOut &, hipStream_t) {
+  reached("combine_lines");
+}
 void launch_merge(const MergeArgs &, hipStream_t) { reached("merge"); }
 void launch_broaden_fwd(bool, const HChunk *, int64_t, const CrystalPlan *, const int32_t *, int64_t, bool,
                         const int64_t *, const double *, const int32_t *, const double *, double, double, int64_t,

@@ -268,6 +268,17 @@ def test_tile_shape_is_validated_and_reported():
         assert ei.value.code == capi.XRD_ERR_INVALID_ARG
 
 
+def test_combine_lines_rejects_bad_arguments():
+    """Missing arrays or a negative weight are refused before any launch."""
+    out = capi.xrd_line_peaks()
+    with pytest.raises(capi.XrdError) as ei:
+        capi.xrd_combine_lines(1, capi.xrd_line(), None, out, 0)
+    assert ei.value.code == capi.XRD_ERR_INVALID_ARG
+    with pytest.raises(capi.XrdError) as ei:
+        capi.xrd_combine_lines(-1, capi.xrd_line(), None, out, 0)
+    assert ei.value.code == capi.XRD_ERR_INVALID_ARG
+
+
 def test_set_lattice_validates_before_any_device_work():
     """A cell needing a larger search box, or an invalid cell, is refused
     before anything is copied (host only)."""
