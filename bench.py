@@ -588,6 +588,27 @@ def rates_live():
         return None
 
 
+def frontend_rate(batch, n=128):
+    """The calculator front-end (get_patterns, Cu K-alpha1 + K-alpha2, families
+    by indices) on the workload's first n crystals: whole calls, wall time,
+    including planning both lines, the device work, the lines' combination on
+    the device and the host's per-peak hkl lists (Python objects); best of 3."""
+    import time as _t
+    import torch
+    from paper_2602_11709_amd import frontend
+    sub = batch.subset(range(min(n, batch.n_crystals)))
+    best, peaks = float("inf"), 0
+    for _ in range(3):
+        torch.cuda.synchronize()
+        t0 = _t.perf_counter()
+        pats = frontend.get_patterns(sub, "CuKa12")
+        best = min(best, _t.perf_counter() - t0)
+        peaks = sum(len(p.x) for p in pats)
+    return {"crystals": sub.n_crystals, "peaks": peaks, "s": round(best, 4),
+            "patterns_per_s": round(sub.n_crystals / best, 1), "peaks_per_s": round(peaks / best, 1),
+            "call": "frontend.get_patterns(first crystals of the workload, 'CuKa12'): wall time of whole calls"}
+
+
 def doublet_ms(batch, reps=20):
     """Forward patterns (peaks and the broadened pattern) of the workload under
     Cu K-alpha1 and K-alpha2 (two lines of the calculator front-end): both
@@ -846,6 +867,7 @@ def main():
     mx = res["mixed"]
     n_c = batch.n_crystals
     dbl_ms = None if args.no_doublet else doublet_ms(batch)
+    front = None if args.no_doublet else frontend_rate(batch)
     fam = families_ms(mx["p"])
     value = n_c / (mx["ms"] * 1e-3)
     eval_terms = mx["eval_terms"]
@@ -891,6 +913,7 @@ def main():
         "host_plan_ms": round(mx["p"].xb.plan_ms, 3),
         "batch_setup_ms": round(mx["p"].plan_ms, 3),
         "peak_families": fam,
+        "frontend": front,
         "kalpha_doublet": None if dbl_ms is None else {
             "ms_per_step": round(dbl_ms, 6), "patterns_per_s": round(n_c / (dbl_ms * 1e-3), 1),
             "step": "Cu K-alpha1 + K-alpha2: enumerate, structure factors, merge, 4001-point pattern per line "

@@ -4,10 +4,11 @@
 // K-alpha1/K-alpha2 doublet is computed as two lines whose peaks are listed
 // side by side and scaled together).
 //
-// One block per crystal.  Each line's peaks are already in ascending 2theta,
-// so a peak's slot in the combined list is its index in its own list plus the
-// number of the other line's peaks before it (binary search; at equal 2theta
-// the first line's peaks come first).  The crystal's combined offset is the
+// kSplit blocks per crystal (each takes every kSplit-th stretch of kThreads
+// peaks and computes the crystal's maximum itself).  Each line's peaks are
+// already in ascending 2theta, so a peak's slot in the combined list is its
+// index in its own list plus the number of the other line's peaks before it
+// (binary search; at equal 2theta the first line's peaks come first).  The crystal's combined offset is the
 // sum of the two lines' offsets, so no scan is needed.
 #include <math.h>
 
@@ -18,6 +19,7 @@ namespace xrd {
 namespace {
 
 constexpr int kThreads = 256;
+constexpr int kSplit = 8;  // blocks per crystal
 
 // Number of elements of the ascending a[0, n) below t (strict) or at most t.
 template <bool INCLUSIVE>
@@ -44,7 +46,7 @@ struct LineIn {
 __device__ void place_line(const LineIn &me, const LineIn &other, bool second, int64_t a, int64_t b, int64_t oa,
                            int64_t ob, int64_t o, double mx, int line, const LineOut &out) {
   const int64_t n_other = ob - oa;
-  for (int64_t i = a + threadIdx.x; i < b; i += kThreads) {
+  for (int64_t i = a + (int64_t)blockIdx.y * kThreads + threadIdx.x; i < b; i += (int64_t)kSplit * kThreads) {
     const double t = me.tt[i];
     // the first line's peaks precede the second's at equal 2theta
     const int64_t r = second ? rank_in<true>(other.tt + oa, n_other, t) : rank_in<false>(other.tt + oa, n_other, t);
@@ -79,7 +81,7 @@ __global__ __launch_bounds__(kThreads) void k_combine_lines(int64_t n_c, LineIn 
   const int64_t o = a0 + a1;
   place_line(l0, l1, false, a0, b0, a1, b1, o, mx, 0, out);
   if (two) place_line(l1, l0, true, a1, b1, a0, b0, o, mx, 1, out);
-  if (threadIdx.x == 0) {
+  if (threadIdx.x == 0 && blockIdx.y == 0) {
     out.peak_offset[c] = o;
     if (c == n_c - 1) out.peak_offset[n_c] = l0.offset[n_c] + (two ? l1.offset[n_c] : 0);
   }
@@ -107,7 +109,8 @@ void launch_combine_lines(int64_t n_c, const LinePeaks &p0, const LinePeaks *p1,
   }
   const LineIn l0 = line_in(p0);
   const LineIn l1 = p1 ? line_in(*p1) : l0;
-  hipLaunchKernelGGL(k_combine_lines, dim3((unsigned)n_c), dim3(kThreads), 0, s, n_c, l0, l1, p1 != nullptr, out);
+  hipLaunchKernelGGL(k_combine_lines, dim3((unsigned)n_c, kSplit), dim3(kThreads), 0, s, n_c, l0, l1, p1 != nullptr,
+                     out);
 }
 
 }  // namespace xrd
