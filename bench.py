@@ -876,7 +876,7 @@ def main():
     # the other long kernels of the step, timed per launch from the profiler's
     # kernel records over eager steps
     kus = kernel_device_us(torch, mx["p"].stream, mx["p"].step, 10,
-                           ["k_sf<", "k_sf_bw<", "k_broaden_gather<", "k_broaden_adj<", "k_sort_crystal<",
+                           ["k_sf<", "k_sf_bw<", "k_broaden_gather<", "k_broaden_adj<", "k_sort_merge<",
                             "k_peak_move", "k_peak_scan", "k_enum_fill", "k_enum_count", "k_enum_scan1",
                             "k_entry_prep<", "k_bw_finish"])
     pairs = entry_window_pairs(mx["p"])
@@ -944,7 +944,8 @@ def main():
                 "k_broaden_gather", pairs, kus["k_broaden_gather<"], "pair",
                 "profiler kernel records, 10 eager steps; pairs = grid points within 8 sigma of each evaluated "
                 "reflection"),
-            "merge": {"kernels": "k_sort_crystal (4 size classes, concurrent) + k_peak_scan + k_peak_move",
+            "merge": {"kernels": "k_sort_merge (one launch for every crystal) + k_peak_move (numbering included "
+                                 "up to 4096 crystals)",
                       "bound": "hbm", "achieved": round(merge_bytes / (mx["stages"]["merge"] * 1e-3) / 1e9, 1),
                       "peak": 8000.0, "unit": "GB/s",
                       "frac": round(merge_bytes / (mx["stages"]["merge"] * 1e-3) / 8e12, 4),
