@@ -648,6 +648,21 @@ __global__ __launch_bounds__(kThreads) void k_peak_move(const HChunk *__restrict
   const int np = mo.pk_count[c];
   const int64_t r0 = refl_offset[c];
   const double mx = __longlong_as_double((long long)mo.cmax[c]);
+  // the chunk's staged peaks, loaded before the offset is known, so that their
+  // latency overlaps the prefix sum's
+  double tt[kPer], iv[kPer];
+  int32_t m[kPer];
+  int64_t f[kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const int64_t k = k0 + u * kThreads + threadIdx.x;
+    if (k < np) {
+      tt[u] = mo.t_tt[r0 + k];
+      iv[u] = mo.t_i[r0 + k];
+      m[u] = mo.t_mult[r0 + k];
+      f[u] = mo.t_first[r0 + k];
+    }
+  }
   int64_t o;
   if (prefix) {
     int64_t part = 0;
@@ -663,17 +678,15 @@ __global__ __launch_bounds__(kThreads) void k_peak_move(const HChunk *__restrict
   } else {
     o = peak_offset[c];
   }
-  if (k0 >= np) return;
 #pragma unroll
   for (int u = 0; u < kPer; ++u) {
     const int64_t k = k0 + u * kThreads + threadIdx.x;
     if (k < np) {
-      const double v = mo.t_i[r0 + k];
-      pk_tt[o + k] = mo.t_tt[r0 + k];
-      pk_i[o + k] = v;
-      pk_y[o + k] = mx > 0.0 ? 100.0 * v / mx : 0.0;
-      pk_mult[o + k] = mo.t_mult[r0 + k];
-      pk_first[o + k] = mo.t_first[r0 + k];
+      pk_tt[o + k] = tt[u];
+      pk_i[o + k] = iv[u];
+      pk_y[o + k] = mx > 0.0 ? 100.0 * iv[u] / mx : 0.0;
+      pk_mult[o + k] = m[u];
+      pk_first[o + k] = f[u];
     }
   }
 }
