@@ -142,8 +142,9 @@ __device__ __forceinline__ double lp_of_q(double q, double lambda) {
 // The structure-factor kernels read each crystal's atoms grouped by species
 // (so that the scattering factor is evaluated once per species and
 // reflection), as 48-byte records.  One wavefront packs one crystal: species
-// histogram in LDS, ascending-species runs, then a stable scatter (peeling one
-// species per step with a ballot).  The wavefront works alone: it orders its
+// histogram in LDS, ascending-species runs, then a stable scatter (an atom's
+// slot is its species cursor plus the lanes of its species below it, the
+// lanes of a species found by ballots over the species bits).  The wavefront works alone: it orders its
 // LDS accesses with wavefront-scope fences, so several crystals can share a
 // block.  The wavefront of crystal 0 also writes the single-precision
 // coefficient table of the mixed path.
@@ -154,6 +155,42 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Lanes of the wavefront holding the same species as this one (among the
+// active lanes), by one ballot per bit that tells the species apart.
+__device__ __forceinline__ uint64_t same_species(bool active, int sp, int nbits) {
+  uint64_t m = __ballot(active);
+  for (int b = 0; b < nbits; ++b) {
+    const bool bit = (sp >> b) & 1;
+    const uint64_t bal = __ballot(active && bit);
+    m &= bit ? bal : ~bal;
+  }
+  return m;
+}
+
+__device__ __forceinline__ int lanes_below(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+struct AtomIn {
+  int sp;
+  double x, y, z, occ, bfac;
+};
+
+__device__ __forceinline__ AtomIn load_atom(int64_t j, int64_t a1, const double *__restrict__ frac,
+                                            const int32_t *__restrict__ species, const double *__restrict__ occ,
+                                            const double *__restrict__ bfac) {
+  AtomIn r{-1, 0.0, 0.0, 0.0, 1.0, 0.0};
+  if (j < a1) {
+    r.sp = species[j];
+    r.x = frac[3 * j];
+    r.y = frac[3 * j + 1];
+    r.z = frac[3 * j + 2];
+    r.occ = occ[j];
+    r.bfac = bfac[j];
+  }
+  return r;
 }
 
 __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan *__restrict__ plan,
@@ -181,17 +218,29 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
   }
   const CrystalPlan &P = plan[c];
   const int64_t a0 = P.atom_begin, a1 = P.atom_end;
+  const int nbits = n_species > 1 ? 32 - __builtin_clz((uint32_t)(n_species - 1)) : 0;
   for (int t = lane; t < n_species; t += 64) cursor[t] = 0;
   wave_sync();
-  for (int64_t j = a0 + lane; j < a1; j += 64) {
-    int sp = species[j];
-    if (sp < 0 || sp >= n_species) {
-      atomicOr(err, 1);
-      sp = 0;
+  // species histogram: the lowest lane of each species group adds its size
+  for (int64_t base = a0; base < a1; base += 256) {
+    int sp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int64_t j = base + 64 * u + lane;
+      sp[u] = j < a1 ? species[j] : 0;
     }
-    atomicAdd(&cursor[sp], 1);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const bool active = base + 64 * u + lane < a1;
+      if (active && (sp[u] < 0 || sp[u] >= n_species)) {
+        atomicOr(err, 1);
+        sp[u] = 0;
+      }
+      const uint64_t m = same_species(active, sp[u], nbits);
+      if (active && lanes_below(m) == 0) cursor[sp[u]] += __popcll(m);
+      wave_sync();
+    }
   }
-  wave_sync();
   // ascending-species runs and cursors (exclusive scan of the histogram)
   int64_t running = a0;
   int nruns = 0;
@@ -206,7 +255,7 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
     }
     const int tot = __shfl(inc, 63, 64);
     const uint64_t nz = __ballot(v > 0);
-    const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(nz >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)nz, 0u));
+    const int rank = lanes_below(nz);
     const int64_t start = running + inc - v;
     if (v > 0) {
       SpeciesRun r;
@@ -222,22 +271,23 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
     nruns += __popcll(nz);
   }
   if (lane == 0) run_count[c] = nruns;
+  // scatter in input order within each species: an atom's slot is its
+  // species cursor plus the lanes of its species below it; the next 64
+  // atoms' records load while these are placed
+  AtomIn in = load_atom(a0 + lane, a1, frac, species, occ, bfac);
   for (int64_t base = a0; base < a1; base += 64) {
     const int64_t j = base + lane;
-    bool active = j < a1;
-    int sp = -1;
+    const AtomIn nx = load_atom(j + 64, a1, frac, species, occ, bfac);
+    const bool active = j < a1;
+    const int sp = active ? (in.sp < 0 || in.sp >= n_species ? 0 : in.sp) : 0;
     AtomRec a{};
     AtomRot z{};
     if (active) {
-      // the atom's record is read before the species peeling, whose steps
-      // then wait on LDS only
-      sp = species[j];
-      if (sp < 0 || sp >= n_species) sp = 0;
-      a.x = frac[3 * j];
-      a.y = frac[3 * j + 1];
-      a.z = frac[3 * j + 2];
-      a.occ = occ[j];
-      a.bfac = bfac[j];
+      a.x = in.x;
+      a.y = in.y;
+      a.z = in.z;
+      a.occ = in.occ;
+      a.bfac = in.bfac;
       a.log2occ = __log2f((float)a.occ);
       a.bl2e = (float)a.bfac * kLog2e;
       // the row recurrence's factors: e^{2 pi i z} and e^{-B G*33 / 2}
@@ -247,25 +297,18 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
       z.zsf = (float)z.zs;
       z.rhof = (float)z.rho;
     }
-    while (true) {
-      const uint64_t act = __ballot(active);
-      if (act == 0) break;
-      const int leader = __builtin_ctzll(act);
-      const int t = __shfl(sp, leader, 64);
-      const uint64_t m = __ballot(active && sp == t);
-      const int base_pos = cursor[t];
-      wave_sync();
-      if (active && sp == t) {
-        const int rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-        const int pos = base_pos + rank;
-        atoms[pos] = a;
-        rot[pos] = z;
-        orig[pos] = (int32_t)j;
-        active = false;
-      }
-      if (lane == leader) cursor[t] = base_pos + __popcll(m);
-      wave_sync();
+    const uint64_t m = same_species(active, sp, nbits);
+    const int below = lanes_below(m);
+    const int pos = active ? cursor[sp] + below : 0;
+    wave_sync();
+    if (active) {
+      if (below == 0) cursor[sp] = pos + __popcll(m);
+      atoms[pos] = a;
+      rot[pos] = z;
+      orig[pos] = (int32_t)j;
     }
+    wave_sync();
+    in = nx;
   }
 }
 
@@ -293,25 +336,27 @@ __global__ __launch_bounds__(64) void k_atom_pack(const CrystalPlan *__restrict_
 }
 
 // Survivor count per enumeration chunk (at most kEnumRows rows), one
-// wavefront per chunk (lane = row), four chunks per block.  The launch also packs the
-// atoms (independent work) when pack is set: blocks from chunk_blocks on
-// take four crystals each, one per wavefront, with n_species LDS cursors per
-// wavefront.
+// wavefront per chunk (lane = row), four chunks per block.  The launch also
+// packs the atoms (independent work) when its grid holds more blocks than
+// the chunks need: the first blocks take four crystals each, one per
+// wavefront, with n_species LDS cursors per wavefront; they come first so
+// that their serial chains start with the counts rather than after them.
 __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__restrict__ plan,
                                                          const EnumChunk *__restrict__ chunks,
                                                          int64_t n_chunks, int64_t n_c, double lambda,
                                                          int32_t *__restrict__ counts, PackArgs pa) {
   const int64_t chunk_blocks = (n_chunks + kThreads / 64 - 1) / (kThreads / 64);
+  const int64_t pack_blocks = (int64_t)gridDim.x - chunk_blocks;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-  if (blockIdx.x >= chunk_blocks) {
+  if (blockIdx.x < pack_blocks) {
     extern __shared__ int32_t cursors[];  // 4 x n_species
-    const int64_t c = (int64_t)(blockIdx.x - chunk_blocks) * (kThreads / 64) + wid;
+    const int64_t c = (int64_t)blockIdx.x * (kThreads / 64) + wid;
     if (c < n_c)
       pack_crystal((int)c, lane, cursors + wid * pa.n_species, plan, pa.n_species, pa.frac, pa.species, pa.occ,
                    pa.bfac, pa.coeff, pa.coeff_f, pa.atoms, pa.rot, pa.orig, pa.runs, pa.run_count, pa.err);
     return;
   }
-  const int64_t chunk = (int64_t)blockIdx.x * (kThreads / 64) + wid;
+  const int64_t chunk = (int64_t)(blockIdx.x - pack_blocks) * (kThreads / 64) + wid;
   if (chunk >= n_chunks) return;
   const EnumChunk ch = chunks[chunk];
   const CrystalPlan &P = plan[ch.crystal];
