@@ -34,6 +34,7 @@ struct xrd_batch {
   std::vector<HChunk> eblocks;  // entry blocks of the broadening (crystal, block of kEntBlock entries)
   std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
   std::vector<int32_t> sort_items;     // the sort launch's two crystal lists (n_small + n_crystals)
+  std::vector<BigChunk> big_chunks, big_crystals;  // the many-block sort's chunks and crystals
   std::vector<int32_t> sf_order;   // crystals by descending atom count
   std::vector<int32_t> sf_likely;  // per crystal: tiles its expected reflection count fills
   std::vector<SfItem> sf_items, sf_items_bw;  // launch orders of the forward sum and the adjoint
@@ -650,6 +651,18 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
       if (fr * expect_eval[c] <= 2 * kTinySort) b->sort_items.push_back(c);
     for (int32_t c : by_expect)
       if (fr * expect_eval[c] > 2 * kTinySort) b->sort_items.push_back(c);
+    // crystals of capacity above kBigSort, expected-heaviest first, with
+    // every chunk of their capacity
+    b->big_chunks.clear();
+    b->big_crystals.clear();
+    int32_t first = 0;
+    for (int32_t c : by_expect) {
+      if (2 * b->plan[c].half_box <= kBigSort) continue;
+      const int32_t n = (int32_t)ceil_div(2 * b->plan[c].half_box, kBigChunk);
+      b->big_crystals.push_back(BigChunk{c, 0, first, n});
+      for (int32_t k = 0; k < n; ++k) b->big_chunks.push_back(BigChunk{c, k, first, n});
+      first += n;
+    }
   }
   // peak chunks: a crystal's peaks are about half its reflections (mates share 2theta)
   {
@@ -765,6 +778,12 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.tmp_mult = take(4 * rc);
   L.tmp_first = take(8 * rc);
   L.sort_items = take(4 * (b->n_small + nc));
+  const int64_t nbc = (int64_t)b->big_chunks.size(), nbig = (int64_t)b->big_crystals.size();
+  L.big_chunks = take((int64_t)sizeof(BigChunk) * nbc);
+  L.big_crystals = take((int64_t)sizeof(BigChunk) * nbig);
+  L.big_cnt = take(4 * 3 * nbc);
+  L.big_off = take(8 * 3 * nbc);
+  L.big_np = take(4 * nc);
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(ec, bins), rc);
   L.scan_part = take(8 * scan_part_elems(scan_n));
   L.bw_w1 = L.bw_w2 = L.bw_ga = L.bw_gb = L.bw_dq = L.bw_part = L.bw_partf = L.bw_part6 = -1;
@@ -818,6 +837,11 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     M.tmp_mult = take(4 * rc);
     M.tmp_first = take(8 * rc);
     M.sort_items = take(4 * (b->n_small + nc));
+    M.big_chunks = take((int64_t)sizeof(BigChunk) * nbc);
+    M.big_crystals = take((int64_t)sizeof(BigChunk) * nbig);
+    M.big_cnt = take(4 * 3 * nbc);
+    M.big_off = take(8 * 3 * nbc);
+    M.big_np = take(4 * nc);
     M.total = o;
   }
   *out = b;
@@ -901,6 +925,8 @@ int xrd_batch_upload(xrd_batch *b, void *ws) {
   if (e == hipSuccess) e = up(L.eblocks, b->eblocks.data(), sizeof(HChunk) * b->eblocks.size());
   if (e == hipSuccess) e = up(L.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
   if (e == hipSuccess) e = up(L.sort_items, b->sort_items.data(), 4 * b->sort_items.size());
+  if (e == hipSuccess) e = up(L.big_chunks, b->big_chunks.data(), sizeof(BigChunk) * b->big_chunks.size());
+  if (e == hipSuccess) e = up(L.big_crystals, b->big_crystals.data(), sizeof(BigChunk) * b->big_crystals.size());
   if (e == hipSuccess) e = up(L.bw_items, b->bw_items.data(), sizeof(BwItem) * b->bw_items.size());
   if (e == hipSuccess) e = up(L.ab_items, b->ab_items.data(), sizeof(AbItem) * b->ab_items.size());
   if (e == hipSuccess) e = up(L.fam_ops, b->fam_ops.data(), sizeof(FamOps) * b->fam_ops.size());
@@ -1088,6 +1114,13 @@ static SortArgs sort_args(xrd_batch *b, void *ws, const WsLayout &L, const xrd_r
   a.friedel = b->desc.friedel != 0 ? 1 : 0;
   a.ent_key = at<double>(ws, L.ent_key);
   a.ent_idx = at<int32_t>(ws, L.ent_idx);
+  a.big_chunks = at<BigChunk>(ws, L.big_chunks);
+  a.n_big_chunks = (int64_t)b->big_chunks.size();
+  a.big_crystals = at<BigChunk>(ws, L.big_crystals);
+  a.n_big = (int64_t)b->big_crystals.size();
+  a.big_cnt = at<int32_t>(ws, L.big_cnt);
+  a.big_off = at<int64_t>(ws, L.big_off);
+  a.big_np = at<int32_t>(ws, L.big_np);
   return a;
 }
 
@@ -1161,6 +1194,8 @@ int xrd_merge_peaks_noalloc(xrd_batch *b, const xrd_refl *r, const double *I, xr
   if (e == hipSuccess) e = up(M.peak_chunks, b->peak_chunks.data(), sizeof(HChunk) * b->peak_chunks.size());
   if (e == hipSuccess) e = up(M.crystal_order, b->crystal_order.data(), 4 * b->crystal_order.size());
   if (e == hipSuccess) e = up(M.sort_items, b->sort_items.data(), 4 * b->sort_items.size());
+  if (e == hipSuccess) e = up(M.big_chunks, b->big_chunks.data(), sizeof(BigChunk) * b->big_chunks.size());
+  if (e == hipSuccess) e = up(M.big_crystals, b->big_crystals.data(), sizeof(BigChunk) * b->big_crystals.size());
   if (e != hipSuccess) return fail(XRD_ERR_HIP, std::string("scratch tables: ") + hipGetErrorString(e));
   launch_merge(merge_args(b, sp, M, r, I, p), s);
   // the sorted order went to the scratch, which later calls may overwrite

@@ -590,7 +590,13 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
       gA[u] = gB[u] = dqv[u] = 0.0;
       if (!valid[u]) continue;
       const int64_t i = idx[u];
-      const double q = qq[i], lp = lpp[i];
+      const double lp = lpp[i];
+      const double gI = m * w1[i];
+      gA[u] = 2.0 * lp * A[u] * gI;
+      gB[u] = 2.0 * lp * B[u] * gI;
+      // the other parts of a split item need gA and gB alone
+      if (ww.part != 0) continue;
+      const double q = qq[i];
       const double us = 0.25 * l2 * q;  // sin^2(theta)
       const double sq = sqrt(1.0 - us);
       const double num = 1.0 + (1.0 - 2.0 * us) * (1.0 - 2.0 * us);
@@ -600,10 +606,6 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
       const double dlp_dq = (dnum * den - num * dden) / (den * den) * (0.25 * l2);
       const double dtt_dq = (360.0 / 3.14159265358979323846) * lambda / (4.0 * sqrt(q) * sq);
       const double f2 = A[u] * A[u] + B[u] * B[u];
-      const double gI = m * w1[i];
-      gA[u] = 2.0 * lp * A[u] * gI;
-      gB[u] = 2.0 * lp * B[u] * gI;
-      if (ww.part != 0) continue;
       if (!P.fused) {
         ga[i] = gA[u];
         gb[i] = gB[u];
@@ -642,91 +644,113 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
     //   (sum h P, sum k P, sum l P, sum s^2 Q),  P = w (gB cos - gA sin),
     //   Q = w (gA cos + gB sin),  w = occ f e^{-B s^2}.
     double4 *out = part_fused + P.pf_begin + (int64_t)tile * (P.atom_end - P.atom_begin);
+    if constexpr (MIXED) {
+      float hf[R], kf[R], lf[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        hf[u] = (float)h[u];
+        kf[u] = (float)k[u];
+        lf[u] = (float)l[u];
+      }
+      // four atoms per round over the wavefront's whole range, across species
+      // runs: each atom takes the factors gA f_t, gB f_t of its run, formed
+      // when the walk enters the run.  The records load together and the 16
+      // sums (atom q, component c at index 4q + c) are reduced in one
+      // butterfly; lane 4q + c then writes component c of atom q (records
+      // past the range's end are re-read copies of its last atom and are not
+      // written)
+      int ir = 0, run_end = INT32_MIN;
+      float fA[R], fB[R];
+      for (int j0 = wa; j0 < wb; j0 += 4) {
+        AtomRec a4[4];
+        float fAq[4][R], fBq[4][R];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = min(j0 + q, wb - 1);
+          a4[q] = atoms[j];
+          if (j >= run_end) {
+            while (cr[ir].end <= j) ++ir;
+            const SpeciesRun run = cr[ir];
+            run_end = run.end;
+            const CoeffF cf = coeff_f[run.species];
+#pragma unroll
+            for (int u = 0; u < R; ++u) {
+              const float f = fsc_f32(cf, s2[u]);
+              fA[u] = (float)gA[u] * f;
+              fB[u] = (float)gB[u] * f;
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            fAq[q][u] = fA[u];
+            fBq[q][u] = fB[u];
+          }
+        }
+        float v[16];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const AtomRec &a = a4[q];
+          float sx = 0.f, sy = 0.f, sz = 0.f, sb = 0.f;
+#pragma unroll
+          for (int u = 0; u < R; ++u) {
+            const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+            const float rho = (float)__builtin_amdgcn_fract(t);
+            const float sn = __builtin_amdgcn_sinf(rho);
+            const float cs = __builtin_amdgcn_cosf(rho);
+            const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
+            const float pP = w * (fBq[q][u] * cs - fAq[q][u] * sn);
+            const float pQ = w * (fAq[q][u] * cs + fBq[q][u] * sn);
+            sx = fmaf(hf[u], pP, sx);
+            sy = fmaf(kf[u], pP, sy);
+            sz = fmaf(lf[u], pP, sz);
+            sb = fmaf(s2[u], pQ, sb);
+          }
+          v[4 * q + 0] = sx;
+          v[4 * q + 1] = sy;
+          v[4 * q + 2] = sz;
+          v[4 * q + 3] = sb;
+        }
+        const float tot = wave_reduce16(v, lane);
+        const int vi = wave_reduce16_index(lane), q = vi >> 2;
+        if ((lane & 3) == 0 && j0 + q < wb)
+          reinterpret_cast<double *>(out + (j0 + q - P.atom_begin))[vi & 3] = (double)tot;
+      }
+      return true;
+    }
+    // plain path: one atom at a time per species run, f_t in double
     for (int ir = 0; ir < nr; ++ir) {
       const SpeciesRun run = cr[ir];
       if (max(run.begin, wa) >= min(run.end, wb)) continue;
       const double *c9 = coeff + 9 * run.species;
-      if constexpr (MIXED) {
-        const CoeffF cf = coeff_f[run.species];
-        float f[R], fA[R], fB[R], hf[R], kf[R], lf[R];
+      double f[R], fA[R], fB[R];
+#pragma unroll
+      for (int u = 0; u < R; ++u) {
+        f[u] = fsc_f64(c9, s2d[u]);
+        fA[u] = gA[u] * f[u];
+        fB[u] = gB[u] * f[u];
+      }
+      for (int j = max(run.begin, wa); j < min(run.end, wb); ++j) {
+        const AtomRec a = atoms[j];
+        double sx = 0.0, sy = 0.0, sz = 0.0, sb = 0.0;
 #pragma unroll
         for (int u = 0; u < R; ++u) {
-          f[u] = fsc_f32(cf, s2[u]);
-          fA[u] = (float)gA[u] * f[u];
-          fB[u] = (float)gB[u] * f[u];
-          hf[u] = (float)h[u];
-          kf[u] = (float)k[u];
-          lf[u] = (float)l[u];
+          const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
+          const double rho = t - rint(t);
+          double sn, cs;
+          sincospi(2.0 * rho, &sn, &cs);
+          const double w = a.occ * exp(-a.bfac * s2d[u]);
+          const double pP = w * (fB[u] * cs - fA[u] * sn);
+          const double pQ = w * (fA[u] * cs + fB[u] * sn);
+          sx = fma(h[u], pP, sx);
+          sy = fma(k[u], pP, sy);
+          sz = fma(l[u], pP, sz);
+          sb = fma(s2d[u], pQ, sb);
         }
-        // four atoms per round: their records load together, and the 16 sums
-        // (atom q, component c at index 4q + c) are reduced in one butterfly;
-        // lane 4q + c then writes component c of atom q (records past the
-        // range's end are re-read copies of its last atom and are not written)
-        const int rb = max(run.begin, wa), re = min(run.end, wb);
-        for (int j0 = rb; j0 < re; j0 += 4) {
-          AtomRec a4[4];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) a4[q] = atoms[min(j0 + q, re - 1)];
-          float v[16];
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            const AtomRec &a = a4[q];
-            float sx = 0.f, sy = 0.f, sz = 0.f, sb = 0.f;
-#pragma unroll
-            for (int u = 0; u < R; ++u) {
-              const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
-              const float rho = (float)__builtin_amdgcn_fract(t);
-              const float sn = __builtin_amdgcn_sinf(rho);
-              const float cs = __builtin_amdgcn_cosf(rho);
-              const float w = __builtin_amdgcn_exp2f(fmaf(-a.bl2e, s2[u], a.log2occ));
-              const float pP = w * (fB[u] * cs - fA[u] * sn);
-              const float pQ = w * (fA[u] * cs + fB[u] * sn);
-              sx = fmaf(hf[u], pP, sx);
-              sy = fmaf(kf[u], pP, sy);
-              sz = fmaf(lf[u], pP, sz);
-              sb = fmaf(s2[u], pQ, sb);
-            }
-            v[4 * q + 0] = sx;
-            v[4 * q + 1] = sy;
-            v[4 * q + 2] = sz;
-            v[4 * q + 3] = sb;
-          }
-          const float tot = wave_reduce16(v, lane);
-          const int vi = wave_reduce16_index(lane), q = vi >> 2;
-          if ((lane & 3) == 0 && j0 + q < re)
-            reinterpret_cast<double *>(out + (j0 + q - P.atom_begin))[vi & 3] = (double)tot;
-        }
-      } else {
-        double f[R], fA[R], fB[R];
-#pragma unroll
-        for (int u = 0; u < R; ++u) {
-          f[u] = fsc_f64(c9, s2d[u]);
-          fA[u] = gA[u] * f[u];
-          fB[u] = gB[u] * f[u];
-        }
-        for (int j = max(run.begin, wa); j < min(run.end, wb); ++j) {
-          const AtomRec a = atoms[j];
-          double sx = 0.0, sy = 0.0, sz = 0.0, sb = 0.0;
-#pragma unroll
-          for (int u = 0; u < R; ++u) {
-            const double t = fma(h[u], a.x, fma(k[u], a.y, l[u] * a.z));
-            const double rho = t - rint(t);
-            double sn, cs;
-            sincospi(2.0 * rho, &sn, &cs);
-            const double w = a.occ * exp(-a.bfac * s2d[u]);
-            const double pP = w * (fB[u] * cs - fA[u] * sn);
-            const double pQ = w * (fA[u] * cs + fB[u] * sn);
-            sx = fma(h[u], pP, sx);
-            sy = fma(k[u], pP, sy);
-            sz = fma(l[u], pP, sz);
-            sb = fma(s2d[u], pQ, sb);
-          }
-          sx = wave_sum_to_63(sx);
-          sy = wave_sum_to_63(sy);
-          sz = wave_sum_to_63(sz);
-          sb = wave_sum_to_63(sb);
-          if (lane == 63) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
-        }
+        sx = wave_sum_to_63(sx);
+        sy = wave_sum_to_63(sy);
+        sz = wave_sum_to_63(sz);
+        sb = wave_sum_to_63(sb);
+        if (lane == 63) out[j - P.atom_begin] = make_double4(sx, sy, sz, sb);
       }
     }
     return true;

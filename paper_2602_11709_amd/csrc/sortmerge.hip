@@ -283,6 +283,384 @@ __device__ void sort_global(int64_t c, const CrystalPlan *__restrict__ plan, con
   }
 }
 
+// ---- many-block global-memory sort ------------------------------------------
+//
+// The same sort and merge as sort_global, for crystals of capacity above
+// kBigSort, spread over blocks of kBigChunk reflections, sorted positions or
+// peak slots each, one launch per phase (a phase ends before the next reads
+// its results, so no block waits on another):
+//   clear the bins -> count (global atomics) -> scan the bins per crystal ->
+//   scatter -> order each bin on (2theta, global index) -> peak-start and
+//   entry flags with per-chunk counts -> scan the chunk counts per crystal ->
+//   write the entries and the peaks (each sum in sorted order).
+// With a relative threshold the peaks are staged in the upper half of the
+// crystal's reflection slots (a crystal has at most R/2 peaks: both mates of
+// a Friedel pair share 2theta bit for bit, so every peak holds both), then
+// counted, scanned and compacted to its lower half.  Every result is that of
+// sort_global: the same bins, order, anchor-rule decisions and sums.
+constexpr int kBigThreads = 256;
+constexpr int kBigPer = kBigChunk / kBigThreads;  // 16
+constexpr int kBigBins = kBigChunk / kBinDiv;     // bins cleared and ordered per block
+
+struct BigArgs {
+  const BigChunk *chunks;
+  const CrystalPlan *plan;
+  const int64_t *refl_offset;
+  const double *tt;
+  int32_t *bin_count;
+  int64_t *bin_start;
+  double *skey;
+  int32_t *sidx;
+  double *ent_key;  // null without Friedel pairing
+  int32_t *ent_idx;
+  int32_t *cnt;     // [3 n_big_chunks]: peak starts, entries, kept peaks of a chunk
+  int64_t *off;     // [3 n_big_chunks]: their exclusive scans per crystal
+  int32_t *np;      // [n_c] peaks of a crystal
+};
+
+// The crystal of a chunk, if the many-block sort takes it (more than
+// 2 kMidSort reflections; the others are sorted in LDS by the one-launch sort).
+struct BigUnit {
+  int64_t c, r0, R;
+  int32_t chunk, slot;  // slot: this chunk's index in cnt/off
+  bool live;
+};
+__device__ __forceinline__ BigUnit big_unit(const BigArgs &a, const BigChunk &bc) {
+  BigUnit u;
+  u.c = bc.crystal;
+  u.r0 = a.refl_offset[u.c];
+  u.R = a.refl_offset[u.c + 1] - u.r0;
+  u.chunk = bc.chunk;
+  u.slot = bc.first + bc.chunk;
+  u.live = u.R > 2 * (int64_t)kMidSort;
+  return u;
+}
+
+// Sum of one int per thread over the block; ``red``: kBigThreads / 64 ints.
+__device__ __forceinline__ int big_block_sum(int v, int32_t *red) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  int t = 0;
+#pragma unroll
+  for (int w = 0; w < kBigThreads / 64; ++w) t += red[w];
+  return t;
+}
+
+__global__ __launch_bounds__(kBigThreads) void kb_clear(BigArgs a, uint64_t *__restrict__ cmax) {
+  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
+  if (!u.live) return;
+  const CrystalPlan &P = a.plan[u.c];
+  const int64_t b0 = (int64_t)u.chunk * kBigBins;
+  for (int64_t b = b0 + threadIdx.x; b < min(b0 + kBigBins, (int64_t)P.n_bins); b += kBigThreads)
+    a.bin_count[P.bin_begin + b] = 0;
+  if (u.chunk == 0 && threadIdx.x == 0 && cmax) cmax[u.c] = 0ull;
+}
+
+__global__ __launch_bounds__(kBigThreads) void kb_count(BigArgs a) {
+  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
+  if (!u.live) return;
+  const CrystalPlan &P = a.plan[u.c];
+  const int64_t i0 = (int64_t)u.chunk * kBigChunk;
+  for (int64_t i = i0 + threadIdx.x; i < min(i0 + kBigChunk, u.R); i += kBigThreads)
+    atomicAdd(&a.bin_count[P.bin_begin + bin_of(P, a.tt[u.r0 + i])], 1);
+}
+
+// One 1024-thread block per crystal: bin_start = exclusive scan of the
+// counts, four consecutive bins per thread and round.
+__global__ __launch_bounds__(1024) void kb_scan_bins(BigArgs a, const BigChunk *__restrict__ crystals) {
+  __shared__ int32_t wsum[1024 / 64];
+  const BigUnit u = big_unit(a, crystals[blockIdx.x]);
+  if (!u.live) return;
+  const CrystalPlan &P = a.plan[u.c];
+  const int64_t nb = P.n_bins;
+  const int32_t *__restrict__ bc = a.bin_count + P.bin_begin;
+  int64_t *__restrict__ bs = a.bin_start + P.bin_begin;
+  int64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += 4 * 1024) {
+    const int64_t b = b0 + 4 * (int64_t)threadIdx.x;
+    int v[4], sum = 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      v[q] = b + q < nb ? bc[b + q] : 0;
+      sum += v[q];
+    }
+    int total;
+    int ex = block_exclusive_scan<1024>(sum, wsum, &total);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (b + q < nb) bs[b + q] = carry + ex;
+      ex += v[q];
+    }
+    carry += total;
+  }
+}
+
+__global__ __launch_bounds__(kBigThreads) void kb_scatter(BigArgs a) {
+  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
+  if (!u.live) return;
+  const CrystalPlan &P = a.plan[u.c];
+  int32_t *__restrict__ bc = a.bin_count + P.bin_begin;
+  const int64_t *__restrict__ bs = a.bin_start + P.bin_begin;
+  const int64_t i0 = (int64_t)u.chunk * kBigChunk;
+  for (int64_t i = i0 + threadIdx.x; i < min(i0 + kBigChunk, u.R); i += kBigThreads) {
+    const double t = a.tt[u.r0 + i];
+    const int b = bin_of(P, t);
+    const int64_t slot = u.r0 + bs[b] + atomicSub(&bc[b], 1) - 1;
+    a.skey[slot] = t;
+    a.sidx[slot] = (int32_t)(u.r0 + i);
+  }
+}
+
+// Insertion sort of each bin on (2theta, global index), a bin per thread.
+__global__ __launch_bounds__(kBigThreads) void kb_binsort(BigArgs a) {
+  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
+  if (!u.live) return;
+  const CrystalPlan &P = a.plan[u.c];
+  const int64_t nb = P.n_bins;
+  const int64_t *__restrict__ bs = a.bin_start + P.bin_begin;
+  const int64_t b0 = (int64_t)u.chunk * kBigBins;
+  for (int64_t b = b0 + threadIdx.x; b < min(b0 + kBigBins, nb); b += kBigThreads) {
+    const int64_t s0 = u.r0 + bs[b], e0 = b + 1 < nb ? u.r0 + bs[b + 1] : u.r0 + u.R;
+    for (int64_t x = s0 + 1; x < e0; ++x) {
+      const double kx = a.skey[x];
+      const int32_t ix = a.sidx[x];
+      int64_t j = x - 1;
+      while (j >= s0) {
+        const double kj = a.skey[j];
+        const int32_t ij = a.sidx[j];
+        if (!(kj > kx || (kj == kx && ij > ix))) break;
+        a.skey[j + 1] = kj;
+        a.sidx[j + 1] = ij;
+        --j;
+      }
+      a.skey[j + 1] = kx;
+      a.sidx[j + 1] = ix;
+    }
+  }
+}
+
+// Peak start at sorted position j: a gap >= tol before it, or the anchor
+// rule walked from the start of its component (the last position at or
+// before j with such a gap, or 0) up to j.  The same decisions as the one
+// walker per component of sort_global, taken by each position for itself.
+__device__ __forceinline__ bool big_peak_start(const double *__restrict__ k, int64_t j, double tol) {
+#pragma clang fp contract(off)
+  if (j == 0 || k[j] - k[j - 1] >= tol) return true;
+  int64_t s = j - 1;
+  while (s > 0 && k[s] - k[s - 1] < tol) --s;
+  double anchor = k[s];
+  bool open = false;
+  for (int64_t x = s + 1; x <= j; ++x) {
+    open = (k[x] - anchor) >= tol;
+    if (open) anchor = k[x];
+  }
+  return open;
+}
+
+// Per chunk of sorted positions: perm, the peak-start flags and the entry
+// flags (the evaluated half: global index in the upper half of the
+// crystal's slots), and their counts.
+__global__ __launch_bounds__(kBigThreads) void kb_flags(BigArgs a, MergeOut mo) {
+  __shared__ int32_t red[kBigThreads / 64];
+  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
+  if (!u.live) return;
+  const bool merge = mo.inten != nullptr;
+  const int64_t mid = u.r0 + u.R / 2;
+  const int64_t j0 = (int64_t)u.chunk * kBigChunk + (int64_t)threadIdx.x * kBigPer;
+  int np = 0, ne = 0;
+#pragma unroll 4
+  for (int q = 0; q < kBigPer; ++q) {
+    const int64_t j = j0 + q;
+    if (j >= u.R) break;
+    const int32_t ix = a.sidx[u.r0 + j];
+    ne += ix >= mid ? 1 : 0;
+    if (merge) {
+      mo.perm[u.r0 + j] = ix;
+      const bool f = big_peak_start(a.skey + u.r0, j, mo.tol);
+      mo.flags[u.r0 + j] = f ? 1 : 0;
+      np += f ? 1 : 0;
+    }
+  }
+  np = big_block_sum(np, red);
+  ne = big_block_sum(ne, red);
+  if (threadIdx.x == 0) {
+    a.cnt[3 * (int64_t)u.slot + 0] = np;
+    a.cnt[3 * (int64_t)u.slot + 1] = ne;
+  }
+}
+
+// Exclusive scan of a crystal's chunk counts (component ``k`` of cnt) into
+// off, one wavefront per crystal; returns the crystal's total.
+__device__ int64_t big_scan_chunks(const BigArgs &a, const BigChunk &bc, int k) {
+  const int lane = threadIdx.x & 63;
+  int64_t carry = 0;
+  for (int32_t i0 = 0; i0 < bc.n; i0 += 64) {
+    const int32_t i = i0 + lane;
+    const int64_t v = i < bc.n ? a.cnt[3 * ((int64_t)bc.first + i) + k] : 0;
+    int64_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t o = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += o;
+    }
+    if (i < bc.n) a.off[3 * ((int64_t)bc.first + i) + k] = carry + inc - v;
+    carry += __shfl(inc, 63, 64);
+  }
+  return carry;
+}
+
+__global__ __launch_bounds__(64) void kb_scan_counts(BigArgs a, const BigChunk *__restrict__ crystals, MergeOut mo) {
+  const BigChunk bc = crystals[blockIdx.x];
+  const BigUnit u = big_unit(a, bc);
+  if (!u.live) return;
+  big_scan_chunks(a, bc, 1);
+  if (mo.inten == nullptr) return;
+  const int64_t np = big_scan_chunks(a, bc, 0);
+  if (threadIdx.x == 0) {
+    a.np[u.c] = (int32_t)np;
+    if (!(mo.thr > 0.0)) mo.pk_count[u.c] = (int32_t)np;
+  }
+}
+
+// Exclusive block scan of one count per thread (the thread's kBigPer
+// consecutive positions); ``wsum``: kBigThreads / 64 ints.
+__device__ __forceinline__ int big_block_scan(int v, int32_t *wsum) {
+  int total;
+  return block_exclusive_scan<kBigThreads>(v, wsum, &total);
+}
+
+// Per chunk of sorted positions: the entries at their ranks, and each peak
+// (start, members' intensity sum in sorted order, multiplicity) at its
+// number, staged at r0 + p (r0 + R/2 + p when a threshold follows); the
+// crystal's largest peak intensity by one atomic per block.
+__global__ __launch_bounds__(kBigThreads) void kb_write(BigArgs a, MergeOut mo) {
+  __shared__ int32_t wsum[kBigThreads / 64];
+  __shared__ unsigned long long smax[1];
+  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
+  if (!u.live) return;
+  const bool merge = mo.inten != nullptr;
+  const int64_t mid = u.r0 + u.R / 2;
+  const int64_t j0 = (int64_t)u.chunk * kBigChunk + (int64_t)threadIdx.x * kBigPer;
+  const int64_t jend = min(j0 + kBigPer, u.R);
+  if (a.ent_key) {
+    int ne = 0;
+    for (int64_t j = j0; j < jend; ++j) ne += a.sidx[u.r0 + j] >= mid ? 1 : 0;
+    int64_t e = u.r0 / 2 + a.off[3 * (int64_t)u.slot + 1] + big_block_scan(ne, wsum);
+    for (int64_t j = j0; j < jend; ++j) {
+      const int32_t ix = a.sidx[u.r0 + j];
+      if (ix >= mid) {
+        a.ent_key[e] = a.skey[u.r0 + j];
+        a.ent_idx[e] = ix;
+        ++e;
+      }
+    }
+  }
+  if (!merge) return;
+  int nf = 0;
+  for (int64_t j = j0; j < jend; ++j) nf += mo.flags[u.r0 + j];
+  int64_t p = a.off[3 * (int64_t)u.slot + 0] + big_block_scan(nf, wsum);
+  const int64_t base = u.r0 + (mo.thr > 0.0 ? u.R / 2 : 0);
+  double mx = 0.0;
+  for (int64_t j = j0; j < jend; ++j) {
+    if (!mo.flags[u.r0 + j]) continue;
+    double s = mo.inten[a.sidx[u.r0 + j]];
+    int m = 1;
+    for (int64_t x = j + 1; x < u.R && !mo.flags[u.r0 + x]; ++x) {
+      s += mo.inten[a.sidx[u.r0 + x]];
+      ++m;
+    }
+    mo.t_tt[base + p] = a.skey[u.r0 + j];
+    mo.t_i[base + p] = s;
+    mo.t_mult[base + p] = m;
+    mo.t_first[base + p] = u.r0 + j;
+    mx = fmax(mx, s);
+    ++p;
+  }
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) mx = fmax(mx, __shfl_xor(mx, d, 64));
+  if (threadIdx.x == 0) *smax = 0ull;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) atomicMax(smax, (unsigned long long)__double_as_longlong(mx));
+  __syncthreads();
+  if (threadIdx.x == 0) atomicMax(reinterpret_cast<unsigned long long *>(&mo.cmax[u.c]), *smax);
+}
+
+// Threshold, per chunk of staged peak slots: the kept peaks (I >= thr max),
+// counted, then (after their scan) moved to r0 + rank.
+template <bool MOVE>
+__global__ __launch_bounds__(kBigThreads) void kb_keep(BigArgs a, MergeOut mo) {
+  __shared__ int32_t wsum[kBigThreads / 64];
+  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
+  if (!u.live) return;
+  const int64_t np = a.np[u.c];
+  const int64_t src = u.r0 + u.R / 2;
+  const double cut = mo.thr * __longlong_as_double((long long)mo.cmax[u.c]);
+  const int64_t k0 = (int64_t)u.chunk * kBigChunk + (int64_t)threadIdx.x * kBigPer;
+  const int64_t kend = min(k0 + kBigPer, np);
+  int nk = 0;
+  for (int64_t k = k0; k < kend; ++k) nk += mo.t_i[src + k] >= cut ? 1 : 0;
+  if constexpr (!MOVE) {
+    nk = big_block_sum(nk, wsum);
+    if (threadIdx.x == 0) a.cnt[3 * (int64_t)u.slot + 2] = nk;
+  } else {
+    int64_t d = u.r0 + a.off[3 * (int64_t)u.slot + 2] + big_block_scan(nk, wsum);
+    for (int64_t k = k0; k < kend; ++k) {
+      const double iv = mo.t_i[src + k];
+      if (iv >= cut) {
+        mo.t_tt[d] = mo.t_tt[src + k];
+        mo.t_i[d] = iv;
+        mo.t_mult[d] = mo.t_mult[src + k];
+        mo.t_first[d] = mo.t_first[src + k];
+        ++d;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(64) void kb_scan_kept(BigArgs a, const BigChunk *__restrict__ crystals, MergeOut mo) {
+  const BigChunk bc = crystals[blockIdx.x];
+  const BigUnit u = big_unit(a, bc);
+  if (!u.live) return;
+  const int64_t kept = big_scan_chunks(a, bc, 2);
+  if (threadIdx.x == 0) mo.pk_count[u.c] = (int32_t)kept;
+}
+
+void big_sort(const SortArgs &s, const MergeOut &mo, hipStream_t st) {
+  if (s.n_big_chunks <= 0) return;
+  BigArgs a;
+  a.chunks = s.big_chunks;
+  a.plan = s.plan;
+  a.refl_offset = s.refl_offset;
+  a.tt = s.tt;
+  a.bin_count = s.bin_count;
+  a.bin_start = s.bin_start;
+  a.skey = s.skey;
+  a.sidx = s.sidx;
+  a.ent_key = s.friedel ? s.ent_key : nullptr;
+  a.ent_idx = s.friedel ? s.ent_idx : nullptr;
+  a.cnt = s.big_cnt;
+  a.off = s.big_off;
+  a.np = s.big_np;
+  const bool merge = mo.inten != nullptr;
+  const dim3 g((unsigned)s.n_big_chunks), b(kBigThreads), gc((unsigned)s.n_big);
+  hipLaunchKernelGGL(kb_clear, g, b, 0, st, a, merge ? mo.cmax : nullptr);
+  hipLaunchKernelGGL(kb_count, g, b, 0, st, a);
+  hipLaunchKernelGGL(kb_scan_bins, gc, dim3(1024), 0, st, a, s.big_crystals);
+  hipLaunchKernelGGL(kb_scatter, g, b, 0, st, a);
+  hipLaunchKernelGGL(kb_binsort, g, b, 0, st, a);
+  if (!merge && !a.ent_key) return;  // the sorted keys are the entries
+  hipLaunchKernelGGL(kb_flags, g, b, 0, st, a, mo);
+  hipLaunchKernelGGL(kb_scan_counts, gc, dim3(64), 0, st, a, s.big_crystals, mo);
+  hipLaunchKernelGGL(kb_write, g, b, 0, st, a, mo);
+  if (!merge || !(mo.thr > 0.0)) return;
+  hipLaunchKernelGGL(kb_keep<false>, g, b, 0, st, a, mo);
+  hipLaunchKernelGGL(kb_scan_kept, gc, dim3(64), 0, st, a, s.big_crystals, mo);
+  hipLaunchKernelGGL(kb_keep<true>, g, b, 0, st, a, mo);
+}
+
 // LDS sort and merge of one crystal of at most 2 CAP reflections by a group
 // of T threads (``gt``: index in the group; c < 0: no crystal, the group only
 // keeps step with the block's barriers).  The group's LDS: key[CAP],
@@ -580,8 +958,12 @@ __global__ __launch_bounds__(1024, 8) void k_sort_merge(int64_t n_c, int64_t n_b
   if (blk < n_big) {
     const int64_t c = items[blk];
     const int64_t R = refl_offset[c + 1] - refl_offset[c];
-    if (R > 2 * (int64_t)CAPMAX)
-      sort_global<1024>(c, plan, refl_offset, tt, skey, sidx, ent_key, ent_idx, bin_count, bin_start, mo, wsum, smax);
+    if (R > 2 * (int64_t)CAPMAX) {
+      // capacity above kBigSort: the many-block sort takes the crystal
+      if (2 * plan[c].half_box <= kBigSort)
+        sort_global<1024>(c, plan, refl_offset, tt, skey, sidx, ent_key, ent_idx, bin_count, bin_start, mo, wsum,
+                          smax);
+    }
     else if (R > 2 * kSmallSort)
       sort_lds<CAPMAX, 1024>(c, (int)threadIdx.x, key, pos, cnt, wsum, smax, plan, refl_offset, tt, skey, sidx,
                              ent_key, ent_idx, mo);
@@ -718,6 +1100,7 @@ void sort_kernels(const SortArgs &a, const MergeOut &mo, hipStream_t s) {
   const unsigned grid = (unsigned)(a.n_small + (a.n_c + 3) / 4);
   hipLaunchKernelGGL(k_sort_merge<kMidSort>, dim3(grid), dim3(1024), 0, s, a.n_c, a.n_small, a.items, a.plan,
                      a.refl_offset, a.tt, a.skey, a.sidx, ek, ei, a.bin_count, a.bin_start, mo);
+  big_sort(a, mo, s);
 }
 
 }  // namespace

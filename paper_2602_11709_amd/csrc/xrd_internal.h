@@ -37,6 +37,12 @@ constexpr int kSplitBw = 48;
 constexpr int kTinySort = 1024;      // Friedel-positive reflections sorted in LDS by one 256-thread block
 constexpr int kSmallSort = 4096;     // ... by one 1024-thread block
 constexpr int kMidSort = 6144;       // ... by one 1024-thread block; larger crystals sort in global memory
+// Crystals whose reflection capacity exceeds kBigSort sort in global memory
+// over many blocks (kBigChunk reflections, sorted positions or peak slots
+// each) when they have more than 2 kMidSort reflections; the others in
+// global memory take one block.
+constexpr int64_t kBigSort = 65536;
+constexpr int kBigChunk = 4096;
 constexpr int kSpanPts = 16;         // grid points per span of the broadening gather (a quarter wavefront)
 constexpr int kRecLen = 8;           // reflections per segment of the row-recurrence structure factors
 constexpr int kRecMinAtoms = 256;    // XRD_SF_AUTO: default atom threshold of the recurrence
@@ -127,6 +133,13 @@ struct HChunk {
   int32_t chunk;
 };
 
+// Unit of the many-block global-memory sort: chunk ``chunk`` of crystal
+// ``crystal``, whose n chunks hold the slots first .. first + n - 1 of the
+// per-chunk count and offset arrays (the crystal list uses chunk = 0).
+struct BigChunk {
+  int32_t crystal, chunk, first, n;
+};
+
 // Structure-factor work item: a tile of reflections of one crystal, with
 // the crystal's atom range and species-run slots (from the plan), so that a
 // wavefront's atom loads do not wait for the plan (32 bytes, one scalar load).
@@ -150,6 +163,7 @@ struct WsLayout {
   int64_t flags;
   int64_t cmax, pk_count, tmp_tt, tmp_i, tmp_mult, tmp_first;
   int64_t sort_items;  // the sort launch's crystal lists
+  int64_t big_chunks, big_crystals, big_cnt, big_off, big_np;  // the many-block sort's tables and scratch
   int64_t scan_part;
   int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6, bw_partf;
   int64_t sf_deriv;  // kept (A, B, dA/ds^2, dB/ds^2) per reflection, or -1
@@ -276,6 +290,16 @@ struct SortArgs {
   int32_t friedel;       // write the evaluated-half entries below
   double *ent_key;       // [half capacity] 2theta of the evaluated half, sorted per crystal
   int32_t *ent_idx;      // its global reflection indices
+  // crystals of capacity above kBigSort: their chunks and the crystals
+  // themselves, per-chunk counts and offsets (3 each) and per-crystal peak
+  // counts of the many-block sort
+  const BigChunk *big_chunks;
+  int64_t n_big_chunks;
+  const BigChunk *big_crystals;
+  int64_t n_big;
+  int32_t *big_cnt;
+  int64_t *big_off;
+  int32_t *big_np;
 };
 // Two more streams for independent work inside one call: the caller's stream
 // records ``fork``, the side streams wait for it, run their parts and record
