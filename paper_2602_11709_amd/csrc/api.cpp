@@ -781,8 +781,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   const int64_t nbc = (int64_t)b->big_chunks.size(), nbig = (int64_t)b->big_crystals.size();
   L.big_chunks = take((int64_t)sizeof(BigChunk) * nbc);
   L.big_crystals = take((int64_t)sizeof(BigChunk) * nbig);
-  L.big_cnt = take(4 * 3 * nbc);
-  L.big_off = take(8 * 3 * nbc);
+  L.big_cnt = take(4 * 4 * nbc);
+  L.big_off = take(8 * 4 * nbc);
   L.big_np = take(4 * nc);
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(ec, bins), rc);
   L.scan_part = take(8 * scan_part_elems(scan_n));
@@ -839,8 +839,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     M.sort_items = take(4 * (b->n_small + nc));
     M.big_chunks = take((int64_t)sizeof(BigChunk) * nbc);
     M.big_crystals = take((int64_t)sizeof(BigChunk) * nbig);
-    M.big_cnt = take(4 * 3 * nbc);
-    M.big_off = take(8 * 3 * nbc);
+    M.big_cnt = take(4 * 4 * nbc);
+    M.big_off = take(8 * 4 * nbc);
     M.big_np = take(4 * nc);
     M.total = o;
   }

@@ -287,12 +287,13 @@ __device__ void sort_global(int64_t c, const CrystalPlan *__restrict__ plan, con
 //
 // The same sort and merge as sort_global, for crystals of capacity above
 // kBigSort, spread over blocks of kBigChunk reflections, sorted positions or
-// peak slots each, one launch per phase (a phase ends before the next reads
-// its results, so no block waits on another):
-//   clear the bins -> count (global atomics) -> scan the bins per crystal ->
-//   scatter -> order each bin on (2theta, global index) -> peak-start and
-//   entry flags with per-chunk counts -> scan the chunk counts per crystal ->
-//   write the entries and the peaks (each sum in sorted order).
+// peak slots (or kBigBins bins) each, one launch per phase (a phase ends
+// before the next reads its results, so no block waits on another):
+//   clear the bins -> count (global atomics) -> per-chunk bin sums -> their
+//   scan per crystal -> the bins' scan within each chunk -> scatter -> order
+//   each bin on (2theta, global index) -> peak-start and entry flags with
+//   per-chunk counts -> their scan per crystal -> write the entries and the
+//   peaks (each sum in sorted order).
 // With a relative threshold the peaks are staged in the upper half of the
 // crystal's reflection slots (a crystal has at most R/2 peaks: both mates of
 // a Friedel pair share 2theta bit for bit, so every peak holds both), then
@@ -300,7 +301,11 @@ __device__ void sort_global(int64_t c, const CrystalPlan *__restrict__ plan, con
 // sort_global: the same bins, order, anchor-rule decisions and sums.
 constexpr int kBigThreads = 256;
 constexpr int kBigPer = kBigChunk / kBigThreads;  // 16
-constexpr int kBigBins = kBigChunk / kBinDiv;     // bins cleared and ordered per block
+constexpr int kBigBins = kBigChunk / kBinDiv;     // bins per block of the bin phases
+static_assert(kBigBins == 4 * kBigThreads, "four consecutive bins per thread");
+// per-chunk counters (cnt) and their scans per crystal (off)
+enum BigSlot { kSlotPeaks = 0, kSlotEntries = 1, kSlotKept = 2, kSlotBins = 3, kBigSlots = 4 };
+constexpr int kBinSortRegs = 8;  // bins up to this size are ordered in registers
 
 struct BigArgs {
   const BigChunk *chunks;
@@ -313,8 +318,8 @@ struct BigArgs {
   int32_t *sidx;
   double *ent_key;  // null without Friedel pairing
   int32_t *ent_idx;
-  int32_t *cnt;     // [3 n_big_chunks]: peak starts, entries, kept peaks of a chunk
-  int64_t *off;     // [3 n_big_chunks]: their exclusive scans per crystal
+  int32_t *cnt;     // [kBigSlots n_big_chunks]
+  int64_t *off;     // [kBigSlots n_big_chunks]
   int32_t *np;      // [n_c] peaks of a crystal
 };
 
@@ -322,7 +327,8 @@ struct BigArgs {
 // 2 kMidSort reflections; the others are sorted in LDS by the one-launch sort).
 struct BigUnit {
   int64_t c, r0, R;
-  int32_t chunk, slot;  // slot: this chunk's index in cnt/off
+  int32_t chunk;
+  int64_t slot;  // this chunk's first counter
   bool live;
 };
 __device__ __forceinline__ BigUnit big_unit(const BigArgs &a, const BigChunk &bc) {
@@ -331,7 +337,7 @@ __device__ __forceinline__ BigUnit big_unit(const BigArgs &a, const BigChunk &bc
   u.r0 = a.refl_offset[u.c];
   u.R = a.refl_offset[u.c + 1] - u.r0;
   u.chunk = bc.chunk;
-  u.slot = bc.first + bc.chunk;
+  u.slot = (int64_t)kBigSlots * (bc.first + bc.chunk);
   u.live = u.R > 2 * (int64_t)kMidSort;
   return u;
 }
@@ -347,6 +353,26 @@ __device__ __forceinline__ int big_block_sum(int v, int32_t *red) {
 #pragma unroll
   for (int w = 0; w < kBigThreads / 64; ++w) t += red[w];
   return t;
+}
+
+// Block-wide ranks of the set lanes of one flag per thread: returns the
+// number of set flags in lower threads and sets *total; ``red``: kBigThreads
+// / 64 ints, free again on return.
+__device__ __forceinline__ int big_block_rank(bool f, int32_t *red, int *total) {
+  const uint64_t bal = __ballot(f);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = __popcll(bal);
+  __syncthreads();
+  int below = __builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+  int t = 0;
+#pragma unroll
+  for (int w = 0; w < kBigThreads / 64; ++w) {
+    below += w < wid ? red[w] : 0;
+    t += red[w];
+  }
+  __syncthreads();
+  *total = t;
+  return below;
 }
 
 __global__ __launch_bounds__(kBigThreads) void kb_clear(BigArgs a, uint64_t *__restrict__ cmax) {
@@ -368,33 +394,43 @@ __global__ __launch_bounds__(kBigThreads) void kb_count(BigArgs a) {
     atomicAdd(&a.bin_count[P.bin_begin + bin_of(P, a.tt[u.r0 + i])], 1);
 }
 
-// One 1024-thread block per crystal: bin_start = exclusive scan of the
-// counts, four consecutive bins per thread and round.
-__global__ __launch_bounds__(1024) void kb_scan_bins(BigArgs a, const BigChunk *__restrict__ crystals) {
-  __shared__ int32_t wsum[1024 / 64];
-  const BigUnit u = big_unit(a, crystals[blockIdx.x]);
+// A chunk's four consecutive bins of this thread (zero past the crystal's).
+__device__ __forceinline__ int big_bins4(const BigArgs &a, const CrystalPlan &P, const BigUnit &u, int (&v)[4]) {
+  const int64_t b = (int64_t)u.chunk * kBigBins + 4 * (int64_t)threadIdx.x;
+  int s = 0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    v[q] = b + q < P.n_bins ? a.bin_count[P.bin_begin + b + q] : 0;
+    s += v[q];
+  }
+  return s;
+}
+
+__global__ __launch_bounds__(kBigThreads) void kb_bin_sums(BigArgs a) {
+  __shared__ int32_t red[kBigThreads / 64];
+  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
+  if (!u.live) return;
+  int v[4];
+  const int s = big_block_sum(big_bins4(a, a.plan[u.c], u, v), red);
+  if (threadIdx.x == 0) a.cnt[u.slot + kSlotBins] = s;
+}
+
+// bin_start of the chunk's bins: the exclusive scan of the counts within the
+// chunk plus the chunk's offset.
+__global__ __launch_bounds__(kBigThreads) void kb_scan_bins(BigArgs a) {
+  __shared__ int32_t wsum[kBigThreads / 64];
+  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
   if (!u.live) return;
   const CrystalPlan &P = a.plan[u.c];
-  const int64_t nb = P.n_bins;
-  const int32_t *__restrict__ bc = a.bin_count + P.bin_begin;
-  int64_t *__restrict__ bs = a.bin_start + P.bin_begin;
-  int64_t carry = 0;
-  for (int64_t b0 = 0; b0 < nb; b0 += 4 * 1024) {
-    const int64_t b = b0 + 4 * (int64_t)threadIdx.x;
-    int v[4], sum = 0;
+  int v[4];
+  const int s = big_bins4(a, P, u, v);
+  int total;
+  int64_t o = a.off[u.slot + kSlotBins] + block_exclusive_scan<kBigThreads>(s, wsum, &total);
+  const int64_t b = (int64_t)u.chunk * kBigBins + 4 * (int64_t)threadIdx.x;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      v[q] = b + q < nb ? bc[b + q] : 0;
-      sum += v[q];
-    }
-    int total;
-    int ex = block_exclusive_scan<1024>(sum, wsum, &total);
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (b + q < nb) bs[b + q] = carry + ex;
-      ex += v[q];
-    }
-    carry += total;
+  for (int q = 0; q < 4; ++q) {
+    if (b + q < P.n_bins) a.bin_start[P.bin_begin + b + q] = o;
+    o += v[q];
   }
 }
 
@@ -414,7 +450,9 @@ __global__ __launch_bounds__(kBigThreads) void kb_scatter(BigArgs a) {
   }
 }
 
-// Insertion sort of each bin on (2theta, global index), a bin per thread.
+// Order of each bin on (2theta, global index), a bin per thread: up to
+// kBinSortRegs items by an odd-even transposition network in registers
+// (padded with keys that sort last), larger bins by insertion in place.
 __global__ __launch_bounds__(kBigThreads) void kb_binsort(BigArgs a) {
   const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
   if (!u.live) return;
@@ -422,12 +460,44 @@ __global__ __launch_bounds__(kBigThreads) void kb_binsort(BigArgs a) {
   const int64_t nb = P.n_bins;
   const int64_t *__restrict__ bs = a.bin_start + P.bin_begin;
   const int64_t b0 = (int64_t)u.chunk * kBigBins;
-  for (int64_t b = b0 + threadIdx.x; b < min(b0 + kBigBins, nb); b += kBigThreads) {
+  for (int q = 0; q < kBigBins / kBigThreads; ++q) {
+    const int64_t b = b0 + q * kBigThreads + threadIdx.x;
+    if (b >= nb) break;
     const int64_t s0 = u.r0 + bs[b], e0 = b + 1 < nb ? u.r0 + bs[b + 1] : u.r0 + u.R;
-    for (int64_t x = s0 + 1; x < e0; ++x) {
-      const double kx = a.skey[x];
-      const int32_t ix = a.sidx[x];
-      int64_t j = x - 1;
+    const int64_t n = e0 - s0;
+    if (n <= 1) continue;
+    if (n <= kBinSortRegs) {
+      double k[kBinSortRegs];
+      int32_t x[kBinSortRegs];
+#pragma unroll
+      for (int i = 0; i < kBinSortRegs; ++i) {
+        k[i] = i < n ? a.skey[s0 + i] : __builtin_inf();
+        x[i] = i < n ? a.sidx[s0 + i] : INT32_MAX;
+      }
+#pragma unroll
+      for (int r = 0; r < kBinSortRegs; ++r)
+#pragma unroll
+        for (int i = r & 1; i + 1 < kBinSortRegs; i += 2) {
+          const bool sw = k[i] > k[i + 1] || (k[i] == k[i + 1] && x[i] > x[i + 1]);
+          const double tk = sw ? k[i + 1] : k[i];
+          const int32_t tx = sw ? x[i + 1] : x[i];
+          k[i + 1] = sw ? k[i] : k[i + 1];
+          x[i + 1] = sw ? x[i] : x[i + 1];
+          k[i] = tk;
+          x[i] = tx;
+        }
+#pragma unroll
+      for (int i = 0; i < kBinSortRegs; ++i)
+        if (i < n) {
+          a.skey[s0 + i] = k[i];
+          a.sidx[s0 + i] = x[i];
+        }
+      continue;
+    }
+    for (int64_t xi = s0 + 1; xi < e0; ++xi) {
+      const double kx = a.skey[xi];
+      const int32_t ix = a.sidx[xi];
+      int64_t j = xi - 1;
       while (j >= s0) {
         const double kj = a.skey[j];
         const int32_t ij = a.sidx[j];
@@ -469,11 +539,10 @@ __global__ __launch_bounds__(kBigThreads) void kb_flags(BigArgs a, MergeOut mo) 
   if (!u.live) return;
   const bool merge = mo.inten != nullptr;
   const int64_t mid = u.r0 + u.R / 2;
-  const int64_t j0 = (int64_t)u.chunk * kBigChunk + (int64_t)threadIdx.x * kBigPer;
+  const int64_t j0 = (int64_t)u.chunk * kBigChunk;
   int np = 0, ne = 0;
-#pragma unroll 4
   for (int q = 0; q < kBigPer; ++q) {
-    const int64_t j = j0 + q;
+    const int64_t j = j0 + q * kBigThreads + threadIdx.x;
     if (j >= u.R) break;
     const int32_t ix = a.sidx[u.r0 + j];
     ne += ix >= mid ? 1 : 0;
@@ -487,49 +556,55 @@ __global__ __launch_bounds__(kBigThreads) void kb_flags(BigArgs a, MergeOut mo) 
   np = big_block_sum(np, red);
   ne = big_block_sum(ne, red);
   if (threadIdx.x == 0) {
-    a.cnt[3 * (int64_t)u.slot + 0] = np;
-    a.cnt[3 * (int64_t)u.slot + 1] = ne;
+    a.cnt[u.slot + kSlotPeaks] = np;
+    a.cnt[u.slot + kSlotEntries] = ne;
   }
 }
 
-// Exclusive scan of a crystal's chunk counts (component ``k`` of cnt) into
-// off, one wavefront per crystal; returns the crystal's total.
+// Exclusive scan of a crystal's chunk counters ``k`` into off, one wavefront
+// per crystal; returns the crystal's total.
 __device__ int64_t big_scan_chunks(const BigArgs &a, const BigChunk &bc, int k) {
   const int lane = threadIdx.x & 63;
   int64_t carry = 0;
   for (int32_t i0 = 0; i0 < bc.n; i0 += 64) {
     const int32_t i = i0 + lane;
-    const int64_t v = i < bc.n ? a.cnt[3 * ((int64_t)bc.first + i) + k] : 0;
+    const int64_t s = (int64_t)kBigSlots * ((int64_t)bc.first + i) + k;
+    const int64_t v = i < bc.n ? a.cnt[s] : 0;
     int64_t inc = v;
 #pragma unroll
     for (int d = 1; d < 64; d <<= 1) {
       const int64_t o = __shfl_up(inc, d, 64);
       if (lane >= d) inc += o;
     }
-    if (i < bc.n) a.off[3 * ((int64_t)bc.first + i) + k] = carry + inc - v;
+    if (i < bc.n) a.off[s] = carry + inc - v;
     carry += __shfl(inc, 63, 64);
   }
   return carry;
 }
 
+// Scans per crystal: the bin sums (BINS), or the entry and peak counts, or
+// the kept counts; with the peak counts the crystal's peak count (and, with
+// no threshold to follow, its kept count), with the kept counts the latter.
+enum BigScan { kScanBins, kScanFlags, kScanKept };
+template <int WHICH>
 __global__ __launch_bounds__(64) void kb_scan_counts(BigArgs a, const BigChunk *__restrict__ crystals, MergeOut mo) {
   const BigChunk bc = crystals[blockIdx.x];
   const BigUnit u = big_unit(a, bc);
   if (!u.live) return;
-  big_scan_chunks(a, bc, 1);
-  if (mo.inten == nullptr) return;
-  const int64_t np = big_scan_chunks(a, bc, 0);
-  if (threadIdx.x == 0) {
-    a.np[u.c] = (int32_t)np;
-    if (!(mo.thr > 0.0)) mo.pk_count[u.c] = (int32_t)np;
+  if constexpr (WHICH == kScanBins) {
+    big_scan_chunks(a, bc, kSlotBins);
+  } else if constexpr (WHICH == kScanFlags) {
+    big_scan_chunks(a, bc, kSlotEntries);
+    if (mo.inten == nullptr) return;
+    const int64_t np = big_scan_chunks(a, bc, kSlotPeaks);
+    if (threadIdx.x == 0) {
+      a.np[u.c] = (int32_t)np;
+      if (!(mo.thr > 0.0)) mo.pk_count[u.c] = (int32_t)np;
+    }
+  } else {
+    const int64_t kept = big_scan_chunks(a, bc, kSlotKept);
+    if (threadIdx.x == 0) mo.pk_count[u.c] = (int32_t)kept;
   }
-}
-
-// Exclusive block scan of one count per thread (the thread's kBigPer
-// consecutive positions); ``wsum``: kBigThreads / 64 ints.
-__device__ __forceinline__ int big_block_scan(int v, int32_t *wsum) {
-  int total;
-  return block_exclusive_scan<kBigThreads>(v, wsum, &total);
 }
 
 // Per chunk of sorted positions: the entries at their ranks, and each peak
@@ -537,48 +612,48 @@ __device__ __forceinline__ int big_block_scan(int v, int32_t *wsum) {
 // number, staged at r0 + p (r0 + R/2 + p when a threshold follows); the
 // crystal's largest peak intensity by one atomic per block.
 __global__ __launch_bounds__(kBigThreads) void kb_write(BigArgs a, MergeOut mo) {
-  __shared__ int32_t wsum[kBigThreads / 64];
+  __shared__ int32_t red[kBigThreads / 64];
   __shared__ unsigned long long smax[1];
   const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
   if (!u.live) return;
-  const bool merge = mo.inten != nullptr;
+  const bool merge = mo.inten != nullptr, ent = a.ent_key != nullptr;
   const int64_t mid = u.r0 + u.R / 2;
-  const int64_t j0 = (int64_t)u.chunk * kBigChunk + (int64_t)threadIdx.x * kBigPer;
-  const int64_t jend = min(j0 + kBigPer, u.R);
-  if (a.ent_key) {
-    int ne = 0;
-    for (int64_t j = j0; j < jend; ++j) ne += a.sidx[u.r0 + j] >= mid ? 1 : 0;
-    int64_t e = u.r0 / 2 + a.off[3 * (int64_t)u.slot + 1] + big_block_scan(ne, wsum);
-    for (int64_t j = j0; j < jend; ++j) {
-      const int32_t ix = a.sidx[u.r0 + j];
-      if (ix >= mid) {
-        a.ent_key[e] = a.skey[u.r0 + j];
-        a.ent_idx[e] = ix;
-        ++e;
-      }
-    }
-  }
-  if (!merge) return;
-  int nf = 0;
-  for (int64_t j = j0; j < jend; ++j) nf += mo.flags[u.r0 + j];
-  int64_t p = a.off[3 * (int64_t)u.slot + 0] + big_block_scan(nf, wsum);
+  const int64_t j0 = (int64_t)u.chunk * kBigChunk;
+  int64_t e = u.r0 / 2 + a.off[u.slot + kSlotEntries];
+  int64_t p = a.off[u.slot + kSlotPeaks];
   const int64_t base = u.r0 + (mo.thr > 0.0 ? u.R / 2 : 0);
   double mx = 0.0;
-  for (int64_t j = j0; j < jend; ++j) {
-    if (!mo.flags[u.r0 + j]) continue;
-    double s = mo.inten[a.sidx[u.r0 + j]];
-    int m = 1;
-    for (int64_t x = j + 1; x < u.R && !mo.flags[u.r0 + x]; ++x) {
-      s += mo.inten[a.sidx[u.r0 + x]];
-      ++m;
+  for (int q = 0; q < kBigPer; ++q) {
+    const int64_t j = j0 + q * kBigThreads + threadIdx.x;
+    if (j0 + q * kBigThreads >= u.R) break;  // the same for the whole block
+    const bool live = j < u.R;
+    const int32_t ix = live ? a.sidx[u.r0 + j] : 0;
+    const bool fe = ent && live && ix >= mid;
+    const bool fp = merge && live && mo.flags[u.r0 + j];
+    int te, tp;
+    const int re = big_block_rank(fe, red, &te);
+    const int rp = big_block_rank(fp, red, &tp);
+    if (fe) {
+      a.ent_key[e + re] = a.skey[u.r0 + j];
+      a.ent_idx[e + re] = ix;
     }
-    mo.t_tt[base + p] = a.skey[u.r0 + j];
-    mo.t_i[base + p] = s;
-    mo.t_mult[base + p] = m;
-    mo.t_first[base + p] = u.r0 + j;
-    mx = fmax(mx, s);
-    ++p;
+    if (fp) {
+      double s = mo.inten[ix];
+      int m = 1;
+      for (int64_t x = j + 1; x < u.R && !mo.flags[u.r0 + x]; ++x) {
+        s += mo.inten[a.sidx[u.r0 + x]];
+        ++m;
+      }
+      mo.t_tt[base + p + rp] = a.skey[u.r0 + j];
+      mo.t_i[base + p + rp] = s;
+      mo.t_mult[base + p + rp] = m;
+      mo.t_first[base + p + rp] = u.r0 + j;
+      mx = fmax(mx, s);
+    }
+    e += te;
+    p += tp;
   }
+  if (!merge) return;
 #pragma unroll
   for (int d = 32; d >= 1; d >>= 1) mx = fmax(mx, __shfl_xor(mx, d, 64));
   if (threadIdx.x == 0) *smax = 0ull;
@@ -592,40 +667,38 @@ __global__ __launch_bounds__(kBigThreads) void kb_write(BigArgs a, MergeOut mo) 
 // counted, then (after their scan) moved to r0 + rank.
 template <bool MOVE>
 __global__ __launch_bounds__(kBigThreads) void kb_keep(BigArgs a, MergeOut mo) {
-  __shared__ int32_t wsum[kBigThreads / 64];
+  __shared__ int32_t red[kBigThreads / 64];
   const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
   if (!u.live) return;
   const int64_t np = a.np[u.c];
   const int64_t src = u.r0 + u.R / 2;
   const double cut = mo.thr * __longlong_as_double((long long)mo.cmax[u.c]);
-  const int64_t k0 = (int64_t)u.chunk * kBigChunk + (int64_t)threadIdx.x * kBigPer;
-  const int64_t kend = min(k0 + kBigPer, np);
+  const int64_t k0 = (int64_t)u.chunk * kBigChunk;
   int nk = 0;
-  for (int64_t k = k0; k < kend; ++k) nk += mo.t_i[src + k] >= cut ? 1 : 0;
-  if constexpr (!MOVE) {
-    nk = big_block_sum(nk, wsum);
-    if (threadIdx.x == 0) a.cnt[3 * (int64_t)u.slot + 2] = nk;
-  } else {
-    int64_t d = u.r0 + a.off[3 * (int64_t)u.slot + 2] + big_block_scan(nk, wsum);
-    for (int64_t k = k0; k < kend; ++k) {
-      const double iv = mo.t_i[src + k];
-      if (iv >= cut) {
-        mo.t_tt[d] = mo.t_tt[src + k];
-        mo.t_i[d] = iv;
-        mo.t_mult[d] = mo.t_mult[src + k];
-        mo.t_first[d] = mo.t_first[src + k];
-        ++d;
+  int64_t d = u.r0 + (MOVE ? a.off[u.slot + kSlotKept] : 0);
+  for (int q = 0; q < kBigPer; ++q) {
+    const int64_t k = k0 + q * kBigThreads + threadIdx.x;
+    if (k0 + q * kBigThreads >= np) break;  // the same for the whole block
+    const double iv = k < np ? mo.t_i[src + k] : 0.0;
+    const bool keep = k < np && iv >= cut;
+    if constexpr (!MOVE) {
+      nk += keep ? 1 : 0;
+    } else {
+      int t;
+      const int r = big_block_rank(keep, red, &t);
+      if (keep) {
+        mo.t_tt[d + r] = mo.t_tt[src + k];
+        mo.t_i[d + r] = iv;
+        mo.t_mult[d + r] = mo.t_mult[src + k];
+        mo.t_first[d + r] = mo.t_first[src + k];
       }
+      d += t;
     }
   }
-}
-
-__global__ __launch_bounds__(64) void kb_scan_kept(BigArgs a, const BigChunk *__restrict__ crystals, MergeOut mo) {
-  const BigChunk bc = crystals[blockIdx.x];
-  const BigUnit u = big_unit(a, bc);
-  if (!u.live) return;
-  const int64_t kept = big_scan_chunks(a, bc, 2);
-  if (threadIdx.x == 0) mo.pk_count[u.c] = (int32_t)kept;
+  if constexpr (!MOVE) {
+    nk = big_block_sum(nk, red);
+    if (threadIdx.x == 0) a.cnt[u.slot + kSlotKept] = nk;
+  }
 }
 
 void big_sort(const SortArgs &s, const MergeOut &mo, hipStream_t st) {
@@ -645,19 +718,21 @@ void big_sort(const SortArgs &s, const MergeOut &mo, hipStream_t st) {
   a.off = s.big_off;
   a.np = s.big_np;
   const bool merge = mo.inten != nullptr;
-  const dim3 g((unsigned)s.n_big_chunks), b(kBigThreads), gc((unsigned)s.n_big);
+  const dim3 g((unsigned)s.n_big_chunks), b(kBigThreads), gc((unsigned)s.n_big), w(64);
   hipLaunchKernelGGL(kb_clear, g, b, 0, st, a, merge ? mo.cmax : nullptr);
   hipLaunchKernelGGL(kb_count, g, b, 0, st, a);
-  hipLaunchKernelGGL(kb_scan_bins, gc, dim3(1024), 0, st, a, s.big_crystals);
+  hipLaunchKernelGGL(kb_bin_sums, g, b, 0, st, a);
+  hipLaunchKernelGGL(kb_scan_counts<kScanBins>, gc, w, 0, st, a, s.big_crystals, mo);
+  hipLaunchKernelGGL(kb_scan_bins, g, b, 0, st, a);
   hipLaunchKernelGGL(kb_scatter, g, b, 0, st, a);
   hipLaunchKernelGGL(kb_binsort, g, b, 0, st, a);
   if (!merge && !a.ent_key) return;  // the sorted keys are the entries
   hipLaunchKernelGGL(kb_flags, g, b, 0, st, a, mo);
-  hipLaunchKernelGGL(kb_scan_counts, gc, dim3(64), 0, st, a, s.big_crystals, mo);
+  hipLaunchKernelGGL(kb_scan_counts<kScanFlags>, gc, w, 0, st, a, s.big_crystals, mo);
   hipLaunchKernelGGL(kb_write, g, b, 0, st, a, mo);
   if (!merge || !(mo.thr > 0.0)) return;
   hipLaunchKernelGGL(kb_keep<false>, g, b, 0, st, a, mo);
-  hipLaunchKernelGGL(kb_scan_kept, gc, dim3(64), 0, st, a, s.big_crystals, mo);
+  hipLaunchKernelGGL(kb_scan_counts<kScanKept>, gc, w, 0, st, a, s.big_crystals, mo);
   hipLaunchKernelGGL(kb_keep<true>, g, b, 0, st, a, mo);
 }
 

@@ -291,8 +291,8 @@ struct SortArgs {
   double *ent_key;       // [half capacity] 2theta of the evaluated half, sorted per crystal
   int32_t *ent_idx;      // its global reflection indices
   // crystals of capacity above kBigSort: their chunks and the crystals
-  // themselves, per-chunk counts and offsets (3 each) and per-crystal peak
-  // counts of the many-block sort
+  // themselves, per-chunk counters and their scans (4 each) and per-crystal
+  // peak counts of the many-block sort
   const BigChunk *big_chunks;
   int64_t n_big_chunks;
   const BigChunk *big_crystals;

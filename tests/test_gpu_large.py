@@ -81,6 +81,35 @@ def test_large_cell_sampled_parity(large, crystal, precision):
     assert worst <= (1e-4 if precision == "mixed" else 1e-10)
 
 
+@pytest.mark.parametrize("precision,friedel", [("mixed", True), ("fp64", False)])
+def test_large_cells_threshold_filters_the_peaks(large, precision, friedel):
+    """Two large cells merged with a relative threshold (each crystal above
+    2 * 6144 reflections, sorted over many blocks, its peaks staged, counted
+    and compacted): exactly the peaks of the unthresholded merge whose
+    intensity reaches thr times the crystal's largest, in order, bit for bit,
+    with the same 0-100 scale; the unthresholded merge is the one checked
+    against the oracle above."""
+    from paper_2602_11709_amd.api import simulate
+    b = large.subset([3, 12])
+    thr = 0.02
+    full = simulate(b, precision=precision, friedel=friedel)
+    cut = simulate(b, precision=precision, friedel=friedel, rel_threshold=thr)
+    np.testing.assert_array_equal(cut.perm, full.perm)
+    kept = 0
+    for c in range(b.n_crystals):
+        a0, a1 = full.peak_offset[c], full.peak_offset[c + 1]
+        iv = full.pk_intensity[a0:a1]
+        keep = np.flatnonzero(iv >= thr * iv.max())
+        g0, g1 = cut.peak_offset[c], cut.peak_offset[c + 1]
+        print(precision, "crystal", c, "peaks", a1 - a0, "kept", len(keep), flush=True)
+        assert 0 < len(keep) < a1 - a0
+        assert g1 - g0 == len(keep)
+        for name in ("pk_two_theta", "pk_intensity", "pk_scaled", "pk_mult", "pk_first"):
+            np.testing.assert_array_equal(getattr(cut, name)[g0:g1], getattr(full, name)[a0:a1][keep], err_msg=name)
+        kept += len(keep)
+    assert cut.peak_offset[-1] == kept
+
+
 def test_database_stream_slice_full_parity():
     """The first 512 crystals of the database-scale stream (Mo K-alpha,
     2theta 2-60, 1-1000 atoms log-normal): every reflection and peak."""
