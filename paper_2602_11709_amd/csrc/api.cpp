@@ -35,6 +35,8 @@ struct xrd_batch {
   std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
   std::vector<int32_t> sort_items;     // the sort launch's two crystal lists (n_small + n_crystals)
   std::vector<BigChunk> big_chunks, big_crystals;  // the many-block sort's chunks and crystals
+  int64_t big_hist = 0, big_buckets = 0;           // its (chunk, bucket) counters and buckets in all
+  int32_t big_nb_max = 0;
   std::vector<int32_t> sf_order;   // crystals by descending atom count
   std::vector<int32_t> sf_likely;  // per crystal: tiles its expected reflection count fills
   std::vector<SfItem> sf_items, sf_items_bw;  // launch orders of the forward sum and the adjoint
@@ -529,7 +531,8 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     // also writes its peak offset)
     P.sort_chunks = (int32_t)std::max<int64_t>(1, ceil_div(2 * P.half_box, kSortChunk));
     sc += P.sort_chunks;
-    P.n_bins = (int32_t)std::max<int64_t>(1, 2 * P.half_box / kBinDiv);
+    // (the many-block sort of the largest crystals uses buckets of its own)
+    P.n_bins = 2 * P.half_box > kBigSort ? 1 : (int32_t)std::max<int64_t>(1, 2 * P.half_box / kBinDiv);
     P.bin_begin = bins;
     P.bin_scale = (double)P.n_bins / (P.tmax - P.tmin);
     bins += P.n_bins;
@@ -655,13 +658,28 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     // every chunk of their capacity
     b->big_chunks.clear();
     b->big_crystals.clear();
+    b->big_hist = b->big_buckets = 0;
+    b->big_nb_max = 0;
     int32_t first = 0;
     for (int32_t c : by_expect) {
-      if (2 * b->plan[c].half_box <= kBigSort) continue;
-      const int32_t n = (int32_t)ceil_div(2 * b->plan[c].half_box, kBigChunk);
-      b->big_crystals.push_back(BigChunk{c, 0, first, n});
-      for (int32_t k = 0; k < n; ++k) b->big_chunks.push_back(BigChunk{c, k, first, n});
+      const int64_t cap = 2 * b->plan[c].half_box;
+      if (cap <= kBigSort) continue;
+      const int32_t n = (int32_t)ceil_div(cap, kBigChunk);
+      // buckets of 128-256 capacity slots (about 70-130 reflections), a
+      // power of two in [64, kBigBucketsMax]
+      int32_t nb = 64;
+      while (nb < kBigBucketsMax && (int64_t)nb * 256 < cap) nb *= 2;
+      const BigChunk bc{c, 0, first, n, nb, 0, b->big_hist, b->big_buckets};
+      b->big_crystals.push_back(bc);
+      for (int32_t k = 0; k < n; ++k) {
+        BigChunk ck = bc;
+        ck.chunk = k;
+        b->big_chunks.push_back(ck);
+      }
       first += n;
+      b->big_hist += (int64_t)n * nb;
+      b->big_buckets += nb;
+      b->big_nb_max = std::max(b->big_nb_max, nb);
     }
   }
   // peak chunks: a crystal's peaks are about half its reflections (mates share 2theta)
@@ -781,9 +799,12 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   const int64_t nbc = (int64_t)b->big_chunks.size(), nbig = (int64_t)b->big_crystals.size();
   L.big_chunks = take((int64_t)sizeof(BigChunk) * nbc);
   L.big_crystals = take((int64_t)sizeof(BigChunk) * nbig);
-  L.big_cnt = take(4 * 4 * nbc);
-  L.big_off = take(8 * 4 * nbc);
+  L.big_cnt = take(4 * 3 * nbc);
+  L.big_off = take(8 * 3 * nbc);
   L.big_np = take(4 * nc);
+  L.big_hist = take(4 * b->big_hist);
+  L.big_boff = take(8 * b->big_buckets);
+  L.big_over = take(8 * b->big_buckets + 8);
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(ec, bins), rc);
   L.scan_part = take(8 * scan_part_elems(scan_n));
   L.bw_w1 = L.bw_w2 = L.bw_ga = L.bw_gb = L.bw_dq = L.bw_part = L.bw_partf = L.bw_part6 = -1;
@@ -839,9 +860,12 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     M.sort_items = take(4 * (b->n_small + nc));
     M.big_chunks = take((int64_t)sizeof(BigChunk) * nbc);
     M.big_crystals = take((int64_t)sizeof(BigChunk) * nbig);
-    M.big_cnt = take(4 * 4 * nbc);
-    M.big_off = take(8 * 4 * nbc);
+    M.big_cnt = take(4 * 3 * nbc);
+    M.big_off = take(8 * 3 * nbc);
     M.big_np = take(4 * nc);
+    M.big_hist = take(4 * b->big_hist);
+    M.big_boff = take(8 * b->big_buckets);
+    M.big_over = take(8 * b->big_buckets + 8);
     M.total = o;
   }
   *out = b;
@@ -1121,6 +1145,11 @@ static SortArgs sort_args(xrd_batch *b, void *ws, const WsLayout &L, const xrd_r
   a.big_cnt = at<int32_t>(ws, L.big_cnt);
   a.big_off = at<int64_t>(ws, L.big_off);
   a.big_np = at<int32_t>(ws, L.big_np);
+  a.big_nb_max = b->big_nb_max;
+  a.big_hist = at<int32_t>(ws, L.big_hist);
+  a.big_boff = at<int64_t>(ws, L.big_boff);
+  a.big_buckets = b->big_buckets;
+  a.big_over = at<int2>(ws, L.big_over);
   return a;
 }
 

@@ -285,35 +285,37 @@ __device__ void sort_global(int64_t c, const CrystalPlan *__restrict__ plan, con
 
 // ---- many-block global-memory sort ------------------------------------------
 //
-// The same sort and merge as sort_global, for crystals of capacity above
+// The order and merge of sort_global, for crystals of capacity above
 // kBigSort, spread over blocks of kBigChunk reflections, sorted positions or
-// peak slots (or kBigBins bins) each, one launch per phase (a phase ends
-// before the next reads its results, so no block waits on another):
-//   clear the bins -> count (global atomics) -> per-chunk bin sums -> their
-//   scan per crystal -> the bins' scan within each chunk -> scatter -> order
-//   each bin on (2theta, global index) -> peak-start and entry flags with
-//   per-chunk counts -> their scan per crystal -> write the entries and the
-//   peaks (each sum in sorted order).
-// With a relative threshold the peaks are staged in the upper half of the
-// crystal's reflection slots (a crystal has at most R/2 peaks: both mates of
-// a Friedel pair share 2theta bit for bit, so every peak holds both), then
-// counted, scanned and compacted to its lower half.  Every result is that of
-// sort_global: the same bins, order, anchor-rule decisions and sums.
+// peak slots each, one launch per phase (a phase ends before the next reads
+// its results, so no block waits on another), with no global atomics in the
+// sort:
+//   per-chunk histograms of nb 2theta buckets (monotone in 2theta, LDS
+//   counters) -> a scan over the chunks of each bucket -> a scan over the
+//   buckets -> scatter (each chunk's items to its ranges of their buckets,
+//   ranked with LDS atomics) -> each bucket ordered in LDS on (2theta, global
+//   index) by a bitonic network -> peak-start and entry flags with per-chunk counts ->
+//   their scan per crystal -> write the entries and the peaks (each sum in
+//   sorted order).
+// The order on (2theta, global index) is total, so it is the one sort_global
+// produces, whatever the bucketing.  With a relative threshold the peaks are
+// staged in the upper half of the crystal's reflection slots (a crystal has
+// at most R/2 peaks: both mates of a Friedel pair share 2theta bit for bit,
+// so every peak holds both), then counted, scanned and compacted to its
+// lower half.
 constexpr int kBigThreads = 256;
 constexpr int kBigPer = kBigChunk / kBigThreads;  // 16
-constexpr int kBigBins = kBigChunk / kBinDiv;     // bins per block of the bin phases
-static_assert(kBigBins == 4 * kBigThreads, "four consecutive bins per thread");
 // per-chunk counters (cnt) and their scans per crystal (off)
-enum BigSlot { kSlotPeaks = 0, kSlotEntries = 1, kSlotKept = 2, kSlotBins = 3, kBigSlots = 4 };
-constexpr int kBinSortRegs = 8;  // bins up to this size are ordered in registers
+enum BigSlot { kSlotPeaks = 0, kSlotEntries = 1, kSlotKept = 2, kBigSlots = 3 };
+constexpr int kWaveBucket = 512;   // items of a bucket ordered by one wavefront in LDS
+constexpr int kBucketCap = 2048;   // ... by a block (the rare larger buckets); beyond, by insertion in place
+constexpr int kOverBlocks = 64;    // blocks taking the buckets above kWaveBucket
 
 struct BigArgs {
   const BigChunk *chunks;
   const CrystalPlan *plan;
   const int64_t *refl_offset;
   const double *tt;
-  int32_t *bin_count;
-  int64_t *bin_start;
   double *skey;
   int32_t *sidx;
   double *ent_key;  // null without Friedel pairing
@@ -321,6 +323,10 @@ struct BigArgs {
   int32_t *cnt;     // [kBigSlots n_big_chunks]
   int64_t *off;     // [kBigSlots n_big_chunks]
   int32_t *np;      // [n_c] peaks of a crystal
+  int32_t *hist;    // per (chunk, bucket): count, then the exclusive scan over the chunks
+  int64_t *boff;    // per (crystal, bucket): total, then the exclusive scan over the buckets
+  int2 *over;       // (crystal list index, bucket) of the buckets above kWaveBucket items
+  int32_t *n_over;  // their number
 };
 
 // The crystal of a chunk, if the many-block sort takes it (more than
@@ -375,139 +381,245 @@ __device__ __forceinline__ int big_block_rank(bool f, int32_t *red, int *total) 
   return below;
 }
 
-__global__ __launch_bounds__(kBigThreads) void kb_clear(BigArgs a, uint64_t *__restrict__ cmax) {
-  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
-  if (!u.live) return;
-  const CrystalPlan &P = a.plan[u.c];
-  const int64_t b0 = (int64_t)u.chunk * kBigBins;
-  for (int64_t b = b0 + threadIdx.x; b < min(b0 + kBigBins, (int64_t)P.n_bins); b += kBigThreads)
-    a.bin_count[P.bin_begin + b] = 0;
-  if (u.chunk == 0 && threadIdx.x == 0 && cmax) cmax[u.c] = 0ull;
+// Bucket of 2theta t among nb (floor of an affine map with a positive slope,
+// each step of which preserves order in IEEE arithmetic, so the bucket order
+// never contradicts the key order).
+__device__ __forceinline__ int big_bucket(const CrystalPlan &P, int nb, double t) {
+#pragma clang fp contract(off)
+  const double x = floor((t - P.tmin) * ((double)nb / (P.tmax - P.tmin)));
+  return x < 0.0 ? 0 : (x >= (double)(nb - 1) ? nb - 1 : (int)x);
 }
 
-__global__ __launch_bounds__(kBigThreads) void kb_count(BigArgs a) {
-  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
-  if (!u.live) return;
+// Chunks holding reflections (the others take no part).
+__device__ __forceinline__ int64_t big_filled_chunks(const BigUnit &u) { return (u.R + kBigChunk - 1) / kBigChunk; }
+
+// Per chunk: its reflections' bucket counts (LDS atomics), written out.
+__global__ __launch_bounds__(kBigThreads) void kb_hist(BigArgs a, uint64_t *__restrict__ cmax) {
+  __shared__ int32_t h[kBigBucketsMax];
+  const BigChunk bc = a.chunks[blockIdx.x];
+  const BigUnit u = big_unit(a, bc);
+  if (!u.live || u.chunk >= big_filled_chunks(u)) return;
+  if (u.chunk == 0 && threadIdx.x == 0 && cmax) cmax[u.c] = 0ull;
   const CrystalPlan &P = a.plan[u.c];
+  const int nb = bc.nb;
+  for (int b = threadIdx.x; b < nb; b += kBigThreads) h[b] = 0;
+  __syncthreads();
   const int64_t i0 = (int64_t)u.chunk * kBigChunk;
   for (int64_t i = i0 + threadIdx.x; i < min(i0 + kBigChunk, u.R); i += kBigThreads)
-    atomicAdd(&a.bin_count[P.bin_begin + bin_of(P, a.tt[u.r0 + i])], 1);
+    atomicAdd(&h[big_bucket(P, nb, a.tt[u.r0 + i])], 1);
+  __syncthreads();
+  int32_t *__restrict__ out = a.hist + bc.hbase + (int64_t)u.chunk * nb;
+  for (int b = threadIdx.x; b < nb; b += kBigThreads) out[b] = h[b];
 }
 
-// A chunk's four consecutive bins of this thread (zero past the crystal's).
-__device__ __forceinline__ int big_bins4(const BigArgs &a, const CrystalPlan &P, const BigUnit &u, int (&v)[4]) {
-  const int64_t b = (int64_t)u.chunk * kBigBins + 4 * (int64_t)threadIdx.x;
-  int s = 0;
+// Per (crystal, bucket), a thread: the exclusive scan of the bucket's counts
+// over the filled chunks (in place) and its total.
+__global__ __launch_bounds__(kBigThreads) void kb_colscan(BigArgs a, const BigChunk *__restrict__ crystals) {
+  const BigChunk bc = crystals[blockIdx.x];
+  const BigUnit u = big_unit(a, bc);
+  const int b = (int)blockIdx.y * kBigThreads + (int)threadIdx.x;
+  if (!u.live || b >= bc.nb) return;
+  const int64_t nk = big_filled_chunks(u);
+  int32_t *__restrict__ col = a.hist + bc.hbase + b;
+  int64_t run = 0;
+  int64_t k = 0;
+  for (; k + 8 <= nk; k += 8) {
+    int32_t v[8];
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    v[q] = b + q < P.n_bins ? a.bin_count[P.bin_begin + b + q] : 0;
+    for (int q = 0; q < 8; ++q) v[q] = col[(k + q) * bc.nb];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      col[(k + q) * bc.nb] = (int32_t)run;
+      run += v[q];
+    }
+  }
+  for (; k < nk; ++k) {
+    const int32_t v = col[k * bc.nb];
+    col[k * bc.nb] = (int32_t)run;
+    run += v;
+  }
+  a.boff[bc.bbase + b] = run;
+}
+
+// Per crystal: the exclusive scan of its bucket totals (in place), a
+// thread's consecutive buckets at a time.
+__global__ __launch_bounds__(kBigThreads) void kb_bscan(BigArgs a, const BigChunk *__restrict__ crystals) {
+  __shared__ int32_t wsum[kBigThreads / 64];
+  constexpr int PER = kBigBucketsMax / kBigThreads;  // 32
+  if (blockIdx.x == 0 && threadIdx.x == 0) *a.n_over = 0;
+  const BigChunk bc = crystals[blockIdx.x];
+  const BigUnit u = big_unit(a, bc);
+  if (!u.live) return;
+  int64_t *__restrict__ bo = a.boff + bc.bbase;
+  const int b0 = (int)threadIdx.x * PER;
+  int v[PER], s = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    v[q] = b0 + q < bc.nb ? (int)bo[b0 + q] : 0;
     s += v[q];
   }
-  return s;
-}
-
-__global__ __launch_bounds__(kBigThreads) void kb_bin_sums(BigArgs a) {
-  __shared__ int32_t red[kBigThreads / 64];
-  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
-  if (!u.live) return;
-  int v[4];
-  const int s = big_block_sum(big_bins4(a, a.plan[u.c], u, v), red);
-  if (threadIdx.x == 0) a.cnt[u.slot + kSlotBins] = s;
-}
-
-// bin_start of the chunk's bins: the exclusive scan of the counts within the
-// chunk plus the chunk's offset.
-__global__ __launch_bounds__(kBigThreads) void kb_scan_bins(BigArgs a) {
-  __shared__ int32_t wsum[kBigThreads / 64];
-  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
-  if (!u.live) return;
-  const CrystalPlan &P = a.plan[u.c];
-  int v[4];
-  const int s = big_bins4(a, P, u, v);
   int total;
-  int64_t o = a.off[u.slot + kSlotBins] + block_exclusive_scan<kBigThreads>(s, wsum, &total);
-  const int64_t b = (int64_t)u.chunk * kBigBins + 4 * (int64_t)threadIdx.x;
+  int64_t o = block_exclusive_scan<kBigThreads>(s, wsum, &total);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (b + q < P.n_bins) a.bin_start[P.bin_begin + b + q] = o;
+  for (int q = 0; q < PER; ++q) {
+    if (b0 + q < bc.nb) bo[b0 + q] = o;
     o += v[q];
   }
 }
 
+// Per chunk: each reflection to the next slot of its bucket's range for
+// this chunk (the bucket's offset plus the chunk's column prefix), ranked
+// with LDS atomics; the order inside a bucket is settled afterwards.
 __global__ __launch_bounds__(kBigThreads) void kb_scatter(BigArgs a) {
-  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
-  if (!u.live) return;
+  __shared__ int32_t cur[kBigBucketsMax];
+  const BigChunk bc = a.chunks[blockIdx.x];
+  const BigUnit u = big_unit(a, bc);
+  if (!u.live || u.chunk >= big_filled_chunks(u)) return;
   const CrystalPlan &P = a.plan[u.c];
-  int32_t *__restrict__ bc = a.bin_count + P.bin_begin;
-  const int64_t *__restrict__ bs = a.bin_start + P.bin_begin;
+  const int nb = bc.nb;
+  const int32_t *__restrict__ col = a.hist + bc.hbase + (int64_t)u.chunk * nb;
+  // the chunk's reflections load while the cursors are set up, eight
+  // cursors' loads in flight per thread at a time
   const int64_t i0 = (int64_t)u.chunk * kBigChunk;
-  for (int64_t i = i0 + threadIdx.x; i < min(i0 + kBigChunk, u.R); i += kBigThreads) {
-    const double t = a.tt[u.r0 + i];
-    const int b = bin_of(P, t);
-    const int64_t slot = u.r0 + bs[b] + atomicSub(&bc[b], 1) - 1;
-    a.skey[slot] = t;
-    a.sidx[slot] = (int32_t)(u.r0 + i);
+  double t[kBigPer];
+#pragma unroll
+  for (int q = 0; q < kBigPer; ++q) {
+    const int64_t i = i0 + q * kBigThreads + threadIdx.x;
+    t[q] = i < u.R ? a.tt[u.r0 + i] : 0.0;
+  }
+  for (int b0 = threadIdx.x; b0 < nb; b0 += 8 * kBigThreads) {
+    int64_t o[8];
+    int32_t c[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int b = b0 + q * kBigThreads;
+      o[q] = b < nb ? a.boff[bc.bbase + b] : 0;
+      c[q] = b < nb ? col[b] : 0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (b0 + q * kBigThreads < nb) cur[b0 + q * kBigThreads] = (int32_t)o[q] + c[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kBigPer; ++q) {
+    const int64_t i = i0 + q * kBigThreads + threadIdx.x;
+    if (i < u.R) {
+      const int64_t slot = u.r0 + atomicAdd(&cur[big_bucket(P, nb, t[q])], 1);
+      a.skey[slot] = t[q];
+      a.sidx[slot] = (int32_t)(u.r0 + i);
+    }
   }
 }
 
-// Order of each bin on (2theta, global index), a bin per thread: up to
-// kBinSortRegs items by an odd-even transposition network in registers
-// (padded with keys that sort last), larger bins by insertion in place.
-__global__ __launch_bounds__(kBigThreads) void kb_binsort(BigArgs a) {
-  const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
-  if (!u.live) return;
-  const CrystalPlan &P = a.plan[u.c];
-  const int64_t nb = P.n_bins;
-  const int64_t *__restrict__ bs = a.bin_start + P.bin_begin;
-  const int64_t b0 = (int64_t)u.chunk * kBigBins;
-  for (int q = 0; q < kBigBins / kBigThreads; ++q) {
-    const int64_t b = b0 + q * kBigThreads + threadIdx.x;
-    if (b >= nb) break;
-    const int64_t s0 = u.r0 + bs[b], e0 = b + 1 < nb ? u.r0 + bs[b + 1] : u.r0 + u.R;
-    const int64_t n = e0 - s0;
-    if (n <= 1) continue;
-    if (n <= kBinSortRegs) {
-      double k[kBinSortRegs];
-      int32_t x[kBinSortRegs];
-#pragma unroll
-      for (int i = 0; i < kBinSortRegs; ++i) {
-        k[i] = i < n ? a.skey[s0 + i] : __builtin_inf();
-        x[i] = i < n ? a.sidx[s0 + i] : INT32_MAX;
+// Ascending bitonic network over the n items at gk/gx, staged in LDS at
+// sk/sx (room for the next power of two N >= n; padding sorts last) by the
+// T threads ``t`` = 0 .. T-1 of a wavefront (T = 64) or of a block, which
+// ``sync`` orders; pair p compares slot i (bit j clear) with i + j,
+// ascending where bit k of i is clear.
+template <int T, typename Sync>
+__device__ __forceinline__ void bitonic_bucket(double *__restrict__ gk, int32_t *__restrict__ gx, int n, double *sk,
+                                               int32_t *sx, int t, Sync sync) {
+  int N = 2;
+  while (N < n) N <<= 1;
+  for (int i = t; i < N; i += T) {
+    sk[i] = i < n ? gk[i] : __builtin_inf();
+    sx[i] = i < n ? gx[i] : INT32_MAX;
+  }
+  sync();
+  for (int k = 2; k <= N; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int p = t; p < N / 2; p += T) {
+        const int i = 2 * p - (p & (j - 1)), l = i + j;
+        const double ki = sk[i], kl = sk[l];
+        const int32_t xi = sx[i], xl = sx[l];
+        const bool gt = ki > kl || (ki == kl && xi > xl);
+        if (gt == ((i & k) == 0)) {
+          sk[i] = kl;
+          sk[l] = ki;
+          sx[i] = xl;
+          sx[l] = xi;
+        }
       }
-#pragma unroll
-      for (int r = 0; r < kBinSortRegs; ++r)
-#pragma unroll
-        for (int i = r & 1; i + 1 < kBinSortRegs; i += 2) {
-          const bool sw = k[i] > k[i + 1] || (k[i] == k[i + 1] && x[i] > x[i + 1]);
-          const double tk = sw ? k[i + 1] : k[i];
-          const int32_t tx = sw ? x[i + 1] : x[i];
-          k[i + 1] = sw ? k[i] : k[i + 1];
-          x[i + 1] = sw ? x[i] : x[i + 1];
-          k[i] = tk;
-          x[i] = tx;
-        }
-#pragma unroll
-      for (int i = 0; i < kBinSortRegs; ++i)
-        if (i < n) {
-          a.skey[s0 + i] = k[i];
-          a.sidx[s0 + i] = x[i];
-        }
+      sync();
+    }
+  for (int i = t; i < n; i += T) {
+    gk[i] = sk[i];
+    gx[i] = sx[i];
+  }
+}
+
+__device__ __forceinline__ void big_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// A bucket's range of sorted positions (relative to the crystal's r0).
+__device__ __forceinline__ void big_bucket_range(const BigArgs &a, const BigChunk &bc, const BigUnit &u, int b,
+                                                 int64_t *s0, int *n) {
+  *s0 = a.boff[bc.bbase + b];
+  const int64_t e0 = b + 1 < bc.nb ? a.boff[bc.bbase + b + 1] : u.R;
+  *n = (int)(e0 - *s0);
+}
+
+// Per (crystal, bucket), a wavefront (four buckets to a block): the bucket's
+// items ordered in LDS on (2theta, global index) and written back.  Buckets
+// above kWaveBucket items, which the bucket sizing makes rare, are listed
+// for kb_bsort_over.
+__global__ __launch_bounds__(kBigThreads) void kb_bsort(BigArgs a, const BigChunk *__restrict__ crystals) {
+  __shared__ double sk[kBigThreads / 64][kWaveBucket];
+  __shared__ int32_t sx[kBigThreads / 64][kWaveBucket];
+  const BigChunk bc = crystals[blockIdx.x];
+  const BigUnit u = big_unit(a, bc);
+  const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
+  const int b = (int)blockIdx.y * (kBigThreads / 64) + wid;
+  if (!u.live || b >= bc.nb) return;
+  int64_t s0;
+  int n;
+  big_bucket_range(a, bc, u, b, &s0, &n);
+  if (n <= 1) return;
+  if (n > kWaveBucket) {
+    if (lane == 0) a.over[atomicAdd(a.n_over, 1)] = make_int2((int)blockIdx.x, b);
+    return;
+  }
+  bitonic_bucket<64>(a.skey + u.r0 + s0, a.sidx + u.r0 + s0, n, sk[wid], sx[wid], lane, [] { big_wave_sync(); });
+}
+
+// The listed buckets above kWaveBucket items, a block each in turn: the
+// bitonic network in LDS up to kBucketCap items, an insertion sort in place
+// by one thread beyond.
+__global__ __launch_bounds__(kBigThreads) void kb_bsort_over(BigArgs a, const BigChunk *__restrict__ crystals) {
+  __shared__ double sk[kBucketCap];
+  __shared__ int32_t sx[kBucketCap];
+  const int n_over = *a.n_over;
+  for (int o = blockIdx.x; o < n_over; o += gridDim.x) {
+    const int2 w = a.over[o];
+    const BigChunk bc = crystals[w.x];
+    const BigUnit u = big_unit(a, bc);
+    int64_t s0;
+    int n;
+    big_bucket_range(a, bc, u, w.y, &s0, &n);
+    double *__restrict__ gk = a.skey + u.r0 + s0;
+    int32_t *__restrict__ gx = a.sidx + u.r0 + s0;
+    if (n <= kBucketCap) {
+      bitonic_bucket<kBigThreads>(gk, gx, n, sk, sx, (int)threadIdx.x, [] { __syncthreads(); });
+      __syncthreads();  // the LDS is reused by the next bucket
       continue;
     }
-    for (int64_t xi = s0 + 1; xi < e0; ++xi) {
-      const double kx = a.skey[xi];
-      const int32_t ix = a.sidx[xi];
-      int64_t j = xi - 1;
-      while (j >= s0) {
-        const double kj = a.skey[j];
-        const int32_t ij = a.sidx[j];
-        if (!(kj > kx || (kj == kx && ij > ix))) break;
-        a.skey[j + 1] = kj;
-        a.sidx[j + 1] = ij;
-        --j;
+    if (threadIdx.x == 0) {
+      for (int xi = 1; xi < n; ++xi) {
+        const double kx = gk[xi];
+        const int32_t ix = gx[xi];
+        int j = xi - 1;
+        while (j >= 0 && (gk[j] > kx || (gk[j] == kx && gx[j] > ix))) {
+          gk[j + 1] = gk[j];
+          gx[j + 1] = gx[j];
+          --j;
+        }
+        gk[j + 1] = kx;
+        gx[j + 1] = ix;
       }
-      a.skey[j + 1] = kx;
-      a.sidx[j + 1] = ix;
     }
   }
 }
@@ -582,18 +694,16 @@ __device__ int64_t big_scan_chunks(const BigArgs &a, const BigChunk &bc, int k) 
   return carry;
 }
 
-// Scans per crystal: the bin sums (BINS), or the entry and peak counts, or
-// the kept counts; with the peak counts the crystal's peak count (and, with
-// no threshold to follow, its kept count), with the kept counts the latter.
-enum BigScan { kScanBins, kScanFlags, kScanKept };
+// Scans per crystal: the entry and peak counts, or the kept counts; with
+// the peak counts the crystal's peak count (and, with no threshold to
+// follow, its kept count), with the kept counts the latter.
+enum BigScan { kScanFlags, kScanKept };
 template <int WHICH>
 __global__ __launch_bounds__(64) void kb_scan_counts(BigArgs a, const BigChunk *__restrict__ crystals, MergeOut mo) {
   const BigChunk bc = crystals[blockIdx.x];
   const BigUnit u = big_unit(a, bc);
   if (!u.live) return;
-  if constexpr (WHICH == kScanBins) {
-    big_scan_chunks(a, bc, kSlotBins);
-  } else if constexpr (WHICH == kScanFlags) {
+  if constexpr (WHICH == kScanFlags) {
     big_scan_chunks(a, bc, kSlotEntries);
     if (mo.inten == nullptr) return;
     const int64_t np = big_scan_chunks(a, bc, kSlotPeaks);
@@ -708,8 +818,6 @@ void big_sort(const SortArgs &s, const MergeOut &mo, hipStream_t st) {
   a.plan = s.plan;
   a.refl_offset = s.refl_offset;
   a.tt = s.tt;
-  a.bin_count = s.bin_count;
-  a.bin_start = s.bin_start;
   a.skey = s.skey;
   a.sidx = s.sidx;
   a.ent_key = s.friedel ? s.ent_key : nullptr;
@@ -717,15 +825,20 @@ void big_sort(const SortArgs &s, const MergeOut &mo, hipStream_t st) {
   a.cnt = s.big_cnt;
   a.off = s.big_off;
   a.np = s.big_np;
+  a.hist = s.big_hist;
+  a.boff = s.big_boff;
+  a.over = s.big_over;
+  a.n_over = reinterpret_cast<int32_t *>(s.big_over + s.big_buckets);
   const bool merge = mo.inten != nullptr;
   const dim3 g((unsigned)s.n_big_chunks), b(kBigThreads), gc((unsigned)s.n_big), w(64);
-  hipLaunchKernelGGL(kb_clear, g, b, 0, st, a, merge ? mo.cmax : nullptr);
-  hipLaunchKernelGGL(kb_count, g, b, 0, st, a);
-  hipLaunchKernelGGL(kb_bin_sums, g, b, 0, st, a);
-  hipLaunchKernelGGL(kb_scan_counts<kScanBins>, gc, w, 0, st, a, s.big_crystals, mo);
-  hipLaunchKernelGGL(kb_scan_bins, g, b, 0, st, a);
+  const dim3 gcols((unsigned)s.n_big, (unsigned)((s.big_nb_max + kBigThreads - 1) / kBigThreads));
+  const dim3 gbuckets((unsigned)s.n_big, (unsigned)((s.big_nb_max + 3) / 4));
+  hipLaunchKernelGGL(kb_hist, g, b, 0, st, a, merge ? mo.cmax : nullptr);
+  hipLaunchKernelGGL(kb_colscan, gcols, b, 0, st, a, s.big_crystals);
+  hipLaunchKernelGGL(kb_bscan, gc, b, 0, st, a, s.big_crystals);
   hipLaunchKernelGGL(kb_scatter, g, b, 0, st, a);
-  hipLaunchKernelGGL(kb_binsort, g, b, 0, st, a);
+  hipLaunchKernelGGL(kb_bsort, gbuckets, b, 0, st, a, s.big_crystals);
+  hipLaunchKernelGGL(kb_bsort_over, dim3(kOverBlocks), b, 0, st, a, s.big_crystals);
   if (!merge && !a.ent_key) return;  // the sorted keys are the entries
   hipLaunchKernelGGL(kb_flags, g, b, 0, st, a, mo);
   hipLaunchKernelGGL(kb_scan_counts<kScanFlags>, gc, w, 0, st, a, s.big_crystals, mo);

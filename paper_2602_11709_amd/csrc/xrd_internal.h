@@ -135,10 +135,15 @@ struct HChunk {
 
 // Unit of the many-block global-memory sort: chunk ``chunk`` of crystal
 // ``crystal``, whose n chunks hold the slots first .. first + n - 1 of the
-// per-chunk count and offset arrays (the crystal list uses chunk = 0).
+// per-chunk count and offset arrays, whose nb 2theta buckets have their
+// per-chunk counts at hbase + chunk nb + bucket and their offsets at bbase +
+// bucket (the crystal list uses chunk = 0).
 struct BigChunk {
-  int32_t crystal, chunk, first, n;
+  int32_t crystal, chunk, first, n, nb, pad;
+  int64_t hbase, bbase;
 };
+static_assert(sizeof(BigChunk) == 40, "BigChunk layout");
+constexpr int kBigBucketsMax = 8192;  // 2theta buckets of a crystal in the many-block sort, at most
 
 // Structure-factor work item: a tile of reflections of one crystal, with
 // the crystal's atom range and species-run slots (from the plan), so that a
@@ -163,7 +168,9 @@ struct WsLayout {
   int64_t flags;
   int64_t cmax, pk_count, tmp_tt, tmp_i, tmp_mult, tmp_first;
   int64_t sort_items;  // the sort launch's crystal lists
-  int64_t big_chunks, big_crystals, big_cnt, big_off, big_np;  // the many-block sort's tables and scratch
+  int64_t big_chunks, big_crystals, big_cnt, big_off, big_np, big_hist, big_boff, big_over;  // the many-block
+                                                                                             // sort's tables
+                                                                                             // and scratch
   int64_t scan_part;
   int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6, bw_partf;
   int64_t sf_deriv;  // kept (A, B, dA/ds^2, dB/ds^2) per reflection, or -1
@@ -291,15 +298,20 @@ struct SortArgs {
   double *ent_key;       // [half capacity] 2theta of the evaluated half, sorted per crystal
   int32_t *ent_idx;      // its global reflection indices
   // crystals of capacity above kBigSort: their chunks and the crystals
-  // themselves, per-chunk counters and their scans (4 each) and per-crystal
-  // peak counts of the many-block sort
+  // themselves, per-chunk counters and their scans (3 each), per-crystal
+  // peak counts and the bucket counters of the many-block sort
   const BigChunk *big_chunks;
   int64_t n_big_chunks;
   const BigChunk *big_crystals;
   int64_t n_big;
+  int32_t big_nb_max;  // most buckets of a crystal
   int32_t *big_cnt;
   int64_t *big_off;
   int32_t *big_np;
+  int32_t *big_hist;   // per (chunk, bucket) counts, then their column scans
+  int64_t *big_boff;   // per (crystal, bucket) totals, then their offsets
+  int64_t big_buckets; // buckets in all
+  int2 *big_over;      // [big_buckets] large buckets listed by the wavefront sort, then their count (int32)
 };
 // Two more streams for independent work inside one call: the caller's stream
 // records ``fork``, the side streams wait for it, run their parts and record
