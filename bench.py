@@ -72,6 +72,11 @@ UNIT_OPS = {
 }
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result goes to stdout)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def unit_peak_per_s(kernel):
     """Units per second at the peak rates (costs of the classes added)."""
     ops = UNIT_OPS[kernel]
@@ -98,6 +103,8 @@ def parse():
     ap.add_argument("--no-rates", action="store_true", help="skip the instruction-rate microbenchmark")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (to scale HBM counters), then exit")
+    ap.add_argument("--config", choices=["rocksalt", "large_cells", "gradient_256", "database_stream"],
+                    help="only run this workload's leg (printed as one JSON object), then exit")
     return ap.parse_args()
 
 
@@ -329,6 +336,7 @@ def leg_recurrence(batch, reps):
     includes building its segments), evaluated terms per second, the
     recurrence kernel's own time, and the forward step (enumerate, structure
     factors, merge) per replay."""
+    progress("leg_recurrence")
     import torch
     out = {}
     for precision in ("mixed", "fp64"):
@@ -355,6 +363,7 @@ def leg_database(chunk=8192, planners=6):
     chunks planned on host threads while the GPU computes; peaks stay on the
     device.  Also per bin of reflection count (the paper's Fig. 8 bins), the
     bins' crystals streamed on their own."""
+    progress("leg_database")
     import oracle
     from paper_2602_11709_amd import synth
     from paper_2602_11709_amd.stream import DatabaseStream
@@ -401,6 +410,7 @@ def leg_database(chunk=8192, planners=6):
 def leg_rocksalt(steps):
     """The single rock-salt cell (the closed-form pin case), plain FP64 path
     as the configuration names it, and the mixed path: forward pattern."""
+    progress("leg_rocksalt")
     import oracle
     from paper_2602_11709_amd import synth
     b = synth.rocksalt()
@@ -450,7 +460,9 @@ def leg_large_cells(steps):
     """The large-cell stress batch (16 cells of 2000-5000 atoms, ~2e5-5e5
     reflections each): mixed path, plain FP64 path evaluating every
     reflection, and FP64 with Friedel halving (so the precision alone is
-    compared with the mixed path)."""
+    compared with the mixed path).  The structure-factor method is the
+    library's "auto" choice, which the autotuner settles per batch (direct
+    sums or the row recurrence above an atom threshold)."""
     from paper_2602_11709_amd import synth
     b = synth.large_cells()
     out = {"workload": "large_cells: 16 cells (8 monoclinic, 8 triclinic), a,b,c~U(30,50) A, 2000-5000 atoms, "
@@ -458,7 +470,8 @@ def leg_large_cells(steps):
     peaks = {}
     for name, precision, friedel in (("mixed", "mixed", True), ("fp64", "fp64", False),
                                      ("fp64_friedel", "fp64", True)):
-        f = Forward(b, precision, friedel, autotune=True)
+        progress(f"large cells, {name}")
+        f = Forward(b, precision, friedel, sf_method="auto", autotune=True)
         ms = f.replay_ms(steps)
         sf = f.sf_ms(3)
         full, ev = f.terms()
@@ -491,6 +504,7 @@ def leg_gradients(steps):
     """The differentiation workload (256 crystals of 50-500 atoms, 4001-point
     pattern): one step = enumerate, structure factors keeping dF/ds^2, the
     broadened pattern and its adjoint for a fixed dL/dy, mixed and FP64."""
+    progress("leg_gradients")
     from concurrent.futures import ThreadPoolExecutor
     import oracle
     import torch
@@ -735,6 +749,7 @@ def cpu_baseline(batch):
     """The oracle on the host: whole passes over the workload on the host
     threads until about 20 thread-seconds, and one thread on a crystal
     sample for the single-core figure."""
+    progress("cpu_baseline")
     import oracle
     threads = host_threads()
     model, visible = cpu_info()
@@ -819,6 +834,11 @@ def main():
     if not torch.cuda.is_available():
         print("no GPU visible", file=sys.stderr)
         sys.exit(1)
+    if args.config:
+        legs = {"rocksalt": lambda: leg_rocksalt(20), "large_cells": lambda: leg_large_cells(3),
+                "gradient_256": lambda: leg_gradients(5), "database_stream": leg_database}
+        print(json.dumps({args.config: legs[args.config]()}), flush=True)
+        return
     graph = not args.no_graph
     batch = synth.triclinic_1024()
     rates = None if args.no_rates else rates_live()
