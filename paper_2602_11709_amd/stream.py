@@ -95,12 +95,15 @@ class DatabaseStream:
     """Peaks (2theta, intensity, 0-100 scaled intensity, multiplicity) of every
     crystal of ``batch``, in chunks of ``chunk`` consecutive crystals.
 
-    ``planners`` host threads plan chunks ahead of the GPU.  ``run`` calls
+    ``planners`` host threads plan chunks ahead of the GPU.  With ``ramp``
+    the first chunks grow (an eighth, a quarter and a half of ``chunk``), so
+    that the GPU starts after planning a small chunk rather than a full one.
+    ``run`` calls
     ``consume(ChunkPeaks)`` once per chunk, in order, with device views of the
     chunk's peaks (and, with ``to_host``, host copies instead)."""
 
     def __init__(self, batch: CrystalBatch, chunk: int = 4096, precision: str = "mixed",
-                 sf_method: str = "direct", planners: int = 4, device="cuda"):
+                 sf_method: str = "direct", planners: int = 4, device="cuda", ramp: bool = True):
         if precision not in PRECISIONS:
             raise ValueError(f"precision must be one of {list(PRECISIONS)}")
         if sf_method not in SF_METHODS:
@@ -116,7 +119,12 @@ class DatabaseStream:
         self.sf_method = sf_method
         self.planners = planners
         n = batch.n_crystals
-        self.bounds = [(c0, min(c0 + chunk, n)) for c0 in range(0, n, chunk)]
+        self.bounds = []
+        c0, size = 0, max(1, chunk // 8) if ramp else chunk
+        while c0 < n:
+            self.bounds.append((c0, min(c0 + size, n)))
+            c0 += size
+            size = min(2 * size, chunk)
         dev = self.device
         f64 = dict(dtype=torch.float64, device=dev)
         # every atom on the device once; a chunk's descriptor points into these

@@ -33,7 +33,8 @@ def test_stream_matches_one_batch_and_oracle(precision, method):
 
     st = DatabaseStream(b, chunk=600, precision=precision, sf_method=method, planners=3).run(consume, to_host=True)
     print(precision, method, {k: v for k, v in st.items() if not isinstance(v, float) or v < 1e9}, flush=True)
-    assert sorted(got) == [0, 600, 1200, 1800, 2400]  # the last chunk is ragged
+    # chunks of 75, 150, 300, then 600 (the last one ragged)
+    assert sorted(got) == [0, 75, 225, 525, 1125, 1725, 2325]
     whole = simulate(b, precision=precision, sf_method=method)
     assert st["reflections"] == int(whole.refl_offset[-1]) and st["peaks"] == int(whole.peak_offset[-1])
     for c0, cp in got.items():
@@ -58,9 +59,10 @@ def test_stream_device_hand_over_and_empty_chunks():
     from tests.test_gpu_forward import ragged_batch
     b = ragged_batch()
     dev = []
-    DatabaseStream(b, chunk=5, planners=2).run(lambda cp: dev.append(cp.intensity.cpu().numpy().copy()))
+    DatabaseStream(b, chunk=5, planners=2, ramp=False).run(lambda cp: dev.append(cp.intensity.cpu().numpy().copy()))
     host = []
-    DatabaseStream(b, chunk=5, planners=2).run(lambda cp: host.append(cp.intensity.numpy().copy()), to_host=True)
+    DatabaseStream(b, chunk=5, planners=2, ramp=False).run(lambda cp: host.append(cp.intensity.numpy().copy()),
+                                                           to_host=True)
     assert len(dev) == len(host) == 3
     for a, c in zip(dev, host):
         np.testing.assert_array_equal(a, c)
@@ -75,8 +77,8 @@ def test_peak_numbering_with_and_without_the_scan():
     from paper_2602_11709_amd.stream import DatabaseStream
     b = synth.database_stream(n_crystals=5000)
     got = {}
-    DatabaseStream(b, chunk=2500, precision="mixed", planners=2).run(lambda cp: got.__setitem__(cp.first, cp),
-                                                                     to_host=True)
+    DatabaseStream(b, chunk=2500, precision="mixed", planners=2, ramp=False).run(
+        lambda cp: got.__setitem__(cp.first, cp), to_host=True)
     whole = simulate(b, precision="mixed")
     assert sorted(got) == [0, 2500]
     for c0, cp in got.items():
