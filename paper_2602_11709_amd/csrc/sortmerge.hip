@@ -628,9 +628,13 @@ __global__ __launch_bounds__(kBigThreads) void kb_bsort_over(BigArgs a, const Bi
 // rule walked from the start of its component (the last position at or
 // before j with such a gap, or 0) up to j.  The same decisions as the one
 // walker per component of sort_global, taken by each position for itself.
+// A key equal to its predecessor's never opens a peak (tol > 0: the anchor
+// is at most that key), which keeps shells of many equivalent reflections
+// from walking.
 __device__ __forceinline__ bool big_peak_start(const double *__restrict__ k, int64_t j, double tol) {
 #pragma clang fp contract(off)
   if (j == 0 || k[j] - k[j - 1] >= tol) return true;
+  if (k[j] == k[j - 1]) return false;
   int64_t s = j - 1;
   while (s > 0 && k[s] - k[s - 1] < tol) --s;
   double anchor = k[s];

@@ -81,6 +81,44 @@ def test_large_cell_sampled_parity(large, crystal, precision):
     assert worst <= (1e-4 if precision == "mixed" else 1e-10)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_large_cubic_cell_exact_ties(precision):
+    """A rock-salt cell of a = 40 A: about 2e5 reflections in shells of up to
+    ~700 with one 2theta (equivalent reflections and coincident h^2+k^2+l^2),
+    sorted over many blocks, with buckets of clumped equal keys (some above
+    the one-wavefront size) and long runs of equal keys for the anchor rule.
+    The reflection list, the sorted order and the peak partition exactly
+    against the oracle's enumeration, sort and merge; sampled peak
+    intensities against the oracle's structure factors of their members."""
+    from paper_2602_11709_amd.api import simulate
+    b = synth.rocksalt(a=40.0)
+    res = simulate(b, precision=precision)
+    hkl, q, tt, amb = oracle.enumerate_hkl(b.lattice[0], b.wavelength, b.two_theta_min[0], b.two_theta_max[0])
+    n = len(tt)
+    print(precision, "cubic cell reflections", n, "peaks", len(res.pk_mult), flush=True)
+    assert n > 1.5e5 and amb == 0
+    np.testing.assert_array_equal(res.hkl, hkl)
+    assert np.max(np.abs(res.two_theta - tt)) <= 1e-9
+    perm_g = oracle.sort_order(res.two_theta, res.hkl)
+    np.testing.assert_array_equal(res.perm, perm_g)
+    g_tt, _, g_m, g_f, _ = oracle.merge(res.two_theta[perm_g], np.zeros(n), b.merge_tol)
+    np.testing.assert_array_equal(res.pk_mult, g_m)
+    np.testing.assert_array_equal(res.pk_first, g_f)
+    np.testing.assert_array_equal(res.pk_two_theta, g_tt)
+    assert res.pk_mult.max() >= 500
+    rng = np.random.default_rng(40)
+    worst = 0.0
+    strong = np.nonzero(res.pk_intensity >= 1e-3 * res.pk_intensity.max())[0]
+    for p in rng.choice(strong, size=min(40, len(strong)), replace=False):
+        mem = res.perm[res.pk_first[p]: res.pk_first[p] + res.pk_mult[p]]
+        fr, fi, _ = oracle.structure_factors(hkl[mem], q[mem], b.frac, b.species, b.occ, b.bfac, b.sf_coeff)
+        lpv = np.array([oracle.lp(t) for t in tt[mem]])
+        want = float(((fr * fr + fi * fi) * lpv).sum())
+        worst = max(worst, abs(res.pk_intensity[p] - want) / want)
+    print(precision, "sampled strong-peak rel err", worst, flush=True)
+    assert worst <= (1e-4 if precision == "mixed" else 1e-10)
+
+
 @pytest.mark.parametrize("precision,friedel", [("mixed", True), ("fp64", False)])
 def test_large_cells_threshold_filters_the_peaks(large, precision, friedel):
     """Two large cells merged with a relative threshold (each crystal above
