@@ -172,21 +172,45 @@ def get_patterns(batch: CrystalBatch, wavelength: Union[float, str] = "CuKa", sc
                              fam_n=cpu(fam[0], mp), fam_label=cpu(fam[2], n), fam_mult=cpu(fam[3], n)))
     labels = np.array([label for _, _, label in lines])
     y_all = host["scaled"] if scaled else host["intensity"]
+    # each combined peak's members and families, gathered per line with array
+    # operations and turned into Python objects in bulk
+    hexa = np.array([is_hexagonal(batch.lattice[c]) for c in range(n_c)], dtype=bool)
+    peak_crystal = np.repeat(np.arange(n_c), np.diff(po))
+    members_of = [None] * m
+    families_of = [None] * m
+
+    def runs_of(start, count):
+        # start[p] + 0 .. count[p] - 1 for every p, concatenated
+        total = int(count.sum())
+        base = np.repeat(start - (np.cumsum(count) - count), count)
+        return base + np.arange(total, dtype=np.int64)
+
+    for li, L in enumerate(per_line):
+        sel = np.nonzero(host["line"] == li)[0]
+        if len(sel) == 0:
+            continue
+        src = host["source"][sel]
+        f = L["first"][src].astype(np.int64)
+        mlt = L["mult"][src].astype(np.int64)
+        rows = list(map(tuple, L["hkl"][L["perm"][runs_of(f, mlt)]].tolist()))
+        offs = np.concatenate([[0], np.cumsum(mlt)]).tolist()
+        nf = L["fam_n"][src].astype(np.int64)
+        fpos = runs_of(f, nf)
+        fh = L["hkl"][L["fam_label"][fpos]].astype(np.int64)
+        hx = np.repeat(hexa[peak_crystal[sel]], nf)
+        fm_mult = L["fam_mult"][fpos].tolist()
+        fl = [_label(r, x) for r, x in zip(fh.tolist(), hx.tolist())]
+        foffs = np.concatenate([[0], np.cumsum(nf)]).tolist()
+        for j, p in enumerate(sel.tolist()):
+            members_of[p] = rows[offs[j]:offs[j + 1]]
+            families_of[p] = [{"hkl": fl[q], "multiplicity": int(fm_mult[q])} for q in range(foffs[j], foffs[j + 1])]
     result = []
     for c in range(n_c):
         p0, p1 = int(po[c]), int(po[c + 1])
-        hexagonal = is_hexagonal(batch.lattice[c])
-        hk, fm = [], []
-        for li, src in zip(host["line"][p0:p1], host["source"][p0:p1]):
-            L = per_line[li]
-            f, mlt, nf = int(L["first"][src]), int(L["mult"][src]), int(L["fam_n"][src])
-            members = L["perm"][f:f + mlt]
-            hk.append([tuple(int(v) for v in L["hkl"][i]) for i in members])
-            fm.append([{"hkl": _label(L["hkl"][L["fam_label"][f + j]], hexagonal),
-                        "multiplicity": int(L["fam_mult"][f + j])} for j in range(nf)])
         result.append(DiffractionPattern(x=host["two_theta"][p0:p1].copy(), y=y_all[p0:p1].copy(),
                                          mult=host["mult"][p0:p1].copy(), d_hkls=host["d"][p0:p1].copy(),
-                                         hkls=fm, line=labels[host["line"][p0:p1]], members=hk))
+                                         hkls=families_of[p0:p1], line=labels[host["line"][p0:p1]],
+                                         members=members_of[p0:p1]))
     return result
 
 
