@@ -485,6 +485,17 @@ def leg_large_cells(steps):
                      "reflections": f.n_refl, "peaks": f.n_peaks, "autotune": f.tuned}
         peaks[name] = f.peaks()
         del f
+    # one cell alone (the paper times single large structures): the median
+    # cell by atom count, its whole forward as one graph replay
+    na = np.diff(b.atom_offset)
+    med = int(np.argsort(na)[len(na) // 2])
+    progress("large cells, one cell")
+    f = Forward(b.subset([med]), "mixed", True, sf_method="auto", autotune=True)
+    ms = f.replay_ms(10)
+    out["one_cell"] = {"crystal": med, "atoms": int(na[med]), "reflections": f.n_refl, "peaks": f.n_peaks,
+                       "ms_per_pattern": round(ms, 4), "precision": "mixed",
+                       "note": "enumerate, structure factors, merge of one cell, graph replay"}
+    del f
     po, got, m1 = peaks["mixed"]
     _, ref, m2 = peaks["fp64"]
     out["mixed_vs_fp64_same_peaks"] = bool(np.array_equal(m1, m2))
