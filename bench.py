@@ -540,6 +540,11 @@ def leg_gradients(steps):
             dy = torch.randn(b.n_crystals, grid.n_points, generator=torch.Generator().manual_seed(5),
                              dtype=torch.float64).cuda()
             grads = xb.new_grads()
+            # set-up: tile shape and split-K of both sums tuned on the enumerated reflections
+            xb.enumerate(refl)
+            split_fwd, split_bw, _ = xb.autotune(refl)
+            tuned = {"reflections_per_lane": xb.sf_rpt, "split_atoms_forward": split_fwd,
+                     "split_atoms_adjoint": split_bw}
 
         def fwd():
             xb.enumerate(refl)
@@ -568,7 +573,7 @@ def leg_gradients(steps):
         n_refl = np.diff(refl.refl_offset.cpu().numpy())
         full = int((n_refl * b.counts()).sum())
         out[precision] = {"ms_per_step": round(ms, 4), "patterns_per_s": round(b.n_crystals / (ms * 1e-3), 1),
-                          "forward_ms": round(fwd_ms, 4), "adjoint_ms": round(bwd_ms, 4),
+                          "forward_ms": round(fwd_ms, 4), "adjoint_ms": round(bwd_ms, 4), "autotune": tuned,
                           "reflections": int(n_refl.sum()), "sf_terms": full}
         del g, xb
     # the autograd path as an optimisation loop calls it: plan, forward, backward

@@ -1222,6 +1222,10 @@ __global__ __launch_bounds__(kThreads) void k_peak_move(const HChunk *__restrict
   const int np = mo.pk_count[c];
   const int64_t r0 = refl_offset[c];
   const double mx = __longlong_as_double((long long)mo.cmax[c]);
+  // chunks past the crystal's peaks (the table covers its capacity) have
+  // nothing to move; a crystal's chunk 0 still writes its offset and block 0
+  // the total
+  if (k0 >= np && ch.chunk != 0 && blockIdx.x != 0) return;
   // the chunk's staged peaks, loaded before the offset is known, so that their
   // latency overlaps the prefix sum's
   double tt[kPer], iv[kPer];

@@ -25,7 +25,8 @@ def _gpu():
 def first_batch():
     """Crystals of every sort size class: tiny and small cells, two of the
     mid class (8192-16384 reflections) and one above the single-block limits
-    (the global-memory sort path)."""
+    (capacity ~1e5: sorted in global memory over many blocks, with its
+    bucket tables in the fixed scratch too)."""
     small = synth.random_triclinic(71, 90, atoms_hi=80)
     big = synth.random_triclinic(72, 1, atoms_lo=20, atoms_hi=20, len_lo=24.0, len_hi=26.0)
     mid = synth.random_triclinic(73, 2, atoms_lo=10, atoms_hi=10, len_lo=13.0, len_hi=15.0)
