@@ -119,6 +119,44 @@ def test_large_cubic_cell_exact_ties(precision):
     assert worst <= (1e-4 if precision == "mixed" else 1e-10)
 
 
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_big_capacity_crystals_on_both_sort_paths(large, precision):
+    """One batch with a large cell over 5-120 deg (4e5 reflections: the
+    many-block sort), the same cell over 60-61 deg (capacity 1.6e5 but 3630
+    reflections: sorted in LDS, the many-block kernels pass it by) and over
+    0.1-0.2 deg (no reflection at all): per crystal, the reflection list,
+    the sorted order and the peak partition exactly against the oracle."""
+    import dataclasses
+    from paper_2602_11709_amd.api import simulate
+    b = large.subset([0, 0, 0])
+    tmin = np.array(b.two_theta_min, dtype=float)
+    tmax = np.array(b.two_theta_max, dtype=float)
+    tmin[1], tmax[1] = 60.0, 61.0
+    tmin[2], tmax[2] = 0.1, 0.2
+    b = dataclasses.replace(b, two_theta_min=tmin, two_theta_max=tmax)
+    res = simulate(b, precision=precision)
+    counts = []
+    for c in range(b.n_crystals):
+        hkl, q, tt, amb = oracle.enumerate_hkl(b.lattice[c], b.wavelength, tmin[c], tmax[c])
+        assert amb == 0
+        r0, r1 = int(res.refl_offset[c]), int(res.refl_offset[c + 1])
+        p0, p1 = int(res.peak_offset[c]), int(res.peak_offset[c + 1])
+        counts.append(r1 - r0)
+        np.testing.assert_array_equal(res.hkl[r0:r1], hkl)
+        if r1 == r0:
+            assert p1 == p0
+            continue
+        gtt, ghkl = res.two_theta[r0:r1], res.hkl[r0:r1]
+        perm = oracle.sort_order(gtt, ghkl)
+        np.testing.assert_array_equal(res.perm[r0:r1] - r0, perm)
+        o_tt, _, o_m, o_f, _ = oracle.merge(gtt[perm], np.zeros(r1 - r0), b.merge_tol)
+        np.testing.assert_array_equal(res.pk_mult[p0:p1], o_m)
+        np.testing.assert_array_equal(res.pk_first[p0:p1] - r0, o_f)
+        np.testing.assert_array_equal(res.pk_two_theta[p0:p1], o_tt)
+    print(precision, "reflections per crystal", counts, flush=True)
+    assert counts[0] > 2 * 6144 and 0 < counts[1] <= 2 * 6144 and counts[2] == 0
+
+
 @pytest.mark.parametrize("precision,friedel", [("mixed", True), ("fp64", False)])
 def test_large_cells_threshold_filters_the_peaks(large, precision, friedel):
     """Two large cells merged with a relative threshold (each crystal above
