@@ -807,10 +807,9 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
   L.big_over = take(8 * b->big_buckets + 8);
   int64_t scan_n = std::max<int64_t>(std::max<int64_t>(ec, bins), rc);
   L.scan_part = take(8 * scan_part_elems(scan_n));
-  L.bw_w1 = L.bw_w2 = L.bw_ga = L.bw_gb = L.bw_dq = L.bw_part = L.bw_partf = L.bw_part6 = -1;
+  L.bw_w12 = L.bw_ga = L.bw_gb = L.bw_dq = L.bw_part = L.bw_partf = L.bw_part6 = -1;
   if (adjoint) {
-    L.bw_w1 = take(8 * rc);
-    L.bw_w2 = take(8 * rc);
+    L.bw_w12 = take(16 * rc);
     L.bw_ga = take(8 * rc);
     L.bw_gb = take(8 * rc);
     L.bw_dq = take(8 * rc);
@@ -1280,16 +1279,16 @@ int xrd_pattern_backward(xrd_batch *b, void *ws, const xrd_refl *r, const xrd_gr
   const CrystalPlan *plan = at<CrystalPlan>(ws, L.plan);
   const SfItem *items = at<SfItem>(ws, L.sf_items_bw);
   const int64_t n_items = (int64_t)b->sf_items_bw.size();
-  double *w1 = at<double>(ws, L.bw_w1), *w2 = at<double>(ws, L.bw_w2);
+  double2 *w12 = at<double2>(ws, L.bw_w12);
   double *ga = at<double>(ws, L.bw_ga), *gb = at<double>(ws, L.bw_gb), *dq = at<double>(ws, L.bw_dq);
   ensure_sorted(b, ws, r);
   const void *deriv = (L.sf_deriv >= 0 && b->deriv_ws == ws && b->deriv_h == r->h) ? at<char>(ws, L.sf_deriv) : nullptr;
   launch_broaden_adj(mixed, at<HChunk>(ws, L.eblocks), (int64_t)b->eblocks.size(), plan, friedel,
                      r->refl_offset, at<double>(ws, L.ent_key), at<int32_t>(ws, L.ent_idx), dL_dy, g->t0, g->dt,
-                     g->n_points, g->sigma, g->window_sigmas, w1, w2, s);
+                     g->n_points, g->sigma, g->window_sigmas, w12, s);
   launch_sf_bw(mixed, friedel, items, n_items, b->sf_heavy_bw, plan, r->refl_offset, r->h, r->k, r->l, r->q, r->lp,
                b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count),
-               b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), deriv, w1, w2, ga, gb, dq, at<double>(ws, L.bw_part6),
+               b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), deriv, w12, ga, gb, dq, at<double>(ws, L.bw_part6),
                at<double>(ws, L.bw_partf), b->rpt, s);
   launch_atom_bw(mixed, friedel, at<BwItem>(ws, L.bw_items), (int64_t)b->bw_items.size(), plan, r->refl_offset,
                  r->h, r->k, r->l, r->q, ga, gb, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
@@ -1317,12 +1316,12 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
   double *I = at<double>(ws, L.tmp_first);
   void *deriv = L.sf_deriv >= 0 ? at<char>(ws, L.sf_deriv) : nullptr;
   const bool adjoint = !b->desc.forward_only;
-  double *w1 = adjoint ? at<double>(ws, L.bw_w1) : nullptr, *w2 = adjoint ? at<double>(ws, L.bw_w2) : nullptr;
+  double2 *w12 = adjoint ? at<double2>(ws, L.bw_w12) : nullptr;
   const int64_t nc = b->desc.n_crystals;
   auto run_bw = [&](const std::vector<SfItem> &t, int64_t nh) {
     launch_sf_bw(mixed, friedel, at<SfItem>(ws, L.sf_items_bw), (int64_t)t.size(), nh, plan, r->refl_offset, r->h,
                  r->k, r->l, r->q, r->lp, b->desc.wavelength, at<AtomRec>(ws, L.atoms), at<SpeciesRun>(ws, L.runs),
-                 at<int32_t>(ws, L.run_count), b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), deriv, w1, w2,
+                 at<int32_t>(ws, L.run_count), b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f), deriv, w12,
                  at<double>(ws, L.bw_ga), at<double>(ws, L.bw_gb), at<double>(ws, L.bw_dq), at<double>(ws, L.bw_part6),
                  at<double>(ws, L.bw_partf), b->rpt, s);
   };
@@ -1416,8 +1415,7 @@ int xrd_autotune(xrd_batch *b, void *ws, const xrd_refl *r, int32_t *split_out) 
     // the adjoint's inputs: derivatives of the chosen forward tables, zero grid weights
     if (e == hipSuccess) {
       launch_forward_sums(b, ws, r, A, B, I, deriv);
-      launch_fill_u64(reinterpret_cast<uint64_t *>(w1), b->refl_cap, 0, s);
-      launch_fill_u64(reinterpret_cast<uint64_t *>(w2), b->refl_cap, 0, s);
+      launch_fill_u64(reinterpret_cast<uint64_t *>(w12), 2 * b->refl_cap, 0, s);
       e = hipGetLastError();
     }
     std::vector<SfItem> t;

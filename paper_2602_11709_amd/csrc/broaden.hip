@@ -289,7 +289,9 @@ __global__ __launch_bounds__(256) void k_broaden_gather(const int32_t *__restric
 // interval of the grid; the block stages that stretch of the crystal's
 // dL/dy row in LDS (converted to the working precision) when it has at most
 // kAdjSpan points and reads the row from global memory otherwise.  Results
-// go to w1/w2 at the entries' reflection indices.
+// go to (w1, w2) records at the entries' reflection indices (one 16-byte
+// store each: the indices are scattered, so one store per record halves the
+// partial-line writes).
 template <typename real, typename src_t>
 __device__ __forceinline__ void adj_walk(const src_t *__restrict__ src, int off, int wl, int wh, const GridArgs &g,
                                          double t, real rho, real dtr, real *a1o, real *a2o) {
@@ -331,7 +333,7 @@ __global__ __launch_bounds__(256) void k_broaden_adj(const HChunk *__restrict__ 
                                                      const double *__restrict__ ent_key,
                                                      const int32_t *__restrict__ ent_idx,
                                                      const double *__restrict__ dy, GridArgs g,
-                                                     double *__restrict__ w1, double *__restrict__ w2) {
+                                                     double2 *__restrict__ w12) {
 #pragma clang fp contract(off)
   using real = typename std::conditional<MIXED, float, double>::type;
   __shared__ real s_dy[kAdjSpan];
@@ -385,8 +387,7 @@ __global__ __launch_bounds__(256) void k_broaden_adj(const HChunk *__restrict__ 
       adj_walk<real, real>(s_dy, lo, w[u].x, w[u].y, g, t[u], rho, dtr, &a1, &a2);
     else
       adj_walk<real, double>(dyc, 0, w[u].x, w[u].y, g, t[u], rho, dtr, &a1, &a2);
-    w1[idx[u]] = (double)a1;
-    w2[idx[u]] = (double)a2 * inv_s2;
+    w12[idx[u]] = make_double2((double)a1, (double)a2 * inv_s2);
   }
 }
 
@@ -433,17 +434,17 @@ void launch_broaden_fwd(bool mixed, const HChunk *eblocks, int64_t n_eblocks, co
 
 void launch_broaden_adj(bool mixed, const HChunk *eblocks, int64_t n_eblocks, const CrystalPlan *plan,
                         bool friedel, const int64_t *refl_offset, const double *ent_key, const int32_t *ent_idx,
-                        const double *dy, double t0, double dt, int64_t n, double sigma, double window, double *w1,
-                        double *w2, hipStream_t s) {
+                        const double *dy, double t0, double dt, int64_t n, double sigma, double window,
+                        double2 *w12, hipStream_t s) {
   if (n_eblocks <= 0 || n <= 0) return;
   const GridArgs g = make_grid(t0, dt, n, sigma, window);
   const dim3 grid((unsigned)n_eblocks), block(256);
   if (mixed)
     hipLaunchKernelGGL(k_broaden_adj<true>, grid, block, 0, s, eblocks, plan, friedel, refl_offset, ent_key,
-                       ent_idx, dy, g, w1, w2);
+                       ent_idx, dy, g, w12);
   else
     hipLaunchKernelGGL(k_broaden_adj<false>, grid, block, 0, s, eblocks, plan, friedel, refl_offset, ent_key,
-                       ent_idx, dy, g, w1, w2);
+                       ent_idx, dy, g, w12);
 }
 
 

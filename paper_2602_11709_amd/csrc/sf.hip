@@ -535,8 +535,7 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
                                                     const int32_t *__restrict__ run_count,
                                                     const double *__restrict__ coeff,
                                                     const CoeffF *__restrict__ coeff_f, const void *__restrict__ cache,
-                                                    const double *__restrict__ w1,
-                                                    const double *__restrict__ w2, double *__restrict__ ga,
+                                                    const double2 *__restrict__ w12, double *__restrict__ ga,
                                                     double *__restrict__ gb, double *__restrict__ dq,
                                                     double *__restrict__ part6, double4 *__restrict__ part_fused) {
   // heavy blocks without the kept derivatives: per wave, value (8 floats or
@@ -591,7 +590,8 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
       if (!valid[u]) continue;
       const int64_t i = idx[u];
       const double lp = lpp[i];
-      const double gI = m * w1[i];
+      const double2 wv = w12[i];
+      const double gI = m * wv.x;
       gA[u] = 2.0 * lp * A[u] * gI;
       gB[u] = 2.0 * lp * B[u] * gI;
       // the other parts of a split item need gA and gB alone
@@ -610,7 +610,7 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
         ga[i] = gA[u];
         gb[i] = gB[u];
       }
-      dqv[u] = gI * f2 * dlp_dq + 0.25 * (gA[u] * dA[u] + gB[u] * dB[u]) + m * w2[i] * f2 * lp * dtt_dq;
+      dqv[u] = gI * f2 * dlp_dq + 0.25 * (gA[u] * dA[u] + gB[u] * dB[u]) + m * wv.y * f2 * lp * dtt_dq;
       dq[i] = dqv[u];
     }
     if (ww.part == 0) {
@@ -1097,14 +1097,14 @@ void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
                   const int32_t *run_count, const double *coeff, const CoeffF *coeff_f, const void *deriv_cache,
-                  const double *w1, const double *w2, double *ga, double *gb, double *dq, double *part6,
-                  double *part_fused, int rpt, hipStream_t s) {
+                  const double2 *w12, double *ga, double *gb, double *dq, double *part6, double *part_fused,
+                  int rpt, hipStream_t s) {
   if (n_items <= 0) return;
   const dim3 grid((unsigned)(n_heavy + (n_items - n_heavy + 3) / 4)), block(kThreads);
   double4 *pf = (double4 *)part_fused;
 #define XRD_SF_BW(M, C, R)                                                                                          \
   hipLaunchKernelGGL((k_sf_bw<M, C, R>), grid, block, 0, s, items, n_items, n_heavy, friedel, plan, refl_offset, h, \
-                     k, l, q, lp, lambda, atoms, runs, run_count, coeff, coeff_f, deriv_cache, w1, w2, ga, gb, dq,  \
+                     k, l, q, lp, lambda, atoms, runs, run_count, coeff, coeff_f, deriv_cache, w12, ga, gb, dq,       \
                      part6, pf)
 #define XRD_SF_BW_R(M, C)   \
   if (rpt == 1)             \

@@ -172,7 +172,7 @@ struct WsLayout {
                                                                                              // sort's tables
                                                                                              // and scratch
   int64_t scan_part;
-  int64_t bw_w1, bw_w2, bw_ga, bw_gb, bw_dq, bw_part, bw_part6, bw_partf;
+  int64_t bw_w12, bw_ga, bw_gb, bw_dq, bw_part, bw_part6, bw_partf;  // bw_w12: (w1, w2) per reflection
   int64_t sf_deriv;  // kept (A, B, dA/ds^2, dB/ds^2) per reflection, or -1
   int64_t coeff_f;   // [n_species] CoeffF
   int64_t sf_items_bw;  // structure-factor items in the adjoint's launch order
@@ -360,15 +360,14 @@ void launch_broaden_fwd(bool mixed, const HChunk *eblocks, int64_t n_eblocks, co
                         double *y, hipStream_t s);
 void launch_broaden_adj(bool mixed, const HChunk *eblocks, int64_t n_eblocks, const CrystalPlan *plan,
                         bool friedel, const int64_t *refl_offset, const double *ent_key, const int32_t *ent_idx,
-                        const double *dy, double t0, double dt, int64_t n, double sigma, double window, double *w1,
-                        double *w2, hipStream_t s);
+                        const double *dy, double t0, double dt, int64_t n, double sigma, double window, double2 *w12,
+                        hipStream_t s);
 void launch_sf_bw(bool mixed, bool friedel, const SfItem *items, int64_t n_items, int64_t n_heavy,
                   const CrystalPlan *plan,
                   const int64_t *refl_offset, const int16_t *h, const int16_t *k, const int16_t *l, const double *q,
                   const double *lp, double lambda, const AtomRec *atoms, const SpeciesRun *runs,
                   const int32_t *run_count, const double *coeff, const CoeffF *coeff_f, const void *deriv_cache,
-                  const double *w1,
-                  const double *w2, double *ga, double *gb, double *dq, double *part6, double *part_fused,
+                  const double2 *w12, double *ga, double *gb, double *dq, double *part6, double *part_fused,
                   int rpt, hipStream_t s);
 size_t atom_bw_lds_bytes(bool mixed, int tile, int runs_cap);
 void launch_atom_bw(bool mixed, bool friedel, const BwItem *items, int64_t n_items, const CrystalPlan *plan,

@@ -46,14 +46,14 @@ void launch_broaden_fwd(bool, const HChunk *, int64_t, const CrystalPlan *, cons
   reached("broaden_fwd");
 }
 void launch_broaden_adj(bool, const HChunk *, int64_t, const CrystalPlan *, bool, const int64_t *, const double *,
-                        const int32_t *, const double *, double, double, int64_t, double, double, double *, double *,
+                        const int32_t *, const double *, double, double, int64_t, double, double, double2 *,
                         hipStream_t) {
   reached("broaden_adj");
 }
 void launch_sf_bw(bool, bool, const SfItem *, int64_t, int64_t, const CrystalPlan *, const int64_t *, const int16_t *,
                   const int16_t *, const int16_t *, const double *, const double *, double, const AtomRec *,
-                  const SpeciesRun *, const int32_t *, const double *, const CoeffF *, const void *, const double *,
-                  const double *, double *, double *, double *, double *, double *, int, hipStream_t) {
+                  const SpeciesRun *, const int32_t *, const double *, const CoeffF *, const void *, const double2 *,
+                  double *, double *, double *, double *, double *, int, hipStream_t) {
   reached("sf_bw");
 }
 void launch_atom_bw(bool, bool, const BwItem *, int64_t, const CrystalPlan *, const int64_t *, const int16_t *,
