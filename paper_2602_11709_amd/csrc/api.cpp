@@ -30,6 +30,7 @@ struct xrd_batch {
   std::vector<int64_t> atom_offset;
   std::vector<CrystalPlan> plan;
   std::vector<EnumChunk> enum_chunks;  // enumeration chunks, crystal by crystal
+  int64_t max_enum_chunks = 0;         // most chunks of one crystal (INT64_MAX if a crystal has none)
   std::vector<HChunk> peak_chunks;  // peak chunks of the merge (crystal, chunk)
   std::vector<HChunk> eblocks;  // entry blocks of the broadening (crystal, block of kEntBlock entries)
   std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
@@ -588,6 +589,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
       CrystalPlan &P = b->plan[c];
       P.enum_chunk_begin = ec;
       P.enum_chunks = (int32_t)chunks_of[c].size();
+      b->max_enum_chunks = P.enum_chunks == 0 ? INT64_MAX : std::max<int64_t>(b->max_enum_chunks, P.enum_chunks);
       ec += P.enum_chunks;
       b->enum_chunks.insert(b->enum_chunks.end(), chunks_of[c].begin(), chunks_of[c].end());
     }
@@ -984,7 +986,7 @@ int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r) {
                    b->desc.occ, b->desc.bfac, b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f),
                    at<AtomRec>(ws, L.atoms), at<AtomRot>(ws, L.rot), at<int32_t>(ws, L.atom_orig),
                    at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), at<int32_t>(ws, L.err_flag),
-                   stream_of(b));
+                   b->max_enum_chunks, stream_of(b));
   b->last_ws = ws;
   return hip_check("enumerate");
 }

@@ -344,7 +344,8 @@ __global__ __launch_bounds__(64) void k_atom_pack(const CrystalPlan *__restrict_
 __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__restrict__ plan,
                                                          const EnumChunk *__restrict__ chunks,
                                                          int64_t n_chunks, int64_t n_c, double lambda,
-                                                         int32_t *__restrict__ counts, PackArgs pa) {
+                                                         int32_t *__restrict__ counts,
+                                                         int64_t *__restrict__ block_sums, PackArgs pa) {
   const int64_t chunk_blocks = (n_chunks + kThreads / 64 - 1) / (kThreads / 64);
   const int64_t pack_blocks = (int64_t)gridDim.x - chunk_blocks;
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
@@ -357,18 +358,33 @@ __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__re
     return;
   }
   const int64_t chunk = (int64_t)(blockIdx.x - pack_blocks) * (kThreads / 64) + wid;
-  if (chunk >= n_chunks) return;
-  const EnumChunk ch = chunks[chunk];
-  const CrystalPlan &P = plan[ch.crystal];
-  int n = lane < ch.n_rows ? row_count(P, row_of(P, (int64_t)ch.row_begin + lane), lambda) : 0;
+  int n = 0;
+  if (chunk < n_chunks) {
+    const EnumChunk ch = chunks[chunk];
+    const CrystalPlan &P = plan[ch.crystal];
+    n = lane < ch.n_rows ? row_count(P, row_of(P, (int64_t)ch.row_begin + lane), lambda) : 0;
 #pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) n += __shfl_xor(n, d, 64);
-  if (lane == 0) counts[chunk] = n;
+    for (int d = 32; d >= 1; d >>= 1) n += __shfl_xor(n, d, 64);
+    if (lane == 0) counts[chunk] = n;
+  }
+  if (block_sums) {
+    // the block's four counts summed, for a fill that forms its own offsets
+    __shared__ int32_t s_n[kThreads / 64];
+    if (lane == 0) s_n[wid] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int64_t t = 0;
+#pragma unroll
+      for (int v = 0; v < kThreads / 64; ++v) t += s_n[v];
+      block_sums[blockIdx.x - pack_blocks] = t;
+    }
+  }
 }
 
 // Exclusive scan of the chunk counts and the crystal offsets in one block
 // (batches with up to kOneBlockChunks enumeration chunks).
 constexpr int kOneBlockChunks = 8192;
+constexpr int kSelfChunks = 256;  // most chunks of one crystal for a fill that forms its own offsets
 __global__ __launch_bounds__(1024) void k_enum_scan1(const CrystalPlan *__restrict__ plan, int64_t n_c,
                                                      int64_t n_chunks, const int32_t *__restrict__ counts,
                                                      int64_t *__restrict__ prefix, int64_t *__restrict__ refl_offset) {
@@ -432,30 +448,100 @@ __global__ void k_enum_offsets(const CrystalPlan *__restrict__ plan, int64_t n_c
   if (c == n_c) refl_offset[n_c] = 2 * prefix[n_chunks];
 }
 
+// Sum over a wavefront of one value per lane.
+__device__ __forceinline__ int32_t wave_sum_i32(int32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
 // One wavefront per chunk (lane = row, for the chunk's first n_rows lanes),
 // four chunks per block.  The chunk's rows are flattened into their candidate points in
 // lexicographic order; the wavefront then takes the points 64 at a time, one
 // per lane (a binary search over the rows' candidate offsets finds a point's
 // row), tests them, ranks the survivors with a ballot and writes each with
 // its Friedel mate: (h, k, l), q, 2theta and LP.
+//
+// Output positions come from the exclusive prefix P of the chunk counts: the
+// crystal starts at 2 P(first chunk), holds 2 (P(end) - P(first)) reflections,
+// and the chunk's survivors rank from P(chunk) - P(first).  Without SELF, P
+// is a scanned array.  With SELF (at most kOneBlockChunks chunks, at most
+// kSelfChunks per crystal) each block forms the values it needs from the
+// counts themselves, so no scan launch sits between the count and the fill:
+// the block sums the count launch's per-block sums before it (B = P(b0), b0
+// its first chunk; both launches take kThreads / 64 chunks per block), and each
+// wavefront sums the counts of [min(first, b0), end) in four parts, from
+// which P(first) = B - sum[first, b0) + sum[b0, first), the crystal's count
+// and the chunk's rank follow.  The wavefront at a crystal's first chunk
+// writes refl_offset[c] = 2 P(first) (and refl_offset[n_c] for the last
+// crystal): every crystal has at least one chunk.
+template <bool SELF>
 __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__restrict__ plan,
                                                         const EnumChunk *__restrict__ chunks,
                                                         int64_t n_chunks, const int64_t *__restrict__ prefix,
+                                                        const int32_t *__restrict__ counts,
+                                                        const int64_t *__restrict__ block_sums, int64_t n_c,
+                                                        int64_t *__restrict__ refl_offset,
                                                         double lambda, int16_t *__restrict__ oh,
                                                         int16_t *__restrict__ ok, int16_t *__restrict__ ol,
                                                         double *__restrict__ oq, double *__restrict__ ott,
                                                         double *__restrict__ olp) {
   __shared__ int32_t s_off[kThreads / 64][kEnumRows + 1];  // candidate offsets of a wavefront's rows
   __shared__ int32_t s_lo[kThreads / 64][kEnumRows], s_h[kThreads / 64][kEnumRows], s_k[kThreads / 64][kEnumRows];
+  __shared__ int64_t s_red[kThreads / 64];
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
   const int64_t chunk = (int64_t)blockIdx.x * (kThreads / 64) + wid;
-  if (chunk >= n_chunks) return;
-  const EnumChunk ch = chunks[chunk];
+  const bool live = chunk < n_chunks;
+  // wavefronts past the last chunk read the last one (they only take part in
+  // the block's sum)
+  const EnumChunk ch = chunks[live ? chunk : n_chunks - 1];
   const CrystalPlan &P = plan[ch.crystal];
   const int64_t first_chunk = P.enum_chunk_begin;
-  const int64_t c_begin = prefix[first_chunk];
-  const int64_t rh = prefix[first_chunk + P.enum_chunks] - c_begin;  // positive-half count
-  const int64_t seg = 2 * c_begin;                                     // crystal's first reflection
+  int64_t c_begin, rh, rank0;
+  if constexpr (SELF) {
+    // every load first: the block sums before this block, then the counts
+    // of [min(first, b0), end) (at most kSelfChunks + 3 of them)
+    const int64_t b0 = (int64_t)blockIdx.x * (kThreads / 64), end = first_chunk + P.enum_chunks;
+    const int64_t lo = min(first_chunk, b0);
+    int64_t part = 0;
+#pragma unroll
+    for (int u = 0; u < kOneBlockChunks / (kThreads / 64) / kThreads; ++u) {
+      const int64_t i = (int64_t)u * kThreads + threadIdx.x;
+      if (i < (int64_t)blockIdx.x) part += block_sums[i];
+    }
+    int32_t before_b0 = 0, b0_to_first = 0, first_to_chunk = 0, crystal = 0;
+#pragma unroll
+    for (int u = 0; u < kSelfChunks / 64 + 1; ++u) {
+      const int64_t i = lo + u * 64 + lane;
+      if (i < end) {
+        const int32_t v = counts[i];
+        before_b0 += i < b0 ? v : 0;
+        b0_to_first += i >= b0 && i < first_chunk ? v : 0;
+        first_to_chunk += i >= first_chunk && i < chunk ? v : 0;
+        crystal += i >= first_chunk ? v : 0;
+      }
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) part += __shfl_xor(part, d, 64);
+    if (lane == 0) s_red[wid] = part;
+    c_begin = wave_sum_i32(b0_to_first) - (int64_t)wave_sum_i32(before_b0);
+    rank0 = wave_sum_i32(first_to_chunk);
+    rh = wave_sum_i32(crystal);
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < kThreads / 64; ++v) c_begin += s_red[v];
+    if (!live) return;
+    if (chunk == first_chunk && lane == 0) {
+      refl_offset[ch.crystal] = 2 * c_begin;
+      if (ch.crystal == n_c - 1) refl_offset[n_c] = 2 * (c_begin + rh);
+    }
+  } else {
+    if (!live) return;
+    c_begin = prefix[first_chunk];
+    rh = prefix[first_chunk + P.enum_chunks] - c_begin;  // positive-half count
+    rank0 = prefix[chunk] - c_begin;
+  }
+  const int64_t seg = 2 * c_begin;  // crystal's first reflection
   int lo = 1, hi = 0;
   Row r{0, 0, 1, 0};
   if (lane < ch.n_rows) {
@@ -479,7 +565,7 @@ __global__ __launch_bounds__(kThreads) void k_enum_fill(const CrystalPlan *__res
   }
   if (lane == 0) off[kEnumRows] = total;
   wave_sync();
-  int64_t rank = prefix[chunk] - c_begin;
+  int64_t rank = rank0;
   // four candidates per lane per round: their searches, tests and 2theta
   // are independent, so their latencies overlap
   constexpr int U = 4;
@@ -537,8 +623,15 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const EnumChunk *chu
                       int16_t *k, int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset,
                       int32_t n_species, const double *frac, const int32_t *species, const double *occ,
                       const double *bfac, const double *coeff, CoeffF *coeff_f, AtomRec *atoms, AtomRot *rot,
-                      int32_t *orig, SpeciesRun *runs, int32_t *run_count, int32_t *err, hipStream_t s) {
+                      int32_t *orig, SpeciesRun *runs, int32_t *run_count, int32_t *err, int64_t max_crystal_chunks,
+                      hipStream_t s) {
   const PackArgs pa{n_species, frac, species, occ, bfac, coeff, coeff_f, atoms, rot, orig, runs, run_count, err};
+  // the fill forms its own offsets when the counts are few and every crystal
+  // has at least one chunk (so that one wavefront writes its offset)
+  const bool self = n_chunks > 0 && n_chunks <= kOneBlockChunks && n_chunks >= n_c &&
+                    max_crystal_chunks <= kSelfChunks;
+  // the per-block sums of the counts take the scanned prefix's place
+  int64_t *block_sums = self ? prefix : nullptr;
   // the packing rides along in the count launch while its cursors stay small
   const size_t fused_lds = (size_t)(kThreads / 64) * n_species * sizeof(int32_t);
   const bool fuse = n_chunks > 0 && fused_lds <= kFusedPackLds;
@@ -549,18 +642,26 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const EnumChunk *chu
     const int64_t chunk_blocks = (n_chunks + kThreads / 64 - 1) / (kThreads / 64);
     const int64_t pack_blocks = fuse ? (n_c + kThreads / 64 - 1) / (kThreads / 64) : 0;
     hipLaunchKernelGGL(k_enum_count, dim3((unsigned)(chunk_blocks + pack_blocks)), dim3(kThreads),
-                       fuse ? fused_lds : 0, s, plan, chunks, n_chunks, n_c, lambda, counts, pa);
+                       fuse ? fused_lds : 0, s, plan, chunks, n_chunks, n_c, lambda, counts, block_sums, pa);
   }
-  if (n_chunks <= kOneBlockChunks) {
-    hipLaunchKernelGGL(k_enum_scan1, dim3(1), dim3(1024), 0, s, plan, n_c, n_chunks, counts, prefix, refl_offset);
-  } else {
-    launch_scan_i32(counts, n_chunks, nullptr, prefix, scan_part, s);
-    hipLaunchKernelGGL(k_enum_offsets, dim3((unsigned)((n_c + 1 + 255) / 256)), dim3(256), 0, s, plan, n_c, n_chunks,
-                       prefix, refl_offset);
+  if (!self) {
+    if (n_chunks <= kOneBlockChunks) {
+      hipLaunchKernelGGL(k_enum_scan1, dim3(1), dim3(1024), 0, s, plan, n_c, n_chunks, counts, prefix,
+                         refl_offset);
+    } else {
+      launch_scan_i32(counts, n_chunks, nullptr, prefix, scan_part, s);
+      hipLaunchKernelGGL(k_enum_offsets, dim3((unsigned)((n_c + 1 + 255) / 256)), dim3(256), 0, s, plan, n_c,
+                         n_chunks, prefix, refl_offset);
+    }
   }
   if (n_chunks > 0) {
-    hipLaunchKernelGGL(k_enum_fill, dim3((unsigned)((n_chunks + kThreads / 64 - 1) / (kThreads / 64))),
-                       dim3(kThreads), 0, s, plan, chunks, n_chunks, prefix, lambda, h, k, l, q, tt, lp);
+    const dim3 grid((unsigned)((n_chunks + kThreads / 64 - 1) / (kThreads / 64)));
+    if (self)
+      hipLaunchKernelGGL(k_enum_fill<true>, grid, dim3(kThreads), 0, s, plan, chunks, n_chunks, prefix, counts,
+                         block_sums, n_c, refl_offset, lambda, h, k, l, q, tt, lp);
+    else
+      hipLaunchKernelGGL(k_enum_fill<false>, grid, dim3(kThreads), 0, s, plan, chunks, n_chunks, prefix, counts,
+                         block_sums, n_c, refl_offset, lambda, h, k, l, q, tt, lp);
   }
 }
 
