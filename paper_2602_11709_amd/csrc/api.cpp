@@ -1090,12 +1090,19 @@ static void release_side(xrd_batch *b) {
 
 // The batch's side streams on the current device (default priority,
 // non-blocking), or none if they cannot be made (then everything runs on the
-// caller's stream).
+// caller's stream).  They are made at the first call outside stream capture
+// (making a stream would end a capture); a call captured before that runs on
+// the caller's stream alone.
 static Fork side_of(xrd_batch *b) {
   const Fork none{nullptr, nullptr, nullptr, nullptr, nullptr};
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return none;
   if (b->side_device != dev) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream_of(b), &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+      (void)hipGetLastError();
+      return none;
+    }
     release_side(b);
     bool ok = hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) == hipSuccess &&
               hipStreamCreateWithFlags(&b->side2, hipStreamNonBlocking) == hipSuccess &&

@@ -81,3 +81,34 @@ def test_mixed_size_launch_against_oracle(precision, method):
         st = compare_crystal_sampled(res, c, b, precision, rng, label="mixed sizes")
         print(precision, "large crystal", c, "atoms", int(sizes[c]), st, flush=True)
     print(precision, "small crystals", len(small), worst_small, "reflections", int(res.refl_offset[-1]), flush=True)
+
+
+def test_first_structure_factor_call_captured_runs_on_one_stream():
+    """Under sf_method "auto" this batch takes both the recurrence and the
+    direct sum, which split over a side stream of the batch.  When the
+    batch's first such call is captured in a graph there is no side stream yet
+    (making one would end the capture), so the call runs on the batch's
+    stream alone; its replays match a later eager (forked) call bit for bit."""
+    from paper_2602_11709_amd.api import XrdBatch
+    b, _ = mixed_batch()
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        xb = XrdBatch(b, precision="mixed", sf_method="auto")
+        refl, sf = xb.new_reflections(), xb.new_sf()
+        xb.enumerate(refl)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        xb.structure_factors(refl, sf)
+    with torch.cuda.stream(s):
+        xb.structure_factors(refl, sf)
+    torch.cuda.synchronize()
+    n = int(refl.refl_offset[-1])
+    want = sf[2][:n].clone()
+    print("reflections", n, flush=True)
+    for rep in range(3):
+        sf[2].fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(sf[2][:n], want), f"replay {rep}"
