@@ -140,3 +140,24 @@ def test_many_species_packs_atoms_in_their_own_launch(precision):
     worst = compare_batch(res, b, orcs, precision, "many species")
     assert worst["ambiguous"] == 0
     print(precision, worst, flush=True)
+
+
+def test_offsets_formed_by_the_fill_for_mid_size_crystals():
+    """Cells of 22-28 A (1.6e4-3.5e4 positive-half reflections: more than 64
+    enumeration chunks of at most 256 candidates each, so a fill wavefront
+    sums its crystal's chunk counts over several passes of its lanes, and
+    below 256 chunks, so the fill forms the crystal offsets itself) between
+    small crystals: every reflection list exactly, structure factors and
+    strong peaks sampled, against the oracle."""
+    from tests.parity import compare_crystal_sampled
+    small = synth.random_triclinic(35, 6, atoms_lo=1, atoms_hi=30, len_lo=3.0, len_hi=9.0)
+    mid = synth.random_triclinic(36, 4, atoms_lo=5, atoms_hi=20, len_lo=22.0, len_hi=28.0)
+    mid.sf_coeff = small.sf_coeff
+    b = concat([small.subset(range(3)), mid.subset([0, 1]), small.subset(range(3, 6)), mid.subset([2, 3])])
+    res = run(b, "mixed")
+    counts = np.diff(res.refl_offset) // 2
+    print("positive-half reflections", counts.tolist(), flush=True)
+    assert counts.max() > 64 * 256
+    rng = np.random.default_rng(0)
+    for c in range(b.n_crystals):
+        compare_crystal_sampled(res, c, b, "mixed", rng, n_sample=200, n_strong=30, label="mid-size")
