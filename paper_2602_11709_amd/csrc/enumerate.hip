@@ -341,6 +341,8 @@ __global__ __launch_bounds__(64) void k_atom_pack(const CrystalPlan *__restrict_
 // the chunks need: the first blocks take four crystals each, one per
 // wavefront, with n_species LDS cursors per wavefront; they come first so
 // that their serial chains start with the counts rather than after them.
+// With block_sums, each counting block also writes the sum of its four
+// counts (block b of the counting blocks: chunks 4b .. 4b + 3).
 __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__restrict__ plan,
                                                          const EnumChunk *__restrict__ chunks,
                                                          int64_t n_chunks, int64_t n_c, double lambda,
