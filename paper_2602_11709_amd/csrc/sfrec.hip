@@ -61,9 +61,13 @@ __device__ __forceinline__ bool continues_row(const int16_t *__restrict__ h, con
 }
 
 // Segment counts: one block per (crystal, kEntBlock entries); an entry that
-// starts a run (its predecessor is in another row or not at l - 1) walks
-// its run and records ceil(run / kRecLen) segments, every other entry 0.
-// Block 0 also records the batch's entry count for the scan.
+// starts a run (its predecessor is in another row or not at l - 1) records
+// ceil(run / kRecLen) segments, every other entry 0.  A run's length is
+// the distance to the next run start: the block ballots its run starts into
+// a kEntBlock-bit mask in LDS, and wavefront 0 measures how far the row of
+// the block's last entry continues past the block (64 entries a round), for
+// the last run that starts in the block.  Block 0 also records the batch's
+// entry count for the scan.
 __global__ __launch_bounds__(kThreads) void k_seg_count(const HChunk *__restrict__ eblocks, int64_t n_c,
                                                         const int64_t *__restrict__ refl_offset, bool friedel,
                                                         const int32_t *__restrict__ rec_of,
@@ -71,42 +75,71 @@ __global__ __launch_bounds__(kThreads) void k_seg_count(const HChunk *__restrict
                                                         const int16_t *__restrict__ kk,
                                                         const int16_t *__restrict__ ll, int32_t *__restrict__ cnt,
                                                         int64_t *__restrict__ n_entries) {
+  static_assert(kEntBlock == 4 * kThreads, "four entries per thread, one mask word per wavefront and slot");
+  __shared__ uint64_t s_start[kEntBlock / 64];
+  __shared__ int64_t s_cont;
   if (blockIdx.x == 0 && threadIdx.x == 0) n_entries[0] = friedel ? refl_offset[n_c] / 2 : refl_offset[n_c];
   const HChunk hk = eblocks[blockIdx.x];
   const Entries en = entries_of(refl_offset, hk.crystal, friedel);
   const bool rec = rec_of[hk.crystal] != 0;  // other crystals get no segments
   const int64_t e0 = (int64_t)hk.chunk * kEntBlock;
-  for (int64_t e = e0 + threadIdx.x; e < min(e0 + (int64_t)kEntBlock, en.count); e += kThreads) {
-    const int64_t i = en.first + e;
-    int32_t n = 0;
-    if (rec && (e == 0 || !continues_row(hh, kk, ll, i))) {
-      // walk the run eight entries at a time (their loads issued together)
-      int64_t len = 1;
-      bool open = true;
-      while (open) {
-        constexpr int W = 8;
-        int16_t h8[W + 1], k8[W + 1], l8[W + 1];
+  const int64_t e1 = min(e0 + (int64_t)kEntBlock, en.count);
+  if (e0 >= e1) return;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (!rec) {
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) cnt[en.base + e] = 0;
+    return;
+  }
+  // entry e0 + 256 u + t: slot u of thread t, mask word 4 u + (t / 64)
+  bool st[4];
 #pragma unroll
-        for (int u = 0; u <= W; ++u) {
-          const int64_t x = min(e + len - 1 + u, en.count - 1);
-          h8[u] = hh[en.first + x];
-          k8[u] = kk[en.first + x];
-          l8[u] = ll[en.first + x];
-        }
-#pragma unroll
-        for (int u = 1; u <= W; ++u) {
-          if (open) {
-            const bool more = e + len < en.count && h8[u] == h8[u - 1] && k8[u] == k8[u - 1] && l8[u] == l8[u - 1] + 1;
-            if (more)
-              ++len;
-            else
-              open = false;
-          }
-        }
+  for (int u = 0; u < 4; ++u) {
+    const int64_t e = e0 + u * kThreads + threadIdx.x;
+    st[u] = e < e1 && (e == 0 || !continues_row(hh, kk, ll, en.first + e));
+    const uint64_t b = __ballot(st[u]);
+    if (lane == 0) s_start[4 * u + wid] = b;
+  }
+  if (wid == 0) {
+    // entries past the block that continue the row of its last entry
+    int64_t c = 0;
+    for (int64_t j0 = e1;; j0 += 64) {
+      const int64_t j = j0 + lane;
+      const bool more = j < en.count && continues_row(hh, kk, ll, en.first + j);
+      const uint64_t b = __ballot(more);
+      if (b == ~0ull) {
+        c += 64;
+        continue;
       }
+      c += __builtin_ctzll(~b);
+      break;
+    }
+    if (lane == 0) s_cont = c;
+  }
+  __syncthreads();
+  const int nb = (int)(e1 - e0);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int p = u * kThreads + (int)threadIdx.x;  // position in the block
+    if (p >= nb) continue;
+    int32_t n = 0;
+    if (st[u]) {
+      // the next run start after p in the mask, else the block's end plus
+      // the continuation
+      int64_t len = -1;
+      int w = p >> 6;
+      uint64_t m = (p & 63) == 63 ? 0ull : s_start[w] & (~0ull << ((p & 63) + 1));
+      while (true) {
+        if (m != 0ull) {
+          len = (int64_t)(64 * w + __builtin_ctzll(m)) - p;
+          break;
+        }
+        if (++w >= kEntBlock / 64) break;
+        m = s_start[w];
+      }
+      if (len < 0 || p + len > nb) len = (int64_t)nb - p + s_cont;
       n = (int32_t)((len + R - 1) / R);
     }
-    cnt[en.base + e] = n;
+    cnt[en.base + e0 + p] = n;
   }
 }
 
