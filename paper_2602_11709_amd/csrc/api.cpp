@@ -31,6 +31,7 @@ struct xrd_batch {
   std::vector<CrystalPlan> plan;
   std::vector<EnumChunk> enum_chunks;  // enumeration chunks, crystal by crystal
   int64_t max_enum_chunks = 0;         // most chunks of one crystal (INT64_MAX if a crystal has none)
+  int64_t max_atoms = 0;               // most atoms of one crystal
   std::vector<HChunk> peak_chunks;  // peak chunks of the merge (crystal, chunk)
   std::vector<HChunk> eblocks;  // entry blocks of the broadening (crystal, block of kEntBlock entries)
   std::vector<int32_t> crystal_order;  // crystals by descending reflection capacity
@@ -555,6 +556,7 @@ int xrd_batch_create(const xrd_batch_desc *d, xrd_batch **out) {
     const int64_t fine_tiles = ceil_div(evalcap, 64 * kSfRptMin);
     tiles_total += fine_tiles;
     P.fused = na <= kFusedMaxAtoms ? 1 : 0;
+    b->max_atoms = std::max<int64_t>(b->max_atoms, na);
     if (P.fused) {
       pfused += fine_tiles * na;
     } else {
@@ -986,7 +988,7 @@ int xrd_enumerate_hkl(xrd_batch *b, void *ws, const xrd_refl *r) {
                    b->desc.occ, b->desc.bfac, b->desc.sf_coeff, at<CoeffF>(ws, L.coeff_f),
                    at<AtomRec>(ws, L.atoms), at<AtomRot>(ws, L.rot), at<int32_t>(ws, L.atom_orig),
                    at<SpeciesRun>(ws, L.runs), at<int32_t>(ws, L.run_count), at<int32_t>(ws, L.err_flag),
-                   b->max_enum_chunks, stream_of(b));
+                   b->max_enum_chunks, b->max_atoms, stream_of(b));
   b->last_ws = ws;
   return hip_check("enumerate");
 }

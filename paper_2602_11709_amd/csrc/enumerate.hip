@@ -30,6 +30,7 @@ constexpr int kThreads = 256;
 static_assert(kEnumRows <= 64, "one row per lane of a wavefront");
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kFusedPackLds = 4096;  // largest cursor space the fused count-and-pack launch carries
+constexpr int64_t kFusedPackAtoms = 1024;  // largest crystal the fused launch packs (one batch of records in flight)
 
 struct Hkl {
   int h, k, l;
@@ -193,6 +194,10 @@ __device__ __forceinline__ AtomIn load_atom(int64_t j, int64_t a1, const double 
   return r;
 }
 
+// D: batches of 64 atom records in flight ahead of the one being placed
+// (and 4 D batches of species per histogram round); larger D hides more of
+// the loads' latency on crystals of many atoms at the cost of registers.
+template <int D>
 __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan *__restrict__ plan,
                              int32_t n_species, const double *__restrict__ frac,
                              const int32_t *__restrict__ species, const double *__restrict__ occ,
@@ -222,15 +227,15 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
   for (int t = lane; t < n_species; t += 64) cursor[t] = 0;
   wave_sync();
   // species histogram: the lowest lane of each species group adds its size
-  for (int64_t base = a0; base < a1; base += 256) {
-    int sp[4];
+  for (int64_t base = a0; base < a1; base += 256 * D) {
+    int sp[4 * D];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 4 * D; ++u) {
       const int64_t j = base + 64 * u + lane;
       sp[u] = j < a1 ? species[j] : 0;
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < 4 * D; ++u) {
       const bool active = base + 64 * u + lane < a1;
       if (active && (sp[u] < 0 || sp[u] >= n_species)) {
         atomicOr(err, 1);
@@ -272,43 +277,54 @@ __device__ void pack_crystal(int c, int lane, int32_t *cursor, const CrystalPlan
   }
   if (lane == 0) run_count[c] = nruns;
   // scatter in input order within each species: an atom's slot is its
-  // species cursor plus the lanes of its species below it; the next 64
-  // atoms' records load while these are placed
-  AtomIn in = load_atom(a0 + lane, a1, frac, species, occ, bfac);
-  for (int64_t base = a0; base < a1; base += 64) {
-    const int64_t j = base + lane;
-    const AtomIn nx = load_atom(j + 64, a1, frac, species, occ, bfac);
-    const bool active = j < a1;
-    const int sp = active ? (in.sp < 0 || in.sp >= n_species ? 0 : in.sp) : 0;
-    AtomRec a{};
-    AtomRot z{};
-    if (active) {
-      a.x = in.x;
-      a.y = in.y;
-      a.z = in.z;
-      a.occ = in.occ;
-      a.bfac = in.bfac;
-      a.log2occ = __log2f((float)a.occ);
-      a.bl2e = (float)a.bfac * kLog2e;
-      // the row recurrence's factors: e^{2 pi i z} and e^{-B G*33 / 2}
-      sincospi(2.0 * a.z, &z.zs, &z.zc);
-      z.rho = exp(-0.5 * a.bfac * P.gs[2]);
-      z.zcf = (float)z.zc;
-      z.zsf = (float)z.zs;
-      z.rhof = (float)z.rho;
+  // species cursor plus the lanes of its species below it; the next D
+  // batches of 64 atoms' records load while these are placed
+  AtomIn cur[D];
+#pragma unroll
+  for (int u = 0; u < D; ++u) cur[u] = load_atom(a0 + 64 * u + lane, a1, frac, species, occ, bfac);
+  for (int64_t batch = a0; batch < a1; batch += 64 * D) {
+    AtomIn nxt[D];
+#pragma unroll
+    for (int u = 0; u < D; ++u) nxt[u] = load_atom(batch + 64 * (D + u) + lane, a1, frac, species, occ, bfac);
+#pragma unroll
+    for (int u = 0; u < D; ++u) {
+      const int64_t base = batch + 64 * u;
+      if (base >= a1) break;
+      const AtomIn &in = cur[u];
+      const int64_t j = base + lane;
+      const bool active = j < a1;
+      const int sp = active ? (in.sp < 0 || in.sp >= n_species ? 0 : in.sp) : 0;
+      AtomRec a{};
+      AtomRot z{};
+      if (active) {
+        a.x = in.x;
+        a.y = in.y;
+        a.z = in.z;
+        a.occ = in.occ;
+        a.bfac = in.bfac;
+        a.log2occ = __log2f((float)a.occ);
+        a.bl2e = (float)a.bfac * kLog2e;
+        // the row recurrence's factors: e^{2 pi i z} and e^{-B G*33 / 2}
+        sincospi(2.0 * a.z, &z.zs, &z.zc);
+        z.rho = exp(-0.5 * a.bfac * P.gs[2]);
+        z.zcf = (float)z.zc;
+        z.zsf = (float)z.zs;
+        z.rhof = (float)z.rho;
+      }
+      const uint64_t m = same_species(active, sp, nbits);
+      const int below = lanes_below(m);
+      const int pos = active ? cursor[sp] + below : 0;
+      wave_sync();
+      if (active) {
+        if (below == 0) cursor[sp] = pos + __popcll(m);
+        atoms[pos] = a;
+        rot[pos] = z;
+        orig[pos] = (int32_t)j;
+      }
+      wave_sync();
     }
-    const uint64_t m = same_species(active, sp, nbits);
-    const int below = lanes_below(m);
-    const int pos = active ? cursor[sp] + below : 0;
-    wave_sync();
-    if (active) {
-      if (below == 0) cursor[sp] = pos + __popcll(m);
-      atoms[pos] = a;
-      rot[pos] = z;
-      orig[pos] = (int32_t)j;
-    }
-    wave_sync();
-    in = nx;
+#pragma unroll
+    for (int u = 0; u < D; ++u) cur[u] = nxt[u];
   }
 }
 
@@ -329,9 +345,10 @@ struct PackArgs {
 };
 
 // Atom packing alone, one wavefront per crystal.
+template <int D>
 __global__ __launch_bounds__(64) void k_atom_pack(const CrystalPlan *__restrict__ plan, int64_t n_c, PackArgs a) {
   extern __shared__ int32_t cursor[];  // n_species
-  pack_crystal(blockIdx.x, threadIdx.x, cursor, plan, a.n_species, a.frac, a.species, a.occ, a.bfac, a.coeff,
+  pack_crystal<D>(blockIdx.x, threadIdx.x, cursor, plan, a.n_species, a.frac, a.species, a.occ, a.bfac, a.coeff,
                a.coeff_f, a.atoms, a.rot, a.orig, a.runs, a.run_count, a.err);
 }
 
@@ -355,7 +372,7 @@ __global__ __launch_bounds__(kThreads) void k_enum_count(const CrystalPlan *__re
     extern __shared__ int32_t cursors[];  // 4 x n_species
     const int64_t c = (int64_t)blockIdx.x * (kThreads / 64) + wid;
     if (c < n_c)
-      pack_crystal((int)c, lane, cursors + wid * pa.n_species, plan, pa.n_species, pa.frac, pa.species, pa.occ,
+      pack_crystal<1>((int)c, lane, cursors + wid * pa.n_species, plan, pa.n_species, pa.frac, pa.species, pa.occ,
                    pa.bfac, pa.coeff, pa.coeff_f, pa.atoms, pa.rot, pa.orig, pa.runs, pa.run_count, pa.err);
     return;
   }
@@ -626,7 +643,7 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const EnumChunk *chu
                       int32_t n_species, const double *frac, const int32_t *species, const double *occ,
                       const double *bfac, const double *coeff, CoeffF *coeff_f, AtomRec *atoms, AtomRot *rot,
                       int32_t *orig, SpeciesRun *runs, int32_t *run_count, int32_t *err, int64_t max_crystal_chunks,
-                      hipStream_t s) {
+                      int64_t max_crystal_atoms, hipStream_t s) {
   const PackArgs pa{n_species, frac, species, occ, bfac, coeff, coeff_f, atoms, rot, orig, runs, run_count, err};
   // the fill forms its own offsets when the counts are few and every crystal
   // has at least one chunk (so that one wavefront writes its offset)
@@ -635,11 +652,13 @@ void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const EnumChunk *chu
   // the per-block sums of the counts take the scanned prefix's place
   int64_t *block_sums = self ? prefix : nullptr;
   // the packing rides along in the count launch while its cursors stay small
+  // and its crystals small; otherwise a launch of its own, with four batches
+  // of atom records in flight per wavefront
   const size_t fused_lds = (size_t)(kThreads / 64) * n_species * sizeof(int32_t);
-  const bool fuse = n_chunks > 0 && fused_lds <= kFusedPackLds;
+  const bool fuse = n_chunks > 0 && fused_lds <= kFusedPackLds && max_crystal_atoms <= kFusedPackAtoms;
   if (!fuse && n_c > 0)
-    hipLaunchKernelGGL(k_atom_pack, dim3((unsigned)n_c), dim3(64), (size_t)n_species * sizeof(int32_t), s, plan, n_c,
-                       pa);
+    hipLaunchKernelGGL(k_atom_pack<4>, dim3((unsigned)n_c), dim3(64), (size_t)n_species * sizeof(int32_t), s, plan,
+                       n_c, pa);
   if (n_chunks > 0) {
     const int64_t chunk_blocks = (n_chunks + kThreads / 64 - 1) / (kThreads / 64);
     const int64_t pack_blocks = fuse ? (n_c + kThreads / 64 - 1) / (kThreads / 64) : 0;

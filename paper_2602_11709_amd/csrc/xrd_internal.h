@@ -235,13 +235,15 @@ struct AbItem {
 // the atoms into species runs for the structure-factor kernels.
 // max_crystal_chunks: the most enumeration chunks of one crystal (INT64_MAX
 // when a crystal has none); with few chunks the fill forms the offsets itself.
+// max_crystal_atoms: the most atoms of one crystal (the packing of large
+// crystals gets a launch of its own).
 void launch_enumerate(const CrystalPlan *plan, int64_t n_c, const EnumChunk *chunks, int64_t n_chunks,
                       double lambda, int32_t *counts, int64_t *prefix, int64_t *scan_part, int16_t *h, int16_t *k,
                       int16_t *l, double *q, double *tt, double *lp, int64_t *refl_offset, int32_t n_species,
                       const double *frac, const int32_t *species, const double *occ, const double *bfac,
                       const double *coeff, CoeffF *coeff_f, AtomRec *atoms, AtomRot *rot, int32_t *orig,
                       SpeciesRun *runs, int32_t *run_count, int32_t *err, int64_t max_crystal_chunks,
-                      hipStream_t s);
+                      int64_t max_crystal_atoms, hipStream_t s);
 // Items: the first n_heavy take a block each (atoms split over its four
 // wavefronts), the rest one wavefront each.  A non-null deriv_cache
 // ([refl_cap] float4 under mixed precision, else double4) receives

@@ -26,7 +26,7 @@ void launch_peak_families(const HChunk *, int64_t, const FamOps *, const int64_t
 void launch_enumerate(const CrystalPlan *, int64_t, const EnumChunk *, int64_t, double, int32_t *, int64_t *,
                       int64_t *, int16_t *, int16_t *, int16_t *, double *, double *, double *, int64_t *, int32_t,
                       const double *, const int32_t *, const double *, const double *, const double *, CoeffF *,
-                      AtomRec *, AtomRot *, int32_t *, SpeciesRun *, int32_t *, int32_t *, int64_t, hipStream_t) {
+                      AtomRec *, AtomRot *, int32_t *, SpeciesRun *, int32_t *, int32_t *, int64_t, int64_t, hipStream_t) {
   reached("enumerate");
 }
 void launch_sf(bool, bool, const SfItem *, int64_t, int64_t, const CrystalPlan *, const int64_t *, const int16_t *,
