@@ -549,6 +549,68 @@ __device__ __forceinline__ void bitonic_bucket(double *__restrict__ gk, int32_t 
   }
 }
 
+// The same ascending network over at most 64 E items in the registers of
+// one wavefront: lane t holds slots 64 t / 64 .. : slot i = E t + e in its
+// e-th register (padding sorts last).  Pairs (i, i + j) with j < E are in
+// one lane; for j >= E the partner sits at lane t ^ (j / E), register e, and
+// each lane keeps the minimum or the maximum of the two by its slot's bits
+// j and k.  No LDS and no barriers; (2theta, index) is a total order, so
+// the result is the LDS network's.
+template <int E>
+__device__ __forceinline__ void bitonic_regs(double *__restrict__ gk, int32_t *__restrict__ gx, int n, int lane) {
+  constexpr int N = 64 * E;
+  double k[E];
+  int32_t x[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = lane * E + e;
+    k[e] = i < n ? gk[i] : __builtin_inf();
+    x[e] = i < n ? gx[i] : INT32_MAX;
+  }
+#pragma unroll
+  for (int kk = 2; kk <= N; kk <<= 1)
+#pragma unroll
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      if (j >= E) {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int i = lane * E + e;
+          const double ko = __shfl_xor(k[e], j / E, 64);
+          const int32_t xo = __shfl_xor(x[e], j / E, 64);
+          const bool gt = k[e] > ko || (k[e] == ko && x[e] > xo);
+          const bool keep_min = ((i & j) == 0) == ((i & kk) == 0);
+          if (keep_min ? gt : !gt) {
+            k[e] = ko;
+            x[e] = xo;
+          }
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          if (e & j) continue;
+          const int f = e | j, i = lane * E + e;
+          const bool gt = k[e] > k[f] || (k[e] == k[f] && x[e] > x[f]);
+          if (gt == ((i & kk) == 0)) {
+            const double tk = k[e];
+            k[e] = k[f];
+            k[f] = tk;
+            const int32_t tx = x[e];
+            x[e] = x[f];
+            x[f] = tx;
+          }
+        }
+      }
+    }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int i = lane * E + e;
+    if (i < n) {
+      gk[i] = k[e];
+      gx[i] = x[e];
+    }
+  }
+}
+
 __device__ __forceinline__ void big_wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -564,12 +626,11 @@ __device__ __forceinline__ void big_bucket_range(const BigArgs &a, const BigChun
 }
 
 // Per (crystal, bucket), a wavefront (four buckets to a block): the bucket's
-// items ordered in LDS on (2theta, global index) and written back.  Buckets
-// above kWaveBucket items, which the bucket sizing makes rare, are listed
-// for kb_bsort_over.
+// items ordered in registers on (2theta, global index) and written back.
+// Buckets above kWaveBucket items, which the bucket sizing makes rare, are
+// listed for kb_bsort_over.
 __global__ __launch_bounds__(kBigThreads) void kb_bsort(BigArgs a, const BigChunk *__restrict__ crystals) {
-  __shared__ double sk[kBigThreads / 64][kWaveBucket];
-  __shared__ int32_t sx[kBigThreads / 64][kWaveBucket];
+  static_assert(kWaveBucket == 512, "register networks of up to 8 items per lane");
   const BigChunk bc = crystals[blockIdx.x];
   const BigUnit u = big_unit(a, bc);
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
@@ -583,7 +644,16 @@ __global__ __launch_bounds__(kBigThreads) void kb_bsort(BigArgs a, const BigChun
     if (lane == 0) a.over[atomicAdd(a.n_over, 1)] = make_int2((int)blockIdx.x, b);
     return;
   }
-  bitonic_bucket<64>(a.skey + u.r0 + s0, a.sidx + u.r0 + s0, n, sk[wid], sx[wid], lane, [] { big_wave_sync(); });
+  double *gk = a.skey + u.r0 + s0;
+  int32_t *gx = a.sidx + u.r0 + s0;
+  if (n <= 64)
+    bitonic_regs<1>(gk, gx, n, lane);
+  else if (n <= 128)
+    bitonic_regs<2>(gk, gx, n, lane);
+  else if (n <= 256)
+    bitonic_regs<4>(gk, gx, n, lane);
+  else
+    bitonic_regs<8>(gk, gx, n, lane);
 }
 
 // The listed buckets above kWaveBucket items, a block each in turn: the
