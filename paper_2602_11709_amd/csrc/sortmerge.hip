@@ -794,10 +794,15 @@ __global__ __launch_bounds__(64) void kb_scan_counts(BigArgs a, const BigChunk *
 // Per chunk of sorted positions: the entries at their ranks, and each peak
 // (start, members' intensity sum in sorted order, multiplicity) at its
 // number, staged at r0 + p (r0 + R/2 + p when a threshold follows); the
-// crystal's largest peak intensity by one atomic per block.
+// crystal's largest peak intensity by one atomic per block.  Each window of
+// kBigThreads positions gathers its intensities at once into LDS with the
+// peak-start flags; a peak sums its members from there, in sorted order,
+// and continues in global memory only past the window's end.
 __global__ __launch_bounds__(kBigThreads) void kb_write(BigArgs a, MergeOut mo) {
   __shared__ int32_t red[kBigThreads / 64];
   __shared__ unsigned long long smax[1];
+  __shared__ double s_v[kBigThreads];
+  __shared__ int32_t s_f[kBigThreads];
   const BigUnit u = big_unit(a, a.chunks[blockIdx.x]);
   if (!u.live) return;
   const bool merge = mo.inten != nullptr, ent = a.ent_key != nullptr;
@@ -821,13 +826,25 @@ __global__ __launch_bounds__(kBigThreads) void kb_write(BigArgs a, MergeOut mo) 
       a.ent_key[e + re] = a.skey[u.r0 + j];
       a.ent_idx[e + re] = ix;
     }
+    if (merge) {
+      // positions past the crystal stop a peak like a flag
+      s_v[threadIdx.x] = live ? mo.inten[ix] : 0.0;
+      s_f[threadIdx.x] = live ? (int32_t)mo.flags[u.r0 + j] : 1;
+    }
+    __syncthreads();
     if (fp) {
-      double s = mo.inten[ix];
+      double s = s_v[threadIdx.x];
       int m = 1;
-      for (int64_t x = j + 1; x < u.R && !mo.flags[u.r0 + x]; ++x) {
-        s += mo.inten[a.sidx[u.r0 + x]];
+      int t = (int)threadIdx.x + 1;
+      for (; t < kBigThreads && !s_f[t]; ++t) {
+        s += s_v[t];
         ++m;
       }
+      if (t == kBigThreads)
+        for (int64_t x = j0 + (int64_t)(q + 1) * kBigThreads; x < u.R && !mo.flags[u.r0 + x]; ++x) {
+          s += mo.inten[a.sidx[u.r0 + x]];
+          ++m;
+        }
       mo.t_tt[base + p + rp] = a.skey[u.r0 + j];
       mo.t_i[base + p + rp] = s;
       mo.t_mult[base + p + rp] = m;
@@ -836,6 +853,7 @@ __global__ __launch_bounds__(kBigThreads) void kb_write(BigArgs a, MergeOut mo) 
     }
     e += te;
     p += tp;
+    __syncthreads();  // s_v and s_f are written again by the next window
   }
   if (!merge) return;
 #pragma unroll
