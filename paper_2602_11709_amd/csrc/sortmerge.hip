@@ -550,8 +550,8 @@ __device__ __forceinline__ void bitonic_bucket(double *__restrict__ gk, int32_t 
 }
 
 // The same ascending network over at most 64 E items in the registers of
-// one wavefront: lane t holds slots 64 t / 64 .. : slot i = E t + e in its
-// e-th register (padding sorts last).  Pairs (i, i + j) with j < E are in
+// one wavefront: lane t holds slots E t .. E t + E - 1, slot i = E t + e in
+// its e-th register (padding sorts last).  Pairs (i, i + j) with j < E are in
 // one lane; for j >= E the partner sits at lane t ^ (j / E), register e, and
 // each lane keeps the minimum or the maximum of the two by its slot's bits
 // j and k.  No LDS and no barriers; (2theta, index) is a total order, so
