@@ -598,13 +598,17 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
       if (ww.part != 0) continue;
       const double q = qq[i];
       const double us = 0.25 * l2 * q;  // sin^2(theta)
-      const double sq = sqrt(1.0 - us);
+      const double cs2 = 1.0 - us;      // cos^2(theta)
+      const double sq = sqrt(cs2);
+      // LP = num / den, num = 1 + (1 - 2 us)^2, den = us cos(theta); with
+      // g = us cos^2(theta) and one reciprocal of it:
+      //   dLP/dus = cos(theta) (2 cos^2 dnum us - num (2 - 3 us)) / (2 g^2),
+      //   d(2theta)/dq = (180/pi) lambda^2 / (4 sqrt(g))  (= ... sqrt(g) / g)
+      const double g = us * cs2, inv = 1.0 / g;
       const double num = 1.0 + (1.0 - 2.0 * us) * (1.0 - 2.0 * us);
-      const double den = us * sq;
       const double dnum = -4.0 * (1.0 - 2.0 * us);
-      const double dden = (2.0 - 3.0 * us) / (2.0 * sq);
-      const double dlp_dq = (dnum * den - num * dden) / (den * den) * (0.25 * l2);
-      const double dtt_dq = (360.0 / 3.14159265358979323846) * lambda / (4.0 * sqrt(q) * sq);
+      const double dlp_dq = sq * (2.0 * cs2 * dnum * us - num * (2.0 - 3.0 * us)) * (0.5 * inv * inv) * (0.25 * l2);
+      const double dtt_dq = (180.0 / 3.14159265358979323846) * 0.25 * l2 * sqrt(g) * inv;
       const double f2 = A[u] * A[u] + B[u] * B[u];
       if (!P.fused) {
         ga[i] = gA[u];
