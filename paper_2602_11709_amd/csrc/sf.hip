@@ -87,6 +87,35 @@ __device__ __forceinline__ double wave_sum_to_63(double v) {
   return v;
 }
 
+// Six per-lane doubles summed over the wavefront at once by halving: at
+// lane distances 32, 16 and 8 each lane keeps one value of every pair (the
+// one its lane bit selects) plus its partner's copy of that value, then
+// three exchanges finish the one value left.  Lane l ends with the wave
+// total of value 4 ((l >> 3) & 1) + 2 ((l >> 4) & 1) + ((l >> 5) & 1)
+// (values 6 and 7 are zero padding).
+__device__ __forceinline__ double wave_reduce6(const double (&r)[6], int lane) {
+  double v[8] = {r[0], r[1], r[2], r[3], r[4], r[5], 0.0, 0.0};
+#pragma unroll
+  for (int step = 0; step < 3; ++step) {
+    const int m = 32 >> step, pairs = 4 >> step;
+    const bool b = (lane & m) != 0;
+    double nv[4];
+#pragma unroll
+    for (int i = 0; i < pairs; ++i) {
+      const double send = b ? v[2 * i] : v[2 * i + 1];
+      const double keep = b ? v[2 * i + 1] : v[2 * i];
+      nv[i] = keep + __shfl_xor(send, m, 64);
+    }
+#pragma unroll
+    for (int i = 0; i < pairs; ++i) v[i] = nv[i];
+  }
+  double x = v[0];
+  x += __shfl_xor(x, 4, 64);
+  x += __shfl_xor(x, 2, 64);
+  x += __shfl_xor(x, 1, 64);
+  return x;
+}
+
 // Sixteen per-lane values reduced over the wavefront at once, with no
 // selects for the two cross-row levels: v_permlane32_swap exchanges the upper
 // half-wave of one register with the lower half of another, so pairing
@@ -633,13 +662,9 @@ __global__ __launch_bounds__(kThreads) void k_sf_bw(const SfItem *__restrict__ i
         r6[4] += 2.0 * g * h[u] * l[u];
         r6[5] += 2.0 * g * k[u] * l[u];
       }
-#pragma unroll
-      for (int e = 0; e < 6; ++e) r6[e] = wave_sum_to_63(r6[e]);
-      if (lane == 63) {
-        double *row = part6 + ((int64_t)P.tile_begin + tile) * 6;
-#pragma unroll
-        for (int e = 0; e < 6; ++e) row[e] = r6[e];
-      }
+      const double tot = wave_reduce6(r6, lane);
+      const int e6 = 4 * ((lane >> 3) & 1) + 2 * ((lane >> 4) & 1) + ((lane >> 5) & 1);
+      if ((lane & 7) == 0 && e6 < 6) part6[((int64_t)P.tile_begin + tile) * 6 + e6] = tot;
     }
     if (!P.fused) return true;
     // Fused atom gradients (small crystals): walk the atoms again; for each atom
