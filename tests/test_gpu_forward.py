@@ -161,3 +161,27 @@ def test_offsets_formed_by_the_fill_for_mid_size_crystals():
     rng = np.random.default_rng(0)
     for c in range(b.n_crystals):
         compare_crystal_sampled(res, c, b, "mixed", rng, n_sample=200, n_strong=30, label="mid-size")
+
+
+@pytest.mark.parametrize("case", ["2100 species", "1500-atom crystal"])
+def test_separate_packing_launch_shapes(case):
+    """The packing launch of its own in both shapes: 2100 species (eight
+    wavefronts' cursor arrays would not fit in 64 KB of LDS, so one
+    wavefront packs each crystal), and a 1500-atom crystal of 40 species
+    between small ones (above 1024 atoms: eight wavefronts share the crystal,
+    each a slice with many species runs, joined by one scan over (species,
+    wavefront)).  Every reflection, structure factor and peak against the
+    oracle."""
+    if case == "2100 species":
+        b = synth.random_triclinic(43, 6, atoms_lo=20, atoms_hi=90, species_per_crystal=40, pool=2100)
+    else:
+        small = synth.random_triclinic(44, 4, atoms_lo=5, atoms_hi=60, species_per_crystal=40, pool=300)
+        big = synth.random_triclinic(45, 1, atoms_lo=1500, atoms_hi=1500, species_per_crystal=40, pool=300,
+                                     len_lo=5.0, len_hi=7.0)
+        big.sf_coeff = small.sf_coeff
+        b = concat([small.subset([0, 1]), big, small.subset([2, 3])])
+    res = run(b, "mixed")
+    orcs = [oracle.pattern(b, c) for c in range(b.n_crystals)]
+    worst = compare_batch(res, b, orcs, "mixed", case)
+    assert worst["ambiguous"] == 0
+    print(case, worst, flush=True)
