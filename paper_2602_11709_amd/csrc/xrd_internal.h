@@ -40,8 +40,11 @@ constexpr int kMidSort = 6144;       // ... by one 1024-thread block; larger cry
 // Crystals whose reflection capacity exceeds kBigSort sort in global memory
 // over many blocks (kBigChunk reflections, sorted positions or peak slots
 // each) when they have more than 2 kMidSort reflections; the others in
-// global memory take one block.
-constexpr int64_t kBigSort = 65536;
+// global memory take one block (they must fill more than half their search
+// box, which a sphere shell in a box rarely does).  2 kBigSort bounds the
+// capacity of 15 A cells under Cu K-alpha to 90 deg, so such batches launch
+// no many-block kernels.
+constexpr int64_t kBigSort = 24576;
 constexpr int kBigChunk = 4096;
 constexpr int kSpanPts = 16;         // grid points per span of the broadening gather (a quarter wavefront)
 constexpr int kRecLen = 8;           // reflections per segment of the row-recurrence structure factors

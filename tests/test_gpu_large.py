@@ -242,3 +242,33 @@ def test_graph_replay_matches_eager():
         got = snap()
         for i, (a, bb) in enumerate(zip(eager, got)):
             assert torch.equal(a, bb), f"replay {rep}: output {i} differs from eager"
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_one_block_global_sort_of_a_box_filling_cell(precision):
+    """A cubic 11.49 A cell over 0.5-179.9 deg fills more than half of its
+    search box: |h| <= 14, so a capacity of 29^3 - 1 = 24388 (at most the
+    many-block threshold, 24576) holds about 1.4e4 reflections (above the
+    12288 that one block sorts in LDS), and one block sorts it in global
+    memory, next to a small crystal.  Reflections, structure factors and
+    peaks exactly against the oracle."""
+    import math
+    from tests.parity import compare_crystal
+    from tests.test_gpu_forward import concat, run
+    a = 11.49
+    h_max = math.floor(a * 2.0 * math.sin(math.radians(179.9 / 2)) / synth.CU_KA)
+    assert h_max == 14 and (2 * h_max + 1) ** 3 - 1 <= 24576
+    rng = np.random.default_rng(8)
+    base = synth.random_triclinic(48, 1, atoms_lo=6, atoms_hi=6)
+    cell = synth.CrystalBatch("cubic", np.array([[a, a, a, 90.0, 90.0, 90.0]]), np.array([0, 5], np.int64),
+                              rng.uniform(size=(5, 3)), np.array([0, 1, 2, 0, 1], np.int32), np.ones(5),
+                              rng.uniform(0.2, 1.0, 5), base.sf_coeff, synth.CU_KA, np.array([0.5]),
+                              np.array([179.9]))
+    small = synth.random_triclinic(48, 1, atoms_lo=6, atoms_hi=6)
+    b = concat([cell, small])
+    res = run(b, precision)
+    n = int(res.refl_offset[1] - res.refl_offset[0])
+    print(precision, "reflections", n, flush=True)
+    assert n > 12288
+    for c in range(b.n_crystals):
+        compare_crystal(res, c, oracle.pattern(b, c), precision, "box-filling")
