@@ -625,23 +625,47 @@ __device__ __forceinline__ void big_bucket_range(const BigArgs &a, const BigChun
   *n = (int)(e0 - *s0);
 }
 
-// Per (crystal, bucket), a wavefront (four buckets to a block): the bucket's
-// items ordered in registers on (2theta, global index) and written back.
-// Buckets above kWaveBucket items, which the bucket sizing makes rare, are
-// listed for kb_bsort_over.
-__global__ __launch_bounds__(kBigThreads) void kb_bsort(BigArgs a, const BigChunk *__restrict__ crystals) {
+// Per bucket of the batch, a wavefront (four buckets to a block): the
+// bucket's items ordered in registers on (2theta, global index) and written
+// back.  FLAT: the grid runs over the batch's buckets, crystal after
+// crystal (a crystal's buckets start at its bbase), and each wavefront finds
+// its crystal by a binary search over those starts (for batches of few
+// large crystals of different sizes); otherwise grid (crystal, group of four
+// buckets up to the largest count), blocks past a crystal's buckets ending
+// at once (for many crystals, where the search would be long).  Buckets
+// above kWaveBucket items, which the bucket sizing makes rare, are listed
+// for kb_bsort_over.
+template <bool FLAT>
+__global__ __launch_bounds__(kBigThreads) void kb_bsort(BigArgs a, const BigChunk *__restrict__ crystals, int64_t n_big,
+                                                        int64_t n_buckets) {
   static_assert(kWaveBucket == 512, "register networks of up to 8 items per lane");
-  const BigChunk bc = crystals[blockIdx.x];
-  const BigUnit u = big_unit(a, bc);
   const int wid = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), lane = threadIdx.x & 63;
-  const int b = (int)blockIdx.y * (kBigThreads / 64) + wid;
+  int64_t lo;
+  int b;
+  if constexpr (FLAT) {
+    const int64_t fb = (int64_t)blockIdx.x * (kBigThreads / 64) + wid;
+    if (fb >= n_buckets) return;
+    int64_t hi = n_big - 1;  // the last crystal whose buckets start at or before fb
+    lo = 0;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if (crystals[mid].bbase <= fb) lo = mid;
+      else hi = mid - 1;
+    }
+    b = (int)(fb - crystals[lo].bbase);
+  } else {
+    lo = blockIdx.x;
+    b = (int)blockIdx.y * (kBigThreads / 64) + wid;
+  }
+  const BigChunk bc = crystals[lo];
+  const BigUnit u = big_unit(a, bc);
   if (!u.live || b >= bc.nb) return;
   int64_t s0;
   int n;
   big_bucket_range(a, bc, u, b, &s0, &n);
   if (n <= 1) return;
   if (n > kWaveBucket) {
-    if (lane == 0) a.over[atomicAdd(a.n_over, 1)] = make_int2((int)blockIdx.x, b);
+    if (lane == 0) a.over[atomicAdd(a.n_over, 1)] = make_int2((int)lo, b);
     return;
   }
   double *gk = a.skey + u.r0 + s0;
@@ -924,12 +948,19 @@ void big_sort(const SortArgs &s, const MergeOut &mo, hipStream_t st) {
   const bool merge = mo.inten != nullptr;
   const dim3 g((unsigned)s.n_big_chunks), b(kBigThreads), gc((unsigned)s.n_big), w(64);
   const dim3 gcols((unsigned)s.n_big, (unsigned)((s.big_nb_max + kBigThreads - 1) / kBigThreads));
-  const dim3 gbuckets((unsigned)s.n_big, (unsigned)((s.big_nb_max + 3) / 4));
+  // the bucket sort's grid: flat over the buckets for up to kFlatBig crystals
+  constexpr int64_t kFlatBig = 64;
+  const bool flat = s.n_big <= kFlatBig;
+  const dim3 gbuckets = flat ? dim3((unsigned)((s.big_buckets + kBigThreads / 64 - 1) / (kBigThreads / 64)))
+                             : dim3((unsigned)s.n_big, (unsigned)((s.big_nb_max + 3) / 4));
   hipLaunchKernelGGL(kb_hist, g, b, 0, st, a, merge ? mo.cmax : nullptr);
   hipLaunchKernelGGL(kb_colscan, gcols, b, 0, st, a, s.big_crystals);
   hipLaunchKernelGGL(kb_bscan, gc, b, 0, st, a, s.big_crystals);
   hipLaunchKernelGGL(kb_scatter, g, b, 0, st, a);
-  hipLaunchKernelGGL(kb_bsort, gbuckets, b, 0, st, a, s.big_crystals);
+  if (flat)
+    hipLaunchKernelGGL(kb_bsort<true>, gbuckets, b, 0, st, a, s.big_crystals, s.n_big, s.big_buckets);
+  else
+    hipLaunchKernelGGL(kb_bsort<false>, gbuckets, b, 0, st, a, s.big_crystals, s.n_big, s.big_buckets);
   hipLaunchKernelGGL(kb_bsort_over, dim3(kOverBlocks), b, 0, st, a, s.big_crystals);
   if (!merge && !a.ent_key) return;  // the sorted keys are the entries
   hipLaunchKernelGGL(kb_flags, g, b, 0, st, a, mo);
